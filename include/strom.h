@@ -1,0 +1,171 @@
+/*
+ * strom.h -- C ABI of the MI355X sGS-ADMM solver for PSD-only multi-block SDPs.
+ *
+ * The solver runs Algorithm 1 of Kang, Xu, Sarva, Liang, Yang, "Fast and Certifiable
+ * Trajectory Optimization" (sGS-ADMM, Sec. "Algorithmic Backbone") on the standard SDP
+ *     min <C,X>  s.t.  A(X) = b,  X = (X_1, ..., X_B) with every X_beta PSD
+ * (the standard multi-block SDP equation of Sec. "Faster Conversion to Standard SDP") and its
+ * dual  max <b,y> s.t. A^*y + S = C, S PSD.  Every step of the iteration runs in HIP
+ * kernels on one MI355X (gfx950); the host only does one-time setup (validation, the
+ * ordering and the FP64 LDL^T factorization of eps*I + A A^*) and reads results back.
+ *
+ * Conventions shared by every call:
+ *   - X, S and C are stored as the concatenation of the svec of every block in block order:
+ *     column-major upper triangle, off-diagonal entries multiplied by sqrt(2), so that
+ *     <svec P, svec Q> = tr(PQ) (the svec of the cited SDPT3 convention, Sec. "GPU Speedup").
+ *   - A is CSR with m rows over the n_svec svec columns: row i holds svec(A_i), int64 row
+ *     pointers, int32 column indices, FP64 values.
+ *   - Every call returns a strom_status (0 = OK, < 0 = error) and never aborts or throws;
+ *     strom_last_error() returns a thread-local description of the last error.
+ *   - Host pointers are read before the call returns; the caller keeps ownership.
+ *     Device pointers are caller-owned (for example PyTorch tensors); the library never
+ *     frees them.  Device memory the library allocates itself belongs to the ctx / sdp
+ *     handle and is released by the matching destroy call.
+ *   - Work is enqueued on the HIP stream given to strom_ctx_create (or the stream argument
+ *     of strom_project_psd_batched); calls that return host data synchronize that stream.
+ *   - A strom_sdp handle must be used by one host thread at a time.
+ */
+#ifndef STROM_H
+#define STROM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STROM_OK = 0,
+  STROM_E_INVAL = -1,    /* malformed argument: bad CSR, column >= n_svec, block size <= 0 */
+  STROM_E_NOMEM = -2,    /* device allocation failed or the HBM budget is exceeded          */
+  STROM_E_HIP = -3,      /* a HIP runtime call failed                                       */
+  STROM_E_FACTOR = -4,   /* a non-positive pivot in the LDL^T factor of eps*I + A A^*        */
+  STROM_E_AGAIN = -5,    /* result not ready yet (strom_poll)                               */
+  STROM_E_NOTFOUND = -6, /* unknown ticket                                                  */
+  STROM_E_STATE = -7     /* call not valid in the handle's current state                    */
+} strom_status;
+
+typedef enum { STROM_F64 = 0, STROM_F32 = 1 } strom_dtype;
+
+typedef enum {
+  STROM_RUNNING = 0,
+  STROM_CONVERGED = 1, /* eta <= tol                          */
+  STROM_MAXITER = 2,   /* maxiter reached with eta > tol      */
+  STROM_DIVERGED = 3   /* NaN or Inf in the KKT residuals     */
+} strom_solve_state;
+
+typedef struct strom_ctx strom_ctx; /* one per device: stream, scratch, HBM budget, queue */
+typedef struct strom_sdp strom_sdp; /* one per SDP instance: device data, factor, iterates */
+
+/* Solver options.  The paper fixes only tau in (0, 2) and sigma > 0 (Algorithm 1 input) and
+ * the stopping rule eta <= tol or maxiter (termination paragraph); the other values are
+ * this library's choices.  strom_default_opts fills:
+ *   sigma0 = 1, tau = 1.6, eps_reg = 1e-12 (eps = eps_reg * max_i (A A^*)_ii), tol = 1e-6,
+ *   maxiter = 100000, kkt_every = 10, proj_dtype = STROM_F64, polish_eta = 1e-5,
+ *   sigma_every = 50 (residual balancing: every sigma_every iterations sigma is doubled
+ *   when eta_d > 5 eta_p and halved when eta_p > 5 eta_d, clamped to [1e-4, 1e4];
+ *   0 keeps sigma fixed).  sigma_every must be a multiple of kkt_every (or 0). */
+typedef struct {
+  double sigma0;
+  double tau;
+  double eps_reg;
+  double tol;
+  int64_t maxiter;
+  int32_t kkt_every;
+  strom_dtype proj_dtype; /* precision of the eigensolver / reconstruction in the projection */
+  double polish_eta;      /* with proj_dtype = F32: switch the projection to FP64 once eta <= polish_eta */
+  int32_t sigma_every;
+} strom_opts;
+
+typedef struct {
+  double eta_p, eta_d, eta_g; /* KKT residuals of the termination rule (FP64) */
+  double pobj, dobj;          /* <C,X> and <b,y> */
+  double sigma;
+  int64_t iters;
+  strom_solve_state state;
+  double t_queue_s, t_setup_s, t_solve_s;
+} strom_info;
+
+/* One SDP instance, host arrays.  The blocks X_beta are given by their sizes; the svec
+ * length is sum_beta n_beta (n_beta + 1) / 2.  X0/S0 are the starting point of Algorithm 1
+ * (NULL means zero). */
+typedef struct {
+  int32_t nblocks;
+  const int32_t *block_sizes;
+  int32_t m;
+  int64_t nnz;
+  const int64_t *A_rowptr; /* m + 1 */
+  const int32_t *A_col;    /* nnz, svec column index of each entry */
+  const double *A_val;     /* nnz */
+  const double *b;         /* m */
+  const double *C_svec;    /* n_svec */
+  const double *X0_svec;   /* n_svec or NULL */
+  const double *S0_svec;   /* n_svec or NULL */
+} strom_problem;
+
+void strom_default_opts(strom_opts *opts);
+const char *strom_last_error(void);
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t, NULL
+ * for the default stream).  hbm_budget_bytes bounds the device memory of all instances
+ * set up in this ctx (0 = no bound). */
+strom_status strom_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, strom_ctx **out);
+strom_status strom_ctx_destroy(strom_ctx *ctx);
+
+/* Set up one instance: validates the CSR (E_INVAL), orders the rows (clique interiors first,
+ * then the rows coupling two cliques by nested dissection over the chain, a consequence of the
+ * chain-like sparsity of Def. 1), factors eps*I + A A^* = P L D L^T P^T in FP64 on the host
+ * (the paper's Cholesky-with-pre-permutation equation; E_FACTOR on a non-positive pivot),
+ * uploads everything and sets the iterate to (X0, 0, S0).  opts may be NULL (defaults). */
+strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *problem, const strom_opts *opts,
+                             strom_sdp **out);
+strom_status strom_sdp_destroy(strom_sdp *sdp);
+
+/* Run up to n_iter iterations of Algorithm 1 (steps 1-4) on the device.  The KKT residuals
+ * are evaluated every kkt_every iterations and after the last one; the call returns early
+ * once eta <= tol (state CONVERGED), or NaN appears (DIVERGED), or maxiter is reached.
+ * info (nullable) receives the residuals of the final iterate.  Synchronizes the stream. */
+strom_status strom_admm_step(strom_sdp *sdp, int32_t n_iter, strom_info *info);
+
+/* Enqueue exactly n_iter iterations without any host synchronization or convergence check
+ * (the residual-balancing sigma rule still runs on the device).  Used for timing. */
+strom_status strom_admm_enqueue(strom_sdp *sdp, int32_t n_iter);
+
+/* KKT residuals of the current iterate (termination-rule equation), FP64; synchronizes. */
+strom_status strom_kkt_residuals(strom_sdp *sdp, strom_info *out);
+
+/* Copy the current iterate to / from host arrays (X, S: n_svec; y: m).  Any pointer may be
+ * NULL to skip that part.  set_iterate also resets the iteration count. */
+strom_status strom_get_iterate(strom_sdp *sdp, double *X_svec, double *y, double *S_svec);
+strom_status strom_set_iterate(strom_sdp *sdp, const double *X_svec, const double *y,
+                               const double *S_svec);
+/* Sizes of an instance: n_svec, m and nnz of the L factor. */
+strom_status strom_sdp_sizes(strom_sdp *sdp, int64_t *n_svec, int32_t *m, int64_t *nnz_L);
+
+/* Projection onto the PSD cone of nblocks dense symmetric blocks (the parallel PSD cone
+ * projection of Sec. "GPU Speedup": eigendecomposition, negative eigenvalues set to zero,
+ * reconstruction).  Block k is n_dev[k] x n_dev[k], column-major, starting at element
+ * offset_dev[k] of in_dev / out_dev; in and out may alias.  n_dev, offset_dev, in_dev and
+ * out_dev are device pointers; max_n (host) bounds every n_dev[k] and must be <= 116 for
+ * F64, <= 160 for F32.  dtype selects double or float data.  Only the upper triangle of
+ * each input block is read; the output block is exactly symmetric. */
+strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblocks, int32_t max_n,
+                                       const int32_t *n_dev, const int64_t *offset_dev,
+                                       const void *in_dev, void *out_dev, strom_dtype dtype,
+                                       void *hip_stream);
+
+/* Serving.  strom_submit copies a problem and queues it; a solver thread owned by the ctx
+ * admits queued problems while their device footprint fits the ctx's HBM budget, keeps their
+ * iterates on the device, advances every admitted instance, retires an instance when it
+ * converges (or reaches maxiter, or diverges) and admits the next.  strom_poll returns
+ * E_AGAIN while the ticket is in flight; once done it fills info (and the optional host
+ * arrays) and forgets the ticket. */
+strom_status strom_submit(strom_ctx *ctx, const strom_problem *problem, const strom_opts *opts,
+                          uint64_t *ticket);
+strom_status strom_poll(strom_ctx *ctx, uint64_t ticket, strom_info *out, double *X_svec,
+                        double *y, double *S_svec);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
