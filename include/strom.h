@@ -62,9 +62,9 @@ typedef struct strom_sdp strom_sdp; /* one per SDP instance: device data, factor
  * this library's choices.  strom_default_opts fills:
  *   sigma0 = 1, tau = 1.6, eps_reg = 1e-12 (eps = eps_reg * max_i (A A^*)_ii), tol = 1e-6,
  *   maxiter = 100000, kkt_every = 10, proj_dtype = STROM_F64, polish_eta = 1e-5,
- *   sigma_every = 50 (residual balancing: every sigma_every iterations sigma is doubled
- *   when eta_d > 5 eta_p and halved when eta_p > 5 eta_d, clamped to [1e-4, 1e4];
- *   0 keeps sigma fixed).  sigma_every must be a multiple of kkt_every (or 0). */
+ *   sigma_every = 50 (every sigma_every iterations, with rho = max(eta_p, eta_g) / eta_d,
+ *   sigma is divided by 1.5 when rho > 10 and multiplied by 1.5 when rho < 3, clamped to
+ *   [1e-4, 1e4]; 0 keeps sigma fixed).  sigma_every must be a multiple of kkt_every (or 0). */
 typedef struct {
   double sigma0;
   double tau;
@@ -131,6 +131,15 @@ strom_status strom_admm_step(strom_sdp *sdp, int32_t n_iter, strom_info *info);
  * (the residual-balancing sigma rule still runs on the device).  Used for timing. */
 strom_status strom_admm_enqueue(strom_sdp *sdp, int32_t n_iter);
 
+/* Mean device time per iteration of each phase, measured with HIP events on the instance's
+ * stream over `reps` real iterations (the iterate advances as with strom_admm_enqueue;
+ * residuals are evaluated every iteration).  rhs and solve include both right-hand sides /
+ * both y-solves of an iteration; project is the PSD projection of every block. */
+typedef struct {
+  double rhs_ms, solve_ms, xb_ms, project_ms, xupdate_ms, kkt_ms, iteration_ms;
+} strom_phase_times;
+strom_status strom_profile_iteration(strom_sdp *sdp, int32_t reps, strom_phase_times *out);
+
 /* KKT residuals of the current iterate (termination-rule equation), FP64; synchronizes. */
 strom_status strom_kkt_residuals(strom_sdp *sdp, strom_info *out);
 
@@ -146,9 +155,11 @@ strom_status strom_sdp_sizes(strom_sdp *sdp, int64_t *n_svec, int32_t *m, int64_
  * projection of Sec. "GPU Speedup": eigendecomposition, negative eigenvalues set to zero,
  * reconstruction).  Block k is n_dev[k] x n_dev[k], column-major, starting at element
  * offset_dev[k] of in_dev / out_dev; in and out may alias.  n_dev, offset_dev, in_dev and
- * out_dev are device pointers; max_n (host) bounds every n_dev[k] and must be <= 116 for
- * F64, <= 160 for F32.  dtype selects double or float data.  Only the upper triangle of
- * each input block is read; the output block is exactly symmetric. */
+ * out_dev are device pointers; max_n (host) bounds every n_dev[k]; one block and its
+ * eigenvectors must fit the LDS of one workgroup (160 KiB on gfx950: max_n <= 112 for F64,
+ * <= 124 for F32 -- the eigenvectors are accumulated in double in both), else E_INVAL.  A block with n_dev[k] <= 0 or > max_n makes the call
+ * return E_INVAL (other blocks are still written).  dtype selects double or float data.
+ * Only the upper triangle of each input block is read; the output is exactly symmetric. */
 strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblocks, int32_t max_n,
                                        const int32_t *n_dev, const int64_t *offset_dev,
                                        const void *in_dev, void *out_dev, strom_dtype dtype,

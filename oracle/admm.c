@@ -15,8 +15,10 @@
  *   eta_g = |<C,X> - <b,y>| / (1 + |<C,X>| + |<b,y>|),
  * two-norms on R^m and Frobenius norms (= 2-norms of svec) on Omega.
  * (A A^*)^{-1} is applied through the LDL^T factor of eps I + A A^* (ldl.c).
- * The paper fixes neither sigma nor its schedule: every `sigma_every` iterations sigma is
- * doubled when eta_d > 5 eta_p and halved when eta_p > 5 eta_d, kept in [1e-4, 1e4].
+ * The paper fixes neither sigma nor its schedule.  Every `sigma_every` iterations the primal
+ * infeasibility r_P = max(eta_p, eta_K), with eta_K = ||X - Pi(X)|| / (1 + ||X||) the distance
+ * of X from the cone, is balanced against eta_d: sigma is multiplied by 1.5 when
+ * eta_d > 3 r_P and divided by 1.5 when r_P > 3 eta_d, kept in [1e-4, 1e4].
  */
 #include <math.h>
 #include <stdlib.h>
@@ -188,8 +190,18 @@ int orc_admm_solve(int32_t nblocks, const int32_t *bsize, int32_t m, const int64
     if (!(info->eta == info->eta)) break; /* NaN: diverged */
     if (info->eta <= o.tol) { info->converged = 1; it++; break; }
     if (o.sigma_every > 0 && (it + 1) % o.sigma_every == 0) {
-      if (info->eta_d > 5.0 * info->eta_p) sigma = fmin(2.0 * sigma, 1e4);
-      else if (info->eta_p > 5.0 * info->eta_d) sigma = fmax(0.5 * sigma, 1e-4);
+      /* primal infeasibility including the cone: eta_K = ||X - Pi(X)|| / (1 + ||X||) */
+      orc_project_svec(nblocks, bsize, X, P);
+      double dk = 0.0, nx = 0.0;
+      for (int64_t i = 0; i < n; ++i) {
+        const double d = P[i] - X[i];
+        dk += d * d;
+        nx += X[i] * X[i];
+      }
+      const double eta_k = sqrt(dk) / (1.0 + sqrt(nx));
+      const double rp = fmax(info->eta_p, eta_k);
+      if (info->eta_d > 3.0 * rp) sigma = fmin(sigma * 1.5, 1e4);
+      else if (rp > 3.0 * info->eta_d) sigma = fmax(sigma / 1.5, 1e-4);
     }
   }
   info->iters = it;

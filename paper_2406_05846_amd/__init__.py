@@ -1,0 +1,292 @@
+"""MI355X sGS-ADMM solver for the PSD-only SDPs of sparse moment relaxations.
+
+Thin ctypes binding of ``libstrom.so`` (include/strom.h, include/strom_gen.h): every call
+marshals arguments and forwards to the C ABI; every step of the ADMM iteration runs in the
+library's HIP kernels.  PyTorch is used only for device memory and streams.  Importing this
+package fails loudly when the native library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstrom.so")
+
+F64, F32 = 0, 1
+RUNNING, CONVERGED, MAXITER, DIVERGED = 0, 1, 2, 3
+STATUS = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_HIP", -4: "E_FACTOR", -5: "E_AGAIN",
+          -6: "E_NOTFOUND", -7: "E_STATE"}
+EXPORTS = [
+    "strom_default_opts", "strom_last_error", "strom_ctx_create", "strom_ctx_destroy",
+    "strom_sdp_setup", "strom_sdp_destroy", "strom_admm_step", "strom_admm_enqueue",
+    "strom_kkt_residuals", "strom_get_iterate", "strom_set_iterate", "strom_sdp_sizes",
+    "strom_project_psd_batched", "strom_submit", "strom_poll", "strom_profile_iteration",
+    "strom_gen_build", "strom_gen_sizes", "strom_gen_export", "strom_gen_free",
+]
+
+
+class StromError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(C.Structure):
+    _fields_ = [("sigma0", C.c_double), ("tau", C.c_double), ("eps_reg", C.c_double), ("tol", C.c_double),
+                ("maxiter", C.c_int64), ("kkt_every", C.c_int32), ("proj_dtype", C.c_int32),
+                ("polish_eta", C.c_double), ("sigma_every", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("eta_p", C.c_double), ("eta_d", C.c_double), ("eta_g", C.c_double), ("pobj", C.c_double),
+                ("dobj", C.c_double), ("sigma", C.c_double), ("iters", C.c_int64), ("state", C.c_int32),
+                ("t_queue_s", C.c_double), ("t_setup_s", C.c_double), ("t_solve_s", C.c_double)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["eta"] = max(d["eta_p"], d["eta_d"], d["eta_g"])
+        return d
+
+
+class Problem_(C.Structure):
+    _fields_ = [("nblocks", C.c_int32), ("block_sizes", C.c_void_p), ("m", C.c_int32), ("nnz", C.c_int64),
+                ("A_rowptr", C.c_void_p), ("A_col", C.c_void_p), ("A_val", C.c_void_p), ("b", C.c_void_p),
+                ("C_svec", C.c_void_p), ("X0_svec", C.c_void_p), ("S0_svec", C.c_void_p)]
+
+
+class PhaseTimes(C.Structure):
+    _fields_ = [("rhs_ms", C.c_double), ("solve_ms", C.c_double), ("xb_ms", C.c_double),
+                ("project_ms", C.c_double), ("xupdate_ms", C.c_double), ("kkt_ms", C.c_double),
+                ("iteration_ms", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.strom_default_opts.argtypes = [C.POINTER(Opts)]
+    L.strom_last_error.restype = C.c_char_p
+    L.strom_ctx_create.argtypes = [C.c_int, vp, C.c_size_t, C.POINTER(vp)]
+    L.strom_ctx_destroy.argtypes = [vp]
+    L.strom_sdp_setup.argtypes = [vp, C.POINTER(Problem_), C.POINTER(Opts), C.POINTER(vp)]
+    L.strom_sdp_destroy.argtypes = [vp]
+    L.strom_admm_step.argtypes = [vp, i32, C.POINTER(Info)]
+    L.strom_admm_enqueue.argtypes = [vp, i32]
+    L.strom_kkt_residuals.argtypes = [vp, C.POINTER(Info)]
+    L.strom_get_iterate.argtypes = [vp, vp, vp, vp]
+    L.strom_set_iterate.argtypes = [vp, vp, vp, vp]
+    L.strom_sdp_sizes.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64)]
+    L.strom_project_psd_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp, C.c_int, vp]
+    L.strom_submit.argtypes = [vp, C.POINTER(Problem_), C.POINTER(Opts), C.POINTER(C.c_uint64)]
+    L.strom_poll.argtypes = [vp, C.c_uint64, C.POINTER(Info), vp, vp, vp]
+    L.strom_profile_iteration.argtypes = [vp, i32, C.POINTER(PhaseTimes)]
+    L.strom_gen_build.argtypes = [C.c_int, C.c_int, vp, C.c_int, C.POINTER(vp)]
+    L.strom_gen_sizes.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), C.POINTER(i64)]
+    L.strom_gen_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.strom_gen_free.argtypes = [vp]
+    for name in EXPORTS:
+        if name not in ("strom_default_opts", "strom_last_error", "strom_gen_free"):
+            getattr(L, name).restype = C.c_int
+    return L
+
+
+_L = _load()
+
+
+def lib():
+    return _L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise StromError(rc, _L.strom_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    _L.strom_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if k == "proj_dtype" and isinstance(v, str):
+            v = F32 if v.lower() in ("f32", "fp32", "float32") else F64
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """Host copy of one SDP in the C ABI's layout (svec columns, CSR rows)."""
+
+    def __init__(self, block_sizes, rowptr, col, val, b, C_svec, X0=None, S0=None, row_kind=None):
+        self.block_sizes = np.ascontiguousarray(block_sizes, dtype=np.int32)
+        self.rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.val = np.ascontiguousarray(val, dtype=np.float64)
+        self.b = np.ascontiguousarray(b, dtype=np.float64)
+        self.C = np.ascontiguousarray(C_svec, dtype=np.float64)
+        self.X0 = None if X0 is None else np.ascontiguousarray(X0, dtype=np.float64)
+        self.S0 = None if S0 is None else np.ascontiguousarray(S0, dtype=np.float64)
+        self.row_kind = row_kind
+        self.m = len(self.b)
+        self.nsvec = len(self.C)
+        self.nnz = len(self.col)
+
+    def _c(self) -> Problem_:
+        p = Problem_()
+        p.nblocks = len(self.block_sizes)
+        p.block_sizes = _ptr(self.block_sizes)
+        p.m = self.m
+        p.nnz = self.nnz
+        p.A_rowptr = _ptr(self.rowptr)
+        p.A_col = _ptr(self.col)
+        p.A_val = _ptr(self.val)
+        p.b = _ptr(self.b)
+        p.C_svec = _ptr(self.C)
+        p.X0_svec = _ptr(self.X0)
+        p.S0_svec = _ptr(self.S0)
+        return p
+
+
+def generate(family: int, N: int, params) -> Problem:
+    """Relaxation of one trajectory problem (strom_gen_build)."""
+    prm = np.ascontiguousarray(params, dtype=np.float64)
+    h = C.c_void_p()
+    _check(_L.strom_gen_build(int(family), int(N), _ptr(prm), len(prm), C.byref(h)))
+    try:
+        nb, m, nnz, n = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64()
+        _check(_L.strom_gen_sizes(h, C.byref(nb), C.byref(m), C.byref(nnz), C.byref(n)))
+        bs = np.zeros(nb.value, np.int32)
+        rp = np.zeros(m.value + 1, np.int64)
+        ci = np.zeros(nnz.value, np.int32)
+        av = np.zeros(nnz.value, np.float64)
+        b = np.zeros(m.value, np.float64)
+        Cv = np.zeros(n.value, np.float64)
+        kind = np.zeros(m.value, np.int32)
+        _check(_L.strom_gen_export(h, _ptr(bs), _ptr(rp), _ptr(ci), _ptr(av), _ptr(b), _ptr(Cv), _ptr(kind)))
+    finally:
+        _L.strom_gen_free(h)
+    return Problem(bs, rp, ci, av, b, Cv, row_kind=kind)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+class Context:
+    """One device: stream, HBM budget and the serving queue (strom_ctx)."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0):
+        import weakref
+        self._h = C.c_void_p()
+        self._instances = weakref.WeakSet()
+        _check(_L.strom_ctx_create(int(device), _stream_handle(stream), C.c_size_t(hbm_budget), C.byref(self._h)))
+
+    def close(self):
+        """Destroy the context; instances still alive on it are destroyed first."""
+        if self._h:
+            for inst in list(self._instances):
+                inst.close()
+            _check(_L.strom_ctx_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, problem: Problem, opts: Opts | None = None) -> int:
+        t = C.c_uint64()
+        p = problem._c()
+        _check(_L.strom_submit(self._h, C.byref(p), C.byref(opts) if opts is not None else None, C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, nsvec: int | None = None, m: int | None = None):
+        """None while in flight, else (info dict, X, y, S) (arrays only if sizes are given)."""
+        info = Info()
+        X = np.zeros(nsvec) if nsvec else None
+        S = np.zeros(nsvec) if nsvec else None
+        y = np.zeros(m) if m else None
+        rc = _L.strom_poll(self._h, C.c_uint64(ticket), C.byref(info), _ptr(X), _ptr(y), _ptr(S))
+        if rc == -5:
+            return None
+        _check(rc)
+        return info.as_dict(), X, y, S
+
+    def project_psd_batched(self, n_dev, offset_dev, inp, out, max_n: int, stream=None):
+        """Project dense column-major blocks (torch device tensors) onto the PSD cone."""
+        import torch
+        dt = F32 if inp.dtype == torch.float32 else F64
+        _check(_L.strom_project_psd_batched(self._h, int(n_dev.numel()), int(max_n), C.c_void_p(n_dev.data_ptr()),
+                                            C.c_void_p(offset_dev.data_ptr()), C.c_void_p(inp.data_ptr()),
+                                            C.c_void_p(out.data_ptr()), dt, _stream_handle(stream)))
+
+
+class Instance:
+    """One SDP on the device (strom_sdp)."""
+
+    def __init__(self, ctx: Context, problem: Problem, opts: Opts | None = None):
+        self.ctx = ctx
+        self._h = C.c_void_p()
+        p = problem._c()
+        if not ctx._h:
+            raise StromError(-7, "context is closed")
+        _check(_L.strom_sdp_setup(ctx._h, C.byref(p), C.byref(opts) if opts is not None else None,
+                                  C.byref(self._h)))
+        ctx._instances.add(self)
+        n, m, nl = C.c_int64(), C.c_int32(), C.c_int64()
+        _check(_L.strom_sdp_sizes(self._h, C.byref(n), C.byref(m), C.byref(nl)))
+        self.nsvec, self.m, self.nnzL = n.value, m.value, nl.value
+
+    def close(self):
+        if self._h:
+            _check(_L.strom_sdp_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n_iter: int) -> dict:
+        info = Info()
+        _check(_L.strom_admm_step(self._h, int(n_iter), C.byref(info)))
+        return info.as_dict()
+
+    def enqueue(self, n_iter: int):
+        _check(_L.strom_admm_enqueue(self._h, int(n_iter)))
+
+    def kkt(self) -> dict:
+        info = Info()
+        _check(_L.strom_kkt_residuals(self._h, C.byref(info)))
+        return info.as_dict()
+
+    def get_iterate(self):
+        X = np.zeros(self.nsvec)
+        y = np.zeros(self.m)
+        S = np.zeros(self.nsvec)
+        _check(_L.strom_get_iterate(self._h, _ptr(X), _ptr(y), _ptr(S)))
+        return X, y, S
+
+    def set_iterate(self, X=None, y=None, S=None):
+        X = None if X is None else np.ascontiguousarray(X, dtype=np.float64)
+        y = None if y is None else np.ascontiguousarray(y, dtype=np.float64)
+        S = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
+        _check(_L.strom_set_iterate(self._h, _ptr(X), _ptr(y), _ptr(S)))
+
+    def profile(self, reps: int = 10) -> dict:
+        t = PhaseTimes()
+        _check(_L.strom_profile_iteration(self._h, int(reps), C.byref(t)))
+        return {f: getattr(t, f) for f, _ in t._fields_}

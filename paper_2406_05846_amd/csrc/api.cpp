@@ -1,0 +1,630 @@
+// api.cpp -- the C ABI of include/strom.h: contexts, instance setup and upload, the device
+// iteration driver, KKT readback and the dense batched projection.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/strom.h"
+#include "kernels.h"
+#include "serve.h"
+#include "strom_internal.h"
+
+using strom::dev::DevState;
+
+namespace {
+thread_local std::string g_err;
+
+strom_status fail(strom_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(STROM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Bump allocator over one device allocation.
+struct Arena {
+  size_t bytes = 0;
+  template <typename T>
+  size_t reserve(size_t count) {
+    const size_t off = bytes;
+    bytes += ((count * sizeof(T) + 255) / 256) * 256;
+    return off;
+  }
+};
+}  // namespace
+
+struct strom_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  size_t used = 0;
+  int32_t *err_flag = nullptr;  // device flag of the dense projection
+  int64_t live = 0;             // instances set up directly (not through the server)
+  size_t max_lds = 0;
+  std::mutex mu;
+  strom::Server *server = nullptr;
+};
+
+struct strom_sdp {
+  strom_ctx *ctx = nullptr;
+  hipStream_t stream = nullptr;  // stream the instance is enqueued on (the ctx stream by default)
+  strom_opts opts{};
+  int32_t m = 0, nblocks = 0;
+  int64_t nsvec = 0, nnz = 0, nnzL = 0;
+  unsigned char *arena = nullptr;
+  size_t arena_bytes = 0;
+  // device arrays
+  int64_t *A_rp = nullptr; int32_t *A_ci = nullptr; double *A_v = nullptr;
+  int64_t *At_rp = nullptr; int32_t *At_ci = nullptr; double *At_v = nullptr;
+  double *b = nullptr, *C = nullptr, *X = nullptr, *S = nullptr, *Xb = nullptr, *y = nullptr, *w = nullptr;
+  int32_t *pinv = nullptr;
+  int64_t *boff = nullptr; int32_t *bsz = nullptr; int32_t *blk_ids = nullptr;
+  DevState *st = nullptr;
+  double *part_rows = nullptr, *part_cols = nullptr, *part_cone = nullptr;
+  strom::dev::SolveArgs sa{};
+  strom::dev::SolveSchedule sch;
+  std::vector<int> cls_n, cls_off, cls_cnt;  // projection launches, one per block size
+  double normb = 0, normC = 0;
+  int64_t iters = 0;
+  strom_solve_state state = STROM_RUNNING;
+  double t_setup = 0, t_solve = 0;
+  DevState *st_host = nullptr;  // pinned mirror
+  int32_t max_n = 0;
+};
+
+extern "C" void strom_default_opts(strom_opts *o) {
+  if (!o) return;
+  o->sigma0 = 1.0;
+  o->tau = 1.6;
+  o->eps_reg = 1e-12;
+  o->tol = 1e-6;
+  o->maxiter = 100000;
+  o->kkt_every = 10;
+  o->proj_dtype = STROM_F64;
+  o->polish_eta = 1e-5;
+  o->sigma_every = 50;
+}
+
+extern "C" const char *strom_last_error(void) { return g_err.c_str(); }
+
+extern "C" strom_status strom_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, strom_ctx **out) {
+  if (!out) return fail(STROM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(STROM_E_INVAL, "bad device index");
+  HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  auto *c = new strom_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->budget = hbm_budget_bytes;
+  c->max_lds = prop.sharedMemPerBlock;
+  if (hipMalloc(&c->err_flag, 256) != hipSuccess) {
+    delete c;
+    return fail(STROM_E_NOMEM, "hipMalloc of the context flag failed");
+  }
+  *out = c;
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_ctx_destroy(strom_ctx *c) {
+  if (!c) return fail(STROM_E_INVAL, "ctx is NULL");
+  if (c->server) { strom::server_stop(c->server); c->server = nullptr; }
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->live > 0) return fail(STROM_E_STATE, std::to_string(c->live) + " instance(s) still set up on this ctx");
+  }
+  hipSetDevice(c->device);
+  hipFree(c->err_flag);
+  delete c;
+  return STROM_OK;
+}
+
+static size_t proj_need(int n, bool f32) {
+  return strom::dev::project_lds_bytes(n, f32, strom::dev::project_threads(n));
+}
+
+extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, const strom_opts *opts,
+                                        strom_sdp **out) {
+  if (!ctx || !P || !out) return fail(STROM_E_INVAL, "NULL argument");
+  *out = nullptr;
+  const double t0 = now_s();
+  strom_opts o;
+  if (opts) o = *opts; else strom_default_opts(&o);
+  if (!(o.sigma0 > 0) || !(o.tau > 0 && o.tau < 2) || o.kkt_every <= 0 || o.maxiter <= 0 || o.sigma_every < 0 ||
+      (o.sigma_every > 0 && o.sigma_every % o.kkt_every != 0))
+    return fail(STROM_E_INVAL, "invalid options");
+  if (!P->A_rowptr || !P->A_col || !P->A_val || !P->b || !P->C_svec || !P->block_sizes)
+    return fail(STROM_E_INVAL, "NULL problem array");
+  if (P->nnz != (P->m > 0 ? P->A_rowptr[P->m] : 0)) return fail(STROM_E_INVAL, "nnz != rowptr[m]");
+  strom::HostAnalysis H;
+  std::string err;
+  strom_status rc = strom::analyze_instance(P->nblocks, P->block_sizes, P->m, P->A_rowptr, P->A_col, P->A_val,
+                                            o.eps_reg, H, err);
+  if (rc != STROM_OK) return fail(rc, err);
+  int32_t max_n = 0;
+  for (int32_t n : H.bsize) max_n = std::max(max_n, n);
+  const bool f32 = o.proj_dtype == STROM_F32;
+  if (proj_need(max_n, false) > ctx->max_lds || (f32 && proj_need(max_n, true) > ctx->max_lds))
+    return fail(STROM_E_INVAL, "block of size " + std::to_string(max_n) + " does not fit the LDS of one workgroup");
+
+  auto *s = new strom_sdp();
+  s->ctx = ctx;
+  s->stream = ctx->stream;
+  s->opts = o;
+  s->m = P->m;
+  s->nblocks = P->nblocks;
+  s->nsvec = H.nsvec;
+  s->nnz = P->nnz;
+  s->nnzL = H.nnzL;
+  s->max_n = max_n;
+  const int32_t m = P->m;
+  const int64_t n = H.nsvec, nnz = P->nnz;
+  const int ntask = int(H.task_r0.size());
+  const int nrb = (m + 255) / 256, ncb = int((n + 255) / 256);
+
+  // projection launches: blocks grouped by size
+  std::map<int, std::vector<int32_t>> by_n;
+  for (int32_t k = 0; k < P->nblocks; ++k) by_n[H.bsize[size_t(k)]].push_back(k);
+  std::vector<int32_t> ids;
+  for (auto &kv : by_n) {
+    s->cls_n.push_back(kv.first);
+    s->cls_off.push_back(int(ids.size()));
+    s->cls_cnt.push_back(int(kv.second.size()));
+    ids.insert(ids.end(), kv.second.begin(), kv.second.end());
+  }
+
+  Arena ar;
+  const size_t oArp = ar.reserve<int64_t>(size_t(m) + 1), oAci = ar.reserve<int32_t>(size_t(nnz)),
+               oAv = ar.reserve<double>(size_t(nnz));
+  const size_t oTrp = ar.reserve<int64_t>(size_t(n) + 1), oTci = ar.reserve<int32_t>(size_t(nnz)),
+               oTv = ar.reserve<double>(size_t(nnz));
+  const size_t ob = ar.reserve<double>(size_t(m)), oC = ar.reserve<double>(size_t(n)),
+               oX = ar.reserve<double>(size_t(n)), oS = ar.reserve<double>(size_t(n)),
+               oXb = ar.reserve<double>(size_t(n)), oy = ar.reserve<double>(size_t(m)),
+               ow = ar.reserve<double>(size_t(m));
+  const size_t operm = ar.reserve<int32_t>(size_t(m)), opinv = ar.reserve<int32_t>(size_t(m));
+  const size_t oLrp = ar.reserve<int64_t>(size_t(m) + 1), oLci = ar.reserve<int32_t>(H.Lci.size()),
+               oLv = ar.reserve<double>(H.Lv.size());
+  const size_t oUrp = ar.reserve<int64_t>(size_t(m) + 1), oUci = ar.reserve<int32_t>(H.Uci.size()),
+               oUv = ar.reserve<double>(H.Uv.size());
+  const size_t oD = ar.reserve<double>(size_t(m));
+  const size_t oInv = ar.reserve<double>(std::max<size_t>(1, H.inv.size())),
+               oInvT = ar.reserve<double>(std::max<size_t>(1, H.invT.size()));
+  const size_t oTk = ar.reserve<int32_t>(size_t(ntask) * 7), oTinv = ar.reserve<int64_t>(size_t(ntask));
+  const size_t oFl = ar.reserve<int32_t>(std::max<size_t>(1, H.flevptr.size())),
+               oFr = ar.reserve<int32_t>(std::max<size_t>(1, H.frows.size())),
+               oBl = ar.reserve<int32_t>(std::max<size_t>(1, H.blevptr.size())),
+               oBr = ar.reserve<int32_t>(std::max<size_t>(1, H.brows.size()));
+  const size_t oFo = ar.reserve<int32_t>(H.fwd_order.size()), oBo = ar.reserve<int32_t>(H.bwd_order.size());
+  const size_t oBoff = ar.reserve<int64_t>(size_t(P->nblocks)), oBsz = ar.reserve<int32_t>(size_t(P->nblocks)),
+               oIds = ar.reserve<int32_t>(ids.size());
+  const size_t oSt = ar.reserve<DevState>(1);
+  const size_t oPr = ar.reserve<double>(2 * size_t(nrb)), oPc = ar.reserve<double>(2 * size_t(ncb)),
+               oPk = ar.reserve<double>(2 * size_t(ncb));
+  s->arena_bytes = ar.bytes;
+
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->budget && ctx->used + ar.bytes > ctx->budget) {
+      delete s;
+      return fail(STROM_E_NOMEM, "instance needs " + std::to_string(ar.bytes) + " bytes, over the HBM budget");
+    }
+    ctx->used += ar.bytes;
+    ctx->live++;
+  }
+  auto undo = [&](strom_status st, const std::string &msg) {
+    { std::lock_guard<std::mutex> lk(ctx->mu); ctx->used -= s->arena_bytes; ctx->live--; }
+    if (s->arena) hipFree(s->arena);
+    if (s->st_host) hipHostFree(s->st_host);
+    delete s;
+    return fail(st, msg);
+  };
+  if (hipSetDevice(ctx->device) != hipSuccess) return undo(STROM_E_HIP, "hipSetDevice failed");
+  if (hipMalloc(&s->arena, ar.bytes) != hipSuccess) return undo(STROM_E_NOMEM, "hipMalloc of the instance failed");
+  if (hipHostMalloc(&s->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+    return undo(STROM_E_NOMEM, "hipHostMalloc failed");
+  unsigned char *base = s->arena;
+  auto P64 = [&](size_t o) { return reinterpret_cast<int64_t *>(base + o); };
+  auto P32 = [&](size_t o) { return reinterpret_cast<int32_t *>(base + o); };
+  auto PD = [&](size_t o) { return reinterpret_cast<double *>(base + o); };
+  s->A_rp = P64(oArp); s->A_ci = P32(oAci); s->A_v = PD(oAv);
+  s->At_rp = P64(oTrp); s->At_ci = P32(oTci); s->At_v = PD(oTv);
+  s->b = PD(ob); s->C = PD(oC); s->X = PD(oX); s->S = PD(oS); s->Xb = PD(oXb); s->y = PD(oy); s->w = PD(ow);
+  s->pinv = P32(opinv);
+  s->boff = P64(oBoff); s->bsz = P32(oBsz); s->blk_ids = P32(oIds);
+  s->st = reinterpret_cast<DevState *>(base + oSt);
+  s->part_rows = PD(oPr); s->part_cols = PD(oPc); s->part_cone = PD(oPk);
+  int32_t *tk = P32(oTk);
+  auto &sa = s->sa;
+  sa.task_r0 = tk; sa.task_r1 = tk + ntask; sa.task_type = tk + 2 * ntask; sa.task_flev0 = tk + 3 * ntask;
+  sa.task_fnlev = tk + 4 * ntask; sa.task_blev0 = tk + 5 * ntask; sa.task_bnlev = tk + 6 * ntask;
+  sa.task_inv = P64(oTinv);
+  sa.flevptr = P32(oFl); sa.frows = P32(oFr); sa.blevptr = P32(oBl); sa.brows = P32(oBr);
+  sa.Lrp = P64(oLrp); sa.Lci = P32(oLci); sa.Lv = PD(oLv);
+  sa.Urp = P64(oUrp); sa.Uci = P32(oUci); sa.Uv = PD(oUv);
+  sa.D = PD(oD); sa.inv = PD(oInv); sa.invT = PD(oInvT); sa.perm = P32(operm);
+  s->sch.fwd_gptr = H.fwd_gptr;
+  s->sch.bwd_gptr = H.bwd_gptr;
+  s->sch.fwd_order_dev = P32(oFo);
+  s->sch.bwd_order_dev = P32(oBo);
+  s->sch.max_dense_rows = H.max_dense_rows;
+
+  // host staging of the small arrays, then synchronous uploads
+  std::vector<int32_t> tkh(size_t(ntask) * 7);
+  for (int t = 0; t < ntask; ++t) {
+    tkh[size_t(t)] = H.task_r0[size_t(t)];
+    tkh[size_t(ntask + t)] = H.task_r1[size_t(t)];
+    tkh[size_t(2 * ntask + t)] = H.task_type[size_t(t)];
+    tkh[size_t(3 * ntask + t)] = H.task_flev0[size_t(t)];
+    tkh[size_t(4 * ntask + t)] = H.task_fnlev[size_t(t)];
+    tkh[size_t(5 * ntask + t)] = H.task_blev0[size_t(t)];
+    tkh[size_t(6 * ntask + t)] = H.task_bnlev[size_t(t)];
+  }
+  std::vector<double> zeros;
+  auto up = [&](const void *dst, const void *src, size_t bytes) -> bool {
+    return bytes == 0 || hipMemcpy(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  bool ok = true;
+  ok &= up(s->A_rp, P->A_rowptr, sizeof(int64_t) * (size_t(m) + 1));
+  ok &= up(s->A_ci, P->A_col, sizeof(int32_t) * size_t(nnz));
+  ok &= up(s->A_v, P->A_val, sizeof(double) * size_t(nnz));
+  ok &= up(s->At_rp, H.Atrp.data(), sizeof(int64_t) * H.Atrp.size());
+  ok &= up(s->At_ci, H.Atci.data(), sizeof(int32_t) * H.Atci.size());
+  ok &= up(s->At_v, H.Atv.data(), sizeof(double) * H.Atv.size());
+  ok &= up(s->b, P->b, sizeof(double) * size_t(m));
+  ok &= up(s->C, P->C_svec, sizeof(double) * size_t(n));
+  ok &= hipMemset(s->X, 0, sizeof(double) * size_t(n)) == hipSuccess;
+  ok &= hipMemset(s->S, 0, sizeof(double) * size_t(n)) == hipSuccess;
+  ok &= hipMemset(s->y, 0, sizeof(double) * size_t(m)) == hipSuccess;
+  if (P->X0_svec) ok &= up(s->X, P->X0_svec, sizeof(double) * size_t(n));
+  if (P->S0_svec) ok &= up(s->S, P->S0_svec, sizeof(double) * size_t(n));
+  ok &= up(sa.perm, H.perm.data(), sizeof(int32_t) * size_t(m));
+  ok &= up(s->pinv, H.pinv.data(), sizeof(int32_t) * size_t(m));
+  ok &= up(const_cast<int64_t *>(sa.Lrp), H.Lrp.data(), sizeof(int64_t) * H.Lrp.size());
+  ok &= up(const_cast<int32_t *>(sa.Lci), H.Lci.data(), sizeof(int32_t) * H.Lci.size());
+  ok &= up(const_cast<double *>(sa.Lv), H.Lv.data(), sizeof(double) * H.Lv.size());
+  ok &= up(const_cast<int64_t *>(sa.Urp), H.Urp.data(), sizeof(int64_t) * H.Urp.size());
+  ok &= up(const_cast<int32_t *>(sa.Uci), H.Uci.data(), sizeof(int32_t) * H.Uci.size());
+  ok &= up(const_cast<double *>(sa.Uv), H.Uv.data(), sizeof(double) * H.Uv.size());
+  ok &= up(const_cast<double *>(sa.D), H.D.data(), sizeof(double) * H.D.size());
+  ok &= up(const_cast<double *>(sa.inv), H.inv.data(), sizeof(double) * H.inv.size());
+  ok &= up(const_cast<double *>(sa.invT), H.invT.data(), sizeof(double) * H.invT.size());
+  ok &= up(tk, tkh.data(), sizeof(int32_t) * tkh.size());
+  ok &= up(const_cast<int64_t *>(sa.task_inv), H.task_inv.data(), sizeof(int64_t) * H.task_inv.size());
+  ok &= up(const_cast<int32_t *>(sa.flevptr), H.flevptr.data(), sizeof(int32_t) * H.flevptr.size());
+  ok &= up(const_cast<int32_t *>(sa.frows), H.frows.data(), sizeof(int32_t) * H.frows.size());
+  ok &= up(const_cast<int32_t *>(sa.blevptr), H.blevptr.data(), sizeof(int32_t) * H.blevptr.size());
+  ok &= up(const_cast<int32_t *>(sa.brows), H.brows.data(), sizeof(int32_t) * H.brows.size());
+  ok &= up(const_cast<int32_t *>(s->sch.fwd_order_dev), H.fwd_order.data(), sizeof(int32_t) * H.fwd_order.size());
+  ok &= up(const_cast<int32_t *>(s->sch.bwd_order_dev), H.bwd_order.data(), sizeof(int32_t) * H.bwd_order.size());
+  ok &= up(s->boff, H.boff.data(), sizeof(int64_t) * size_t(P->nblocks));
+  ok &= up(s->bsz, H.bsize.data(), sizeof(int32_t) * size_t(P->nblocks));
+  ok &= up(s->blk_ids, ids.data(), sizeof(int32_t) * ids.size());
+  DevState st0{};
+  st0.sigma = o.sigma0;
+  st0.tau = o.tau;
+  st0.sigma_used = o.sigma0;
+  ok &= up(s->st, &st0, sizeof(DevState));
+  if (!ok) return undo(STROM_E_HIP, "upload of the instance failed");
+  double nb2 = 0, nc2 = 0;
+  for (int32_t i = 0; i < m; ++i) nb2 += P->b[i] * P->b[i];
+  for (int64_t c = 0; c < n; ++c) nc2 += P->C_svec[c] * P->C_svec[c];
+  s->normb = std::sqrt(nb2);
+  s->normC = std::sqrt(nc2);
+  s->t_setup = now_s() - t0;
+  *out = s;
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_sdp_destroy(strom_sdp *s) {
+  if (!s) return fail(STROM_E_INVAL, "sdp is NULL");
+  hipSetDevice(s->ctx->device);
+  hipStreamSynchronize(s->stream);
+  hipFree(s->arena);
+  hipHostFree(s->st_host);
+  {
+    std::lock_guard<std::mutex> lk(s->ctx->mu);
+    s->ctx->used -= s->arena_bytes;
+    s->ctx->live--;
+  }
+  delete s;
+  return STROM_OK;
+}
+
+namespace {
+
+// S_out = (Pi(X_in) - X_in) * scale for every block (scale <= 0: 1 / sigma).
+hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, double scale) {
+  const bool f32 = s->opts.proj_dtype == STROM_F32;
+  for (size_t c = 0; c < s->cls_n.size(); ++c) {
+    hipError_t e = strom::dev::launch_project_admm(s->stream, f32, s->cls_n[c], s->cls_cnt[c],
+                                                   s->blk_ids + s->cls_off[c], s->boff, s->bsz, X_in, S_out, s->st,
+                                                   scale);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Residuals of the current iterate (part_cols must hold the dual-residual partials); with
+// do_sigma, the cone distance of X (through the scratch X_b buffer) and the sigma rule.
+hipError_t enqueue_kkt(strom_sdp *s, bool do_sigma) {
+  if (do_sigma) {
+    hipError_t e = enqueue_projection(s, s->X, s->Xb, 1.0);
+    if (e != hipSuccess) return e;
+  }
+  return strom::dev::launch_kkt(s->stream, s->m, s->nsvec, s->A_rp, s->A_ci, s->A_v, s->X, s->b, s->y, s->part_rows,
+                                s->part_cols, s->Xb, s->part_cone, s->normb, s->normC, do_sigma ? 1 : 0, s->st);
+}
+
+// Enqueue one iteration (steps 1-4); with kkt, also the residuals of the new iterate.
+hipError_t enqueue_iteration(strom_sdp *s, bool kkt, bool do_sigma) {
+  hipStream_t q = s->stream;
+  hipError_t e;
+  // step 1
+  if ((e = strom::dev::launch_rhs(q, s->m, s->A_rp, s->A_ci, s->A_v, s->X, s->S, s->C, s->b, s->pinv, s->st, s->w)))
+    return e;
+  if ((e = strom::dev::launch_solve(q, s->sch, s->sa, s->w, s->y))) return e;
+  // step 2
+  if ((e = strom::dev::launch_xb(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->X, s->C, s->st, s->Xb))) return e;
+  if ((e = enqueue_projection(s, s->Xb, s->S, 0.0))) return e;
+  // step 3
+  if ((e = strom::dev::launch_rhs(q, s->m, s->A_rp, s->A_ci, s->A_v, s->X, s->S, s->C, s->b, s->pinv, s->st, s->w)))
+    return e;
+  if ((e = strom::dev::launch_solve(q, s->sch, s->sa, s->w, s->y))) return e;
+  // step 4
+  if ((e = strom::dev::launch_xupdate(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->S, s->C, s->st, s->X,
+                                      kkt ? s->part_cols : nullptr, 1)))
+    return e;
+  if (kkt)
+    if ((e = enqueue_kkt(s, do_sigma))) return e;
+  return hipSuccess;
+}
+
+void fill_info(const strom_sdp *s, strom_info *info) {
+  const DevState &d = *s->st_host;
+  info->eta_p = d.eta_p;
+  info->eta_d = d.eta_d;
+  info->eta_g = d.eta_g;
+  info->pobj = d.pobj;
+  info->dobj = d.dobj;
+  info->sigma = d.sigma;
+  info->iters = s->iters;
+  info->state = s->state;
+  info->t_queue_s = 0;
+  info->t_setup_s = s->t_setup;
+  info->t_solve_s = s->t_solve;
+}
+
+strom_solve_state classify(const strom_sdp *s) {
+  const DevState &d = *s->st_host;
+  const double eta = std::max(d.eta_p, std::max(d.eta_d, d.eta_g));
+  if (!std::isfinite(eta)) return STROM_DIVERGED;
+  if (eta <= s->opts.tol) return STROM_CONVERGED;
+  if (s->iters >= s->opts.maxiter) return STROM_MAXITER;
+  return STROM_RUNNING;
+}
+
+}  // namespace
+
+namespace strom {
+// Used by the serving loop: enqueue n iterations without synchronizing; returns true when
+// residuals were computed on the last one.
+hipError_t sdp_enqueue(strom_sdp *s, int n_iter, bool kkt_last) {
+  for (int k = 0; k < n_iter; ++k) {
+    const int64_t it = s->iters;
+    const bool sig = s->opts.sigma_every > 0 && (it + 1) % s->opts.sigma_every == 0;
+    const bool kkt = sig || (kkt_last && k == n_iter - 1);
+    hipError_t e = enqueue_iteration(s, kkt, sig);
+    if (e != hipSuccess) return e;
+    s->iters++;
+  }
+  return hipSuccess;
+}
+hipError_t sdp_read_state(strom_sdp *s) {
+  hipError_t e = hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s->stream);
+}
+strom_solve_state sdp_classify(strom_sdp *s) { return s->state = classify(s); }
+void sdp_info(strom_sdp *s, strom_info *info) { fill_info(s, info); }
+const strom_opts &sdp_opts(strom_sdp *s) { return s->opts; }
+void sdp_set_stream(strom_sdp *s, hipStream_t q) { s->stream = q; }
+}  // namespace strom
+
+extern "C" strom_status strom_admm_step(strom_sdp *s, int32_t n_iter, strom_info *info) {
+  if (!s || n_iter < 0) return fail(STROM_E_INVAL, "bad argument");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  const double t0 = now_s();
+  const int kk = s->opts.kkt_every;
+  int done = 0;
+  s->state = STROM_RUNNING;
+  while (done < n_iter && s->iters < s->opts.maxiter) {
+    int chunk = int(std::min<int64_t>(kk - (s->iters % kk), int64_t(n_iter - done)));
+    chunk = int(std::min<int64_t>(chunk, s->opts.maxiter - s->iters));
+    HIP_TRY(strom::sdp_enqueue(s, chunk, true));
+    done += chunk;
+    HIP_TRY(strom::sdp_read_state(s));
+    if (classify(s) != STROM_RUNNING) break;
+  }
+  if (n_iter == 0) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  s->state = classify(s);
+  s->t_solve += now_s() - t0;
+  if (info) fill_info(s, info);
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_admm_enqueue(strom_sdp *s, int32_t n_iter) {
+  if (!s || n_iter < 0) return fail(STROM_E_INVAL, "bad argument");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  HIP_TRY(strom::sdp_enqueue(s, n_iter, false));
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_profile_iteration(strom_sdp *s, int32_t reps, strom_phase_times *out) {
+  if (!s || reps <= 0 || !out) return fail(STROM_E_INVAL, "bad argument");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t q = s->stream;
+  hipEvent_t ev[11];
+  for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+  double acc[6] = {0, 0, 0, 0, 0, 0}, total = 0;
+  strom_status rc = STROM_OK;
+  for (int r = 0; r < reps && rc == STROM_OK; ++r) {
+    const int64_t it = s->iters;
+    const bool sig = s->opts.sigma_every > 0 && (it + 1) % s->opts.sigma_every == 0;
+    hipError_t e = hipSuccess;
+    auto rec = [&](int k) { if (e == hipSuccess) e = hipEventRecord(ev[k], q); };
+    rec(0);
+    if (!e) e = strom::dev::launch_rhs(q, s->m, s->A_rp, s->A_ci, s->A_v, s->X, s->S, s->C, s->b, s->pinv, s->st, s->w);
+    rec(1);
+    if (!e) e = strom::dev::launch_solve(q, s->sch, s->sa, s->w, s->y);
+    rec(2);
+    if (!e) e = strom::dev::launch_xb(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->X, s->C, s->st, s->Xb);
+    rec(3);
+    if (!e) e = enqueue_projection(s, s->Xb, s->S, 0.0);
+    rec(4);
+    if (!e) e = strom::dev::launch_rhs(q, s->m, s->A_rp, s->A_ci, s->A_v, s->X, s->S, s->C, s->b, s->pinv, s->st, s->w);
+    rec(5);
+    if (!e) e = strom::dev::launch_solve(q, s->sch, s->sa, s->w, s->y);
+    rec(6);
+    if (!e) e = strom::dev::launch_xupdate(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->S, s->C, s->st, s->X,
+                                           s->part_cols, 1);
+    rec(7);
+    if (!e) e = enqueue_kkt(s, sig);
+    rec(8);
+    if (!e) e = hipEventSynchronize(ev[8]);
+    if (e) { rc = fail(STROM_E_HIP, std::string("profile: ") + hipGetErrorString(e)); break; }
+    s->iters++;
+    float ms[8];
+    for (int k = 0; k < 8; ++k) hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]);
+    acc[0] += ms[0] + ms[4];  // both right-hand sides
+    acc[1] += ms[1] + ms[5];  // both y-solves
+    acc[2] += ms[2];
+    acc[3] += ms[3];
+    acc[4] += ms[6];
+    acc[5] += ms[7];
+    float tot;
+    hipEventElapsedTime(&tot, ev[0], ev[8]);
+    total += tot;
+  }
+  for (auto &e : ev) hipEventDestroy(e);
+  if (rc != STROM_OK) return rc;
+  out->rhs_ms = acc[0] / reps;
+  out->solve_ms = acc[1] / reps;
+  out->xb_ms = acc[2] / reps;
+  out->project_ms = acc[3] / reps;
+  out->xupdate_ms = acc[4] / reps;
+  out->kkt_ms = acc[5] / reps;
+  out->iteration_ms = total / reps;
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_kkt_residuals(strom_sdp *s, strom_info *info) {
+  if (!s || !info) return fail(STROM_E_INVAL, "bad argument");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t q = s->stream;
+  // dual residual and <C,X> of the current iterate (no update), then the primal part
+  HIP_TRY(strom::dev::launch_xupdate(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->S, s->C, s->st, s->X,
+                                     s->part_cols, 0));
+  HIP_TRY(enqueue_kkt(s, false));
+  HIP_TRY(strom::sdp_read_state(s));
+  fill_info(s, info);
+  info->state = classify(s);
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_get_iterate(strom_sdp *s, double *X, double *y, double *S) {
+  if (!s) return fail(STROM_E_INVAL, "sdp is NULL");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (X) HIP_TRY(hipMemcpy(X, s->X, sizeof(double) * size_t(s->nsvec), hipMemcpyDeviceToHost));
+  if (y) HIP_TRY(hipMemcpy(y, s->y, sizeof(double) * size_t(s->m), hipMemcpyDeviceToHost));
+  if (S) HIP_TRY(hipMemcpy(S, s->S, sizeof(double) * size_t(s->nsvec), hipMemcpyDeviceToHost));
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_set_iterate(strom_sdp *s, const double *X, const double *y, const double *S) {
+  if (!s) return fail(STROM_E_INVAL, "sdp is NULL");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (X) HIP_TRY(hipMemcpy(s->X, X, sizeof(double) * size_t(s->nsvec), hipMemcpyHostToDevice));
+  if (y) HIP_TRY(hipMemcpy(s->y, y, sizeof(double) * size_t(s->m), hipMemcpyHostToDevice));
+  if (S) HIP_TRY(hipMemcpy(s->S, S, sizeof(double) * size_t(s->nsvec), hipMemcpyHostToDevice));
+  s->iters = 0;
+  s->state = STROM_RUNNING;
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_sdp_sizes(strom_sdp *s, int64_t *n_svec, int32_t *m, int64_t *nnz_L) {
+  if (!s) return fail(STROM_E_INVAL, "sdp is NULL");
+  if (n_svec) *n_svec = s->nsvec;
+  if (m) *m = s->m;
+  if (nnz_L) *nnz_L = s->nnzL;
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblocks, int32_t max_n,
+                                                  const int32_t *n_dev, const int64_t *offset_dev,
+                                                  const void *in_dev, void *out_dev, strom_dtype dtype,
+                                                  void *hip_stream) {
+  if (!ctx || nblocks < 0 || (nblocks > 0 && (!n_dev || !offset_dev || !in_dev || !out_dev)))
+    return fail(STROM_E_INVAL, "bad argument");
+  if (nblocks == 0) return STROM_OK;
+  const bool f32 = dtype == STROM_F32;
+  if (dtype != STROM_F32 && dtype != STROM_F64) return fail(STROM_E_INVAL, "bad dtype");
+  if (max_n <= 0 || proj_need(max_n, f32) > ctx->max_lds)
+    return fail(STROM_E_INVAL, "max_n out of range for the LDS of one workgroup");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t q = (hipStream_t)hip_stream;
+  HIP_TRY(hipMemsetAsync(ctx->err_flag, 0, sizeof(int32_t), q));
+  HIP_TRY(strom::dev::launch_project_dense(q, f32, nblocks, max_n, n_dev, offset_dev, in_dev, out_dev, ctx->err_flag));
+  int32_t flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, ctx->err_flag, sizeof(int32_t), hipMemcpyDeviceToHost, q));
+  HIP_TRY(hipStreamSynchronize(q));
+  if (flag) return fail(STROM_E_INVAL, "a block size is <= 0 or > max_n");
+  return STROM_OK;
+}
+
+// ------------------------------------------------------------------ serving entry points
+extern "C" strom_status strom_submit(strom_ctx *ctx, const strom_problem *P, const strom_opts *opts,
+                                     uint64_t *ticket) {
+  if (!ctx || !P || !ticket) return fail(STROM_E_INVAL, "NULL argument");
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->server) ctx->server = strom::server_start(ctx);
+  }
+  std::string err;
+  strom_status rc = strom::server_submit(ctx->server, P, opts, ticket, err);
+  if (rc != STROM_OK) return fail(rc, err);
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_poll(strom_ctx *ctx, uint64_t ticket, strom_info *out, double *X, double *y,
+                                   double *S) {
+  if (!ctx) return fail(STROM_E_INVAL, "ctx is NULL");
+  if (!ctx->server) return fail(STROM_E_NOTFOUND, "no submitted problems");
+  std::string err;
+  strom_status rc = strom::server_poll(ctx->server, ticket, out, X, y, S, err);
+  if (rc != STROM_OK && rc != STROM_E_AGAIN) return fail(rc, err);
+  if (rc == STROM_E_AGAIN) g_err = "in flight";
+  return rc;
+}

@@ -1,0 +1,68 @@
+// kernels.h -- device-side types and host launchers of the sGS-ADMM kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace strom {
+namespace dev {
+
+// Per-instance scalars that live in device memory, so that the iteration can be enqueued
+// without host round trips.
+struct DevState {
+  double sigma;       // current sigma
+  double tau;
+  double eta_p, eta_d, eta_g, pobj, dobj;
+  double sigma_used;  // sigma of the iteration the residuals belong to
+};
+
+// Device arrays of the triangular solves (see setup.cpp for their meaning).
+struct SolveArgs {
+  const int32_t *task_r0, *task_r1, *task_type;
+  const int32_t *task_flev0, *task_fnlev, *task_blev0, *task_bnlev;
+  const int64_t *task_inv;
+  const int32_t *flevptr, *frows, *blevptr, *brows;
+  const int64_t *Lrp;
+  const int32_t *Lci;
+  const double *Lv;
+  const int64_t *Urp;
+  const int32_t *Uci;
+  const double *Uv;
+  const double *D;
+  const double *inv, *invT;
+  const int32_t *perm;
+};
+
+struct SolveSchedule {
+  std::vector<int32_t> fwd_gptr, bwd_gptr;  // host: group boundaries
+  const int32_t *fwd_order_dev = nullptr, *bwd_order_dev = nullptr;
+  int32_t max_dense_rows = 0;
+};
+
+size_t project_lds_bytes(int n, bool f32, int nthreads);
+int project_threads(int n);
+
+hipError_t launch_rhs(hipStream_t s, int32_t m, const int64_t *rp, const int32_t *ci, const double *av,
+                      const double *X, const double *S, const double *C, const double *b, const int32_t *pinv,
+                      const DevState *st, double *w);
+hipError_t launch_solve(hipStream_t s, const SolveSchedule &sch, const SolveArgs &a, double *w, double *y);
+hipError_t launch_xb(hipStream_t s, int64_t n, const int64_t *trp, const int32_t *tci, const double *tv,
+                     const double *y, const double *X, const double *C, const DevState *st, double *Xb);
+// S = (Pi(X_b) - X_b) * scale for the listed blocks; scale <= 0 means 1 / sigma.
+hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const int32_t *ids, const int64_t *boff,
+                               const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale);
+hipError_t launch_project_dense(hipStream_t s, bool f32, int nblocks, int max_n, const int32_t *nd, const int64_t *od,
+                                const void *in, void *out, int32_t *err);
+hipError_t launch_xupdate(hipStream_t s, int64_t n, const int64_t *trp, const int32_t *tci, const double *tv,
+                          const double *y, const double *S, const double *C, const DevState *st, double *X,
+                          double *part, int update);
+// Residuals of the termination rule; with do_sigma also the sigma rule, which needs
+// cone_diff = Pi(X) - X (svec) for the cone distance of X.
+hipError_t launch_kkt(hipStream_t s, int32_t m, int64_t n, const int64_t *rp, const int32_t *ci, const double *av,
+                      const double *X, const double *b, const double *y, double *part_rows, const double *part_cols,
+                      const double *cone_diff, double *part_cone, double normb, double normC, int do_sigma,
+                      DevState *st);
+
+}  // namespace dev
+}  // namespace strom

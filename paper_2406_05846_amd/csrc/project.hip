@@ -1,0 +1,342 @@
+// project.hip -- projection of dense symmetric blocks onto the PSD cone (the parallel PSD cone
+// projection of the paper's Sec. "GPU Speedup": eigendecomposition, negative eigenvalues set
+// to zero, reconstruction), one workgroup per block with the block resident in LDS.
+//
+// Eigensolver: cyclic Jacobi in the round-robin parallel ordering.  In one round the n/2
+// disjoint pairs are rotated together, A <- J^T A J; the new value of every 2x2 block
+// (pair P1 x pair P2) depends only on its own four old entries, so each thread updates whole
+// 2x2 blocks of the packed upper triangle with no barrier inside the round.  The matrix is
+// held in T (double, or float for the reduced-precision form); the eigenvectors, the norms
+// and the reconstruction are always accumulated in double, which keeps the float form within
+// about 1e-6 of the double result.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace strom {
+namespace dev {
+
+__device__ inline int pidx(int i, int j) {  // packed upper triangle, by columns
+  if (i > j) { const int t = i; i = j; j = t; }
+  return j * (j + 1) / 2 + i;
+}
+
+__device__ inline void tri_ij(int k, int &i, int &j) {  // k -> (i <= j) of the packed index
+  j = (int)((sqrtf(8.0f * k + 1.0f) - 1.0f) * 0.5f);
+  while (j * (j + 1) / 2 > k) --j;
+  while ((j + 1) * (j + 2) / 2 <= k) ++j;
+  i = k - j * (j + 1) / 2;
+}
+
+// Pair k of round r of the circle schedule over nn (even) slots.
+__device__ inline void rr_pair(int r, int k, int nn, int &p, int &q) {
+  const int mm = nn - 1;
+  if (k == 0) { p = r; q = mm; }
+  else { p = (r + k) % mm; q = (r - k + mm) % mm; }
+  if (p > q) { const int t = p; p = q; q = t; }
+}
+
+template <typename T>
+struct JacobiTol;
+template <>
+struct JacobiTol<double> {
+  static constexpr double off_rel = 1e-13;   // stop when off(A) <= off_rel * ||A||_F
+  static constexpr double skip_rel = 1e-18;  // no rotation for |a_pq| <= skip_rel * ||A||_F
+};
+template <>
+struct JacobiTol<float> {
+  static constexpr double off_rel = 1e-6;
+  static constexpr double skip_rel = 1e-9;
+};
+
+// LDS: V (n*n doubles, column-major) | red (nthreads doubles) | A (packed, T) | rot (4 T per
+// pair: c, s, new a_pp, new a_qq) | sel (n + 4 ints).
+template <typename T>
+inline size_t lds_bytes_t(int n, int nthreads) {
+  const size_t np2 = (size_t)(n + 1) / 2, npk = (size_t)n * (n + 1) / 2;
+  return 8 * ((size_t)n * n + nthreads) + sizeof(T) * (npk + 4 * np2) + sizeof(int) * (size_t)(n + 4) + 16;
+}
+
+struct Smem {
+  double *V, *red;
+  void *A, *rot;
+  int *sel;
+};
+
+template <typename T>
+__device__ inline Smem carve(unsigned char *base, int n) {
+  Smem s;
+  const int np2 = (n + 1) / 2, npk = n * (n + 1) / 2;
+  s.V = reinterpret_cast<double *>(base);
+  s.red = s.V + n * n;
+  T *A = reinterpret_cast<T *>(s.red + blockDim.x);
+  s.A = A;
+  s.rot = A + npk;
+  s.sel = reinterpret_cast<int *>(reinterpret_cast<T *>(s.rot) + 4 * np2);
+  return s;
+}
+
+__device__ inline double wg_sum(double v, double *red) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = nth / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *red, int *flag) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int np2 = (n + 1) / 2, nn = 2 * np2;
+  const int npk = n * (n + 1) / 2;
+  const int nblk = np2 * (np2 + 1) / 2;
+  for (int k = tid; k < n * n; k += nth) V[k] = (k % (n + 1) == 0) ? 1.0 : 0.0;
+  double f2 = 0.0;
+  for (int k = tid; k < npk; k += nth) {
+    int i, j;
+    tri_ij(k, i, j);
+    const double a = (double)A[k];
+    f2 += (i == j ? 1.0 : 2.0) * a * a;
+  }
+  const double fro2 = wg_sum(f2, red);
+  const T skip = (T)(JacobiTol<T>::skip_rel * sqrt(fro2));
+  const double offtol2 = JacobiTol<T>::off_rel * JacobiTol<T>::off_rel * fro2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int r = 0; r < nn - 1; ++r) {
+      for (int k = tid; k < np2; k += nth) {
+        int p, q;
+        rr_pair(r, k, nn, p, q);
+        T c = 1, s = 0, dp = 0, dq = 0;
+        if (q < n) {
+          const T apq = A[pidx(p, q)], app = A[pidx(p, p)], aqq = A[pidx(q, q)];
+          dp = app;
+          dq = aqq;
+          if (fabs(apq) > skip) {
+            const T theta = (aqq - app) / (T(2) * apq);
+            const T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
+            c = T(1) / sqrt(t * t + T(1));
+            s = t * c;
+            dp = app - t * apq;
+            dq = aqq + t * apq;
+            *flag = 1;
+          }
+        }
+        rot[4 * k] = c;
+        rot[4 * k + 1] = s;
+        rot[4 * k + 2] = dp;
+        rot[4 * k + 3] = dq;
+      }
+      __syncthreads();
+      for (int k = tid; k < nblk + n * np2; k += nth) {
+        if (k < nblk) {
+          int I, J;
+          tri_ij(k, I, J);
+          int p1, q1, p2, q2;
+          rr_pair(r, I, nn, p1, q1);
+          if (I == J) {
+            if (q1 < n) {
+              A[pidx(p1, p1)] = rot[4 * I + 2];
+              A[pidx(q1, q1)] = rot[4 * I + 3];
+              A[pidx(p1, q1)] = T(0);
+            }
+            continue;
+          }
+          rr_pair(r, J, nn, p2, q2);
+          const T c1 = rot[4 * I], s1 = rot[4 * I + 1], c2 = rot[4 * J], s2 = rot[4 * J + 1];
+          const bool hq1 = q1 < n, hq2 = q2 < n;
+          const T a = A[pidx(p1, p2)];
+          const T bq = hq2 ? A[pidx(p1, q2)] : T(0);
+          const T cq = hq1 ? A[pidx(q1, p2)] : T(0);
+          const T d = (hq1 && hq2) ? A[pidx(q1, q2)] : T(0);
+          const T ra = c1 * a - s1 * cq, rb = c1 * bq - s1 * d;  // rows p1, q1 rotated
+          const T rc = s1 * a + c1 * cq, rd = s1 * bq + c1 * d;
+          A[pidx(p1, p2)] = c2 * ra - s2 * rb;  // then columns p2, q2
+          if (hq2) A[pidx(p1, q2)] = s2 * ra + c2 * rb;
+          if (hq1) A[pidx(q1, p2)] = c2 * rc - s2 * rd;
+          if (hq1 && hq2) A[pidx(q1, q2)] = s2 * rc + c2 * rd;
+        } else {
+          const int kk = k - nblk;
+          const int row = kk % n, I = kk / n;
+          int p, q;
+          rr_pair(r, I, nn, p, q);
+          if (q >= n) continue;
+          double c = (double)rot[4 * I], s = (double)rot[4 * I + 1];
+          const double nr = 1.0 / sqrt(c * c + s * s);  // exactly orthogonal in double
+          c *= nr;
+          s *= nr;
+          const double vp = V[row + p * n], vq = V[row + q * n];
+          V[row + p * n] = c * vp - s * vq;
+          V[row + q * n] = s * vp + c * vq;
+        }
+      }
+      __syncthreads();
+    }
+    double off = 0.0;
+    for (int k = tid; k < npk; k += nth) {
+      int i, j;
+      tri_ij(k, i, j);
+      const double a = (double)A[k];
+      if (i != j) off += 2.0 * a * a;
+    }
+    const double offsum = wg_sum(off, red);
+    const int rotated = *flag;
+    __syncthreads();
+    if (offsum <= offtol2 || !rotated) break;
+  }
+}
+
+// Eigen-indices of the cheaper side: the positive eigenvalues when they are at most as many
+// as the negative ones (Pi = sum_{lam > 0} lam v v^T), else the negative ones
+// (Pi = X - sum_{lam < 0} lam v v^T).  sel[n] = 1 for the positive side, sel[n+1] = count.
+template <typename T>
+__device__ void select_side(int n, const T *A, int *sel) {
+  if (threadIdx.x == 0) {
+    int np = 0, nneg = 0;
+    for (int k = 0; k < n; ++k) {
+      const T l = A[pidx(k, k)];
+      np += l > T(0);
+      nneg += l < T(0);
+    }
+    const int pos = np <= nneg;
+    int c = 0;
+    for (int k = 0; k < n; ++k) {
+      const T l = A[pidx(k, k)];
+      if (pos ? (l > T(0)) : (l < T(0))) sel[c++] = k;
+    }
+    sel[n] = pos;
+    sel[n + 1] = c;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ inline double rebuild(int i, int j, int n, const T *A, const double *V, const int *sel, int cnt) {
+  double acc = 0.0;
+  for (int t = 0; t < cnt; ++t) {
+    const int e = sel[t];
+    acc += (double)A[pidx(e, e)] * V[i + e * n] * V[j + e * n];
+  }
+  return acc;
+}
+
+// ADMM step 2: S = (Pi(X_b) - X_b) / sigma for the listed blocks (svec in and out).
+template <typename T>
+__global__ void __launch_bounds__(256) k_project_admm(const int32_t *__restrict__ blk_ids, const int64_t *__restrict__ boff,
+                                                      const int32_t *__restrict__ bsz, const double *__restrict__ Xb,
+                                                      double *__restrict__ S, const DevState *__restrict__ st,
+                                                      double scale) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int32_t bk = blk_ids[blockIdx.x];
+  const int n = bsz[bk];
+  const int64_t off = boff[bk];
+  const int nth = blockDim.x, tid = threadIdx.x;
+  const int npk = n * (n + 1) / 2;
+  Smem sm = carve<T>(smem, n);
+  T *A = reinterpret_cast<T *>(sm.A);
+  const double rs2 = 0.70710678118654752440, s2 = 1.41421356237309504880;
+  for (int k = tid; k < npk; k += nth) {  // svec is the packed upper triangle with sqrt(2) off-diagonal
+    int i, j;
+    tri_ij(k, i, j);
+    const double v = Xb[off + k];
+    A[k] = (T)(i == j ? v : v * rs2);
+  }
+  __syncthreads();
+  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.red, sm.sel + n + 2);
+  select_side<T>(n, A, sm.sel);
+  const int pos = sm.sel[n], cnt = sm.sel[n + 1];
+  const double inv_sig = scale > 0.0 ? scale : 1.0 / st->sigma;  // scale 1: S = Pi(X_b) - X_b
+  for (int k = tid; k < npk; k += nth) {
+    int i, j;
+    tri_ij(k, i, j);
+    const double acc = rebuild<T>(i, j, n, A, sm.V, sm.sel, cnt) * (i == j ? 1.0 : s2);
+    S[off + k] = pos ? (acc - Xb[off + k]) * inv_sig   // (Pi - X_b) / sigma
+                     : -acc * inv_sig;                  // -Pi_-(X_b) / sigma
+  }
+}
+
+// strom_project_psd_batched: column-major blocks in T, at element offsets.
+template <typename T>
+__global__ void __launch_bounds__(256) k_project_dense(int32_t nblocks, const int32_t *__restrict__ nd,
+                                                       const int64_t *__restrict__ od, const T *__restrict__ in,
+                                                       T *__restrict__ out, int32_t max_n, int32_t *__restrict__ err) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int32_t bk = blockIdx.x;
+  const int n = nd[bk];
+  const int64_t off = od[bk];
+  if (n <= 0 || n > max_n) {
+    if (threadIdx.x == 0) atomicOr(err, 1);
+    return;
+  }
+  const int nth = blockDim.x, tid = threadIdx.x;
+  const int npk = n * (n + 1) / 2;
+  Smem sm = carve<T>(smem, n);
+  T *A = reinterpret_cast<T *>(sm.A);
+  for (int k = tid; k < npk; k += nth) {
+    int i, j;
+    tri_ij(k, i, j);
+    A[k] = in[off + i + (int64_t)j * n];
+  }
+  __syncthreads();
+  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.red, sm.sel + n + 2);
+  select_side<T>(n, A, sm.sel);
+  const int pos = sm.sel[n], cnt = sm.sel[n + 1];
+  // every thread reads only the upper entries it writes, so out may alias in
+  for (int k = tid; k < npk; k += nth) {
+    int i, j;
+    tri_ij(k, i, j);
+    const double acc = rebuild<T>(i, j, n, A, sm.V, sm.sel, cnt);
+    const double x = (double)in[off + i + (int64_t)j * n];
+    const T pv = (T)(pos ? acc : x - acc);
+    out[off + i + (int64_t)j * n] = pv;
+    if (i != j) out[off + j + (int64_t)i * n] = pv;
+  }
+}
+
+size_t project_lds_bytes(int n, bool f32, int nthreads) {
+  return f32 ? lds_bytes_t<float>(n, nthreads) : lds_bytes_t<double>(n, nthreads);
+}
+
+int project_threads(int n) { return n <= 16 ? 64 : 256; }
+
+hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const int32_t *ids, const int64_t *boff,
+                               const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale) {
+  const int nt = project_threads(n);
+  const size_t lds = project_lds_bytes(n, f32, nt);
+  if (f32) {
+    (void)hipFuncSetAttribute((const void *)k_project_admm<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_project_admm<float>, dim3(count), dim3(nt), lds, s, ids, boff, bsz, Xb, S, st, scale);
+  } else {
+    (void)hipFuncSetAttribute((const void *)k_project_admm<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_project_admm<double>, dim3(count), dim3(nt), lds, s, ids, boff, bsz, Xb, S, st, scale);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_project_dense(hipStream_t s, bool f32, int nblocks, int max_n, const int32_t *nd, const int64_t *od,
+                                const void *in, void *out, int32_t *err) {
+  const int nt = project_threads(max_n);
+  const size_t lds = project_lds_bytes(max_n, f32, nt);
+  if (f32) {
+    (void)hipFuncSetAttribute((const void *)k_project_dense<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_project_dense<float>, dim3(nblocks), dim3(nt), lds, s, nblocks, nd, od, (const float *)in,
+                       (float *)out, max_n, err);
+  } else {
+    (void)hipFuncSetAttribute((const void *)k_project_dense<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_project_dense<double>, dim3(nblocks), dim3(nt), lds, s, nblocks, nd, od, (const double *)in,
+                       (double *)out, max_n, err);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dev
+}  // namespace strom

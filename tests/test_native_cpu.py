@@ -1,0 +1,93 @@
+"""Host-side checks of the native library (CPU only, no compute on the device).
+
+* libstrom.so loads and exports every function declared in include/*.h;
+* the product's own relaxation generator (strom_gen_*) reproduces the oracle's relaxation row
+  by row -- two independent implementations of the same conventions;
+* argument validation of the generator.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b(strom_[a-z0-9_]+)\s*\(", src):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    import paper_2406_05846_amd as S
+    lib = ctypes.CDLL(S.LIB_PATH)
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(S.EXPORTS) <= declared
+
+
+def test_default_opts():
+    import paper_2406_05846_amd as S
+    o = S.default_opts()
+    assert o.sigma0 == 1.0 and o.tau == 1.6 and o.tol == 1e-6 and o.kkt_every == 10 and o.sigma_every == 50
+
+
+CASES = [
+    (0, 3, [2.0, 0.1, 1.0]),
+    (1, 10, [0.5, 0.0]),
+    (2, 6, [0.1, 0.2, 0.5, 0.3]),
+    (3, 4, [0.3, 0.5]),
+    (4, 3, [0, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
+    (4, 3, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
+]
+
+
+@pytest.mark.parametrize("fam,N,prm", CASES)
+def test_generators_agree(orc, fam, N, prm):
+    import paper_2406_05846_amd as S
+    p = S.generate(fam, N, prm)
+    o = orc.relax(fam, N, prm)
+    assert p.m == o.m and p.nsvec == o.nsvec
+    assert np.array_equal(p.block_sizes, o.bsize)
+    assert np.array_equal(p.rowptr, o.rowptr)
+    assert np.array_equal(p.col, o.col)
+    assert np.array_equal(p.row_kind, o.rowkind)
+    assert np.abs(p.val - o.val).max() <= 4e-16
+    assert np.abs(p.b - o.b).max() == 0.0
+    assert np.abs(p.C - o.C).max() <= 1e-14 * max(1.0, np.abs(o.C).max())
+
+
+def test_generator_rejects_bad_arguments():
+    import paper_2406_05846_amd as S
+    with pytest.raises(S.StromError):
+        S.generate(9, 3, [0.0])
+    with pytest.raises(S.StromError):
+        S.generate(1, 0, [0.5, 0.0])
+    with pytest.raises(S.StromError):
+        S.generate(2, 3, [0.1])
+
+
+def test_workloads_are_seeded():
+    import workloads as W
+    a = W.instance_params(W.CARTPOLE, 3)
+    assert a == W.instance_params(W.CARTPOLE, 3)
+    assert a != W.instance_params(W.CARTPOLE, 4)
+    b = W.mixed_batch(0, 16)
+    assert b == W.mixed_batch(0, 16)
+    assert all(10 <= N <= 60 for _, N, _ in b)
+    car = W.instance_params(W.CAR, 5)
+    assert car[0] == 1.0  # odd seed -> bicycle-13
+    r = W.poisson_arrivals(0, 100.0, 1.0)
+    ts = [t for t, *_ in r]
+    assert ts == sorted(ts) and 50 < len(ts) < 150
