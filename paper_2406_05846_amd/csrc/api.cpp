@@ -76,6 +76,9 @@ struct strom_sdp {
   int64_t *boff = nullptr; int32_t *bsz = nullptr; int32_t *blk_ids = nullptr;
   DevState *st = nullptr;
   double *part_rows = nullptr, *part_cols = nullptr, *part_cone = nullptr;
+  double *Q = nullptr;         // eigenvectors of every block from the last ADMM projection
+  int64_t *qoff = nullptr;     // offset of block k in Q
+  bool q_valid = false;        // Q holds eigenvectors of the current iterate's blocks
   strom::dev::SolveArgs sa{};
   strom::dev::SolveSchedule sch;
   std::vector<int> cls_n, cls_off, cls_cnt;  // projection launches, one per block size
@@ -206,19 +209,27 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   const size_t oUrp = ar.reserve<int64_t>(size_t(m) + 1), oUci = ar.reserve<int32_t>(H.Uci.size()),
                oUv = ar.reserve<double>(H.Uv.size());
   const size_t oD = ar.reserve<double>(size_t(m));
-  const size_t oInv = ar.reserve<double>(std::max<size_t>(1, H.inv.size())),
-               oInvT = ar.reserve<double>(std::max<size_t>(1, H.invT.size()));
-  const size_t oTk = ar.reserve<int32_t>(size_t(ntask) * 7), oTinv = ar.reserve<int64_t>(size_t(ntask));
-  const size_t oFl = ar.reserve<int32_t>(std::max<size_t>(1, H.flevptr.size())),
-               oFr = ar.reserve<int32_t>(std::max<size_t>(1, H.frows.size())),
-               oBl = ar.reserve<int32_t>(std::max<size_t>(1, H.blevptr.size())),
-               oBr = ar.reserve<int32_t>(std::max<size_t>(1, H.brows.size()));
+  const size_t oInvR = ar.reserve<double>(std::max<size_t>(1, H.invR.size())),
+               oInvC = ar.reserve<double>(std::max<size_t>(1, H.invC.size()));
+  const size_t nph = H.ph_type.size();
+  const size_t oTk = ar.reserve<int32_t>(size_t(ntask) * 4), oPh = ar.reserve<int32_t>(std::max<size_t>(1, nph) * 7),
+               oPinv = ar.reserve<int64_t>(std::max<size_t>(1, nph));
+  const size_t oLev = ar.reserve<int32_t>(std::max<size_t>(1, H.levptr.size())),
+               oGf = ar.reserve<int32_t>(std::max<size_t>(1, H.lvl_gf.size())),
+               oGb = ar.reserve<int32_t>(std::max<size_t>(1, H.lvl_gb.size()));
   const size_t oFo = ar.reserve<int32_t>(H.fwd_order.size()), oBo = ar.reserve<int32_t>(H.bwd_order.size());
   const size_t oBoff = ar.reserve<int64_t>(size_t(P->nblocks)), oBsz = ar.reserve<int32_t>(size_t(P->nblocks)),
                oIds = ar.reserve<int32_t>(ids.size());
   const size_t oSt = ar.reserve<DevState>(1);
   const size_t oPr = ar.reserve<double>(2 * size_t(nrb)), oPc = ar.reserve<double>(2 * size_t(ncb)),
                oPk = ar.reserve<double>(2 * size_t(ncb));
+  std::vector<int64_t> qoff(size_t(P->nblocks));
+  int64_t qtot = 0;
+  for (int32_t k = 0; k < P->nblocks; ++k) {
+    qoff[size_t(k)] = qtot;
+    qtot += int64_t(H.bsize[size_t(k)]) * H.bsize[size_t(k)];
+  }
+  const size_t oQ = ar.reserve<double>(size_t(qtot)), oQoff = ar.reserve<int64_t>(size_t(P->nblocks));
   s->arena_bytes = ar.bytes;
 
   {
@@ -252,31 +263,39 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   s->boff = P64(oBoff); s->bsz = P32(oBsz); s->blk_ids = P32(oIds);
   s->st = reinterpret_cast<DevState *>(base + oSt);
   s->part_rows = PD(oPr); s->part_cols = PD(oPc); s->part_cone = PD(oPk);
-  int32_t *tk = P32(oTk);
+  s->Q = PD(oQ); s->qoff = P64(oQoff);
+  int32_t *tk = P32(oTk), *ph = P32(oPh);
   auto &sa = s->sa;
-  sa.task_r0 = tk; sa.task_r1 = tk + ntask; sa.task_type = tk + 2 * ntask; sa.task_flev0 = tk + 3 * ntask;
-  sa.task_fnlev = tk + 4 * ntask; sa.task_blev0 = tk + 5 * ntask; sa.task_bnlev = tk + 6 * ntask;
-  sa.task_inv = P64(oTinv);
-  sa.flevptr = P32(oFl); sa.frows = P32(oFr); sa.blevptr = P32(oBl); sa.brows = P32(oBr);
+  sa.task_r0 = tk; sa.task_r1 = tk + ntask; sa.task_ph0 = tk + 2 * ntask; sa.task_ph1 = tk + 3 * ntask;
+  sa.ph_type = ph; sa.ph_a = ph + nph; sa.ph_b = ph + 2 * nph; sa.ph_l0 = ph + 3 * nph; sa.ph_nl = ph + 4 * nph;
+  sa.ph_gf = ph + 5 * nph; sa.ph_gb = ph + 6 * nph;
+  sa.ph_inv = P64(oPinv);
+  sa.levptr = P32(oLev); sa.lvl_gf = P32(oGf); sa.lvl_gb = P32(oGb);
   sa.Lrp = P64(oLrp); sa.Lci = P32(oLci); sa.Lv = PD(oLv);
   sa.Urp = P64(oUrp); sa.Uci = P32(oUci); sa.Uv = PD(oUv);
-  sa.D = PD(oD); sa.inv = PD(oInv); sa.invT = PD(oInvT); sa.perm = P32(operm);
+  sa.D = PD(oD); sa.invR = PD(oInvR); sa.invC = PD(oInvC); sa.perm = P32(operm);
+  sa.lds_rows = std::min(H.max_task_rows, strom::kMaxLdsTaskRows);
   s->sch.fwd_gptr = H.fwd_gptr;
   s->sch.bwd_gptr = H.bwd_gptr;
   s->sch.fwd_order_dev = P32(oFo);
   s->sch.bwd_order_dev = P32(oBo);
-  s->sch.max_dense_rows = H.max_dense_rows;
 
   // host staging of the small arrays, then synchronous uploads
-  std::vector<int32_t> tkh(size_t(ntask) * 7);
+  std::vector<int32_t> tkh(size_t(ntask) * 4), phh(std::max<size_t>(1, nph) * 7);
   for (int t = 0; t < ntask; ++t) {
     tkh[size_t(t)] = H.task_r0[size_t(t)];
     tkh[size_t(ntask + t)] = H.task_r1[size_t(t)];
-    tkh[size_t(2 * ntask + t)] = H.task_type[size_t(t)];
-    tkh[size_t(3 * ntask + t)] = H.task_flev0[size_t(t)];
-    tkh[size_t(4 * ntask + t)] = H.task_fnlev[size_t(t)];
-    tkh[size_t(5 * ntask + t)] = H.task_blev0[size_t(t)];
-    tkh[size_t(6 * ntask + t)] = H.task_bnlev[size_t(t)];
+    tkh[size_t(2 * ntask + t)] = H.task_ph0[size_t(t)];
+    tkh[size_t(3 * ntask + t)] = H.task_ph1[size_t(t)];
+  }
+  for (size_t k = 0; k < nph; ++k) {
+    phh[k] = H.ph_type[k];
+    phh[nph + k] = H.ph_a[k];
+    phh[2 * nph + k] = H.ph_b[k];
+    phh[3 * nph + k] = H.ph_l0[k];
+    phh[4 * nph + k] = H.ph_nl[k];
+    phh[5 * nph + k] = H.ph_gf[k];
+    phh[6 * nph + k] = H.ph_gb[k];
   }
   std::vector<double> zeros;
   auto up = [&](const void *dst, const void *src, size_t bytes) -> bool {
@@ -305,17 +324,18 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   ok &= up(const_cast<int32_t *>(sa.Uci), H.Uci.data(), sizeof(int32_t) * H.Uci.size());
   ok &= up(const_cast<double *>(sa.Uv), H.Uv.data(), sizeof(double) * H.Uv.size());
   ok &= up(const_cast<double *>(sa.D), H.D.data(), sizeof(double) * H.D.size());
-  ok &= up(const_cast<double *>(sa.inv), H.inv.data(), sizeof(double) * H.inv.size());
-  ok &= up(const_cast<double *>(sa.invT), H.invT.data(), sizeof(double) * H.invT.size());
+  ok &= up(sa.invR, H.invR.data(), sizeof(double) * H.invR.size());
+  ok &= up(sa.invC, H.invC.data(), sizeof(double) * H.invC.size());
   ok &= up(tk, tkh.data(), sizeof(int32_t) * tkh.size());
-  ok &= up(const_cast<int64_t *>(sa.task_inv), H.task_inv.data(), sizeof(int64_t) * H.task_inv.size());
-  ok &= up(const_cast<int32_t *>(sa.flevptr), H.flevptr.data(), sizeof(int32_t) * H.flevptr.size());
-  ok &= up(const_cast<int32_t *>(sa.frows), H.frows.data(), sizeof(int32_t) * H.frows.size());
-  ok &= up(const_cast<int32_t *>(sa.blevptr), H.blevptr.data(), sizeof(int32_t) * H.blevptr.size());
-  ok &= up(const_cast<int32_t *>(sa.brows), H.brows.data(), sizeof(int32_t) * H.brows.size());
+  ok &= up(ph, phh.data(), sizeof(int32_t) * phh.size());
+  ok &= up(sa.ph_inv, H.ph_inv.data(), sizeof(int64_t) * H.ph_inv.size());
+  ok &= up(sa.levptr, H.levptr.data(), sizeof(int32_t) * H.levptr.size());
+  ok &= up(sa.lvl_gf, H.lvl_gf.data(), sizeof(int32_t) * H.lvl_gf.size());
+  ok &= up(sa.lvl_gb, H.lvl_gb.data(), sizeof(int32_t) * H.lvl_gb.size());
   ok &= up(const_cast<int32_t *>(s->sch.fwd_order_dev), H.fwd_order.data(), sizeof(int32_t) * H.fwd_order.size());
   ok &= up(const_cast<int32_t *>(s->sch.bwd_order_dev), H.bwd_order.data(), sizeof(int32_t) * H.bwd_order.size());
   ok &= up(s->boff, H.boff.data(), sizeof(int64_t) * size_t(P->nblocks));
+  ok &= up(s->qoff, qoff.data(), sizeof(int64_t) * qoff.size());
   ok &= up(s->bsz, H.bsize.data(), sizeof(int32_t) * size_t(P->nblocks));
   ok &= up(s->blk_ids, ids.data(), sizeof(int32_t) * ids.size());
   DevState st0{};
@@ -351,15 +371,17 @@ extern "C" strom_status strom_sdp_destroy(strom_sdp *s) {
 
 namespace {
 
-// S_out = (Pi(X_in) - X_in) * scale for every block (scale <= 0: 1 / sigma).
-hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, double scale) {
+// S_out = (Pi(X_in) - X_in) * scale for every block (scale <= 0: 1 / sigma).  The ADMM step
+// (admm = true) warm-starts from, and refreshes, the eigenvectors kept per block.
+hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, double scale, bool admm) {
   const bool f32 = s->opts.proj_dtype == STROM_F32;
   for (size_t c = 0; c < s->cls_n.size(); ++c) {
     hipError_t e = strom::dev::launch_project_admm(s->stream, f32, s->cls_n[c], s->cls_cnt[c],
                                                    s->blk_ids + s->cls_off[c], s->boff, s->bsz, X_in, S_out, s->st,
-                                                   scale);
+                                                   scale, admm ? s->Q : nullptr, s->qoff, admm && s->q_valid);
     if (e != hipSuccess) return e;
   }
+  if (admm) s->q_valid = true;
   return hipSuccess;
 }
 
@@ -367,7 +389,7 @@ hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, d
 // do_sigma, the cone distance of X (through the scratch X_b buffer) and the sigma rule.
 hipError_t enqueue_kkt(strom_sdp *s, bool do_sigma) {
   if (do_sigma) {
-    hipError_t e = enqueue_projection(s, s->X, s->Xb, 1.0);
+    hipError_t e = enqueue_projection(s, s->X, s->Xb, 1.0, false);
     if (e != hipSuccess) return e;
   }
   return strom::dev::launch_kkt(s->stream, s->m, s->nsvec, s->A_rp, s->A_ci, s->A_v, s->X, s->b, s->y, s->part_rows,
@@ -384,7 +406,7 @@ hipError_t enqueue_iteration(strom_sdp *s, bool kkt, bool do_sigma) {
   if ((e = strom::dev::launch_solve(q, s->sch, s->sa, s->w, s->y))) return e;
   // step 2
   if ((e = strom::dev::launch_xb(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->X, s->C, s->st, s->Xb))) return e;
-  if ((e = enqueue_projection(s, s->Xb, s->S, 0.0))) return e;
+  if ((e = enqueue_projection(s, s->Xb, s->S, 0.0, true))) return e;
   // step 3
   if ((e = strom::dev::launch_rhs(q, s->m, s->A_rp, s->A_ci, s->A_v, s->X, s->S, s->C, s->b, s->pinv, s->st, s->w)))
     return e;
@@ -500,7 +522,7 @@ extern "C" strom_status strom_profile_iteration(strom_sdp *s, int32_t reps, stro
     rec(2);
     if (!e) e = strom::dev::launch_xb(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->X, s->C, s->st, s->Xb);
     rec(3);
-    if (!e) e = enqueue_projection(s, s->Xb, s->S, 0.0);
+    if (!e) e = enqueue_projection(s, s->Xb, s->S, 0.0, true);
     rec(4);
     if (!e) e = strom::dev::launch_rhs(q, s->m, s->A_rp, s->A_ci, s->A_v, s->X, s->S, s->C, s->b, s->pinv, s->st, s->w);
     rec(5);
@@ -570,6 +592,7 @@ extern "C" strom_status strom_set_iterate(strom_sdp *s, const double *X, const d
   if (y) HIP_TRY(hipMemcpy(s->y, y, sizeof(double) * size_t(s->m), hipMemcpyHostToDevice));
   if (S) HIP_TRY(hipMemcpy(s->S, S, sizeof(double) * size_t(s->nsvec), hipMemcpyHostToDevice));
   s->iters = 0;
+  s->q_valid = false;
   s->state = STROM_RUNNING;
   return STROM_OK;
 }

@@ -19,10 +19,10 @@ struct DevState {
 
 // Device arrays of the triangular solves (see setup.cpp for their meaning).
 struct SolveArgs {
-  const int32_t *task_r0, *task_r1, *task_type;
-  const int32_t *task_flev0, *task_fnlev, *task_blev0, *task_bnlev;
-  const int64_t *task_inv;
-  const int32_t *flevptr, *frows, *blevptr, *brows;
+  const int32_t *task_r0, *task_r1, *task_ph0, *task_ph1;
+  const int32_t *ph_type, *ph_a, *ph_b, *ph_l0, *ph_nl, *ph_gf, *ph_gb;
+  const int64_t *ph_inv;
+  const int32_t *levptr, *lvl_gf, *lvl_gb;
   const int64_t *Lrp;
   const int32_t *Lci;
   const double *Lv;
@@ -30,14 +30,14 @@ struct SolveArgs {
   const int32_t *Uci;
   const double *Uv;
   const double *D;
-  const double *inv, *invT;
+  const double *invR, *invC;
   const int32_t *perm;
+  int32_t lds_rows;  // tasks with at most this many rows keep their values in LDS
 };
 
 struct SolveSchedule {
   std::vector<int32_t> fwd_gptr, bwd_gptr;  // host: group boundaries
   const int32_t *fwd_order_dev = nullptr, *bwd_order_dev = nullptr;
-  int32_t max_dense_rows = 0;
 };
 
 size_t project_lds_bytes(int n, bool f32, int nthreads);
@@ -49,9 +49,12 @@ hipError_t launch_rhs(hipStream_t s, int32_t m, const int64_t *rp, const int32_t
 hipError_t launch_solve(hipStream_t s, const SolveSchedule &sch, const SolveArgs &a, double *w, double *y);
 hipError_t launch_xb(hipStream_t s, int64_t n, const int64_t *trp, const int32_t *tci, const double *tv,
                      const double *y, const double *X, const double *C, const DevState *st, double *Xb);
-// S = (Pi(X_b) - X_b) * scale for the listed blocks; scale <= 0 means 1 / sigma.
+// S = (Pi(X_b) - X_b) * scale for the listed blocks; scale <= 0 means 1 / sigma.  Q (nullable)
+// holds the eigenvectors of each block at qoff[k]; warm starts from them, and they are
+// overwritten with the new ones.
 hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const int32_t *ids, const int64_t *boff,
-                               const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale);
+                               const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale,
+                               double *Q, const int64_t *qoff, bool warm);
 hipError_t launch_project_dense(hipStream_t s, bool f32, int nblocks, int max_n, const int32_t *nd, const int64_t *od,
                                 const void *in, void *out, int32_t *err);
 hipError_t launch_xupdate(hipStream_t s, int64_t n, const int64_t *trp, const int32_t *tci, const double *tv,

@@ -16,6 +16,7 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "strom_internal.h"
 
 namespace strom {
 namespace dev {
@@ -54,87 +55,135 @@ __global__ void __launch_bounds__(256) k_rhs(int32_t m, const int64_t *__restric
 }
 
 // ------------------------------------------------------------------ triangular solves
-// One workgroup per task.  Level tasks walk their rows level by level with a barrier in
-// between; dense tasks gather the contributions of earlier tasks and multiply by the
-// explicit inverse of their diagonal block.
-__global__ void __launch_bounds__(256) k_solve_fwd(const int32_t *__restrict__ tasks, SolveArgs a, double *__restrict__ w) {
-  extern __shared__ double sh[];
-  const int32_t t = tasks[blockIdx.x];
-  const int32_t r0 = a.task_r0[t], r1 = a.task_r1[t];
-  if (a.task_type[t] == 0) {
-    const int32_t l0 = a.task_flev0[t], nl = a.task_fnlev[t];
-    for (int32_t l = 0; l < nl; ++l) {
-      const int32_t k0 = a.flevptr[l0 + l], k1 = a.flevptr[l0 + l + 1];
-      for (int32_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
-        const int32_t i = a.frows[k];
-        double s = w[i];
-        for (int64_t p = a.Lrp[i]; p < a.Lrp[i + 1]; ++p) s -= a.Lv[p] * w[a.Lci[p]];
-        w[i] = s;
-      }
-      __threadfence_block();
-      __syncthreads();
-    }
-  } else {
-    const int32_t nt = r1 - r0;
-    double *c = sh;
-    for (int32_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-      double s = w[i];
-      for (int64_t p = a.Lrp[i]; p < a.Lrp[i + 1]; ++p) {
-        const int32_t j = a.Lci[p];
-        if (j >= r0) break;  // columns ascending: the rest lies in the diagonal block
-        s -= a.Lv[p] * w[j];
-      }
-      c[i - r0] = s;
-    }
-    __syncthreads();
-    const double *inv = a.inv + a.task_inv[t];
-    for (int32_t i = threadIdx.x; i < nt; i += blockDim.x) {
-      double x = 0.0;
-      for (int32_t j = 0; j <= i; ++j) x += inv[i + (int64_t)j * nt] * c[j];
-      w[r0 + i] = x;
-    }
-  }
+// One workgroup per task; the task's values stay in LDS while its phases run.  A level
+// phase walks its levels with a barrier in between, g lanes per row (shuffle reduction);
+// a dense phase gathers the contributions of earlier rows and multiplies by the explicit
+// inverse of its diagonal block.
+__device__ inline double group_sum(double v, int g) {
+  for (int off = g >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
-__global__ void __launch_bounds__(256) k_solve_bwd(const int32_t *__restrict__ tasks, SolveArgs a, double *__restrict__ w,
-                                                   double *__restrict__ y) {
+__global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__restrict__ tasks, SolveArgs a,
+                                                             double *__restrict__ w) {
   extern __shared__ double sh[];
+  const int tid = threadIdx.x, nth = blockDim.x;
   const int32_t t = tasks[blockIdx.x];
-  const int32_t r0 = a.task_r0[t], r1 = a.task_r1[t];
-  if (a.task_type[t] == 0) {
-    const int32_t l0 = a.task_blev0[t], nl = a.task_bnlev[t];
-    for (int32_t l = 0; l < nl; ++l) {
-      const int32_t k0 = a.blevptr[l0 + l], k1 = a.blevptr[l0 + l + 1];
-      for (int32_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
-        const int32_t j = a.brows[k];
-        double s = w[j] / a.D[j];
-        for (int64_t p = a.Urp[j]; p < a.Urp[j + 1]; ++p) s -= a.Uv[p] * w[a.Uci[p]];
-        w[j] = s;
-        y[a.perm[j]] = s;
+  const int32_t r0 = a.task_r0[t], r1 = a.task_r1[t], nt = r1 - r0;
+  const bool inl = nt <= a.lds_rows;
+  double *xs = inl ? sh : (w + r0);  // values of the task rows, index i - r0
+  double *c = inl ? sh + nt : sh;    // gathered right-hand side of a dense phase
+  if (inl)
+    for (int i = tid; i < nt; i += nth) xs[i] = w[r0 + i];
+  __syncthreads();
+  for (int32_t ph = a.task_ph0[t]; ph < a.task_ph1[t]; ++ph) {
+    if (a.ph_type[ph] == 0) {
+      const int32_t l0 = a.ph_l0[ph], nl = a.ph_nl[ph];
+      for (int32_t q = 0; q < nl; ++q) {
+        const int32_t i0 = a.levptr[l0 + q], i1 = a.levptr[l0 + q + 1], g = a.lvl_gf[l0 + q];
+        const int lane = tid & (g - 1);
+        for (int r = tid / g; r < i1 - i0; r += nth / g) {
+          const int32_t i = i0 + r;
+          double s = 0.0;
+          for (int64_t p = a.Lrp[i] + lane; p < a.Lrp[i + 1]; p += g) {
+            const int32_t j = a.Lci[p];
+            s += a.Lv[p] * (j >= r0 ? xs[j - r0] : w[j]);
+          }
+          s = group_sum(s, g);
+          if (lane == 0) xs[i - r0] -= s;
+        }
+        __syncthreads();
       }
-      __threadfence_block();
+    } else {
+      const int32_t pa = a.ph_a[ph], nd = a.ph_b[ph] - pa, g = a.ph_gf[ph];
+      const int lane = tid & (g - 1);
+      for (int r = tid / g; r < nd; r += nth / g) {
+        const int32_t i = pa + r;
+        double s = 0.0;
+        for (int64_t p = a.Lrp[i] + lane; p < a.Lrp[i + 1]; p += g) {
+          const int32_t j = a.Lci[p];
+          if (j < pa) s += a.Lv[p] * (j >= r0 ? xs[j - r0] : w[j]);
+        }
+        s = group_sum(s, g);
+        if (lane == 0) c[r] = xs[i - r0] - s;
+      }
+      __syncthreads();
+      const double *inv = a.invR + a.ph_inv[ph];  // row r of the inverse is contiguous
+      const int ln = tid & 7;
+      for (int r = tid / 8; r < nd; r += nth / 8) {
+        double s = 0.0;
+        for (int j = ln; j <= r; j += 8) s += inv[(int64_t)r * nd + j] * c[j];
+        s = group_sum(s, 8);
+        if (ln == 0) xs[pa + r - r0] = s;
+      }
       __syncthreads();
     }
-  } else {
-    const int32_t nt = r1 - r0;
-    double *c = sh;
-    for (int32_t j = r0 + threadIdx.x; j < r1; j += blockDim.x) {
-      double s = w[j] / a.D[j];
-      for (int64_t p = a.Urp[j]; p < a.Urp[j + 1]; ++p) {
-        const int32_t i = a.Uci[p];
-        if (i < r1) continue;  // inside the diagonal block
-        s -= a.Uv[p] * w[i];
+  }
+  if (inl)
+    for (int i = tid; i < nt; i += nth) w[r0 + i] = xs[i];
+}
+
+// Backward: L^T x = D^{-1} z over the phases and levels in reverse order (a row at forward
+// level l only depends here on rows at higher levels or in later tasks).
+__global__ void __launch_bounds__(kSolveThreads) k_solve_bwd(const int32_t *__restrict__ tasks, SolveArgs a,
+                                                             double *__restrict__ w, double *__restrict__ y) {
+  extern __shared__ double sh[];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int32_t t = tasks[blockIdx.x];
+  const int32_t r0 = a.task_r0[t], r1 = a.task_r1[t], nt = r1 - r0;
+  const bool inl = nt <= a.lds_rows;
+  double *xs = inl ? sh : (w + r0);
+  double *c = inl ? sh + nt : sh;
+  if (inl)
+    for (int i = tid; i < nt; i += nth) xs[i] = w[r0 + i];
+  __syncthreads();
+  for (int32_t ph = a.task_ph1[t] - 1; ph >= a.task_ph0[t]; --ph) {
+    if (a.ph_type[ph] == 0) {
+      const int32_t l0 = a.ph_l0[ph], nl = a.ph_nl[ph];
+      for (int32_t q = nl - 1; q >= 0; --q) {
+        const int32_t i0 = a.levptr[l0 + q], i1 = a.levptr[l0 + q + 1], g = a.lvl_gb[l0 + q];
+        const int lane = tid & (g - 1);
+        for (int r = tid / g; r < i1 - i0; r += nth / g) {
+          const int32_t j = i0 + r;
+          double s = 0.0;
+          for (int64_t p = a.Urp[j] + lane; p < a.Urp[j + 1]; p += g) {
+            const int32_t i = a.Uci[p];
+            s += a.Uv[p] * (i < r1 ? xs[i - r0] : w[i]);
+          }
+          s = group_sum(s, g);
+          if (lane == 0) xs[j - r0] = xs[j - r0] / a.D[j] - s;
+        }
+        __syncthreads();
       }
-      c[j - r0] = s;
+    } else {
+      const int32_t pa = a.ph_a[ph], pb = a.ph_b[ph], nd = pb - pa, g = a.ph_gb[ph];
+      const int lane = tid & (g - 1);
+      for (int r = tid / g; r < nd; r += nth / g) {
+        const int32_t j = pa + r;
+        double s = 0.0;
+        for (int64_t p = a.Urp[j] + lane; p < a.Urp[j + 1]; p += g) {
+          const int32_t i = a.Uci[p];
+          if (i >= pb) s += a.Uv[p] * (i < r1 ? xs[i - r0] : w[i]);
+        }
+        s = group_sum(s, g);
+        if (lane == 0) c[r] = xs[j - r0] / a.D[j] - s;
+      }
+      __syncthreads();
+      const double *inv = a.invC + a.ph_inv[ph];  // column r of the inverse is contiguous
+      const int ln = tid & 7;
+      for (int r = tid / 8; r < nd; r += nth / 8) {
+        double s = 0.0;
+        for (int i = r + ln; i < nd; i += 8) s += inv[(int64_t)r * nd + i] * c[i];
+        s = group_sum(s, 8);
+        if (ln == 0) xs[pa + r - r0] = s;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    const double *invT = a.invT + a.task_inv[t];
-    for (int32_t j = threadIdx.x; j < nt; j += blockDim.x) {
-      double x = 0.0;
-      for (int32_t i = j; i < nt; ++i) x += invT[(int64_t)i * nt + j] * c[i];
-      w[r0 + j] = x;
-      y[a.perm[r0 + j]] = x;
-    }
+  }
+  for (int i = tid; i < nt; i += nth) {
+    const double v = xs[i];
+    if (inl) w[r0 + i] = v;
+    y[a.perm[r0 + i]] = v;
   }
 }
 
@@ -270,16 +319,19 @@ hipError_t launch_rhs(hipStream_t s, int32_t m, const int64_t *rp, const int32_t
 }
 
 hipError_t launch_solve(hipStream_t s, const SolveSchedule &sch, const SolveArgs &a, double *w, double *y) {
-  const size_t lds = sizeof(double) * (size_t)(sch.max_dense_rows > 0 ? sch.max_dense_rows : 1);
+  const size_t lds = sizeof(double) * (size_t)(a.lds_rows + kMaxDenseRows);
+  (void)hipFuncSetAttribute((const void *)k_solve_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void *)k_solve_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   for (int g = 0; g + 1 < (int)sch.fwd_gptr.size(); ++g) {
     const int cnt = sch.fwd_gptr[g + 1] - sch.fwd_gptr[g];
     if (cnt <= 0) continue;
-    hipLaunchKernelGGL(k_solve_fwd, dim3(cnt), dim3(256), lds, s, sch.fwd_order_dev + sch.fwd_gptr[g], a, w);
+    hipLaunchKernelGGL(k_solve_fwd, dim3(cnt), dim3(kSolveThreads), lds, s, sch.fwd_order_dev + sch.fwd_gptr[g], a, w);
   }
   for (int g = 0; g + 1 < (int)sch.bwd_gptr.size(); ++g) {
     const int cnt = sch.bwd_gptr[g + 1] - sch.bwd_gptr[g];
     if (cnt <= 0) continue;
-    hipLaunchKernelGGL(k_solve_bwd, dim3(cnt), dim3(256), lds, s, sch.bwd_order_dev + sch.bwd_gptr[g], a, w, y);
+    hipLaunchKernelGGL(k_solve_bwd, dim3(cnt), dim3(kSolveThreads), lds, s, sch.bwd_order_dev + sch.bwd_gptr[g], a, w,
+                       y);
   }
   return hipGetLastError();
 }

@@ -5,10 +5,14 @@
 // Eigensolver: cyclic Jacobi in the round-robin parallel ordering.  In one round the n/2
 // disjoint pairs are rotated together, A <- J^T A J; the new value of every 2x2 block
 // (pair P1 x pair P2) depends only on its own four old entries, so each thread updates whole
-// 2x2 blocks of the packed upper triangle with no barrier inside the round.  The matrix is
-// held in T (double, or float for the reduced-precision form); the eigenvectors, the norms
-// and the reconstruction are always accumulated in double, which keeps the float form within
-// about 1e-6 of the double result.
+// 2x2 blocks of the packed upper triangle with no barrier inside the round.  Each thread
+// computes the indices of its (at most kSlots) 2x2 blocks and eigenvector rows once, so a
+// round costs no integer division.  The matrix is held in T (double, or float for the
+// reduced-precision form); eigenvectors, norms and the reconstruction are double.
+//
+// Warm start (ADMM step): the eigenvectors of the previous call on the same block are kept
+// in HBM; the sweeps start from A = Q^T X_b Q and V = Q, which is nearly diagonal once the
+// iteration settles, so one to three sweeps replace the eight to ten of a cold start.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,6 +22,8 @@
 
 namespace strom {
 namespace dev {
+
+constexpr int kSlots = 8;  // 2x2 blocks (and eigenvector rows) per thread and round
 
 __device__ inline int pidx(int i, int j) {  // packed upper triangle, by columns
   if (i > j) { const int t = i; i = j; j = t; }
@@ -31,11 +37,15 @@ __device__ inline void tri_ij(int k, int &i, int &j) {  // k -> (i <= j) of the 
   i = k - j * (j + 1) / 2;
 }
 
-// Pair k of round r of the circle schedule over nn (even) slots.
-__device__ inline void rr_pair(int r, int k, int nn, int &p, int &q) {
-  const int mm = nn - 1;
+// Pair k of round r of the circle schedule over nn (even) slots, mm = nn - 1.
+__device__ inline void rr_pair(int r, int k, int mm, int &p, int &q) {
   if (k == 0) { p = r; q = mm; }
-  else { p = (r + k) % mm; q = (r - k + mm) % mm; }
+  else {
+    p = r + k;
+    if (p >= mm) p -= mm;
+    q = r - k;
+    if (q < 0) q += mm;
+  }
   if (p > q) { const int t = p; p = q; q = t; }
 }
 
@@ -52,16 +62,17 @@ struct JacobiTol<float> {
   static constexpr double skip_rel = 1e-9;
 };
 
-// LDS: V (n*n doubles, column-major) | red (nthreads doubles) | A (packed, T) | rot (4 T per
-// pair: c, s, new a_pp, new a_qq) | sel (n + 4 ints).
+// LDS: V (n*n doubles, column-major) | red (nthreads doubles) | work (8n doubles, warm start)
+//      | A (packed, T) | rot (4 T per pair: c, s, new a_pp, new a_qq) | sel (n + 4 ints).
 template <typename T>
 inline size_t lds_bytes_t(int n, int nthreads) {
   const size_t np2 = (size_t)(n + 1) / 2, npk = (size_t)n * (n + 1) / 2;
-  return 8 * ((size_t)n * n + nthreads) + sizeof(T) * (npk + 4 * np2) + sizeof(int) * (size_t)(n + 4) + 16;
+  return 8 * ((size_t)n * n + nthreads + 8 * (size_t)n) + sizeof(T) * (npk + 4 * np2) + sizeof(int) * (size_t)(n + 4) +
+         16;
 }
 
 struct Smem {
-  double *V, *red;
+  double *V, *red, *work;
   void *A, *rot;
   int *sel;
 };
@@ -72,7 +83,8 @@ __device__ inline Smem carve(unsigned char *base, int n) {
   const int np2 = (n + 1) / 2, npk = n * (n + 1) / 2;
   s.V = reinterpret_cast<double *>(base);
   s.red = s.V + n * n;
-  T *A = reinterpret_cast<T *>(s.red + blockDim.x);
+  s.work = s.red + blockDim.x;
+  T *A = reinterpret_cast<T *>(s.work + 8 * n);
   s.A = A;
   s.rot = A + npk;
   s.sel = reinterpret_cast<int *>(reinterpret_cast<T *>(s.rot) + 4 * np2);
@@ -92,13 +104,55 @@ __device__ inline double wg_sum(double v, double *red) {
   return r;
 }
 
+// A <- Q^T X Q (upper triangle, packed into A) with Q = V in LDS and X the svec block at xs
+// in global memory; work holds 8 columns of X Q at a time.
 template <typename T>
-__device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *red, int *flag) {
+__device__ void rotate_into_basis(int n, const double *xs, const double *V, double *work, T *A) {
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int np2 = (n + 1) / 2, nn = 2 * np2;
+  const double rs2 = 0.70710678118654752440;
+  for (int j0 = 0; j0 < n; j0 += 8) {
+    const int cb = min(8, n - j0);
+    for (int e = tid; e < n * cb; e += nth) {  // work(i, c) = sum_k X(i,k) Q(k, j0 + c)
+      const int i = e % n, c = e / n;
+      const double *q = V + (j0 + c) * n;
+      double s = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double x = xs[pidx(i, k)];
+        s += (i == k ? x : x * rs2) * q[k];
+      }
+      work[c * n + i] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * cb; e += nth) {  // A(i, j) = sum_k Q(k, i) work(k, j - j0), i <= j
+      const int i = e % n, c = e / n, j = j0 + c;
+      if (i > j) continue;
+      const double *q = V + i * n;
+      const double *t = work + c * n;
+      double s = 0.0;
+      for (int k = 0; k < n; ++k) s += q[k] * t[k];
+      A[pidx(i, j)] = (T)s;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *red, int *flag, bool v_ready) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int np2 = (n + 1) / 2, nn = 2 * np2, mm = nn - 1;
   const int npk = n * (n + 1) / 2;
-  const int nblk = np2 * (np2 + 1) / 2;
-  for (int k = tid; k < n * n; k += nth) V[k] = (k % (n + 1) == 0) ? 1.0 : 0.0;
+  const int nblk = np2 * (np2 + 1) / 2, nvt = n * np2;
+  // this thread's 2x2 blocks (I <= J) and eigenvector rows (row, I), decoded once
+  int bI[kSlots], bJ[kSlots], vR[kSlots], vI[kSlots];
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const int k = tid + s * nth;
+    bI[s] = bJ[s] = vR[s] = vI[s] = -1;
+    if (k < nblk) tri_ij(k, bI[s], bJ[s]);
+    if (k < nvt) { vR[s] = k % n; vI[s] = k / n; }
+  }
+  if (!v_ready)
+    for (int k = tid; k < n * n; k += nth) V[k] = (k % (n + 1) == 0) ? 1.0 : 0.0;
   double f2 = 0.0;
   for (int k = tid; k < npk; k += nth) {
     int i, j;
@@ -110,12 +164,18 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *red, int *fla
   const T skip = (T)(JacobiTol<T>::skip_rel * sqrt(fro2));
   const double offtol2 = JacobiTol<T>::off_rel * JacobiTol<T>::off_rel * fro2;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid == 0) *flag = 0;
-    __syncthreads();
-    for (int r = 0; r < nn - 1; ++r) {
+    double off = 0.0;  // off-diagonal mass at the start of the sweep
+    for (int k = tid; k < npk; k += nth) {
+      int i, j;
+      tri_ij(k, i, j);
+      const double a = (double)A[k];
+      if (i != j) off += 2.0 * a * a;
+    }
+    if (wg_sum(off, red) <= offtol2) break;
+    for (int r = 0; r < mm; ++r) {
       for (int k = tid; k < np2; k += nth) {
         int p, q;
-        rr_pair(r, k, nn, p, q);
+        rr_pair(r, k, mm, p, q);
         T c = 1, s = 0, dp = 0, dq = 0;
         if (q < n) {
           const T apq = A[pidx(p, q)], app = A[pidx(p, p)], aqq = A[pidx(q, q)];
@@ -128,7 +188,6 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *red, int *fla
             s = t * c;
             dp = app - t * apq;
             dq = aqq + t * apq;
-            *flag = 1;
           }
         }
         rot[4 * k] = c;
@@ -137,62 +196,54 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *red, int *fla
         rot[4 * k + 3] = dq;
       }
       __syncthreads();
-      for (int k = tid; k < nblk + n * np2; k += nth) {
-        if (k < nblk) {
-          int I, J;
-          tri_ij(k, I, J);
-          int p1, q1, p2, q2;
-          rr_pair(r, I, nn, p1, q1);
-          if (I == J) {
-            if (q1 < n) {
-              A[pidx(p1, p1)] = rot[4 * I + 2];
-              A[pidx(q1, q1)] = rot[4 * I + 3];
-              A[pidx(p1, q1)] = T(0);
-            }
-            continue;
+#pragma unroll
+      for (int sl = 0; sl < kSlots; ++sl) {
+        const int I = bI[sl], J = bJ[sl];
+        if (I < 0) continue;
+        int p1, q1;
+        rr_pair(r, I, mm, p1, q1);
+        if (I == J) {
+          if (q1 < n) {
+            A[pidx(p1, p1)] = rot[4 * I + 2];
+            A[pidx(q1, q1)] = rot[4 * I + 3];
+            A[pidx(p1, q1)] = T(0);
           }
-          rr_pair(r, J, nn, p2, q2);
-          const T c1 = rot[4 * I], s1 = rot[4 * I + 1], c2 = rot[4 * J], s2 = rot[4 * J + 1];
-          const bool hq1 = q1 < n, hq2 = q2 < n;
-          const T a = A[pidx(p1, p2)];
-          const T bq = hq2 ? A[pidx(p1, q2)] : T(0);
-          const T cq = hq1 ? A[pidx(q1, p2)] : T(0);
-          const T d = (hq1 && hq2) ? A[pidx(q1, q2)] : T(0);
-          const T ra = c1 * a - s1 * cq, rb = c1 * bq - s1 * d;  // rows p1, q1 rotated
-          const T rc = s1 * a + c1 * cq, rd = s1 * bq + c1 * d;
-          A[pidx(p1, p2)] = c2 * ra - s2 * rb;  // then columns p2, q2
-          if (hq2) A[pidx(p1, q2)] = s2 * ra + c2 * rb;
-          if (hq1) A[pidx(q1, p2)] = c2 * rc - s2 * rd;
-          if (hq1 && hq2) A[pidx(q1, q2)] = s2 * rc + c2 * rd;
-        } else {
-          const int kk = k - nblk;
-          const int row = kk % n, I = kk / n;
-          int p, q;
-          rr_pair(r, I, nn, p, q);
-          if (q >= n) continue;
-          double c = (double)rot[4 * I], s = (double)rot[4 * I + 1];
-          const double nr = 1.0 / sqrt(c * c + s * s);  // exactly orthogonal in double
-          c *= nr;
-          s *= nr;
-          const double vp = V[row + p * n], vq = V[row + q * n];
-          V[row + p * n] = c * vp - s * vq;
-          V[row + q * n] = s * vp + c * vq;
+          continue;
         }
+        int p2, q2;
+        rr_pair(r, J, mm, p2, q2);
+        const T c1 = rot[4 * I], s1 = rot[4 * I + 1], c2 = rot[4 * J], s2 = rot[4 * J + 1];
+        const bool hq1 = q1 < n, hq2 = q2 < n;
+        const T a = A[pidx(p1, p2)];
+        const T bq = hq2 ? A[pidx(p1, q2)] : T(0);
+        const T cq = hq1 ? A[pidx(q1, p2)] : T(0);
+        const T d = (hq1 && hq2) ? A[pidx(q1, q2)] : T(0);
+        const T ra = c1 * a - s1 * cq, rb = c1 * bq - s1 * d;  // rows p1, q1 rotated
+        const T rc = s1 * a + c1 * cq, rd = s1 * bq + c1 * d;
+        A[pidx(p1, p2)] = c2 * ra - s2 * rb;  // then columns p2, q2
+        if (hq2) A[pidx(p1, q2)] = s2 * ra + c2 * rb;
+        if (hq1) A[pidx(q1, p2)] = c2 * rc - s2 * rd;
+        if (hq1 && hq2) A[pidx(q1, q2)] = s2 * rc + c2 * rd;
+      }
+#pragma unroll
+      for (int sl = 0; sl < kSlots; ++sl) {
+        const int row = vR[sl], I = vI[sl];
+        if (row < 0) continue;
+        int p, q;
+        rr_pair(r, I, mm, p, q);
+        if (q >= n) continue;
+        double c = (double)rot[4 * I], s = (double)rot[4 * I + 1];
+        const double nr = 1.0 / sqrt(c * c + s * s);  // exactly orthogonal in double
+        c *= nr;
+        s *= nr;
+        const double vp = V[row + p * n], vq = V[row + q * n];
+        V[row + p * n] = c * vp - s * vq;
+        V[row + q * n] = s * vp + c * vq;
       }
       __syncthreads();
     }
-    double off = 0.0;
-    for (int k = tid; k < npk; k += nth) {
-      int i, j;
-      tri_ij(k, i, j);
-      const double a = (double)A[k];
-      if (i != j) off += 2.0 * a * a;
-    }
-    const double offsum = wg_sum(off, red);
-    const int rotated = *flag;
-    __syncthreads();
-    if (offsum <= offtol2 || !rotated) break;
   }
+  (void)flag;
 }
 
 // Eigen-indices of the cheaper side: the positive eigenvalues when they are at most as many
@@ -229,12 +280,15 @@ __device__ inline double rebuild(int i, int j, int n, const T *A, const double *
   return acc;
 }
 
-// ADMM step 2: S = (Pi(X_b) - X_b) / sigma for the listed blocks (svec in and out).
+// ADMM step 2: S = (Pi(X_b) - X_b) * scale for the listed blocks (svec in and out), scale <= 0
+// meaning 1 / sigma.  With Q != nullptr the eigenvectors of block k live at Q + qoff[k]; warm
+// selects a start from them (else a cold start) and they are written back after the sweeps.
 template <typename T>
-__global__ void __launch_bounds__(256) k_project_admm(const int32_t *__restrict__ blk_ids, const int64_t *__restrict__ boff,
-                                                      const int32_t *__restrict__ bsz, const double *__restrict__ Xb,
-                                                      double *__restrict__ S, const DevState *__restrict__ st,
-                                                      double scale) {
+__global__ void __launch_bounds__(1024) k_project_admm(const int32_t *__restrict__ blk_ids, const int64_t *__restrict__ boff,
+                                                       const int32_t *__restrict__ bsz, const double *__restrict__ Xb,
+                                                       double *__restrict__ S, const DevState *__restrict__ st,
+                                                       double scale, double *__restrict__ Q,
+                                                       const int64_t *__restrict__ qoff, int32_t warm) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int32_t bk = blk_ids[blockIdx.x];
   const int n = bsz[bk];
@@ -244,31 +298,41 @@ __global__ void __launch_bounds__(256) k_project_admm(const int32_t *__restrict_
   Smem sm = carve<T>(smem, n);
   T *A = reinterpret_cast<T *>(sm.A);
   const double rs2 = 0.70710678118654752440, s2 = 1.41421356237309504880;
-  for (int k = tid; k < npk; k += nth) {  // svec is the packed upper triangle with sqrt(2) off-diagonal
-    int i, j;
-    tri_ij(k, i, j);
-    const double v = Xb[off + k];
-    A[k] = (T)(i == j ? v : v * rs2);
+  double *q = Q ? Q + qoff[bk] : nullptr;
+  const bool use_q = q && warm;
+  if (use_q) {
+    for (int k = tid; k < n * n; k += nth) sm.V[k] = q[k];
+    __syncthreads();
+    rotate_into_basis<T>(n, Xb + off, sm.V, sm.work, A);
+  } else {
+    for (int k = tid; k < npk; k += nth) {  // svec is the packed upper triangle with sqrt(2) off-diagonal
+      int i, j;
+      tri_ij(k, i, j);
+      const double v = Xb[off + k];
+      A[k] = (T)(i == j ? v : v * rs2);
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.red, sm.sel + n + 2);
+  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.red, sm.sel + n + 2, use_q);
   select_side<T>(n, A, sm.sel);
+  if (q)
+    for (int k = tid; k < n * n; k += nth) q[k] = sm.V[k];
   const int pos = sm.sel[n], cnt = sm.sel[n + 1];
-  const double inv_sig = scale > 0.0 ? scale : 1.0 / st->sigma;  // scale 1: S = Pi(X_b) - X_b
+  const double mul = scale > 0.0 ? scale : 1.0 / st->sigma;
   for (int k = tid; k < npk; k += nth) {
     int i, j;
     tri_ij(k, i, j);
     const double acc = rebuild<T>(i, j, n, A, sm.V, sm.sel, cnt) * (i == j ? 1.0 : s2);
-    S[off + k] = pos ? (acc - Xb[off + k]) * inv_sig   // (Pi - X_b) / sigma
-                     : -acc * inv_sig;                  // -Pi_-(X_b) / sigma
+    S[off + k] = pos ? (acc - Xb[off + k]) * mul   // (Pi - X_b) * mul
+                     : -acc * mul;                  // -Pi_-(X_b) * mul
   }
 }
 
 // strom_project_psd_batched: column-major blocks in T, at element offsets.
 template <typename T>
-__global__ void __launch_bounds__(256) k_project_dense(int32_t nblocks, const int32_t *__restrict__ nd,
-                                                       const int64_t *__restrict__ od, const T *__restrict__ in,
-                                                       T *__restrict__ out, int32_t max_n, int32_t *__restrict__ err) {
+__global__ void __launch_bounds__(1024) k_project_dense(int32_t nblocks, const int32_t *__restrict__ nd,
+                                                        const int64_t *__restrict__ od, const T *__restrict__ in,
+                                                        T *__restrict__ out, int32_t max_n, int32_t *__restrict__ err) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int32_t bk = blockIdx.x;
   const int n = nd[bk];
@@ -287,7 +351,7 @@ __global__ void __launch_bounds__(256) k_project_dense(int32_t nblocks, const in
     A[k] = in[off + i + (int64_t)j * n];
   }
   __syncthreads();
-  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.red, sm.sel + n + 2);
+  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.red, sm.sel + n + 2, false);
   select_side<T>(n, A, sm.sel);
   const int pos = sm.sel[n], cnt = sm.sel[n + 1];
   // every thread reads only the upper entries it writes, so out may alias in
@@ -306,18 +370,31 @@ size_t project_lds_bytes(int n, bool f32, int nthreads) {
   return f32 ? lds_bytes_t<float>(n, nthreads) : lds_bytes_t<double>(n, nthreads);
 }
 
-int project_threads(int n) { return n <= 16 ? 64 : 256; }
+// Threads per block: 16 waves for the large blocks (latency hiding of the LDS traffic), and
+// for small blocks enough that every thread holds at most kSlots 2x2 blocks and eigenvector
+// rows per round.
+int project_threads(int n) {
+  if (n > 32) return 1024;
+  const int np2 = (n + 1) / 2;
+  const int need = np2 * (np2 + 1) / 2 > n * np2 ? np2 * (np2 + 1) / 2 : n * np2;
+  int nt = 64;
+  while (nt < 1024 && (nt * kSlots < need || nt < 4 * np2)) nt *= 2;
+  return nt;
+}
 
 hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const int32_t *ids, const int64_t *boff,
-                               const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale) {
+                               const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale,
+                               double *Q, const int64_t *qoff, bool warm) {
   const int nt = project_threads(n);
   const size_t lds = project_lds_bytes(n, f32, nt);
   if (f32) {
     (void)hipFuncSetAttribute((const void *)k_project_admm<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_project_admm<float>, dim3(count), dim3(nt), lds, s, ids, boff, bsz, Xb, S, st, scale);
+    hipLaunchKernelGGL(k_project_admm<float>, dim3(count), dim3(nt), lds, s, ids, boff, bsz, Xb, S, st, scale, Q, qoff,
+                       warm ? 1 : 0);
   } else {
     (void)hipFuncSetAttribute((const void *)k_project_admm<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_project_admm<double>, dim3(count), dim3(nt), lds, s, ids, boff, bsz, Xb, S, st, scale);
+    hipLaunchKernelGGL(k_project_admm<double>, dim3(count), dim3(nt), lds, s, ids, boff, bsz, Xb, S, st, scale, Q, qoff,
+                       warm ? 1 : 0);
   }
   return hipGetLastError();
 }

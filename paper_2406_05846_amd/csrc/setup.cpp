@@ -8,11 +8,13 @@
 //  * eps*I + A A^* = P L D L^T P^T in FP64 (the paper's pre-permuted sparse factorization,
 //    Sec. "GPU Speedup"), eps = eps_reg * max_i (A A^*)_ii, by a left-looking column method
 //    with a symbolic pass over the elimination tree;
-//  * the schedule of the device triangular solves: every group (and every coupling set) is
-//    one task; a task is either solved row-level by row-level inside one workgroup, or --
-//    when it is small and nearly sequential -- through the explicit inverse of its unit
-//    lower-triangular diagonal block (a dense matrix-vector product).  Tasks are launched
-//    by dependency depth, computed from the nonzeros of L.
+//  * the schedule of the device triangular solves.  Every group (and every coupling set) is
+//    one task, solved by one workgroup.  Inside a task the rows are relabeled in order of
+//    their dependency level (a topological order, so the relabeled L is the factor of the
+//    relabeled matrix and nothing is refactored).  Wide levels become level phases (the
+//    rows of a level are independent); runs of narrow levels become dense phases of at most
+//    kMaxDenseRows rows, solved through the explicit inverse of their unit lower-triangular
+//    diagonal block.  Tasks are launched by dependency depth, computed from L.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -33,6 +35,13 @@ void chain_nd(int lo, int hi, std::vector<int> &out) {
   out.push_back(mid);
 }
 
+// Lanes per row for a gather of up to `len` entries.
+int32_t lanes_for(int64_t len) {
+  int32_t g = 1;
+  while (g < 64 && int64_t(g) * 4 < len) g *= 2;
+  return g;
+}
+
 }  // namespace
 
 strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *rowptr,
@@ -47,7 +56,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   H.m = m;
   H.nblocks = nblocks;
   H.bsize.assign(bsize, bsize + nblocks);
-  H.boff.resize(size_t(nblocks) + 1);
+  H.boff.resize(static_cast<size_t>(nblocks) + 1);
   H.boff[0] = 0;
   for (int32_t k = 0; k < nblocks; ++k) {
     if (bsize[k] <= 0) { err = "block size <= 0"; return STROM_E_INVAL; }
@@ -87,7 +96,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
 
   // ---------------------------------------------------------------- grouping and order
   // A block is attached to the largest block that shares a row with it, if that one is larger.
-  std::vector<int32_t> attach(size_t(nblocks), -1);
+  std::vector<int32_t> attach(static_cast<size_t>(nblocks), -1);
   std::vector<int32_t> rb;  // blocks of the current row
   for (int32_t i = 0; i < m; ++i) {
     rb.clear();
@@ -100,7 +109,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
         if (bsize[c] > bsize[a] && (attach[size_t(a)] < 0 || bsize[c] > bsize[attach[size_t(a)]]))
           attach[size_t(a)] = c;
   }
-  std::vector<int32_t> bgroup(size_t(nblocks), -1);
+  std::vector<int32_t> bgroup(static_cast<size_t>(nblocks), -1);
   int32_t ngroups = 0;
   for (int32_t k = 0; k < nblocks; ++k)
     if (attach[size_t(k)] < 0) bgroup[size_t(k)] = ngroups++;
@@ -109,11 +118,9 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     while (attach[size_t(r)] >= 0 && hops++ < nblocks) r = attach[size_t(r)];
     bgroup[size_t(k)] = bgroup[size_t(r)];
   }
-  // row class: interior of group g -> key (0, g); coupling (g1, g1+1) -> (1, chain position);
-  // anything else -> (2, 0).
+  // row class: interior of group g -> (0, g); coupling of groups g, g+1 -> (1, g); other -> (2, 0)
   std::vector<int32_t> rclass(static_cast<size_t>(m)), rkey(static_cast<size_t>(m));
   std::vector<int32_t> rg;
-  bool chain = true;
   for (int32_t i = 0; i < m; ++i) {
     rg.clear();
     for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) rg.push_back(bgroup[size_t(colblock[size_t(col[p])])]);
@@ -121,12 +128,11 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     rg.erase(std::unique(rg.begin(), rg.end()), rg.end());
     if (rg.size() <= 1) { rclass[size_t(i)] = 0; rkey[size_t(i)] = rg.empty() ? 0 : rg[0]; }
     else if (rg.size() == 2 && rg[1] == rg[0] + 1) { rclass[size_t(i)] = 1; rkey[size_t(i)] = rg[0]; }
-    else { rclass[size_t(i)] = 2; rkey[size_t(i)] = 0; chain = false; }
+    else { rclass[size_t(i)] = 2; rkey[size_t(i)] = 0; }
   }
-  (void)chain;
   std::vector<int> sep_pos;
   chain_nd(0, std::max(0, ngroups - 2), sep_pos);
-  std::vector<int32_t> sep_rank(size_t(std::max(1, ngroups)), 0);
+  std::vector<int32_t> sep_rank(static_cast<size_t>(std::max(1, ngroups)), 0);
   for (size_t r = 0; r < sep_pos.size(); ++r) sep_rank[size_t(sep_pos[r])] = int32_t(r);
   H.perm.resize(size_t(m));
   std::iota(H.perm.begin(), H.perm.end(), 0);
@@ -184,11 +190,10 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
 
   // ---------------------------------------------------------------- symbolic factorization
   // struct(L_{:,j}) = struct(K_{j+1:,j}) U (union of struct(L_{:,c}) \ {j} over etree children c)
-  std::vector<int32_t> parent(size_t(m), -1);
-  std::vector<std::vector<int32_t>> children(static_cast<size_t>(m));
   std::vector<int64_t> Cp(size_t(m) + 1, 0);
   std::vector<int32_t> Ci;
   {
+    std::vector<std::vector<int32_t>> children(static_cast<size_t>(m));
     std::vector<int32_t> mark(size_t(m), -1), buf;
     for (int32_t j = 0; j < m; ++j) {
       buf.clear();
@@ -205,21 +210,16 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
         }
       std::sort(buf.begin(), buf.end());
       Ci.insert(Ci.end(), buf.begin(), buf.end());
-      if (!buf.empty()) {
-        parent[size_t(j)] = buf[0];
-        children[size_t(buf[0])].push_back(j);
-      }
+      if (!buf.empty()) children[size_t(buf[0])].push_back(j);
       if (Ci.size() > size_t(1) << 31) { err = "factor too large"; return STROM_E_NOMEM; }
     }
     Cp[size_t(m)] = int64_t(Ci.size());
   }
-  children.clear();
-  children.shrink_to_fit();
 
   // ---------------------------------------------------------------- numeric, left-looking
   const int64_t nnzL = Cp[size_t(m)];
   std::vector<double> Cx(size_t(nnzL), 0.0);
-  H.D.assign(size_t(m), 0.0);
+  std::vector<double> Dn(size_t(m), 0.0);
   {
     std::vector<double> w(size_t(m), 0.0);
     std::vector<int64_t> nxt(size_t(m), 0);        // next unused entry of column k
@@ -230,7 +230,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
       while (k >= 0) {
         const int32_t knext = link[size_t(k)];
         const int64_t p0 = nxt[size_t(k)], pend = Cp[size_t(k) + 1];
-        const double f = Cx[size_t(p0)] * H.D[size_t(k)];  // L(j,k) D(k)
+        const double f = Cx[size_t(p0)] * Dn[size_t(k)];  // L(j,k) D(k)
         for (int64_t p = p0; p < pend; ++p) w[size_t(Ci[size_t(p)])] -= Cx[size_t(p)] * f;
         nxt[size_t(k)] = p0 + 1;
         if (p0 + 1 < pend) {
@@ -246,7 +246,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
         err = "non-positive pivot in LDL^T of eps*I + A A^* at row " + std::to_string(j);
         return STROM_E_FACTOR;
       }
-      H.D[size_t(j)] = dj;
+      Dn[size_t(j)] = dj;
       for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
         const int32_t i = Ci[size_t(p)];
         Cx[size_t(p)] = w[size_t(i)] / dj;
@@ -261,114 +261,186 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     }
   }
   H.nnzL = nnzL;
-  // CSC of L is the CSR of L^T
-  H.Urp = Cp;
-  H.Uci = Ci;
-  H.Uv = Cx;
-  // CSR of L
-  H.Lrp.assign(size_t(m) + 1, 0);
-  for (int64_t p = 0; p < nnzL; ++p) H.Lrp[size_t(Ci[size_t(p)]) + 1]++;
-  for (int32_t i = 0; i < m; ++i) H.Lrp[size_t(i) + 1] += H.Lrp[size_t(i)];
-  H.Lci.resize(size_t(nnzL));
-  H.Lv.resize(size_t(nnzL));
-  {
-    std::vector<int64_t> fill(H.Lrp.begin(), H.Lrp.end() - 1);
-    for (int32_t j = 0; j < m; ++j)  // columns ascending -> each row's columns ascending
-      for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
-        const int64_t q = fill[size_t(Ci[size_t(p)])]++;
-        H.Lci[size_t(q)] = j;
-        H.Lv[size_t(q)] = Cx[size_t(p)];
-      }
-  }
+  Kp.clear(); Ki.clear(); Kx.clear();
 
-  // ---------------------------------------------------------------- solve tasks
+  // ---------------------------------------------------------------- relabel by level
+  // Forward dependency level of every row inside its task; rows of a task are relabeled
+  // in (level, old position) order.  Dependencies point to lower levels, so the relabeled
+  // L stays unit lower triangular and is the factor of the relabeled matrix.
   const int32_t ntask = int32_t(H.task_r0.size());
+  std::vector<int32_t> lev(size_t(m), 0);  // longest dependency path inside the row's task
+  std::vector<int32_t> newpos(static_cast<size_t>(m));
+  {
+    std::vector<int32_t> row_task(static_cast<size_t>(m));
+    for (int32_t t = 0; t < ntask; ++t)
+      for (int32_t r = H.task_r0[size_t(t)]; r < H.task_r1[size_t(t)]; ++r) row_task[size_t(r)] = t;
+    for (int32_t j = 0; j < m; ++j)
+      for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
+        const int32_t i = Ci[size_t(p)];
+        if (row_task[size_t(i)] == row_task[size_t(j)]) lev[size_t(i)] = std::max(lev[size_t(i)], lev[size_t(j)] + 1);
+      }
+    for (int32_t t = 0; t < ntask; ++t) {
+      const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];
+      std::vector<int32_t> rows(size_t(r1 - r0));
+      std::iota(rows.begin(), rows.end(), r0);
+      std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) { return lev[size_t(a)] < lev[size_t(b)]; });
+      for (int32_t k = 0; k < r1 - r0; ++k) newpos[size_t(rows[size_t(k)])] = r0 + k;
+    }
+  }
+  {
+    std::vector<int32_t> perm2(static_cast<size_t>(m));
+    std::vector<double> D2(static_cast<size_t>(m));
+    std::vector<int32_t> lev2(static_cast<size_t>(m));
+    for (int32_t i = 0; i < m; ++i) {
+      perm2[size_t(newpos[size_t(i)])] = H.perm[size_t(i)];
+      D2[size_t(newpos[size_t(i)])] = Dn[size_t(i)];
+      lev2[size_t(newpos[size_t(i)])] = lev[size_t(i)];
+    }
+    H.perm.swap(perm2);
+    H.D.swap(D2);
+    lev.swap(lev2);
+    for (int32_t k = 0; k < m; ++k) H.pinv[size_t(H.perm[size_t(k)])] = k;
+  }
+  // CSR of L (rows ascending columns) and of L^T, in the relabeled order
+  H.Lrp.assign(size_t(m) + 1, 0);
+  H.Urp.assign(size_t(m) + 1, 0);
+  for (int32_t j = 0; j < m; ++j)
+    for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
+      H.Lrp[size_t(newpos[size_t(Ci[size_t(p)])]) + 1]++;
+      H.Urp[size_t(newpos[size_t(j)]) + 1]++;
+    }
+  for (int32_t i = 0; i < m; ++i) { H.Lrp[size_t(i) + 1] += H.Lrp[size_t(i)]; H.Urp[size_t(i) + 1] += H.Urp[size_t(i)]; }
+  H.Lci.resize(size_t(nnzL)); H.Lv.resize(size_t(nnzL));
+  H.Uci.resize(size_t(nnzL)); H.Uv.resize(size_t(nnzL));
+  {
+    std::vector<int64_t> fl(H.Lrp.begin(), H.Lrp.end() - 1), fu(H.Urp.begin(), H.Urp.end() - 1);
+    for (int32_t j = 0; j < m; ++j)
+      for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
+        const int32_t ni = newpos[size_t(Ci[size_t(p)])], nj = newpos[size_t(j)];
+        const int64_t ql = fl[size_t(ni)]++, qu = fu[size_t(nj)]++;
+        H.Lci[size_t(ql)] = nj; H.Lv[size_t(ql)] = Cx[size_t(p)];
+        H.Uci[size_t(qu)] = ni; H.Uv[size_t(qu)] = Cx[size_t(p)];
+      }
+    auto sort_rows = [](std::vector<int64_t> &rp, std::vector<int32_t> &ci, std::vector<double> &v, int32_t mm) {
+      std::vector<std::pair<int32_t, double>> tmp;
+      for (int32_t i = 0; i < mm; ++i) {
+        tmp.clear();
+        for (int64_t p = rp[size_t(i)]; p < rp[size_t(i) + 1]; ++p) tmp.emplace_back(ci[size_t(p)], v[size_t(p)]);
+        std::sort(tmp.begin(), tmp.end());
+        int64_t q = rp[size_t(i)];
+        for (auto &e : tmp) { ci[size_t(q)] = e.first; v[size_t(q)] = e.second; ++q; }
+      }
+    };
+    sort_rows(H.Lrp, H.Lci, H.Lv, m);
+    sort_rows(H.Urp, H.Uci, H.Uv, m);
+  }
+  for (int32_t i = 0; i < m; ++i)  // relabeling kept L lower triangular
+    for (int64_t p = H.Lrp[size_t(i)]; p < H.Lrp[size_t(i) + 1]; ++p)
+      if (H.Lci[size_t(p)] >= i) { err = "internal: relabeled factor not lower triangular"; return STROM_E_FACTOR; }
+  Cp.clear(); Ci.clear(); Cx.clear();
+
+  // ---------------------------------------------------------------- phases and schedule
   std::vector<int32_t> row_task(static_cast<size_t>(m));
   for (int32_t t = 0; t < ntask; ++t)
     for (int32_t r = H.task_r0[size_t(t)]; r < H.task_r1[size_t(t)]; ++r) row_task[size_t(r)] = t;
-  H.task_type.assign(size_t(ntask), kTaskLevels);
-  H.task_flev0.assign(size_t(ntask), 0);
-  H.task_fnlev.assign(size_t(ntask), 0);
-  H.task_blev0.assign(size_t(ntask), 0);
-  H.task_bnlev.assign(size_t(ntask), 0);
-  H.task_inv.assign(size_t(ntask), -1);
   std::vector<int32_t> fdepth(size_t(ntask), 0), bdepth(size_t(ntask), 0);
-  std::vector<int32_t> lev(size_t(m), 0);
   for (int32_t t = 0; t < ntask; ++t) {
     const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)], nt = r1 - r0;
     H.max_task_rows = std::max(H.max_task_rows, nt);
-    // forward levels inside the task and forward task depth
-    int32_t nlev = 0;
-    for (int32_t i = r0; i < r1; ++i) {
-      int32_t l = 0;
+    for (int32_t i = r0; i < r1; ++i)
       for (int64_t p = H.Lrp[size_t(i)]; p < H.Lrp[size_t(i) + 1]; ++p) {
         const int32_t j = H.Lci[size_t(p)];
-        if (j >= r0) l = std::max(l, lev[size_t(j)] + 1);
-        else fdepth[size_t(t)] = std::max(fdepth[size_t(t)], fdepth[size_t(row_task[size_t(j)])] + 1);
+        if (j < r0) fdepth[size_t(t)] = std::max(fdepth[size_t(t)], fdepth[size_t(row_task[size_t(j)])] + 1);
       }
-      lev[size_t(i)] = l;
-      nlev = std::max(nlev, l + 1);
-    }
-    if (nt <= 512 && nlev * 4 > nt && nt > 1) {
-      H.task_type[size_t(t)] = kTaskDense;
-      H.max_dense_rows = std::max(H.max_dense_rows, nt);
-      // explicit inverse of the unit lower-triangular diagonal block, column by column
-      std::vector<double> blk(size_t(nt) * nt, 0.0), inv(size_t(nt) * nt, 0.0);
-      for (int32_t i = r0; i < r1; ++i)
-        for (int64_t p = H.Lrp[size_t(i)]; p < H.Lrp[size_t(i) + 1]; ++p) {
-          const int32_t j = H.Lci[size_t(p)];
-          if (j >= r0) blk[size_t(i - r0) + size_t(j - r0) * nt] = H.Lv[size_t(p)];
+    // level boundaries (rows of one level are contiguous after the relabeling)
+    std::vector<int32_t> lb;
+    for (int32_t i = r0; i < r1; ++i)
+      if (i == r0 || lev[size_t(i)] != lev[size_t(i) - 1]) lb.push_back(i);
+    lb.push_back(r1);
+    H.task_ph0.push_back(int32_t(H.ph_type.size()));
+    const int32_t nl = int32_t(lb.size()) - 1;
+    const int32_t wide = 16;  // levels with fewer rows are merged into dense phases
+    int32_t l = 0;
+    while (l < nl) {
+      if (lb[size_t(l) + 1] - lb[size_t(l)] >= wide || nl == 1) {
+        int32_t l1 = l;  // maximal run of wide levels
+        while (l1 < nl && (lb[size_t(l1) + 1] - lb[size_t(l1)] >= wide || nl == 1)) ++l1;
+        H.ph_type.push_back(kPhaseLevels);
+        H.ph_a.push_back(lb[size_t(l)]);
+        H.ph_b.push_back(lb[size_t(l1)]);
+        H.ph_l0.push_back(int32_t(H.levptr.size()));
+        H.ph_nl.push_back(l1 - l);
+        for (int32_t q = l; q <= l1; ++q) H.levptr.push_back(lb[size_t(q)]);
+        for (int32_t q = l; q < l1; ++q) {
+          int64_t mf = 0, mb = 0;
+          for (int32_t i = lb[size_t(q)]; i < lb[size_t(q) + 1]; ++i) {
+            mf = std::max(mf, H.Lrp[size_t(i) + 1] - H.Lrp[size_t(i)]);
+            mb = std::max(mb, H.Urp[size_t(i) + 1] - H.Urp[size_t(i)]);
+          }
+          H.lvl_gf.push_back(lanes_for(mf));
+          H.lvl_gb.push_back(lanes_for(mb));
         }
-      for (int32_t c = 0; c < nt; ++c) {
-        inv[size_t(c) + size_t(c) * nt] = 1.0;
-        for (int32_t i = c + 1; i < nt; ++i) {
-          double s = 0.0;
-          for (int32_t k = c; k < i; ++k) s -= blk[size_t(i) + size_t(k) * nt] * inv[size_t(k) + size_t(c) * nt];
-          inv[size_t(i) + size_t(c) * nt] = s;
+        H.lvl_gf.push_back(1);  // entry of the closing boundary: lvl_g* stays aligned with levptr
+        H.lvl_gb.push_back(1);
+        H.ph_gf.push_back(0);
+        H.ph_gb.push_back(0);
+        H.ph_inv.push_back(-1);
+        l = l1;
+      } else {
+        int32_t l1 = l;  // narrow levels up to kMaxDenseRows rows
+        while (l1 < nl && (lb[size_t(l1) + 1] - lb[size_t(l1)] < wide) &&
+               lb[size_t(l1) + 1] - lb[size_t(l)] <= kMaxDenseRows)
+          ++l1;
+        if (l1 == l) l1 = l + 1;
+        const int32_t a = lb[size_t(l)], b = lb[size_t(l1)], nd = b - a;
+        H.max_dense_rows = std::max(H.max_dense_rows, nd);
+        int64_t mf = 0, mb = 0;
+        std::vector<double> blk(size_t(nd) * nd, 0.0);
+        for (int32_t i = a; i < b; ++i) {
+          int64_t ext = 0;
+          for (int64_t p = H.Lrp[size_t(i)]; p < H.Lrp[size_t(i) + 1]; ++p) {
+            const int32_t j = H.Lci[size_t(p)];
+            if (j >= a) blk[size_t(i - a) * nd + size_t(j - a)] = H.Lv[size_t(p)];
+            else ++ext;
+          }
+          mf = std::max(mf, ext);
+          int64_t extb = 0;
+          for (int64_t p = H.Urp[size_t(i)]; p < H.Urp[size_t(i) + 1]; ++p) extb += H.Uci[size_t(p)] >= b;
+          mb = std::max(mb, extb);
         }
+        // inverse of the unit lower-triangular block, row-major: inv(i, j) for j <= i
+        std::vector<double> inv(size_t(nd) * nd, 0.0);
+        for (int32_t c = 0; c < nd; ++c) {
+          inv[size_t(c) * nd + size_t(c)] = 1.0;
+          for (int32_t i = c + 1; i < nd; ++i) {
+            double s = 0.0;
+            for (int32_t k = c; k < i; ++k) s -= blk[size_t(i) * nd + size_t(k)] * inv[size_t(k) * nd + size_t(c)];
+            inv[size_t(i) * nd + size_t(c)] = s;
+          }
+        }
+        H.ph_type.push_back(kPhaseDense);
+        H.ph_a.push_back(a);
+        H.ph_b.push_back(b);
+        H.ph_l0.push_back(0);
+        H.ph_nl.push_back(0);
+        H.ph_gf.push_back(lanes_for(mf));
+        H.ph_gb.push_back(lanes_for(mb));
+        H.ph_inv.push_back(int64_t(H.invR.size()));
+        H.invR.insert(H.invR.end(), inv.begin(), inv.end());
+        for (int32_t j = 0; j < nd; ++j)  // column-major copy: column j contiguous
+          for (int32_t i = 0; i < nd; ++i) H.invC.push_back(inv[size_t(i) * nd + size_t(j)]);
+        l = l1;
       }
-      H.task_inv[size_t(t)] = int64_t(H.inv.size());
-      H.inv.insert(H.inv.end(), inv.begin(), inv.end());
-      for (int32_t i = 0; i < nt; ++i)
-        for (int32_t c = 0; c < nt; ++c) H.invT.push_back(inv[size_t(i) + size_t(c) * nt]);  // row-major
-    } else {
-      H.task_flev0[size_t(t)] = int32_t(H.flevptr.size());
-      H.task_fnlev[size_t(t)] = nlev;
-      std::vector<int32_t> cnt(size_t(nlev) + 1, 0);
-      for (int32_t i = r0; i < r1; ++i) cnt[size_t(lev[size_t(i)]) + 1]++;
-      for (int32_t l = 0; l < nlev; ++l) cnt[size_t(l) + 1] += cnt[size_t(l)];
-      const int32_t base = int32_t(H.frows.size());
-      for (int32_t l = 0; l <= nlev; ++l) H.flevptr.push_back(base + cnt[size_t(l)]);
-      H.frows.resize(H.frows.size() + size_t(nt));
-      for (int32_t i = r0; i < r1; ++i) H.frows[size_t(base + cnt[size_t(lev[size_t(i)])]++)] = i;
     }
+    H.task_ph1.push_back(int32_t(H.ph_type.size()));
   }
-  // backward levels (dependencies on rows with larger index) and backward task depth
-  std::fill(lev.begin(), lev.end(), 0);
   for (int32_t t = ntask - 1; t >= 0; --t) {
-    const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)], nt = r1 - r0;
-    int32_t nlev = 0;
-    for (int32_t j = r1 - 1; j >= r0; --j) {
-      int32_t l = 0;
+    const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];
+    for (int32_t j = r0; j < r1; ++j)
       for (int64_t p = H.Urp[size_t(j)]; p < H.Urp[size_t(j) + 1]; ++p) {
         const int32_t i = H.Uci[size_t(p)];
-        if (i < r1) l = std::max(l, lev[size_t(i)] + 1);
-        else bdepth[size_t(t)] = std::max(bdepth[size_t(t)], bdepth[size_t(row_task[size_t(i)])] + 1);
+        if (i >= r1) bdepth[size_t(t)] = std::max(bdepth[size_t(t)], bdepth[size_t(row_task[size_t(i)])] + 1);
       }
-      lev[size_t(j)] = l;
-      nlev = std::max(nlev, l + 1);
-    }
-    if (H.task_type[size_t(t)] == kTaskLevels) {
-      H.task_blev0[size_t(t)] = int32_t(H.blevptr.size());
-      H.task_bnlev[size_t(t)] = nlev;
-      std::vector<int32_t> cnt(size_t(nlev) + 1, 0);
-      for (int32_t j = r0; j < r1; ++j) cnt[size_t(lev[size_t(j)]) + 1]++;
-      for (int32_t l = 0; l < nlev; ++l) cnt[size_t(l) + 1] += cnt[size_t(l)];
-      const int32_t base = int32_t(H.brows.size());
-      for (int32_t l = 0; l <= nlev; ++l) H.blevptr.push_back(base + cnt[size_t(l)]);
-      H.brows.resize(H.brows.size() + size_t(nt));
-      for (int32_t j = r0; j < r1; ++j) H.brows[size_t(base + cnt[size_t(lev[size_t(j)])]++)] = j;
-    }
   }
   auto group_by = [&](const std::vector<int32_t> &depth, std::vector<int32_t> &order, std::vector<int32_t> &gptr) {
     const int32_t maxd = ntask ? *std::max_element(depth.begin(), depth.end()) : 0;

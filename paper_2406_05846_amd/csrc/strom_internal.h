@@ -8,8 +8,11 @@
 
 namespace strom {
 
-// Task types of the triangular solves.
-enum : int32_t { kTaskLevels = 0, kTaskDense = 1 };
+// Phase types of the triangular solves.
+enum : int32_t { kPhaseLevels = 0, kPhaseDense = 1 };
+constexpr int32_t kSolveThreads = 512;     // workgroup size of the solve kernels
+constexpr int32_t kMaxDenseRows = 256;     // rows of one dense phase
+constexpr int32_t kMaxLdsTaskRows = 14336; // task values kept in LDS up to this many rows
 
 // Host result of the one-time analysis of an SDP instance.
 struct HostAnalysis {
@@ -33,13 +36,18 @@ struct HostAnalysis {
   std::vector<int32_t> Uci;
   std::vector<double> Uv;
   std::vector<double> D;
-  // Solve tasks: contiguous row ranges of the new order.
-  std::vector<int32_t> task_r0, task_r1, task_type;
-  std::vector<int32_t> task_flev0, task_fnlev, task_blev0, task_bnlev;  // level tasks
-  std::vector<int64_t> task_inv;                                        // dense tasks
-  std::vector<int32_t> flevptr, frows, blevptr, brows;                  // level lists (absolute rows)
-  std::vector<double> inv;   // dense inverses of diagonal blocks, column-major
-  std::vector<double> invT;  // same, transposed (row-major), for the backward GEMV
+  // Solve tasks: contiguous row ranges of the new order (rows sorted by dependency level
+  // inside a task).  A task is a sequence of phases over consecutive row ranges:
+  //   level phase: consecutive levels [ph_l0, ph_l0 + ph_nl) of levptr, each level a row
+  //                range whose rows are independent; lvl_gf / lvl_gb lanes per row;
+  //   dense phase: rows [ph_a, ph_b) solved through the explicit inverse of their unit
+  //                lower-triangular diagonal block (row-major at ph_inv in invR,
+  //                column-major at ph_inv in invC); ph_g lanes per row for the gathers.
+  std::vector<int32_t> task_r0, task_r1, task_ph0, task_ph1;
+  std::vector<int32_t> ph_type, ph_a, ph_b, ph_l0, ph_nl, ph_gf, ph_gb;
+  std::vector<int64_t> ph_inv;
+  std::vector<int32_t> levptr, lvl_gf, lvl_gb;
+  std::vector<double> invR, invC;
   // Launch schedule: task ids grouped by dependency depth.
   std::vector<int32_t> fwd_order, fwd_gptr, bwd_order, bwd_gptr;
   int32_t max_task_rows = 0;
