@@ -1,9 +1,15 @@
-"""Benchmark: sGS-ADMM iterations/s and solves/s on one MI355X.
+"""Benchmark of the sGS-ADMM hot path on one MI355X; prints one JSON line.
 
-Workload (default): cart-pole, horizon N = 30 (cliques of 11 variables: 30 moment blocks
-78x78 and 60 localizing blocks 12x12; n_svec = 97,110, m = 78,267), instance seed 0, FP64.
-A step is one full sGS-ADMM iteration (steps 1-4 of Algorithm 1, with the device-side sigma
-rule) over that instance, inputs resident in HBM.  Prints one JSON line.
+Workload of ``value``: cart-pole swing-up, horizon N = 30 (cliques of 11 variables: 30 moment
+blocks 78x78 and 60 localizing blocks 12x12; n_svec = 97,110, m = 78,267), instance seed 0,
+plain FP64.  A step is one full sGS-ADMM iteration (steps 1-4 of Algorithm 1 with the
+device-side sigma rule and the KKT residuals every ``kkt_every`` iterations) over that
+instance, its data resident in HBM.  ``value`` is iterations per second.
+
+Beside it: full solves to max KKT residual 1e-6 of the pendulum workload (N = 10, seeds
+0..solves-1; generator + setup + solve, one after another) for solves/s and p50/p99
+latency; the per-phase times of one iteration; the roofline of the dominant kernel; and the
+FP64 CPU oracle timed on a bounded sample of the same cart-pole iteration.
 """
 from __future__ import annotations
 
@@ -16,9 +22,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6
-PEAK_FP32_TFLOPS = 157.3
-PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (vector and matrix)
 
 
 def _log(msg: str) -> None:
@@ -26,34 +30,38 @@ def _log(msg: str) -> None:
 
 
 def _proj_flops(block_sizes) -> float:
-    """Algorithmic flops of one projection of every block: 9n^3 (symmetric eigendecomposition
-    with vectors, Golub-Van Loan count) + 2n^3 (reconstruction)."""
+    """Algorithmic flops of one PSD projection of every block: 9 n^3 for the symmetric
+    eigendecomposition with eigenvectors (tridiagonal reduction + implicit QR with vector
+    accumulation) and 2 n^3 for the reconstruction V diag(max(lambda, 0)) V^T."""
     return float(sum(11.0 * int(n) ** 3 for n in block_sizes))
 
 
 def _cpu_baseline(fam: int, N: int, prm, iters: int) -> dict:
     import oracle
+    oracle.build(force=False)
     t0 = time.perf_counter()
     sdp = oracle.relax(fam, N, prm)
     t1 = time.perf_counter()
     r = oracle.admm_solve(sdp, maxiter=iters, tol=0.0)
-    return {"value": iters / r["t_solve_s"], "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} iterations of the same instance after setup (relaxation {t1 - t0:.2f} s, "
-                      f"LDL^T {r['t_setup_s']:.2f} s), single thread, FP64"}
+    return {"value": round(iters / r["t_solve_s"], 4), "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} sGS-ADMM iterations of the same cart-pole N=30 instance (relaxation "
+                      f"{t1 - t0:.2f} s and LDL^T {r['t_setup_s']:.2f} s excluded), one thread, FP64"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--solves", type=int, default=3, help="full solves timed for solves/s and latency")
+    ap.add_argument("--solves", type=int, default=8, help="pendulum solves timed for solves/s and latency")
+    ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); instances shard across GPUs "
-              "without collectives, so the per-GPU number is the one measured here.", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for {args.gpus}): instances are independent and "
+              "would shard across GPUs without collectives, so only the one-GPU figure is reported.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -65,39 +73,45 @@ def main():
     torch.zeros(1, device="cuda:0")
     fam, N = W.CARTPOLE, 30
     prm = W.instance_params(fam, args.seed)
+    t = time.perf_counter()
     prob = S.generate(fam, N, prm)
+    t_gen = time.perf_counter() - t
     ctx = S.Context(0)
+    t = time.perf_counter()
     inst = S.Instance(ctx, prob)
-
-    # phase breakdown (advances the iterate; done before the timed region)
-    prof = inst.profile(20)
-    _log(f"phase profile (ms): {prof}")
-    inst.set_iterate(np.zeros(prob.nsvec), np.zeros(prob.m), np.zeros(prob.nsvec))
+    t_setup = time.perf_counter() - t
+    _log(f"cart-pole N={N}: n_svec {prob.nsvec}, m {prob.m}, generate {t_gen:.3f} s, setup {t_setup:.3f} s")
 
     inst.enqueue(args.warmup)
     torch.cuda.synchronize()
+    _log(f"warmup {args.warmup} iterations done")
     t0 = time.perf_counter()
     inst.enqueue(args.steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
+    elapsed = time.perf_counter() - t0
     _log(f"timed {args.steps} iterations in {elapsed:.3f} s")
-    iters_per_s = args.steps / elapsed
     info_after = inst.kkt()
+
+    # per-phase times from HIP events on the instance's stream (continues the same iterate)
+    prof = inst.profile(50)
+    _log(f"phase profile (ms): {prof}")
     inst.close()
 
-    # full solves to eta <= 1e-6 (setup included): solves/s and latency
-    lat, iters_needed, pobj = [], [], []
+    # full solves of the pendulum workload at eta <= 1e-6
+    lat, solve_only, iters_needed, states = [], [], [], []
     for k in range(args.solves):
-        p = W.instance_params(fam, args.seed + k)
+        p = W.instance_params(W.PENDULUM, args.seed + k)
         t = time.perf_counter()
-        pr = S.generate(fam, N, p)
+        pr = S.generate(W.PENDULUM, 10, p)
         ins = S.Instance(ctx, pr)
-        inf = ins.step(100000)
-        lat.append(time.perf_counter() - t)
-        _log(f"solve {k}: {lat[-1]:.3f} s, {inf['iters']} iterations, state {inf['state']}")
-        iters_needed.append(inf["iters"])
-        pobj.append(inf["pobj"])
+        t1 = time.perf_counter()
+        inf = ins.step(50000)
+        t2 = time.perf_counter()
+        lat.append(t2 - t)
+        solve_only.append(t2 - t1)
+        iters_needed.append(int(inf["iters"]))
+        states.append(int(inf["state"]))
+        _log(f"pendulum solve {k}: {lat[-1]:.3f} s, {inf['iters']} iterations, state {inf['state']}")
         ins.close()
     lat = np.array(lat)
 
@@ -106,7 +120,7 @@ def main():
     achieved = flops / proj_s / 1e12
     out = {
         "metric": "ADMM iters/s (one instance, FP64) + solves/s at rel KKT 1e-6",
-        "value": round(iters_per_s, 2),
+        "value": round(args.steps / elapsed, 2),
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -117,22 +131,28 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "cart-pole N=30 (30x 78x78 + 60x 12x12 PSD blocks, n_svec 97110, m 78267), "
-                               f"seed {args.seed}, plain FP64 single instance",
-                   "n_svec": prob.nsvec, "m": prob.m, "nnz_A": prob.nnz},
-        "solves_per_s": round(float(1.0 / lat.mean()), 4),
-        "solve_latency_s": {"p50": round(float(np.percentile(lat, 50)), 4),
-                            "p99": round(float(np.percentile(lat, 99)), 4)},
-        "solve_iters": iters_needed,
+        "config": {"workload": "cart-pole swing-up N=30, plain FP64 single instance: 30 moment blocks 78x78 + "
+                               f"60 localizing blocks 12x12, n_svec {prob.nsvec}, m {prob.m}, seed {args.seed}",
+                   "n_svec": prob.nsvec, "m": prob.m, "nnz_A": int(prob.nnz)},
+        "kkt_after_timed": {"iters": int(info_after["iters"]), "eta_p": info_after["eta_p"],
+                            "eta_d": info_after["eta_d"], "eta_g": info_after["eta_g"]},
+        "solves": {"workload": "pendulum N=10 (10 moment blocks 36x36 + 20 localizing 8x8), FP64, "
+                               "generator + setup + solve to eta <= 1e-6, sequential",
+                   "solves_per_s": round(float(1.0 / lat.mean()), 4),
+                   "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4),
+                                 "p99": round(float(np.percentile(lat, 99)), 4)},
+                   "solve_only_s_mean": round(float(np.mean(solve_only)), 4),
+                   "iters": iters_needed, "converged": sum(s == S.CONVERGED for s in states)},
         "phase_ms": {k: round(v, 4) for k, v in prof.items()},
-        "roofline": {"bound": "alu", "kernel": "PSD projection (all blocks of one iteration)",
+        "roofline": {"bound": "alu", "kernel": "k_project_admm<double> (every PSD block of one iteration)",
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 6), "traffic": None},
-        "eta_after_timed": max(info_after["eta_p"], info_after["eta_d"], info_after["eta_g"]),
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = _cpu_baseline(fam, N, prm, 25)
-    print(json.dumps(out))
+        _log("CPU oracle baseline ...")
+        out["cpu_baseline"] = _cpu_baseline(fam, N, prm, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 if __name__ == "__main__":

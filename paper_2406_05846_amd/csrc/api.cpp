@@ -218,6 +218,12 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
                oGf = ar.reserve<int32_t>(std::max<size_t>(1, H.lvl_gf.size())),
                oGb = ar.reserve<int32_t>(std::max<size_t>(1, H.lvl_gb.size()));
   const size_t oFo = ar.reserve<int32_t>(H.fwd_order.size()), oBo = ar.reserve<int32_t>(H.bwd_order.size());
+  const size_t nseg = std::max<size_t>(1, H.seg_pb.size());
+  const size_t oLin = ar.reserve<int64_t>(size_t(m)), oLend = ar.reserve<int64_t>(size_t(m)),
+               oUbeg = ar.reserve<int64_t>(size_t(m)), oSptr = ar.reserve<int64_t>(size_t(m) + 1),
+               oSpb = ar.reserve<int64_t>(nseg), oSpe = ar.reserve<int64_t>(nseg),
+               oTsp = ar.reserve<int32_t>(size_t(ntask) + 1), oTseg = ar.reserve<int32_t>(nseg),
+               oTsg = ar.reserve<int32_t>(size_t(ntask)), oPart = ar.reserve<double>(nseg);
   const size_t oBoff = ar.reserve<int64_t>(size_t(P->nblocks)), oBsz = ar.reserve<int32_t>(size_t(P->nblocks)),
                oIds = ar.reserve<int32_t>(ids.size());
   const size_t oSt = ar.reserve<DevState>(1);
@@ -274,6 +280,9 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   sa.Lrp = P64(oLrp); sa.Lci = P32(oLci); sa.Lv = PD(oLv);
   sa.Urp = P64(oUrp); sa.Uci = P32(oUci); sa.Uv = PD(oUv);
   sa.D = PD(oD); sa.invR = PD(oInvR); sa.invC = PD(oInvC); sa.perm = P32(operm);
+  sa.Lin = P64(oLin); sa.Lend = P64(oLend); sa.Ubeg = P64(oUbeg); sa.sptr = P64(oSptr);
+  sa.seg_pb = P64(oSpb); sa.seg_pe = P64(oSpe); sa.tsptr = P32(oTsp); sa.tseg = P32(oTseg);
+  sa.task_sg = P32(oTsg); sa.part = PD(oPart);
   sa.lds_rows = std::min(H.max_task_rows, strom::kMaxLdsTaskRows);
   s->sch.fwd_gptr = H.fwd_gptr;
   s->sch.bwd_gptr = H.bwd_gptr;
@@ -332,6 +341,15 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   ok &= up(sa.levptr, H.levptr.data(), sizeof(int32_t) * H.levptr.size());
   ok &= up(sa.lvl_gf, H.lvl_gf.data(), sizeof(int32_t) * H.lvl_gf.size());
   ok &= up(sa.lvl_gb, H.lvl_gb.data(), sizeof(int32_t) * H.lvl_gb.size());
+  ok &= up(const_cast<int64_t *>(sa.Lin), H.Lin.data(), sizeof(int64_t) * H.Lin.size());
+  ok &= up(const_cast<int64_t *>(sa.Lend), H.Lend.data(), sizeof(int64_t) * H.Lend.size());
+  ok &= up(const_cast<int64_t *>(sa.Ubeg), H.Ubeg.data(), sizeof(int64_t) * H.Ubeg.size());
+  ok &= up(const_cast<int64_t *>(sa.sptr), H.sptr.data(), sizeof(int64_t) * H.sptr.size());
+  ok &= up(const_cast<int64_t *>(sa.seg_pb), H.seg_pb.data(), sizeof(int64_t) * H.seg_pb.size());
+  ok &= up(const_cast<int64_t *>(sa.seg_pe), H.seg_pe.data(), sizeof(int64_t) * H.seg_pe.size());
+  ok &= up(const_cast<int32_t *>(sa.tsptr), H.tsptr.data(), sizeof(int32_t) * H.tsptr.size());
+  ok &= up(const_cast<int32_t *>(sa.tseg), H.tseg.data(), sizeof(int32_t) * H.tseg.size());
+  ok &= up(const_cast<int32_t *>(sa.task_sg), H.task_sg.data(), sizeof(int32_t) * H.task_sg.size());
   ok &= up(const_cast<int32_t *>(s->sch.fwd_order_dev), H.fwd_order.data(), sizeof(int32_t) * H.fwd_order.size());
   ok &= up(const_cast<int32_t *>(s->sch.bwd_order_dev), H.bwd_order.data(), sizeof(int32_t) * H.bwd_order.size());
   ok &= up(s->boff, H.boff.data(), sizeof(int64_t) * size_t(P->nblocks));

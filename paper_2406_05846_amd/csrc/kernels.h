@@ -32,6 +32,10 @@ struct SolveArgs {
   const double *D;
   const double *invR, *invC;
   const int32_t *perm;
+  const int64_t *Lin, *Lend, *Ubeg;
+  const int64_t *sptr, *seg_pb, *seg_pe;
+  const int32_t *tsptr, *tseg, *task_sg;
+  double *part;      // one partial sum per push segment
   int32_t lds_rows;  // tasks with at most this many rows keep their values in LDS
 };
 

@@ -58,10 +58,72 @@ __global__ void __launch_bounds__(256) k_rhs(int32_t m, const int64_t *__restric
 // One workgroup per task; the task's values stay in LDS while its phases run.  A level
 // phase walks its levels with a barrier in between, g lanes per row (shuffle reduction);
 // a dense phase gathers the contributions of earlier rows and multiplies by the explicit
-// inverse of its diagonal block.
+// inverse of its diagonal block.  Forward contributions from other tasks' columns are not
+// gathered by the receiving row: the task owning the columns computes them as partial sums
+// ("push segments") right after its own rows are solved, so the work of a separator row is
+// spread over the tasks below it.  Every gather keeps four loads in flight per lane.
 __device__ inline double group_sum(double v, int g) {
   for (int off = g >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// sum over p = b, b + g, ... < e of v[p] * xs[ci[p] - r0]
+__device__ inline double gather_own(const int32_t *__restrict__ ci, const double *__restrict__ v, int64_t b, int64_t e,
+                                    int g, const double *xs, int32_t r0) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t p = b;
+  for (; p + 3 * g < e; p += 4 * g) {
+    const int32_t j0 = ci[p], j1 = ci[p + g], j2 = ci[p + 2 * g], j3 = ci[p + 3 * g];
+    const double v0 = v[p], v1 = v[p + g], v2 = v[p + 2 * g], v3 = v[p + 3 * g];
+    s0 += v0 * xs[j0 - r0];
+    s1 += v1 * xs[j1 - r0];
+    s2 += v2 * xs[j2 - r0];
+    s3 += v3 * xs[j3 - r0];
+  }
+  for (; p < e; p += g) s0 += v[p] * xs[ci[p] - r0];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// as gather_own, with columns at or after r1 read from the global vector w
+__device__ inline double gather_mixed(const int32_t *__restrict__ ci, const double *__restrict__ v, int64_t b,
+                                      int64_t e, int g, const double *xs, int32_t r0, int32_t r1,
+                                      const double *__restrict__ w) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t p = b;
+  for (; p + 3 * g < e; p += 4 * g) {
+    const int32_t j0 = ci[p], j1 = ci[p + g], j2 = ci[p + 2 * g], j3 = ci[p + 3 * g];
+    const double v0 = v[p], v1 = v[p + g], v2 = v[p + 2 * g], v3 = v[p + 3 * g];
+    s0 += v0 * (j0 < r1 ? xs[j0 - r0] : w[j0]);
+    s1 += v1 * (j1 < r1 ? xs[j1 - r0] : w[j1]);
+    s2 += v2 * (j2 < r1 ? xs[j2 - r0] : w[j2]);
+    s3 += v3 * (j3 < r1 ? xs[j3 - r0] : w[j3]);
+  }
+  for (; p < e; p += g) {
+    const int32_t j = ci[p];
+    s0 += v[p] * (j < r1 ? xs[j - r0] : w[j]);
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
+__device__ inline double sum_parts(const double *__restrict__ part, int64_t b, int64_t e, int g) {
+  double s = 0.0;
+  for (int64_t q = b; q < e; q += g) s += part[q];
+  return s;
+}
+
+// dot product of a packed inverse row (or column) of length len with c[0 .. len), 16 lanes
+__device__ inline double dense_dot(const double *__restrict__ inv, const double *c, int len, int ln) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = ln;
+  for (; j + 48 < len; j += 64) {
+    const double a0 = inv[j], a1 = inv[j + 16], a2 = inv[j + 32], a3 = inv[j + 48];
+    s0 += a0 * c[j];
+    s1 += a1 * c[j + 16];
+    s2 += a2 * c[j + 32];
+    s3 += a3 * c[j + 48];
+  }
+  for (; j < len; j += 16) s0 += inv[j] * c[j];
+  return (s0 + s1) + (s2 + s3);
 }
 
 __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__restrict__ tasks, SolveArgs a,
@@ -84,11 +146,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__re
         const int lane = tid & (g - 1);
         for (int r = tid / g; r < i1 - i0; r += nth / g) {
           const int32_t i = i0 + r;
-          double s = 0.0;
-          for (int64_t p = a.Lrp[i] + lane; p < a.Lrp[i + 1]; p += g) {
-            const int32_t j = a.Lci[p];
-            s += a.Lv[p] * (j >= r0 ? xs[j - r0] : w[j]);
-          }
+          double s = gather_own(a.Lci, a.Lv, a.Lin[i] + lane, a.Lend[i], g, xs, r0);
+          s += sum_parts(a.part, a.sptr[i] + lane, a.sptr[i + 1], g);
           s = group_sum(s, g);
           if (lane == 0) xs[i - r0] -= s;
         }
@@ -99,24 +158,30 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__re
       const int lane = tid & (g - 1);
       for (int r = tid / g; r < nd; r += nth / g) {
         const int32_t i = pa + r;
-        double s = 0.0;
-        for (int64_t p = a.Lrp[i] + lane; p < a.Lrp[i + 1]; p += g) {
-          const int32_t j = a.Lci[p];
-          if (j < pa) s += a.Lv[p] * (j >= r0 ? xs[j - r0] : w[j]);
-        }
+        double s = gather_own(a.Lci, a.Lv, a.Lin[i] + lane, a.Lend[i], g, xs, r0);
+        s += sum_parts(a.part, a.sptr[i] + lane, a.sptr[i + 1], g);
         s = group_sum(s, g);
         if (lane == 0) c[r] = xs[i - r0] - s;
       }
       __syncthreads();
-      const double *inv = a.invR + a.ph_inv[ph];  // row r of the inverse is contiguous
-      const int ln = tid & 7;
-      for (int r = tid / 8; r < nd; r += nth / 8) {
-        double s = 0.0;
-        for (int j = ln; j <= r; j += 8) s += inv[(int64_t)r * nd + j] * c[j];
-        s = group_sum(s, 8);
+      const double *inv = a.invR + a.ph_inv[ph];  // row r of the inverse at r(r+1)/2
+      const int ln = tid & 15;
+      for (int r = tid >> 4; r < nd; r += nth >> 4) {
+        double s = dense_dot(inv + (int64_t)r * (r + 1) / 2, c, r + 1, ln);
+        s = group_sum(s, 16);
         if (ln == 0) xs[pa + r - r0] = s;
       }
       __syncthreads();
+    }
+  }
+  // push: partial sums of the later rows over this task's columns
+  {
+    const int g = a.task_sg[t], lane = tid & (g - 1);
+    for (int32_t k = a.tsptr[t] + tid / g; k < a.tsptr[t + 1]; k += nth / g) {
+      const int32_t sg = a.tseg[k];
+      double s = gather_own(a.Lci, a.Lv, a.seg_pb[sg] + lane, a.seg_pe[sg], g, xs, r0);
+      s = group_sum(s, g);
+      if (lane == 0) a.part[sg] = s;
     }
   }
   if (inl)
@@ -145,11 +210,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd(const int32_t *__re
         const int lane = tid & (g - 1);
         for (int r = tid / g; r < i1 - i0; r += nth / g) {
           const int32_t j = i0 + r;
-          double s = 0.0;
-          for (int64_t p = a.Urp[j] + lane; p < a.Urp[j + 1]; p += g) {
-            const int32_t i = a.Uci[p];
-            s += a.Uv[p] * (i < r1 ? xs[i - r0] : w[i]);
-          }
+          double s = gather_mixed(a.Uci, a.Uv, a.Ubeg[j] + lane, a.Urp[j + 1], g, xs, r0, r1, w);
           s = group_sum(s, g);
           if (lane == 0) xs[j - r0] = xs[j - r0] / a.D[j] - s;
         }
@@ -160,21 +221,16 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd(const int32_t *__re
       const int lane = tid & (g - 1);
       for (int r = tid / g; r < nd; r += nth / g) {
         const int32_t j = pa + r;
-        double s = 0.0;
-        for (int64_t p = a.Urp[j] + lane; p < a.Urp[j + 1]; p += g) {
-          const int32_t i = a.Uci[p];
-          if (i >= pb) s += a.Uv[p] * (i < r1 ? xs[i - r0] : w[i]);
-        }
+        double s = gather_mixed(a.Uci, a.Uv, a.Ubeg[j] + lane, a.Urp[j + 1], g, xs, r0, r1, w);
         s = group_sum(s, g);
         if (lane == 0) c[r] = xs[j - r0] / a.D[j] - s;
       }
       __syncthreads();
-      const double *inv = a.invC + a.ph_inv[ph];  // column r of the inverse is contiguous
-      const int ln = tid & 7;
-      for (int r = tid / 8; r < nd; r += nth / 8) {
-        double s = 0.0;
-        for (int i = r + ln; i < nd; i += 8) s += inv[(int64_t)r * nd + i] * c[i];
-        s = group_sum(s, 8);
+      const double *inv = a.invC + a.ph_inv[ph];  // column r of the inverse at r*nd - r(r-1)/2
+      const int ln = tid & 15;
+      for (int r = tid >> 4; r < nd; r += nth >> 4) {
+        double s = dense_dot(inv + (int64_t)r * nd - (int64_t)r * (r - 1) / 2, c + r, nd - r, ln);
+        s = group_sum(s, 16);
         if (ln == 0) xs[pa + r - r0] = s;
       }
       __syncthreads();

@@ -4,11 +4,11 @@
 //
 // Eigensolver: cyclic Jacobi in the round-robin parallel ordering.  In one round the n/2
 // disjoint pairs are rotated together, A <- J^T A J; the new value of every 2x2 block
-// (pair P1 x pair P2) depends only on its own four old entries, so each thread updates whole
-// 2x2 blocks of the packed upper triangle with no barrier inside the round.  Each thread
-// computes the indices of its (at most kSlots) 2x2 blocks and eigenvector rows once, so a
-// round costs no integer division.  The matrix is held in T (double, or float for the
-// reduced-precision form); eigenvectors, norms and the reconstruction are double.
+// (pair P1 x pair P2) depends only on its own four old entries, so the 2x2 blocks of the
+// packed upper triangle are updated in parallel with no barrier inside the round.  Rotation
+// parameters are computed in double for both storage types; the matrix is held in T (double,
+// or float for the reduced-precision form); eigenvectors, norms and the reconstruction are
+// double.
 //
 // Warm start (ADMM step): the eigenvectors of the previous call on the same block are kept
 // in HBM; the sweeps start from A = Q^T X_b Q and V = Q, which is nearly diagonal once the
@@ -22,8 +22,6 @@
 
 namespace strom {
 namespace dev {
-
-constexpr int kSlots = 8;  // 2x2 blocks (and eigenvector rows) per thread and round
 
 __device__ inline int pidx(int i, int j) {  // packed upper triangle, by columns
   if (i > j) { const int t = i; i = j; j = t; }
@@ -62,17 +60,17 @@ struct JacobiTol<float> {
   static constexpr double skip_rel = 1e-9;
 };
 
-// LDS: V (n*n doubles, column-major) | red (nthreads doubles) | work (8n doubles, warm start)
-//      | A (packed, T) | rot (4 T per pair: c, s, new a_pp, new a_qq) | sel (n + 4 ints).
+// LDS: V (n*n doubles, column-major) | red (nthreads doubles) | rotd (2 doubles per pair: c, s)
+//      | A (packed upper triangle, T) | rot (4 T per pair: c, s, new a_pp, new a_qq)
+//      | sel (n + 4 ints).
 template <typename T>
 inline size_t lds_bytes_t(int n, int nthreads) {
   const size_t np2 = (size_t)(n + 1) / 2, npk = (size_t)n * (n + 1) / 2;
-  return 8 * ((size_t)n * n + nthreads + 8 * (size_t)n) + sizeof(T) * (npk + 4 * np2) + sizeof(int) * (size_t)(n + 4) +
-         16;
+  return 8 * ((size_t)n * n + nthreads + 2 * np2) + sizeof(T) * (npk + 4 * np2) + sizeof(int) * (size_t)(n + 4) + 16;
 }
 
 struct Smem {
-  double *V, *red, *work;
+  double *V, *red, *rotd;
   void *A, *rot;
   int *sel;
 };
@@ -83,8 +81,8 @@ __device__ inline Smem carve(unsigned char *base, int n) {
   const int np2 = (n + 1) / 2, npk = n * (n + 1) / 2;
   s.V = reinterpret_cast<double *>(base);
   s.red = s.V + n * n;
-  s.work = s.red + blockDim.x;
-  T *A = reinterpret_cast<T *>(s.work + 8 * n);
+  s.rotd = s.red + blockDim.x;
+  T *A = reinterpret_cast<T *>(s.rotd + 2 * np2);
   s.A = A;
   s.rot = A + npk;
   s.sel = reinterpret_cast<int *>(reinterpret_cast<T *>(s.rot) + 4 * np2);
@@ -104,53 +102,61 @@ __device__ inline double wg_sum(double v, double *red) {
   return r;
 }
 
-// A <- Q^T X Q (upper triangle, packed into A) with Q = V in LDS and X the svec block at xs
-// in global memory; work holds 8 columns of X Q at a time.
+// A <- Q^T X Q (packed upper triangle) with Q = V (LDS) and X the svec block at xs (global).
+// Each thread forms 4 entries of a column of W = X Q at a time from X staged through A, then
+// A is overwritten column block by column block once W is complete: W is kept in the block's
+// slot wq of the eigenvector buffer (n*n doubles, free until the eigenvectors are written back).
 template <typename T>
-__device__ void rotate_into_basis(int n, const double *xs, const double *V, double *work, T *A) {
+__device__ void rotate_into_basis(int n, const double *xs, const double *V, double *wq, T *A) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const double rs2 = 0.70710678118654752440;
-  for (int j0 = 0; j0 < n; j0 += 8) {
-    const int cb = min(8, n - j0);
-    for (int e = tid; e < n * cb; e += nth) {  // work(i, c) = sum_k X(i,k) Q(k, j0 + c)
-      const int i = e % n, c = e / n;
-      const double *q = V + (j0 + c) * n;
-      double s = 0.0;
-      for (int k = 0; k < n; ++k) {
-        const double x = xs[pidx(i, k)];
-        s += (i == k ? x : x * rs2) * q[k];
-      }
-      work[c * n + i] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < n * cb; e += nth) {  // A(i, j) = sum_k Q(k, i) work(k, j - j0), i <= j
-      const int i = e % n, c = e / n, j = j0 + c;
-      if (i > j) continue;
-      const double *q = V + i * n;
-      const double *t = work + c * n;
-      double s = 0.0;
-      for (int k = 0; k < n; ++k) s += q[k] * t[k];
-      A[pidx(i, j)] = (T)s;
-    }
-    __syncthreads();
+  const int npk = n * (n + 1) / 2;
+  for (int k = tid; k < npk; k += nth) {  // A <- X (packed, unscaled off-diagonal)
+    int i, j;
+    tri_ij(k, i, j);
+    const double v = xs[k];
+    A[k] = (T)(i == j ? v : v * rs2);
   }
+  __syncthreads();
+  const int nc4 = (n + 3) / 4;
+  for (int e = tid; e < n * nc4; e += nth) {  // W(i, 4c .. 4c+3) = sum_k X(i,k) Q(k, 4c ..)
+    const int i = e % n, c0 = 4 * (e / n);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const int c1 = min(c0 + 1, n - 1), c2 = min(c0 + 2, n - 1), c3 = min(c0 + 3, n - 1);
+    for (int k = 0; k < n; ++k) {
+      const double x = (double)A[pidx(i, k)];
+      s0 += x * V[c0 * n + k];
+      s1 += x * V[c1 * n + k];
+      s2 += x * V[c2 * n + k];
+      s3 += x * V[c3 * n + k];
+    }
+    wq[c0 * n + i] = s0;
+    if (c0 + 1 < n) wq[(c0 + 1) * n + i] = s1;
+    if (c0 + 2 < n) wq[(c0 + 2) * n + i] = s2;
+    if (c0 + 3 < n) wq[(c0 + 3) * n + i] = s3;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int e = tid; e < npk; e += nth) {  // A(i, j) = sum_k Q(k, i) W(k, j), i <= j
+    int i, j;
+    tri_ij(e, i, j);
+    const double *q = V + i * n;
+    const double *w = wq + j * n;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += q[k] * w[k];
+    A[e] = (T)s;
+  }
+  __syncthreads();
 }
 
 template <typename T>
-__device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *red, int *flag, bool v_ready) {
+__device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double *red, bool v_ready) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int np2 = (n + 1) / 2, nn = 2 * np2, mm = nn - 1;
   const int npk = n * (n + 1) / 2;
-  const int nblk = np2 * (np2 + 1) / 2, nvt = n * np2;
-  // this thread's 2x2 blocks (I <= J) and eigenvector rows (row, I), decoded once
-  int bI[kSlots], bJ[kSlots], vR[kSlots], vI[kSlots];
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    const int k = tid + s * nth;
-    bI[s] = bJ[s] = vR[s] = vI[s] = -1;
-    if (k < nblk) tri_ij(k, bI[s], bJ[s]);
-    if (k < nvt) { vR[s] = k % n; vI[s] = k / n; }
-  }
+  const int nblk = np2 * (np2 + 1) / 2;
+  // eigenvector rows: thread -> (row, first pair, pair stride), fixed over the rounds
+  const int vks = nth / n, vrow = tid % n, vk0 = vks > 0 && tid < vks * n ? tid / n : np2;
   if (!v_ready)
     for (int k = tid; k < n * n; k += nth) V[k] = (k % (n + 1) == 0) ? 1.0 : 0.0;
   double f2 = 0.0;
@@ -161,7 +167,7 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *red, int *fla
     f2 += (i == j ? 1.0 : 2.0) * a * a;
   }
   const double fro2 = wg_sum(f2, red);
-  const T skip = (T)(JacobiTol<T>::skip_rel * sqrt(fro2));
+  const double skip = JacobiTol<T>::skip_rel * sqrt(fro2);
   const double offtol2 = JacobiTol<T>::off_rel * JacobiTol<T>::off_rel * fro2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0;  // off-diagonal mass at the start of the sweep
@@ -176,30 +182,31 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *red, int *fla
       for (int k = tid; k < np2; k += nth) {
         int p, q;
         rr_pair(r, k, mm, p, q);
-        T c = 1, s = 0, dp = 0, dq = 0;
+        double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
         if (q < n) {
-          const T apq = A[pidx(p, q)], app = A[pidx(p, p)], aqq = A[pidx(q, q)];
+          const double apq = (double)A[pidx(p, q)], app = (double)A[pidx(p, p)], aqq = (double)A[pidx(q, q)];
           dp = app;
           dq = aqq;
           if (fabs(apq) > skip) {
-            const T theta = (aqq - app) / (T(2) * apq);
-            const T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
-            c = T(1) / sqrt(t * t + T(1));
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
             s = t * c;
             dp = app - t * apq;
             dq = aqq + t * apq;
           }
         }
-        rot[4 * k] = c;
-        rot[4 * k + 1] = s;
-        rot[4 * k + 2] = dp;
-        rot[4 * k + 3] = dq;
+        rot[4 * k] = (T)c;
+        rot[4 * k + 1] = (T)s;
+        rot[4 * k + 2] = (T)dp;
+        rot[4 * k + 3] = (T)dq;
+        rotd[2 * k] = c;
+        rotd[2 * k + 1] = s;
       }
       __syncthreads();
-#pragma unroll
-      for (int sl = 0; sl < kSlots; ++sl) {
-        const int I = bI[sl], J = bJ[sl];
-        if (I < 0) continue;
+      for (int e = tid; e < nblk; e += nth) {
+        int I, J;
+        tri_ij(e, I, J);
         int p1, q1;
         rr_pair(r, I, mm, p1, q1);
         if (I == J) {
@@ -225,47 +232,50 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *red, int *fla
         if (hq1) A[pidx(q1, p2)] = c2 * rc - s2 * rd;
         if (hq1 && hq2) A[pidx(q1, q2)] = s2 * rc + c2 * rd;
       }
-#pragma unroll
-      for (int sl = 0; sl < kSlots; ++sl) {
-        const int row = vR[sl], I = vI[sl];
-        if (row < 0) continue;
+      for (int k = vk0; k < np2; k += vks) {
         int p, q;
-        rr_pair(r, I, mm, p, q);
+        rr_pair(r, k, mm, p, q);
         if (q >= n) continue;
-        double c = (double)rot[4 * I], s = (double)rot[4 * I + 1];
-        const double nr = 1.0 / sqrt(c * c + s * s);  // exactly orthogonal in double
-        c *= nr;
-        s *= nr;
-        const double vp = V[row + p * n], vq = V[row + q * n];
-        V[row + p * n] = c * vp - s * vq;
-        V[row + q * n] = s * vp + c * vq;
+        const double c = rotd[2 * k], s = rotd[2 * k + 1];
+        const double vp = V[vrow + p * n], vq = V[vrow + q * n];
+        V[vrow + p * n] = c * vp - s * vq;
+        V[vrow + q * n] = s * vp + c * vq;
       }
       __syncthreads();
     }
   }
-  (void)flag;
 }
 
 // Eigen-indices of the cheaper side: the positive eigenvalues when they are at most as many
 // as the negative ones (Pi = sum_{lam > 0} lam v v^T), else the negative ones
 // (Pi = X - sum_{lam < 0} lam v v^T).  sel[n] = 1 for the positive side, sel[n+1] = count.
+// The first wave counts and compacts with ballots.
 template <typename T>
 __device__ void select_side(int n, const T *A, int *sel) {
-  if (threadIdx.x == 0) {
+  const int tid = threadIdx.x;
+  if (tid < 64) {
     int np = 0, nneg = 0;
-    for (int k = 0; k < n; ++k) {
-      const T l = A[pidx(k, k)];
-      np += l > T(0);
-      nneg += l < T(0);
+    for (int b = 0; b < n; b += 64) {
+      const int i = b + tid;
+      const T l = i < n ? A[pidx(i, i)] : T(0);
+      np += __popcll(__ballot(l > T(0)));
+      nneg += __popcll(__ballot(l < T(0)));
     }
     const int pos = np <= nneg;
+    const unsigned long long below = (tid == 0) ? 0ull : (~0ull >> (64 - tid));
     int c = 0;
-    for (int k = 0; k < n; ++k) {
-      const T l = A[pidx(k, k)];
-      if (pos ? (l > T(0)) : (l < T(0))) sel[c++] = k;
+    for (int b = 0; b < n; b += 64) {
+      const int i = b + tid;
+      const T l = i < n ? A[pidx(i, i)] : T(0);
+      const bool f = i < n && (pos ? (l > T(0)) : (l < T(0)));
+      const unsigned long long m = __ballot(f);
+      if (f) sel[c + __popcll(m & below)] = i;
+      c += __popcll(m);
     }
-    sel[n] = pos;
-    sel[n + 1] = c;
+    if (tid == 0) {
+      sel[n] = pos;
+      sel[n + 1] = c;
+    }
   }
   __syncthreads();
 }
@@ -303,7 +313,7 @@ __global__ void __launch_bounds__(1024) k_project_admm(const int32_t *__restrict
   if (use_q) {
     for (int k = tid; k < n * n; k += nth) sm.V[k] = q[k];
     __syncthreads();
-    rotate_into_basis<T>(n, Xb + off, sm.V, sm.work, A);
+    rotate_into_basis<T>(n, Xb + off, sm.V, q, A);
   } else {
     for (int k = tid; k < npk; k += nth) {  // svec is the packed upper triangle with sqrt(2) off-diagonal
       int i, j;
@@ -313,7 +323,7 @@ __global__ void __launch_bounds__(1024) k_project_admm(const int32_t *__restrict
     }
     __syncthreads();
   }
-  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.red, sm.sel + n + 2, use_q);
+  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red, use_q);
   select_side<T>(n, A, sm.sel);
   if (q)
     for (int k = tid; k < n * n; k += nth) q[k] = sm.V[k];
@@ -351,7 +361,7 @@ __global__ void __launch_bounds__(1024) k_project_dense(int32_t nblocks, const i
     A[k] = in[off + i + (int64_t)j * n];
   }
   __syncthreads();
-  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.red, sm.sel + n + 2, false);
+  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red, false);
   select_side<T>(n, A, sm.sel);
   const int pos = sm.sel[n], cnt = sm.sel[n + 1];
   // every thread reads only the upper entries it writes, so out may alias in
@@ -371,21 +381,23 @@ size_t project_lds_bytes(int n, bool f32, int nthreads) {
 }
 
 // Threads per block: 16 waves for the large blocks (latency hiding of the LDS traffic), and
-// for small blocks enough that every thread holds at most kSlots 2x2 blocks and eigenvector
-// rows per round.
+// for small blocks one thread per 2x2 block and eigenvector row pair where possible.  Always
+// at least 2n, so that every eigenvector row has its own threads.
 int project_threads(int n) {
   if (n > 32) return 1024;
   const int np2 = (n + 1) / 2;
   const int need = np2 * (np2 + 1) / 2 > n * np2 ? np2 * (np2 + 1) / 2 : n * np2;
   int nt = 64;
-  while (nt < 1024 && (nt * kSlots < need || nt < 4 * np2)) nt *= 2;
+  while (nt < 1024 && (nt < need / 2 || nt < 2 * n)) nt *= 2;
   return nt;
 }
 
 hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const int32_t *ids, const int64_t *boff,
                                const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale,
                                double *Q, const int64_t *qoff, bool warm) {
+  if (count <= 0) return hipSuccess;
   const int nt = project_threads(n);
+  if (nt < n) return hipErrorInvalidValue;
   const size_t lds = project_lds_bytes(n, f32, nt);
   if (f32) {
     (void)hipFuncSetAttribute((const void *)k_project_admm<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -402,6 +414,7 @@ hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const 
 hipError_t launch_project_dense(hipStream_t s, bool f32, int nblocks, int max_n, const int32_t *nd, const int64_t *od,
                                 const void *in, void *out, int32_t *err) {
   const int nt = project_threads(max_n);
+  if (nt < max_n) return hipErrorInvalidValue;
   const size_t lds = project_lds_bytes(max_n, f32, nt);
   if (f32) {
     (void)hipFuncSetAttribute((const void *)k_project_dense<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

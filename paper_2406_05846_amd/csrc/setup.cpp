@@ -426,13 +426,58 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
         H.ph_gf.push_back(lanes_for(mf));
         H.ph_gb.push_back(lanes_for(mb));
         H.ph_inv.push_back(int64_t(H.invR.size()));
-        H.invR.insert(H.invR.end(), inv.begin(), inv.end());
-        for (int32_t j = 0; j < nd; ++j)  // column-major copy: column j contiguous
-          for (int32_t i = 0; i < nd; ++i) H.invC.push_back(inv[size_t(i) * nd + size_t(j)]);
+        for (int32_t i = 0; i < nd; ++i)  // packed lower triangle by rows
+          for (int32_t j = 0; j <= i; ++j) H.invR.push_back(inv[size_t(i) * nd + size_t(j)]);
+        for (int32_t j = 0; j < nd; ++j)  // packed lower triangle by columns
+          for (int32_t i = j; i < nd; ++i) H.invC.push_back(inv[size_t(i) * nd + size_t(j)]);
         l = l1;
       }
     }
     H.task_ph1.push_back(int32_t(H.ph_type.size()));
+  }
+  // entry ranges of the gathers and the push segments
+  H.Lin.resize(size_t(m));
+  H.Lend.resize(size_t(m));
+  H.Ubeg.resize(size_t(m));
+  H.sptr.assign(size_t(m) + 1, 0);
+  std::vector<std::vector<int32_t>> owned(static_cast<size_t>(ntask));
+  std::vector<int64_t> seg_max(static_cast<size_t>(ntask), 0);
+  for (int32_t t = 0; t < ntask; ++t)
+    for (int32_t ph = H.task_ph0[size_t(t)]; ph < H.task_ph1[size_t(t)]; ++ph) {
+      const int32_t a = H.ph_a[size_t(ph)], b = H.ph_b[size_t(ph)];
+      const bool dense = H.ph_type[size_t(ph)] == kPhaseDense;
+      for (int32_t i = a; i < b; ++i) {
+        const int32_t r0 = H.task_r0[size_t(t)];
+        int64_t p = H.Lrp[size_t(i)];
+        const int64_t e = H.Lrp[size_t(i) + 1];
+        int64_t q = p;
+        while (q < e && H.Lci[size_t(q)] < r0) ++q;
+        H.Lin[size_t(i)] = q;
+        int64_t qe = q;
+        if (dense) while (qe < e && H.Lci[size_t(qe)] < a) ++qe;
+        else qe = e;
+        H.Lend[size_t(i)] = qe;
+        while (p < q) {  // split the columns of other tasks by owner
+          const int32_t ot = row_task[size_t(H.Lci[size_t(p)])];
+          int64_t pe = p;
+          while (pe < q && row_task[size_t(H.Lci[size_t(pe)])] == ot) ++pe;
+          owned[size_t(ot)].push_back(int32_t(H.seg_pb.size()));
+          seg_max[size_t(ot)] = std::max(seg_max[size_t(ot)], pe - p);
+          H.seg_pb.push_back(p);
+          H.seg_pe.push_back(pe);
+          p = pe;
+        }
+        H.sptr[size_t(i) + 1] = int64_t(H.seg_pb.size());
+        int64_t u = H.Urp[size_t(i)];
+        if (dense) while (u < H.Urp[size_t(i) + 1] && H.Uci[size_t(u)] < b) ++u;
+        H.Ubeg[size_t(i)] = u;
+      }
+    }
+  H.tsptr.assign(1, 0);
+  for (int32_t t = 0; t < ntask; ++t) {
+    H.tseg.insert(H.tseg.end(), owned[size_t(t)].begin(), owned[size_t(t)].end());
+    H.tsptr.push_back(int32_t(H.tseg.size()));
+    H.task_sg.push_back(std::min<int32_t>(16, lanes_for(seg_max[size_t(t)])));
   }
   for (int32_t t = ntask - 1; t >= 0; --t) {
     const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];

@@ -41,13 +41,25 @@ struct HostAnalysis {
   //   level phase: consecutive levels [ph_l0, ph_l0 + ph_nl) of levptr, each level a row
   //                range whose rows are independent; lvl_gf / lvl_gb lanes per row;
   //   dense phase: rows [ph_a, ph_b) solved through the explicit inverse of their unit
-  //                lower-triangular diagonal block (row-major at ph_inv in invR,
-  //                column-major at ph_inv in invC); ph_g lanes per row for the gathers.
+  //                lower-triangular diagonal block, packed lower triangle at ph_inv (by rows
+  //                in invR: row r at r(r+1)/2; by columns in invC: column c at
+  //                c*nd - c(c-1)/2); ph_g lanes per row for the gathers.
   std::vector<int32_t> task_r0, task_r1, task_ph0, task_ph1;
   std::vector<int32_t> ph_type, ph_a, ph_b, ph_l0, ph_nl, ph_gf, ph_gb;
   std::vector<int64_t> ph_inv;
   std::vector<int32_t> levptr, lvl_gf, lvl_gb;
   std::vector<double> invR, invC;
+  // Forward entries of row i: [Lrp[i], Lin[i]) lie in columns of other (earlier) tasks and
+  // arrive as pushed partial sums; [Lin[i], Lend[i]) are the task's own columns gathered by
+  // the row (Lend[i] < Lrp[i+1] for a dense-phase row: the diagonal block is in the inverse).
+  // Backward entries of row j: [Ubeg[j], Urp[j+1]) (the prefix inside a dense block skipped).
+  std::vector<int64_t> Lin, Lend, Ubeg;
+  // Push segments: segment s is the run [seg_pb[s], seg_pe[s]) of one row's forward entries
+  // whose columns belong to one other task; the owner task computes its partial sum right
+  // after solving its rows.  Row i sums segments [sptr[i], sptr[i+1]); task t owns the
+  // segments tseg[tsptr[t] .. tsptr[t+1]) and pushes them task_sg[t] lanes per segment.
+  std::vector<int64_t> sptr, seg_pb, seg_pe;
+  std::vector<int32_t> tsptr, tseg, task_sg;
   // Launch schedule: task ids grouped by dependency depth.
   std::vector<int32_t> fwd_order, fwd_gptr, bwd_order, bwd_gptr;
   int32_t max_task_rows = 0;
