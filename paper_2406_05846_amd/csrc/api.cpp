@@ -211,12 +211,10 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   const size_t oD = ar.reserve<double>(size_t(m));
   const size_t oInvR = ar.reserve<double>(std::max<size_t>(1, H.invR.size())),
                oInvC = ar.reserve<double>(std::max<size_t>(1, H.invC.size()));
-  const size_t nph = H.ph_type.size();
-  const size_t oTk = ar.reserve<int32_t>(size_t(ntask) * 4), oPh = ar.reserve<int32_t>(std::max<size_t>(1, nph) * 7),
-               oPinv = ar.reserve<int64_t>(std::max<size_t>(1, nph));
-  const size_t oLev = ar.reserve<int32_t>(std::max<size_t>(1, H.levptr.size())),
-               oGf = ar.reserve<int32_t>(std::max<size_t>(1, H.lvl_gf.size())),
-               oGb = ar.reserve<int32_t>(std::max<size_t>(1, H.lvl_gb.size()));
+  const size_t nph = H.ph_a.size();
+  const size_t oTk = ar.reserve<int32_t>(size_t(ntask) * 4), oPh = ar.reserve<int32_t>(std::max<size_t>(1, nph) * 5);
+  const size_t oRcs = ar.reserve<int32_t>(size_t(m)), oRce = ar.reserve<int32_t>(size_t(m)),
+               oRio = ar.reserve<int64_t>(size_t(m));
   const size_t oFo = ar.reserve<int32_t>(H.fwd_order.size()), oBo = ar.reserve<int32_t>(H.bwd_order.size());
   const size_t nseg = std::max<size_t>(1, H.seg_pb.size());
   const size_t oLin = ar.reserve<int64_t>(size_t(m)), oLend = ar.reserve<int64_t>(size_t(m)),
@@ -224,6 +222,15 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
                oSpb = ar.reserve<int64_t>(nseg), oSpe = ar.reserve<int64_t>(nseg),
                oTsp = ar.reserve<int32_t>(size_t(ntask) + 1), oTseg = ar.reserve<int32_t>(nseg),
                oTsg = ar.reserve<int32_t>(size_t(ntask)), oPart = ar.reserve<double>(nseg);
+  size_t oSv[4], oSi[4], oSoff[4], oSK[4], oST[4], oSra[4];
+  for (int k = 0; k < 4; ++k) {
+    oSv[k] = ar.reserve<double>(std::max<size_t>(1, H.sval[k].size()));
+    oSi[k] = ar.reserve<int32_t>(std::max<size_t>(1, H.sidx[k].size()));
+    oSoff[k] = ar.reserve<int64_t>(std::max<size_t>(1, H.s_off[k].size()));
+    oSK[k] = ar.reserve<int32_t>(std::max<size_t>(1, H.s_K[k].size()));
+    oST[k] = ar.reserve<int32_t>(std::max<size_t>(1, H.s_T[k].size()));
+    oSra[k] = ar.reserve<int32_t>(std::max<size_t>(1, H.s_ra[k].size()));
+  }
   const size_t oBoff = ar.reserve<int64_t>(size_t(P->nblocks)), oBsz = ar.reserve<int32_t>(size_t(P->nblocks)),
                oIds = ar.reserve<int32_t>(ids.size());
   const size_t oSt = ar.reserve<DevState>(1);
@@ -273,24 +280,29 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   int32_t *tk = P32(oTk), *ph = P32(oPh);
   auto &sa = s->sa;
   sa.task_r0 = tk; sa.task_r1 = tk + ntask; sa.task_ph0 = tk + 2 * ntask; sa.task_ph1 = tk + 3 * ntask;
-  sa.ph_type = ph; sa.ph_a = ph + nph; sa.ph_b = ph + 2 * nph; sa.ph_l0 = ph + 3 * nph; sa.ph_nl = ph + 4 * nph;
-  sa.ph_gf = ph + 5 * nph; sa.ph_gb = ph + 6 * nph;
-  sa.ph_inv = P64(oPinv);
-  sa.levptr = P32(oLev); sa.lvl_gf = P32(oGf); sa.lvl_gb = P32(oGb);
+  sa.ph_a = ph; sa.ph_b = ph + nph; sa.ph_nns = ph + 2 * nph; sa.ph_gf = ph + 3 * nph; sa.ph_gb = ph + 4 * nph;
+  sa.rcs = P32(oRcs); sa.rce = P32(oRce); sa.rio = P64(oRio);
   sa.Lrp = P64(oLrp); sa.Lci = P32(oLci); sa.Lv = PD(oLv);
   sa.Urp = P64(oUrp); sa.Uci = P32(oUci); sa.Uv = PD(oUv);
   sa.D = PD(oD); sa.invR = PD(oInvR); sa.invC = PD(oInvC); sa.perm = P32(operm);
   sa.Lin = P64(oLin); sa.Lend = P64(oLend); sa.Ubeg = P64(oUbeg); sa.sptr = P64(oSptr);
   sa.seg_pb = P64(oSpb); sa.seg_pe = P64(oSpe); sa.tsptr = P32(oTsp); sa.tseg = P32(oTseg);
   sa.task_sg = P32(oTsg); sa.part = PD(oPart);
-  sa.lds_rows = std::min(H.max_task_rows, strom::kMaxLdsTaskRows);
+  for (int k = 0; k < 4; ++k) {
+    sa.sval[k] = PD(oSv[k]); sa.sidx[k] = P32(oSi[k]); sa.s_off[k] = P64(oSoff[k]);
+    sa.s_K[k] = P32(oSK[k]); sa.s_T[k] = P32(oST[k]); sa.s_ra[k] = P32(oSra[k]);
+  }
+  sa.c_cap = std::max(1, H.max_phase_nns);
+  sa.lds_rows = std::min(H.max_task_rows,
+                         std::min(strom::kMaxLdsTaskRows, int32_t(ctx->max_lds / sizeof(double)) - sa.c_cap -
+                                                             strom::kSolveThreads * 3 / 2 - 8));
   s->sch.fwd_gptr = H.fwd_gptr;
   s->sch.bwd_gptr = H.bwd_gptr;
   s->sch.fwd_order_dev = P32(oFo);
   s->sch.bwd_order_dev = P32(oBo);
 
   // host staging of the small arrays, then synchronous uploads
-  std::vector<int32_t> tkh(size_t(ntask) * 4), phh(std::max<size_t>(1, nph) * 7);
+  std::vector<int32_t> tkh(size_t(ntask) * 4), phh(std::max<size_t>(1, nph) * 5);
   for (int t = 0; t < ntask; ++t) {
     tkh[size_t(t)] = H.task_r0[size_t(t)];
     tkh[size_t(ntask + t)] = H.task_r1[size_t(t)];
@@ -298,13 +310,11 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
     tkh[size_t(3 * ntask + t)] = H.task_ph1[size_t(t)];
   }
   for (size_t k = 0; k < nph; ++k) {
-    phh[k] = H.ph_type[k];
-    phh[nph + k] = H.ph_a[k];
-    phh[2 * nph + k] = H.ph_b[k];
-    phh[3 * nph + k] = H.ph_l0[k];
-    phh[4 * nph + k] = H.ph_nl[k];
-    phh[5 * nph + k] = H.ph_gf[k];
-    phh[6 * nph + k] = H.ph_gb[k];
+    phh[k] = H.ph_a[k];
+    phh[nph + k] = H.ph_b[k];
+    phh[2 * nph + k] = H.ph_nns[k];
+    phh[3 * nph + k] = H.ph_gf[k];
+    phh[4 * nph + k] = H.ph_gb[k];
   }
   std::vector<double> zeros;
   auto up = [&](const void *dst, const void *src, size_t bytes) -> bool {
@@ -337,10 +347,9 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   ok &= up(sa.invC, H.invC.data(), sizeof(double) * H.invC.size());
   ok &= up(tk, tkh.data(), sizeof(int32_t) * tkh.size());
   ok &= up(ph, phh.data(), sizeof(int32_t) * phh.size());
-  ok &= up(sa.ph_inv, H.ph_inv.data(), sizeof(int64_t) * H.ph_inv.size());
-  ok &= up(sa.levptr, H.levptr.data(), sizeof(int32_t) * H.levptr.size());
-  ok &= up(sa.lvl_gf, H.lvl_gf.data(), sizeof(int32_t) * H.lvl_gf.size());
-  ok &= up(sa.lvl_gb, H.lvl_gb.data(), sizeof(int32_t) * H.lvl_gb.size());
+  ok &= up(const_cast<int32_t *>(sa.rcs), H.rcs.data(), sizeof(int32_t) * H.rcs.size());
+  ok &= up(const_cast<int32_t *>(sa.rce), H.rce.data(), sizeof(int32_t) * H.rce.size());
+  ok &= up(const_cast<int64_t *>(sa.rio), H.rio.data(), sizeof(int64_t) * H.rio.size());
   ok &= up(const_cast<int64_t *>(sa.Lin), H.Lin.data(), sizeof(int64_t) * H.Lin.size());
   ok &= up(const_cast<int64_t *>(sa.Lend), H.Lend.data(), sizeof(int64_t) * H.Lend.size());
   ok &= up(const_cast<int64_t *>(sa.Ubeg), H.Ubeg.data(), sizeof(int64_t) * H.Ubeg.size());
@@ -350,6 +359,14 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   ok &= up(const_cast<int32_t *>(sa.tsptr), H.tsptr.data(), sizeof(int32_t) * H.tsptr.size());
   ok &= up(const_cast<int32_t *>(sa.tseg), H.tseg.data(), sizeof(int32_t) * H.tseg.size());
   ok &= up(const_cast<int32_t *>(sa.task_sg), H.task_sg.data(), sizeof(int32_t) * H.task_sg.size());
+  for (int k = 0; k < 4; ++k) {
+    ok &= up(const_cast<double *>(sa.sval[k]), H.sval[k].data(), sizeof(double) * H.sval[k].size());
+    ok &= up(const_cast<int32_t *>(sa.sidx[k]), H.sidx[k].data(), sizeof(int32_t) * H.sidx[k].size());
+    ok &= up(const_cast<int64_t *>(sa.s_off[k]), H.s_off[k].data(), sizeof(int64_t) * H.s_off[k].size());
+    ok &= up(const_cast<int32_t *>(sa.s_K[k]), H.s_K[k].data(), sizeof(int32_t) * H.s_K[k].size());
+    ok &= up(const_cast<int32_t *>(sa.s_T[k]), H.s_T[k].data(), sizeof(int32_t) * H.s_T[k].size());
+    ok &= up(const_cast<int32_t *>(sa.s_ra[k]), H.s_ra[k].data(), sizeof(int32_t) * H.s_ra[k].size());
+  }
   ok &= up(const_cast<int32_t *>(s->sch.fwd_order_dev), H.fwd_order.data(), sizeof(int32_t) * H.fwd_order.size());
   ok &= up(const_cast<int32_t *>(s->sch.bwd_order_dev), H.bwd_order.data(), sizeof(int32_t) * H.bwd_order.size());
   ok &= up(s->boff, H.boff.data(), sizeof(int64_t) * size_t(P->nblocks));

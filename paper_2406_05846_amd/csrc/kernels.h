@@ -20,9 +20,9 @@ struct DevState {
 // Device arrays of the triangular solves (see setup.cpp for their meaning).
 struct SolveArgs {
   const int32_t *task_r0, *task_r1, *task_ph0, *task_ph1;
-  const int32_t *ph_type, *ph_a, *ph_b, *ph_l0, *ph_nl, *ph_gf, *ph_gb;
-  const int64_t *ph_inv;
-  const int32_t *levptr, *lvl_gf, *lvl_gb;
+  const int32_t *ph_a, *ph_b, *ph_nns, *ph_gf, *ph_gb;
+  const int32_t *rcs, *rce;
+  const int64_t *rio;
   const int64_t *Lrp;
   const int32_t *Lci;
   const double *Lv;
@@ -36,7 +36,17 @@ struct SolveArgs {
   const int64_t *sptr, *seg_pb, *seg_pe;
   const int32_t *tsptr, *tseg, *task_sg;
   double *part;      // one partial sum per push segment
+  // phase streams, kinds 0 forward gather, 1 forward inverse, 2 backward gather,
+  // 3 backward inverse: values, indices, per-phase offset, entries per thread, thread
+  // stride, row runs
+  const double *sval[4];
+  const int32_t *sidx[4];
+  const int64_t *s_off[4];
+  const int32_t *s_K[4];
+  const int32_t *s_T[4];
+  const int32_t *s_ra[4];
   int32_t lds_rows;  // tasks with at most this many rows keep their values in LDS
+  int32_t c_cap;     // LDS doubles for the right-hand sides of a phase's components
 };
 
 struct SolveSchedule {

@@ -55,10 +55,10 @@ __global__ void __launch_bounds__(256) k_rhs(int32_t m, const int64_t *__restric
 }
 
 // ------------------------------------------------------------------ triangular solves
-// One workgroup per task; the task's values stay in LDS while its phases run.  A level
-// phase walks its levels with a barrier in between, g lanes per row (shuffle reduction);
-// a dense phase gathers the contributions of earlier rows and multiplies by the explicit
-// inverse of its diagonal block.  Forward contributions from other tasks' columns are not
+// One workgroup per task; the task's values stay in LDS while its phases run.  A phase
+// gathers, g lanes per row (shuffle reduction), the contributions of earlier phases to each
+// of its rows; rows on their own are then solved, and every component of two or more rows
+// is solved by a product with the explicit inverse of its diagonal block.  Forward contributions from other tasks' columns are not
 // gathered by the receiving row: the task owning the columns computes them as partial sums
 // ("push segments") right after its own rows are solved, so the work of a separator row is
 // spread over the tasks below it.  Every gather keeps four loads in flight per lane.
@@ -126,6 +126,62 @@ __device__ inline double dense_dot(const double *__restrict__ inv, const double 
   return (s0 + s1) + (s2 + s3);
 }
 
+// One phase stream (see setup.cpp): thread t walks its slice of K entries (entry k at
+// off + k * Tp + t), eight loads in flight, then the eight factors get(index) (get never
+// reads what fin writes), then adds them in order; fin(row, sum) completes a row.  A row
+// that started in an earlier slice is completed after a barrier by the thread holding its
+// last entry, adding the pieces of the earlier slices in order (tail_v / tail_r: the open
+// row of every slice).  Contains one __syncthreads(): call from all threads.
+template <class Get, class Fin>
+__device__ inline void stream_phase(const double *__restrict__ val, const int32_t *__restrict__ idx, int64_t off,
+                                    int32_t K, int32_t Tp, const int32_t *__restrict__ first, double *tail_v,
+                                    int32_t *tail_r, Get get, Fin fin) {
+  const int t = threadIdx.x;
+  int32_t head_row = -1;
+  double head_v = 0.0;
+  if (t < Tp) {
+    const int32_t f = first[t];
+    int32_t row = f & (kStartFlag - 1);
+    bool own = (f & kStartFlag) != 0;
+    const double *vp = val + off + t;
+    const int32_t *ip = idx + off + t;
+    double acc = 0.0;
+    for (int32_t k0 = 0; k0 < K; k0 += 8) {
+      double v[8];
+      int32_t x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[u] = vp[(int64_t)(k0 + u) * Tp];
+        x[u] = ip[(int64_t)(k0 + u) * Tp];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] *= get(x[u] & (kLastFlag - 1));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        acc += v[u];
+        if (x[u] & kLastFlag) {
+          if (own) fin(row, acc);
+          else { head_row = row; head_v = acc; }
+          acc = 0.0;
+          ++row;
+          own = true;
+        }
+      }
+    }
+    tail_v[t] = acc;
+    tail_r[t] = own ? row : -1 - row;  // the open row; negative: it started in an earlier slice
+  }
+  __syncthreads();
+  if (head_row >= 0) {
+    double s = 0.0;
+    int u = t - 1;
+    while (u >= 0 && tail_r[u] == -1 - head_row) --u;  // slices lying inside the row
+    // u is the slice where the row starts (its open row is head_row, non-negative)
+    for (int q = u; q < t; ++q) s += tail_v[q];
+    fin(head_row, s + head_v);
+  }
+}
+
 __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__restrict__ tasks, SolveArgs a,
                                                              double *__restrict__ w) {
   extern __shared__ double sh[];
@@ -133,46 +189,31 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__re
   const int32_t t = tasks[blockIdx.x];
   const int32_t r0 = a.task_r0[t], r1 = a.task_r1[t], nt = r1 - r0;
   const bool inl = nt <= a.lds_rows;
-  double *xs = inl ? sh : (w + r0);  // values of the task rows, index i - r0
-  double *c = inl ? sh + nt : sh;    // gathered right-hand side of a dense phase
+  double *tail_v = sh;  // open-row pieces of the stream slices
+  int32_t *tail_r = reinterpret_cast<int32_t *>(sh + kSolveThreads);
+  double *buf = sh + kSolveThreads + kSolveThreads / 2;
+  double *xs = inl ? buf : (w + r0);  // values of the task rows, index i - r0
+  double *c = inl ? buf + nt : buf;   // right-hand sides of the phase's components
   if (inl)
     for (int i = tid; i < nt; i += nth) xs[i] = w[r0 + i];
   __syncthreads();
   for (int32_t ph = a.task_ph0[t]; ph < a.task_ph1[t]; ++ph) {
-    if (a.ph_type[ph] == 0) {
-      const int32_t l0 = a.ph_l0[ph], nl = a.ph_nl[ph];
-      for (int32_t q = 0; q < nl; ++q) {
-        const int32_t i0 = a.levptr[l0 + q], i1 = a.levptr[l0 + q + 1], g = a.lvl_gf[l0 + q];
-        const int lane = tid & (g - 1);
-        for (int r = tid / g; r < i1 - i0; r += nth / g) {
-          const int32_t i = i0 + r;
-          double s = gather_own(a.Lci, a.Lv, a.Lin[i] + lane, a.Lend[i], g, xs, r0);
-          s += sum_parts(a.part, a.sptr[i] + lane, a.sptr[i + 1], g);
-          s = group_sum(s, g);
-          if (lane == 0) xs[i - r0] -= s;
-        }
-        __syncthreads();
-      }
-    } else {
-      const int32_t pa = a.ph_a[ph], nd = a.ph_b[ph] - pa, g = a.ph_gf[ph];
-      const int lane = tid & (g - 1);
-      for (int r = tid / g; r < nd; r += nth / g) {
-        const int32_t i = pa + r;
-        double s = gather_own(a.Lci, a.Lv, a.Lin[i] + lane, a.Lend[i], g, xs, r0);
-        s += sum_parts(a.part, a.sptr[i] + lane, a.sptr[i + 1], g);
-        s = group_sum(s, g);
-        if (lane == 0) c[r] = xs[i - r0] - s;
-      }
+    const int32_t pa = a.ph_a[ph], nns = a.ph_nns[ph];
+    stream_phase(a.sval[0], a.sidx[0], a.s_off[0][ph], a.s_K[0][ph], a.s_T[0][ph],
+                a.s_ra[0] + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
+                [&](int32_t j) { return (j & kPartFlag) ? a.part[j & (kPartFlag - 1)] : xs[j - r0]; },
+                [&](int32_t r, double acc) {
+                  const double v = xs[pa + r - r0] - acc;
+                  if (r < nns) c[r] = v;
+                  else xs[pa + r - r0] = v;  // a row on its own: solved
+                });
+    if (nns > 0) {
       __syncthreads();
-      const double *inv = a.invR + a.ph_inv[ph];  // row r of the inverse at r(r+1)/2
-      const int ln = tid & 15;
-      for (int r = tid >> 4; r < nd; r += nth >> 4) {
-        double s = dense_dot(inv + (int64_t)r * (r + 1) / 2, c, r + 1, ln);
-        s = group_sum(s, 16);
-        if (ln == 0) xs[pa + r - r0] = s;
-      }
-      __syncthreads();
+      stream_phase(a.sval[1], a.sidx[1], a.s_off[1][ph], a.s_K[1][ph], a.s_T[1][ph],
+                  a.s_ra[1] + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
+                  [&](int32_t j) { return c[j]; }, [&](int32_t r, double acc) { xs[pa + r - r0] = acc; });
     }
+    __syncthreads();
   }
   // push: partial sums of the later rows over this task's columns
   {
@@ -188,8 +229,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__re
     for (int i = tid; i < nt; i += nth) w[r0 + i] = xs[i];
 }
 
-// Backward: L^T x = D^{-1} z over the phases and levels in reverse order (a row at forward
-// level l only depends here on rows at higher levels or in later tasks).
+// Backward: L^T x = D^{-1} z over the phases in reverse order (a row only depends here on
+// its own component, later phases and later tasks).
 __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd(const int32_t *__restrict__ tasks, SolveArgs a,
                                                              double *__restrict__ w, double *__restrict__ y) {
   extern __shared__ double sh[];
@@ -197,44 +238,32 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd(const int32_t *__re
   const int32_t t = tasks[blockIdx.x];
   const int32_t r0 = a.task_r0[t], r1 = a.task_r1[t], nt = r1 - r0;
   const bool inl = nt <= a.lds_rows;
-  double *xs = inl ? sh : (w + r0);
-  double *c = inl ? sh + nt : sh;
+  double *tail_v = sh;
+  int32_t *tail_r = reinterpret_cast<int32_t *>(sh + kSolveThreads);
+  double *buf = sh + kSolveThreads + kSolveThreads / 2;
+  double *xs = inl ? buf : (w + r0);
+  double *c = inl ? buf + nt : buf;
   if (inl)
     for (int i = tid; i < nt; i += nth) xs[i] = w[r0 + i];
   __syncthreads();
   for (int32_t ph = a.task_ph1[t] - 1; ph >= a.task_ph0[t]; --ph) {
-    if (a.ph_type[ph] == 0) {
-      const int32_t l0 = a.ph_l0[ph], nl = a.ph_nl[ph];
-      for (int32_t q = nl - 1; q >= 0; --q) {
-        const int32_t i0 = a.levptr[l0 + q], i1 = a.levptr[l0 + q + 1], g = a.lvl_gb[l0 + q];
-        const int lane = tid & (g - 1);
-        for (int r = tid / g; r < i1 - i0; r += nth / g) {
-          const int32_t j = i0 + r;
-          double s = gather_mixed(a.Uci, a.Uv, a.Ubeg[j] + lane, a.Urp[j + 1], g, xs, r0, r1, w);
-          s = group_sum(s, g);
-          if (lane == 0) xs[j - r0] = xs[j - r0] / a.D[j] - s;
-        }
-        __syncthreads();
-      }
-    } else {
-      const int32_t pa = a.ph_a[ph], pb = a.ph_b[ph], nd = pb - pa, g = a.ph_gb[ph];
-      const int lane = tid & (g - 1);
-      for (int r = tid / g; r < nd; r += nth / g) {
-        const int32_t j = pa + r;
-        double s = gather_mixed(a.Uci, a.Uv, a.Ubeg[j] + lane, a.Urp[j + 1], g, xs, r0, r1, w);
-        s = group_sum(s, g);
-        if (lane == 0) c[r] = xs[j - r0] / a.D[j] - s;
-      }
+    const int32_t pa = a.ph_a[ph], nns = a.ph_nns[ph];
+    stream_phase(a.sval[2], a.sidx[2], a.s_off[2][ph], a.s_K[2][ph], a.s_T[2][ph],
+                a.s_ra[2] + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
+                [&](int32_t i) { return i < r1 ? xs[i - r0] : w[i]; },
+                [&](int32_t r, double acc) {
+                  const int32_t j = pa + r;
+                  const double v = xs[j - r0] / a.D[j] - acc;
+                  if (r < nns) c[r] = v;
+                  else xs[j - r0] = v;
+                });
+    if (nns > 0) {
       __syncthreads();
-      const double *inv = a.invC + a.ph_inv[ph];  // column r of the inverse at r*nd - r(r-1)/2
-      const int ln = tid & 15;
-      for (int r = tid >> 4; r < nd; r += nth >> 4) {
-        double s = dense_dot(inv + (int64_t)r * nd - (int64_t)r * (r - 1) / 2, c + r, nd - r, ln);
-        s = group_sum(s, 16);
-        if (ln == 0) xs[pa + r - r0] = s;
-      }
-      __syncthreads();
+      stream_phase(a.sval[3], a.sidx[3], a.s_off[3][ph], a.s_K[3][ph], a.s_T[3][ph],
+                  a.s_ra[3] + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
+                  [&](int32_t j) { return c[j]; }, [&](int32_t r, double acc) { xs[pa + r - r0] = acc; });
     }
+    __syncthreads();
   }
   for (int i = tid; i < nt; i += nth) {
     const double v = xs[i];
@@ -375,7 +404,7 @@ hipError_t launch_rhs(hipStream_t s, int32_t m, const int64_t *rp, const int32_t
 }
 
 hipError_t launch_solve(hipStream_t s, const SolveSchedule &sch, const SolveArgs &a, double *w, double *y) {
-  const size_t lds = sizeof(double) * (size_t)(a.lds_rows + kMaxDenseRows);
+  const size_t lds = sizeof(double) * (size_t)(kSolveThreads + kSolveThreads / 2 + a.lds_rows + a.c_cap);
   (void)hipFuncSetAttribute((const void *)k_solve_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipFuncSetAttribute((const void *)k_solve_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   for (int g = 0; g + 1 < (int)sch.fwd_gptr.size(); ++g) {

@@ -9,12 +9,14 @@
 //    Sec. "GPU Speedup"), eps = eps_reg * max_i (A A^*)_ii, by a left-looking column method
 //    with a symbolic pass over the elimination tree;
 //  * the schedule of the device triangular solves.  Every group (and every coupling set) is
-//    one task, solved by one workgroup.  Inside a task the rows are relabeled in order of
-//    their dependency level (a topological order, so the relabeled L is the factor of the
-//    relabeled matrix and nothing is refactored).  Wide levels become level phases (the
-//    rows of a level are independent); runs of narrow levels become dense phases of at most
-//    kMaxDenseRows rows, solved through the explicit inverse of their unit lower-triangular
-//    diagonal block.  Tasks are launched by dependency depth, computed from L.
+//    one task, solved by one workgroup.  The dependency levels of a task are cut into
+//    phases whose rows form small connected components (chains of the factor); each
+//    component is solved at once through the explicit inverse of its unit lower-triangular
+//    diagonal block, so a phase costs one gather and one small dense product whatever the
+//    number of levels it spans.  Rows are relabeled in (phase, component, level) order (a
+//    topological order, so the relabeled L is the factor of the relabeled matrix and
+//    nothing is refactored).  Contributions to rows of later tasks are pushed as partial
+//    sums by the task owning the columns.  Tasks are launched by dependency depth.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -50,6 +52,10 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   // ---------------------------------------------------------------- validation
   if (nblocks <= 0 || !bsize || m <= 0 || !rowptr || !col || !val) {
     err = "empty problem or NULL array";
+    return STROM_E_INVAL;
+  }
+  if (m >= kPartFlag) {
+    err = "too many constraints";
     return STROM_E_INVAL;
   }
   H = HostAnalysis();
@@ -263,42 +269,126 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   H.nnzL = nnzL;
   Kp.clear(); Ki.clear(); Kx.clear();
 
-  // ---------------------------------------------------------------- relabel by level
-  // Forward dependency level of every row inside its task; rows of a task are relabeled
-  // in (level, old position) order.  Dependencies point to lower levels, so the relabeled
-  // L stays unit lower triangular and is the factor of the relabeled matrix.
+  // ---------------------------------------------------------------- phases and relabeling
+  // Forward dependency level of every row inside its task (longest dependency path from a
+  // row of the task that depends on no other row of it).  The levels of a task are cut
+  // greedily into phases: a phase is a run of consecutive levels whose rows, joined by the
+  // dependencies among them, form connected components of at most kMaxBlockRows rows (at
+  // most kMaxPhaseBlockRows rows in components of two or more).  Rows of a task are then
+  // relabeled in (phase, component, level) order.  Dependencies inside a component point to
+  // lower levels and dependencies between phases to earlier phases, so the relabeled L stays
+  // unit lower triangular and is the factor of the relabeled matrix (nothing is refactored).
   const int32_t ntask = int32_t(H.task_r0.size());
-  std::vector<int32_t> lev(size_t(m), 0);  // longest dependency path inside the row's task
-  std::vector<int32_t> newpos(static_cast<size_t>(m));
+  std::vector<int32_t> row_task(static_cast<size_t>(m));
+  for (int32_t t = 0; t < ntask; ++t)
+    for (int32_t r = H.task_r0[size_t(t)]; r < H.task_r1[size_t(t)]; ++r) row_task[size_t(r)] = t;
+  std::vector<int32_t> lev(size_t(m), 0);
+  std::vector<int64_t> predp(size_t(m) + 1, 0);  // predecessors inside the task, CSR by row
+  std::vector<int32_t> predi;
+  for (int32_t j = 0; j < m; ++j)
+    for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
+      const int32_t i = Ci[size_t(p)];
+      if (row_task[size_t(i)] == row_task[size_t(j)]) {
+        lev[size_t(i)] = std::max(lev[size_t(i)], lev[size_t(j)] + 1);
+        predp[size_t(i) + 1]++;
+      }
+    }
+  for (int32_t i = 0; i < m; ++i) predp[size_t(i) + 1] += predp[size_t(i)];
+  predi.resize(size_t(predp[size_t(m)]));
   {
-    std::vector<int32_t> row_task(static_cast<size_t>(m));
-    for (int32_t t = 0; t < ntask; ++t)
-      for (int32_t r = H.task_r0[size_t(t)]; r < H.task_r1[size_t(t)]; ++r) row_task[size_t(r)] = t;
+    std::vector<int64_t> f(predp.begin(), predp.end() - 1);
     for (int32_t j = 0; j < m; ++j)
       for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
         const int32_t i = Ci[size_t(p)];
-        if (row_task[size_t(i)] == row_task[size_t(j)]) lev[size_t(i)] = std::max(lev[size_t(i)], lev[size_t(j)] + 1);
+        if (row_task[size_t(i)] == row_task[size_t(j)]) predi[size_t(f[size_t(i)]++)] = j;
       }
-    for (int32_t t = 0; t < ntask; ++t) {
-      const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];
-      std::vector<int32_t> rows(size_t(r1 - r0));
-      std::iota(rows.begin(), rows.end(), r0);
-      std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) { return lev[size_t(a)] < lev[size_t(b)]; });
-      for (int32_t k = 0; k < r1 - r0; ++k) newpos[size_t(rows[size_t(k)])] = r0 + k;
-    }
   }
+  std::vector<int32_t> rphase(size_t(m), 0), rcomp(size_t(m), 0), rcsize(size_t(m), 1);
+  std::vector<int32_t> newpos(static_cast<size_t>(m));
+  std::vector<int32_t> task_nph(size_t(ntask), 0);
+  for (int32_t t = 0; t < ntask; ++t) {
+    const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)], nt = r1 - r0;
+    int32_t L = 0;
+    for (int32_t i = r0; i < r1; ++i) L = std::max(L, lev[size_t(i)] + 1);
+    std::vector<std::vector<int32_t>> bylev(static_cast<size_t>(L));
+    for (int32_t i = r0; i < r1; ++i) bylev[size_t(lev[size_t(i)])].push_back(i);
+    std::vector<int32_t> par(static_cast<size_t>(nt)), sz(static_cast<size_t>(nt), 1);
+    std::iota(par.begin(), par.end(), 0);
+    auto find = [&](std::vector<int32_t> &pa, int32_t x) {
+      while (pa[size_t(x)] != x) { pa[size_t(x)] = pa[size_t(pa[size_t(x)])]; x = pa[size_t(x)]; }
+      return x;
+    };
+    int32_t l = 0, ph = 0;
+    while (l < L) {
+      int32_t l1 = l, maxc = 1;
+      int64_t nns = 0;  // rows in components of two or more
+      while (l1 < L) {
+        std::vector<int32_t> par2 = par, sz2 = sz;
+        int32_t maxc2 = maxc;
+        for (int32_t i : bylev[size_t(l1)])
+          for (int64_t p = predp[size_t(i)]; p < predp[size_t(i) + 1]; ++p) {
+            const int32_t j = predi[size_t(p)];
+            if (lev[size_t(j)] < l) continue;  // earlier phase
+            int32_t a = find(par2, i - r0), b = find(par2, j - r0);
+            if (a == b) continue;
+            if (sz2[size_t(a)] < sz2[size_t(b)]) std::swap(a, b);
+            par2[size_t(b)] = a;
+            sz2[size_t(a)] += sz2[size_t(b)];
+            maxc2 = std::max(maxc2, sz2[size_t(a)]);
+          }
+        int64_t nns2 = 0;
+        if (maxc2 > 1) {
+          for (int32_t q = l; q <= l1; ++q)
+            for (int32_t i : bylev[size_t(q)]) nns2 += sz2[size_t(find(par2, i - r0))] > 1;
+        }
+        if (l1 > l && (maxc2 > kMaxBlockRows || nns2 > kMaxPhaseBlockRows)) break;
+        par.swap(par2);
+        sz.swap(sz2);
+        maxc = maxc2;
+        nns = nns2;
+        ++l1;
+      }
+      (void)nns;
+      for (int32_t q = l; q < l1; ++q)
+        for (int32_t i : bylev[size_t(q)]) {
+          const int32_t root = find(par, i - r0);
+          rphase[size_t(i)] = ph;
+          rcomp[size_t(i)] = root;
+          rcsize[size_t(i)] = sz[size_t(root)];
+        }
+      ++ph;
+      l = l1;
+    }
+    task_nph[size_t(t)] = ph;
+    std::vector<int32_t> rows(static_cast<size_t>(nt));
+    std::iota(rows.begin(), rows.end(), r0);
+    std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) {
+      if (rphase[size_t(a)] != rphase[size_t(b)]) return rphase[size_t(a)] < rphase[size_t(b)];
+      const bool sa = rcsize[size_t(a)] == 1, sb = rcsize[size_t(b)] == 1;
+      if (sa != sb) return !sa;  // components of two or more first, singletons last
+      if (rcomp[size_t(a)] != rcomp[size_t(b)]) return rcomp[size_t(a)] < rcomp[size_t(b)];
+      return lev[size_t(a)] < lev[size_t(b)];
+    });
+    for (int32_t k = 0; k < nt; ++k) newpos[size_t(rows[size_t(k)])] = r0 + k;
+  }
+  predp.clear(); predi.clear();
   {
     std::vector<int32_t> perm2(static_cast<size_t>(m));
     std::vector<double> D2(static_cast<size_t>(m));
-    std::vector<int32_t> lev2(static_cast<size_t>(m));
+    std::vector<int32_t> ph2(static_cast<size_t>(m)), cs2(static_cast<size_t>(m)), cz2(static_cast<size_t>(m));
     for (int32_t i = 0; i < m; ++i) {
-      perm2[size_t(newpos[size_t(i)])] = H.perm[size_t(i)];
-      D2[size_t(newpos[size_t(i)])] = Dn[size_t(i)];
-      lev2[size_t(newpos[size_t(i)])] = lev[size_t(i)];
+      const size_t ni = size_t(newpos[size_t(i)]);
+      perm2[ni] = H.perm[size_t(i)];
+      D2[ni] = Dn[size_t(i)];
+      ph2[ni] = rphase[size_t(i)];
+      cs2[ni] = rcomp[size_t(i)];
+      cz2[ni] = rcsize[size_t(i)];
     }
     H.perm.swap(perm2);
     H.D.swap(D2);
-    lev.swap(lev2);
+    rphase.swap(ph2);
+    rcomp.swap(cs2);
+    rcsize.swap(cz2);
     for (int32_t k = 0; k < m; ++k) H.pinv[size_t(H.perm[size_t(k)])] = k;
   }
   // CSR of L (rows ascending columns) and of L^T, in the relabeled order
@@ -339,10 +429,18 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
       if (H.Lci[size_t(p)] >= i) { err = "internal: relabeled factor not lower triangular"; return STROM_E_FACTOR; }
   Cp.clear(); Ci.clear(); Cx.clear();
 
-  // ---------------------------------------------------------------- phases and schedule
-  std::vector<int32_t> row_task(static_cast<size_t>(m));
-  for (int32_t t = 0; t < ntask; ++t)
-    for (int32_t r = H.task_r0[size_t(t)]; r < H.task_r1[size_t(t)]; ++r) row_task[size_t(r)] = t;
+  // ---------------------------------------------------------------- phase descriptors
+  // Per phase: rows [ph_a, ph_b), of which the first ph_nns lie in components of two or
+  // more rows.  Per row: its component [rcs, rce) and the offset rio of the component's
+  // inverse (-1 for a single row).  The inverse of the component's unit lower-triangular
+  // diagonal block of L is stored as a packed lower triangle, by rows in invR (row r at
+  // r(r+1)/2) and by columns in invC (column c at c*n - c(c-1)/2), at the same offset.
+  H.rcs.resize(size_t(m));
+  H.rce.resize(size_t(m));
+  H.rio.assign(size_t(m), -1);
+  H.Lin.resize(size_t(m));
+  H.Lend.resize(size_t(m));
+  H.Ubeg.resize(size_t(m));
   std::vector<int32_t> fdepth(size_t(ntask), 0), bdepth(size_t(ntask), 0);
   for (int32_t t = 0; t < ntask; ++t) {
     const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)], nt = r1 - r0;
@@ -352,133 +450,188 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
         const int32_t j = H.Lci[size_t(p)];
         if (j < r0) fdepth[size_t(t)] = std::max(fdepth[size_t(t)], fdepth[size_t(row_task[size_t(j)])] + 1);
       }
-    // level boundaries (rows of one level are contiguous after the relabeling)
-    std::vector<int32_t> lb;
-    for (int32_t i = r0; i < r1; ++i)
-      if (i == r0 || lev[size_t(i)] != lev[size_t(i) - 1]) lb.push_back(i);
-    lb.push_back(r1);
-    H.task_ph0.push_back(int32_t(H.ph_type.size()));
-    const int32_t nl = int32_t(lb.size()) - 1;
-    const int32_t wide = 16;  // levels with fewer rows are merged into dense phases
-    int32_t l = 0;
-    while (l < nl) {
-      if (lb[size_t(l) + 1] - lb[size_t(l)] >= wide || nl == 1) {
-        int32_t l1 = l;  // maximal run of wide levels
-        while (l1 < nl && (lb[size_t(l1) + 1] - lb[size_t(l1)] >= wide || nl == 1)) ++l1;
-        H.ph_type.push_back(kPhaseLevels);
-        H.ph_a.push_back(lb[size_t(l)]);
-        H.ph_b.push_back(lb[size_t(l1)]);
-        H.ph_l0.push_back(int32_t(H.levptr.size()));
-        H.ph_nl.push_back(l1 - l);
-        for (int32_t q = l; q <= l1; ++q) H.levptr.push_back(lb[size_t(q)]);
-        for (int32_t q = l; q < l1; ++q) {
-          int64_t mf = 0, mb = 0;
-          for (int32_t i = lb[size_t(q)]; i < lb[size_t(q) + 1]; ++i) {
-            mf = std::max(mf, H.Lrp[size_t(i) + 1] - H.Lrp[size_t(i)]);
-            mb = std::max(mb, H.Urp[size_t(i) + 1] - H.Urp[size_t(i)]);
+    H.task_ph0.push_back(int32_t(H.ph_a.size()));
+    int32_t a = r0;
+    while (a < r1) {
+      int32_t b = a;
+      while (b < r1 && rphase[size_t(b)] == rphase[size_t(a)]) ++b;
+      int32_t nns = 0;
+      int64_t mf = 0, mb = 0;
+      int32_t c0 = a;
+      while (c0 < b) {  // components: runs of equal rcomp
+        int32_t c1 = c0;
+        while (c1 < b && rcomp[size_t(c1)] == rcomp[size_t(c0)]) ++c1;
+        const int32_t cn = c1 - c0;
+        int64_t io = -1;
+        if (cn > 1) {
+          nns += cn;
+          std::vector<double> blk(size_t(cn) * cn, 0.0), inv(size_t(cn) * cn, 0.0);
+          for (int32_t i = c0; i < c1; ++i)
+            for (int64_t p = H.Lrp[size_t(i)]; p < H.Lrp[size_t(i) + 1]; ++p) {
+              const int32_t j = H.Lci[size_t(p)];
+              if (j >= c0) blk[size_t(i - c0) * cn + size_t(j - c0)] = H.Lv[size_t(p)];
+              else if (j >= a) { err = "internal: dependency between components of a phase"; return STROM_E_FACTOR; }
+            }
+          for (int32_t c = 0; c < cn; ++c) {  // inverse of the unit lower-triangular block
+            inv[size_t(c) * cn + size_t(c)] = 1.0;
+            for (int32_t i = c + 1; i < cn; ++i) {
+              double sacc = 0.0;
+              for (int32_t k = c; k < i; ++k) sacc -= blk[size_t(i) * cn + size_t(k)] * inv[size_t(k) * cn + size_t(c)];
+              inv[size_t(i) * cn + size_t(c)] = sacc;
+            }
           }
-          H.lvl_gf.push_back(lanes_for(mf));
-          H.lvl_gb.push_back(lanes_for(mb));
+          io = int64_t(H.invR.size());
+          for (int32_t i = 0; i < cn; ++i)
+            for (int32_t j = 0; j <= i; ++j) H.invR.push_back(inv[size_t(i) * cn + size_t(j)]);
+          for (int32_t j = 0; j < cn; ++j)
+            for (int32_t i = j; i < cn; ++i) H.invC.push_back(inv[size_t(i) * cn + size_t(j)]);
         }
-        H.lvl_gf.push_back(1);  // entry of the closing boundary: lvl_g* stays aligned with levptr
-        H.lvl_gb.push_back(1);
-        H.ph_gf.push_back(0);
-        H.ph_gb.push_back(0);
-        H.ph_inv.push_back(-1);
-        l = l1;
-      } else {
-        int32_t l1 = l;  // narrow levels up to kMaxDenseRows rows
-        while (l1 < nl && (lb[size_t(l1) + 1] - lb[size_t(l1)] < wide) &&
-               lb[size_t(l1) + 1] - lb[size_t(l)] <= kMaxDenseRows)
-          ++l1;
-        if (l1 == l) l1 = l + 1;
-        const int32_t a = lb[size_t(l)], b = lb[size_t(l1)], nd = b - a;
-        H.max_dense_rows = std::max(H.max_dense_rows, nd);
-        int64_t mf = 0, mb = 0;
-        std::vector<double> blk(size_t(nd) * nd, 0.0);
-        for (int32_t i = a; i < b; ++i) {
-          int64_t ext = 0;
-          for (int64_t p = H.Lrp[size_t(i)]; p < H.Lrp[size_t(i) + 1]; ++p) {
-            const int32_t j = H.Lci[size_t(p)];
-            if (j >= a) blk[size_t(i - a) * nd + size_t(j - a)] = H.Lv[size_t(p)];
-            else ++ext;
-          }
-          mf = std::max(mf, ext);
-          int64_t extb = 0;
-          for (int64_t p = H.Urp[size_t(i)]; p < H.Urp[size_t(i) + 1]; ++p) extb += H.Uci[size_t(p)] >= b;
-          mb = std::max(mb, extb);
+        for (int32_t i = c0; i < c1; ++i) {
+          H.rcs[size_t(i)] = c0;
+          H.rce[size_t(i)] = c1;
+          H.rio[size_t(i)] = io;
+          int64_t q = H.Lrp[size_t(i)];
+          while (q < H.Lrp[size_t(i) + 1] && H.Lci[size_t(q)] < r0) ++q;
+          H.Lin[size_t(i)] = q;
+          while (q < H.Lrp[size_t(i) + 1] && H.Lci[size_t(q)] < a) ++q;
+          H.Lend[size_t(i)] = q;
+          int64_t u = H.Urp[size_t(i)];
+          while (u < H.Urp[size_t(i) + 1] && H.Uci[size_t(u)] < c1) ++u;
+          H.Ubeg[size_t(i)] = u;
+          mb = std::max(mb, H.Urp[size_t(i) + 1] - u);
         }
-        // inverse of the unit lower-triangular block, row-major: inv(i, j) for j <= i
-        std::vector<double> inv(size_t(nd) * nd, 0.0);
-        for (int32_t c = 0; c < nd; ++c) {
-          inv[size_t(c) * nd + size_t(c)] = 1.0;
-          for (int32_t i = c + 1; i < nd; ++i) {
-            double s = 0.0;
-            for (int32_t k = c; k < i; ++k) s -= blk[size_t(i) * nd + size_t(k)] * inv[size_t(k) * nd + size_t(c)];
-            inv[size_t(i) * nd + size_t(c)] = s;
-          }
-        }
-        H.ph_type.push_back(kPhaseDense);
-        H.ph_a.push_back(a);
-        H.ph_b.push_back(b);
-        H.ph_l0.push_back(0);
-        H.ph_nl.push_back(0);
-        H.ph_gf.push_back(lanes_for(mf));
-        H.ph_gb.push_back(lanes_for(mb));
-        H.ph_inv.push_back(int64_t(H.invR.size()));
-        for (int32_t i = 0; i < nd; ++i)  // packed lower triangle by rows
-          for (int32_t j = 0; j <= i; ++j) H.invR.push_back(inv[size_t(i) * nd + size_t(j)]);
-        for (int32_t j = 0; j < nd; ++j)  // packed lower triangle by columns
-          for (int32_t i = j; i < nd; ++i) H.invC.push_back(inv[size_t(i) * nd + size_t(j)]);
-        l = l1;
+        c0 = c1;
       }
+      for (int32_t i = a; i < b; ++i) mf = std::max(mf, H.Lend[size_t(i)] - H.Lin[size_t(i)]);
+      H.ph_a.push_back(a);
+      H.ph_b.push_back(b);
+      H.ph_nns.push_back(nns);
+      H.ph_gf.push_back(lanes_for(mf));
+      H.ph_gb.push_back(lanes_for(mb));
+      H.max_phase_nns = std::max(H.max_phase_nns, nns);
+      a = b;
     }
-    H.task_ph1.push_back(int32_t(H.ph_type.size()));
+    H.task_ph1.push_back(int32_t(H.ph_a.size()));
   }
-  // entry ranges of the gathers and the push segments
-  H.Lin.resize(size_t(m));
-  H.Lend.resize(size_t(m));
-  H.Ubeg.resize(size_t(m));
+
+  // ---------------------------------------------------------------- push segments
+  // The forward entries of row i in columns of other tasks, [Lrp[i], Lin[i]), are split by
+  // the owner task of the columns; each run is one segment, summed by its owner.
   H.sptr.assign(size_t(m) + 1, 0);
   std::vector<std::vector<int32_t>> owned(static_cast<size_t>(ntask));
   std::vector<int64_t> seg_max(static_cast<size_t>(ntask), 0);
-  for (int32_t t = 0; t < ntask; ++t)
-    for (int32_t ph = H.task_ph0[size_t(t)]; ph < H.task_ph1[size_t(t)]; ++ph) {
-      const int32_t a = H.ph_a[size_t(ph)], b = H.ph_b[size_t(ph)];
-      const bool dense = H.ph_type[size_t(ph)] == kPhaseDense;
-      for (int32_t i = a; i < b; ++i) {
-        const int32_t r0 = H.task_r0[size_t(t)];
-        int64_t p = H.Lrp[size_t(i)];
-        const int64_t e = H.Lrp[size_t(i) + 1];
-        int64_t q = p;
-        while (q < e && H.Lci[size_t(q)] < r0) ++q;
-        H.Lin[size_t(i)] = q;
-        int64_t qe = q;
-        if (dense) while (qe < e && H.Lci[size_t(qe)] < a) ++qe;
-        else qe = e;
-        H.Lend[size_t(i)] = qe;
-        while (p < q) {  // split the columns of other tasks by owner
-          const int32_t ot = row_task[size_t(H.Lci[size_t(p)])];
-          int64_t pe = p;
-          while (pe < q && row_task[size_t(H.Lci[size_t(pe)])] == ot) ++pe;
-          owned[size_t(ot)].push_back(int32_t(H.seg_pb.size()));
-          seg_max[size_t(ot)] = std::max(seg_max[size_t(ot)], pe - p);
-          H.seg_pb.push_back(p);
-          H.seg_pe.push_back(pe);
-          p = pe;
-        }
-        H.sptr[size_t(i) + 1] = int64_t(H.seg_pb.size());
-        int64_t u = H.Urp[size_t(i)];
-        if (dense) while (u < H.Urp[size_t(i) + 1] && H.Uci[size_t(u)] < b) ++u;
-        H.Ubeg[size_t(i)] = u;
-      }
+  for (int32_t i = 0; i < m; ++i) {
+    int64_t p = H.Lrp[size_t(i)];
+    const int64_t q = H.Lin[size_t(i)];
+    while (p < q) {
+      const int32_t ot = row_task[size_t(H.Lci[size_t(p)])];
+      int64_t pe = p;
+      while (pe < q && row_task[size_t(H.Lci[size_t(pe)])] == ot) ++pe;
+      owned[size_t(ot)].push_back(int32_t(H.seg_pb.size()));
+      seg_max[size_t(ot)] = std::max(seg_max[size_t(ot)], pe - p);
+      H.seg_pb.push_back(p);
+      H.seg_pe.push_back(pe);
+      p = pe;
     }
+    H.sptr[size_t(i) + 1] = int64_t(H.seg_pb.size());
+  }
+  if (int64_t(H.seg_pb.size()) >= int64_t(kPartFlag)) {
+    err = "too many push segments";
+    return STROM_E_INVAL;
+  }
+  // the row gathers also sum their segments: widen the phase lanes by the segment count
+  for (size_t ph = 0; ph < H.ph_a.size(); ++ph) {
+    int64_t mf = 0;
+    for (int32_t i = H.ph_a[ph]; i < H.ph_b[ph]; ++i)
+      mf = std::max(mf, H.Lend[size_t(i)] - H.Lin[size_t(i)] + H.sptr[size_t(i) + 1] - H.sptr[size_t(i)]);
+    H.ph_gf[ph] = lanes_for(mf);
+  }
   H.tsptr.assign(1, 0);
   for (int32_t t = 0; t < ntask; ++t) {
     H.tseg.insert(H.tseg.end(), owned[size_t(t)].begin(), owned[size_t(t)].end());
     H.tsptr.push_back(int32_t(H.tseg.size()));
     H.task_sg.push_back(std::min<int32_t>(16, lanes_for(seg_max[size_t(t)])));
   }
+
+  // ---------------------------------------------------------------- phase streams
+  // Every phase is solved from four entry streams.  The entries of the phase's rows (in row
+  // order; a row with no entry gets one zero entry) are cut into Tp equal slices of K
+  // entries (Tp <= kSolveThreads a multiple of 64, K a multiple of 8, as few slices of 8 as
+  // cover the phase), slice t for thread t, entry k of it at off + k * Tp + t so that every
+  // load of a wave is contiguous.  A row may span several slices; its pieces are added in
+  // slice order.  An entry is a value and an index; the index of the last entry of a row
+  // carries kLastFlag.  s_ra holds per thread the phase-relative row of its first entry,
+  // with kStartFlag when that entry starts the row.  Streams:
+  //   fg: forward gather, the row's pushed partial sums (index s | kPartFlag, value 1) and
+  //       L(i, j) for own-task columns j of earlier phases (index j);
+  //   fi: forward inverse, row i of its component's inverse (index: position in the phase
+  //       right-hand side buffer);
+  //   bg: backward gather, L(i, j) for rows i after the row's component (index i);
+  //   bi: backward inverse, column j of its component's inverse (index as fi).
+  {
+    const int32_t T = kSolveThreads;
+    auto build = [&](int32_t ph, int32_t rbeg, int32_t rend, int kind) {
+      const int32_t pad_idx = (kind == 0 || kind == 2) ? rbeg : 0;
+      std::vector<std::pair<int32_t, double>> ent;  // the whole phase, rows in order
+      std::vector<int32_t> erow;                    // phase-relative row of each entry
+      std::vector<char> efirst;                     // entry starts its row
+      for (int32_t i = rbeg; i < rend; ++i) {
+        const size_t e0 = ent.size();
+        if (kind == 0) {
+          for (int64_t q = H.sptr[size_t(i)]; q < H.sptr[size_t(i) + 1]; ++q) ent.emplace_back(int32_t(q) | kPartFlag, 1.0);
+          for (int64_t p = H.Lin[size_t(i)]; p < H.Lend[size_t(i)]; ++p) ent.emplace_back(H.Lci[size_t(p)], H.Lv[size_t(p)]);
+        } else if (kind == 2) {
+          for (int64_t p = H.Ubeg[size_t(i)]; p < H.Urp[size_t(i) + 1]; ++p) ent.emplace_back(H.Uci[size_t(p)], H.Uv[size_t(p)]);
+        } else {
+          const int32_t cs = H.rcs[size_t(i)], cn = H.rce[size_t(i)] - cs, kk = i - cs;
+          const int32_t base = cs - H.ph_a[size_t(ph)];
+          if (kind == 1)
+            for (int32_t j = 0; j <= kk; ++j) ent.emplace_back(base + j, H.invR[size_t(H.rio[size_t(i)] + int64_t(kk) * (kk + 1) / 2 + j)]);
+          else
+            for (int32_t e = 0; e < cn - kk; ++e)
+              ent.emplace_back(base + kk + e, H.invC[size_t(H.rio[size_t(i)] + int64_t(kk) * cn - int64_t(kk) * (kk - 1) / 2 + e)]);
+        }
+        if (ent.size() == e0) ent.emplace_back(pad_idx, 0.0);
+        ent.back().first |= kLastFlag;
+        for (size_t e = e0; e < ent.size(); ++e) {
+          erow.push_back(i - rbeg);
+          efirst.push_back(e == e0);
+        }
+      }
+      const int64_t E = int64_t(ent.size());
+      int64_t K = 8;
+      int32_t Tp = int32_t(std::min<int64_t>(T, (E + K - 1) / K));
+      if (int64_t(Tp) * K < E) K = ((E + Tp - 1) / Tp + 7) / 8 * 8;
+      Tp = std::min<int32_t>(T, std::max<int32_t>(64, (Tp + 63) / 64 * 64));
+      std::vector<int32_t> ra(size_t(T) + 1, rend - rbeg);
+      std::vector<double> &V = H.sval[size_t(kind)];
+      std::vector<int32_t> &X = H.sidx[size_t(kind)];
+      const int64_t off = int64_t(V.size());
+      V.resize(size_t(off + K * Tp), 0.0);
+      X.resize(size_t(off + K * Tp), pad_idx);
+      for (int32_t t = 0; t < Tp; ++t) {
+        const int64_t e0 = int64_t(t) * K;
+        if (e0 < E) ra[size_t(t)] = erow[size_t(e0)] | (efirst[size_t(e0)] ? kStartFlag : 0);
+        for (int64_t k = 0; k < K && e0 + k < E; ++k) {
+          V[size_t(off + k * Tp + t)] = ent[size_t(e0 + k)].second;
+          X[size_t(off + k * Tp + t)] = ent[size_t(e0 + k)].first;
+        }
+      }
+      H.s_off[size_t(kind)].push_back(off);
+      H.s_K[size_t(kind)].push_back(int32_t(K));
+      H.s_T[size_t(kind)].push_back(Tp);
+      H.s_ra[size_t(kind)].insert(H.s_ra[size_t(kind)].end(), ra.begin(), ra.end());
+    };
+    for (size_t ph = 0; ph < H.ph_a.size(); ++ph) {
+      const int32_t a = H.ph_a[ph], b = H.ph_b[ph], nns = H.ph_nns[ph];
+      build(int32_t(ph), a, b, 0);
+      build(int32_t(ph), a, a + nns, 1);
+      build(int32_t(ph), a, b, 2);
+      build(int32_t(ph), a, a + nns, 3);
+    }
+  }
+
+  // ---------------------------------------------------------------- launch schedule
   for (int32_t t = ntask - 1; t >= 0; --t) {
     const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];
     for (int32_t j = r0; j < r1; ++j)
@@ -499,6 +652,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   };
   group_by(fdepth, H.fwd_order, H.fwd_gptr);
   group_by(bdepth, H.bwd_order, H.bwd_gptr);
+  (void)task_nph;
   return STROM_OK;
 }
 

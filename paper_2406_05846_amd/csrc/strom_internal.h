@@ -8,11 +8,13 @@
 
 namespace strom {
 
-// Phase types of the triangular solves.
-enum : int32_t { kPhaseLevels = 0, kPhaseDense = 1 };
-constexpr int32_t kSolveThreads = 512;     // workgroup size of the solve kernels
-constexpr int32_t kMaxDenseRows = 256;     // rows of one dense phase
-constexpr int32_t kMaxLdsTaskRows = 14336; // task values kept in LDS up to this many rows
+constexpr int32_t kSolveThreads = 512;        // workgroup size of the solve kernels
+constexpr int32_t kMaxBlockRows = 64;         // rows of one component (dense diagonal block) of a phase
+constexpr int32_t kMaxPhaseBlockRows = 4096;  // rows in components of two or more, per phase
+constexpr int32_t kMaxLdsTaskRows = 14336;    // task values kept in LDS up to this many rows
+constexpr int32_t kLastFlag = int32_t(1) << 30;  // stream index flag: last entry of a row
+constexpr int32_t kPartFlag = int32_t(1) << 29;  // forward gather index flag: a pushed partial sum
+constexpr int32_t kStartFlag = int32_t(1) << 30; // first-row flag of a stream slice: the row starts there
 
 // Host result of the one-time analysis of an SDP instance.
 struct HostAnalysis {
@@ -36,23 +38,22 @@ struct HostAnalysis {
   std::vector<int32_t> Uci;
   std::vector<double> Uv;
   std::vector<double> D;
-  // Solve tasks: contiguous row ranges of the new order (rows sorted by dependency level
-  // inside a task).  A task is a sequence of phases over consecutive row ranges:
-  //   level phase: consecutive levels [ph_l0, ph_l0 + ph_nl) of levptr, each level a row
-  //                range whose rows are independent; lvl_gf / lvl_gb lanes per row;
-  //   dense phase: rows [ph_a, ph_b) solved through the explicit inverse of their unit
-  //                lower-triangular diagonal block, packed lower triangle at ph_inv (by rows
-  //                in invR: row r at r(r+1)/2; by columns in invC: column c at
-  //                c*nd - c(c-1)/2); ph_g lanes per row for the gathers.
+  // Solve tasks: contiguous row ranges of the new order.  A task is a sequence of phases
+  // over consecutive row ranges [ph_a, ph_b); the rows of a phase form connected components
+  // (contiguous, the first ph_nns rows in components of two or more rows, single rows last).
+  // Row i belongs to component [rcs[i], rce[i]) whose inverse diagonal block starts at
+  // rio[i] (-1 for a single row), packed lower triangle by rows in invR (row r at r(r+1)/2)
+  // and by columns in invC (column c at c*n - c(c-1)/2).  ph_gf / ph_gb: lanes per row of
+  // the forward / backward gathers.
   std::vector<int32_t> task_r0, task_r1, task_ph0, task_ph1;
-  std::vector<int32_t> ph_type, ph_a, ph_b, ph_l0, ph_nl, ph_gf, ph_gb;
-  std::vector<int64_t> ph_inv;
-  std::vector<int32_t> levptr, lvl_gf, lvl_gb;
+  std::vector<int32_t> ph_a, ph_b, ph_nns, ph_gf, ph_gb;
+  std::vector<int32_t> rcs, rce;
+  std::vector<int64_t> rio;
   std::vector<double> invR, invC;
   // Forward entries of row i: [Lrp[i], Lin[i]) lie in columns of other (earlier) tasks and
-  // arrive as pushed partial sums; [Lin[i], Lend[i]) are the task's own columns gathered by
-  // the row (Lend[i] < Lrp[i+1] for a dense-phase row: the diagonal block is in the inverse).
-  // Backward entries of row j: [Ubeg[j], Urp[j+1]) (the prefix inside a dense block skipped).
+  // arrive as pushed partial sums; [Lin[i], Lend[i]) are the task's own columns of earlier
+  // phases, gathered by the row ([Lend[i], Lrp[i+1]) lie in the row's own component).
+  // Backward entries of row j: [Ubeg[j], Urp[j+1]) (the prefix inside the component skipped).
   std::vector<int64_t> Lin, Lend, Ubeg;
   // Push segments: segment s is the run [seg_pb[s], seg_pe[s]) of one row's forward entries
   // whose columns belong to one other task; the owner task computes its partial sum right
@@ -60,10 +61,19 @@ struct HostAnalysis {
   // segments tseg[tsptr[t] .. tsptr[t+1]) and pushes them task_sg[t] lanes per segment.
   std::vector<int64_t> sptr, seg_pb, seg_pe;
   std::vector<int32_t> tsptr, tseg, task_sg;
+  // Phase streams (kinds 0 fg, 1 fi, 2 bg, 3 bi; see setup.cpp): values and indices, and per
+  // phase the offset, the entries per thread K, the thread count Tp and, for kSolveThreads + 1
+  // threads, the first row of each slice.
+  std::vector<double> sval[4];
+  std::vector<int32_t> sidx[4];
+  std::vector<int64_t> s_off[4];
+  std::vector<int32_t> s_K[4];
+  std::vector<int32_t> s_T[4];   // thread stride of the phase's layout
+  std::vector<int32_t> s_ra[4];
   // Launch schedule: task ids grouped by dependency depth.
   std::vector<int32_t> fwd_order, fwd_gptr, bwd_order, bwd_gptr;
   int32_t max_task_rows = 0;
-  int32_t max_dense_rows = 0;
+  int32_t max_phase_nns = 0;
   int64_t nnzL = 0;
 };
 
