@@ -36,6 +36,20 @@ def _proj_flops(block_sizes) -> float:
     return float(sum(11.0 * int(n) ** 3 for n in block_sizes))
 
 
+def _traffic(path: str, source: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter record, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, path)) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, source), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    return rec["hbm_bytes_per_dispatch"] if rec.get("source_sha256") == sha else None
+
+
 def _cpu_baseline(fam: int, N: int, prm, iters: int) -> dict:
     import oracle
     oracle.build(force=False)
@@ -55,8 +69,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--solves", type=int, default=8, help="pendulum solves timed for solves/s and latency")
+    ap.add_argument("--serve", type=int, default=48, help="requests of the serving sample (0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy five times (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (asked for {args.gpus}): instances are independent and "
@@ -71,6 +88,14 @@ def main():
     import workloads as W
 
     torch.zeros(1, device="cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 2 * src.numel() * 8, "launches": 5}))
+        return
     fam, N = W.CARTPOLE, 30
     prm = W.instance_params(fam, args.seed)
     t = time.perf_counter()
@@ -82,38 +107,94 @@ def main():
     t_setup = time.perf_counter() - t
     _log(f"cart-pole N={N}: n_svec {prob.nsvec}, m {prob.m}, generate {t_gen:.3f} s, setup {t_setup:.3f} s")
 
-    inst.enqueue(args.warmup)
-    torch.cuda.synchronize()
-    _log(f"warmup {args.warmup} iterations done")
-    t0 = time.perf_counter()
-    inst.enqueue(args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    _log(f"timed {args.steps} iterations in {elapsed:.3f} s")
-    info_after = inst.kkt()
+    def timed_iterations(ins):
+        ins.enqueue(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ins.enqueue(args.steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
+    elapsed = timed_iterations(inst)
+    _log(f"timed {args.steps} FP64 iterations in {elapsed:.3f} s")
+    info_after = inst.kkt()
     # per-phase times from HIP events on the instance's stream (continues the same iterate)
     prof = inst.profile(50)
     _log(f"phase profile (ms): {prof}")
     inst.close()
 
-    # full solves of the pendulum workload at eta <= 1e-6
-    lat, solve_only, iters_needed, states = [], [], [], []
-    for k in range(args.solves):
-        p = W.instance_params(W.PENDULUM, args.seed + k)
-        t = time.perf_counter()
-        pr = S.generate(W.PENDULUM, 10, p)
-        ins = S.Instance(ctx, pr)
-        t1 = time.perf_counter()
-        inf = ins.step(50000)
-        t2 = time.perf_counter()
-        lat.append(t2 - t)
-        solve_only.append(t2 - t1)
-        iters_needed.append(int(inf["iters"]))
-        states.append(int(inf["state"]))
-        _log(f"pendulum solve {k}: {lat[-1]:.3f} s, {inf['iters']} iterations, state {inf['state']}")
-        ins.close()
-    lat = np.array(lat)
+    # the reduced-precision form on the same instance (eta stays above the polish switch here)
+    inst32 = S.Instance(ctx, prob, S.default_opts(proj_dtype=S.F32))
+    elapsed32 = timed_iterations(inst32)
+    prof32 = inst32.profile(20)
+    inst32.close()
+    _log(f"timed {args.steps} FP32-projection iterations in {elapsed32:.3f} s; phases {prof32}")
+
+    def solve_set(opts, label):
+        lat, solve_only, iters, states = [], [], [], []
+        for k in range(args.solves):
+            p = W.instance_params(W.PENDULUM, args.seed + k)
+            t = time.perf_counter()
+            pr = S.generate(W.PENDULUM, 10, p)
+            ins = S.Instance(ctx, pr, opts)
+            t1 = time.perf_counter()
+            inf = ins.step(50000)
+            t2 = time.perf_counter()
+            lat.append(t2 - t)
+            solve_only.append(t2 - t1)
+            iters.append(int(inf["iters"]))
+            states.append(int(inf["state"]))
+            _log(f"pendulum {label} solve {k}: {lat[-1]:.3f} s, {inf['iters']} iterations, state {inf['state']}")
+            ins.close()
+        if not lat:
+            return None
+        lat = np.array(lat)
+        return {"solves_per_s": round(float(len(lat) / lat.sum()), 4),
+                "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4),
+                              "p99": round(float(np.percentile(lat, 99)), 4)},
+                "solve_only_s_mean": round(float(np.mean(solve_only)), 4),
+                "iters": iters, "converged": sum(st == S.CONVERGED for st in states)}
+
+    solves64 = solve_set(None, "fp64")
+    solves32 = solve_set(S.default_opts(proj_dtype=S.F32), "fp32+polish")
+
+    serving = None
+    if args.serve > 0:
+        # Poisson arrivals (seeded), pendulum requests with N ~ U{6..12}, admitted by the
+        # context's request loop; latency = arrival to retire
+        rng = W.SplitMix64(1000 + args.seed)
+        rate = 400.0
+        reqs, t_arr = [], 0.0
+        for k in range(args.serve):
+            t_arr += rng.exponential(rate)
+            Nk = rng.randint(6, 12)
+            reqs.append((t_arr, S.generate(W.PENDULUM, Nk, W.instance_params(W.PENDULUM, 500 + k))))
+        _log(f"serving: {len(reqs)} requests over {t_arr:.3f} s of arrivals")
+        start = time.perf_counter()
+        pending, lat, states, k = {}, [], [], 0
+        while k < len(reqs) or pending:
+            now = time.perf_counter() - start
+            while k < len(reqs) and reqs[k][0] <= now:
+                pending[ctx.submit(reqs[k][1])] = reqs[k][0]
+                k += 1
+            for tk in list(pending):
+                r = ctx.poll(tk)
+                if r is not None:
+                    lat.append(time.perf_counter() - start - pending.pop(tk))
+                    states.append(r[0]["state"])
+            if time.perf_counter() - start > 120:
+                _log("serving sample cut at 120 s")
+                break
+            time.sleep(0.0005)
+        wall = time.perf_counter() - start
+        lat = np.array(lat)
+        serving = {"workload": f"{len(reqs)} pendulum requests, N ~ U{{6..12}}, Poisson arrivals at "
+                               f"{rate:.0f}/s, FP64, retire at eta <= 1e-6 (or maxiter)",
+                   "solves_per_s": round(float(sum(st == S.CONVERGED for st in states) / wall), 3),
+                   "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4),
+                                 "p99": round(float(np.percentile(lat, 99)), 4)} if len(lat) else None,
+                   "completed": int(len(lat)), "converged": int(sum(st == S.CONVERGED for st in states))}
+        _log(f"serving: {serving}")
 
     flops = _proj_flops(prob.block_sizes)
     proj_s = prof["project_ms"] * 1e-3
@@ -136,17 +217,21 @@ def main():
                    "n_svec": prob.nsvec, "m": prob.m, "nnz_A": int(prob.nnz)},
         "kkt_after_timed": {"iters": int(info_after["iters"]), "eta_p": info_after["eta_p"],
                             "eta_d": info_after["eta_d"], "eta_g": info_after["eta_g"]},
-        "solves": {"workload": "pendulum N=10 (10 moment blocks 36x36 + 20 localizing 8x8), FP64, "
+        "fp32_polish": {"value": round(args.steps / elapsed32, 2), "unit": "iters/s",
+                        "ms_per_step": round(1e3 * elapsed32 / args.steps, 4),
+                        "project_ms": round(prof32["project_ms"], 4),
+                        "note": "same instance and timing, FP32 projection (FP64 eigenvectors, solves, "
+                                "iterates and residuals); eta stays above the 1e-5 polish switch here"},
+        "solves": {"workload": "pendulum N=10 (10 moment blocks 36x36 + 20 localizing 8x8), "
                                "generator + setup + solve to eta <= 1e-6, sequential",
-                   "solves_per_s": round(float(1.0 / lat.mean()), 4),
-                   "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4),
-                                 "p99": round(float(np.percentile(lat, 99)), 4)},
-                   "solve_only_s_mean": round(float(np.mean(solve_only)), 4),
-                   "iters": iters_needed, "converged": sum(s == S.CONVERGED for s in states)},
+                   "fp64": solves64, "fp32_polish": solves32},
+        "serving": serving,
         "phase_ms": {k: round(v, 4) for k, v in prof.items()},
         "roofline": {"bound": "alu", "kernel": "k_project_admm<double> (every PSD block of one iteration)",
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 6), "traffic": None},
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 6),
+                     "traffic": _traffic("profiles/k_project_admm_cartpole_n30_traffic.json",
+                                         "paper_2406_05846_amd/csrc/project.hip")},
     }
     if not args.no_cpu:
         _log("CPU oracle baseline ...")

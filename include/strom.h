@@ -62,9 +62,14 @@ typedef struct strom_sdp strom_sdp; /* one per SDP instance: device data, factor
  * this library's choices.  strom_default_opts fills:
  *   sigma0 = 1, tau = 1.6, eps_reg = 1e-12 (eps = eps_reg * max_i (A A^*)_ii), tol = 1e-6,
  *   maxiter = 100000, kkt_every = 10, proj_dtype = STROM_F64, polish_eta = 1e-5,
- *   sigma_every = 50 (every sigma_every iterations, with rho = max(eta_p, eta_g) / eta_d,
- *   sigma is divided by 1.5 when rho > 10 and multiplied by 1.5 when rho < 3, clamped to
- *   [1e-4, 1e4]; 0 keeps sigma fixed).  sigma_every must be a multiple of kkt_every (or 0). */
+ *   sigma_every = 50.  Sigma rule: every sigma_every iterations, with the primal
+ *   infeasibility r_P = max(eta_p, eta_K), eta_K = ||X - Pi(X)|| / (1 + ||X||) the distance of
+ *   X from the cone, sigma is multiplied by 1.5 when eta_d > 3 r_P and divided by 1.5 when
+ *   r_P > 3 eta_d, kept in [1e-4, 1e4]; 0 keeps sigma fixed.  sigma_every must be a multiple
+ *   of kkt_every (or 0).  With proj_dtype = STROM_F32 the projection runs in FP32 (FP64
+ *   eigenvectors) until eta <= polish_eta or eta has not halved over 500 iterations, then in
+ *   FP64 (the switch is taken where the residuals are read: strom_admm_step and the serving
+ *   loop); y-solves, iterates and residuals are FP64 throughout. */
 typedef struct {
   double sigma0;
   double tau;
@@ -156,8 +161,8 @@ strom_status strom_sdp_sizes(strom_sdp *sdp, int64_t *n_svec, int32_t *m, int64_
  * reconstruction).  Block k is n_dev[k] x n_dev[k], column-major, starting at element
  * offset_dev[k] of in_dev / out_dev; in and out may alias.  n_dev, offset_dev, in_dev and
  * out_dev are device pointers; max_n (host) bounds every n_dev[k]; one block and its
- * eigenvectors must fit the LDS of one workgroup (160 KiB on gfx950: max_n <= 112 for F64,
- * <= 124 for F32 -- the eigenvectors are accumulated in double in both), else E_INVAL.  A block with n_dev[k] <= 0 or > max_n makes the call
+ * eigenvectors must fit the LDS of one workgroup (160 KiB on gfx950: max_n <= 111 for F64,
+ * <= 122 for F32 -- the eigenvectors are accumulated in double in both), else E_INVAL.  A block with n_dev[k] <= 0 or > max_n makes the call
  * return E_INVAL (other blocks are still written).  dtype selects double or float data.
  * Only the upper triangle of each input block is read; the output is exactly symmetric. */
 strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblocks, int32_t max_n,

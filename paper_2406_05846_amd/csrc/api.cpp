@@ -79,6 +79,10 @@ struct strom_sdp {
   double *Q = nullptr;         // eigenvectors of every block from the last ADMM projection
   int64_t *qoff = nullptr;     // offset of block k in Q
   bool q_valid = false;        // Q holds eigenvectors of the current iterate's blocks
+  // reduced-precision projection: active until the polish switch (FP64 from then on)
+  bool f32_active = false;
+  double f32_ref_eta = 0.0;    // eta at the last progress check of the FP32 phase
+  int64_t f32_ref_iter = 0;
   strom::dev::SolveArgs sa{};
   strom::dev::SolveSchedule sch;
   std::vector<int> cls_n, cls_off, cls_cnt;  // projection launches, one per block size
@@ -172,6 +176,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   s->ctx = ctx;
   s->stream = ctx->stream;
   s->opts = o;
+  s->f32_active = o.proj_dtype == STROM_F32;
   s->m = P->m;
   s->nblocks = P->nblocks;
   s->nsvec = H.nsvec;
@@ -183,15 +188,19 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   const int ntask = int(H.task_r0.size());
   const int nrb = (m + 255) / 256, ncb = int((n + 255) / 256);
 
-  // projection launches: blocks grouped by size
+  // projection launches: one launch over every block (largest first) when they fit the chip
+  // in one wave of workgroups, else one launch per block size
   std::map<int, std::vector<int32_t>> by_n;
   for (int32_t k = 0; k < P->nblocks; ++k) by_n[H.bsize[size_t(k)]].push_back(k);
   std::vector<int32_t> ids;
-  for (auto &kv : by_n) {
-    s->cls_n.push_back(kv.first);
-    s->cls_off.push_back(int(ids.size()));
-    s->cls_cnt.push_back(int(kv.second.size()));
-    ids.insert(ids.end(), kv.second.begin(), kv.second.end());
+  for (auto it = by_n.rbegin(); it != by_n.rend(); ++it) {
+    if (P->nblocks > 256 || s->cls_n.empty()) {
+      s->cls_n.push_back(it->first);
+      s->cls_off.push_back(int(ids.size()));
+      s->cls_cnt.push_back(0);
+    }
+    s->cls_cnt.back() += int(it->second.size());
+    ids.insert(ids.end(), it->second.begin(), it->second.end());
   }
 
   Arena ar;
@@ -406,17 +415,18 @@ extern "C" strom_status strom_sdp_destroy(strom_sdp *s) {
 
 namespace {
 
-// S_out = (Pi(X_in) - X_in) * scale for every block (scale <= 0: 1 / sigma).  The ADMM step
-// (admm = true) warm-starts from, and refreshes, the eigenvectors kept per block.
-hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, double scale, bool admm) {
-  const bool f32 = s->opts.proj_dtype == STROM_F32;
+// S_out = (Pi(X_in) - X_in) * scale for every block (scale <= 0: 1 / sigma).  Every call
+// warm-starts from, and refreshes, the eigenvectors kept per block (the cone distance of X
+// uses them too: X and X_b differ little, and any orthogonal start gives the same result).
+hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, double scale) {
+  const bool f32 = s->f32_active;
   for (size_t c = 0; c < s->cls_n.size(); ++c) {
     hipError_t e = strom::dev::launch_project_admm(s->stream, f32, s->cls_n[c], s->cls_cnt[c],
                                                    s->blk_ids + s->cls_off[c], s->boff, s->bsz, X_in, S_out, s->st,
-                                                   scale, admm ? s->Q : nullptr, s->qoff, admm && s->q_valid);
+                                                   scale, s->Q, s->qoff, s->q_valid);
     if (e != hipSuccess) return e;
   }
-  if (admm) s->q_valid = true;
+  s->q_valid = true;
   return hipSuccess;
 }
 
@@ -424,7 +434,7 @@ hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, d
 // do_sigma, the cone distance of X (through the scratch X_b buffer) and the sigma rule.
 hipError_t enqueue_kkt(strom_sdp *s, bool do_sigma) {
   if (do_sigma) {
-    hipError_t e = enqueue_projection(s, s->X, s->Xb, 1.0, false);
+    hipError_t e = enqueue_projection(s, s->X, s->Xb, 1.0);
     if (e != hipSuccess) return e;
   }
   return strom::dev::launch_kkt(s->stream, s->m, s->nsvec, s->A_rp, s->A_ci, s->A_v, s->X, s->b, s->y, s->part_rows,
@@ -441,7 +451,7 @@ hipError_t enqueue_iteration(strom_sdp *s, bool kkt, bool do_sigma) {
   if ((e = strom::dev::launch_solve(q, s->sch, s->sa, s->w, s->y))) return e;
   // step 2
   if ((e = strom::dev::launch_xb(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->X, s->C, s->st, s->Xb))) return e;
-  if ((e = enqueue_projection(s, s->Xb, s->S, 0.0, true))) return e;
+  if ((e = enqueue_projection(s, s->Xb, s->S, 0.0))) return e;
   // step 3
   if ((e = strom::dev::launch_rhs(q, s->m, s->A_rp, s->A_ci, s->A_v, s->X, s->S, s->C, s->b, s->pinv, s->st, s->w)))
     return e;
@@ -495,10 +505,24 @@ hipError_t sdp_enqueue(strom_sdp *s, int n_iter, bool kkt_last) {
   }
   return hipSuccess;
 }
+// Reads the device scalars; applies the polish switch of the reduced-precision form: the
+// FP32 projection is replaced by the FP64 one once eta <= polish_eta, or once eta has not
+// halved over 500 iterations.
 hipError_t sdp_read_state(strom_sdp *s) {
   hipError_t e = hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream);
   if (e != hipSuccess) return e;
-  return hipStreamSynchronize(s->stream);
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess || !s->f32_active) return e;
+  const DevState &d = *s->st_host;
+  const double eta = std::max(d.eta_p, std::max(d.eta_d, d.eta_g));
+  if (eta <= s->opts.polish_eta) {
+    s->f32_active = false;
+  } else if (s->iters - s->f32_ref_iter >= 500) {
+    if (s->f32_ref_iter > 0 && !(eta <= 0.5 * s->f32_ref_eta)) s->f32_active = false;
+    s->f32_ref_eta = eta;
+    s->f32_ref_iter = s->iters;
+  }
+  return hipSuccess;
 }
 strom_solve_state sdp_classify(strom_sdp *s) { return s->state = classify(s); }
 void sdp_info(strom_sdp *s, strom_info *info) { fill_info(s, info); }
@@ -557,7 +581,7 @@ extern "C" strom_status strom_profile_iteration(strom_sdp *s, int32_t reps, stro
     rec(2);
     if (!e) e = strom::dev::launch_xb(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->X, s->C, s->st, s->Xb);
     rec(3);
-    if (!e) e = enqueue_projection(s, s->Xb, s->S, 0.0, true);
+    if (!e) e = enqueue_projection(s, s->Xb, s->S, 0.0);
     rec(4);
     if (!e) e = strom::dev::launch_rhs(q, s->m, s->A_rp, s->A_ci, s->A_v, s->X, s->S, s->C, s->b, s->pinv, s->st, s->w);
     rec(5);
@@ -628,6 +652,9 @@ extern "C" strom_status strom_set_iterate(strom_sdp *s, const double *X, const d
   if (S) HIP_TRY(hipMemcpy(s->S, S, sizeof(double) * size_t(s->nsvec), hipMemcpyHostToDevice));
   s->iters = 0;
   s->q_valid = false;
+  s->f32_active = s->opts.proj_dtype == STROM_F32;
+  s->f32_ref_eta = 0.0;
+  s->f32_ref_iter = 0;
   s->state = STROM_RUNNING;
   return STROM_OK;
 }

@@ -62,11 +62,28 @@ struct JacobiTol<float> {
 
 // LDS: V (n*n doubles, column-major) | red (nthreads doubles) | rotd (2 doubles per pair: c, s)
 //      | A (packed upper triangle, T) | rot (4 T per pair: c, s, new a_pp, new a_qq)
-//      | sel (n + 4 ints).
+//      | sel (n + 4 ints), every region 32-byte aligned.
+struct Layout {
+  size_t red, rotd, A, rot, sel, total;
+};
+
+__host__ __device__ inline size_t align32(size_t x) { return (x + 31) & ~(size_t)31; }
+
+__host__ __device__ inline Layout lds_layout(int n, int nthreads, size_t tsize) {
+  const size_t np2 = (size_t)(n + 1) / 2, npk = (size_t)n * (n + 1) / 2;
+  Layout L;
+  L.red = align32(8 * (size_t)n * n);
+  L.rotd = align32(L.red + 8 * (size_t)nthreads);
+  L.A = align32(L.rotd + 16 * np2);
+  L.rot = align32(L.A + tsize * npk);
+  L.sel = align32(L.rot + 4 * tsize * np2);
+  L.total = align32(L.sel + 4 * ((size_t)n + 4));
+  return L;
+}
+
 template <typename T>
 inline size_t lds_bytes_t(int n, int nthreads) {
-  const size_t np2 = (size_t)(n + 1) / 2, npk = (size_t)n * (n + 1) / 2;
-  return 8 * ((size_t)n * n + nthreads + 2 * np2) + sizeof(T) * (npk + 4 * np2) + sizeof(int) * (size_t)(n + 4) + 16;
+  return lds_layout(n, nthreads, sizeof(T)).total;
 }
 
 struct Smem {
@@ -77,15 +94,14 @@ struct Smem {
 
 template <typename T>
 __device__ inline Smem carve(unsigned char *base, int n) {
+  const Layout L = lds_layout(n, blockDim.x, sizeof(T));
   Smem s;
-  const int np2 = (n + 1) / 2, npk = n * (n + 1) / 2;
   s.V = reinterpret_cast<double *>(base);
-  s.red = s.V + n * n;
-  s.rotd = s.red + blockDim.x;
-  T *A = reinterpret_cast<T *>(s.rotd + 2 * np2);
-  s.A = A;
-  s.rot = A + npk;
-  s.sel = reinterpret_cast<int *>(reinterpret_cast<T *>(s.rot) + 4 * np2);
+  s.red = reinterpret_cast<double *>(base + L.red);
+  s.rotd = reinterpret_cast<double *>(base + L.rotd);
+  s.A = base + L.A;
+  s.rot = base + L.rot;
+  s.sel = reinterpret_cast<int *>(base + L.sel);
   return s;
 }
 
@@ -150,11 +166,57 @@ __device__ void rotate_into_basis(int n, const double *xs, const double *V, doub
 }
 
 template <typename T>
+struct Vec4;
+template <>
+struct Vec4<double> {
+  typedef double4 type;
+};
+template <>
+struct Vec4<float> {
+  typedef float4 type;
+};
+
+// New value of the 2x2 block (pair I) x (pair J), I <= J, of round r.
+template <typename T>
+__device__ inline void rotate_block(int r, int I, int J, int n, int mm, T *A, const T *rot) {
+  typedef typename Vec4<T>::type V4;
+  int p1, q1;
+  rr_pair(r, I, mm, p1, q1);
+  const V4 ri = reinterpret_cast<const V4 *>(rot)[I];
+  if (I == J) {
+    if (q1 < n) {
+      A[pidx(p1, p1)] = ri.z;
+      A[pidx(q1, q1)] = ri.w;
+      A[pidx(p1, q1)] = T(0);
+    }
+    return;
+  }
+  int p2, q2;
+  rr_pair(r, J, mm, p2, q2);
+  const V4 rj = reinterpret_cast<const V4 *>(rot)[J];
+  const T c1 = ri.x, s1 = ri.y, c2 = rj.x, s2 = rj.y;
+  const bool hq1 = q1 < n, hq2 = q2 < n;
+  const T a = A[pidx(p1, p2)];
+  const T bq = hq2 ? A[pidx(p1, q2)] : T(0);
+  const T cq = hq1 ? A[pidx(q1, p2)] : T(0);
+  const T d = (hq1 && hq2) ? A[pidx(q1, q2)] : T(0);
+  const T ra = c1 * a - s1 * cq, rb = c1 * bq - s1 * d;  // rows p1, q1 rotated
+  const T rc = s1 * a + c1 * cq, rd = s1 * bq + c1 * d;
+  A[pidx(p1, p2)] = c2 * ra - s2 * rb;  // then columns p2, q2
+  if (hq2) A[pidx(p1, q2)] = s2 * ra + c2 * rb;
+  if (hq1) A[pidx(q1, p2)] = c2 * rc - s2 * rd;
+  if (hq1 && hq2) A[pidx(q1, q2)] = s2 * rc + c2 * rd;
+}
+
+template <typename T>
 __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double *red, bool v_ready) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int np2 = (n + 1) / 2, nn = 2 * np2, mm = nn - 1;
   const int npk = n * (n + 1) / 2;
-  const int nblk = np2 * (np2 + 1) / 2;
+  const int nblk = np2 * (np2 + 1) / 2;  // at most 2 * nth (checked at launch)
+  int I0 = -1, J0 = -1, I1 = -1, J1 = -1;  // this thread's 2x2 blocks, fixed over the rounds
+  if (tid < nblk) tri_ij(tid, I0, J0);
+  if (tid + nth < nblk) tri_ij(tid + nth, I1, J1);
   // eigenvector rows: thread -> (row, first pair, pair stride), fixed over the rounds
   const int vks = nth / n, vrow = tid % n, vk0 = vks > 0 && tid < vks * n ? tid / n : np2;
   if (!v_ready)
@@ -196,47 +258,24 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double 
             dq = aqq + t * apq;
           }
         }
-        rot[4 * k] = (T)c;
-        rot[4 * k + 1] = (T)s;
-        rot[4 * k + 2] = (T)dp;
-        rot[4 * k + 3] = (T)dq;
-        rotd[2 * k] = c;
-        rotd[2 * k + 1] = s;
+        typedef typename Vec4<T>::type V4;
+        V4 rv;
+        rv.x = (T)c;
+        rv.y = (T)s;
+        rv.z = (T)dp;
+        rv.w = (T)dq;
+        reinterpret_cast<V4 *>(rot)[k] = rv;
+        reinterpret_cast<double2 *>(rotd)[k] = make_double2(c, s);
       }
       __syncthreads();
-      for (int e = tid; e < nblk; e += nth) {
-        int I, J;
-        tri_ij(e, I, J);
-        int p1, q1;
-        rr_pair(r, I, mm, p1, q1);
-        if (I == J) {
-          if (q1 < n) {
-            A[pidx(p1, p1)] = rot[4 * I + 2];
-            A[pidx(q1, q1)] = rot[4 * I + 3];
-            A[pidx(p1, q1)] = T(0);
-          }
-          continue;
-        }
-        int p2, q2;
-        rr_pair(r, J, mm, p2, q2);
-        const T c1 = rot[4 * I], s1 = rot[4 * I + 1], c2 = rot[4 * J], s2 = rot[4 * J + 1];
-        const bool hq1 = q1 < n, hq2 = q2 < n;
-        const T a = A[pidx(p1, p2)];
-        const T bq = hq2 ? A[pidx(p1, q2)] : T(0);
-        const T cq = hq1 ? A[pidx(q1, p2)] : T(0);
-        const T d = (hq1 && hq2) ? A[pidx(q1, q2)] : T(0);
-        const T ra = c1 * a - s1 * cq, rb = c1 * bq - s1 * d;  // rows p1, q1 rotated
-        const T rc = s1 * a + c1 * cq, rd = s1 * bq + c1 * d;
-        A[pidx(p1, p2)] = c2 * ra - s2 * rb;  // then columns p2, q2
-        if (hq2) A[pidx(p1, q2)] = s2 * ra + c2 * rb;
-        if (hq1) A[pidx(q1, p2)] = c2 * rc - s2 * rd;
-        if (hq1 && hq2) A[pidx(q1, q2)] = s2 * rc + c2 * rd;
-      }
+      if (I0 >= 0) rotate_block<T>(r, I0, J0, n, mm, A, rot);
+      if (I1 >= 0) rotate_block<T>(r, I1, J1, n, mm, A, rot);
       for (int k = vk0; k < np2; k += vks) {
         int p, q;
         rr_pair(r, k, mm, p, q);
         if (q >= n) continue;
-        const double c = rotd[2 * k], s = rotd[2 * k + 1];
+        const double2 cs = reinterpret_cast<const double2 *>(rotd)[k];
+        const double c = cs.x, s = cs.y;
         const double vp = V[vrow + p * n], vq = V[vrow + q * n];
         V[vrow + p * n] = c * vp - s * vq;
         V[vrow + q * n] = s * vp + c * vq;
@@ -299,7 +338,7 @@ __global__ void __launch_bounds__(1024) k_project_admm(const int32_t *__restrict
                                                        double *__restrict__ S, const DevState *__restrict__ st,
                                                        double scale, double *__restrict__ Q,
                                                        const int64_t *__restrict__ qoff, int32_t warm) {
-  extern __shared__ __align__(16) unsigned char smem[];
+  extern __shared__ __align__(32) unsigned char smem[];
   const int32_t bk = blk_ids[blockIdx.x];
   const int n = bsz[bk];
   const int64_t off = boff[bk];
@@ -343,7 +382,7 @@ template <typename T>
 __global__ void __launch_bounds__(1024) k_project_dense(int32_t nblocks, const int32_t *__restrict__ nd,
                                                         const int64_t *__restrict__ od, const T *__restrict__ in,
                                                         T *__restrict__ out, int32_t max_n, int32_t *__restrict__ err) {
-  extern __shared__ __align__(16) unsigned char smem[];
+  extern __shared__ __align__(32) unsigned char smem[];
   const int32_t bk = blockIdx.x;
   const int n = nd[bk];
   const int64_t off = od[bk];
@@ -392,12 +431,17 @@ int project_threads(int n) {
   return nt;
 }
 
+static bool threads_ok(int n, int nt) {
+  const int np2 = (n + 1) / 2;
+  return nt >= n && np2 * (np2 + 1) / 2 <= 2 * nt;
+}
+
 hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const int32_t *ids, const int64_t *boff,
                                const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale,
                                double *Q, const int64_t *qoff, bool warm) {
   if (count <= 0) return hipSuccess;
   const int nt = project_threads(n);
-  if (nt < n) return hipErrorInvalidValue;
+  if (!threads_ok(n, nt)) return hipErrorInvalidValue;
   const size_t lds = project_lds_bytes(n, f32, nt);
   if (f32) {
     (void)hipFuncSetAttribute((const void *)k_project_admm<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -414,7 +458,7 @@ hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const 
 hipError_t launch_project_dense(hipStream_t s, bool f32, int nblocks, int max_n, const int32_t *nd, const int64_t *od,
                                 const void *in, void *out, int32_t *err) {
   const int nt = project_threads(max_n);
-  if (nt < max_n) return hipErrorInvalidValue;
+  if (!threads_ok(max_n, nt)) return hipErrorInvalidValue;
   const size_t lds = project_lds_bytes(max_n, f32, nt);
   if (f32) {
     (void)hipFuncSetAttribute((const void *)k_project_dense<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

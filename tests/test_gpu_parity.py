@@ -227,3 +227,61 @@ def test_hbm_budget(S):
         S.Instance(small, prob)
     assert e.value.code == -2
     small.close()
+
+
+# ----------------------------------------------------------------- reduced-precision form
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_pendulum_f32_polish_converges(S, ctx, orc, seed):
+    """FP32 projection with the FP64 polish switch reaches the same optimum as the oracle:
+    eta <= 1e-6 by the oracle's own KKT evaluation and the objective gap of the FP64 form."""
+    import workloads as W
+    prm = W.instance_params(W.PENDULUM, seed)
+    ref = _converged_ref(seed)
+    prob = S.generate(W.PENDULUM, 10, prm)
+    inst = S.Instance(ctx, prob, S.default_opts(proj_dtype=S.F32))
+    info = inst.step(50000)
+    assert info["state"] == S.CONVERGED, info
+    X, y, Sv = inst.get_iterate()
+    k = orc.kkt(orc.relax(W.PENDULUM, 10, prm), X, y, Sv)
+    assert max(k["eta_p"], k["eta_d"], k["eta_g"]) <= 1e-6 * 1.05, k
+    gap = abs(info["pobj"] - ref["pobj"]) / (1 + abs(info["pobj"]) + abs(ref["pobj"]))
+    assert gap <= 1e-6, (info["pobj"], ref["pobj"])
+    inst.close()
+
+
+# ----------------------------------------------------------------- serving
+
+def test_serving_same_result_alone_and_in_the_mix(S, ctx):
+    """Requests solved through strom_submit / strom_poll while others share the device give the
+    same iterates and iteration counts as the same instances solved alone."""
+    import time
+    import workloads as W
+    cases = [(W.PENDULUM, 10, W.instance_params(W.PENDULUM, s)) for s in range(5)]
+    cases += [(W.TOY1D, 4, [1.5, 0.1, 1.0]), (W.PENDULUM, 6, W.instance_params(W.PENDULUM, 7))]
+    probs = [S.generate(f, N, p) for f, N, p in cases]
+    alone = []
+    for pr in probs:
+        inst = S.Instance(ctx, pr)
+        info = inst.step(50000)
+        alone.append((info, inst.get_iterate()))
+        inst.close()
+    tickets = [ctx.submit(pr) for pr in probs]
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        assert time.time() - t0 < 120, "serving loop did not finish"
+        for t, pr in zip(tickets, probs):
+            if t in done:
+                continue
+            r = ctx.poll(t, pr.nsvec, pr.m)
+            if r is not None:
+                done[t] = r
+        time.sleep(0.01)
+    for (ia, (Xa, ya, Sa)), t in zip(alone, tickets):
+        info, X, y, Sv = done[t]
+        assert info["state"] == ia["state"] == S.CONVERGED
+        assert info["iters"] == ia["iters"]
+        assert np.linalg.norm(X - Xa) <= 1e-9 * max(1.0, np.linalg.norm(Xa))
+        assert np.linalg.norm(Sv - Sa) <= 1e-9 * max(1.0, np.linalg.norm(Sa))
+        assert abs(info["pobj"] - ia["pobj"]) <= 1e-9 * (1 + abs(ia["pobj"]))
