@@ -111,9 +111,13 @@ typedef struct {
 void strom_default_opts(strom_opts *opts);
 const char *strom_last_error(void);
 
-/* Create a context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t, NULL
- * for the default stream).  hbm_budget_bytes bounds the device memory of all instances
- * set up in this ctx (0 = no bound). */
+/* Create a context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t; NULL:
+ * the context creates its own non-blocking stream, so that work of other threads on the
+ * legacy default stream never waits on it).  hbm_budget_bytes bounds the device memory of
+ * all instances set up in this ctx (0 = no bound).  Rounds of kkt_every iterations are
+ * replayed from HIP graphs captured on a private non-blocking stream; the library's own
+ * synchronous copies are serialized with those captures, and a caller must not enqueue work
+ * on the legacy default stream from another thread while strom calls are in flight. */
 strom_status strom_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, strom_ctx **out);
 strom_status strom_ctx_destroy(strom_ctx *ctx);
 

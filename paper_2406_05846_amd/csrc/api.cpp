@@ -32,6 +32,13 @@ strom_status fail(strom_status s, const std::string &msg) {
     if (e_ != hipSuccess) return fail(STROM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Serializes graph captures with the library's synchronous copies, allocations and frees:
+// while a stream is being captured, work that touches the legacy default stream fails.
+std::recursive_mutex &device_lock() {
+  static std::recursive_mutex mu;
+  return mu;
+}
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -54,6 +61,7 @@ struct strom_ctx {
   size_t budget = 0;
   size_t used = 0;
   int32_t *err_flag = nullptr;  // device flag of the dense projection
+  bool own_stream = false;      // stream created by the context
   int64_t live = 0;             // instances set up directly (not through the server)
   size_t max_lds = 0;
   std::mutex mu;
@@ -81,6 +89,11 @@ struct strom_sdp {
   bool q_valid = false;        // Q holds eigenvectors of the current iterate's blocks
   // reduced-precision projection: active until the polish switch (FP64 from then on)
   bool f32_active = false;
+  // HIP graphs of one round of kkt_every iterations (KKT on the last), indexed by
+  // [sigma rule on the last iteration][FP32 projection]; captured on first use
+  hipGraphExec_t round_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipStream_t capture_stream = nullptr;
+  bool graphs = true;
   double f32_ref_eta = 0.0;    // eta at the last progress check of the FP32 phase
   int64_t f32_ref_iter = 0;
   strom::dev::SolveArgs sa{};
@@ -118,12 +131,21 @@ extern "C" strom_status strom_ctx_create(int device, void *hip_stream, size_t hb
   HIP_TRY(hipSetDevice(device));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, device));
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
   auto *c = new strom_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   c->budget = hbm_budget_bytes;
   c->max_lds = prop.sharedMemPerBlock;
+  if (!c->stream) {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(STROM_E_HIP, "stream creation failed");
+    }
+    c->own_stream = true;
+  }
   if (hipMalloc(&c->err_flag, 256) != hipSuccess) {
+    if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
     return fail(STROM_E_NOMEM, "hipMalloc of the context flag failed");
   }
@@ -138,8 +160,10 @@ extern "C" strom_status strom_ctx_destroy(strom_ctx *c) {
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->live > 0) return fail(STROM_E_STATE, std::to_string(c->live) + " instance(s) still set up on this ctx");
   }
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
   hipSetDevice(c->device);
   hipFree(c->err_flag);
+  if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
   return STROM_OK;
 }
@@ -263,6 +287,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
     ctx->used += ar.bytes;
     ctx->live++;
   }
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
   auto undo = [&](strom_status st, const std::string &msg) {
     { std::lock_guard<std::mutex> lk(ctx->mu); ctx->used -= s->arena_bytes; ctx->live--; }
     if (s->arena) hipFree(s->arena);
@@ -326,8 +351,12 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
     phh[4 * nph + k] = H.ph_gb[k];
   }
   std::vector<double> zeros;
+  hipError_t up_err = hipSuccess;
   auto up = [&](const void *dst, const void *src, size_t bytes) -> bool {
-    return bytes == 0 || hipMemcpy(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    if (bytes == 0) return true;
+    const hipError_t e = hipMemcpy(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess && up_err == hipSuccess) up_err = e;
+    return e == hipSuccess;
   };
   bool ok = true;
   ok &= up(s->A_rp, P->A_rowptr, sizeof(int64_t) * (size_t(m) + 1));
@@ -387,7 +416,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   st0.tau = o.tau;
   st0.sigma_used = o.sigma0;
   ok &= up(s->st, &st0, sizeof(DevState));
-  if (!ok) return undo(STROM_E_HIP, "upload of the instance failed");
+  if (!ok) return undo(STROM_E_HIP, std::string("upload of the instance failed: ") + hipGetErrorString(up_err));
   double nb2 = 0, nc2 = 0;
   for (int32_t i = 0; i < m; ++i) nb2 += P->b[i] * P->b[i];
   for (int64_t c = 0; c < n; ++c) nc2 += P->C_svec[c] * P->C_svec[c];
@@ -400,8 +429,13 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
 
 extern "C" strom_status strom_sdp_destroy(strom_sdp *s) {
   if (!s) return fail(STROM_E_INVAL, "sdp is NULL");
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
   hipSetDevice(s->ctx->device);
   hipStreamSynchronize(s->stream);
+  for (auto &row : s->round_graph)
+    for (auto &g : row)
+      if (g) hipGraphExecDestroy(g);
+  if (s->capture_stream) hipStreamDestroy(s->capture_stream);
   hipFree(s->arena);
   hipHostFree(s->st_host);
   {
@@ -494,14 +528,58 @@ strom_solve_state classify(const strom_sdp *s) {
 namespace strom {
 // Used by the serving loop: enqueue n iterations without synchronizing; returns true when
 // residuals were computed on the last one.
+// Captures one round of kkt_every iterations (residuals on the last, the sigma rule too when
+// sigma_last) as a graph; the kernels read sigma, tau and every array from device memory, so
+// the graph replays any round of the instance.
+static hipError_t capture_round(strom_sdp *s, bool sigma_last, hipGraphExec_t *out) {
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
+  hipError_t e = hipSuccess;
+  if (!s->capture_stream && (e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking))) return e;
+  hipStream_t saved = s->stream;
+  s->stream = s->capture_stream;
+  e = hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal);
+  hipError_t e2 = hipSuccess;
+  const int kk = s->opts.kkt_every;
+  for (int k = 0; k < kk && e == hipSuccess && e2 == hipSuccess; ++k)
+    e2 = enqueue_iteration(s, k == kk - 1, sigma_last && k == kk - 1);
+  hipGraph_t g = nullptr;
+  if (e == hipSuccess) e = hipStreamEndCapture(s->capture_stream, &g);
+  s->stream = saved;
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  if (g) hipGraphDestroy(g);
+  return e;
+}
+
+// Enqueues n iterations.  An iteration computes the residuals when it closes a round of
+// kkt_every iterations, when it applies the sigma rule, or when it is the last one asked
+// for with kkt_last.  Full rounds that start on a round boundary, after the first
+// (cold-start) projection, replay a captured graph.
 hipError_t sdp_enqueue(strom_sdp *s, int n_iter, bool kkt_last) {
-  for (int k = 0; k < n_iter; ++k) {
+  const int kk = s->opts.kkt_every;
+  const int se = s->opts.sigma_every;
+  int k = 0;
+  while (k < n_iter) {
     const int64_t it = s->iters;
-    const bool sig = s->opts.sigma_every > 0 && (it + 1) % s->opts.sigma_every == 0;
-    const bool kkt = sig || (kkt_last && k == n_iter - 1);
+    if (s->graphs && s->q_valid && it % kk == 0 && n_iter - k >= kk) {
+      const int sl = (se > 0 && (it + kk) % se == 0) ? 1 : 0, fl = s->f32_active ? 1 : 0;
+      hipError_t e = hipSuccess;
+      if (!s->round_graph[sl][fl] && (e = capture_round(s, sl != 0, &s->round_graph[sl][fl]))) {
+        s->graphs = false;  // capture not available: launch directly from now on
+        (void)hipGetLastError();
+        continue;
+      }
+      if ((e = hipGraphLaunch(s->round_graph[sl][fl], s->stream))) return e;
+      s->iters += kk;
+      k += kk;
+      continue;
+    }
+    const bool sig = se > 0 && (it + 1) % se == 0;
+    const bool kkt = sig || (it + 1) % kk == 0 || (kkt_last && k == n_iter - 1);
     hipError_t e = enqueue_iteration(s, kkt, sig);
     if (e != hipSuccess) return e;
     s->iters++;
+    ++k;
   }
   return hipSuccess;
 }
@@ -635,6 +713,7 @@ extern "C" strom_status strom_kkt_residuals(strom_sdp *s, strom_info *info) {
 
 extern "C" strom_status strom_get_iterate(strom_sdp *s, double *X, double *y, double *S) {
   if (!s) return fail(STROM_E_INVAL, "sdp is NULL");
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
   HIP_TRY(hipSetDevice(s->ctx->device));
   HIP_TRY(hipStreamSynchronize(s->stream));
   if (X) HIP_TRY(hipMemcpy(X, s->X, sizeof(double) * size_t(s->nsvec), hipMemcpyDeviceToHost));
@@ -645,6 +724,7 @@ extern "C" strom_status strom_get_iterate(strom_sdp *s, double *X, double *y, do
 
 extern "C" strom_status strom_set_iterate(strom_sdp *s, const double *X, const double *y, const double *S) {
   if (!s) return fail(STROM_E_INVAL, "sdp is NULL");
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
   HIP_TRY(hipSetDevice(s->ctx->device));
   HIP_TRY(hipStreamSynchronize(s->stream));
   if (X) HIP_TRY(hipMemcpy(s->X, X, sizeof(double) * size_t(s->nsvec), hipMemcpyHostToDevice));
@@ -678,6 +758,7 @@ extern "C" strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblock
   if (dtype != STROM_F32 && dtype != STROM_F64) return fail(STROM_E_INVAL, "bad dtype");
   if (max_n <= 0 || proj_need(max_n, f32) > ctx->max_lds)
     return fail(STROM_E_INVAL, "max_n out of range for the LDS of one workgroup");
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t q = (hipStream_t)hip_stream;
   HIP_TRY(hipMemsetAsync(ctx->err_flag, 0, sizeof(int32_t), q));
