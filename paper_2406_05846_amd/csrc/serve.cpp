@@ -10,6 +10,8 @@
 #include "serve.h"
 
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -59,6 +61,7 @@ struct Server {
   std::vector<char> slot_busy;
   int iters_per_round = 10;
   uint64_t retired_since_wait = 0;
+  std::FILE *log = nullptr;  // round timing, when STROM_SERVE_LOG names a file
 };
 
 namespace {
@@ -175,16 +178,21 @@ void solve_loop(Server *S) {
       act = S->active;
     }
     std::vector<char> bad(act.size(), 0);
+    const double t_round = now_s();
     for (size_t k = 0; k < act.size(); ++k) {
       const strom_opts &o = sdp_opts(act[k]->sdp);
       int n = S->iters_per_round;
       (void)o;
       if (sdp_enqueue(act[k]->sdp, n, true) != hipSuccess) bad[k] = 1;
     }
+    const double t_enq = now_s();
     std::vector<Job *> keep;
     for (size_t k = 0; k < act.size(); ++k) {
       Job *j = act[k];
-      if (bad[k] || sdp_read_state(j->sdp) != hipSuccess) {
+      const double t_s0 = now_s();
+      const bool rd_ok = !bad[k] && sdp_read_state(j->sdp) == hipSuccess;
+      if (S->log) std::fprintf(S->log, "  job %llu wait %.3f ms\n", (unsigned long long)j->id, 1e3 * (now_s() - t_s0));
+      if (!rd_ok) {
         strom_sdp_destroy(j->sdp);
         j->sdp = nullptr;
         {
@@ -198,6 +206,9 @@ void solve_loop(Server *S) {
       if (sdp_classify(j->sdp) != STROM_RUNNING) retire(S, j);
       else keep.push_back(j);
     }
+    if (S->log)
+      std::fprintf(S->log, "round t=%.3f active %zu enqueue %.3f ms total %.3f ms\n", t_round, act.size(),
+                   1e3 * (t_enq - t_round), 1e3 * (now_s() - t_round));
     std::lock_guard<std::mutex> lk(S->mu);
     S->active = keep;
   }
@@ -209,6 +220,7 @@ Server *server_start(strom_ctx *ctx) {
   auto *S = new Server();
   S->ctx = ctx;
   hipGetDevice(&S->device);
+  if (const char *lp = std::getenv("STROM_SERVE_LOG")) S->log = std::fopen(lp, "w");
   const int slots = 8;
   S->streams.resize(slots);
   S->slot_busy.assign(slots, 0);
@@ -232,6 +244,7 @@ void server_stop(Server *S) {
     delete kv.second;
   }
   for (auto q : S->streams) hipStreamDestroy(q);
+  if (S->log) std::fclose(S->log);
   delete S;
 }
 

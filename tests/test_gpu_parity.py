@@ -285,3 +285,70 @@ def test_serving_same_result_alone_and_in_the_mix(S, ctx):
         assert np.linalg.norm(X - Xa) <= 1e-9 * max(1.0, np.linalg.norm(Xa))
         assert np.linalg.norm(Sv - Sa) <= 1e-9 * max(1.0, np.linalg.norm(Sa))
         assert abs(info["pobj"] - ia["pobj"]) <= 1e-9 * (1 + abs(ia["pobj"]))
+
+
+# ----------------------------------------------------------------- car family (both variants)
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_car_iterates_vs_oracle(S, ctx, orc, seed):
+    """Planar car, unicycle-12 (seed 0) and bicycle-13 (seed 1): N = 3 for 15 iterations and the
+    full N = 50 (blocks 91x91 / 105x105, n_svec 236,600 / 309,750) for 3 iterations, fixed
+    sigma, same start: X, S and A^* y within 1e-9 of the oracle."""
+    import workloads as W
+    prm = W.instance_params(W.CAR, seed)
+    for N, k in [(3, 15), (50, 3)]:
+        osdp = orc.relax(W.CAR, N, prm)
+        prob = S.generate(W.CAR, N, prm)
+        assert prob.nsvec == osdp.nsvec and prob.m == osdp.m
+        inst = S.Instance(ctx, prob, _opts(S, sigma_every=0, kkt_every=1, tol=0.0))
+        inst.step(k)
+        Xg, yg, Sg = inst.get_iterate()
+        r = orc.admm_solve(osdp, maxiter=k, tol=0.0, sigma_every=0)
+        assert np.linalg.norm(Xg - r["X"]) / max(1.0, np.linalg.norm(r["X"])) <= 1e-9, (N, k)
+        assert np.linalg.norm(Sg - r["S"]) / max(1.0, np.linalg.norm(r["S"])) <= 1e-9, (N, k)
+        A = osdp.A
+        aty, atyo = A.T @ yg, A.T @ r["y"]
+        assert np.linalg.norm(aty - atyo) / max(1.0, np.linalg.norm(atyo)) <= 1e-9, (N, k)
+        inst.close()
+
+
+# ----------------------------------------------------------------- batch of mixed instances
+
+def test_mixed_batch_through_request_loop(S, ctx, orc):
+    """Mixed families and horizons submitted together (the batched form at test size): every
+    converged result satisfies the oracle's KKT check at 1e-6, and instances that reach the
+    iteration cap report it."""
+    import time
+    import workloads as W
+    rng = W.SplitMix64(4242)
+    cases = []
+    for k in range(10):
+        fam = [W.PENDULUM, W.PENDULUM, W.TOY1D, W.CARTPOLE, W.CAR][k % 5]
+        N = {W.PENDULUM: rng.randint(4, 10), W.TOY1D: rng.randint(2, 6), W.CARTPOLE: 2, W.CAR: 2}[fam]
+        cases.append((fam, N, W.instance_params(fam, 100 + k)))
+    opts = S.default_opts(maxiter=30000)
+    probs = [S.generate(f, N, p) for f, N, p in cases]
+    tickets = [ctx.submit(pr, opts) for pr in probs]
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        assert time.time() - t0 < 240, "request loop did not finish"
+        for t, pr in zip(tickets, probs):
+            if t not in done:
+                r = ctx.poll(t, pr.nsvec, pr.m)
+                if r is not None:
+                    done[t] = r
+        time.sleep(0.01)
+    nconv = 0
+    for (fam, N, prm), t in zip(cases, tickets):
+        info, X, y, Sv = done[t]
+        assert info["state"] in (S.CONVERGED, S.MAXITER), info
+        k = orc.kkt(orc.relax(fam, N, prm), X, y, Sv)
+        eta = max(k["eta_p"], k["eta_d"], k["eta_g"])
+        if info["state"] == S.CONVERGED:
+            nconv += 1
+            assert eta <= 1e-6 * 1.05, (fam, N, k)
+        else:
+            assert info["iters"] == 30000
+            assert abs(eta - max(info["eta_p"], info["eta_d"], info["eta_g"])) <= 1e-6 + 1e-3 * eta
+    assert nconv >= 6
