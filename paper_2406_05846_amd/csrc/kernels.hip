@@ -127,7 +127,7 @@ __device__ inline double dense_dot(const double *__restrict__ inv, const double 
 }
 
 // One phase stream (see setup.cpp): thread t walks its slice of K entries (entry k at
-// off + k * Tp + t), eight loads in flight, then the eight factors get(index) (get never
+// off + k * Tp + t), kStreamBatch loads in flight, then their factors get(index) (get never
 // reads what fin writes), then adds them in order; fin(row, sum) completes a row.  A row
 // that started in an earlier slice is completed after a barrier by the thread holding its
 // last entry, adding the pieces of the earlier slices in order (tail_v / tail_r: the open
@@ -146,18 +146,18 @@ __device__ inline void stream_phase(const double *__restrict__ val, const int32_
     const double *vp = val + off + t;
     const int32_t *ip = idx + off + t;
     double acc = 0.0;
-    for (int32_t k0 = 0; k0 < K; k0 += 8) {
-      double v[8];
-      int32_t x[8];
+    for (int32_t k0 = 0; k0 < K; k0 += kStreamBatch) {
+      double v[kStreamBatch];
+      int32_t x[kStreamBatch];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < kStreamBatch; ++u) {
         v[u] = vp[(int64_t)(k0 + u) * Tp];
         x[u] = ip[(int64_t)(k0 + u) * Tp];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] *= get(x[u] & (kLastFlag - 1));
+      for (int u = 0; u < kStreamBatch; ++u) v[u] *= get(x[u] & (kLastFlag - 1));
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < kStreamBatch; ++u) {
         acc += v[u];
         if (x[u] & kLastFlag) {
           if (own) fin(row, acc);

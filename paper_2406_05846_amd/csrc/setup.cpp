@@ -19,6 +19,7 @@
 //    sums by the task owning the columns.  Tasks are launched by dependency depth.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -303,6 +304,12 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
         if (row_task[size_t(i)] == row_task[size_t(j)]) predi[size_t(f[size_t(i)]++)] = j;
       }
   }
+  // largest component; STROM_BLOCK_ROWS overrides the default (tuning of the solve schedule)
+  int32_t max_block = kMaxBlockRows;
+  if (const char *ev = std::getenv("STROM_BLOCK_ROWS")) {
+    const long v = std::strtol(ev, nullptr, 10);
+    if (v >= 1 && v <= 256) max_block = int32_t(v);
+  }
   std::vector<int32_t> rphase(size_t(m), 0), rcomp(size_t(m), 0), rcsize(size_t(m), 1);
   std::vector<int32_t> newpos(static_cast<size_t>(m));
   std::vector<int32_t> task_nph(size_t(ntask), 0);
@@ -341,7 +348,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
           for (int32_t q = l; q <= l1; ++q)
             for (int32_t i : bylev[size_t(q)]) nns2 += sz2[size_t(find(par2, i - r0))] > 1;
         }
-        if (l1 > l && (maxc2 > kMaxBlockRows || nns2 > kMaxPhaseBlockRows)) break;
+        if (l1 > l && (maxc2 > max_block || nns2 > kMaxPhaseBlockRows)) break;
         par.swap(par2);
         sz.swap(sz2);
         maxc = maxc2;
@@ -556,7 +563,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   // ---------------------------------------------------------------- phase streams
   // Every phase is solved from four entry streams.  The entries of the phase's rows (in row
   // order; a row with no entry gets one zero entry) are cut into Tp equal slices of K
-  // entries (Tp <= kSolveThreads a multiple of 64, K a multiple of 8, as few slices of 8 as
+  // entries (Tp <= kSolveThreads a multiple of 64, K a multiple of kStreamBatch, as few slices as
   // cover the phase), slice t for thread t, entry k of it at off + k * Tp + t so that every
   // load of a wave is contiguous.  A row may span several slices; its pieces are added in
   // slice order.  An entry is a value and an index; the index of the last entry of a row
@@ -599,9 +606,9 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
         }
       }
       const int64_t E = int64_t(ent.size());
-      int64_t K = 8;
+      int64_t K = kStreamBatch;
       int32_t Tp = int32_t(std::min<int64_t>(T, (E + K - 1) / K));
-      if (int64_t(Tp) * K < E) K = ((E + Tp - 1) / Tp + 7) / 8 * 8;
+      if (int64_t(Tp) * K < E) K = ((E + Tp - 1) / Tp + kStreamBatch - 1) / kStreamBatch * kStreamBatch;
       Tp = std::min<int32_t>(T, std::max<int32_t>(64, (Tp + 63) / 64 * 64));
       std::vector<int32_t> ra(size_t(T) + 1, rend - rbeg);
       std::vector<double> &V = H.sval[size_t(kind)];

@@ -8,10 +8,11 @@
 
 namespace strom {
 
-constexpr int32_t kSolveThreads = 512;        // workgroup size of the solve kernels
-constexpr int32_t kMaxBlockRows = 64;         // rows of one component (dense diagonal block) of a phase
+constexpr int32_t kSolveThreads = 1024;       // workgroup size of the solve kernels
+constexpr int32_t kMaxBlockRows = 128;        // rows of one component (dense diagonal block) of a phase
 constexpr int32_t kMaxPhaseBlockRows = 4096;  // rows in components of two or more, per phase
 constexpr int32_t kMaxLdsTaskRows = 14336;    // task values kept in LDS up to this many rows
+constexpr int32_t kStreamBatch = 8;              // stream entries loaded per thread at a time
 constexpr int32_t kLastFlag = int32_t(1) << 30;  // stream index flag: last entry of a row
 constexpr int32_t kPartFlag = int32_t(1) << 29;  // forward gather index flag: a pushed partial sum
 constexpr int32_t kStartFlag = int32_t(1) << 30; // first-row flag of a stream slice: the row starts there
