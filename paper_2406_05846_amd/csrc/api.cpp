@@ -237,22 +237,13 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
                oXb = ar.reserve<double>(size_t(n)), oy = ar.reserve<double>(size_t(m)),
                ow = ar.reserve<double>(size_t(m));
   const size_t operm = ar.reserve<int32_t>(size_t(m)), opinv = ar.reserve<int32_t>(size_t(m));
-  const size_t oLrp = ar.reserve<int64_t>(size_t(m) + 1), oLci = ar.reserve<int32_t>(H.Lci.size()),
-               oLv = ar.reserve<double>(H.Lv.size());
-  const size_t oUrp = ar.reserve<int64_t>(size_t(m) + 1), oUci = ar.reserve<int32_t>(H.Uci.size()),
-               oUv = ar.reserve<double>(H.Uv.size());
   const size_t oD = ar.reserve<double>(size_t(m));
-  const size_t oInvR = ar.reserve<double>(std::max<size_t>(1, H.invR.size())),
-               oInvC = ar.reserve<double>(std::max<size_t>(1, H.invC.size()));
   const size_t nph = H.ph_a.size();
-  const size_t oTk = ar.reserve<int32_t>(size_t(ntask) * 4), oPh = ar.reserve<int32_t>(std::max<size_t>(1, nph) * 5);
-  const size_t oRcs = ar.reserve<int32_t>(size_t(m)), oRce = ar.reserve<int32_t>(size_t(m)),
-               oRio = ar.reserve<int64_t>(size_t(m));
+  const size_t oTk = ar.reserve<int32_t>(size_t(ntask) * 4), oPh = ar.reserve<int32_t>(std::max<size_t>(1, nph) * 2);
   const size_t oFo = ar.reserve<int32_t>(H.fwd_order.size()), oBo = ar.reserve<int32_t>(H.bwd_order.size());
   const size_t nseg = std::max<size_t>(1, H.seg_pb.size());
-  const size_t oLin = ar.reserve<int64_t>(size_t(m)), oLend = ar.reserve<int64_t>(size_t(m)),
-               oUbeg = ar.reserve<int64_t>(size_t(m)), oSptr = ar.reserve<int64_t>(size_t(m) + 1),
-               oSpb = ar.reserve<int64_t>(nseg), oSpe = ar.reserve<int64_t>(nseg),
+  const size_t oPoff = ar.reserve<int64_t>(H.push_off.size()), oPci = ar.reserve<int32_t>(std::max<size_t>(1, H.push_ci.size())),
+               oPv = ar.reserve<double>(std::max<size_t>(1, H.push_v.size())),
                oTsp = ar.reserve<int32_t>(size_t(ntask) + 1), oTseg = ar.reserve<int32_t>(nseg),
                oTsg = ar.reserve<int32_t>(size_t(ntask)), oPart = ar.reserve<double>(nseg);
   size_t oSv[4], oSi[4], oSoff[4], oSK[4], oST[4], oSra[4];
@@ -314,14 +305,10 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   int32_t *tk = P32(oTk), *ph = P32(oPh);
   auto &sa = s->sa;
   sa.task_r0 = tk; sa.task_r1 = tk + ntask; sa.task_ph0 = tk + 2 * ntask; sa.task_ph1 = tk + 3 * ntask;
-  sa.ph_a = ph; sa.ph_b = ph + nph; sa.ph_nns = ph + 2 * nph; sa.ph_gf = ph + 3 * nph; sa.ph_gb = ph + 4 * nph;
-  sa.rcs = P32(oRcs); sa.rce = P32(oRce); sa.rio = P64(oRio);
-  sa.Lrp = P64(oLrp); sa.Lci = P32(oLci); sa.Lv = PD(oLv);
-  sa.Urp = P64(oUrp); sa.Uci = P32(oUci); sa.Uv = PD(oUv);
-  sa.D = PD(oD); sa.invR = PD(oInvR); sa.invC = PD(oInvC); sa.perm = P32(operm);
-  sa.Lin = P64(oLin); sa.Lend = P64(oLend); sa.Ubeg = P64(oUbeg); sa.sptr = P64(oSptr);
-  sa.seg_pb = P64(oSpb); sa.seg_pe = P64(oSpe); sa.tsptr = P32(oTsp); sa.tseg = P32(oTseg);
-  sa.task_sg = P32(oTsg); sa.part = PD(oPart);
+  sa.ph_a = ph; sa.ph_nns = ph + nph;
+  sa.D = PD(oD); sa.perm = P32(operm);
+  sa.push_off = P64(oPoff); sa.push_ci = P32(oPci); sa.push_v = PD(oPv);
+  sa.tsptr = P32(oTsp); sa.tseg = P32(oTseg); sa.task_sg = P32(oTsg); sa.part = PD(oPart);
   for (int k = 0; k < 4; ++k) {
     sa.sval[k] = PD(oSv[k]); sa.sidx[k] = P32(oSi[k]); sa.s_off[k] = P64(oSoff[k]);
     sa.s_K[k] = P32(oSK[k]); sa.s_T[k] = P32(oST[k]); sa.s_ra[k] = P32(oSra[k]);
@@ -336,7 +323,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   s->sch.bwd_order_dev = P32(oBo);
 
   // host staging of the small arrays, then synchronous uploads
-  std::vector<int32_t> tkh(size_t(ntask) * 4), phh(std::max<size_t>(1, nph) * 5);
+  std::vector<int32_t> tkh(size_t(ntask) * 4), phh(std::max<size_t>(1, nph) * 2);
   for (int t = 0; t < ntask; ++t) {
     tkh[size_t(t)] = H.task_r0[size_t(t)];
     tkh[size_t(ntask + t)] = H.task_r1[size_t(t)];
@@ -345,10 +332,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   }
   for (size_t k = 0; k < nph; ++k) {
     phh[k] = H.ph_a[k];
-    phh[nph + k] = H.ph_b[k];
-    phh[2 * nph + k] = H.ph_nns[k];
-    phh[3 * nph + k] = H.ph_gf[k];
-    phh[4 * nph + k] = H.ph_gb[k];
+    phh[nph + k] = H.ph_nns[k];
   }
   std::vector<double> zeros;
   hipError_t up_err = hipSuccess;
@@ -374,26 +358,12 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   if (P->S0_svec) ok &= up(s->S, P->S0_svec, sizeof(double) * size_t(n));
   ok &= up(sa.perm, H.perm.data(), sizeof(int32_t) * size_t(m));
   ok &= up(s->pinv, H.pinv.data(), sizeof(int32_t) * size_t(m));
-  ok &= up(const_cast<int64_t *>(sa.Lrp), H.Lrp.data(), sizeof(int64_t) * H.Lrp.size());
-  ok &= up(const_cast<int32_t *>(sa.Lci), H.Lci.data(), sizeof(int32_t) * H.Lci.size());
-  ok &= up(const_cast<double *>(sa.Lv), H.Lv.data(), sizeof(double) * H.Lv.size());
-  ok &= up(const_cast<int64_t *>(sa.Urp), H.Urp.data(), sizeof(int64_t) * H.Urp.size());
-  ok &= up(const_cast<int32_t *>(sa.Uci), H.Uci.data(), sizeof(int32_t) * H.Uci.size());
-  ok &= up(const_cast<double *>(sa.Uv), H.Uv.data(), sizeof(double) * H.Uv.size());
   ok &= up(const_cast<double *>(sa.D), H.D.data(), sizeof(double) * H.D.size());
-  ok &= up(sa.invR, H.invR.data(), sizeof(double) * H.invR.size());
-  ok &= up(sa.invC, H.invC.data(), sizeof(double) * H.invC.size());
   ok &= up(tk, tkh.data(), sizeof(int32_t) * tkh.size());
   ok &= up(ph, phh.data(), sizeof(int32_t) * phh.size());
-  ok &= up(const_cast<int32_t *>(sa.rcs), H.rcs.data(), sizeof(int32_t) * H.rcs.size());
-  ok &= up(const_cast<int32_t *>(sa.rce), H.rce.data(), sizeof(int32_t) * H.rce.size());
-  ok &= up(const_cast<int64_t *>(sa.rio), H.rio.data(), sizeof(int64_t) * H.rio.size());
-  ok &= up(const_cast<int64_t *>(sa.Lin), H.Lin.data(), sizeof(int64_t) * H.Lin.size());
-  ok &= up(const_cast<int64_t *>(sa.Lend), H.Lend.data(), sizeof(int64_t) * H.Lend.size());
-  ok &= up(const_cast<int64_t *>(sa.Ubeg), H.Ubeg.data(), sizeof(int64_t) * H.Ubeg.size());
-  ok &= up(const_cast<int64_t *>(sa.sptr), H.sptr.data(), sizeof(int64_t) * H.sptr.size());
-  ok &= up(const_cast<int64_t *>(sa.seg_pb), H.seg_pb.data(), sizeof(int64_t) * H.seg_pb.size());
-  ok &= up(const_cast<int64_t *>(sa.seg_pe), H.seg_pe.data(), sizeof(int64_t) * H.seg_pe.size());
+  ok &= up(const_cast<int64_t *>(sa.push_off), H.push_off.data(), sizeof(int64_t) * H.push_off.size());
+  ok &= up(const_cast<int32_t *>(sa.push_ci), H.push_ci.data(), sizeof(int32_t) * H.push_ci.size());
+  ok &= up(const_cast<double *>(sa.push_v), H.push_v.data(), sizeof(double) * H.push_v.size());
   ok &= up(const_cast<int32_t *>(sa.tsptr), H.tsptr.data(), sizeof(int32_t) * H.tsptr.size());
   ok &= up(const_cast<int32_t *>(sa.tseg), H.tseg.data(), sizeof(int32_t) * H.tseg.size());
   ok &= up(const_cast<int32_t *>(sa.task_sg), H.task_sg.data(), sizeof(int32_t) * H.task_sg.size());

@@ -20,25 +20,19 @@ struct DevState {
 // Device arrays of the triangular solves (see setup.cpp for their meaning).
 struct SolveArgs {
   const int32_t *task_r0, *task_r1, *task_ph0, *task_ph1;
-  const int32_t *ph_a, *ph_b, *ph_nns, *ph_gf, *ph_gb;
-  const int32_t *rcs, *rce;
-  const int64_t *rio;
-  const int64_t *Lrp;
-  const int32_t *Lci;
-  const double *Lv;
-  const int64_t *Urp;
-  const int32_t *Uci;
-  const double *Uv;
+  const int32_t *ph_a, *ph_nns;  // first row and rows in components of 2+ of every phase
   const double *D;
-  const double *invR, *invC;
   const int32_t *perm;
-  const int64_t *Lin, *Lend, *Ubeg;
-  const int64_t *sptr, *seg_pb, *seg_pe;
+  // pushes: segment s of task t (tseg[tsptr[t] ..]) is [push_off[s], push_off[s+1]) of
+  // push_ci / push_v, pushed task_sg[t] lanes per segment into part[s]
+  const int64_t *push_off;
+  const int32_t *push_ci;
+  const double *push_v;
   const int32_t *tsptr, *tseg, *task_sg;
-  double *part;      // one partial sum per push segment
+  double *part;
   // phase streams, kinds 0 forward gather, 1 forward inverse, 2 backward gather,
   // 3 backward inverse: values, indices, per-phase offset, entries per thread, thread
-  // stride, row runs
+  // stride, first rows of the slices
   const double *sval[4];
   const int32_t *sidx[4];
   const int64_t *s_off[4];

@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__re
     const int g = a.task_sg[t], lane = tid & (g - 1);
     for (int32_t k = a.tsptr[t] + tid / g; k < a.tsptr[t + 1]; k += nth / g) {
       const int32_t sg = a.tseg[k];
-      double s = gather_own(a.Lci, a.Lv, a.seg_pb[sg] + lane, a.seg_pe[sg], g, xs, r0);
+      double s = gather_own(a.push_ci, a.push_v, a.push_off[sg] + lane, a.push_off[sg + 1], g, xs, r0);
       s = group_sum(s, g);
       if (lane == 0) a.part[sg] = s;
     }

@@ -553,6 +553,14 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
       mf = std::max(mf, H.Lend[size_t(i)] - H.Lin[size_t(i)] + H.sptr[size_t(i) + 1] - H.sptr[size_t(i)]);
     H.ph_gf[ph] = lanes_for(mf);
   }
+  H.push_off.assign(1, 0);
+  for (size_t sg = 0; sg < H.seg_pb.size(); ++sg) {
+    for (int64_t p = H.seg_pb[sg]; p < H.seg_pe[sg]; ++p) {
+      H.push_ci.push_back(H.Lci[size_t(p)]);
+      H.push_v.push_back(H.Lv[size_t(p)]);
+    }
+    H.push_off.push_back(int64_t(H.push_ci.size()));
+  }
   H.tsptr.assign(1, 0);
   for (int32_t t = 0; t < ntask; ++t) {
     H.tseg.insert(H.tseg.end(), owned[size_t(t)].begin(), owned[size_t(t)].end());

@@ -62,6 +62,11 @@ struct HostAnalysis {
   // segments tseg[tsptr[t] .. tsptr[t+1]) and pushes them task_sg[t] lanes per segment.
   std::vector<int64_t> sptr, seg_pb, seg_pe;
   std::vector<int32_t> tsptr, tseg, task_sg;
+  // The entries of every segment, copied in segment order (what the device reads for the
+  // pushes): segment s is [push_off[s], push_off[s+1]) of push_ci / push_v.
+  std::vector<int64_t> push_off;
+  std::vector<int32_t> push_ci;
+  std::vector<double> push_v;
   // Phase streams (kinds 0 fg, 1 fi, 2 bg, 3 bi; see setup.cpp): values and indices, and per
   // phase the offset, the entries per thread K, the thread count Tp and, for kSolveThreads + 1
   // threads, the first row of each slice.
