@@ -60,9 +60,9 @@ struct JacobiTol<float> {
   static constexpr double skip_rel = 1e-9;
 };
 
-// LDS: V (n*n doubles, column-major) | red (nthreads doubles) | rotd (2 doubles per pair: c, s)
-//      | A (packed upper triangle, T) | rot (4 T per pair: c, s, new a_pp, new a_qq)
-//      | sel (n + 4 ints), every region 32-byte aligned.
+// LDS: V (n*n doubles, column-major) | red (nthreads doubles) | rotd (two buffers of 2 doubles
+//      per pair: c, s) | A (packed upper triangle, T) | rot (two buffers of 4 T per pair: c, s,
+//      new a_pp, new a_qq) | sel (n + 4 ints), every region 32-byte aligned.
 struct Layout {
   size_t red, rotd, A, rot, sel, total;
 };
@@ -74,9 +74,9 @@ __host__ __device__ inline Layout lds_layout(int n, int nthreads, size_t tsize) 
   Layout L;
   L.red = align32(8 * (size_t)n * n);
   L.rotd = align32(L.red + 8 * (size_t)nthreads);
-  L.A = align32(L.rotd + 16 * np2);
+  L.A = align32(L.rotd + 2 * 16 * np2);
   L.rot = align32(L.A + tsize * npk);
-  L.sel = align32(L.rot + 4 * tsize * np2);
+  L.sel = align32(L.rot + 2 * 4 * tsize * np2);
   L.total = align32(L.sel + 4 * ((size_t)n + 4));
   return L;
 }
@@ -208,6 +208,57 @@ __device__ inline void rotate_block(int r, int I, int J, int n, int mm, T *A, co
   if (hq1 && hq2) A[pidx(q1, q2)] = s2 * rc + c2 * rd;
 }
 
+// Rotation parameters of every pair of round r from A (threads t0, t0 + stride, ...).
+template <typename T>
+__device__ inline void round_rotations(int r, int n, int np2, int mm, double skip, const T *A, T *rot, double *rotd,
+                                       int t0, int stride) {
+  for (int k = t0; k < np2; k += stride) {
+    int p, q;
+    rr_pair(r, k, mm, p, q);
+    double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
+    if (q < n) {
+      const double apq = (double)A[pidx(p, q)], app = (double)A[pidx(p, p)], aqq = (double)A[pidx(q, q)];
+      dp = app;
+      dq = aqq;
+      if (fabs(apq) > skip) {
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        c = 1.0 / sqrt(t * t + 1.0);
+        s = t * c;
+        dp = app - t * apq;
+        dq = aqq + t * apq;
+      }
+    }
+    typedef typename Vec4<T>::type V4;
+    V4 rv;
+    rv.x = (T)c;
+    rv.y = (T)s;
+    rv.z = (T)dp;
+    rv.w = (T)dq;
+    reinterpret_cast<V4 *>(rot)[k] = rv;
+    reinterpret_cast<double2 *>(rotd)[k] = make_double2(c, s);
+  }
+}
+
+// V <- V J for the rotations rotd of round r: this thread's eigenvector row vrow, pairs
+// vk0, vk0 + vks, ...
+__device__ inline void rotate_vectors(int r, int n, int np2, int mm, const double *rotd, double *V, int vrow, int vk0,
+                                      int vks) {
+  for (int k = vk0; k < np2; k += vks) {
+    int p, q;
+    rr_pair(r, k, mm, p, q);
+    if (q >= n) continue;
+    const double2 cs = reinterpret_cast<const double2 *>(rotd)[k];
+    const double c = cs.x, s = cs.y;
+    const double vp = V[vrow + p * n], vq = V[vrow + q * n];
+    V[vrow + p * n] = c * vp - s * vq;
+    V[vrow + q * n] = s * vp + c * vq;
+  }
+}
+
+// Cyclic Jacobi, two barriers per round.  With enough threads (split), the first wave
+// computes the rotations of round r while the other waves apply those of round r - 1 to the
+// eigenvectors (rot / rotd double-buffered); then all threads rotate the 2x2 blocks of A.
 template <typename T>
 __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double *red, bool v_ready) {
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -217,8 +268,11 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double 
   int I0 = -1, J0 = -1, I1 = -1, J1 = -1;  // this thread's 2x2 blocks, fixed over the rounds
   if (tid < nblk) tri_ij(tid, I0, J0);
   if (tid + nth < nblk) tri_ij(tid + nth, I1, J1);
-  // eigenvector rows: thread -> (row, first pair, pair stride), fixed over the rounds
-  const int vks = nth / n, vrow = tid % n, vk0 = vks > 0 && tid < vks * n ? tid / n : np2;
+  // eigenvector rows: thread -> (row, first pair, pair stride), fixed over the rounds; in
+  // split mode the first wave takes no rows
+  const bool split = nth - 64 >= n;
+  const int vt = split ? tid - 64 : tid, nv = split ? nth - 64 : nth;
+  const int vks = nv / n, vrow = vt >= 0 ? vt % n : 0, vk0 = (vt >= 0 && vks > 0 && vt < vks * n) ? vt / n : np2;
   if (!v_ready)
     for (int k = tid; k < n * n; k += nth) V[k] = (k % (n + 1) == 0) ? 1.0 : 0.0;
   double f2 = 0.0;
@@ -231,6 +285,8 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double 
   const double fro2 = wg_sum(f2, red);
   const double skip = JacobiTol<T>::skip_rel * sqrt(fro2);
   const double offtol2 = JacobiTol<T>::off_rel * JacobiTol<T>::off_rel * fro2;
+  int g = 0;         // rounds done; round g uses buffer g & 1
+  int pending = -1;  // split mode: round whose eigenvector update is still to do
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0;  // off-diagonal mass at the start of the sweep
     for (int k = tid; k < npk; k += nth) {
@@ -240,48 +296,26 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double 
       if (i != j) off += 2.0 * a * a;
     }
     if (wg_sum(off, red) <= offtol2) break;
-    for (int r = 0; r < mm; ++r) {
-      for (int k = tid; k < np2; k += nth) {
-        int p, q;
-        rr_pair(r, k, mm, p, q);
-        double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
-        if (q < n) {
-          const double apq = (double)A[pidx(p, q)], app = (double)A[pidx(p, p)], aqq = (double)A[pidx(q, q)];
-          dp = app;
-          dq = aqq;
-          if (fabs(apq) > skip) {
-            const double theta = (aqq - app) / (2.0 * apq);
-            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-            dp = app - t * apq;
-            dq = aqq + t * apq;
-          }
-        }
-        typedef typename Vec4<T>::type V4;
-        V4 rv;
-        rv.x = (T)c;
-        rv.y = (T)s;
-        rv.z = (T)dp;
-        rv.w = (T)dq;
-        reinterpret_cast<V4 *>(rot)[k] = rv;
-        reinterpret_cast<double2 *>(rotd)[k] = make_double2(c, s);
+    for (int r = 0; r < mm; ++r, ++g) {
+      T *rc = rot + (g & 1) * 4 * np2;
+      double *rdc = rotd + (g & 1) * 2 * np2;
+      if (split) {
+        if (tid < 64) round_rotations<T>(r, n, np2, mm, skip, A, rc, rdc, tid, 64);
+        else if (pending >= 0) rotate_vectors(pending, n, np2, mm, rotd + ((g + 1) & 1) * 2 * np2, V, vrow, vk0, vks);
+      } else {
+        round_rotations<T>(r, n, np2, mm, skip, A, rc, rdc, tid, nth);
       }
       __syncthreads();
-      if (I0 >= 0) rotate_block<T>(r, I0, J0, n, mm, A, rot);
-      if (I1 >= 0) rotate_block<T>(r, I1, J1, n, mm, A, rot);
-      for (int k = vk0; k < np2; k += vks) {
-        int p, q;
-        rr_pair(r, k, mm, p, q);
-        if (q >= n) continue;
-        const double2 cs = reinterpret_cast<const double2 *>(rotd)[k];
-        const double c = cs.x, s = cs.y;
-        const double vp = V[vrow + p * n], vq = V[vrow + q * n];
-        V[vrow + p * n] = c * vp - s * vq;
-        V[vrow + q * n] = s * vp + c * vq;
-      }
+      if (I0 >= 0) rotate_block<T>(r, I0, J0, n, mm, A, rc);
+      if (I1 >= 0) rotate_block<T>(r, I1, J1, n, mm, A, rc);
+      if (split) pending = r;
+      else rotate_vectors(r, n, np2, mm, rdc, V, vrow, vk0, vks);
       __syncthreads();
     }
+  }
+  if (pending >= 0) {  // the last round's eigenvector update
+    if (tid >= 64) rotate_vectors(pending, n, np2, mm, rotd + ((g + 1) & 1) * 2 * np2, V, vrow, vk0, vks);
+    __syncthreads();
   }
 }
 
