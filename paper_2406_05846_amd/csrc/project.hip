@@ -123,7 +123,7 @@ __device__ inline double wg_sum(double v, double *red) {
 // A is overwritten column block by column block once W is complete: W is kept in the block's
 // slot wq of the eigenvector buffer (n*n doubles, free until the eigenvectors are written back).
 template <typename T>
-__device__ void rotate_into_basis(int n, const double *xs, const double *V, double *wq, T *A) {
+__device__ __forceinline__ void rotate_into_basis(int n, const double *xs, const double *V, double *wq, T *A) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const double rs2 = 0.70710678118654752440;
   const int npk = n * (n + 1) / 2;
@@ -178,7 +178,7 @@ struct Vec4<float> {
 
 // New value of the 2x2 block (pair I) x (pair J), I <= J, of round r.
 template <typename T>
-__device__ inline void rotate_block(int r, int I, int J, int n, int mm, T *A, const T *rot) {
+__device__ __forceinline__ void rotate_block(int r, int I, int J, int n, int mm, T *A, const T *rot) {
   typedef typename Vec4<T>::type V4;
   int p1, q1;
   rr_pair(r, I, mm, p1, q1);
@@ -210,7 +210,7 @@ __device__ inline void rotate_block(int r, int I, int J, int n, int mm, T *A, co
 
 // Rotation parameters of every pair of round r from A (threads t0, t0 + stride, ...).
 template <typename T>
-__device__ inline void round_rotations(int r, int n, int np2, int mm, double skip, const T *A, T *rot, double *rotd,
+__device__ __forceinline__ void round_rotations(int r, int n, int np2, int mm, double skip, const T *A, T *rot, double *rotd,
                                        int t0, int stride) {
   for (int k = t0; k < np2; k += stride) {
     int p, q;
@@ -242,7 +242,7 @@ __device__ inline void round_rotations(int r, int n, int np2, int mm, double ski
 
 // V <- V J for the rotations rotd of round r: this thread's eigenvector row vrow, pairs
 // vk0, vk0 + vks, ...
-__device__ inline void rotate_vectors(int r, int n, int np2, int mm, const double *rotd, double *V, int vrow, int vk0,
+__device__ __forceinline__ void rotate_vectors(int r, int n, int np2, int mm, const double *rotd, double *V, int vrow, int vk0,
                                       int vks) {
   for (int k = vk0; k < np2; k += vks) {
     int p, q;
@@ -260,7 +260,7 @@ __device__ inline void rotate_vectors(int r, int n, int np2, int mm, const doubl
 // computes the rotations of round r while the other waves apply those of round r - 1 to the
 // eigenvectors (rot / rotd double-buffered); then all threads rotate the 2x2 blocks of A.
 template <typename T>
-__device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double *red, bool v_ready) {
+__device__ __forceinline__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double *red, bool v_ready) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int np2 = (n + 1) / 2, nn = 2 * np2, mm = nn - 1;
   const int npk = n * (n + 1) / 2;
@@ -324,7 +324,7 @@ __device__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double 
 // (Pi = X - sum_{lam < 0} lam v v^T).  sel[n] = 1 for the positive side, sel[n+1] = count.
 // The first wave counts and compacts with ballots.
 template <typename T>
-__device__ void select_side(int n, const T *A, int *sel) {
+__device__ __forceinline__ void select_side(int n, const T *A, int *sel) {
   const int tid = threadIdx.x;
   if (tid < 64) {
     int np = 0, nneg = 0;
