@@ -246,6 +246,9 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
                oPv = ar.reserve<double>(std::max<size_t>(1, H.push_v.size())),
                oTsp = ar.reserve<int32_t>(size_t(ntask) + 1), oTseg = ar.reserve<int32_t>(nseg),
                oTsg = ar.reserve<int32_t>(size_t(ntask)), oPart = ar.reserve<double>(nseg);
+  const size_t oTpin = ar.reserve<int32_t>(size_t(ntask) + 1), oTinl = ar.reserve<int32_t>(size_t(ntask)),
+               oTxoff = ar.reserve<int64_t>(size_t(ntask) + 1),
+               oTxrow = ar.reserve<int32_t>(std::max<size_t>(1, H.task_xrow.size()));
   size_t oSv[4], oSi[4], oSoff[4], oSK[4], oST[4], oSra[4];
   for (int k = 0; k < 4; ++k) {
     oSv[k] = ar.reserve<double>(std::max<size_t>(1, H.sval[k].size()));
@@ -309,14 +312,15 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   sa.D = PD(oD); sa.perm = P32(operm);
   sa.push_off = P64(oPoff); sa.push_ci = P32(oPci); sa.push_v = PD(oPv);
   sa.tsptr = P32(oTsp); sa.tseg = P32(oTseg); sa.task_sg = P32(oTsg); sa.part = PD(oPart);
+  sa.task_pin = P32(oTpin); sa.task_inl = P32(oTinl); sa.task_xoff = P64(oTxoff); sa.task_xrow = P32(oTxrow);
   for (int k = 0; k < 4; ++k) {
     sa.sval[k] = PD(oSv[k]); sa.sidx[k] = P32(oSi[k]); sa.s_off[k] = P64(oSoff[k]);
     sa.s_K[k] = P32(oSK[k]); sa.s_T[k] = P32(oST[k]); sa.s_ra[k] = P32(oSra[k]);
   }
   sa.c_cap = std::max(1, H.max_phase_nns);
-  sa.lds_rows = std::min(H.max_task_rows,
-                         std::min(strom::kMaxLdsTaskRows, int32_t(ctx->max_lds / sizeof(double)) - sa.c_cap -
-                                                             strom::kSolveThreads * 3 / 2 - 8));
+  sa.lds_rows = std::max(1, H.max_task_stage);
+  if (size_t(strom::kSolveThreads * 3 / 2 + sa.lds_rows + sa.c_cap) * sizeof(double) > ctx->max_lds)
+    return undo(STROM_E_INVAL, "the solve schedule needs more LDS than the device has");
   s->sch.fwd_gptr = H.fwd_gptr;
   s->sch.bwd_gptr = H.bwd_gptr;
   s->sch.fwd_order_dev = P32(oFo);
@@ -367,6 +371,13 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   ok &= up(const_cast<int32_t *>(sa.tsptr), H.tsptr.data(), sizeof(int32_t) * H.tsptr.size());
   ok &= up(const_cast<int32_t *>(sa.tseg), H.tseg.data(), sizeof(int32_t) * H.tseg.size());
   ok &= up(const_cast<int32_t *>(sa.task_sg), H.task_sg.data(), sizeof(int32_t) * H.task_sg.size());
+  {
+    const std::vector<int32_t> inl(H.task_inl.begin(), H.task_inl.end());
+    ok &= up(const_cast<int32_t *>(sa.task_inl), inl.data(), sizeof(int32_t) * inl.size());
+  }
+  ok &= up(const_cast<int32_t *>(sa.task_pin), H.task_pin.data(), sizeof(int32_t) * H.task_pin.size());
+  ok &= up(const_cast<int64_t *>(sa.task_xoff), H.task_xoff.data(), sizeof(int64_t) * H.task_xoff.size());
+  ok &= up(const_cast<int32_t *>(sa.task_xrow), H.task_xrow.data(), sizeof(int32_t) * H.task_xrow.size());
   for (int k = 0; k < 4; ++k) {
     ok &= up(const_cast<double *>(sa.sval[k]), H.sval[k].data(), sizeof(double) * H.sval[k].size());
     ok &= up(const_cast<int32_t *>(sa.sidx[k]), H.sidx[k].data(), sizeof(int32_t) * H.sidx[k].size());

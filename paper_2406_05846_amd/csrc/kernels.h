@@ -39,7 +39,13 @@ struct SolveArgs {
   const int32_t *s_K[4];
   const int32_t *s_T[4];
   const int32_t *s_ra[4];
-  int32_t lds_rows;  // tasks with at most this many rows keep their values in LDS
+  // task-local staging (task_inl[t] != 0): the task's rows, then its incoming partial sums
+  // part[task_pin[t] ..] (forward) or the later-task rows task_xrow[task_xoff[t] ..]
+  // (backward) are staged in LDS and the fg / bg stream indices address that buffer
+  const int32_t *task_pin, *task_inl;
+  const int64_t *task_xoff;
+  const int32_t *task_xrow;
+  int32_t lds_rows;  // LDS doubles for a staged task (at least every staged task's total)
   int32_t c_cap;     // LDS doubles for the right-hand sides of a phase's components
 };
 

@@ -84,27 +84,6 @@ __device__ inline double gather_own(const int32_t *__restrict__ ci, const double
   return (s0 + s1) + (s2 + s3);
 }
 
-// as gather_own, with columns at or after r1 read from the global vector w
-__device__ inline double gather_mixed(const int32_t *__restrict__ ci, const double *__restrict__ v, int64_t b,
-                                      int64_t e, int g, const double *xs, int32_t r0, int32_t r1,
-                                      const double *__restrict__ w) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t p = b;
-  for (; p + 3 * g < e; p += 4 * g) {
-    const int32_t j0 = ci[p], j1 = ci[p + g], j2 = ci[p + 2 * g], j3 = ci[p + 3 * g];
-    const double v0 = v[p], v1 = v[p + g], v2 = v[p + 2 * g], v3 = v[p + 3 * g];
-    s0 += v0 * (j0 < r1 ? xs[j0 - r0] : w[j0]);
-    s1 += v1 * (j1 < r1 ? xs[j1 - r0] : w[j1]);
-    s2 += v2 * (j2 < r1 ? xs[j2 - r0] : w[j2]);
-    s3 += v3 * (j3 < r1 ? xs[j3 - r0] : w[j3]);
-  }
-  for (; p < e; p += g) {
-    const int32_t j = ci[p];
-    s0 += v[p] * (j < r1 ? xs[j - r0] : w[j]);
-  }
-  return (s0 + s1) + (s2 + s3);
-}
-
 __device__ inline double sum_parts(const double *__restrict__ part, int64_t b, int64_t e, int g) {
   double s = 0.0;
   for (int64_t q = b; q < e; q += g) s += part[q];
@@ -182,26 +161,33 @@ __device__ inline void stream_phase(const double *__restrict__ val, const int32_
   }
 }
 
-__global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__restrict__ tasks, SolveArgs a,
-                                                             double *__restrict__ w) {
-  extern __shared__ double sh[];
+// Forward solve of task t.  INL: the task is staged in LDS -- its rows, then the partial sums
+// pushed to it -- and the stream indices are task-local; else its values are read and written
+// in place in w and the indices are global.  A separate instantiation for each case keeps every
+// access in one address space (LDS or global).
+template <bool INL>
+__device__ __forceinline__ void solve_fwd_task(int32_t t, const SolveArgs &a, double *__restrict__ w, double *sh) {
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int32_t t = tasks[blockIdx.x];
   const int32_t r0 = a.task_r0[t], r1 = a.task_r1[t], nt = r1 - r0;
-  const bool inl = nt <= a.lds_rows;
   double *tail_v = sh;  // open-row pieces of the stream slices
   int32_t *tail_r = reinterpret_cast<int32_t *>(sh + kSolveThreads);
   double *buf = sh + kSolveThreads + kSolveThreads / 2;
-  double *xs = inl ? buf : (w + r0);  // values of the task rows, index i - r0
-  double *c = inl ? buf + nt : buf;   // right-hand sides of the phase's components
-  if (inl)
+  const int32_t p0 = INL ? a.task_pin[t] : 0, npin = INL ? a.task_pin[t + 1] - p0 : 0;
+  double *xs = INL ? buf : (w + r0);          // values of the task rows, index i - r0
+  double *c = INL ? buf + nt + npin : buf;    // right-hand sides of the phase's components
+  if (INL) {
     for (int i = tid; i < nt; i += nth) xs[i] = w[r0 + i];
+    for (int k = tid; k < npin; k += nth) xs[nt + k] = a.part[p0 + k];
+  }
   __syncthreads();
   for (int32_t ph = a.task_ph0[t]; ph < a.task_ph1[t]; ++ph) {
     const int32_t pa = a.ph_a[ph], nns = a.ph_nns[ph];
     stream_phase(a.sval[0], a.sidx[0], a.s_off[0][ph], a.s_K[0][ph], a.s_T[0][ph],
                 a.s_ra[0] + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
-                [&](int32_t j) { return (j & kPartFlag) ? a.part[j & (kPartFlag - 1)] : xs[j - r0]; },
+                [&](int32_t j) {
+                  if constexpr (INL) return xs[j];
+                  else return (j & kPartFlag) ? a.part[j & (kPartFlag - 1)] : w[j];
+                },
                 [&](int32_t r, double acc) {
                   const double v = xs[pa + r - r0] - acc;
                   if (r < nns) c[r] = v;
@@ -225,32 +211,46 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__re
       if (lane == 0) a.part[sg] = s;
     }
   }
-  if (inl)
+  if (INL)
     for (int i = tid; i < nt; i += nth) w[r0 + i] = xs[i];
 }
 
-// Backward: L^T x = D^{-1} z over the phases in reverse order (a row only depends here on
-// its own component, later phases and later tasks).
-__global__ void __launch_bounds__(kSolveThreads) k_solve_bwd(const int32_t *__restrict__ tasks, SolveArgs a,
-                                                             double *__restrict__ w, double *__restrict__ y) {
+__global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__restrict__ tasks, SolveArgs a,
+                                                             double *__restrict__ w) {
   extern __shared__ double sh[];
-  const int tid = threadIdx.x, nth = blockDim.x;
   const int32_t t = tasks[blockIdx.x];
+  if (a.task_inl[t]) solve_fwd_task<true>(t, a, w, sh);
+  else solve_fwd_task<false>(t, a, w, sh);
+}
+
+// Backward: L^T x = D^{-1} z over the phases in reverse order (a row only depends here on
+// its own component, later phases and later tasks).  INL: the task's rows and the rows of
+// later tasks it reads are staged in LDS, stream indices task-local.
+template <bool INL>
+__device__ __forceinline__ void solve_bwd_task(int32_t t, const SolveArgs &a, double *__restrict__ w,
+                                               double *__restrict__ y, double *sh) {
+  const int tid = threadIdx.x, nth = blockDim.x;
   const int32_t r0 = a.task_r0[t], r1 = a.task_r1[t], nt = r1 - r0;
-  const bool inl = nt <= a.lds_rows;
   double *tail_v = sh;
   int32_t *tail_r = reinterpret_cast<int32_t *>(sh + kSolveThreads);
   double *buf = sh + kSolveThreads + kSolveThreads / 2;
-  double *xs = inl ? buf : (w + r0);
-  double *c = inl ? buf + nt : buf;
-  if (inl)
+  const int64_t x0 = INL ? a.task_xoff[t] : 0;
+  const int32_t nx = INL ? (int32_t)(a.task_xoff[t + 1] - x0) : 0;
+  double *xs = INL ? buf : (w + r0);
+  double *c = INL ? buf + nt + nx : buf;
+  if (INL) {
     for (int i = tid; i < nt; i += nth) xs[i] = w[r0 + i];
+    for (int k = tid; k < nx; k += nth) xs[nt + k] = w[a.task_xrow[x0 + k]];
+  }
   __syncthreads();
   for (int32_t ph = a.task_ph1[t] - 1; ph >= a.task_ph0[t]; --ph) {
     const int32_t pa = a.ph_a[ph], nns = a.ph_nns[ph];
     stream_phase(a.sval[2], a.sidx[2], a.s_off[2][ph], a.s_K[2][ph], a.s_T[2][ph],
                 a.s_ra[2] + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
-                [&](int32_t i) { return i < r1 ? xs[i - r0] : w[i]; },
+                [&](int32_t i) {
+                  if constexpr (INL) return xs[i];
+                  else return w[i];
+                },
                 [&](int32_t r, double acc) {
                   const int32_t j = pa + r;
                   const double v = xs[j - r0] / a.D[j] - acc;
@@ -267,9 +267,17 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd(const int32_t *__re
   }
   for (int i = tid; i < nt; i += nth) {
     const double v = xs[i];
-    if (inl) w[r0 + i] = v;
+    if (INL) w[r0 + i] = v;
     y[a.perm[r0 + i]] = v;
   }
+}
+
+__global__ void __launch_bounds__(kSolveThreads) k_solve_bwd(const int32_t *__restrict__ tasks, SolveArgs a,
+                                                             double *__restrict__ w, double *__restrict__ y) {
+  extern __shared__ double sh[];
+  const int32_t t = tasks[blockIdx.x];
+  if (a.task_inl[t]) solve_bwd_task<true>(t, a, w, y, sh);
+  else solve_bwd_task<false>(t, a, w, y, sh);
 }
 
 // ------------------------------------------------------------------ step 2: X_b

@@ -276,135 +276,283 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   // greedily into phases: a phase is a run of consecutive levels whose rows, joined by the
   // dependencies among them, form connected components of at most kMaxBlockRows rows (at
   // most kMaxPhaseBlockRows rows in components of two or more).  Rows of a task are then
-  // relabeled in (phase, component, level) order.  Dependencies inside a component point to
-  // lower levels and dependencies between phases to earlier phases, so the relabeled L stays
-  // unit lower triangular and is the factor of the relabeled matrix (nothing is refactored).
-  const int32_t ntask = int32_t(H.task_r0.size());
-  std::vector<int32_t> row_task(static_cast<size_t>(m));
-  for (int32_t t = 0; t < ntask; ++t)
-    for (int32_t r = H.task_r0[size_t(t)]; r < H.task_r1[size_t(t)]; ++r) row_task[size_t(r)] = t;
-  std::vector<int32_t> lev(size_t(m), 0);
-  std::vector<int64_t> predp(size_t(m) + 1, 0);  // predecessors inside the task, CSR by row
-  std::vector<int32_t> predi;
-  for (int32_t j = 0; j < m; ++j)
-    for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
-      const int32_t i = Ci[size_t(p)];
-      if (row_task[size_t(i)] == row_task[size_t(j)]) {
-        lev[size_t(i)] = std::max(lev[size_t(i)], lev[size_t(j)] + 1);
-        predp[size_t(i) + 1]++;
-      }
-    }
-  for (int32_t i = 0; i < m; ++i) predp[size_t(i) + 1] += predp[size_t(i)];
-  predi.resize(size_t(predp[size_t(m)]));
-  {
-    std::vector<int64_t> f(predp.begin(), predp.end() - 1);
-    for (int32_t j = 0; j < m; ++j)
-      for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
-        const int32_t i = Ci[size_t(p)];
-        if (row_task[size_t(i)] == row_task[size_t(j)]) predi[size_t(f[size_t(i)]++)] = j;
-      }
-  }
-  // largest component; STROM_BLOCK_ROWS overrides the default (tuning of the solve schedule)
-  int32_t max_block = kMaxBlockRows;
+  // relabeled in (phase, component, level) order.  Every relabeling here is a topological
+  // order of the factor's dependencies, so the relabeled L stays unit lower triangular and is
+  // the factor of the relabeled matrix (nothing is refactored).
+  //
+  // Load balance: a group task whose cost (stream entries per thread, see phase_cost) is far
+  // above the typical group task -- the first and last cliques of a trajectory carry the
+  // boundary-condition rows -- is split: the components of its first phase, which do not
+  // depend on each other, are dealt to several tasks, and its later phases move into the
+  // coupling task next to it that comes first in the order (that task depends on them
+  // anyway), so the split adds no dependency depth.
+  int32_t max_block = kMaxBlockRows;  // STROM_BLOCK_ROWS overrides (tuning of the solve schedule)
   if (const char *ev = std::getenv("STROM_BLOCK_ROWS")) {
     const long v = std::strtol(ev, nullptr, 10);
     if (v >= 1 && v <= 256) max_block = int32_t(v);
   }
+  bool allow_split = true;  // STROM_TASK_SPLIT=0 disables the split
+  if (const char *ev = std::getenv("STROM_TASK_SPLIT")) allow_split = std::strtol(ev, nullptr, 10) != 0;
+  int32_t ntask = int32_t(H.task_r0.size());
+  std::vector<int32_t> row_task(static_cast<size_t>(m));
+  auto set_row_task = [&]() {
+    ntask = int32_t(H.task_r0.size());
+    for (int32_t t = 0; t < ntask; ++t)
+      for (int32_t r = H.task_r0[size_t(t)]; r < H.task_r1[size_t(t)]; ++r) row_task[size_t(r)] = t;
+  };
   std::vector<int32_t> rphase(size_t(m), 0), rcomp(size_t(m), 0), rcsize(size_t(m), 1);
+  std::vector<int32_t> lev(size_t(m), 0);
   std::vector<int32_t> newpos(static_cast<size_t>(m));
-  std::vector<int32_t> task_nph(size_t(ntask), 0);
-  for (int32_t t = 0; t < ntask; ++t) {
-    const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)], nt = r1 - r0;
-    int32_t L = 0;
-    for (int32_t i = r0; i < r1; ++i) L = std::max(L, lev[size_t(i)] + 1);
-    std::vector<std::vector<int32_t>> bylev(static_cast<size_t>(L));
-    for (int32_t i = r0; i < r1; ++i) bylev[size_t(lev[size_t(i)])].push_back(i);
-    std::vector<int32_t> par(static_cast<size_t>(nt)), sz(static_cast<size_t>(nt), 1);
-    std::iota(par.begin(), par.end(), 0);
-    auto find = [&](std::vector<int32_t> &pa, int32_t x) {
-      while (pa[size_t(x)] != x) { pa[size_t(x)] = pa[size_t(pa[size_t(x)])]; x = pa[size_t(x)]; }
-      return x;
-    };
-    int32_t l = 0, ph = 0;
-    while (l < L) {
-      int32_t l1 = l, maxc = 1;
-      int64_t nns = 0;  // rows in components of two or more
-      while (l1 < L) {
-        std::vector<int32_t> par2 = par, sz2 = sz;
-        int32_t maxc2 = maxc;
-        for (int32_t i : bylev[size_t(l1)])
-          for (int64_t p = predp[size_t(i)]; p < predp[size_t(i) + 1]; ++p) {
-            const int32_t j = predi[size_t(p)];
-            if (lev[size_t(j)] < l) continue;  // earlier phase
-            int32_t a = find(par2, i - r0), b = find(par2, j - r0);
-            if (a == b) continue;
-            if (sz2[size_t(a)] < sz2[size_t(b)]) std::swap(a, b);
-            par2[size_t(b)] = a;
-            sz2[size_t(a)] += sz2[size_t(b)];
-            maxc2 = std::max(maxc2, sz2[size_t(a)]);
-          }
-        int64_t nns2 = 0;
-        if (maxc2 > 1) {
-          for (int32_t q = l; q <= l1; ++q)
-            for (int32_t i : bylev[size_t(q)]) nns2 += sz2[size_t(find(par2, i - r0))] > 1;
+  std::vector<int32_t> task_nph;
+  // Levels and phases of every task; newpos = the (phase, component, level) order.
+  auto partition = [&]() {
+    std::fill(lev.begin(), lev.end(), 0);
+    std::vector<int64_t> predp(size_t(m) + 1, 0);  // predecessors inside the task, CSR by row
+    std::vector<int32_t> predi;
+    for (int32_t j = 0; j < m; ++j)
+      for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
+        const int32_t i = Ci[size_t(p)];
+        if (row_task[size_t(i)] == row_task[size_t(j)]) {
+          lev[size_t(i)] = std::max(lev[size_t(i)], lev[size_t(j)] + 1);
+          predp[size_t(i) + 1]++;
         }
-        if (l1 > l && (maxc2 > max_block || nns2 > kMaxPhaseBlockRows)) break;
-        par.swap(par2);
-        sz.swap(sz2);
-        maxc = maxc2;
-        nns = nns2;
-        ++l1;
       }
-      (void)nns;
-      for (int32_t q = l; q < l1; ++q)
-        for (int32_t i : bylev[size_t(q)]) {
-          const int32_t root = find(par, i - r0);
-          rphase[size_t(i)] = ph;
-          rcomp[size_t(i)] = root;
-          rcsize[size_t(i)] = sz[size_t(root)];
+    for (int32_t i = 0; i < m; ++i) predp[size_t(i) + 1] += predp[size_t(i)];
+    predi.resize(size_t(predp[size_t(m)]));
+    {
+      std::vector<int64_t> f(predp.begin(), predp.end() - 1);
+      for (int32_t j = 0; j < m; ++j)
+        for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
+          const int32_t i = Ci[size_t(p)];
+          if (row_task[size_t(i)] == row_task[size_t(j)]) predi[size_t(f[size_t(i)]++)] = j;
         }
-      ++ph;
-      l = l1;
     }
-    task_nph[size_t(t)] = ph;
-    std::vector<int32_t> rows(static_cast<size_t>(nt));
-    std::iota(rows.begin(), rows.end(), r0);
-    std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) {
-      if (rphase[size_t(a)] != rphase[size_t(b)]) return rphase[size_t(a)] < rphase[size_t(b)];
-      const bool sa = rcsize[size_t(a)] == 1, sb = rcsize[size_t(b)] == 1;
-      if (sa != sb) return !sa;  // components of two or more first, singletons last
-      if (rcomp[size_t(a)] != rcomp[size_t(b)]) return rcomp[size_t(a)] < rcomp[size_t(b)];
-      return lev[size_t(a)] < lev[size_t(b)];
-    });
-    for (int32_t k = 0; k < nt; ++k) newpos[size_t(rows[size_t(k)])] = r0 + k;
-  }
-  predp.clear(); predi.clear();
-  {
-    std::vector<int32_t> perm2(static_cast<size_t>(m));
-    std::vector<double> D2(static_cast<size_t>(m));
-    std::vector<int32_t> ph2(static_cast<size_t>(m)), cs2(static_cast<size_t>(m)), cz2(static_cast<size_t>(m));
-    for (int32_t i = 0; i < m; ++i) {
-      const size_t ni = size_t(newpos[size_t(i)]);
-      perm2[ni] = H.perm[size_t(i)];
-      D2[ni] = Dn[size_t(i)];
-      ph2[ni] = rphase[size_t(i)];
-      cs2[ni] = rcomp[size_t(i)];
-      cz2[ni] = rcsize[size_t(i)];
+    task_nph.assign(size_t(ntask), 0);
+    for (int32_t t = 0; t < ntask; ++t) {
+      const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)], nt = r1 - r0;
+      int32_t L = 0;
+      for (int32_t i = r0; i < r1; ++i) L = std::max(L, lev[size_t(i)] + 1);
+      std::vector<std::vector<int32_t>> bylev(static_cast<size_t>(L));
+      for (int32_t i = r0; i < r1; ++i) bylev[size_t(lev[size_t(i)])].push_back(i);
+      std::vector<int32_t> par(static_cast<size_t>(nt)), sz(static_cast<size_t>(nt), 1);
+      std::iota(par.begin(), par.end(), 0);
+      auto find = [&](std::vector<int32_t> &pa, int32_t x) {
+        while (pa[size_t(x)] != x) { pa[size_t(x)] = pa[size_t(pa[size_t(x)])]; x = pa[size_t(x)]; }
+        return x;
+      };
+      int32_t l = 0, ph = 0;
+      while (l < L) {
+        int32_t l1 = l, maxc = 1;
+        int64_t nns = 0;  // rows in components of two or more
+        while (l1 < L) {
+          std::vector<int32_t> par2 = par, sz2 = sz;
+          int32_t maxc2 = maxc;
+          for (int32_t i : bylev[size_t(l1)])
+            for (int64_t p = predp[size_t(i)]; p < predp[size_t(i) + 1]; ++p) {
+              const int32_t j = predi[size_t(p)];
+              if (lev[size_t(j)] < l) continue;  // earlier phase
+              int32_t a = find(par2, i - r0), b = find(par2, j - r0);
+              if (a == b) continue;
+              if (sz2[size_t(a)] < sz2[size_t(b)]) std::swap(a, b);
+              par2[size_t(b)] = a;
+              sz2[size_t(a)] += sz2[size_t(b)];
+              maxc2 = std::max(maxc2, sz2[size_t(a)]);
+            }
+          int64_t nns2 = 0;
+          if (maxc2 > 1) {
+            for (int32_t q = l; q <= l1; ++q)
+              for (int32_t i : bylev[size_t(q)]) nns2 += sz2[size_t(find(par2, i - r0))] > 1;
+          }
+          if (l1 > l && (maxc2 > max_block || nns2 > kMaxPhaseBlockRows)) break;
+          par.swap(par2);
+          sz.swap(sz2);
+          maxc = maxc2;
+          nns = nns2;
+          ++l1;
+        }
+        (void)nns;
+        for (int32_t q = l; q < l1; ++q)
+          for (int32_t i : bylev[size_t(q)]) {
+            const int32_t root = find(par, i - r0);
+            rphase[size_t(i)] = ph;
+            rcomp[size_t(i)] = root;
+            rcsize[size_t(i)] = sz[size_t(root)];
+          }
+        ++ph;
+        l = l1;
+      }
+      task_nph[size_t(t)] = ph;
+      std::vector<int32_t> rows(static_cast<size_t>(nt));
+      std::iota(rows.begin(), rows.end(), r0);
+      std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) {
+        if (rphase[size_t(a)] != rphase[size_t(b)]) return rphase[size_t(a)] < rphase[size_t(b)];
+        const bool sa = rcsize[size_t(a)] == 1, sb = rcsize[size_t(b)] == 1;
+        if (sa != sb) return !sa;  // components of two or more first, singletons last
+        if (rcomp[size_t(a)] != rcomp[size_t(b)]) return rcomp[size_t(a)] < rcomp[size_t(b)];
+        return lev[size_t(a)] < lev[size_t(b)];
+      });
+      for (int32_t k = 0; k < nt; ++k) newpos[size_t(rows[size_t(k)])] = r0 + k;
     }
-    H.perm.swap(perm2);
-    H.D.swap(D2);
-    rphase.swap(ph2);
-    rcomp.swap(cs2);
-    rcsize.swap(cz2);
+  };
+  // Relabel row i -> np[i]: the factor (Cp/Ci/Cx by columns), D, the order and the per-row
+  // phase data follow.
+  auto relabel = [&](const std::vector<int32_t> &np) {
+    std::vector<int64_t> Cp2(size_t(m) + 1, 0);
+    std::vector<int32_t> Ci2(static_cast<size_t>(nnzL));
+    std::vector<double> Cx2(static_cast<size_t>(nnzL));
+    for (int32_t j = 0; j < m; ++j) Cp2[size_t(np[size_t(j)]) + 1] = Cp[size_t(j) + 1] - Cp[size_t(j)];
+    for (int32_t j = 0; j < m; ++j) Cp2[size_t(j) + 1] += Cp2[size_t(j)];
+    for (int32_t j = 0; j < m; ++j) {
+      int64_t q = Cp2[size_t(np[size_t(j)])];
+      for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p, ++q) {
+        Ci2[size_t(q)] = np[size_t(Ci[size_t(p)])];
+        Cx2[size_t(q)] = Cx[size_t(p)];
+      }
+    }
+    Cp.swap(Cp2);
+    Ci.swap(Ci2);
+    Cx.swap(Cx2);
+    auto permute = [&](auto &v) {
+      auto w = v;
+      for (int32_t i = 0; i < m; ++i) w[size_t(np[size_t(i)])] = v[size_t(i)];
+      v.swap(w);
+    };
+    permute(H.perm);
+    permute(Dn);
+    permute(rphase);
+    permute(rcomp);
+    permute(rcsize);
     for (int32_t k = 0; k < m; ++k) H.pinv[size_t(H.perm[size_t(k)])] = k;
+  };
+  set_row_task();
+  partition();
+  relabel(newpos);
+  if (allow_split && ntask > 1) {
+    // Component starts, and the factor entries every row gathers from outside its component.
+    std::vector<int32_t> cst(static_cast<size_t>(m));
+    for (int32_t i = 0; i < m; ++i)
+      cst[size_t(i)] = (i > 0 && row_task[size_t(i)] == row_task[size_t(i - 1)] &&
+                        rphase[size_t(i)] == rphase[size_t(i - 1)] && rcsize[size_t(i)] > 1 &&
+                        rcomp[size_t(i)] == rcomp[size_t(i - 1)])
+                           ? cst[size_t(i - 1)]
+                           : i;
+    std::vector<int64_t> gext(static_cast<size_t>(m), 0);
+    for (int32_t j = 0; j < m; ++j)
+      for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p)
+        if (j < cst[size_t(Ci[size_t(p)])]) gext[size_t(Ci[size_t(p)])]++;
+    // Cost of the rows [a, b) (whole components): packed inverses plus gathered entries.
+    auto rows_cost = [&](int32_t a, int32_t b) {
+      int64_t e = 0;
+      for (int32_t i = a; i < b; ++i) {
+        e += gext[size_t(i)];
+        if (cst[size_t(i)] == i && rcsize[size_t(i)] > 1) e += int64_t(rcsize[size_t(i)]) * (rcsize[size_t(i)] + 1) / 2;
+      }
+      return double(e) / kSolveThreads;
+    };
+    const double phase_overhead = 4.0;  // per-phase cost of the barriers, in entries per thread
+    std::vector<double> tcost(static_cast<size_t>(ntask), 0.0), p0cost(static_cast<size_t>(ntask), 0.0);
+    std::vector<int32_t> p0end(static_cast<size_t>(ntask));
+    std::vector<double> group_costs;
+    for (int32_t t = 0; t < ntask; ++t) {
+      const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];
+      for (int32_t a = r0; a < r1;) {
+        int32_t b = a;
+        while (b < r1 && rphase[size_t(b)] == rphase[size_t(a)]) ++b;
+        const double c = rows_cost(a, b) + phase_overhead;
+        if (a == r0) { p0end[size_t(t)] = b; p0cost[size_t(t)] = c; }
+        tcost[size_t(t)] += c;
+        a = b;
+      }
+      if (rclass[size_t(H.perm[size_t(r0)])] == 0) group_costs.push_back(tcost[size_t(t)]);
+    }
+    double ref = 0.0;
+    if (!group_costs.empty()) {
+      std::nth_element(group_costs.begin(), group_costs.begin() + group_costs.size() / 2, group_costs.end());
+      ref = group_costs[group_costs.size() / 2];
+    }
+    // Plan: parts of the first phase (cut at component boundaries, balanced by cost) and the
+    // task that receives the later phases (-1: they stay a task of their own).
+    std::vector<std::vector<int32_t>> cuts(static_cast<size_t>(ntask));
+    std::vector<int32_t> dest(static_cast<size_t>(ntask), -1);
+    std::vector<std::vector<int32_t>> front(static_cast<size_t>(ntask));
+    bool any = false;
+    for (int32_t t = 0; ref > 0.0 && t < ntask; ++t) {
+      const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];
+      const int32_t o0 = H.perm[size_t(r0)];
+      if (rclass[size_t(o0)] != 0 || tcost[size_t(t)] <= 1.5 * ref) continue;
+      const int32_t nparts = std::min<int32_t>(8, std::max<int32_t>(1, int32_t(std::ceil(p0cost[size_t(t)] / ref))));
+      if (nparts == 1 && p0end[size_t(t)] == r1) continue;
+      const double total = rows_cost(r0, p0end[size_t(t)]);
+      double acc = 0.0;
+      int32_t k = 1;
+      for (int32_t i = r0; i < p0end[size_t(t)];) {
+        int32_t c1 = i + 1;
+        while (c1 < p0end[size_t(t)] && cst[size_t(c1)] == i) ++c1;
+        acc += rows_cost(i, c1);
+        i = c1;
+        if (k < nparts && i < p0end[size_t(t)] && acc >= total * k / nparts) { cuts[size_t(t)].push_back(i); ++k; }
+      }
+      cuts[size_t(t)].push_back(p0end[size_t(t)]);
+      if (p0end[size_t(t)] < r1) {
+        const int32_t g = rkey[size_t(o0)];
+        for (int32_t u = t + 1; u < ntask; ++u) {
+          const int32_t ou = H.perm[size_t(H.task_r0[size_t(u)])];
+          if (rclass[size_t(ou)] == 1 && (rkey[size_t(ou)] == g || rkey[size_t(ou)] == g - 1)) { dest[size_t(t)] = u; break; }
+        }
+        if (dest[size_t(t)] >= 0)
+          for (int32_t r = p0end[size_t(t)]; r < r1; ++r) front[size_t(dest[size_t(t)])].push_back(r);
+      }
+      any = true;
+    }
+    if (any) {
+      std::vector<int32_t> ord, nr0, nr1;
+      ord.reserve(size_t(m));
+      for (int32_t t = 0; t < ntask; ++t) {
+        const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];
+        if (!cuts[size_t(t)].empty()) {
+          int32_t a = r0;
+          for (int32_t c : cuts[size_t(t)]) {
+            nr0.push_back(int32_t(ord.size()));
+            for (int32_t r = a; r < c; ++r) ord.push_back(r);
+            nr1.push_back(int32_t(ord.size()));
+            a = c;
+          }
+          if (dest[size_t(t)] < 0 && a < r1) {
+            nr0.push_back(int32_t(ord.size()));
+            for (int32_t r = a; r < r1; ++r) ord.push_back(r);
+            nr1.push_back(int32_t(ord.size()));
+          }
+        } else {
+          nr0.push_back(int32_t(ord.size()));
+          for (int32_t r : front[size_t(t)]) ord.push_back(r);
+          for (int32_t r = r0; r < r1; ++r) ord.push_back(r);
+          nr1.push_back(int32_t(ord.size()));
+        }
+      }
+      std::vector<int32_t> np(static_cast<size_t>(m));
+      for (int32_t k = 0; k < m; ++k) np[size_t(ord[size_t(k)])] = k;
+      bool topo = int32_t(ord.size()) == m;
+      for (int32_t j = 0; topo && j < m; ++j)
+        for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p)
+          if (np[size_t(Ci[size_t(p)])] <= np[size_t(j)]) { topo = false; break; }
+      if (topo) {  // else the split would need a refactorization: keep the tasks as they are
+        relabel(np);
+        H.task_r0.swap(nr0);
+        H.task_r1.swap(nr1);
+        set_row_task();
+        partition();
+        relabel(newpos);
+      }
+    }
   }
-  // CSR of L (rows ascending columns) and of L^T, in the relabeled order
+  H.D = Dn;
+  // CSR of L (rows ascending columns) and of L^T, in the final order
   H.Lrp.assign(size_t(m) + 1, 0);
   H.Urp.assign(size_t(m) + 1, 0);
   for (int32_t j = 0; j < m; ++j)
     for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
-      H.Lrp[size_t(newpos[size_t(Ci[size_t(p)])]) + 1]++;
-      H.Urp[size_t(newpos[size_t(j)]) + 1]++;
+      H.Lrp[size_t(Ci[size_t(p)]) + 1]++;
+      H.Urp[size_t(j) + 1]++;
     }
   for (int32_t i = 0; i < m; ++i) { H.Lrp[size_t(i) + 1] += H.Lrp[size_t(i)]; H.Urp[size_t(i) + 1] += H.Urp[size_t(i)]; }
   H.Lci.resize(size_t(nnzL)); H.Lv.resize(size_t(nnzL));
@@ -413,7 +561,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     std::vector<int64_t> fl(H.Lrp.begin(), H.Lrp.end() - 1), fu(H.Urp.begin(), H.Urp.end() - 1);
     for (int32_t j = 0; j < m; ++j)
       for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
-        const int32_t ni = newpos[size_t(Ci[size_t(p)])], nj = newpos[size_t(j)];
+        const int32_t ni = Ci[size_t(p)], nj = j;
         const int64_t ql = fl[size_t(ni)]++, qu = fu[size_t(nj)]++;
         H.Lci[size_t(ql)] = nj; H.Lv[size_t(ql)] = Cx[size_t(p)];
         H.Uci[size_t(qu)] = ni; H.Uv[size_t(qu)] = Cx[size_t(p)];
@@ -568,6 +716,31 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     H.task_sg.push_back(std::min<int32_t>(16, lanes_for(seg_max[size_t(t)])));
   }
 
+  // ---------------------------------------------------------------- task-local staging
+  H.task_pin.assign(size_t(ntask) + 1, 0);
+  H.task_xoff.assign(size_t(ntask) + 1, 0);
+  H.task_inl.assign(size_t(ntask), 0);
+  std::vector<int32_t> ph_task(H.ph_a.size());
+  for (int32_t t = 0; t < ntask; ++t) {
+    const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)], nt = r1 - r0;
+    for (int32_t ph = H.task_ph0[size_t(t)]; ph < H.task_ph1[size_t(t)]; ++ph) ph_task[size_t(ph)] = t;
+    H.task_pin[size_t(t)] = int32_t(H.sptr[size_t(r0)]);
+    H.task_pin[size_t(t) + 1] = int32_t(H.sptr[size_t(r1)]);
+    std::vector<int32_t> ext;
+    for (int32_t i = r0; i < r1; ++i)
+      for (int64_t p = H.Ubeg[size_t(i)]; p < H.Urp[size_t(i) + 1]; ++p)
+        if (H.Uci[size_t(p)] >= r1) ext.push_back(H.Uci[size_t(p)]);
+    std::sort(ext.begin(), ext.end());
+    ext.erase(std::unique(ext.begin(), ext.end()), ext.end());
+    const int64_t stage = int64_t(nt) + std::max<int64_t>(H.sptr[size_t(r1)] - H.sptr[size_t(r0)], int64_t(ext.size()));
+    if (stage <= kMaxLdsTaskRows) {
+      H.task_inl[size_t(t)] = 1;
+      H.max_task_stage = std::max(H.max_task_stage, int32_t(stage));
+      H.task_xrow.insert(H.task_xrow.end(), ext.begin(), ext.end());
+    }
+    H.task_xoff[size_t(t) + 1] = int64_t(H.task_xrow.size());
+  }
+
   // ---------------------------------------------------------------- phase streams
   // Every phase is solved from four entry streams.  The entries of the phase's rows (in row
   // order; a row with no entry gets one zero entry) are cut into Tp equal slices of K
@@ -577,26 +750,39 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   // slice order.  An entry is a value and an index; the index of the last entry of a row
   // carries kLastFlag.  s_ra holds per thread the phase-relative row of its first entry,
   // with kStartFlag when that entry starts the row.  Streams:
-  //   fg: forward gather, the row's pushed partial sums (index s | kPartFlag, value 1) and
-  //       L(i, j) for own-task columns j of earlier phases (index j);
+  //   fg: forward gather, the row's pushed partial sums (value 1) and L(i, j) for own-task
+  //       columns j of earlier phases;
   //   fi: forward inverse, row i of its component's inverse (index: position in the phase
   //       right-hand side buffer);
-  //   bg: backward gather, L(i, j) for rows i after the row's component (index i);
+  //   bg: backward gather, L(i, j) for rows i after the row's component;
   //   bi: backward inverse, column j of its component's inverse (index as fi).
+  // fg / bg indices are task-local for a task staged in LDS (see task_inl), else the row
+  // (and s | kPartFlag for the partial sum s).
   {
     const int32_t T = kSolveThreads;
     auto build = [&](int32_t ph, int32_t rbeg, int32_t rend, int kind) {
-      const int32_t pad_idx = (kind == 0 || kind == 2) ? rbeg : 0;
+      const int32_t t = ph_task[size_t(ph)], r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];
+      const bool inl = H.task_inl[size_t(t)] != 0;
+      const int32_t *xr = H.task_xrow.data() + H.task_xoff[size_t(t)];
+      const int64_t nx = H.task_xoff[size_t(t) + 1] - H.task_xoff[size_t(t)];
+      auto fidx = [&](int32_t j) { return inl ? j - r0 : j; };
+      auto bidx = [&](int32_t i) {
+        if (!inl) return i;
+        if (i < r1) return i - r0;
+        return (r1 - r0) + int32_t(std::lower_bound(xr, xr + nx, i) - xr);
+      };
+      const int32_t pad_idx = (kind == 0 || kind == 2) ? (inl ? rbeg - r0 : rbeg) : 0;
       std::vector<std::pair<int32_t, double>> ent;  // the whole phase, rows in order
       std::vector<int32_t> erow;                    // phase-relative row of each entry
       std::vector<char> efirst;                     // entry starts its row
       for (int32_t i = rbeg; i < rend; ++i) {
         const size_t e0 = ent.size();
         if (kind == 0) {
-          for (int64_t q = H.sptr[size_t(i)]; q < H.sptr[size_t(i) + 1]; ++q) ent.emplace_back(int32_t(q) | kPartFlag, 1.0);
-          for (int64_t p = H.Lin[size_t(i)]; p < H.Lend[size_t(i)]; ++p) ent.emplace_back(H.Lci[size_t(p)], H.Lv[size_t(p)]);
+          for (int64_t q = H.sptr[size_t(i)]; q < H.sptr[size_t(i) + 1]; ++q)
+            ent.emplace_back(inl ? (r1 - r0) + int32_t(q - H.task_pin[size_t(t)]) : (int32_t(q) | kPartFlag), 1.0);
+          for (int64_t p = H.Lin[size_t(i)]; p < H.Lend[size_t(i)]; ++p) ent.emplace_back(fidx(H.Lci[size_t(p)]), H.Lv[size_t(p)]);
         } else if (kind == 2) {
-          for (int64_t p = H.Ubeg[size_t(i)]; p < H.Urp[size_t(i) + 1]; ++p) ent.emplace_back(H.Uci[size_t(p)], H.Uv[size_t(p)]);
+          for (int64_t p = H.Ubeg[size_t(i)]; p < H.Urp[size_t(i) + 1]; ++p) ent.emplace_back(bidx(H.Uci[size_t(p)]), H.Uv[size_t(p)]);
         } else {
           const int32_t cs = H.rcs[size_t(i)], cn = H.rce[size_t(i)] - cs, kk = i - cs;
           const int32_t base = cs - H.ph_a[size_t(ph)];

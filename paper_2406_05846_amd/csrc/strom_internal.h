@@ -76,6 +76,16 @@ struct HostAnalysis {
   std::vector<int32_t> s_K[4];
   std::vector<int32_t> s_T[4];   // thread stride of the phase's layout
   std::vector<int32_t> s_ra[4];
+  // Task-local index space of a task whose values are staged in LDS (task_inl): local index
+  // k < nt is row r0 + k; in the forward streams nt + q is the pushed partial sum
+  // task_pin[t] + q (the task's rows sum the segments [task_pin[t], task_pin[t + 1])); in the
+  // backward streams nt + q is the value of row task_xrow[task_xoff[t] + q] of a later task.
+  // Other tasks index rows and partial sums (kPartFlag) globally.
+  std::vector<int32_t> task_pin;
+  std::vector<int64_t> task_xoff;
+  std::vector<int32_t> task_xrow;
+  std::vector<char> task_inl;
+  int32_t max_task_stage = 0;  // max over LDS tasks of nt + max(partial sums, later-task rows)
   // Launch schedule: task ids grouped by dependency depth.
   std::vector<int32_t> fwd_order, fwd_gptr, bwd_order, bwd_gptr;
   int32_t max_task_rows = 0;
