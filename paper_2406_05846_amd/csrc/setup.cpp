@@ -717,6 +717,11 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   }
 
   // ---------------------------------------------------------------- task-local staging
+  int64_t max_stage = kMaxLdsTaskRows;  // STROM_STAGE_ROWS lowers it (0: every task in place)
+  if (const char *ev = std::getenv("STROM_STAGE_ROWS")) {
+    const long v = std::strtol(ev, nullptr, 10);
+    if (v >= 0 && v < max_stage) max_stage = v;
+  }
   H.task_pin.assign(size_t(ntask) + 1, 0);
   H.task_xoff.assign(size_t(ntask) + 1, 0);
   H.task_inl.assign(size_t(ntask), 0);
@@ -733,7 +738,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     std::sort(ext.begin(), ext.end());
     ext.erase(std::unique(ext.begin(), ext.end()), ext.end());
     const int64_t stage = int64_t(nt) + std::max<int64_t>(H.sptr[size_t(r1)] - H.sptr[size_t(r0)], int64_t(ext.size()));
-    if (stage <= kMaxLdsTaskRows) {
+    if (stage <= max_stage) {
       H.task_inl[size_t(t)] = 1;
       H.max_task_stage = std::max(H.max_task_stage, int32_t(stage));
       H.task_xrow.insert(H.task_xrow.end(), ext.begin(), ext.end());

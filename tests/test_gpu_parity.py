@@ -162,6 +162,29 @@ def test_cartpole_full_size_iterates(S, ctx, orc):
     inst.close()
 
 
+@pytest.mark.parametrize("env", [
+    {"STROM_STAGE_ROWS": "0"},  # every task solved in place in global memory
+    {"STROM_TASK_SPLIT": "0", "STROM_STAGE_ROWS": "600", "STROM_BLOCK_ROWS": "32"},  # mixed, more phases
+])
+def test_solve_schedule_variants_iterates(S, ctx, orc, monkeypatch, env):
+    """Cart-pole N = 10 under other solve schedules (the analysis reads these variables):
+    five iterations with a fixed sigma against the oracle."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    prm = [0.1, 0.2, 0.5, 0.3]
+    osdp = orc.relax(2, 10, prm)
+    prob = S.generate(2, 10, prm)
+    inst = S.Instance(ctx, prob, _opts(S, sigma_every=0, kkt_every=1, tol=0.0))
+    inst.step(5)
+    Xg, yg, Sg = inst.get_iterate()
+    r = orc.admm_solve(osdp, maxiter=5, tol=0.0, sigma_every=0)
+    assert np.linalg.norm(Xg - r["X"]) / max(1.0, np.linalg.norm(r["X"])) <= 1e-9
+    assert np.linalg.norm(Sg - r["S"]) / max(1.0, np.linalg.norm(r["S"])) <= 1e-9
+    aty, atyo = osdp.A.T @ yg, osdp.A.T @ r["y"]
+    assert np.linalg.norm(aty - atyo) / max(1.0, np.linalg.norm(atyo)) <= 1e-9
+    inst.close()
+
+
 def _converged_ref(seed):
     """Oracle optimum of the pendulum workload (N = 10) at eta <= 1e-8, written by
     tests/golden/make_converged_refs.py."""

@@ -1,0 +1,68 @@
+"""The device solve schedule, executed on the CPU (no GPU needed).
+
+tests/native/solve_schedule_sim.cpp runs the library's host analysis (row order, FP64 LDL^T,
+task split, phases, component inverses, push segments, task-local staging, phase streams,
+launch groups) and then walks the schedule exactly as the solve kernels read it.  Its
+y = (eps I + A A^*)^{-1} r must match the oracle's own sparse factorization: a schedule that
+drops, doubles or misindexes a stream entry, or runs a task before one it depends on, fails
+here.  Every case runs with the task split on and off and with every task staged in LDS,
+some staged, and none (the in-place kernel path).
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+CASES = [  # (family, N, parameters): pendulum, cart-pole, car (the split applies to the first two)
+    (1, 10, [0.5, 0.0]),
+    (2, 10, [0.1, 0.2, 0.5, 0.3]),
+    (4, 4, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
+]
+VARIANTS = [  # environment of the analysis
+    {},
+    {"STROM_TASK_SPLIT": "0"},
+    {"STROM_STAGE_ROWS": "0"},
+    {"STROM_STAGE_ROWS": "600", "STROM_BLOCK_ROWS": "32"},
+]
+
+
+@pytest.fixture(scope="module")
+def sim(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("sim") / "solve_schedule_sim")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-o", exe,
+                    os.path.join(ROOT, "tests", "native", "solve_schedule_sim.cpp"),
+                    os.path.join(ROOT, "paper_2406_05846_amd", "csrc", "setup.cpp")], check=True)
+    return exe
+
+
+@pytest.mark.parametrize("fam,N,prm", CASES)
+def test_schedule_solves_the_system(sim, orc, tmp_path, fam, N, prm):
+    p = orc.relax(fam, N, prm)
+    A = p.A.tocsr()
+    rng = np.random.default_rng(fam * 100 + N)
+    r = A @ rng.standard_normal(p.nsvec)
+    F = orc.LDL(p)
+    yo = F.solve(r)
+    for name, arr in [("bs", np.asarray(p.bsize, dtype=np.int32)), ("rp", A.indptr.astype(np.int64)),
+                      ("ci", A.indices.astype(np.int32)), ("av", A.data.astype(np.float64)), ("r", r)]:
+        arr.tofile(str(tmp_path / name))
+    tasks = {}
+    for env in VARIANTS:
+        out = subprocess.run([sim, str(tmp_path)], env={**os.environ, **env}, capture_output=True, text=True)
+        assert out.returncode == 0, (env, out.stdout, out.stderr)
+        fields = out.stdout.split()
+        tasks[tuple(sorted(env.items()))] = dict(zip(fields[0::2], map(int, fields[1::2])))
+        y = np.fromfile(str(tmp_path / "y"))
+        resid = A @ (A.T @ y) + F.eps * y - r
+        assert np.linalg.norm(resid) <= 1e-12 * np.linalg.norm(r), env
+        # same system, two factorizations in different orders: agree to rounding
+        assert np.linalg.norm(A.T @ (y - yo)) <= 1e-10 * np.linalg.norm(A.T @ yo), env
+    base = tasks[()]
+    assert base["staged"] == base["tasks"]
+    assert tasks[(("STROM_STAGE_ROWS", "0"),)]["staged"] == 0
+    if fam in (1, 2):  # the first clique carries the initial-state rows: its task is split
+        assert base["tasks"] > tasks[(("STROM_TASK_SPLIT", "0"),)]["tasks"]
+        assert base["fwd_groups"] == tasks[(("STROM_TASK_SPLIT", "0"),)]["fwd_groups"]
