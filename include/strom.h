@@ -165,8 +165,8 @@ strom_status strom_sdp_sizes(strom_sdp *sdp, int64_t *n_svec, int32_t *m, int64_
  * reconstruction).  Block k is n_dev[k] x n_dev[k], column-major, starting at element
  * offset_dev[k] of in_dev / out_dev; in and out may alias.  n_dev, offset_dev, in_dev and
  * out_dev are device pointers; max_n (host) bounds every n_dev[k]; one block and its
- * eigenvectors must fit the LDS of one workgroup (160 KiB on gfx950: max_n <= 111 for F64,
- * <= 122 for F32 -- the eigenvectors are accumulated in double in both), else E_INVAL.  A block with n_dev[k] <= 0 or > max_n makes the call
+ * eigenvectors must fit the LDS of one workgroup (160 KiB on gfx950: max_n <= 114 for F64,
+ * <= 125 for F32 -- the eigenvectors are accumulated in double in both), else E_INVAL.  A block with n_dev[k] <= 0 or > max_n makes the call
  * return E_INVAL (other blocks are still written).  dtype selects double or float data.
  * Only the upper triangle of each input block is read; the output is exactly symmetric. */
 strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblocks, int32_t max_n,

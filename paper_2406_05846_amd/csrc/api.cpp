@@ -267,7 +267,8 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   int64_t qtot = 0;
   for (int32_t k = 0; k < P->nblocks; ++k) {
     qoff[size_t(k)] = qtot;
-    qtot += int64_t(H.bsize[size_t(k)]) * H.bsize[size_t(k)];
+    const int64_t nb = H.bsize[size_t(k)];
+    qtot += nb * (nb + (nb & 1));  // eigenvectors n x (n rounded up to even) of the projection
   }
   const size_t oQ = ar.reserve<double>(size_t(qtot)), oQoff = ar.reserve<int64_t>(size_t(P->nblocks));
   s->arena_bytes = ar.bytes;

@@ -2,17 +2,25 @@
 // projection of the paper's Sec. "GPU Speedup": eigendecomposition, negative eigenvalues set
 // to zero, reconstruction), one workgroup per block with the block resident in LDS.
 //
-// Eigensolver: cyclic Jacobi in the round-robin parallel ordering.  In one round the n/2
-// disjoint pairs are rotated together, A <- J^T A J; the new value of every 2x2 block
-// (pair P1 x pair P2) depends only on its own four old entries, so the 2x2 blocks of the
-// packed upper triangle are updated in parallel with no barrier inside the round.  Rotation
+// Eigensolver: cyclic Jacobi in the round-robin (circle) parallel ordering.  A block of size n
+// is padded to an even size nn with a zero dummy index when n is odd (its rotations are the
+// identity, so it stays zero and its eigenvalue is 0).  The matrix is kept in *position*
+// order: in every round the rotations pair positions (2k, 2k + 1) -- slot k -- and after the
+// round the data moves by the circle permutation pos_next, which is the same in every round.
+// So a thread rotates the same 2x2 block (slot I x slot J) at the same LDS addresses in every
+// round and writes its four results to fixed, precomputed places: there is no index
+// arithmetic per round.  The 2x2 blocks of the upper triangle are stored as four arrays (entry
+// (p,p), (p,q), (q,p), (q,q) of every block), so the loads of a wave are contiguous.  The
+// eigenvectors stay in logical order (column i belongs to index i; position x holds index
+// logical_index(x, r) in round r), rotated in place one round late while the first wave
+// computes the next rotation parameters.  Rotation
 // parameters are computed in double for both storage types; the matrix is held in T (double,
 // or float for the reduced-precision form); eigenvectors, norms and the reconstruction are
 // double.
 //
 // Warm start (ADMM step): the eigenvectors of the previous call on the same block are kept
 // in HBM; the sweeps start from A = Q^T X_b Q and V = Q, which is nearly diagonal once the
-// iteration settles, so one to three sweeps replace the eight to ten of a cold start.
+// iteration settles, so a few sweeps replace the eight to ten of a cold start.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -22,6 +30,8 @@
 
 namespace strom {
 namespace dev {
+
+constexpr size_t kLdsCap = 160 * 1024;  // LDS of one workgroup on gfx950
 
 __device__ inline int pidx(int i, int j) {  // packed upper triangle, by columns
   if (i > j) { const int t = i; i = j; j = t; }
@@ -35,16 +45,31 @@ __device__ inline void tri_ij(int k, int &i, int &j) {  // k -> (i <= j) of the 
   i = k - j * (j + 1) / 2;
 }
 
-// Pair k of round r of the circle schedule over nn (even) slots, mm = nn - 1.
-__device__ inline void rr_pair(int r, int k, int mm, int &p, int &q) {
-  if (k == 0) { p = r; q = mm; }
-  else {
-    p = r + k;
-    if (p >= mm) p -= mm;
-    q = r - k;
-    if (q < 0) q += mm;
+// Position of the data at position x after one round of the circle ordering over np2 slots:
+// the first halves of the slots move down one slot, the second halves up one slot, with the
+// turns at both ends; the second half of slot 0 stays.
+__host__ __device__ inline int pos_next(int x, int np2) {
+  if (np2 == 1) return x;
+  const int k = x >> 1;
+  if ((x & 1) == 0) return k >= 1 ? x - 2 : 3;
+  if (k == 0) return 1;
+  return k < np2 - 1 ? x + 2 : x - 1;
+}
+
+__device__ inline int bidx(int I, int J) { return J * (J + 1) / 2 + I; }  // block (I <= J)
+
+// Index held by position x in round r (0 <= r < mm = nn - 1) of the circle ordering: slot k
+// pairs indices (r + k, r - k) mod mm, slot 0 pairs (r, mm).  In round 0, position x holds
+// index logical_index(x, 0); the dummy index of an odd block (mm) stays at position 1.
+__device__ inline int logical_index(int x, int r, int mm) {
+  const int k = x >> 1;
+  if ((x & 1) == 0) {
+    const int i = r + k;
+    return i >= mm ? i - mm : i;
   }
-  if (p > q) { const int t = p; p = q; q = t; }
+  if (k == 0) return mm;
+  const int i = r - k;
+  return i < 0 ? i + mm : i;
 }
 
 template <typename T>
@@ -60,107 +85,134 @@ struct JacobiTol<float> {
   static constexpr double skip_rel = 1e-9;
 };
 
-// LDS: V (n*n doubles, column-major) | red (nthreads doubles) | rotd (two buffers of 2 doubles
-//      per pair: c, s) | A (packed upper triangle, T) | rot (two buffers of 4 T per pair: c, s,
-//      new a_pp, new a_qq) | sel (n + 4 ints), every region 32-byte aligned.
+// LDS: V (n x nn doubles, column-major, column = index) | red (16 doubles) | rotd (two
+//      buffers of (c, s) doubles per slot) | A (nbuf buffers of four arrays of nblk T) | rot
+//      ((c, s, new a_pp, new a_qq) T per slot) | lam (nn doubles) | sel (nn + 4 ints), every
+//      region 32-byte aligned.  nbuf = 2 (a round writes the other buffer) when that fits,
+//      else 1 (one more barrier per round).
 struct Layout {
-  size_t red, rotd, A, rot, sel, total;
+  size_t red, rotd, A, rot, lam, sel, total;
 };
 
 __host__ __device__ inline size_t align32(size_t x) { return (x + 31) & ~(size_t)31; }
 
-__host__ __device__ inline Layout lds_layout(int n, int nthreads, size_t tsize) {
-  const size_t np2 = (size_t)(n + 1) / 2, npk = (size_t)n * (n + 1) / 2;
+__host__ __device__ inline Layout lds_layout(int n, size_t tsize, int nbuf) {
+  const size_t nn = (size_t)n + (n & 1), np2 = nn / 2, nblk = np2 * (np2 + 1) / 2;
   Layout L;
-  L.red = align32(8 * (size_t)n * n);
-  L.rotd = align32(L.red + 8 * (size_t)nthreads);
+  L.red = align32(8 * (size_t)n * nn);
+  L.rotd = align32(L.red + 8 * 16);
   L.A = align32(L.rotd + 2 * 16 * np2);
-  L.rot = align32(L.A + tsize * npk);
-  L.sel = align32(L.rot + 2 * 4 * tsize * np2);
-  L.total = align32(L.sel + 4 * ((size_t)n + 4));
+  L.rot = align32(L.A + (size_t)nbuf * 4 * tsize * nblk);
+  L.lam = align32(L.rot + 4 * tsize * np2);
+  L.sel = align32(L.lam + 8 * nn);
+  L.total = align32(L.sel + 4 * (nn + 4));
   return L;
 }
 
-template <typename T>
-inline size_t lds_bytes_t(int n, int nthreads) {
-  return lds_layout(n, nthreads, sizeof(T)).total;
+// LDS of a launch whose largest block has size n: double-buffered if that fits.
+inline size_t lds_bytes_for(int n, size_t tsize) {
+  const size_t two = lds_layout(n, tsize, 2).total;
+  return two <= kLdsCap ? two : lds_layout(n, tsize, 1).total;
 }
 
 struct Smem {
-  double *V, *red, *rotd;
+  double *V, *red, *rotd, *lam;
   void *A, *rot;
   int *sel;
+  int nbuf;
 };
 
 template <typename T>
-__device__ inline Smem carve(unsigned char *base, int n) {
-  const Layout L = lds_layout(n, blockDim.x, sizeof(T));
+__device__ inline Smem carve(unsigned char *base, int n, size_t lds_cap) {
+  const int nbuf = lds_layout(n, sizeof(T), 2).total <= lds_cap ? 2 : 1;
+  const Layout L = lds_layout(n, sizeof(T), nbuf);
   Smem s;
   s.V = reinterpret_cast<double *>(base);
   s.red = reinterpret_cast<double *>(base + L.red);
   s.rotd = reinterpret_cast<double *>(base + L.rotd);
   s.A = base + L.A;
   s.rot = base + L.rot;
+  s.lam = reinterpret_cast<double *>(base + L.lam);
   s.sel = reinterpret_cast<int *>(base + L.sel);
+  s.nbuf = nbuf;
   return s;
 }
 
+// Sum over the workgroup in a fixed order (wave sums, then the waves in turn).
 __device__ inline double wg_sum(double v, double *red) {
-  const int tid = threadIdx.x, nth = blockDim.x;
-  red[tid] = v;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int nw = blockDim.x >> 6;
+  __syncthreads();  // red may still be read by the previous call
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = nth / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < nw; ++w) r += red[w];
   return r;
 }
 
-// A <- Q^T X Q (packed upper triangle) with Q = V (LDS) and X the svec block at xs (global).
-// Each thread forms 4 entries of a column of W = X Q at a time from X staged through A, then
-// A is overwritten column block by column block once W is complete: W is kept in the block's
-// slot wq of the eigenvector buffer (n*n doubles, free until the eigenvectors are written back).
+// Entry (x, y) of the position-ordered matrix into the block arrays Ab (nblk blocks each).
 template <typename T>
-__device__ __forceinline__ void rotate_into_basis(int n, const double *xs, const double *V, double *wq, T *A) {
+__device__ inline void store_entry(T *Ab, int nblk, int x, int y, T v) {
+  if (x > y) { const int t = x; x = y; y = t; }
+  const int b = bidx(x >> 1, y >> 1);
+  Ab[(((x & 1) << 1) | (y & 1)) * nblk + b] = v;
+  if ((x >> 1) == (y >> 1) && x != y) Ab[2 * nblk + b] = v;  // (q,p) of a diagonal block
+}
+
+template <typename T>
+__device__ inline T diag_entry(const T *Ab, int nblk, int x) {
+  const int k = x >> 1;
+  return Ab[((x & 1) ? 3 : 0) * nblk + bidx(k, k)];
+}
+
+// A <- Q^T X Q in the block arrays Ab (position order of round 0), with Q = V (n x nn, LDS)
+// and X the svec block at xs (global).  X is staged (packed upper triangle, unscaled off-diagonal) in the first buffer;
+// each thread forms 4 entries of a column of W = X Q at a time; W is kept in the block's slot
+// wq of the eigenvector buffer (n x nn doubles, free until the eigenvectors are written back);
+// then A is written from Q and W.
+template <typename T>
+__device__ __forceinline__ void rotate_into_basis(int n, const double *xs, const double *V, double *wq, T *Ab,
+                                                  int nblk) {
   const int tid = threadIdx.x, nth = blockDim.x;
+  const int nn = n + (n & 1);
   const double rs2 = 0.70710678118654752440;
   const int npk = n * (n + 1) / 2;
-  for (int k = tid; k < npk; k += nth) {  // A <- X (packed, unscaled off-diagonal)
+  T *Xs = Ab;
+  for (int k = tid; k < npk; k += nth) {
     int i, j;
     tri_ij(k, i, j);
     const double v = xs[k];
-    A[k] = (T)(i == j ? v : v * rs2);
+    Xs[k] = (T)(i == j ? v : v * rs2);
   }
   __syncthreads();
-  const int nc4 = (n + 3) / 4;
+  const int nc4 = (nn + 3) / 4;
   for (int e = tid; e < n * nc4; e += nth) {  // W(i, 4c .. 4c+3) = sum_k X(i,k) Q(k, 4c ..)
     const int i = e % n, c0 = 4 * (e / n);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    const int c1 = min(c0 + 1, n - 1), c2 = min(c0 + 2, n - 1), c3 = min(c0 + 3, n - 1);
+    const int c1 = min(c0 + 1, nn - 1), c2 = min(c0 + 2, nn - 1), c3 = min(c0 + 3, nn - 1);
     for (int k = 0; k < n; ++k) {
-      const double x = (double)A[pidx(i, k)];
+      const double x = (double)Xs[pidx(i, k)];
       s0 += x * V[c0 * n + k];
       s1 += x * V[c1 * n + k];
       s2 += x * V[c2 * n + k];
       s3 += x * V[c3 * n + k];
     }
     wq[c0 * n + i] = s0;
-    if (c0 + 1 < n) wq[(c0 + 1) * n + i] = s1;
-    if (c0 + 2 < n) wq[(c0 + 2) * n + i] = s2;
-    if (c0 + 3 < n) wq[(c0 + 3) * n + i] = s3;
+    if (c0 + 1 < nn) wq[(c0 + 1) * n + i] = s1;
+    if (c0 + 2 < nn) wq[(c0 + 2) * n + i] = s2;
+    if (c0 + 3 < nn) wq[(c0 + 3) * n + i] = s3;
   }
   __threadfence_block();
   __syncthreads();
-  for (int e = tid; e < npk; e += nth) {  // A(i, j) = sum_k Q(k, i) W(k, j), i <= j
-    int i, j;
-    tri_ij(e, i, j);
-    const double *q = V + i * n;
-    const double *w = wq + j * n;
+  const int mm = nn - 1;
+  for (int e = tid; e < nn * (nn + 1) / 2; e += nth) {  // A(x, y) = sum_k Q(k, i) W(k, j), x <= y
+    int x, y;
+    tri_ij(e, x, y);
+    const double *q = V + logical_index(x, 0, mm) * n;
+    const double *w = wq + logical_index(y, 0, mm) * n;
     double s = 0.0;
     for (int k = 0; k < n; ++k) s += q[k] * w[k];
-    A[e] = (T)s;
+    store_entry<T>(Ab, nblk, x, y, (T)s);
   }
   __syncthreads();
 }
@@ -176,58 +228,71 @@ struct Vec4<float> {
   typedef float4 type;
 };
 
-// New value of the 2x2 block (pair I) x (pair J), I <= J, of round r.
-template <typename T>
-__device__ __forceinline__ void rotate_block(int r, int I, int J, int n, int mm, T *A, const T *rot) {
-  typedef typename Vec4<T>::type V4;
-  int p1, q1;
-  rr_pair(r, I, mm, p1, q1);
-  const V4 ri = reinterpret_cast<const V4 *>(rot)[I];
-  if (I == J) {
-    if (q1 < n) {
-      A[pidx(p1, p1)] = ri.z;
-      A[pidx(q1, q1)] = ri.w;
-      A[pidx(p1, q1)] = T(0);
-    }
-    return;
+// Places of the entries of block (I, J) after one round: index into the block arrays
+// (array * nblk + block) of entry h = (p,p), (p,q), (q,p), (q,q), and a second index (or -1)
+// where the entry lands off the diagonal of a diagonal block (stored twice).  A diagonal block
+// carries its (p,q) entry once: its (q,p) entry gets no place.
+__device__ inline void block_dests(int I, int J, int np2, int nblk, int *d, int *e) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    d[h] = -1;
+    e[h] = -1;
+    if (I < 0 || (I == J && h == 2)) continue;
+    int x = pos_next(2 * I + (h >> 1), np2), y = pos_next(2 * J + (h & 1), np2);
+    if (x > y) { const int t = x; x = y; y = t; }
+    const int b = bidx(x >> 1, y >> 1);
+    d[h] = (((x & 1) << 1) | (y & 1)) * nblk + b;
+    if ((x >> 1) == (y >> 1) && x != y) e[h] = 2 * nblk + b;
   }
-  int p2, q2;
-  rr_pair(r, J, mm, p2, q2);
-  const V4 rj = reinterpret_cast<const V4 *>(rot)[J];
-  const T c1 = ri.x, s1 = ri.y, c2 = rj.x, s2 = rj.y;
-  const bool hq1 = q1 < n, hq2 = q2 < n;
-  const T a = A[pidx(p1, p2)];
-  const T bq = hq2 ? A[pidx(p1, q2)] : T(0);
-  const T cq = hq1 ? A[pidx(q1, p2)] : T(0);
-  const T d = (hq1 && hq2) ? A[pidx(q1, q2)] : T(0);
-  const T ra = c1 * a - s1 * cq, rb = c1 * bq - s1 * d;  // rows p1, q1 rotated
-  const T rc = s1 * a + c1 * cq, rd = s1 * bq + c1 * d;
-  A[pidx(p1, p2)] = c2 * ra - s2 * rb;  // then columns p2, q2
-  if (hq2) A[pidx(p1, q2)] = s2 * ra + c2 * rb;
-  if (hq1) A[pidx(q1, p2)] = c2 * rc - s2 * rd;
-  if (hq1 && hq2) A[pidx(q1, q2)] = s2 * rc + c2 * rd;
 }
 
-// Rotation parameters of every pair of round r from A (threads t0, t0 + stride, ...).
+// New entries of block b = (I, J) for the rotations rot of the current round.
 template <typename T>
-__device__ __forceinline__ void round_rotations(int r, int n, int np2, int mm, double skip, const T *A, T *rot, double *rotd,
-                                       int t0, int stride) {
+__device__ __forceinline__ void rotate_block(int b, int I, int J, int nblk, const T *A, const T *rot, T *o) {
+  typedef typename Vec4<T>::type V4;
+  const V4 ri = reinterpret_cast<const V4 *>(rot)[I];
+  if (I == J) {
+    o[0] = ri.z;
+    o[1] = T(0);
+    o[2] = T(0);
+    o[3] = ri.w;
+    return;
+  }
+  const V4 rj = reinterpret_cast<const V4 *>(rot)[J];
+  const T c1 = ri.x, s1 = ri.y, c2 = rj.x, s2 = rj.y;
+  const T a = A[b], bq = A[nblk + b], cq = A[2 * nblk + b], d = A[3 * nblk + b];
+  const T ra = c1 * a - s1 * cq, rb = c1 * bq - s1 * d;  // rows p1, q1 rotated
+  const T rc = s1 * a + c1 * cq, rd = s1 * bq + c1 * d;
+  o[0] = c2 * ra - s2 * rb;  // then columns p2, q2
+  o[1] = s2 * ra + c2 * rb;
+  o[2] = c2 * rc - s2 * rd;
+  o[3] = s2 * rc + c2 * rd;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_block(T *An, const int *d, const int *e, const T *o) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    if (d[h] >= 0) An[d[h]] = o[h];
+    if (e[h] >= 0) An[e[h]] = o[h];
+  }
+}
+
+// Rotation parameters of every slot from the diagonal blocks of A (threads t0, t0 + stride, ...).
+template <typename T>
+__device__ __forceinline__ void round_rotations(int np2, int nblk, double skip, const T *A, T *rot, double *rotd,
+                                                int t0, int stride) {
   for (int k = t0; k < np2; k += stride) {
-    int p, q;
-    rr_pair(r, k, mm, p, q);
-    double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
-    if (q < n) {
-      const double apq = (double)A[pidx(p, q)], app = (double)A[pidx(p, p)], aqq = (double)A[pidx(q, q)];
-      dp = app;
-      dq = aqq;
-      if (fabs(apq) > skip) {
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        c = 1.0 / sqrt(t * t + 1.0);
-        s = t * c;
-        dp = app - t * apq;
-        dq = aqq + t * apq;
-      }
+    const int bd = bidx(k, k);
+    const double apq = (double)A[nblk + bd], app = (double)A[bd], aqq = (double)A[3 * nblk + bd];
+    double c = 1.0, s = 0.0, dp = app, dq = aqq;
+    if (fabs(apq) > skip) {
+      const double theta = (aqq - app) / (2.0 * apq);
+      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      c = 1.0 / sqrt(t * t + 1.0);
+      s = t * c;
+      dp = app - t * apq;
+      dq = aqq + t * apq;
     }
     typedef typename Vec4<T>::type V4;
     V4 rv;
@@ -240,182 +305,197 @@ __device__ __forceinline__ void round_rotations(int r, int n, int np2, int mm, d
   }
 }
 
-// V <- V J for the rotations rotd of round r: this thread's eigenvector row vrow, pairs
-// vk0, vk0 + vks, ...
-__device__ __forceinline__ void rotate_vectors(int r, int n, int np2, int mm, const double *rotd, double *V, int vrow, int vk0,
-                                      int vks) {
-  for (int k = vk0; k < np2; k += vks) {
-    int p, q;
-    rr_pair(r, k, mm, p, q);
-    if (q >= n) continue;
-    const double2 cs = reinterpret_cast<const double2 *>(rotd)[k];
-    const double c = cs.x, s = cs.y;
-    const double vp = V[vrow + p * n], vq = V[vrow + q * n];
-    V[vrow + p * n] = c * vp - s * vq;
-    V[vrow + q * n] = s * vp + c * vq;
-  }
+// Off-diagonal mass (and with the diagonal: squared Frobenius norm) of block b = (I, J).
+template <typename T>
+__device__ inline double block_mass(const T *A, int nblk, int b, int I, int J, bool with_diag) {
+  const double a = (double)A[b], bq = (double)A[nblk + b], cq = (double)A[2 * nblk + b], d = (double)A[3 * nblk + b];
+  if (I == J) return 2.0 * bq * bq + (with_diag ? a * a + d * d : 0.0);
+  return 2.0 * (a * a + bq * bq + cq * cq + d * d);
 }
 
-// Cyclic Jacobi, two barriers per round.  With enough threads (split), the first wave
-// computes the rotations of round r while the other waves apply those of round r - 1 to the
-// eigenvectors (rot / rotd double-buffered); then all threads rotate the 2x2 blocks of A.
-template <typename T>
-__device__ __forceinline__ void jacobi_eig(int n, T *A, double *V, T *rot, double *rotd, double *red, bool v_ready) {
+// Cyclic Jacobi on the block arrays (buffer 0 on entry, position order of round 0).  Returns
+// the buffer holding the final matrix; rfin = the round (mod mm) whose position order it is in.
+// A round: [rotation parameters (first wave) | in-place eigenvector rotation of the previous
+// round] barrier [2x2 block rotations, stored to the permuted places -- in the other buffer,
+// or after one more barrier when single-buffered] barrier.
+template <typename T, bool BIG>
+__device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *rot, double *rotd, double *red,
+                                          bool v_ready, int &rfin) {
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int np2 = (n + 1) / 2, nn = 2 * np2, mm = nn - 1;
-  const int npk = n * (n + 1) / 2;
-  const int nblk = np2 * (np2 + 1) / 2;  // at most 2 * nth (checked at launch)
-  int I0 = -1, J0 = -1, I1 = -1, J1 = -1;  // this thread's 2x2 blocks, fixed over the rounds
+  const int nn = n + (n & 1), np2 = nn / 2, mm = nn - 1;
+  const int nblk = np2 * (np2 + 1) / 2;  // at most nth, or 2 * nth when BIG (checked at launch)
+  // this thread's 2x2 blocks and their places after a round, fixed over the rounds
+  int I0 = -1, J0 = -1, I1 = -1, J1 = -1;
   if (tid < nblk) tri_ij(tid, I0, J0);
-  if (tid + nth < nblk) tri_ij(tid + nth, I1, J1);
-  // eigenvector rows: thread -> (row, first pair, pair stride), fixed over the rounds; in
-  // split mode the first wave takes no rows
+  if (BIG && tid + nth < nblk) tri_ij(tid + nth, I1, J1);
+  int d0[4], e0[4], d1[4], e1[4];
+  block_dests(I0, J0, np2, nblk, d0, e0);
+  if constexpr (BIG) block_dests(I1, J1, np2, nblk, d1, e1);
+  // eigenvector slots: thread -> (row, first slot, slot stride); in split mode the first wave
+  // takes no rows
   const bool split = nth - 64 >= n;
   const int vt = split ? tid - 64 : tid, nv = split ? nth - 64 : nth;
-  const int vks = nv / n, vrow = vt >= 0 ? vt % n : 0, vk0 = (vt >= 0 && vks > 0 && vt < vks * n) ? vt / n : np2;
+  const int vks = nv / n, vrow = vt >= 0 ? vt % n : 0;
+  const int vk0 = (vt >= 0 && vks > 0 && vt < vks * n) ? vt / n : np2;
   if (!v_ready)
-    for (int k = tid; k < n * n; k += nth) V[k] = (k % (n + 1) == 0) ? 1.0 : 0.0;
+    for (int k = tid; k < n * nn; k += nth) V[k] = (k % (n + 1) == 0 && k / n < n) ? 1.0 : 0.0;
   double f2 = 0.0;
-  for (int k = tid; k < npk; k += nth) {
-    int i, j;
-    tri_ij(k, i, j);
-    const double a = (double)A[k];
-    f2 += (i == j ? 1.0 : 2.0) * a * a;
-  }
+  if (I0 >= 0) f2 += block_mass<T>(Ab, nblk, tid, I0, J0, true);
+  if (BIG && I1 >= 0) f2 += block_mass<T>(Ab, nblk, tid + nth, I1, J1, true);
   const double fro2 = wg_sum(f2, red);
   const double skip = JacobiTol<T>::skip_rel * sqrt(fro2);
   const double offtol2 = JacobiTol<T>::off_rel * JacobiTol<T>::off_rel * fro2;
-  int g = 0;         // rounds done; round g uses buffer g & 1
-  int pending = -1;  // split mode: round whose eigenvector update is still to do
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0.0;  // off-diagonal mass at the start of the sweep
-    for (int k = tid; k < npk; k += nth) {
-      int i, j;
-      tri_ij(k, i, j);
-      const double a = (double)A[k];
-      if (i != j) off += 2.0 * a * a;
+  int cur = 0;
+  int g = 0;        // rounds done; round g writes rotd buffer g & 1
+  int rprev = -1;   // round (mod mm) whose eigenvector rotation is still to do, or -1
+  auto v_rotate = [&](int rr, const double *rdp) {  // columns of slot k in round rr, in place
+    for (int k = vk0; k < np2; k += vks) {
+      const double2 cs = reinterpret_cast<const double2 *>(rdp)[k];
+      double *vp = V + logical_index(2 * k, rr, mm) * n + vrow;
+      double *vq = V + logical_index(2 * k + 1, rr, mm) * n + vrow;
+      const double a = *vp, b = *vq;
+      *vp = cs.x * a - cs.y * b;
+      *vq = cs.y * a + cs.x * b;
     }
+  };
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    const T *Ac = Ab + (size_t)cur * 4 * nblk;
+    double off = 0.0;  // off-diagonal mass at the start of the sweep
+    if (I0 >= 0) off += block_mass<T>(Ac, nblk, tid, I0, J0, false);
+    if (BIG && I1 >= 0) off += block_mass<T>(Ac, nblk, tid + nth, I1, J1, false);
     if (wg_sum(off, red) <= offtol2) break;
     for (int r = 0; r < mm; ++r, ++g) {
-      T *rc = rot + (g & 1) * 4 * np2;
+      T *A = Ab + (size_t)cur * 4 * nblk;
+      T *An = nbuf == 2 ? Ab + (size_t)(cur ^ 1) * 4 * nblk : A;
       double *rdc = rotd + (g & 1) * 2 * np2;
-      if (split) {
-        if (tid < 64) round_rotations<T>(r, n, np2, mm, skip, A, rc, rdc, tid, 64);
-        else if (pending >= 0) rotate_vectors(pending, n, np2, mm, rotd + ((g + 1) & 1) * 2 * np2, V, vrow, vk0, vks);
-      } else {
-        round_rotations<T>(r, n, np2, mm, skip, A, rc, rdc, tid, nth);
-      }
+      if (!split || tid < 64) round_rotations<T>(np2, nblk, skip, A, rot, rdc, tid, split ? 64 : nth);
+      if (rprev >= 0 && vt >= 0) v_rotate(rprev, rotd + ((g + 1) & 1) * 2 * np2);
       __syncthreads();
-      if (I0 >= 0) rotate_block<T>(r, I0, J0, n, mm, A, rc);
-      if (I1 >= 0) rotate_block<T>(r, I1, J1, n, mm, A, rc);
-      if (split) pending = r;
-      else rotate_vectors(r, n, np2, mm, rdc, V, vrow, vk0, vks);
+      T o0[4], o1[4];
+      if (I0 >= 0) rotate_block<T>(tid, I0, J0, nblk, A, rot, o0);
+      if (BIG && I1 >= 0) rotate_block<T>(tid + nth, I1, J1, nblk, A, rot, o1);
+      if (nbuf == 1) __syncthreads();
+      if (I0 >= 0) store_block<T>(An, d0, e0, o0);
+      if (BIG && I1 >= 0) store_block<T>(An, d1, e1, o1);
+      if (nbuf == 2) cur ^= 1;
+      rprev = r;
       __syncthreads();
     }
   }
-  if (pending >= 0) {  // the last round's eigenvector update
-    if (tid >= 64) rotate_vectors(pending, n, np2, mm, rotd + ((g + 1) & 1) * 2 * np2, V, vrow, vk0, vks);
+  if (rprev >= 0) {  // the last round's eigenvector rotation
+    if (vt >= 0) v_rotate(rprev, rotd + ((g + 1) & 1) * 2 * np2);
     __syncthreads();
   }
+  rfin = g % mm;
+  return cur;
 }
 
-// Eigen-indices of the cheaper side: the positive eigenvalues when they are at most as many
-// as the negative ones (Pi = sum_{lam > 0} lam v v^T), else the negative ones
-// (Pi = X - sum_{lam < 0} lam v v^T).  sel[n] = 1 for the positive side, sel[n+1] = count.
-// The first wave counts and compacts with ballots.
+// Eigenpairs of the cheaper side: the positive eigenvalues when they are at most as many as
+// the negative ones (Pi = sum_{lam > 0} lam v v^T), else the negative ones
+// (Pi = X - sum_{lam < 0} lam v v^T).  Entry t: eigenvector column sel[t], eigenvalue lam[t];
+// sel[nn] = 1 for the positive side, sel[nn+1] = count.  A is in the position order of round
+// rfin.  The first wave counts and compacts with ballots.
 template <typename T>
-__device__ __forceinline__ void select_side(int n, const T *A, int *sel) {
+__device__ __forceinline__ void select_side(int nn, int nblk, const T *A, int rfin, int *sel, double *lam) {
   const int tid = threadIdx.x;
   if (tid < 64) {
     int np = 0, nneg = 0;
-    for (int b = 0; b < n; b += 64) {
-      const int i = b + tid;
-      const T l = i < n ? A[pidx(i, i)] : T(0);
+    for (int b = 0; b < nn; b += 64) {
+      const int x = b + tid;
+      const T l = x < nn ? diag_entry(A, nblk, x) : T(0);
       np += __popcll(__ballot(l > T(0)));
       nneg += __popcll(__ballot(l < T(0)));
     }
     const int pos = np <= nneg;
     const unsigned long long below = (tid == 0) ? 0ull : (~0ull >> (64 - tid));
     int c = 0;
-    for (int b = 0; b < n; b += 64) {
-      const int i = b + tid;
-      const T l = i < n ? A[pidx(i, i)] : T(0);
-      const bool f = i < n && (pos ? (l > T(0)) : (l < T(0)));
+    for (int b = 0; b < nn; b += 64) {
+      const int x = b + tid;
+      const T l = x < nn ? diag_entry(A, nblk, x) : T(0);
+      const bool f = x < nn && (pos ? (l > T(0)) : (l < T(0)));
       const unsigned long long m = __ballot(f);
-      if (f) sel[c + __popcll(m & below)] = i;
+      if (f) {
+        const int t = c + __popcll(m & below);
+        sel[t] = logical_index(x, rfin, nn - 1);
+        lam[t] = (double)l;
+      }
       c += __popcll(m);
     }
     if (tid == 0) {
-      sel[n] = pos;
-      sel[n + 1] = c;
+      sel[nn] = pos;
+      sel[nn + 1] = c;
     }
   }
   __syncthreads();
 }
 
-template <typename T>
-__device__ inline double rebuild(int i, int j, int n, const T *A, const double *V, const int *sel, int cnt) {
+__device__ inline double rebuild(int i, int j, int n, const double *lam, const double *V, const int *sel, int cnt) {
   double acc = 0.0;
   for (int t = 0; t < cnt; ++t) {
-    const int e = sel[t];
-    acc += (double)A[pidx(e, e)] * V[i + e * n] * V[j + e * n];
+    const int c = sel[t];
+    acc += lam[t] * V[i + c * n] * V[j + c * n];
   }
   return acc;
 }
 
 // ADMM step 2: S = (Pi(X_b) - X_b) * scale for the listed blocks (svec in and out), scale <= 0
-// meaning 1 / sigma.  With Q != nullptr the eigenvectors of block k live at Q + qoff[k]; warm
-// selects a start from them (else a cold start) and they are written back after the sweeps.
-template <typename T>
+// meaning 1 / sigma.  With Q != nullptr the eigenvectors of block k (n x nn, position order)
+// live at Q + qoff[k]; warm selects a start from them (else a cold start) and they are written
+// back after the sweeps.  lds_cap: the dynamic LDS of the launch.
+template <typename T, bool BIG>
 __global__ void __launch_bounds__(1024) k_project_admm(const int32_t *__restrict__ blk_ids, const int64_t *__restrict__ boff,
                                                        const int32_t *__restrict__ bsz, const double *__restrict__ Xb,
                                                        double *__restrict__ S, const DevState *__restrict__ st,
                                                        double scale, double *__restrict__ Q,
-                                                       const int64_t *__restrict__ qoff, int32_t warm) {
+                                                       const int64_t *__restrict__ qoff, int32_t warm, uint32_t lds_cap) {
   extern __shared__ __align__(32) unsigned char smem[];
   const int32_t bk = blk_ids[blockIdx.x];
   const int n = bsz[bk];
+  const int nn = n + (n & 1), np2 = nn / 2, nblk = np2 * (np2 + 1) / 2;
   const int64_t off = boff[bk];
   const int nth = blockDim.x, tid = threadIdx.x;
   const int npk = n * (n + 1) / 2;
-  Smem sm = carve<T>(smem, n);
-  T *A = reinterpret_cast<T *>(sm.A);
+  Smem sm = carve<T>(smem, n, lds_cap);
+  T *Ab = reinterpret_cast<T *>(sm.A);
   const double rs2 = 0.70710678118654752440, s2 = 1.41421356237309504880;
   double *q = Q ? Q + qoff[bk] : nullptr;
   const bool use_q = q && warm;
   if (use_q) {
-    for (int k = tid; k < n * n; k += nth) sm.V[k] = q[k];
+    for (int k = tid; k < n * nn; k += nth) sm.V[k] = q[k];
     __syncthreads();
-    rotate_into_basis<T>(n, Xb + off, sm.V, q, A);
+    rotate_into_basis<T>(n, Xb + off, sm.V, q, Ab, nblk);
   } else {
-    for (int k = tid; k < npk; k += nth) {  // svec is the packed upper triangle with sqrt(2) off-diagonal
-      int i, j;
-      tri_ij(k, i, j);
-      const double v = Xb[off + k];
-      A[k] = (T)(i == j ? v : v * rs2);
+    for (int e = tid; e < nn * (nn + 1) / 2; e += nth) {  // svec: packed upper triangle, sqrt(2) off-diagonal
+      int x, y;
+      tri_ij(e, x, y);
+      const int i = logical_index(x, 0, nn - 1), j = logical_index(y, 0, nn - 1);
+      const double v = (i < n && j < n) ? Xb[off + pidx(i, j)] : 0.0;
+      store_entry<T>(Ab, nblk, x, y, (T)(i == j ? v : v * rs2));
     }
     __syncthreads();
   }
-  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red, use_q);
-  select_side<T>(n, A, sm.sel);
+  int rfin = 0;
+  const int cur = jacobi_eig<T, BIG>(n, Ab, sm.nbuf, sm.V, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red, use_q, rfin);
+  select_side<T>(nn, nblk, Ab + (size_t)cur * 4 * nblk, rfin, sm.sel, sm.lam);
   if (q)
-    for (int k = tid; k < n * n; k += nth) q[k] = sm.V[k];
-  const int pos = sm.sel[n], cnt = sm.sel[n + 1];
+    for (int k = tid; k < n * nn; k += nth) q[k] = sm.V[k];
+  const int pos = sm.sel[nn], cnt = sm.sel[nn + 1];
   const double mul = scale > 0.0 ? scale : 1.0 / st->sigma;
   for (int k = tid; k < npk; k += nth) {
     int i, j;
     tri_ij(k, i, j);
-    const double acc = rebuild<T>(i, j, n, A, sm.V, sm.sel, cnt) * (i == j ? 1.0 : s2);
+    const double acc = rebuild(i, j, n, sm.lam, sm.V, sm.sel, cnt) * (i == j ? 1.0 : s2);
     S[off + k] = pos ? (acc - Xb[off + k]) * mul   // (Pi - X_b) * mul
                      : -acc * mul;                  // -Pi_-(X_b) * mul
   }
 }
 
 // strom_project_psd_batched: column-major blocks in T, at element offsets.
-template <typename T>
+template <typename T, bool BIG>
 __global__ void __launch_bounds__(1024) k_project_dense(int32_t nblocks, const int32_t *__restrict__ nd,
                                                         const int64_t *__restrict__ od, const T *__restrict__ in,
-                                                        T *__restrict__ out, int32_t max_n, int32_t *__restrict__ err) {
+                                                        T *__restrict__ out, int32_t max_n, int32_t *__restrict__ err,
+                                                        uint32_t lds_cap) {
   extern __shared__ __align__(32) unsigned char smem[];
   const int32_t bk = blockIdx.x;
   const int n = nd[bk];
@@ -424,24 +504,27 @@ __global__ void __launch_bounds__(1024) k_project_dense(int32_t nblocks, const i
     if (threadIdx.x == 0) atomicOr(err, 1);
     return;
   }
+  const int nn = n + (n & 1), np2 = nn / 2, nblk = np2 * (np2 + 1) / 2;
   const int nth = blockDim.x, tid = threadIdx.x;
   const int npk = n * (n + 1) / 2;
-  Smem sm = carve<T>(smem, n);
-  T *A = reinterpret_cast<T *>(sm.A);
-  for (int k = tid; k < npk; k += nth) {
-    int i, j;
-    tri_ij(k, i, j);
-    A[k] = in[off + i + (int64_t)j * n];
+  Smem sm = carve<T>(smem, n, lds_cap);
+  T *Ab = reinterpret_cast<T *>(sm.A);
+  for (int e = tid; e < nn * (nn + 1) / 2; e += nth) {
+    int x, y;
+    tri_ij(e, x, y);
+    const int i = logical_index(x, 0, nn - 1), j = logical_index(y, 0, nn - 1);
+    store_entry<T>(Ab, nblk, x, y, (i < n && j < n) ? in[off + i + (int64_t)j * n] : T(0));
   }
   __syncthreads();
-  jacobi_eig<T>(n, A, sm.V, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red, false);
-  select_side<T>(n, A, sm.sel);
-  const int pos = sm.sel[n], cnt = sm.sel[n + 1];
+  int rfin = 0;
+  const int cur = jacobi_eig<T, BIG>(n, Ab, sm.nbuf, sm.V, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red, false, rfin);
+  select_side<T>(nn, nblk, Ab + (size_t)cur * 4 * nblk, rfin, sm.sel, sm.lam);
+  const int pos = sm.sel[nn], cnt = sm.sel[nn + 1];
   // every thread reads only the upper entries it writes, so out may alias in
   for (int k = tid; k < npk; k += nth) {
     int i, j;
     tri_ij(k, i, j);
-    const double acc = rebuild<T>(i, j, n, A, sm.V, sm.sel, cnt);
+    const double acc = rebuild(i, j, n, sm.lam, sm.V, sm.sel, cnt);
     const double x = (double)in[off + i + (int64_t)j * n];
     const T pv = (T)(pos ? acc : x - acc);
     out[off + i + (int64_t)j * n] = pv;
@@ -450,7 +533,8 @@ __global__ void __launch_bounds__(1024) k_project_dense(int32_t nblocks, const i
 }
 
 size_t project_lds_bytes(int n, bool f32, int nthreads) {
-  return f32 ? lds_bytes_t<float>(n, nthreads) : lds_bytes_t<double>(n, nthreads);
+  (void)nthreads;
+  return lds_bytes_for(n, f32 ? sizeof(float) : sizeof(double));
 }
 
 // Threads per block: 16 waves for the large blocks (latency hiding of the LDS traffic), and
@@ -465,9 +549,23 @@ int project_threads(int n) {
   return nt;
 }
 
-static bool threads_ok(int n, int nt) {
-  const int np2 = (n + 1) / 2;
-  return nt >= n && np2 * (np2 + 1) / 2 <= 2 * nt;
+// The kernels assume: every 2x2 block has a thread (at most two per thread) and every
+// eigenvector row has a thread; then the same holds for every smaller block of a merged
+// launch.  big: the launch needs the two-blocks-per-thread variant.
+static bool threads_ok(int n, int nt, bool &big) {
+  const int nn = n + (n & 1), np2 = nn / 2, nblk = np2 * (np2 + 1) / 2;
+  if (nt < n || nblk > 2 * nt) return false;
+  big = nblk > nt;
+  return true;
+}
+
+template <typename T, bool BIG>
+static void launch_admm_t(hipStream_t s, int count, int nt, size_t lds, const int32_t *ids, const int64_t *boff,
+                          const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale, double *Q,
+                          const int64_t *qoff, bool warm) {
+  (void)hipFuncSetAttribute((const void *)k_project_admm<T, BIG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_project_admm<T, BIG>), dim3(count), dim3(nt), lds, s, ids, boff, bsz, Xb, S, st, scale, Q, qoff,
+                     warm ? 1 : 0, (uint32_t)lds);
 }
 
 hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const int32_t *ids, const int64_t *boff,
@@ -475,33 +573,39 @@ hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const 
                                double *Q, const int64_t *qoff, bool warm) {
   if (count <= 0) return hipSuccess;
   const int nt = project_threads(n);
-  if (!threads_ok(n, nt)) return hipErrorInvalidValue;
   const size_t lds = project_lds_bytes(n, f32, nt);
+  bool big = false;
+  if (!threads_ok(n, nt, big) || lds > kLdsCap) return hipErrorInvalidValue;
   if (f32) {
-    (void)hipFuncSetAttribute((const void *)k_project_admm<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_project_admm<float>, dim3(count), dim3(nt), lds, s, ids, boff, bsz, Xb, S, st, scale, Q, qoff,
-                       warm ? 1 : 0);
+    if (big) launch_admm_t<float, true>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
+    else launch_admm_t<float, false>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
   } else {
-    (void)hipFuncSetAttribute((const void *)k_project_admm<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_project_admm<double>, dim3(count), dim3(nt), lds, s, ids, boff, bsz, Xb, S, st, scale, Q, qoff,
-                       warm ? 1 : 0);
+    if (big) launch_admm_t<double, true>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
+    else launch_admm_t<double, false>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
   }
   return hipGetLastError();
+}
+
+template <typename T, bool BIG>
+static void launch_dense_t(hipStream_t s, int nblocks, int nt, size_t lds, int max_n, const int32_t *nd,
+                           const int64_t *od, const void *in, void *out, int32_t *err) {
+  (void)hipFuncSetAttribute((const void *)k_project_dense<T, BIG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_project_dense<T, BIG>), dim3(nblocks), dim3(nt), lds, s, nblocks, nd, od, (const T *)in,
+                     (T *)out, max_n, err, (uint32_t)lds);
 }
 
 hipError_t launch_project_dense(hipStream_t s, bool f32, int nblocks, int max_n, const int32_t *nd, const int64_t *od,
                                 const void *in, void *out, int32_t *err) {
   const int nt = project_threads(max_n);
-  if (!threads_ok(max_n, nt)) return hipErrorInvalidValue;
   const size_t lds = project_lds_bytes(max_n, f32, nt);
+  bool big = false;
+  if (!threads_ok(max_n, nt, big) || lds > kLdsCap) return hipErrorInvalidValue;
   if (f32) {
-    (void)hipFuncSetAttribute((const void *)k_project_dense<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_project_dense<float>, dim3(nblocks), dim3(nt), lds, s, nblocks, nd, od, (const float *)in,
-                       (float *)out, max_n, err);
+    if (big) launch_dense_t<float, true>(s, nblocks, nt, lds, max_n, nd, od, in, out, err);
+    else launch_dense_t<float, false>(s, nblocks, nt, lds, max_n, nd, od, in, out, err);
   } else {
-    (void)hipFuncSetAttribute((const void *)k_project_dense<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_project_dense<double>, dim3(nblocks), dim3(nt), lds, s, nblocks, nd, od, (const double *)in,
-                       (double *)out, max_n, err);
+    if (big) launch_dense_t<double, true>(s, nblocks, nt, lds, max_n, nd, od, in, out, err);
+    else launch_dense_t<double, false>(s, nblocks, nt, lds, max_n, nd, od, in, out, err);
   }
   return hipGetLastError();
 }
