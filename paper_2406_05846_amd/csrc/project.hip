@@ -56,6 +56,15 @@ __host__ __device__ inline int pos_next(int x, int np2) {
   return k < np2 - 1 ? x + 2 : x - 1;
 }
 
+// The inverse: the position whose data moves to position x in one round.
+__device__ inline int pos_prev(int x, int np2) {
+  if (np2 == 1) return x;
+  const int k = x >> 1;
+  if ((x & 1) == 0) return k < np2 - 1 ? x + 2 : x + 1;
+  if (k == 0) return 1;
+  return k >= 2 ? x - 2 : 0;
+}
+
 __device__ inline int bidx(int I, int J) { return J * (J + 1) / 2 + I; }  // block (I <= J)
 
 // Index held by position x in round r (0 <= r < mm = nn - 1) of the circle ordering: slot k
@@ -87,7 +96,7 @@ struct JacobiTol<float> {
 
 // LDS: V (n x nn doubles, column-major, column = index) | red (16 doubles) | rotd (two
 //      buffers of (c, s) doubles per slot) | A (nbuf buffers of four arrays of nblk T) | rot
-//      ((c, s, new a_pp, new a_qq) T per slot) | lam (nn doubles) | sel (nn + 4 ints), every
+//      (two buffers of (c, s, new a_pp, new a_qq) T per slot) | lam (nn doubles) | sel (nn + 4 ints), every
 //      region 32-byte aligned.  nbuf = 2 (a round writes the other buffer) when that fits,
 //      else 1 (one more barrier per round).
 struct Layout {
@@ -103,7 +112,7 @@ __host__ __device__ inline Layout lds_layout(int n, size_t tsize, int nbuf) {
   L.rotd = align32(L.red + 8 * 16);
   L.A = align32(L.rotd + 2 * 16 * np2);
   L.rot = align32(L.A + (size_t)nbuf * 4 * tsize * nblk);
-  L.lam = align32(L.rot + 4 * tsize * np2);
+  L.lam = align32(L.rot + 2 * 4 * tsize * np2);
   L.sel = align32(L.lam + 8 * nn);
   L.total = align32(L.sel + 4 * (nn + 4));
   return L;
@@ -246,6 +255,19 @@ __device__ inline void block_dests(int I, int J, int np2, int nblk, int *d, int 
   }
 }
 
+// J_I^T [a b; c d] J_J for the rotations (c1, s1) of slot I and (c2, s2) of slot J.  The block
+// rotations and the look-ahead of the next rotation parameters both use this, so they agree
+// to the bit.
+template <typename T>
+__device__ __forceinline__ void rotate_entries(T a, T bq, T cq, T d, T c1, T s1, T c2, T s2, T *o) {
+  const T ra = c1 * a - s1 * cq, rb = c1 * bq - s1 * d;  // rows p1, q1 rotated
+  const T rc = s1 * a + c1 * cq, rd = s1 * bq + c1 * d;
+  o[0] = c2 * ra - s2 * rb;  // then columns p2, q2
+  o[1] = s2 * ra + c2 * rb;
+  o[2] = c2 * rc - s2 * rd;
+  o[3] = s2 * rc + c2 * rd;
+}
+
 // New entries of block b = (I, J) for the rotations rot of the current round.
 template <typename T>
 __device__ __forceinline__ void rotate_block(int b, int I, int J, int nblk, const T *A, const T *rot, T *o) {
@@ -259,14 +281,7 @@ __device__ __forceinline__ void rotate_block(int b, int I, int J, int nblk, cons
     return;
   }
   const V4 rj = reinterpret_cast<const V4 *>(rot)[J];
-  const T c1 = ri.x, s1 = ri.y, c2 = rj.x, s2 = rj.y;
-  const T a = A[b], bq = A[nblk + b], cq = A[2 * nblk + b], d = A[3 * nblk + b];
-  const T ra = c1 * a - s1 * cq, rb = c1 * bq - s1 * d;  // rows p1, q1 rotated
-  const T rc = s1 * a + c1 * cq, rd = s1 * bq + c1 * d;
-  o[0] = c2 * ra - s2 * rb;  // then columns p2, q2
-  o[1] = s2 * ra + c2 * rb;
-  o[2] = c2 * rc - s2 * rd;
-  o[3] = s2 * rc + c2 * rd;
+  rotate_entries<T>(A[b], A[nblk + b], A[2 * nblk + b], A[3 * nblk + b], ri.x, ri.y, rj.x, rj.y, o);
 }
 
 template <typename T>
@@ -278,30 +293,66 @@ __device__ __forceinline__ void store_block(T *An, const int *d, const int *e, c
   }
 }
 
+// Rotation of one slot that annihilates apq of the 2x2 block [app apq; apq aqq]: (c, s) and the
+// new diagonal, written to rot (T) and rotd (double).
+template <typename T>
+__device__ __forceinline__ void slot_rotation(int k, double app, double aqq, double apq, double skip, T *rot,
+                                              double *rotd) {
+  double c = 1.0, s = 0.0, dp = app, dq = aqq;
+  if (fabs(apq) > skip) {
+    const double theta = (aqq - app) / (2.0 * apq);
+    const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+    c = 1.0 / sqrt(t * t + 1.0);
+    s = t * c;
+    dp = app - t * apq;
+    dq = aqq + t * apq;
+  }
+  typedef typename Vec4<T>::type V4;
+  V4 rv;
+  rv.x = (T)c;
+  rv.y = (T)s;
+  rv.z = (T)dp;
+  rv.w = (T)dq;
+  reinterpret_cast<V4 *>(rot)[k] = rv;
+  reinterpret_cast<double2 *>(rotd)[k] = make_double2(c, s);
+}
+
 // Rotation parameters of every slot from the diagonal blocks of A (threads t0, t0 + stride, ...).
 template <typename T>
 __device__ __forceinline__ void round_rotations(int np2, int nblk, double skip, const T *A, T *rot, double *rotd,
                                                 int t0, int stride) {
   for (int k = t0; k < np2; k += stride) {
     const int bd = bidx(k, k);
-    const double apq = (double)A[nblk + bd], app = (double)A[bd], aqq = (double)A[3 * nblk + bd];
-    double c = 1.0, s = 0.0, dp = app, dq = aqq;
-    if (fabs(apq) > skip) {
-      const double theta = (aqq - app) / (2.0 * apq);
-      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-      c = 1.0 / sqrt(t * t + 1.0);
-      s = t * c;
-      dp = app - t * apq;
-      dq = aqq + t * apq;
+    slot_rotation<T>(k, (double)A[bd], (double)A[3 * nblk + bd], (double)A[nblk + bd], skip, rot, rotd);
+  }
+}
+
+// Look-ahead: the rotation parameters of the next round, from A and the rotations rc of the
+// current round, without waiting for the block rotations.  In the next round slot k holds the
+// data of positions x = pos_prev(2k) and y = pos_prev(2k + 1) of this round; its diagonal
+// entries are new diagonal entries of this round's slots (rc .z / .w) and its off-diagonal
+// entry is one entry of the rotated block (slot(x), slot(y)).
+template <typename T>
+__device__ __forceinline__ void next_rotations(int np2, int nblk, double skip, const T *A, const T *rc, T *rn,
+                                               double *rdn, int t0, int stride) {
+  typedef typename Vec4<T>::type V4;
+  for (int k = t0; k < np2; k += stride) {
+    const int x = pos_prev(2 * k, np2), y = pos_prev(2 * k + 1, np2);
+    const int sx = x >> 1, sy = y >> 1;
+    const V4 px = reinterpret_cast<const V4 *>(rc)[sx], py = reinterpret_cast<const V4 *>(rc)[sy];
+    const double app = (double)((x & 1) ? px.w : px.z), aqq = (double)((y & 1) ? py.w : py.z);
+    double apq = 0.0;  // x, y in one slot: the entry the rotation of this round annihilates
+    if (sx != sy) {
+      const bool tr = sx > sy;
+      const int I = tr ? sy : sx, J = tr ? sx : sy;
+      const int h = tr ? (((y & 1) << 1) | (x & 1)) : (((x & 1) << 1) | (y & 1));
+      const int b = bidx(I, J);
+      const V4 ri = tr ? py : px, rj = tr ? px : py;
+      T o[4];
+      rotate_entries<T>(A[b], A[nblk + b], A[2 * nblk + b], A[3 * nblk + b], ri.x, ri.y, rj.x, rj.y, o);
+      apq = (double)o[h];
     }
-    typedef typename Vec4<T>::type V4;
-    V4 rv;
-    rv.x = (T)c;
-    rv.y = (T)s;
-    rv.z = (T)dp;
-    rv.w = (T)dq;
-    reinterpret_cast<V4 *>(rot)[k] = rv;
-    reinterpret_cast<double2 *>(rotd)[k] = make_double2(c, s);
+    slot_rotation<T>(k, app, aqq, apq, skip, rn, rdn);
   }
 }
 
@@ -315,76 +366,73 @@ __device__ inline double block_mass(const T *A, int nblk, int b, int I, int J, b
 
 // Cyclic Jacobi on the block arrays (buffer 0 on entry, position order of round 0).  Returns
 // the buffer holding the final matrix; rfin = the round (mod mm) whose position order it is in.
-// A round: [rotation parameters (first wave) | in-place eigenvector rotation of the previous
-// round] barrier [2x2 block rotations, stored to the permuted places -- in the other buffer,
-// or after one more barrier when single-buffered] barrier.
+// A round is one phase and one barrier: the first wave computes the next round's rotation
+// parameters (look-ahead) while the other threads rotate the eigenvector pairs in place and the
+// 2x2 blocks, storing them to their permuted places (in the other buffer; single-buffered, the
+// stores wait for one more barrier).  With few threads (no split) every thread does all three.
 template <typename T, bool BIG>
 __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *rot, double *rotd, double *red,
                                           bool v_ready, int &rfin) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int nn = n + (n & 1), np2 = nn / 2, mm = nn - 1;
-  const int nblk = np2 * (np2 + 1) / 2;  // at most nth, or 2 * nth when BIG (checked at launch)
-  // this thread's 2x2 blocks and their places after a round, fixed over the rounds
+  const int nblk = np2 * (np2 + 1) / 2;
+  const bool split = nth - 64 >= n;
+  const int wt = split ? tid - 64 : tid, nw = split ? nth - 64 : nth;  // block and eigenvector workers
+  // this thread's 2x2 blocks (at most nw, or 2 nw when BIG: checked at launch) and their places
+  // after a round, fixed over the rounds
   int I0 = -1, J0 = -1, I1 = -1, J1 = -1;
-  if (tid < nblk) tri_ij(tid, I0, J0);
-  if (BIG && tid + nth < nblk) tri_ij(tid + nth, I1, J1);
+  if (wt >= 0 && wt < nblk) tri_ij(wt, I0, J0);
+  if (BIG && wt >= 0 && wt + nw < nblk) tri_ij(wt + nw, I1, J1);
+  const int b0 = wt, b1 = wt + nw;
   int d0[4], e0[4], d1[4], e1[4];
   block_dests(I0, J0, np2, nblk, d0, e0);
   if constexpr (BIG) block_dests(I1, J1, np2, nblk, d1, e1);
-  // eigenvector slots: thread -> (row, first slot, slot stride); in split mode the first wave
-  // takes no rows
-  const bool split = nth - 64 >= n;
-  const int vt = split ? tid - 64 : tid, nv = split ? nth - 64 : nth;
-  const int vks = nv / n, vrow = vt >= 0 ? vt % n : 0;
-  const int vk0 = (vt >= 0 && vks > 0 && vt < vks * n) ? vt / n : np2;
+  // eigenvector slots: worker -> (row, first slot, slot stride)
+  const int vks = nw / n, vrow = wt >= 0 ? wt % n : 0;
+  const int vk0 = (wt >= 0 && vks > 0 && wt < vks * n) ? wt / n : np2;
   if (!v_ready)
     for (int k = tid; k < n * nn; k += nth) V[k] = (k % (n + 1) == 0 && k / n < n) ? 1.0 : 0.0;
   double f2 = 0.0;
-  if (I0 >= 0) f2 += block_mass<T>(Ab, nblk, tid, I0, J0, true);
-  if (BIG && I1 >= 0) f2 += block_mass<T>(Ab, nblk, tid + nth, I1, J1, true);
+  if (I0 >= 0) f2 += block_mass<T>(Ab, nblk, b0, I0, J0, true);
+  if (BIG && I1 >= 0) f2 += block_mass<T>(Ab, nblk, b1, I1, J1, true);
   const double fro2 = wg_sum(f2, red);
   const double skip = JacobiTol<T>::skip_rel * sqrt(fro2);
   const double offtol2 = JacobiTol<T>::off_rel * JacobiTol<T>::off_rel * fro2;
-  int cur = 0;
-  int g = 0;        // rounds done; round g writes rotd buffer g & 1
-  int rprev = -1;   // round (mod mm) whose eigenvector rotation is still to do, or -1
-  auto v_rotate = [&](int rr, const double *rdp) {  // columns of slot k in round rr, in place
-    for (int k = vk0; k < np2; k += vks) {
-      const double2 cs = reinterpret_cast<const double2 *>(rdp)[k];
-      double *vp = V + logical_index(2 * k, rr, mm) * n + vrow;
-      double *vq = V + logical_index(2 * k + 1, rr, mm) * n + vrow;
-      const double a = *vp, b = *vq;
-      *vp = cs.x * a - cs.y * b;
-      *vq = cs.y * a + cs.x * b;
-    }
-  };
+  // parameters of the first round; then round g uses buffer g & 1 and writes (g + 1) & 1
+  round_rotations<T>(np2, nblk, skip, Ab, rot, rotd, tid, nth);
+  int cur = 0, g = 0;
   for (int sweep = 0; sweep < 40; ++sweep) {
     const T *Ac = Ab + (size_t)cur * 4 * nblk;
     double off = 0.0;  // off-diagonal mass at the start of the sweep
-    if (I0 >= 0) off += block_mass<T>(Ac, nblk, tid, I0, J0, false);
-    if (BIG && I1 >= 0) off += block_mass<T>(Ac, nblk, tid + nth, I1, J1, false);
-    if (wg_sum(off, red) <= offtol2) break;
+    if (I0 >= 0) off += block_mass<T>(Ac, nblk, b0, I0, J0, false);
+    if (BIG && I1 >= 0) off += block_mass<T>(Ac, nblk, b1, I1, J1, false);
+    if (wg_sum(off, red) <= offtol2) break;  // (the barriers inside also publish the parameters)
     for (int r = 0; r < mm; ++r, ++g) {
       T *A = Ab + (size_t)cur * 4 * nblk;
       T *An = nbuf == 2 ? Ab + (size_t)(cur ^ 1) * 4 * nblk : A;
-      double *rdc = rotd + (g & 1) * 2 * np2;
-      if (!split || tid < 64) round_rotations<T>(np2, nblk, skip, A, rot, rdc, tid, split ? 64 : nth);
-      if (rprev >= 0 && vt >= 0) v_rotate(rprev, rotd + ((g + 1) & 1) * 2 * np2);
-      __syncthreads();
+      const T *rc = rot + (g & 1) * 4 * np2;
+      const double *rdc = rotd + (g & 1) * 2 * np2;
+      if (!split || tid < 64)
+        next_rotations<T>(np2, nblk, skip, A, rc, rot + ((g + 1) & 1) * 4 * np2, rotd + ((g + 1) & 1) * 2 * np2, tid,
+                          split ? 64 : nth);
+      if (wt >= 0)
+        for (int k = vk0; k < np2; k += vks) {  // eigenvector columns of slot k, in place
+          const double2 cs = reinterpret_cast<const double2 *>(rdc)[k];
+          double *vp = V + logical_index(2 * k, r, mm) * n + vrow;
+          double *vq = V + logical_index(2 * k + 1, r, mm) * n + vrow;
+          const double va = *vp, vb = *vq;
+          *vp = cs.x * va - cs.y * vb;
+          *vq = cs.y * va + cs.x * vb;
+        }
       T o0[4], o1[4];
-      if (I0 >= 0) rotate_block<T>(tid, I0, J0, nblk, A, rot, o0);
-      if (BIG && I1 >= 0) rotate_block<T>(tid + nth, I1, J1, nblk, A, rot, o1);
+      if (I0 >= 0) rotate_block<T>(b0, I0, J0, nblk, A, rc, o0);
+      if (BIG && I1 >= 0) rotate_block<T>(b1, I1, J1, nblk, A, rc, o1);
       if (nbuf == 1) __syncthreads();
       if (I0 >= 0) store_block<T>(An, d0, e0, o0);
       if (BIG && I1 >= 0) store_block<T>(An, d1, e1, o1);
       if (nbuf == 2) cur ^= 1;
-      rprev = r;
       __syncthreads();
     }
-  }
-  if (rprev >= 0) {  // the last round's eigenvector rotation
-    if (vt >= 0) v_rotate(rprev, rotd + ((g + 1) & 1) * 2 * np2);
-    __syncthreads();
   }
   rfin = g % mm;
   return cur;
@@ -549,13 +597,14 @@ int project_threads(int n) {
   return nt;
 }
 
-// The kernels assume: every 2x2 block has a thread (at most two per thread) and every
-// eigenvector row has a thread; then the same holds for every smaller block of a merged
-// launch.  big: the launch needs the two-blocks-per-thread variant.
+// The kernels assume: every 2x2 block has a worker thread (at most two per thread) and every
+// eigenvector row has one; then the same holds for every smaller block of a merged launch.
+// big: the launch needs the two-blocks-per-thread variant.
 static bool threads_ok(int n, int nt, bool &big) {
   const int nn = n + (n & 1), np2 = nn / 2, nblk = np2 * (np2 + 1) / 2;
-  if (nt < n || nblk > 2 * nt) return false;
-  big = nblk > nt;
+  const int nw = nt - 64 >= n ? nt - 64 : nt;  // block workers (the first wave computes parameters)
+  if (nw < n || nblk > 2 * nw) return false;
+  big = nblk > nw;
   return true;
 }
 
