@@ -242,15 +242,14 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   const size_t oTk = ar.reserve<int32_t>(size_t(ntask) * 4), oPh = ar.reserve<int32_t>(std::max<size_t>(1, nph) * 2);
   const size_t oFo = ar.reserve<int32_t>(H.fwd_order.size()), oBo = ar.reserve<int32_t>(H.bwd_order.size());
   const size_t nseg = std::max<size_t>(1, H.seg_pb.size());
-  const size_t oPoff = ar.reserve<int64_t>(H.push_off.size()), oPci = ar.reserve<int32_t>(std::max<size_t>(1, H.push_ci.size())),
-               oPv = ar.reserve<double>(std::max<size_t>(1, H.push_v.size())),
-               oTsp = ar.reserve<int32_t>(size_t(ntask) + 1), oTseg = ar.reserve<int32_t>(nseg),
-               oTsg = ar.reserve<int32_t>(size_t(ntask)), oPart = ar.reserve<double>(nseg);
+  const size_t oTsp = ar.reserve<int32_t>(size_t(ntask) + 1), oTseg = ar.reserve<int32_t>(nseg),
+               oPart = ar.reserve<double>(nseg);
   const size_t oTpin = ar.reserve<int32_t>(size_t(ntask) + 1), oTinl = ar.reserve<int32_t>(size_t(ntask)),
                oTxoff = ar.reserve<int64_t>(size_t(ntask) + 1),
                oTxrow = ar.reserve<int32_t>(std::max<size_t>(1, H.task_xrow.size()));
-  size_t oSv[4], oSi[4], oSoff[4], oSK[4], oST[4], oSra[4];
-  for (int k = 0; k < 4; ++k) {
+  size_t oSv[strom::kStreamKinds], oSi[strom::kStreamKinds], oSoff[strom::kStreamKinds], oSK[strom::kStreamKinds],
+      oST[strom::kStreamKinds], oSra[strom::kStreamKinds];
+  for (int k = 0; k < strom::kStreamKinds; ++k) {
     oSv[k] = ar.reserve<double>(std::max<size_t>(1, H.sval[k].size()));
     oSi[k] = ar.reserve<int32_t>(std::max<size_t>(1, H.sidx[k].size()));
     oSoff[k] = ar.reserve<int64_t>(std::max<size_t>(1, H.s_off[k].size()));
@@ -311,10 +310,9 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   sa.task_r0 = tk; sa.task_r1 = tk + ntask; sa.task_ph0 = tk + 2 * ntask; sa.task_ph1 = tk + 3 * ntask;
   sa.ph_a = ph; sa.ph_nns = ph + nph;
   sa.D = PD(oD); sa.perm = P32(operm);
-  sa.push_off = P64(oPoff); sa.push_ci = P32(oPci); sa.push_v = PD(oPv);
-  sa.tsptr = P32(oTsp); sa.tseg = P32(oTseg); sa.task_sg = P32(oTsg); sa.part = PD(oPart);
+  sa.tsptr = P32(oTsp); sa.tseg = P32(oTseg); sa.part = PD(oPart);
   sa.task_pin = P32(oTpin); sa.task_inl = P32(oTinl); sa.task_xoff = P64(oTxoff); sa.task_xrow = P32(oTxrow);
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < strom::kStreamKinds; ++k) {
     sa.sval[k] = PD(oSv[k]); sa.sidx[k] = P32(oSi[k]); sa.s_off[k] = P64(oSoff[k]);
     sa.s_K[k] = P32(oSK[k]); sa.s_T[k] = P32(oST[k]); sa.s_ra[k] = P32(oSra[k]);
   }
@@ -366,12 +364,8 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   ok &= up(const_cast<double *>(sa.D), H.D.data(), sizeof(double) * H.D.size());
   ok &= up(tk, tkh.data(), sizeof(int32_t) * tkh.size());
   ok &= up(ph, phh.data(), sizeof(int32_t) * phh.size());
-  ok &= up(const_cast<int64_t *>(sa.push_off), H.push_off.data(), sizeof(int64_t) * H.push_off.size());
-  ok &= up(const_cast<int32_t *>(sa.push_ci), H.push_ci.data(), sizeof(int32_t) * H.push_ci.size());
-  ok &= up(const_cast<double *>(sa.push_v), H.push_v.data(), sizeof(double) * H.push_v.size());
   ok &= up(const_cast<int32_t *>(sa.tsptr), H.tsptr.data(), sizeof(int32_t) * H.tsptr.size());
   ok &= up(const_cast<int32_t *>(sa.tseg), H.tseg.data(), sizeof(int32_t) * H.tseg.size());
-  ok &= up(const_cast<int32_t *>(sa.task_sg), H.task_sg.data(), sizeof(int32_t) * H.task_sg.size());
   {
     const std::vector<int32_t> inl(H.task_inl.begin(), H.task_inl.end());
     ok &= up(const_cast<int32_t *>(sa.task_inl), inl.data(), sizeof(int32_t) * inl.size());
@@ -379,7 +373,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   ok &= up(const_cast<int32_t *>(sa.task_pin), H.task_pin.data(), sizeof(int32_t) * H.task_pin.size());
   ok &= up(const_cast<int64_t *>(sa.task_xoff), H.task_xoff.data(), sizeof(int64_t) * H.task_xoff.size());
   ok &= up(const_cast<int32_t *>(sa.task_xrow), H.task_xrow.data(), sizeof(int32_t) * H.task_xrow.size());
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < strom::kStreamKinds; ++k) {
     ok &= up(const_cast<double *>(sa.sval[k]), H.sval[k].data(), sizeof(double) * H.sval[k].size());
     ok &= up(const_cast<int32_t *>(sa.sidx[k]), H.sidx[k].data(), sizeof(int32_t) * H.sidx[k].size());
     ok &= up(const_cast<int64_t *>(sa.s_off[k]), H.s_off[k].data(), sizeof(int64_t) * H.s_off[k].size());

@@ -5,6 +5,8 @@
 #include <cstdint>
 #include <vector>
 
+#include "strom_internal.h"
+
 namespace strom {
 namespace dev {
 
@@ -23,22 +25,18 @@ struct SolveArgs {
   const int32_t *ph_a, *ph_nns;  // first row and rows in components of 2+ of every phase
   const double *D;
   const int32_t *perm;
-  // pushes: segment s of task t (tseg[tsptr[t] ..]) is [push_off[s], push_off[s+1]) of
-  // push_ci / push_v, pushed task_sg[t] lanes per segment into part[s]
-  const int64_t *push_off;
-  const int32_t *push_ci;
-  const double *push_v;
-  const int32_t *tsptr, *tseg, *task_sg;
+  // pushes: task t sums its push stream (kind 4) into part[tseg[tsptr[t] + r]], row r
+  const int32_t *tsptr, *tseg;
   double *part;
-  // phase streams, kinds 0 forward gather, 1 forward inverse, 2 backward gather,
-  // 3 backward inverse: values, indices, per-phase offset, entries per thread, thread
-  // stride, first rows of the slices
-  const double *sval[4];
-  const int32_t *sidx[4];
-  const int64_t *s_off[4];
-  const int32_t *s_K[4];
-  const int32_t *s_T[4];
-  const int32_t *s_ra[4];
+  // streams, kinds 0 forward gather, 1 forward inverse, 2 backward gather, 3 backward inverse
+  // (per phase), 4 push (per task): values, indices, per-phase (task) offset, entries per
+  // thread, thread stride, first rows of the slices
+  const double *sval[kStreamKinds];
+  const int32_t *sidx[kStreamKinds];
+  const int64_t *s_off[kStreamKinds];
+  const int32_t *s_K[kStreamKinds];
+  const int32_t *s_T[kStreamKinds];
+  const int32_t *s_ra[kStreamKinds];
   // task-local staging (task_inl[t] != 0): the task's rows, then its incoming partial sums
   // part[task_pin[t] ..] (forward) or the later-task rows task_xrow[task_xoff[t] ..]
   // (backward) are staged in LDS and the fg / bg stream indices address that buffer

@@ -55,56 +55,14 @@ __global__ void __launch_bounds__(256) k_rhs(int32_t m, const int64_t *__restric
 }
 
 // ------------------------------------------------------------------ triangular solves
-// One workgroup per task; the task's values stay in LDS while its phases run.  A phase
-// gathers, g lanes per row (shuffle reduction), the contributions of earlier phases to each
-// of its rows; rows on their own are then solved, and every component of two or more rows
-// is solved by a product with the explicit inverse of its diagonal block.  Forward contributions from other tasks' columns are not
+// One workgroup per task; the task's values stay in LDS while its phases run.  Every phase is
+// solved from its streams: the forward gather sums, for each row, the contributions of the
+// task's earlier phases and the partial sums pushed by other tasks; rows on their own are
+// then solved, and every component of two or more rows is solved by a product with the
+// explicit inverse of its diagonal block.  Forward contributions to later tasks' rows are not
 // gathered by the receiving row: the task owning the columns computes them as partial sums
-// ("push segments") right after its own rows are solved, so the work of a separator row is
-// spread over the tasks below it.  Every gather keeps four loads in flight per lane.
-__device__ inline double group_sum(double v, int g) {
-  for (int off = g >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// sum over p = b, b + g, ... < e of v[p] * xs[ci[p] - r0]
-__device__ inline double gather_own(const int32_t *__restrict__ ci, const double *__restrict__ v, int64_t b, int64_t e,
-                                    int g, const double *xs, int32_t r0) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t p = b;
-  for (; p + 3 * g < e; p += 4 * g) {
-    const int32_t j0 = ci[p], j1 = ci[p + g], j2 = ci[p + 2 * g], j3 = ci[p + 3 * g];
-    const double v0 = v[p], v1 = v[p + g], v2 = v[p + 2 * g], v3 = v[p + 3 * g];
-    s0 += v0 * xs[j0 - r0];
-    s1 += v1 * xs[j1 - r0];
-    s2 += v2 * xs[j2 - r0];
-    s3 += v3 * xs[j3 - r0];
-  }
-  for (; p < e; p += g) s0 += v[p] * xs[ci[p] - r0];
-  return (s0 + s1) + (s2 + s3);
-}
-
-__device__ inline double sum_parts(const double *__restrict__ part, int64_t b, int64_t e, int g) {
-  double s = 0.0;
-  for (int64_t q = b; q < e; q += g) s += part[q];
-  return s;
-}
-
-// dot product of a packed inverse row (or column) of length len with c[0 .. len), 16 lanes
-__device__ inline double dense_dot(const double *__restrict__ inv, const double *c, int len, int ln) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int j = ln;
-  for (; j + 48 < len; j += 64) {
-    const double a0 = inv[j], a1 = inv[j + 16], a2 = inv[j + 32], a3 = inv[j + 48];
-    s0 += a0 * c[j];
-    s1 += a1 * c[j + 16];
-    s2 += a2 * c[j + 32];
-    s3 += a3 * c[j + 48];
-  }
-  for (; j < len; j += 16) s0 += inv[j] * c[j];
-  return (s0 + s1) + (s2 + s3);
-}
-
+// ("push segments", its push stream) right after its own rows are solved, so the work of a
+// separator row is spread over the tasks below it.
 // One phase stream (see setup.cpp): thread t walks its slice of K entries (entry k at
 // off + k * Tp + t), kStreamBatch loads in flight, then their factors get(index) (get never
 // reads what fin writes), then adds them in order; fin(row, sum) completes a row.  A row
@@ -201,15 +159,16 @@ __device__ __forceinline__ void solve_fwd_task(int32_t t, const SolveArgs &a, do
     }
     __syncthreads();
   }
-  // push: partial sums of the later rows over this task's columns
-  {
-    const int g = a.task_sg[t], lane = tid & (g - 1);
-    for (int32_t k = a.tsptr[t] + tid / g; k < a.tsptr[t + 1]; k += nth / g) {
-      const int32_t sg = a.tseg[k];
-      double s = gather_own(a.push_ci, a.push_v, a.push_off[sg] + lane, a.push_off[sg + 1], g, xs, r0);
-      s = group_sum(s, g);
-      if (lane == 0) a.part[sg] = s;
-    }
+  // push: partial sums of the later rows over this task's columns, one stream row per segment
+  if (a.tsptr[t] < a.tsptr[t + 1]) {
+    const int32_t s0 = a.tsptr[t];
+    stream_phase(a.sval[4], a.sidx[4], a.s_off[4][t], a.s_K[4][t], a.s_T[4][t],
+                 a.s_ra[4] + (int64_t)t * (kSolveThreads + 1), tail_v, tail_r,
+                 [&](int32_t j) {
+                   if constexpr (INL) return xs[j];
+                   else return w[j];
+                 },
+                 [&](int32_t r, double acc) { a.part[a.tseg[s0 + r]] = acc; });
   }
   if (INL)
     for (int i = tid; i < nt; i += nth) w[r0 + i] = xs[i];

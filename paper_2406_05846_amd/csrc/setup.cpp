@@ -760,11 +760,40 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   //   fi: forward inverse, row i of its component's inverse (index: position in the phase
   //       right-hand side buffer);
   //   bg: backward gather, L(i, j) for rows i after the row's component;
-  //   bi: backward inverse, column j of its component's inverse (index as fi).
-  // fg / bg indices are task-local for a task staged in LDS (see task_inl), else the row
+  //   bi: backward inverse, column j of its component's inverse (index as fi);
+  //   push (kind 4, per task): the task's push segments as rows.
+  // fg / bg / push indices are task-local for a task staged in LDS (see task_inl), else the row
   // (and s | kPartFlag for the partial sum s).
   {
     const int32_t T = kSolveThreads;
+    // Lays out the entries of nrows rows (row r's entries contiguous, the last one flagged) as
+    // the stream of one phase (or task) of the given kind.
+    auto emit = [&](const std::vector<std::pair<int32_t, double>> &ent, const std::vector<int32_t> &erow,
+                    const std::vector<char> &efirst, int32_t nrows, int kind, int32_t pad_idx) {
+      const int64_t E = int64_t(ent.size());
+      int64_t K = kStreamBatch;
+      int32_t Tp = int32_t(std::min<int64_t>(T, (E + K - 1) / K));
+      if (int64_t(Tp) * K < E) K = ((E + Tp - 1) / Tp + kStreamBatch - 1) / kStreamBatch * kStreamBatch;
+      Tp = std::min<int32_t>(T, std::max<int32_t>(64, (Tp + 63) / 64 * 64));
+      std::vector<int32_t> ra(size_t(T) + 1, nrows);
+      std::vector<double> &V = H.sval[size_t(kind)];
+      std::vector<int32_t> &X = H.sidx[size_t(kind)];
+      const int64_t off = int64_t(V.size());
+      V.resize(size_t(off + K * Tp), 0.0);
+      X.resize(size_t(off + K * Tp), pad_idx);
+      for (int32_t t = 0; t < Tp; ++t) {
+        const int64_t e0 = int64_t(t) * K;
+        if (e0 < E) ra[size_t(t)] = erow[size_t(e0)] | (efirst[size_t(e0)] ? kStartFlag : 0);
+        for (int64_t k = 0; k < K && e0 + k < E; ++k) {
+          V[size_t(off + k * Tp + t)] = ent[size_t(e0 + k)].second;
+          X[size_t(off + k * Tp + t)] = ent[size_t(e0 + k)].first;
+        }
+      }
+      H.s_off[size_t(kind)].push_back(off);
+      H.s_K[size_t(kind)].push_back(int32_t(K));
+      H.s_T[size_t(kind)].push_back(Tp);
+      H.s_ra[size_t(kind)].insert(H.s_ra[size_t(kind)].end(), ra.begin(), ra.end());
+    };
     auto build = [&](int32_t ph, int32_t rbeg, int32_t rend, int kind) {
       const int32_t t = ph_task[size_t(ph)], r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];
       const bool inl = H.task_inl[size_t(t)] != 0;
@@ -804,29 +833,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
           efirst.push_back(e == e0);
         }
       }
-      const int64_t E = int64_t(ent.size());
-      int64_t K = kStreamBatch;
-      int32_t Tp = int32_t(std::min<int64_t>(T, (E + K - 1) / K));
-      if (int64_t(Tp) * K < E) K = ((E + Tp - 1) / Tp + kStreamBatch - 1) / kStreamBatch * kStreamBatch;
-      Tp = std::min<int32_t>(T, std::max<int32_t>(64, (Tp + 63) / 64 * 64));
-      std::vector<int32_t> ra(size_t(T) + 1, rend - rbeg);
-      std::vector<double> &V = H.sval[size_t(kind)];
-      std::vector<int32_t> &X = H.sidx[size_t(kind)];
-      const int64_t off = int64_t(V.size());
-      V.resize(size_t(off + K * Tp), 0.0);
-      X.resize(size_t(off + K * Tp), pad_idx);
-      for (int32_t t = 0; t < Tp; ++t) {
-        const int64_t e0 = int64_t(t) * K;
-        if (e0 < E) ra[size_t(t)] = erow[size_t(e0)] | (efirst[size_t(e0)] ? kStartFlag : 0);
-        for (int64_t k = 0; k < K && e0 + k < E; ++k) {
-          V[size_t(off + k * Tp + t)] = ent[size_t(e0 + k)].second;
-          X[size_t(off + k * Tp + t)] = ent[size_t(e0 + k)].first;
-        }
-      }
-      H.s_off[size_t(kind)].push_back(off);
-      H.s_K[size_t(kind)].push_back(int32_t(K));
-      H.s_T[size_t(kind)].push_back(Tp);
-      H.s_ra[size_t(kind)].insert(H.s_ra[size_t(kind)].end(), ra.begin(), ra.end());
+      emit(ent, erow, efirst, rend - rbeg, kind, pad_idx);
     };
     for (size_t ph = 0; ph < H.ph_a.size(); ++ph) {
       const int32_t a = H.ph_a[ph], b = H.ph_b[ph], nns = H.ph_nns[ph];
@@ -834,6 +841,29 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
       build(int32_t(ph), a, a + nns, 1);
       build(int32_t(ph), a, b, 2);
       build(int32_t(ph), a, a + nns, 3);
+    }
+    // kind 4, one stream per task: its push segments (rows: the segments tseg[tsptr[t] ..] in
+    // order; entries: the factor entries of the segment, index of the column as in fg)
+    for (int32_t t = 0; t < ntask; ++t) {
+      const int32_t r0 = H.task_r0[size_t(t)];
+      const bool inl = H.task_inl[size_t(t)] != 0;
+      std::vector<std::pair<int32_t, double>> ent;
+      std::vector<int32_t> erow;
+      std::vector<char> efirst;
+      const int32_t nseg = H.tsptr[size_t(t) + 1] - H.tsptr[size_t(t)];
+      for (int32_t r = 0; r < nseg; ++r) {
+        const int32_t sg = H.tseg[size_t(H.tsptr[size_t(t)] + r)];
+        const size_t e0 = ent.size();
+        for (int64_t e = H.push_off[size_t(sg)]; e < H.push_off[size_t(sg) + 1]; ++e)
+          ent.emplace_back(inl ? H.push_ci[size_t(e)] - r0 : H.push_ci[size_t(e)], H.push_v[size_t(e)]);
+        if (ent.size() == e0) ent.emplace_back(inl ? 0 : r0, 0.0);
+        ent.back().first |= kLastFlag;
+        for (size_t e = e0; e < ent.size(); ++e) {
+          erow.push_back(r);
+          efirst.push_back(e == e0);
+        }
+      }
+      emit(ent, erow, efirst, nseg, 4, inl ? 0 : r0);
     }
   }
 

@@ -13,6 +13,7 @@ constexpr int32_t kMaxBlockRows = 128;        // rows of one component (dense di
 constexpr int32_t kMaxPhaseBlockRows = 4096;  // rows in components of two or more, per phase
 constexpr int32_t kMaxLdsTaskRows = 14336;    // task values kept in LDS up to this many rows
 constexpr int32_t kStreamBatch = 8;              // stream entries loaded per thread at a time
+constexpr int kStreamKinds = 5;                  // fg, fi, bg, bi (per phase), push (per task)
 constexpr int32_t kLastFlag = int32_t(1) << 30;  // stream index flag: last entry of a row
 constexpr int32_t kPartFlag = int32_t(1) << 29;  // forward gather index flag: a pushed partial sum
 constexpr int32_t kStartFlag = int32_t(1) << 30; // first-row flag of a stream slice: the row starts there
@@ -67,15 +68,15 @@ struct HostAnalysis {
   std::vector<int64_t> push_off;
   std::vector<int32_t> push_ci;
   std::vector<double> push_v;
-  // Phase streams (kinds 0 fg, 1 fi, 2 bg, 3 bi; see setup.cpp): values and indices, and per
-  // phase the offset, the entries per thread K, the thread count Tp and, for kSolveThreads + 1
-  // threads, the first row of each slice.
-  std::vector<double> sval[4];
-  std::vector<int32_t> sidx[4];
-  std::vector<int64_t> s_off[4];
-  std::vector<int32_t> s_K[4];
-  std::vector<int32_t> s_T[4];   // thread stride of the phase's layout
-  std::vector<int32_t> s_ra[4];
+  // Streams (kinds 0 fg, 1 fi, 2 bg, 3 bi per phase, 4 push per task; see setup.cpp): values
+  // and indices, and per phase (task) the offset, the entries per thread K, the thread count
+  // Tp and, for kSolveThreads + 1 threads, the first row of each slice.
+  std::vector<double> sval[kStreamKinds];
+  std::vector<int32_t> sidx[kStreamKinds];
+  std::vector<int64_t> s_off[kStreamKinds];
+  std::vector<int32_t> s_K[kStreamKinds];
+  std::vector<int32_t> s_T[kStreamKinds];   // thread stride of the layout
+  std::vector<int32_t> s_ra[kStreamKinds];
   // Task-local index space of a task whose values are staged in LDS (task_inl): local index
   // k < nt is row r0 + k; in the forward streams nt + q is the pushed partial sum
   // task_pin[t] + q (the task's rows sum the segments [task_pin[t], task_pin[t + 1])); in the

@@ -68,10 +68,11 @@ int main(int argc, char **argv) {
   }
   const long nph = long(H.ph_a.size());
   const int ntask = int(H.task_r0.size());
-  for (int k = 0; k < 4; ++k) {
-    REQ(long(H.s_off[k].size()) == nph && long(H.s_K[k].size()) == nph);
-    REQ(long(H.s_ra[k].size()) == nph * (kSolveThreads + 1));
-    for (long p = 0; p < nph; ++p) REQ(H.s_off[k][p] + long(H.s_K[k][p]) * H.s_T[k][p] <= long(H.sval[k].size()));
+  for (int k = 0; k < strom::kStreamKinds; ++k) {
+    const long nd = k < 4 ? nph : long(ntask);  // descriptors per phase, or per task for the push
+    REQ(long(H.s_off[k].size()) == nd && long(H.s_K[k].size()) == nd);
+    REQ(long(H.s_ra[k].size()) == nd * (kSolveThreads + 1));
+    for (long p = 0; p < nd; ++p) REQ(H.s_off[k][p] + long(H.s_K[k][p]) * H.s_T[k][p] <= long(H.sval[k].size()));
   }
   // tasks cover the rows in order; every task is in exactly one group of each direction
   REQ(H.task_r0[0] == 0 && H.task_r1[ntask - 1] == m);
@@ -181,14 +182,21 @@ int main(int argc, char **argv) {
       }
       if (inl)
         for (int i = 0; i < nt; ++i) w[size_t(r0 + i)] = xs[size_t(i)];
-      for (int k = H.tsptr[t]; k < H.tsptr[t + 1]; ++k) {
-        const int s = H.tseg[size_t(k)];
-        double v = 0.0;
-        for (long e = H.push_off[size_t(s)]; e < H.push_off[size_t(s) + 1]; ++e) {
-          REQ(H.push_ci[size_t(e)] >= r0 && H.push_ci[size_t(e)] < r1);
-          v += H.push_v[size_t(e)] * w[size_t(H.push_ci[size_t(e)])];
-        }
-        part[size_t(s)] = v;
+      const int nseg = H.tsptr[t + 1] - H.tsptr[t];
+      if (nseg > 0) {  // the push stream: one row per owned segment
+        std::vector<char> pdone(size_t(nseg), 0);
+        walk(4, t, nseg,
+             [&](int j) {
+               if (inl) { REQ(j >= 0 && j < nt); return w[size_t(r0 + j)]; }
+               REQ(j >= r0 && j < r1);
+               return w[size_t(j)];
+             },
+             [&](int rr, double acc) {
+               REQ(!pdone[size_t(rr)]);
+               pdone[size_t(rr)] = 1;
+               part[size_t(H.tseg[size_t(H.tsptr[t] + rr)])] = acc;
+             });
+        for (char x : pdone) REQ(x);
       }
     }
   // backward: L^T x = D^{-1} z
