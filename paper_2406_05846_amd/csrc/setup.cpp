@@ -280,12 +280,12 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   // order of the factor's dependencies, so the relabeled L stays unit lower triangular and is
   // the factor of the relabeled matrix (nothing is refactored).
   //
-  // Load balance: a group task whose cost (stream entries per thread, see phase_cost) is far
+  // Load balance: a group task whose cost (stream entries per thread, see rows_cost) is far
   // above the typical group task -- the first and last cliques of a trajectory carry the
   // boundary-condition rows -- is split: the components of its first phase, which do not
-  // depend on each other, are dealt to several tasks, and its later phases move into the
-  // coupling task next to it that comes first in the order (that task depends on them
-  // anyway), so the split adds no dependency depth.
+  // depend on each other, are dealt to several tasks; its later phases become a task of
+  // their own when the coupling task next to it (which depends on them) is at depth 2 or
+  // more, else they move into that coupling task.  Either way the split adds no depth.
   int32_t max_block = kMaxBlockRows;  // STROM_BLOCK_ROWS overrides (tuning of the solve schedule)
   if (const char *ev = std::getenv("STROM_BLOCK_ROWS")) {
     const long v = std::strtol(ev, nullptr, 10);
@@ -470,6 +470,13 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
       std::nth_element(group_costs.begin(), group_costs.begin() + group_costs.size() / 2, group_costs.end());
       ref = group_costs[group_costs.size() / 2];
     }
+    // Forward dependency depth of the tasks as they are.
+    std::vector<int32_t> depth0(static_cast<size_t>(ntask), 0);
+    for (int32_t j = 0; j < m; ++j)
+      for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
+        const int32_t ti = row_task[size_t(Ci[size_t(p)])], tj = row_task[size_t(j)];
+        if (ti != tj) depth0[size_t(ti)] = std::max(depth0[size_t(ti)], depth0[size_t(tj)] + 1);
+      }
     // Plan: parts of the first phase (cut at component boundaries, balanced by cost) and the
     // task that receives the later phases (-1: they stay a task of their own).
     std::vector<std::vector<int32_t>> cuts(static_cast<size_t>(ntask));
@@ -499,6 +506,9 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
           const int32_t ou = H.perm[size_t(H.task_r0[size_t(u)])];
           if (rclass[size_t(ou)] == 1 && (rkey[size_t(ou)] == g || rkey[size_t(ou)] == g - 1)) { dest[size_t(t)] = u; break; }
         }
+        // a coupling task deeper than 1 waits for another coupling task anyway: the later
+        // phases then run as a task of their own beside that one, at no extra depth
+        if (dest[size_t(t)] >= 0 && depth0[size_t(dest[size_t(t)])] >= 2) dest[size_t(t)] = -1;
         if (dest[size_t(t)] >= 0)
           for (int32_t r = p0end[size_t(t)]; r < r1; ++r) front[size_t(dest[size_t(t)])].push_back(r);
       }
