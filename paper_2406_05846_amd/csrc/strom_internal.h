@@ -9,7 +9,7 @@
 namespace strom {
 
 constexpr int32_t kSolveThreads = 1024;       // workgroup size of the solve kernels
-constexpr int32_t kMaxBlockRows = 128;        // rows of one component (dense diagonal block) of a phase
+constexpr int32_t kMaxBlockRows = 192;        // rows of one component (dense diagonal block) of a phase
 constexpr int32_t kMaxPhaseBlockRows = 4096;  // rows in components of two or more, per phase
 constexpr int32_t kMaxLdsTaskRows = 14336;    // task values kept in LDS up to this many rows
 constexpr int32_t kStreamBatch = 8;              // stream entries loaded per thread at a time
