@@ -280,19 +280,23 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   // order of the factor's dependencies, so the relabeled L stays unit lower triangular and is
   // the factor of the relabeled matrix (nothing is refactored).
   //
-  // Load balance: a group task whose cost (stream entries per thread, see rows_cost) is far
-  // above the typical group task -- the first and last cliques of a trajectory carry the
-  // boundary-condition rows -- is split: the components of its first phase, which do not
-  // depend on each other, are dealt to several tasks; its later phases become a task of
-  // their own when the coupling task next to it (which depends on them) is at depth 2 or
-  // more, else they move into that coupling task.  Either way the split adds no depth.
+  // Load balance: the group tasks run first, one workgroup each, on far fewer CUs than the
+  // device has, and the first clique of a trajectory carries the boundary-condition rows (its
+  // task costs several times the others).  So every group task is split: the components of
+  // its first phase, which do not depend on each other, are dealt to parts of about half the
+  // typical group task's cost (stream entries per thread, see rows_cost); its later phases
+  // become a task of their own when the coupling task next to it (which depends on them) is
+  // at depth 2 or more, else they move into that coupling task.  Either way the split adds
+  // no depth.
   int32_t max_block = kMaxBlockRows;  // STROM_BLOCK_ROWS overrides (tuning of the solve schedule)
   if (const char *ev = std::getenv("STROM_BLOCK_ROWS")) {
     const long v = std::strtol(ev, nullptr, 10);
     if (v >= 1 && v <= 256) max_block = int32_t(v);
   }
-  bool allow_split = true;  // STROM_TASK_SPLIT=0 disables the split
-  if (const char *ev = std::getenv("STROM_TASK_SPLIT")) allow_split = std::strtol(ev, nullptr, 10) != 0;
+  // STROM_TASK_SPLIT: 0 no split, 1 overweight group tasks only, 2 (default) every group task
+  int split_mode = 2;
+  if (const char *ev = std::getenv("STROM_TASK_SPLIT")) split_mode = int(std::strtol(ev, nullptr, 10));
+  const bool allow_split = split_mode != 0;
   int32_t ntask = int32_t(H.task_r0.size());
   std::vector<int32_t> row_task(static_cast<size_t>(m));
   auto set_row_task = [&]() {
@@ -486,8 +490,9 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     for (int32_t t = 0; ref > 0.0 && t < ntask; ++t) {
       const int32_t r0 = H.task_r0[size_t(t)], r1 = H.task_r1[size_t(t)];
       const int32_t o0 = H.perm[size_t(r0)];
-      if (rclass[size_t(o0)] != 0 || tcost[size_t(t)] <= 1.5 * ref) continue;
-      const int32_t nparts = std::min<int32_t>(8, std::max<int32_t>(1, int32_t(std::ceil(p0cost[size_t(t)] / ref))));
+      if (rclass[size_t(o0)] != 0 || (split_mode < 2 && tcost[size_t(t)] <= 1.5 * ref)) continue;
+      const double target = split_mode >= 2 ? 0.5 * ref : ref;  // cost of one part
+      const int32_t nparts = std::min<int32_t>(8, std::max<int32_t>(1, int32_t(std::ceil(p0cost[size_t(t)] / target))));
       if (nparts == 1 && p0end[size_t(t)] == r1) continue;
       const double total = rows_cost(r0, p0end[size_t(t)]);
       double acc = 0.0;

@@ -5,8 +5,9 @@ task split, phases, component inverses, push segments, task-local staging, phase
 launch groups) and then walks the schedule exactly as the solve kernels read it.  Its
 y = (eps I + A A^*)^{-1} r must match the oracle's own sparse factorization: a schedule that
 drops, doubles or misindexes a stream entry, or runs a task before one it depends on, fails
-here.  Every case runs with the task split on and off and with every task staged in LDS,
-some staged, and none (the in-place kernel path).
+here.  Every case runs with the task split of every group task, of the overweight ones only
+and none, and with every task staged in LDS, some staged, and none (the in-place kernel
+path).
 """
 import os
 import subprocess
@@ -24,6 +25,7 @@ CASES = [  # (family, N, parameters): pendulum, cart-pole, car (the split applie
 VARIANTS = [  # environment of the analysis
     {},
     {"STROM_TASK_SPLIT": "0"},
+    {"STROM_TASK_SPLIT": "1"},
     {"STROM_STAGE_ROWS": "0"},
     {"STROM_STAGE_ROWS": "600", "STROM_BLOCK_ROWS": "32"},
 ]
@@ -63,6 +65,7 @@ def test_schedule_solves_the_system(sim, orc, tmp_path, fam, N, prm):
     base = tasks[()]
     assert base["staged"] == base["tasks"]
     assert tasks[(("STROM_STAGE_ROWS", "0"),)]["staged"] == 0
+    assert base["fwd_groups"] == tasks[(("STROM_TASK_SPLIT", "0"),)]["fwd_groups"]  # no added depth
     if fam in (1, 2):  # the first clique carries the initial-state rows: its task is split
         assert base["tasks"] > tasks[(("STROM_TASK_SPLIT", "0"),)]["tasks"]
         assert base["fwd_groups"] == tasks[(("STROM_TASK_SPLIT", "0"),)]["fwd_groups"]
