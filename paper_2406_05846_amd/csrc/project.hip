@@ -32,6 +32,10 @@ namespace strom {
 namespace dev {
 
 constexpr size_t kLdsCap = 160 * 1024;  // LDS of one workgroup on gfx950
+// Eigenvector slots per worker thread (their column offsets stay in registers): at most
+// kSmallVs in the one-block-per-thread variant, big_vs in the other (checked at launch).
+constexpr int kSmallVs = 5;
+__host__ __device__ constexpr int big_vs(bool f32) { return f32 ? 10 : 8; }
 
 __device__ inline int pidx(int i, int j) {  // packed upper triangle, by columns
   if (i > j) { const int t = i; i = j; j = t; }
@@ -238,20 +242,21 @@ struct Vec4<float> {
 };
 
 // Places of the entries of block (I, J) after one round: index into the block arrays
-// (array * nblk + block) of entry h = (p,p), (p,q), (q,p), (q,q), and a second index (or -1)
-// where the entry lands off the diagonal of a diagonal block (stored twice).  A diagonal block
-// carries its (p,q) entry once: its (q,p) entry gets no place.
-__device__ inline void block_dests(int I, int J, int np2, int nblk, int *d, int *e) {
+// (array * nblk + block) of entry h = (p,p), (p,q), (q,p), (q,q), and bit h of *twice when the
+// entry lands off the diagonal of a diagonal block, where it is stored twice: as (p,q) at d[h]
+// and as (q,p) at d[h] + nblk.  A diagonal block carries its (p,q) entry once: its (q,p)
+// entry gets no place (-1).
+__device__ inline void block_dests(int I, int J, int np2, int nblk, int *d, int *twice) {
+  *twice = 0;
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
     d[h] = -1;
-    e[h] = -1;
     if (I < 0 || (I == J && h == 2)) continue;
     int x = pos_next(2 * I + (h >> 1), np2), y = pos_next(2 * J + (h & 1), np2);
     if (x > y) { const int t = x; x = y; y = t; }
     const int b = bidx(x >> 1, y >> 1);
     d[h] = (((x & 1) << 1) | (y & 1)) * nblk + b;
-    if ((x >> 1) == (y >> 1) && x != y) e[h] = 2 * nblk + b;
+    if ((x >> 1) == (y >> 1) && x != y) *twice |= 1 << h;
   }
 }
 
@@ -285,11 +290,11 @@ __device__ __forceinline__ void rotate_block(int b, int I, int J, int nblk, cons
 }
 
 template <typename T>
-__device__ __forceinline__ void store_block(T *An, const int *d, const int *e, const T *o) {
+__device__ __forceinline__ void store_block(T *An, int nblk, const int *d, int twice, const T *o) {
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
     if (d[h] >= 0) An[d[h]] = o[h];
-    if (e[h] >= 0) An[e[h]] = o[h];
+    if (twice & (1 << h)) An[d[h] + nblk] = o[h];
   }
 }
 
@@ -384,12 +389,23 @@ __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *
   if (wt >= 0 && wt < nblk) tri_ij(wt, I0, J0);
   if (BIG && wt >= 0 && wt + nw < nblk) tri_ij(wt + nw, I1, J1);
   const int b0 = wt, b1 = wt + nw;
-  int d0[4], e0[4], d1[4], e1[4];
-  block_dests(I0, J0, np2, nblk, d0, e0);
-  if constexpr (BIG) block_dests(I1, J1, np2, nblk, d1, e1);
-  // eigenvector slots: worker -> (row, first slot, slot stride)
+  int d0[4], d1[4], tw0 = 0, tw1 = 0;
+  block_dests(I0, J0, np2, nblk, d0, &tw0);
+  if constexpr (BIG) block_dests(I1, J1, np2, nblk, d1, &tw1);
+  // eigenvector slots: worker -> (row, first slot, slot stride); the offsets of the two
+  // columns of each slot (index * n) advance by one column per round, wrapping at mm, except
+  // the fixed second index of slot 0
+  constexpr int kMaxVs = BIG ? big_vs(sizeof(T) == 4) : kSmallVs;
   const int vks = nw / n, vrow = wt >= 0 ? wt % n : 0;
   const int vk0 = (wt >= 0 && vks > 0 && wt < vks * n) ? wt / n : np2;
+  const int vwrap = mm * n;
+  int vcp[kMaxVs], vcq[kMaxVs];
+#pragma unroll
+  for (int j = 0; j < kMaxVs; ++j) {
+    const int k = vk0 + j * vks;
+    vcp[j] = k < np2 ? logical_index(2 * k, 0, mm) * n : 0;
+    vcq[j] = k < np2 ? logical_index(2 * k + 1, 0, mm) * n : 0;
+  }
   if (!v_ready)
     for (int k = tid; k < n * nn; k += nth) V[k] = (k % (n + 1) == 0 && k / n < n) ? 1.0 : 0.0;
   double f2 = 0.0;
@@ -415,21 +431,28 @@ __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *
       if (!split || tid < 64)
         next_rotations<T>(np2, nblk, skip, A, rc, rot + ((g + 1) & 1) * 4 * np2, rotd + ((g + 1) & 1) * 2 * np2, tid,
                           split ? 64 : nth);
-      if (wt >= 0)
-        for (int k = vk0; k < np2; k += vks) {  // eigenvector columns of slot k, in place
-          const double2 cs = reinterpret_cast<const double2 *>(rdc)[k];
-          double *vp = V + logical_index(2 * k, r, mm) * n + vrow;
-          double *vq = V + logical_index(2 * k + 1, r, mm) * n + vrow;
-          const double va = *vp, vb = *vq;
-          *vp = cs.x * va - cs.y * vb;
-          *vq = cs.y * va + cs.x * vb;
+      if (wt >= 0) {
+#pragma unroll
+        for (int j = 0; j < kMaxVs; ++j) {  // eigenvector columns of slot k, in place
+          const int k = vk0 + j * vks;
+          if (k < np2) {
+            const double2 cs = reinterpret_cast<const double2 *>(rdc)[k];
+            double *vp = V + vcp[j] + vrow;
+            double *vq = V + vcq[j] + vrow;
+            const double va = *vp, vb = *vq;
+            *vp = cs.x * va - cs.y * vb;
+            *vq = cs.y * va + cs.x * vb;
+            vcp[j] = vcp[j] + n >= vwrap ? vcp[j] + n - vwrap : vcp[j] + n;
+            if (k > 0) vcq[j] = vcq[j] + n >= vwrap ? vcq[j] + n - vwrap : vcq[j] + n;
+          }
         }
+      }
       T o0[4], o1[4];
       if (I0 >= 0) rotate_block<T>(b0, I0, J0, nblk, A, rc, o0);
       if (BIG && I1 >= 0) rotate_block<T>(b1, I1, J1, nblk, A, rc, o1);
       if (nbuf == 1) __syncthreads();
-      if (I0 >= 0) store_block<T>(An, d0, e0, o0);
-      if (BIG && I1 >= 0) store_block<T>(An, d1, e1, o1);
+      if (I0 >= 0) store_block<T>(An, nblk, d0, tw0, o0);
+      if (BIG && I1 >= 0) store_block<T>(An, nblk, d1, tw1, o1);
       if (nbuf == 2) cur ^= 1;
       __syncthreads();
     }
@@ -597,15 +620,17 @@ int project_threads(int n) {
   return nt;
 }
 
-// The kernels assume: every 2x2 block has a worker thread (at most two per thread) and every
-// eigenvector row has one; then the same holds for every smaller block of a merged launch.
-// big: the launch needs the two-blocks-per-thread variant.
-static bool threads_ok(int n, int nt, bool &big) {
+// The kernels assume: every 2x2 block has a worker thread (at most two per thread), every
+// eigenvector row has one and no worker holds more than big_vs eigenvector slots; then the
+// same holds for every smaller block of a merged launch.  big: the launch needs the variant
+// with two blocks and big_vs slots per thread.
+static bool threads_ok(int n, int nt, bool f32, bool &big) {
   const int nn = n + (n & 1), np2 = nn / 2, nblk = np2 * (np2 + 1) / 2;
   const int nw = nt - 64 >= n ? nt - 64 : nt;  // block workers (the first wave computes parameters)
   if (nw < n || nblk > 2 * nw) return false;
-  big = nblk > nw;
-  return true;
+  const int vks = nw / n, slots = (np2 + vks - 1) / vks;
+  big = nblk > nw || slots > kSmallVs;
+  return slots <= big_vs(f32);
 }
 
 template <typename T, bool BIG>
@@ -624,7 +649,7 @@ hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const 
   const int nt = project_threads(n);
   const size_t lds = project_lds_bytes(n, f32, nt);
   bool big = false;
-  if (!threads_ok(n, nt, big) || lds > kLdsCap) return hipErrorInvalidValue;
+  if (!threads_ok(n, nt, f32, big) || lds > kLdsCap) return hipErrorInvalidValue;
   if (f32) {
     if (big) launch_admm_t<float, true>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
     else launch_admm_t<float, false>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
@@ -648,7 +673,7 @@ hipError_t launch_project_dense(hipStream_t s, bool f32, int nblocks, int max_n,
   const int nt = project_threads(max_n);
   const size_t lds = project_lds_bytes(max_n, f32, nt);
   bool big = false;
-  if (!threads_ok(max_n, nt, big) || lds > kLdsCap) return hipErrorInvalidValue;
+  if (!threads_ok(max_n, nt, f32, big) || lds > kLdsCap) return hipErrorInvalidValue;
   if (f32) {
     if (big) launch_dense_t<float, true>(s, nblocks, nt, lds, max_n, nd, od, in, out, err);
     else launch_dense_t<float, false>(s, nblocks, nt, lds, max_n, nd, od, in, out, err);
