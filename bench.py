@@ -104,6 +104,36 @@ def _serving(S, W, np, ctx, args) -> dict:
     return serving
 
 
+def _batched(S, W, torch, args) -> dict:
+    """Batched form: K cart-pole N=30 instances (seeds seed .. seed+K-1) advanced together,
+    each on a context with its own stream (rounds replayed from HIP graphs), aggregate
+    instance-iterations per second of the timed region (after a warmup on every instance)."""
+    K, iters = args.batch, 200
+    ctxs, insts = [], []
+    for k in range(K):
+        c = S.Context(0, stream=torch.cuda.Stream())
+        ctxs.append(c)
+        pr = S.generate(W.CARTPOLE, 30, W.instance_params(W.CARTPOLE, args.seed + k))
+        insts.append(S.Instance(c, pr, S.default_opts(tol=0.0, maxiter=10**9)))
+    for ins in insts:
+        ins.enqueue(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ins in insts:
+        ins.enqueue(iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for ins in insts:
+        ins.close()
+    for c in ctxs:
+        c.close()
+    out = {"workload": f"{K} cart-pole N=30 instances (seeds {args.seed}..{args.seed + K - 1}), FP64, one context "
+                       f"and stream each, {iters} iterations each after {args.warmup} of warmup",
+           "instance_iters_per_s": round(K * iters / dt, 2), "ms_per_iteration_each": round(1e3 * dt / iters, 4)}
+    _log(f"batched: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +142,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--solves", type=int, default=8, help="pendulum solves timed for solves/s and latency")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving sample (0: skip)")
+    ap.add_argument("--batch", type=int, default=8, help="instances of the batched form (0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-only", action="store_true", help="only the serving sample")
@@ -209,6 +240,7 @@ def main():
     solves32 = solve_set(S.default_opts(proj_dtype=S.F32), "fp32+polish")
 
     serving = _serving(S, W, np, ctx, args) if args.serve > 0 else None
+    batched = _batched(S, W, torch, args) if args.batch > 0 else None
 
     flops = _proj_flops(prob.block_sizes)
     proj_s = prof["project_ms"] * 1e-3
@@ -240,6 +272,7 @@ def main():
                                "generator + setup + solve to eta <= 1e-6, sequential",
                    "fp64": solves64, "fp32_polish": solves32},
         "serving": serving,
+        "batched": batched,
         "phase_ms": {k: round(v, 4) for k, v in prof.items()},
         "roofline": {"bound": "alu", "kernel": "k_project_admm<double> (every PSD block of one iteration)",
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

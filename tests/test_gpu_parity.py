@@ -375,3 +375,33 @@ def test_mixed_batch_through_request_loop(S, ctx, orc):
             assert info["iters"] == 30000
             assert abs(eta - max(info["eta_p"], info["eta_d"], info["eta_g"])) <= 1e-6 + 1e-3 * eta
     assert nconv >= 6
+
+
+def test_batched_instances_on_streams_match_alone(S):
+    """The batched form: instances advanced together, each on a context with its own stream,
+    give exactly the iterates each one gives alone (the kernels have no order-dependent
+    reductions)."""
+    import torch
+    probs = [S.generate(1, 10, [0.5 + 0.3 * k, 0.0]) for k in range(3)]
+    opts = S.default_opts(tol=0.0, maxiter=10**6)
+    alone = []
+    c0 = S.Context(0)
+    for p in probs:
+        ins = S.Instance(c0, p, opts)
+        ins.enqueue(40)
+        torch.cuda.synchronize()
+        alone.append(ins.get_iterate())
+        ins.close()
+    c0.close()
+    ctxs = [S.Context(0, stream=torch.cuda.Stream()) for _ in probs]
+    insts = [S.Instance(c, p, opts) for c, p in zip(ctxs, probs)]
+    for ins in insts:
+        ins.enqueue(40)
+    torch.cuda.synchronize()
+    for ins, ref in zip(insts, alone):
+        got = ins.get_iterate()
+        for g, r in zip(got, ref):
+            assert np.array_equal(g, r)
+        ins.close()
+    for c in ctxs:
+        c.close()
