@@ -174,6 +174,39 @@ strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblocks, int32_t 
                                        const void *in_dev, void *out_dev, strom_dtype dtype,
                                        void *hip_stream);
 
+/* Eigendecomposition of nblocks dense symmetric blocks (layout and limits as
+ * strom_project_psd_batched; the same Jacobi eigensolver).  Eigenvalues of block k, in
+ * ascending order (ties in index order), are written at element offset woff_dev[k] of w_dev;
+ * with v_dev != NULL the eigenvectors are written as the columns of an n x n column-major block
+ * at offset_dev[k] of v_dev (column j for eigenvalue j; v_dev may alias in_dev).  With
+ * v_dev == NULL only eigenvalues are computed and the eigenvector work is skipped (the
+ * eigenvalues-only mode used by the certificate below).  n_dev, offset_dev, woff_dev, in_dev,
+ * w_dev and v_dev are device pointers; dtype selects double or float for in, w and v. */
+strom_status strom_eig_batched(strom_ctx *ctx, int32_t nblocks, int32_t max_n, const int32_t *n_dev,
+                               const int64_t *offset_dev, const void *in_dev, const int64_t *woff_dev,
+                               void *w_dev, void *v_dev, strom_dtype dtype, void *hip_stream);
+
+/* Valid lower bound of the refined certificate of suboptimality (Sec. "Algorithmic Backbone",
+ * the valid-lower-bound equation after the rank-one lifting operator): for the current y,
+ *     lb = <b, y> + sum_beta R_beta * min(0, lambda_min((C - A^* y)_beta)),
+ * a lower bound of the POP optimum whenever R_beta >= trace(X(z)_beta) for every feasible z
+ * (the rank-one lifting; App. "Existence of R_beta" gives such bounds from box bounds on the
+ * clique variables: they are problem knowledge, so the caller supplies them).  R_beta: host,
+ * nblocks values.  lb (host) receives the bound; lam_min (host, nullable, nblocks) the smallest
+ * eigenvalue of every block of C - A^* y.  FP64; synchronizes; uses temporary device memory. */
+strom_status strom_dual_bound(strom_sdp *sdp, const double *R_beta, double *lb, double *lam_min);
+
+/* Rank test and extraction from the current X (Sec. "Sparse Moment Relaxation": the rank-one
+ * condition of the convergence theorem, and the first two steps of the extraction heuristic).
+ * For each listed block: lam[2k], lam[2k+1] = the largest and second largest eigenvalue
+ * (lam[2k+1] / lam[2k] small: numerically rank one), and vtop (n_k values per listed block,
+ * concatenated) = the eigenvector of the largest eigenvalue scaled so that its first entry is 1
+ * (for a moment matrix the entries after it are the degree-one moments z-bar); if that entry is
+ * exactly 0 the vector is returned with unit norm and its largest entry positive.  blocks (host,
+ * nlist block indices), lam and vtop are host arrays.  FP64; synchronizes; uses temporary
+ * device memory.  E_INVAL for an index outside [0, nblocks). */
+strom_status strom_extract(strom_sdp *sdp, int32_t nlist, const int32_t *blocks, double *lam, double *vtop);
+
 /* Serving.  strom_submit copies a problem and queues it; a solver thread owned by the ctx
  * admits queued problems while their device footprint fits the ctx's HBM budget, keeps their
  * iterates on the device, advances every admitted instance, retires an instance when it

@@ -17,7 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRCS = ["pop.c", "relax.c", "ldl.c", "jacobi.c", "admm.c"]
+_SRCS = ["pop.c", "relax.c", "ldl.c", "jacobi.c", "admm.c", "cert.c"]
 
 TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR = 0, 1, 2, 3, 4
 ROW_NORM, ROW_MOMENT, ROW_LOCALIZING, ROW_EQUALITY, ROW_CONSENSUS = 0, 1, 2, 3, 4
@@ -99,6 +99,11 @@ def lib():
         L.orc_project_svec.argtypes = [C.c_int32, _i32, _dp, _dp]
         L.orc_kkt.argtypes = [C.c_int32, _i32, C.c_int32, _i64, _i32, _dp, _dp, _dp, _dp, _dp, _dp,
                               C.POINTER(_Info)]
+        L.orc_dual_bound.argtypes = [C.c_int32, _i32, C.c_int32, _i64, _i32, _dp, _dp, _dp, _dp, _dp,
+                                     C.POINTER(C.c_double), _dp]
+        L.orc_dual_bound.restype = C.c_int
+        L.orc_extract.argtypes = [C.c_int32, _i32, _dp, C.c_int32, _i32, _dp, _dp]
+        L.orc_extract.restype = C.c_int
         _lib = L
     return _lib
 
@@ -245,3 +250,34 @@ def kkt(sdp: SDP, X, y, S) -> dict:
                   np.ascontiguousarray(X, dtype=np.float64), np.ascontiguousarray(y, dtype=np.float64),
                   np.ascontiguousarray(S, dtype=np.float64), C.byref(info))
     return {f: getattr(info, f) for f, _ in _Info._fields_}
+
+
+def dual_bound(sdp: SDP, y, R_beta):
+    """Certificate lower bound <b,y> + sum_beta R_beta min(0, lambda_min((C - A^*y)_beta))
+    and lambda_min per block (cert.c)."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    R = np.ascontiguousarray(R_beta, dtype=np.float64)
+    lam = np.zeros(sdp.nblocks)
+    lb = C.c_double()
+    rc = lib().orc_dual_bound(sdp.nblocks, sdp.bsize, sdp.m, sdp.rowptr, sdp.col, sdp.val, sdp.b, sdp.C, y, R,
+                              C.byref(lb), lam)
+    if rc != 0:
+        raise ValueError(f"orc_dual_bound failed: {rc}")
+    return lb.value, lam
+
+
+def extract(sdp: SDP, X, blocks):
+    """Largest two eigenvalues and the top eigenvector (first entry 1) of the listed blocks of X."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    bl = np.ascontiguousarray(blocks, dtype=np.int32)
+    sizes = [int(sdp.bsize[k]) for k in bl]
+    lam = np.zeros(2 * len(bl))
+    vt = np.zeros(sum(sizes))
+    rc = lib().orc_extract(sdp.nblocks, sdp.bsize, X, len(bl), bl, lam, vt)
+    if rc != 0:
+        raise ValueError(f"orc_extract failed: {rc}")
+    out, o = [], 0
+    for n in sizes:
+        out.append(vt[o:o + n])
+        o += n
+    return lam.reshape(-1, 2), out

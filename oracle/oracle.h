@@ -142,6 +142,18 @@ void orc_kkt(int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *ro
              const int32_t *col, const double *val, const double *b, const double *C,
              const double *X, const double *y, const double *S, orc_info *info);
 
+/* ---- certificate (cert.c) ---- */
+/* lb = <b,y> + sum_beta R_beta min(0, lambda_min((C - A^* y)_beta)); lam_min (nullable)
+ * receives lambda_min per block.  Returns 0, or < 0 on an allocation failure. */
+int orc_dual_bound(int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *rowptr,
+                   const int32_t *col, const double *val, const double *b, const double *C,
+                   const double *y, const double *R_beta, double *lb, double *lam_min);
+/* For each listed block of X (svec): lam[2t], lam[2t+1] = largest and second largest eigenvalue;
+ * vtop (n per listed block, concatenated) = the top eigenvector divided by its first entry.
+ * Returns 0, or < 0 for a block index out of range. */
+int orc_extract(int32_t nblocks, const int32_t *bsize, const double *X, int32_t nlist,
+                const int32_t *blocks, double *lam, double *vtop);
+
 #ifdef __cplusplus
 }
 #endif

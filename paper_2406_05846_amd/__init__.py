@@ -24,6 +24,7 @@ EXPORTS = [
     "strom_sdp_setup", "strom_sdp_destroy", "strom_admm_step", "strom_admm_enqueue",
     "strom_kkt_residuals", "strom_get_iterate", "strom_set_iterate", "strom_sdp_sizes",
     "strom_project_psd_batched", "strom_submit", "strom_poll", "strom_profile_iteration",
+    "strom_eig_batched", "strom_dual_bound", "strom_extract",
     "strom_gen_build", "strom_gen_sizes", "strom_gen_export", "strom_gen_free",
 ]
 
@@ -81,6 +82,9 @@ def _load():
     L.strom_set_iterate.argtypes = [vp, vp, vp, vp]
     L.strom_sdp_sizes.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64)]
     L.strom_project_psd_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp, C.c_int, vp]
+    L.strom_eig_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, C.c_int, vp]
+    L.strom_dual_bound.argtypes = [vp, vp, vp, vp]
+    L.strom_extract.argtypes = [vp, i32, vp, vp, vp]
     L.strom_submit.argtypes = [vp, C.POINTER(Problem_), C.POINTER(Opts), C.POINTER(C.c_uint64)]
     L.strom_poll.argtypes = [vp, C.c_uint64, C.POINTER(Info), vp, vp, vp]
     L.strom_profile_iteration.argtypes = [vp, i32, C.POINTER(PhaseTimes)]
@@ -233,6 +237,18 @@ class Context:
                                             C.c_void_p(out.data_ptr()), dt, _stream_handle(stream)))
 
 
+    def eig_batched(self, n_dev, offset_dev, inp, woff_dev, w, v=None, max_n: int = 0, stream=None):
+        """Eigenvalues (ascending, at woff_dev[k] of w) and optionally eigenvectors (columns at
+        offset_dev[k] of v) of dense column-major blocks (torch device tensors)."""
+        import torch
+        dt = F32 if inp.dtype == torch.float32 else F64
+        _check(_L.strom_eig_batched(self._h, int(n_dev.numel()), int(max_n), C.c_void_p(n_dev.data_ptr()),
+                                    C.c_void_p(offset_dev.data_ptr()), C.c_void_p(inp.data_ptr()),
+                                    C.c_void_p(woff_dev.data_ptr()), C.c_void_p(w.data_ptr()),
+                                    C.c_void_p(v.data_ptr() if v is not None else None), dt,
+                                    _stream_handle(stream)))
+
+
 class Instance:
     """One SDP on the device (strom_sdp)."""
 
@@ -267,6 +283,29 @@ class Instance:
 
     def enqueue(self, n_iter: int):
         _check(_L.strom_admm_enqueue(self._h, int(n_iter)))
+
+    def dual_bound(self, R_beta):
+        """(lb, lambda_min per block) of the certificate's lower bound at the current y."""
+        R = np.ascontiguousarray(R_beta, dtype=np.float64)
+        lam = np.zeros(len(R))
+        lb = C.c_double()
+        _check(_L.strom_dual_bound(self._h, R.ctypes.data_as(C.c_void_p), C.cast(C.byref(lb), C.c_void_p),
+                                   lam.ctypes.data_as(C.c_void_p)))
+        return lb.value, lam
+
+    def extract(self, blocks, sizes):
+        """(largest two eigenvalues per listed block, top eigenvectors scaled to first entry 1)
+        of the listed blocks of the current X; sizes: the listed blocks' sizes."""
+        bl = np.ascontiguousarray(blocks, dtype=np.int32)
+        lam = np.zeros(2 * len(bl))
+        vt = np.zeros(int(np.sum(sizes)))
+        _check(_L.strom_extract(self._h, len(bl), bl.ctypes.data_as(C.c_void_p), lam.ctypes.data_as(C.c_void_p),
+                                vt.ctypes.data_as(C.c_void_p)))
+        out, o = [], 0
+        for n in sizes:
+            out.append(vt[o:o + int(n)])
+            o += int(n)
+        return lam.reshape(-1, 2), out
 
     def kkt(self) -> dict:
         info = Info()

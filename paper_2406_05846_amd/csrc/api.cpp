@@ -105,6 +105,7 @@ struct strom_sdp {
   double t_setup = 0, t_solve = 0;
   DevState *st_host = nullptr;  // pinned mirror
   int32_t max_n = 0;
+  std::vector<int32_t> bsize_h;  // block sizes (host copy)
 };
 
 extern "C" void strom_default_opts(strom_opts *o) {
@@ -207,6 +208,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   s->nnz = P->nnz;
   s->nnzL = H.nnzL;
   s->max_n = max_n;
+  s->bsize_h.assign(P->block_sizes, P->block_sizes + P->nblocks);
   const int32_t m = P->m;
   const int64_t n = H.nsvec, nnz = P->nnz;
   const int ntask = int(H.task_r0.size());
@@ -747,6 +749,151 @@ extern "C" strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblock
 }
 
 // ------------------------------------------------------------------ serving entry points
+extern "C" strom_status strom_eig_batched(strom_ctx *ctx, int32_t nblocks, int32_t max_n, const int32_t *n_dev,
+                                          const int64_t *offset_dev, const void *in_dev, const int64_t *woff_dev,
+                                          void *w_dev, void *v_dev, strom_dtype dtype, void *hip_stream) {
+  if (!ctx || nblocks < 0 || (nblocks > 0 && (!n_dev || !offset_dev || !in_dev || !woff_dev || !w_dev)))
+    return fail(STROM_E_INVAL, "bad argument");
+  if (nblocks == 0) return STROM_OK;
+  const bool f32 = dtype == STROM_F32;
+  if (dtype != STROM_F32 && dtype != STROM_F64) return fail(STROM_E_INVAL, "bad dtype");
+  if (max_n <= 0 || proj_need(max_n, f32) > ctx->max_lds)
+    return fail(STROM_E_INVAL, "max_n out of range for the LDS of one workgroup");
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t q = (hipStream_t)hip_stream;
+  HIP_TRY(hipMemsetAsync(ctx->err_flag, 0, sizeof(int32_t), q));
+  HIP_TRY(strom::dev::launch_eig_dense(q, f32, nblocks, max_n, n_dev, offset_dev, in_dev, woff_dev, w_dev, v_dev,
+                                       ctx->err_flag));
+  int32_t flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, ctx->err_flag, sizeof(int32_t), hipMemcpyDeviceToHost, q));
+  HIP_TRY(hipStreamSynchronize(q));
+  if (flag) return fail(STROM_E_INVAL, "a block size is <= 0 or > max_n");
+  return STROM_OK;
+}
+
+namespace {
+// Eigenvalues (and, with want_v, eigenvectors) of the listed blocks of the svec vector sv of
+// an instance, through dense copies in temporary device memory.  w: per listed block its n
+// eigenvalues in ascending order, concatenated; v: per listed block its n x n eigenvectors
+// (column j for eigenvalue j), concatenated.
+strom_status block_eigs(strom_sdp *s, const double *sv, const std::vector<int32_t> &list, bool want_v,
+                        std::vector<double> &w, std::vector<double> &v) {
+  const size_t nl = list.size();
+  std::vector<int64_t> od(nl), wo(nl);
+  std::vector<int32_t> nd(nl);
+  int64_t tn = 0, tn2 = 0;
+  int32_t mx = 1;
+  for (size_t k = 0; k < nl; ++k) {
+    const int32_t n = s->bsize_h[size_t(list[k])];
+    nd[k] = n;
+    od[k] = tn2;
+    wo[k] = tn;
+    tn2 += int64_t(n) * n;
+    tn += n;
+    mx = std::max(mx, n);
+  }
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t q = s->stream;
+  HIP_TRY(hipStreamSynchronize(q));
+  const size_t bytes = sizeof(int32_t) * nl * 2 + sizeof(int64_t) * nl * 2 + sizeof(double) * size_t(tn) +
+                       sizeof(double) * size_t(tn2) * (want_v ? 2 : 1) + 7 * 256;  // + alignment of 7 regions
+  unsigned char *buf = nullptr;
+  if (hipMalloc(&buf, bytes) != hipSuccess) return fail(STROM_E_NOMEM, "device memory for the block eigenvalues");
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t o = 0;
+  int32_t *d_ids = reinterpret_cast<int32_t *>(buf + o); o = al(o + sizeof(int32_t) * nl);
+  int32_t *d_nd = reinterpret_cast<int32_t *>(buf + o); o = al(o + sizeof(int32_t) * nl);
+  int64_t *d_od = reinterpret_cast<int64_t *>(buf + o); o = al(o + sizeof(int64_t) * nl);
+  int64_t *d_wo = reinterpret_cast<int64_t *>(buf + o); o = al(o + sizeof(int64_t) * nl);
+  double *d_w = reinterpret_cast<double *>(buf + o); o = al(o + sizeof(double) * size_t(tn));
+  double *d_dense = reinterpret_cast<double *>(buf + o); o = al(o + sizeof(double) * size_t(tn2));
+  double *d_v = want_v ? reinterpret_cast<double *>(buf + o) : nullptr;
+  strom_status st = STROM_OK;
+  std::string msg;
+  auto chk = [&](hipError_t e, const char *what) {
+    if (e != hipSuccess && st == STROM_OK) { st = STROM_E_HIP; msg = std::string(what) + ": " + hipGetErrorString(e); }
+  };
+  chk(hipMemcpy(d_ids, list.data(), sizeof(int32_t) * nl, hipMemcpyHostToDevice), "upload");
+  chk(hipMemcpy(d_nd, nd.data(), sizeof(int32_t) * nl, hipMemcpyHostToDevice), "upload");
+  chk(hipMemcpy(d_od, od.data(), sizeof(int64_t) * nl, hipMemcpyHostToDevice), "upload");
+  chk(hipMemcpy(d_wo, wo.data(), sizeof(int64_t) * nl, hipMemcpyHostToDevice), "upload");
+  chk(hipMemsetAsync(s->ctx->err_flag, 0, sizeof(int32_t), q), "hipMemsetAsync");
+  chk(strom::dev::launch_unpack_svec(q, int(nl), d_ids, s->boff, s->bsz, sv, d_od, d_dense), "unpack");
+  chk(strom::dev::launch_eig_dense(q, false, int(nl), mx, d_nd, d_od, d_dense, d_wo, d_w, d_v, s->ctx->err_flag),
+      "eigenvalues");
+  chk(hipStreamSynchronize(q), "hipStreamSynchronize");
+  w.resize(size_t(tn));
+  chk(hipMemcpy(w.data(), d_w, sizeof(double) * size_t(tn), hipMemcpyDeviceToHost), "download");
+  if (want_v) {
+    v.resize(size_t(tn2));
+    chk(hipMemcpy(v.data(), d_v, sizeof(double) * size_t(tn2), hipMemcpyDeviceToHost), "download");
+  }
+  hipFree(buf);
+  if (st != STROM_OK) return fail(st, msg);
+  return STROM_OK;
+}
+}  // namespace
+
+extern "C" strom_status strom_dual_bound(strom_sdp *s, const double *R_beta, double *lb, double *lam_min) {
+  if (!s || !R_beta || !lb) return fail(STROM_E_INVAL, "bad argument");
+  strom_info inf{};
+  const strom_status kst = strom_kkt_residuals(s, &inf);  // <b, y> of the current iterate
+  if (kst != STROM_OK) return kst;
+  {
+    std::lock_guard<std::recursive_mutex> dl(device_lock());
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    // Z = C - A^* y into the X_b work buffer (free between iterations)
+    HIP_TRY(strom::dev::launch_slack(s->stream, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->C, s->Xb));
+  }
+  std::vector<int32_t> all(size_t(s->nblocks));
+  for (int32_t k = 0; k < s->nblocks; ++k) all[size_t(k)] = k;
+  std::vector<double> w, v;
+  const strom_status est = block_eigs(s, s->Xb, all, false, w, v);
+  if (est != STROM_OK) return est;
+  double bound = inf.dobj;
+  int64_t wo = 0;
+  for (int32_t k = 0; k < s->nblocks; ++k) {
+    const double lmin = w[size_t(wo)];
+    if (lam_min) lam_min[k] = lmin;
+    bound += R_beta[k] * std::min(0.0, lmin);
+    wo += s->bsize_h[size_t(k)];
+  }
+  *lb = bound;
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_extract(strom_sdp *s, int32_t nlist, const int32_t *blocks, double *lam, double *vtop) {
+  if (!s || nlist < 0 || (nlist > 0 && (!blocks || !lam || !vtop))) return fail(STROM_E_INVAL, "bad argument");
+  if (nlist == 0) return STROM_OK;
+  std::vector<int32_t> list(blocks, blocks + nlist);
+  for (int32_t b : list)
+    if (b < 0 || b >= s->nblocks) return fail(STROM_E_INVAL, "block index out of range");
+  std::vector<double> w, v;
+  const strom_status est = block_eigs(s, s->X, list, true, w, v);
+  if (est != STROM_OK) return est;
+  int64_t wo = 0, vo = 0, out = 0;
+  for (int32_t k = 0; k < nlist; ++k) {
+    const int32_t n = s->bsize_h[size_t(list[size_t(k)])];
+    lam[2 * k] = w[size_t(wo + n - 1)];
+    lam[2 * k + 1] = n >= 2 ? w[size_t(wo + n - 2)] : 0.0;
+    const double *top = v.data() + vo + int64_t(n - 1) * n;  // eigenvector of the largest eigenvalue
+    double scale = top[0];
+    if (scale == 0.0) {  // no leading entry to normalize by: unit norm, largest entry positive
+      int ia = 0;
+      for (int i = 1; i < n; ++i)
+        if (std::fabs(top[i]) > std::fabs(top[ia])) ia = i;
+      scale = top[ia] < 0 ? -1.0 : 1.0;
+    }
+    for (int i = 0; i < n; ++i) vtop[out + i] = top[i] / scale;
+    wo += n;
+    vo += int64_t(n) * n;
+    out += n;
+  }
+  return STROM_OK;
+}
+
 extern "C" strom_status strom_submit(strom_ctx *ctx, const strom_problem *P, const strom_opts *opts,
                                      uint64_t *ticket) {
   if (!ctx || !P || !ticket) return fail(STROM_E_INVAL, "NULL argument");

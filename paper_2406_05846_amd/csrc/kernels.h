@@ -67,6 +67,16 @@ hipError_t launch_xb(hipStream_t s, int64_t n, const int64_t *trp, const int32_t
 hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const int32_t *ids, const int64_t *boff,
                                const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale,
                                double *Q, const int64_t *qoff, bool warm);
+// Eigenvalues (ascending, at w + woff[k]) and, with v != nullptr, eigenvectors (columns of an
+// n x n block at v + od[k]) of dense column-major blocks; err as for launch_project_dense.
+hipError_t launch_eig_dense(hipStream_t s, bool f32, int nblocks, int max_n, const int32_t *nd, const int64_t *od,
+                            const void *in, const int64_t *woff, void *w, void *v, int32_t *err);
+// Dense n x n column-major double copies of the svec blocks ids[k] (at out + od[k]).
+hipError_t launch_unpack_svec(hipStream_t s, int count, const int32_t *ids, const int64_t *boff, const int32_t *bsz,
+                              const double *sv, const int64_t *od, double *out);
+// Z = C - A^* y (svec), A^* through the CSR of A^T.
+hipError_t launch_slack(hipStream_t s, int64_t n, const int64_t *trp, const int32_t *tci, const double *tv,
+                        const double *y, const double *C, double *Z);
 hipError_t launch_project_dense(hipStream_t s, bool f32, int nblocks, int max_n, const int32_t *nd, const int64_t *od,
                                 const void *in, void *out, int32_t *err);
 hipError_t launch_xupdate(hipStream_t s, int64_t n, const int64_t *trp, const int32_t *tci, const double *tv,

@@ -394,6 +394,23 @@ hipError_t launch_xb(hipStream_t s, int64_t n, const int64_t *trp, const int32_t
   return hipGetLastError();
 }
 
+// Dual slack of the certificate's lower bound: Z = C - A^* y.
+__global__ void __launch_bounds__(256) k_slack(int64_t n, const int64_t *__restrict__ trp, const int32_t *__restrict__ tci,
+                                               const double *__restrict__ tv, const double *__restrict__ y,
+                                               const double *__restrict__ C, double *__restrict__ Z) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double aty = 0.0;
+  for (int64_t p = trp[c]; p < trp[c + 1]; ++p) aty += tv[p] * y[tci[p]];
+  Z[c] = C[c] - aty;
+}
+
+hipError_t launch_slack(hipStream_t s, int64_t n, const int64_t *trp, const int32_t *tci, const double *tv,
+                        const double *y, const double *C, double *Z) {
+  hipLaunchKernelGGL(k_slack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, trp, tci, tv, y, C, Z);
+  return hipGetLastError();
+}
+
 hipError_t launch_xupdate(hipStream_t s, int64_t n, const int64_t *trp, const int32_t *tci, const double *tv,
                           const double *y, const double *S, const double *C, const DevState *st, double *X,
                           double *part, int update) {

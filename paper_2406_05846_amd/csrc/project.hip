@@ -375,7 +375,7 @@ __device__ inline double block_mass(const T *A, int nblk, int b, int I, int J, b
 // parameters (look-ahead) while the other threads rotate the eigenvector pairs in place and the
 // 2x2 blocks, storing them to their permuted places (in the other buffer; single-buffered, the
 // stores wait for one more barrier).  With few threads (no split) every thread does all three.
-template <typename T, bool BIG>
+template <typename T, bool BIG, bool WANT_V = true>
 __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *rot, double *rotd, double *red,
                                           bool v_ready, int &rfin) {
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -406,7 +406,7 @@ __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *
     vcp[j] = k < np2 ? logical_index(2 * k, 0, mm) * n : 0;
     vcq[j] = k < np2 ? logical_index(2 * k + 1, 0, mm) * n : 0;
   }
-  if (!v_ready)
+  if (WANT_V && !v_ready)
     for (int k = tid; k < n * nn; k += nth) V[k] = (k % (n + 1) == 0 && k / n < n) ? 1.0 : 0.0;
   double f2 = 0.0;
   if (I0 >= 0) f2 += block_mass<T>(Ab, nblk, b0, I0, J0, true);
@@ -431,7 +431,7 @@ __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *
       if (!split || tid < 64)
         next_rotations<T>(np2, nblk, skip, A, rc, rot + ((g + 1) & 1) * 4 * np2, rotd + ((g + 1) & 1) * 2 * np2, tid,
                           split ? 64 : nth);
-      if (wt >= 0) {
+      if (WANT_V && wt >= 0) {
 #pragma unroll
         for (int j = 0; j < kMaxVs; ++j) {  // eigenvector columns of slot k, in place
           const int k = vk0 + j * vks;
@@ -603,6 +603,76 @@ __global__ void __launch_bounds__(1024) k_project_dense(int32_t nblocks, const i
   }
 }
 
+// strom_eig_batched: eigenvalues of every block in ascending order (ties by index) at
+// w + woff[k], and with WANT_V the eigenvectors as the columns of an n x n column-major block at
+// v + od[k] (column j for eigenvalue j).  Without WANT_V the eigenvector work is skipped.
+template <typename T, bool BIG, bool WANT_V>
+__global__ void __launch_bounds__(1024) k_eig_dense(int32_t nblocks, const int32_t *__restrict__ nd,
+                                                    const int64_t *__restrict__ od, const T *__restrict__ in,
+                                                    const int64_t *__restrict__ woff, T *__restrict__ w,
+                                                    T *__restrict__ v, int32_t max_n, int32_t *__restrict__ err,
+                                                    uint32_t lds_cap) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const int32_t bk = blockIdx.x;
+  const int n = nd[bk];
+  const int64_t off = od[bk];
+  if (n <= 0 || n > max_n) {
+    if (threadIdx.x == 0) atomicOr(err, 1);
+    return;
+  }
+  const int nn = n + (n & 1), np2 = nn / 2, nblk = np2 * (np2 + 1) / 2, mm = nn - 1;
+  const int nth = blockDim.x, tid = threadIdx.x;
+  Smem sm = carve<T>(smem, n, lds_cap);
+  T *Ab = reinterpret_cast<T *>(sm.A);
+  for (int e = tid; e < nn * (nn + 1) / 2; e += nth) {
+    int x, y;
+    tri_ij(e, x, y);
+    const int i = logical_index(x, 0, mm), j = logical_index(y, 0, mm);
+    store_entry<T>(Ab, nblk, x, y, (i < n && j < n) ? in[off + i + (int64_t)j * n] : T(0));
+  }
+  __syncthreads();
+  int rfin = 0;
+  const int cur = jacobi_eig<T, BIG, WANT_V>(n, Ab, sm.nbuf, sm.V, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red,
+                                             false, rfin);
+  const T *A = Ab + (size_t)cur * 4 * nblk;
+  for (int x = tid; x < nn; x += nth) sm.lam[logical_index(x, rfin, mm)] = (double)diag_entry(A, nblk, x);
+  __syncthreads();
+  for (int i = tid; i < n; i += nth) {  // the rank of eigenvalue i among the n real ones
+    const double li = sm.lam[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = sm.lam[j];
+      rank += (lj < li || (lj == li && j < i)) ? 1 : 0;
+    }
+    w[woff[bk] + rank] = (T)li;
+    sm.sel[i] = rank;
+  }
+  if constexpr (WANT_V) {
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nth) {
+      const int r = e % n, i = e / n;
+      v[off + r + (int64_t)sm.sel[i] * n] = (T)sm.V[i * n + r];
+    }
+  }
+}
+
+// Dense n x n column-major copies (both triangles) of listed svec blocks: block ids[k] of the
+// svec vector at boff, into out + od[k].
+__global__ void __launch_bounds__(256) k_unpack_svec(const int32_t *__restrict__ ids, const int64_t *__restrict__ boff,
+                                                     const int32_t *__restrict__ bsz, const double *__restrict__ sv,
+                                                     const int64_t *__restrict__ od, double *__restrict__ out) {
+  const int32_t bk = ids[blockIdx.x];
+  const int n = bsz[bk];
+  const double rs2 = 0.70710678118654752440;
+  const double *src = sv + boff[bk];
+  double *dst = out + od[blockIdx.x];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e % n, j = e / n;
+    const double x = src[pidx(i, j)];
+    dst[e] = i == j ? x : x * rs2;
+  }
+}
+
 size_t project_lds_bytes(int n, bool f32, int nthreads) {
   (void)nthreads;
   return lds_bytes_for(n, f32 ? sizeof(float) : sizeof(double));
@@ -681,6 +751,46 @@ hipError_t launch_project_dense(hipStream_t s, bool f32, int nblocks, int max_n,
     if (big) launch_dense_t<double, true>(s, nblocks, nt, lds, max_n, nd, od, in, out, err);
     else launch_dense_t<double, false>(s, nblocks, nt, lds, max_n, nd, od, in, out, err);
   }
+  return hipGetLastError();
+}
+
+template <typename T, bool BIG, bool WANT_V>
+static void launch_eig_t(hipStream_t s, int nblocks, int nt, size_t lds, int max_n, const int32_t *nd,
+                         const int64_t *od, const void *in, const int64_t *woff, void *w, void *v, int32_t *err) {
+  (void)hipFuncSetAttribute((const void *)k_eig_dense<T, BIG, WANT_V>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL((k_eig_dense<T, BIG, WANT_V>), dim3(nblocks), dim3(nt), lds, s, nblocks, nd, od, (const T *)in,
+                     woff, (T *)w, (T *)v, max_n, err, (uint32_t)lds);
+}
+
+template <typename T>
+static void launch_eig_v(bool big, bool want_v, hipStream_t s, int nblocks, int nt, size_t lds, int max_n,
+                         const int32_t *nd, const int64_t *od, const void *in, const int64_t *woff, void *w, void *v,
+                         int32_t *err) {
+  if (big) {
+    if (want_v) launch_eig_t<T, true, true>(s, nblocks, nt, lds, max_n, nd, od, in, woff, w, v, err);
+    else launch_eig_t<T, true, false>(s, nblocks, nt, lds, max_n, nd, od, in, woff, w, v, err);
+  } else {
+    if (want_v) launch_eig_t<T, false, true>(s, nblocks, nt, lds, max_n, nd, od, in, woff, w, v, err);
+    else launch_eig_t<T, false, false>(s, nblocks, nt, lds, max_n, nd, od, in, woff, w, v, err);
+  }
+}
+
+hipError_t launch_eig_dense(hipStream_t s, bool f32, int nblocks, int max_n, const int32_t *nd, const int64_t *od,
+                            const void *in, const int64_t *woff, void *w, void *v, int32_t *err) {
+  const int nt = project_threads(max_n);
+  const size_t lds = project_lds_bytes(max_n, f32, nt);
+  bool big = false;
+  if (!threads_ok(max_n, nt, f32, big) || lds > kLdsCap) return hipErrorInvalidValue;
+  if (f32) launch_eig_v<float>(big, v != nullptr, s, nblocks, nt, lds, max_n, nd, od, in, woff, w, v, err);
+  else launch_eig_v<double>(big, v != nullptr, s, nblocks, nt, lds, max_n, nd, od, in, woff, w, v, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_svec(hipStream_t s, int count, const int32_t *ids, const int64_t *boff, const int32_t *bsz,
+                              const double *sv, const int64_t *od, double *out) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack_svec, dim3(count), dim3(256), 0, s, ids, boff, bsz, sv, od, out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,113 @@
+"""GPU parity of the certificate entry points (strom_eig_batched, strom_dual_bound,
+strom_extract) with the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2406_05846_amd as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    c = S.Context(0)
+    yield c
+    c.close()
+
+
+def _eig_dense(S, ctx, mats, dtype, want_v):
+    import torch
+    sizes = [m.shape[0] for m in mats]
+    offs = np.concatenate([[0], np.cumsum([n * n for n in sizes])[:-1]]).astype(np.int64)
+    woff = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    x = torch.tensor(np.concatenate([m.reshape(-1, order="F") for m in mats]), dtype=td, device="cuda")
+    w = torch.zeros(sum(sizes), dtype=td, device="cuda")
+    v = torch.zeros_like(x) if want_v else None
+    ctx.eig_batched(torch.tensor(sizes, dtype=torch.int32, device="cuda"), torch.tensor(offs, device="cuda"), x,
+                    torch.tensor(woff, device="cuda"), w, v, max(sizes))
+    torch.cuda.synchronize()
+    wh = w.double().cpu().numpy()
+    ws = [wh[o:o + n] for o, n in zip(woff, sizes)]
+    vs = None
+    if want_v:
+        vh = v.double().cpu().numpy()
+        vs = [vh[o:o + n * n].reshape((n, n), order="F") for o, n in zip(offs, sizes)]
+    return ws, vs
+
+
+SIZES = [1, 2, 3, 7, 8, 12, 13, 36, 55, 78, 91, 105]
+
+
+def test_eig_batched_f64(S, ctx):
+    rng = np.random.default_rng(41)
+    mats = []
+    for n in SIZES:
+        b = rng.standard_normal((n, n))
+        mats.append((b + b.T) / 2)
+    ws, vs = _eig_dense(S, ctx, mats, "f64", True)
+    w_only, _ = _eig_dense(S, ctx, mats, "f64", False)
+    for a, w, v, wo in zip(mats, ws, vs, w_only):
+        n = a.shape[0]
+        na = max(1.0, np.linalg.norm(a))
+        assert np.all(np.diff(w) >= 0)
+        assert np.abs(w - np.linalg.eigvalsh(a)).max() <= 1e-12 * na, n
+        assert np.linalg.norm(a @ v - v * w) <= 1e-12 * na, n
+        assert np.linalg.norm(v.T @ v - np.eye(n)) <= 1e-12 * n, n
+        assert np.array_equal(w, wo)  # the eigenvalues-only mode runs the same rotations
+
+
+def test_eig_batched_f32(S, ctx):
+    rng = np.random.default_rng(42)
+    mats = []
+    for n in SIZES + [120]:
+        b = rng.standard_normal((n, n))
+        mats.append((b + b.T) / 2)
+    ws, _ = _eig_dense(S, ctx, mats, "f32", False)
+    for a, w in zip(mats, ws):
+        a32 = a.astype(np.float32).astype(np.float64)
+        assert np.abs(w - np.linalg.eigvalsh(a32)).max() <= 2e-5 * max(1.0, np.linalg.norm(a32)), a.shape[0]
+
+
+@pytest.mark.parametrize("fam,N,prm", [(1, 10, [0.5, 0.0]), (2, 4, [0.1, 0.2, 0.5, 0.3])])
+def test_dual_bound_vs_oracle(S, ctx, orc, fam, N, prm):
+    osdp = orc.relax(fam, N, prm)
+    inst = S.Instance(ctx, S.generate(fam, N, prm), S.default_opts(sigma_every=0, tol=0.0))
+    inst.step(30)
+    _, y, _ = inst.get_iterate()
+    R = np.linspace(1.0, 3.0, osdp.nblocks)
+    lb, lam = inst.dual_bound(R)
+    lb_o, lam_o = orc.dual_bound(osdp, y, R)
+    scale = 1.0 + np.abs(lam_o).max()
+    assert np.abs(lam - lam_o).max() <= 1e-10 * scale
+    assert abs(lb - lb_o) <= 1e-10 * (1.0 + abs(lb_o))
+    inst.close()
+
+
+@pytest.mark.parametrize("fam,N,prm", [(1, 6, [0.5, 0.0]), (4, 3, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1])])
+def test_extract_vs_oracle_on_a_lifting(S, ctx, orc, fam, N, prm):
+    osdp = orc.relax(fam, N, prm)
+    rng = np.random.default_rng(9)
+    z, _ = orc.rollout(fam, N, prm, rng.uniform(-0.5, 0.5, N * osdp.du), osdp.dx, osdp.du)
+    X, _ = orc.lift(fam, N, prm, z)
+    inst = S.Instance(ctx, S.generate(fam, N, prm))
+    inst.set_iterate(X=X)
+    blocks = [k for k in range(osdp.nblocks) if osdp.bkind[k] == 0] + [1]  # moment blocks and one localizing
+    lam, vt = inst.extract(blocks, [int(osdp.bsize[k]) for k in blocks])
+    lam_o, vt_o = orc.extract(osdp, X, blocks)
+    assert np.abs(lam - lam_o).max() <= 1e-11 * (1.0 + np.abs(lam_o).max())
+    d, step = osdp.nclique_vars, osdp.dx + osdp.du
+    for t, k in enumerate(blocks):
+        if osdp.bkind[k] != 0:
+            continue
+        assert lam[t, 1] <= 1e-11 * lam[t, 0]
+        assert np.allclose(vt[t], vt_o[t], atol=1e-9)
+        c = int(osdp.bclique[k])
+        assert np.allclose(vt[t][1:1 + d], z[c * step: c * step + d], atol=1e-9)
+    inst.close()

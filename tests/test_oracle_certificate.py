@@ -1,0 +1,86 @@
+"""Pins of the oracle's certificate pieces (oracle/cert.c), against what the paper and the
+mathematics fix:
+
+* the valid lower bound (refined certificate of suboptimality, Sec. "Algorithmic Backbone"):
+  lb(y) <= <C, X(z)> = f(z) for ANY y and any feasible z, once R_beta bounds the traces of the
+  rank-one lifting's blocks (here R_beta = those traces, and twice them);
+* at y = 0 the bound is sum_beta R_beta min(0, lambda_min(C_beta)), checked against numpy's
+  eigvalsh (a library routine, independent of the oracle's Jacobi);
+* extraction (Sec. "Sparse Moment Relaxation"): the moment blocks of the lifting X(z) are rank
+  one, and the top eigenvector scaled to first entry 1 carries z's clique variables as its
+  degree-one entries (the basis is graded, degree one in variable order).
+"""
+import numpy as np
+import pytest
+
+CASES = [("PENDULUM", 4, [0.5, 0.0]), ("CARTPOLE", 3, [0.1, 0.2, 0.5, 0.3]),
+         ("CAR", 3, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1])]
+
+
+def _block_traces(sdp, X):
+    tr, off = [], 0
+    for n in sdp.bsize:
+        n = int(n)
+        tr.append(sum(X[off + j * (j + 1) // 2 + j] for j in range(n)))
+        off += n * (n + 1) // 2
+    return np.array(tr)
+
+
+def _feasible(orc, f, N, prm, seed):
+    sdp = orc.relax(f, N, prm)
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-0.5, 0.5, N * sdp.du)
+    z, obj = orc.rollout(f, N, prm, u, sdp.dx, sdp.du)
+    X, _ = orc.lift(f, N, prm, z)
+    return sdp, z, X, obj
+
+
+@pytest.mark.parametrize("fam,N,prm", CASES)
+def test_dual_bound_below_feasible_objective(orc, fam, N, prm):
+    f = getattr(orc, fam)
+    sdp, z, X, obj = _feasible(orc, f, N, prm, 3)
+    tr = _block_traces(sdp, X)
+    assert np.all(tr >= -1e-12)
+    rng = np.random.default_rng(11)
+    for scale in [0.1, 1.0, 10.0]:
+        y = scale * rng.standard_normal(sdp.m)
+        for R in (tr, 2.0 * tr):
+            lb, lam = orc.dual_bound(sdp, y, R)
+            assert lb <= obj + 1e-9 * (1 + abs(obj)), (scale, lb, obj)
+        # the bound decomposes as <b,y> + sum R min(0, lam)
+        assert abs(lb - (sdp.b @ y + np.sum(2.0 * tr * np.minimum(0.0, lam)))) <= 1e-9 * (1 + abs(lb))
+
+
+def test_dual_bound_at_zero_is_the_spectrum_of_C(orc):
+    sdp = orc.relax(orc.PENDULUM, 3, [0.5, 0.0])
+    R = np.linspace(1.0, 2.0, sdp.nblocks)
+    lb, lam = orc.dual_bound(sdp, np.zeros(sdp.m), R)
+    off, ref = 0, []
+    for n in sdp.bsize:
+        n = int(n)
+        a = np.zeros((n, n))
+        for j in range(n):
+            for i in range(j + 1):
+                v = sdp.C[off + j * (j + 1) // 2 + i] * (1.0 if i == j else np.sqrt(0.5))
+                a[i, j] = a[j, i] = v
+        ref.append(np.linalg.eigvalsh(a)[0])
+        off += n * (n + 1) // 2
+    ref = np.array(ref)
+    assert np.allclose(lam, ref, atol=1e-12 * max(1.0, np.abs(sdp.C).max()))
+    assert abs(lb - np.sum(R * np.minimum(0.0, ref))) <= 1e-12 * (1 + abs(lb))
+
+
+@pytest.mark.parametrize("fam,N,prm", CASES)
+def test_extract_recovers_the_lifted_point(orc, fam, N, prm):
+    f = getattr(orc, fam)
+    sdp, z, X, _ = _feasible(orc, f, N, prm, 5)
+    moment = [k for k in range(sdp.nblocks) if sdp.bkind[k] == 0]
+    assert len(moment) == N
+    lam, vt = orc.extract(sdp, X, moment)
+    d, step = sdp.nclique_vars, sdp.dx + sdp.du
+    for t, k in enumerate(moment):
+        assert lam[t, 1] <= 1e-12 * lam[t, 0]  # rank one
+        clique = int(sdp.bclique[k])
+        zk = z[clique * step: clique * step + d]
+        assert abs(vt[t][0] - 1.0) <= 1e-14
+        assert np.allclose(vt[t][1:1 + d], zk, atol=1e-10 * max(1.0, np.abs(zk).max()))
