@@ -134,6 +134,43 @@ def _batched(S, W, torch, args) -> dict:
     return out
 
 
+def _warm_start(S, W, np, ctx, args) -> dict:
+    """Receding-horizon re-solve (pendulum N=10): after a solve, the next problem starts from the
+    state one step later (read from the extracted degree-one moments of clique 0); it is solved
+    from zero (cold) and from the previous solution shifted by one clique (warm)."""
+    import math
+    rows = []
+    for k in range(args.warm):
+        p0 = W.instance_params(W.PENDULUM, args.seed + k)
+        ins0 = S.Instance(ctx, S.generate(W.PENDULUM, 10, p0))
+        ins0.step(50000)
+        X, _, Sv = ins0.get_iterate()
+        _, vt = ins0.extract([0], [36])
+        ins0.close()
+        rc1, rs1, w1 = vt[0][5], vt[0][6], vt[0][7]  # clique 0: (rc, rs, w, u, rc', rs', w'), w scaled by 1/8
+        prob1 = S.generate(W.PENDULUM, 10, [math.atan2(rs1, rc1), 8.0 * w1])
+        bs = [int(n) for n in prob1.block_sizes]
+        out = {}
+        for label, X0, S0 in (("cold", None, None), ("warm", W.shift_one_clique(bs, X), W.shift_one_clique(bs, Sv))):
+            ins = S.Instance(ctx, prob1)
+            if X0 is not None:
+                ins.set_iterate(X=X0, S=S0)
+            t = time.perf_counter()
+            inf = ins.step(50000)
+            out[label] = (time.perf_counter() - t, int(inf["iters"]), int(inf["state"]), inf["pobj"])
+            ins.close()
+        rows.append(out)
+        _log(f"warm start {k}: cold {out['cold'][1]} its {out['cold'][0]:.3f} s, warm {out['warm'][1]} its "
+             f"{out['warm'][0]:.3f} s")
+    res = {"workload": f"pendulum N=10, {args.warm} receding-horizon steps (seeds {args.seed}..{args.seed + args.warm - 1}): "
+                       "the problem one step later, solved to eta <= 1e-6 from zero and from the previous "
+                       "solution shifted by one clique",
+           "cold_iters": [r["cold"][1] for r in rows], "warm_iters": [r["warm"][1] for r in rows],
+           "cold_s": [round(r["cold"][0], 4) for r in rows], "warm_s": [round(r["warm"][0], 4) for r in rows],
+           "converged": sum(r["cold"][2] == S.CONVERGED and r["warm"][2] == S.CONVERGED for r in rows)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +180,7 @@ def main():
     ap.add_argument("--solves", type=int, default=8, help="pendulum solves timed for solves/s and latency")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving sample (0: skip)")
     ap.add_argument("--batch", type=int, default=8, help="instances of the batched form (0: skip)")
+    ap.add_argument("--warm", type=int, default=3, help="receding-horizon warm-start steps (0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-only", action="store_true", help="only the serving sample")
@@ -256,6 +294,7 @@ def main():
 
     serving = _serving(S, W, np, ctx, args) if args.serve > 0 else None
     batched = _batched(S, W, torch, args) if args.batch > 0 else None
+    warm = _warm_start(S, W, np, ctx, args) if args.warm > 0 else None
 
     flops = _proj_flops(prob.block_sizes)
     proj_s = prof["project_ms"] * 1e-3
@@ -289,6 +328,7 @@ def main():
         "serving": serving,
         "batched": batched,
         "certificate": cert,
+        "warm_start": warm,
         "phase_ms": {k: round(v, 4) for k, v in prof.items()},
         "roofline": {"bound": "alu", "kernel": "k_project_admm<double> (every PSD block of one iteration)",
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

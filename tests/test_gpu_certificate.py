@@ -111,3 +111,27 @@ def test_extract_vs_oracle_on_a_lifting(S, ctx, orc, fam, N, prm):
         c = int(osdp.bclique[k])
         assert np.allclose(vt[t][1:1 + d], z[c * step: c * step + d], atol=1e-9)
     inst.close()
+
+
+def test_warm_started_resolve_reaches_the_cold_optimum(S, ctx):
+    """Receding-horizon step: the problem one step later, solved from the previous solution
+    shifted by one clique, converges to the optimum of the cold solve."""
+    import math
+    import workloads as W
+    ins0 = S.Instance(ctx, S.generate(W.PENDULUM, 8, [0.8, 0.0]))
+    assert ins0.step(50000)["state"] == S.CONVERGED
+    X, _, Sv = ins0.get_iterate()
+    _, vt = ins0.extract([0], [36])
+    ins0.close()
+    prob1 = S.generate(W.PENDULUM, 8, [math.atan2(vt[0][6], vt[0][5]), 8.0 * vt[0][7]])
+    bs = [int(n) for n in prob1.block_sizes]
+    res = {}
+    for label, X0, S0 in (("cold", None, None), ("warm", W.shift_one_clique(bs, X), W.shift_one_clique(bs, Sv))):
+        ins = S.Instance(ctx, prob1)
+        if X0 is not None:
+            ins.set_iterate(X=X0, S=S0)
+        res[label] = ins.step(50000)
+        ins.close()
+    assert res["cold"]["state"] == S.CONVERGED and res["warm"]["state"] == S.CONVERGED
+    pc, pw = res["cold"]["pobj"], res["warm"]["pobj"]
+    assert abs(pw - pc) <= 1e-4 * (1.0 + abs(pc))

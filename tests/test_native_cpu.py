@@ -91,3 +91,18 @@ def test_workloads_are_seeded():
     r = W.poisson_arrivals(0, 100.0, 1.0)
     ts = [t for t, *_ in r]
     assert ts == sorted(ts) and 50 < len(ts) < 150
+
+
+def test_shift_one_clique_moves_whole_cliques():
+    """The receding-horizon warm start moves clique k+1's blocks to clique k and repeats the
+    last clique (blocks in clique order, the moment block of each clique first)."""
+    import workloads as W
+    sizes = [5, 2, 2, 5, 2, 2, 5, 2, 2]  # three cliques: one moment block and two localizing each
+    lens = [n * (n + 1) // 2 for n in sizes]
+    x = np.arange(float(sum(lens)))
+    per = sum(lens[:3])
+    out = W.shift_one_clique(sizes, x)
+    assert out.shape == x.shape
+    assert np.array_equal(out[:per], x[per:2 * per])
+    assert np.array_equal(out[per:2 * per], x[2 * per:])
+    assert np.array_equal(out[2 * per:], x[2 * per:])

@@ -123,3 +123,16 @@ def poisson_arrivals(seed: int, rate: float, duration: float, mix=(0.4, 0.4, 0.2
         reqs.append((t, fam, N, instance_params(fam, seed * 1000003 + i)))
         i += 1
     return reqs
+
+
+def shift_one_clique(block_sizes, svec):
+    """Warm start of the next receding-horizon problem: the svec blocks of cliques 1 .. N-1
+    moved to cliques 0 .. N-2 and the last clique's blocks repeated (blocks are in clique order,
+    each clique's moment block, the largest, first).  Data movement only."""
+    import numpy as np
+    sizes = [int(n) for n in block_sizes]
+    big = max(sizes)
+    offs = np.concatenate([[0], np.cumsum([n * (n + 1) // 2 for n in sizes])]).astype(np.int64)
+    starts = [k for k, n in enumerate(sizes) if n == big] + [len(sizes)]
+    cliques = [svec[offs[a]:offs[b]] for a, b in zip(starts[:-1], starts[1:])]
+    return np.concatenate(cliques[1:] + cliques[-1:])
