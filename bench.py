@@ -137,13 +137,15 @@ def _batched(S, W, torch, args) -> dict:
 def _warm_start(S, W, np, ctx, args) -> dict:
     """Receding-horizon re-solve (pendulum N=10): after a solve, the next problem starts from the
     state one step later (read from the extracted degree-one moments of clique 0); it is solved
-    from zero (cold) and from the previous solution shifted by one clique (warm)."""
+    from zero (cold) and from the previous solution shifted by one clique with the previous
+    solve's final sigma as sigma0 (warm).  y needs no warm start: step 1 of Algorithm 1 computes
+    it from X and S."""
     import math
     rows = []
     for k in range(args.warm):
         p0 = W.instance_params(W.PENDULUM, args.seed + k)
         ins0 = S.Instance(ctx, S.generate(W.PENDULUM, 10, p0))
-        ins0.step(50000)
+        sig = ins0.step(50000)["sigma"]
         X, _, Sv = ins0.get_iterate()
         _, vt = ins0.extract([0], [36])
         ins0.close()
@@ -152,7 +154,7 @@ def _warm_start(S, W, np, ctx, args) -> dict:
         bs = [int(n) for n in prob1.block_sizes]
         out = {}
         for label, X0, S0 in (("cold", None, None), ("warm", W.shift_one_clique(bs, X), W.shift_one_clique(bs, Sv))):
-            ins = S.Instance(ctx, prob1)
+            ins = S.Instance(ctx, prob1, None if X0 is None else S.default_opts(sigma0=sig))
             if X0 is not None:
                 ins.set_iterate(X=X0, S=S0)
             t = time.perf_counter()
@@ -164,7 +166,7 @@ def _warm_start(S, W, np, ctx, args) -> dict:
              f"{out['warm'][0]:.3f} s")
     res = {"workload": f"pendulum N=10, {args.warm} receding-horizon steps (seeds {args.seed}..{args.seed + args.warm - 1}): "
                        "the problem one step later, solved to eta <= 1e-6 from zero and from the previous "
-                       "solution shifted by one clique",
+                       "solution shifted by one clique with the previous final sigma",
            "cold_iters": [r["cold"][1] for r in rows], "warm_iters": [r["warm"][1] for r in rows],
            "cold_s": [round(r["cold"][0], 4) for r in rows], "warm_s": [round(r["warm"][0], 4) for r in rows],
            "converged": sum(r["cold"][2] == S.CONVERGED and r["warm"][2] == S.CONVERGED for r in rows)}

@@ -1,5 +1,7 @@
 """GPU parity of the certificate entry points (strom_eig_batched, strom_dual_bound,
 strom_extract) with the oracle, through the C ABI."""
+import time
+
 import numpy as np
 import pytest
 
@@ -115,11 +117,13 @@ def test_extract_vs_oracle_on_a_lifting(S, ctx, orc, fam, N, prm):
 
 def test_warm_started_resolve_reaches_the_cold_optimum(S, ctx):
     """Receding-horizon step: the problem one step later, solved from the previous solution
-    shifted by one clique, converges to the optimum of the cold solve."""
+    shifted by one clique and the previous final sigma, converges to the optimum of the cold
+    solve."""
     import math
     import workloads as W
     ins0 = S.Instance(ctx, S.generate(W.PENDULUM, 8, [0.8, 0.0]))
-    assert ins0.step(50000)["state"] == S.CONVERGED
+    r0 = ins0.step(50000)
+    assert r0["state"] == S.CONVERGED
     X, _, Sv = ins0.get_iterate()
     _, vt = ins0.extract([0], [36])
     ins0.close()
@@ -127,7 +131,7 @@ def test_warm_started_resolve_reaches_the_cold_optimum(S, ctx):
     bs = [int(n) for n in prob1.block_sizes]
     res = {}
     for label, X0, S0 in (("cold", None, None), ("warm", W.shift_one_clique(bs, X), W.shift_one_clique(bs, Sv))):
-        ins = S.Instance(ctx, prob1)
+        ins = S.Instance(ctx, prob1, None if X0 is None else S.default_opts(sigma0=r0["sigma"]))
         if X0 is not None:
             ins.set_iterate(X=X0, S=S0)
         res[label] = ins.step(50000)
@@ -135,3 +139,14 @@ def test_warm_started_resolve_reaches_the_cold_optimum(S, ctx):
     assert res["cold"]["state"] == S.CONVERGED and res["warm"]["state"] == S.CONVERGED
     pc, pw = res["cold"]["pobj"], res["warm"]["pobj"]
     assert abs(pw - pc) <= 1e-4 * (1.0 + abs(pc))
+    # the same warm start through the request loop: X0 and S0 in the problem, sigma0 in opts
+    warm_prob = S.Problem(prob1.block_sizes, prob1.rowptr, prob1.col, prob1.val, prob1.b, prob1.C,
+                          X0=W.shift_one_clique(bs, X), S0=W.shift_one_clique(bs, Sv))
+    t = ctx.submit(warm_prob, S.default_opts(sigma0=r0["sigma"]))
+    t0 = time.time()
+    while (r := ctx.poll(t)) is None:
+        assert time.time() - t0 < 60, "request loop did not finish"
+        time.sleep(0.01)
+    assert r[0]["state"] == S.CONVERGED
+    assert r[0]["iters"] == res["warm"]["iters"]
+    assert abs(r[0]["pobj"] - pw) <= 1e-9 * (1.0 + abs(pw))

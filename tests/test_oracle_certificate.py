@@ -84,3 +84,23 @@ def test_extract_recovers_the_lifted_point(orc, fam, N, prm):
         zk = z[clique * step: clique * step + d]
         assert abs(vt[t][0] - 1.0) <= 1e-14
         assert np.allclose(vt[t][1:1 + d], zk, atol=1e-10 * max(1.0, np.abs(zk).max()))
+
+
+def test_warm_start_shifted_horizon_reaches_the_cold_optimum(orc):
+    """Receding horizon: the problem one step later (initial state from the extracted z of
+    clique 0), started from the previous X and S shifted by one clique and the previous final
+    sigma, converges to the optimum of the cold start (Algorithm 1 takes any X0, S0 and sigma0)."""
+    import math
+    import workloads as W
+    N = 6
+    sdp0 = orc.relax(W.PENDULUM, N, [2.0, 0.0])
+    r0 = orc.admm_solve(sdp0, tol=1e-7, maxiter=50000)
+    assert r0["converged"]
+    _, vt = orc.extract(sdp0, r0["X"], [0])
+    sdp1 = orc.relax(W.PENDULUM, N, [math.atan2(vt[0][6], vt[0][5]), 8.0 * vt[0][7]])
+    bs = [int(n) for n in sdp1.bsize]
+    cold = orc.admm_solve(sdp1, tol=1e-7, maxiter=50000)
+    warm = orc.admm_solve(sdp1, X0=W.shift_one_clique(bs, r0["X"]), S0=W.shift_one_clique(bs, r0["S"]),
+                          sigma0=r0["sigma"], tol=1e-7, maxiter=50000)
+    assert cold["converged"] and warm["converged"]
+    assert abs(warm["pobj"] - cold["pobj"]) <= 1e-5 * (1.0 + abs(cold["pobj"]))
