@@ -105,31 +105,56 @@ def _serving(S, W, np, ctx, args) -> dict:
 
 
 def _batched(S, W, torch, args) -> dict:
-    """Batched form: K cart-pole N=30 instances (seeds seed .. seed+K-1) advanced together,
-    each on a context with its own stream (rounds replayed from HIP graphs), aggregate
-    instance-iterations per second of the timed region (after a warmup on every instance)."""
-    K, iters = args.batch, 200
-    ctxs, insts = [], []
-    for k in range(K):
-        c = S.Context(0, stream=torch.cuda.Stream())
-        ctxs.append(c)
-        pr = S.generate(W.CARTPOLE, 30, W.instance_params(W.CARTPOLE, args.seed + k))
-        insts.append(S.Instance(c, pr, S.default_opts(tol=0.0, maxiter=10**9)))
-    for ins in insts:
-        ins.enqueue(args.warmup)
-    torch.cuda.synchronize()
+    """Batched form: a mixed batch of instances (families uniform over pendulum, cart-pole, car;
+    horizons N ~ U{10..60}) advanced together by merged launches (one per step over all
+    instances, rounds replayed from HIP graphs), FP32 projection with the FP64 polish, FP64
+    solves and residuals, after the projection autotuner.  Beside it, a sample of the same
+    problems stepped one instance at a time in the FP64 per-instance form."""
+    from concurrent.futures import ThreadPoolExecutor
+    K, iters = args.batch, 50
+    cases = W.mixed_batch(args.seed, count=K, nmin=10, nmax=60)
     t0 = time.perf_counter()
-    for ins in insts:
-        ins.enqueue(iters)
+    probs = [S.generate(f, N, p) for f, N, p in cases]
+    t1 = time.perf_counter()
+    ctx = S.Context(0)
+    opts = S.default_opts(tol=0.0, maxiter=10**9, proj_dtype="f32")
+    with ThreadPoolExecutor(max_workers=16) as ex:  # the host analysis runs outside the GIL
+        insts = list(ex.map(lambda pr: S.Instance(ctx, pr, opts), probs))
+    t2 = time.perf_counter()
+    _log(f"batched: {K} instances generated in {t1 - t0:.1f} s, set up in {t2 - t1:.1f} s")
+    bat = S.Batch(ctx, insts)
+    bat.step(10)
+    tuned = bat.tune(reps=3)
+    bat.step(args.batch_warmup)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    t3 = time.perf_counter()
+    bat.step(iters)
+    t4 = time.perf_counter()
+    bat.close()
+    nsvec = sum(pr.nsvec for pr in probs)
     for ins in insts:
         ins.close()
-    for c in ctxs:
-        c.close()
-    out = {"workload": f"{K} cart-pole N=30 instances (seeds {args.seed}..{args.seed + K - 1}), FP64, one context "
-                       f"and stream each, {iters} iterations each after {args.warmup} of warmup",
-           "instance_iters_per_s": round(K * iters / dt, 2), "ms_per_iteration_each": round(1e3 * dt / iters, 4)}
+    # the same problems one at a time, FP64 per-instance form
+    sample = probs[:: max(1, K // 16)][:16]
+    t_alone, it_alone = 0.0, 30
+    for pr in sample:
+        ins = S.Instance(ctx, pr, S.default_opts(tol=0.0, maxiter=10**9))
+        ins.step(10)
+        ta = time.perf_counter()
+        ins.step(it_alone)
+        t_alone += time.perf_counter() - ta
+        ins.close()
+    ctx.close()
+    rate = K * iters / (t4 - t3)
+    rate_alone = len(sample) * it_alone / t_alone
+    out = {"workload": f"{K} instances of the mixed batch of seed {args.seed} (pendulum / cart-pole / car uniform, "
+                       f"N ~ U{{10..60}}, total n_svec {nsvec}), FP32 projection + FP64 polish, merged launches, "
+                       f"{iters} timed iterations after {10 + args.batch_warmup} and the autotuner",
+           "instance_iters_per_s": round(rate, 1), "ms_per_batch_iteration": round(1e3 * (t4 - t3) / iters, 3),
+           "setup_s": round(t2 - t1, 2), "tuned_threads": tuned,
+           "per_instance_fp64": {"sample": f"{len(sample)} of the same problems one at a time, {it_alone} "
+                                           f"iterations each", "instance_iters_per_s": round(rate_alone, 1)},
+           "speedup_vs_per_instance_fp64": round(rate / rate_alone, 2)}
     _log(f"batched: {out}")
     return out
 
@@ -181,7 +206,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--solves", type=int, default=8, help="pendulum solves timed for solves/s and latency")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving sample (0: skip)")
-    ap.add_argument("--batch", type=int, default=8, help="instances of the batched form (0: skip)")
+    ap.add_argument("--batch", type=int, default=256, help="instances of the batched form (0: skip)")
+    ap.add_argument("--batch-warmup", type=int, default=20, help="warmup iterations of the batched form")
     ap.add_argument("--warm", type=int, default=3, help="receding-horizon warm-start steps (0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")

@@ -207,6 +207,34 @@ strom_status strom_dual_bound(strom_sdp *sdp, const double *R_beta, double *lb, 
  * device memory.  E_INVAL for an index outside [0, nblocks). */
 strom_status strom_extract(strom_sdp *sdp, int32_t nlist, const int32_t *blocks, double *lam, double *vtop);
 
+/* Merged form: Alg. 1 advanced for many independent instances at once.  A batch groups instances
+ * of one ctx that were set up with the same kkt_every and sigma_every and stand at the same
+ * iteration count; while it exists they are iterated only through it (strom_admm_step,
+ * strom_admm_enqueue, strom_set_iterate and strom_sdp_destroy on them return E_STATE).  Each
+ * step of the iteration is one launch over all instances (a workgroup per row or column chunk,
+ * solve task or PSD block of any instance; the solve's dependency groups are merged by depth),
+ * and a round of kkt_every iterations is captured as a HIP graph.  Every instance keeps its
+ * own arrays, options, sigma, polish switch and state: strom_batch_step advances the running
+ * instances by up to n_iter iterations and retires each one, unchanged from then on, at the
+ * round where it converges, reaches maxiter or diverges, exactly as strom_admm_step would.
+ * instances: host array of count handles (copied).  infos (host, nullable): count entries,
+ * filled as strom_admm_step fills its info.  Synchronizes once per round. */
+typedef struct strom_batch strom_batch;
+strom_status strom_batch_create(strom_ctx *ctx, int32_t count, strom_sdp *const *instances, strom_batch **out);
+strom_status strom_batch_step(strom_batch *batch, int32_t n_iter, strom_info *infos);
+/* Autotuner of the merged projection: for every class of blocks (block size n and default
+ * threads per workgroup, which is the instance's own launch configuration) and each precision
+ * in use, times reps launches of every thread count the kernel accepts for n on the batch's
+ * current iterates and keeps the fastest (the timing launches refresh the kept eigenvectors
+ * and overwrite the X_b scratch, as a sigma-rule projection does).  reps = 0 only reports.
+ * Needs at least one completed iteration (E_STATE otherwise).  Reports up to cap classes: n,
+ * threads per workgroup for FP64 and FP32 (host arrays, nullable), and the class count in
+ * nclass (nullable). */
+strom_status strom_batch_tune(strom_batch *batch, int32_t reps, int32_t cap, int32_t *n, int32_t *nt_f64,
+                              int32_t *nt_f32, int32_t *nclass);
+/* Releases the batch (not its instances, which can be stepped on their own again). */
+strom_status strom_batch_destroy(strom_batch *batch);
+
 /* Serving.  strom_submit copies a problem and queues it; a solver thread owned by the ctx
  * admits queued problems while their device footprint fits the ctx's HBM budget, keeps their
  * iterates on the device, advances every admitted instance, retires an instance when it

@@ -25,6 +25,7 @@ EXPORTS = [
     "strom_kkt_residuals", "strom_get_iterate", "strom_set_iterate", "strom_sdp_sizes",
     "strom_project_psd_batched", "strom_submit", "strom_poll", "strom_profile_iteration",
     "strom_eig_batched", "strom_dual_bound", "strom_extract",
+    "strom_batch_create", "strom_batch_step", "strom_batch_tune", "strom_batch_destroy",
     "strom_gen_build", "strom_gen_sizes", "strom_gen_export", "strom_gen_free",
 ]
 
@@ -85,6 +86,10 @@ def _load():
     L.strom_eig_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, C.c_int, vp]
     L.strom_dual_bound.argtypes = [vp, vp, vp, vp]
     L.strom_extract.argtypes = [vp, i32, vp, vp, vp]
+    L.strom_batch_create.argtypes = [vp, i32, vp, C.POINTER(vp)]
+    L.strom_batch_step.argtypes = [vp, i32, vp]
+    L.strom_batch_tune.argtypes = [vp, i32, i32, vp, vp, vp, C.POINTER(i32)]
+    L.strom_batch_destroy.argtypes = [vp]
     L.strom_submit.argtypes = [vp, C.POINTER(Problem_), C.POINTER(Opts), C.POINTER(C.c_uint64)]
     L.strom_poll.argtypes = [vp, C.c_uint64, C.POINTER(Info), vp, vp, vp]
     L.strom_profile_iteration.argtypes = [vp, i32, C.POINTER(PhaseTimes)]
@@ -194,11 +199,14 @@ class Context:
         import weakref
         self._h = C.c_void_p()
         self._instances = weakref.WeakSet()
+        self._batches = weakref.WeakSet()
         _check(_L.strom_ctx_create(int(device), _stream_handle(stream), C.c_size_t(hbm_budget), C.byref(self._h)))
 
     def close(self):
         """Destroy the context; instances still alive on it are destroyed first."""
         if self._h:
+            for bat in list(self._batches):
+                bat.close()
             for inst in list(self._instances):
                 inst.close()
             _check(_L.strom_ctx_destroy(self._h))
@@ -329,3 +337,40 @@ class Instance:
         t = PhaseTimes()
         _check(_L.strom_profile_iteration(self._h, int(reps), C.byref(t)))
         return {f: getattr(t, f) for f, _ in t._fields_}
+
+
+class Batch:
+    """Instances of one context iterated together by merged launches (strom_batch_*); while the
+    batch is open they are stepped only through it."""
+
+    def __init__(self, ctx: Context, instances):
+        self.ctx = ctx
+        self.instances = list(instances)
+        hs = (C.c_void_p * len(self.instances))(*[i._h.value for i in self.instances])
+        self._h = C.c_void_p()
+        _check(_L.strom_batch_create(ctx._h, len(self.instances), C.cast(hs, C.c_void_p), C.byref(self._h)))
+        ctx._batches.add(self)
+
+    def step(self, n_iter: int) -> list:
+        infos = (Info * len(self.instances))()
+        _check(_L.strom_batch_step(self._h, int(n_iter), C.cast(infos, C.c_void_p)))
+        return [i.as_dict() for i in infos]
+
+    def tune(self, reps: int = 3) -> list:
+        """Autotune the merged projection; returns (n, threads FP64, threads FP32) per class."""
+        cap = 64
+        n, a, b = (np.zeros(cap, np.int32) for _ in range(3))
+        k = C.c_int32()
+        _check(_L.strom_batch_tune(self._h, int(reps), cap, _ptr(n), _ptr(a), _ptr(b), C.byref(k)))
+        return [(int(n[c]), int(a[c]), int(b[c])) for c in range(min(cap, k.value))]
+
+    def close(self):
+        if self._h:
+            _check(_L.strom_batch_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

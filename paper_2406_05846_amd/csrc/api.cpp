@@ -106,6 +106,7 @@ struct strom_sdp {
   DevState *st_host = nullptr;  // pinned mirror
   int32_t max_n = 0;
   std::vector<int32_t> bsize_h;  // block sizes (host copy)
+  strom_batch *batch = nullptr;  // the batch the instance is iterated in, if any
 };
 
 extern "C" void strom_default_opts(strom_opts *o) {
@@ -324,6 +325,8 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
     return undo(STROM_E_INVAL, "the solve schedule needs more LDS than the device has");
   s->sch.fwd_gptr = H.fwd_gptr;
   s->sch.bwd_gptr = H.bwd_gptr;
+  s->sch.fwd_order = H.fwd_order;
+  s->sch.bwd_order = H.bwd_order;
   s->sch.fwd_order_dev = P32(oFo);
   s->sch.bwd_order_dev = P32(oBo);
 
@@ -407,6 +410,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
 
 extern "C" strom_status strom_sdp_destroy(strom_sdp *s) {
   if (!s) return fail(STROM_E_INVAL, "sdp is NULL");
+  if (s->batch) return fail(STROM_E_STATE, "the instance belongs to a batch: destroy the batch first");
   std::lock_guard<std::recursive_mutex> dl(device_lock());
   hipSetDevice(s->ctx->device);
   hipStreamSynchronize(s->stream);
@@ -564,11 +568,8 @@ hipError_t sdp_enqueue(strom_sdp *s, int n_iter, bool kkt_last) {
 // Reads the device scalars; applies the polish switch of the reduced-precision form: the
 // FP32 projection is replaced by the FP64 one once eta <= polish_eta, or once eta has not
 // halved over 500 iterations.
-hipError_t sdp_read_state(strom_sdp *s) {
-  hipError_t e = hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream);
-  if (e != hipSuccess) return e;
-  e = hipStreamSynchronize(s->stream);
-  if (e != hipSuccess || !s->f32_active) return e;
+static void apply_polish_switch(strom_sdp *s) {
+  if (!s->f32_active) return;
   const DevState &d = *s->st_host;
   const double eta = std::max(d.eta_p, std::max(d.eta_d, d.eta_g));
   if (eta <= s->opts.polish_eta) {
@@ -578,6 +579,13 @@ hipError_t sdp_read_state(strom_sdp *s) {
     s->f32_ref_eta = eta;
     s->f32_ref_iter = s->iters;
   }
+}
+hipError_t sdp_read_state(strom_sdp *s) {
+  hipError_t e = hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return e;
+  apply_polish_switch(s);
   return hipSuccess;
 }
 strom_solve_state sdp_classify(strom_sdp *s) { return s->state = classify(s); }
@@ -588,6 +596,7 @@ void sdp_set_stream(strom_sdp *s, hipStream_t q) { s->stream = q; }
 
 extern "C" strom_status strom_admm_step(strom_sdp *s, int32_t n_iter, strom_info *info) {
   if (!s || n_iter < 0) return fail(STROM_E_INVAL, "bad argument");
+  if (s->batch) return fail(STROM_E_STATE, "the instance is iterated by a batch");
   HIP_TRY(hipSetDevice(s->ctx->device));
   const double t0 = now_s();
   const int kk = s->opts.kkt_every;
@@ -612,6 +621,7 @@ extern "C" strom_status strom_admm_step(strom_sdp *s, int32_t n_iter, strom_info
 
 extern "C" strom_status strom_admm_enqueue(strom_sdp *s, int32_t n_iter) {
   if (!s || n_iter < 0) return fail(STROM_E_INVAL, "bad argument");
+  if (s->batch) return fail(STROM_E_STATE, "the instance is iterated by a batch");
   HIP_TRY(hipSetDevice(s->ctx->device));
   HIP_TRY(strom::sdp_enqueue(s, n_iter, false));
   return STROM_OK;
@@ -702,6 +712,7 @@ extern "C" strom_status strom_get_iterate(strom_sdp *s, double *X, double *y, do
 
 extern "C" strom_status strom_set_iterate(strom_sdp *s, const double *X, const double *y, const double *S) {
   if (!s) return fail(STROM_E_INVAL, "sdp is NULL");
+  if (s->batch) return fail(STROM_E_STATE, "the instance is iterated by a batch");
   std::lock_guard<std::recursive_mutex> dl(device_lock());
   HIP_TRY(hipSetDevice(s->ctx->device));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -891,6 +902,379 @@ extern "C" strom_status strom_extract(strom_sdp *s, int32_t nlist, const int32_t
     vo += int64_t(n) * n;
     out += n;
   }
+  return STROM_OK;
+}
+
+// ------------------------------------------------------------------ merged form
+struct strom_batch {
+  strom_ctx *ctx = nullptr;
+  std::vector<strom_sdp *> inst;
+  hipStream_t stream = nullptr;  // the context's stream
+  int kk = 10, se = 50;          // kkt_every and sigma_every shared by the instances
+  int64_t iters = 0;             // iteration count of the running instances
+  unsigned char *arena = nullptr;
+  strom::dev::BatchInst *bi_dev = nullptr, *bi_host = nullptr;  // bi_host: pinned mirror
+  strom::dev::SolveArgs *sa_dev = nullptr;
+  strom::dev::BatchItem *rows = nullptr, *cols = nullptr, *fwd = nullptr, *bwd = nullptr, *blocks = nullptr;
+  int nrows = 0, ncols = 0;
+  std::vector<int32_t> fwd_gptr, bwd_gptr;  // merged solve groups (by dependency depth)
+  // projection classes: blocks of one size and one default thread count; nt[0] FP64, nt[1] FP32
+  struct Cls {
+    int n, off, cnt, nt[2];
+  };
+  std::vector<Cls> cls;
+  bool any_f32 = false;  // an instance was set up with the FP32 projection
+  size_t solve_lds = 0;
+  DevState *states_dev = nullptr, *states_host = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // one round, [sigma rule on its last iteration]
+  hipStream_t capture_stream = nullptr;
+  bool graphs = true;
+};
+
+namespace {
+
+hipError_t batch_projection(strom_batch *b, hipStream_t q, int cone) {
+  for (const auto &c : b->cls) {
+    hipError_t e = strom::dev::launch_project_batch(q, false, c.n, c.nt[0], c.cnt, b->blocks + c.off, b->bi_dev, cone);
+    if (e != hipSuccess) return e;
+    if (b->any_f32 &&
+        (e = strom::dev::launch_project_batch(q, true, c.n, c.nt[1], c.cnt, b->blocks + c.off, b->bi_dev, cone)))
+      return e;
+  }
+  return hipSuccess;
+}
+
+// One iteration of every running instance (the steps of enqueue_iteration, merged).
+hipError_t batch_iteration(strom_batch *b, hipStream_t q, bool kkt, bool sig) {
+  using namespace strom::dev;
+  hipError_t e;
+  for (int half = 0; half < 2; ++half) {
+    if ((e = launch_rhs_batch(q, b->nrows, b->rows, b->bi_dev))) return e;
+    if ((e = launch_solve_batch(q, b->fwd_gptr, b->fwd, b->bwd_gptr, b->bwd, b->sa_dev, b->bi_dev, b->solve_lds)))
+      return e;
+    if (half == 0) {
+      if ((e = launch_xb_batch(q, b->ncols, b->cols, b->bi_dev))) return e;
+      if ((e = batch_projection(b, q, 0))) return e;
+    }
+  }
+  if ((e = launch_xupdate_batch(q, b->ncols, b->cols, b->bi_dev, kkt ? 1 : 0))) return e;
+  if (kkt) {
+    if (sig && (e = batch_projection(b, q, 1))) return e;
+    if ((e = launch_kkt_batch(q, b->nrows, b->rows, b->ncols, b->cols, int(b->inst.size()), b->bi_dev, sig ? 1 : 0)))
+      return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t batch_capture(strom_batch *b, bool sigma_last, hipGraphExec_t *out) {
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
+  hipError_t e = hipSuccess;
+  if (!b->capture_stream && (e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking))) return e;
+  e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+  hipError_t e2 = hipSuccess;
+  for (int k = 0; k < b->kk && e == hipSuccess && e2 == hipSuccess; ++k)
+    e2 = batch_iteration(b, b->capture_stream, k == b->kk - 1, sigma_last && k == b->kk - 1);
+  hipGraph_t g = nullptr;
+  if (e == hipSuccess) e = hipStreamEndCapture(b->capture_stream, &g);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  if (g) hipGraphDestroy(g);
+  return e;
+}
+
+void batch_drop_graphs(strom_batch *b) {
+  for (auto &g : b->graph)
+    if (g) {
+      hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Flags of every instance for the next launches, copied on the batch stream; the pinned host
+// copy is not written again before that stream has been synchronized.
+hipError_t batch_upload_flags(strom_batch *b) {
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    const strom_sdp *s = b->inst[i];
+    auto &I = b->bi_host[i];
+    I.active = s->state == STROM_RUNNING ? 1 : 0;
+    I.f32 = s->f32_active ? 1 : 0;
+    I.warm = s->q_valid ? 1 : 0;
+  }
+  return hipMemcpyAsync(b->bi_dev, b->bi_host, sizeof(strom::dev::BatchInst) * b->inst.size(), hipMemcpyHostToDevice,
+                        b->stream);
+}
+
+}  // namespace
+
+extern "C" strom_status strom_batch_create(strom_ctx *ctx, int32_t count, strom_sdp *const *instances,
+                                           strom_batch **out) {
+  using strom::dev::BatchInst;
+  using strom::dev::BatchItem;
+  using strom::dev::SolveArgs;
+  if (!ctx || !instances || !out || count <= 0) return fail(STROM_E_INVAL, "bad argument");
+  *out = nullptr;
+  std::vector<strom_sdp *> v(instances, instances + count);
+  for (int32_t i = 0; i < count; ++i) {
+    const strom_sdp *s = v[size_t(i)];
+    if (!s) return fail(STROM_E_INVAL, "instance " + std::to_string(i) + " is NULL");
+    if (s->ctx != ctx) return fail(STROM_E_INVAL, "instance " + std::to_string(i) + " belongs to another context");
+    if (s->batch) return fail(STROM_E_STATE, "instance " + std::to_string(i) + " already belongs to a batch");
+    if (s->opts.kkt_every != v[0]->opts.kkt_every || s->opts.sigma_every != v[0]->opts.sigma_every)
+      return fail(STROM_E_INVAL, "the instances of a batch need the same kkt_every and sigma_every");
+    if (s->iters != v[0]->iters) return fail(STROM_E_INVAL, "the instances of a batch need the same iteration count");
+    for (int32_t j = 0; j < i; ++j)
+      if (v[size_t(j)] == s) return fail(STROM_E_INVAL, "instance listed twice");
+  }
+  auto *b = new strom_batch();
+  b->ctx = ctx;
+  b->inst = v;
+  b->stream = ctx->stream;
+  b->kk = v[0]->opts.kkt_every;
+  b->se = v[0]->opts.sigma_every;
+  b->iters = v[0]->iters;
+
+  std::vector<BatchInst> bi(static_cast<size_t>(count));
+  std::vector<SolveArgs> sa(static_cast<size_t>(count));
+  std::vector<BatchItem> rows, cols, fwd, bwd, blocks;
+  size_t gf = 0, gb = 0;
+  std::map<std::pair<int, int>, std::vector<BatchItem>> by_cls;
+  for (int32_t i = 0; i < count; ++i) {
+    strom_sdp *s = v[size_t(i)];
+    BatchInst &I = bi[size_t(i)];
+    I.m = s->m;
+    I.nrow_chunks = (s->m + 255) / 256;
+    I.n = s->nsvec;
+    I.ncol_chunks = int32_t((s->nsvec + 255) / 256);
+    I.A_rp = s->A_rp; I.At_rp = s->At_rp; I.boff = s->boff; I.qoff = s->qoff;
+    I.A_ci = s->A_ci; I.At_ci = s->At_ci; I.pinv = s->pinv; I.bsz = s->bsz;
+    I.A_v = s->A_v; I.At_v = s->At_v; I.b = s->b; I.C = s->C;
+    I.X = s->X; I.S = s->S; I.Xb = s->Xb; I.y = s->y; I.w = s->w;
+    I.part_rows = s->part_rows; I.part_cols = s->part_cols; I.part_cone = s->part_cone; I.Q = s->Q;
+    I.st = s->st;
+    I.normb = s->normb;
+    I.normC = s->normC;
+    sa[size_t(i)] = s->sa;
+    for (int32_t c = 0; c < I.nrow_chunks; ++c) rows.push_back({i, c});
+    for (int32_t c = 0; c < I.ncol_chunks; ++c) cols.push_back({i, c});
+    gf = std::max(gf, s->sch.fwd_gptr.size() - 1);
+    gb = std::max(gb, s->sch.bwd_gptr.size() - 1);
+    const size_t lds = sizeof(double) * size_t(strom::kSolveThreads * 3 / 2 + s->sa.lds_rows + s->sa.c_cap);
+    b->solve_lds = std::max(b->solve_lds, lds);
+    b->any_f32 |= s->opts.proj_dtype == STROM_F32;
+    // a block keeps the thread count of its own launch: one launch over every block (the
+    // largest's count) when the instance has a single projection class, else its size's
+    const bool merged = s->cls_n.size() == 1;
+    for (int32_t k = 0; k < s->nblocks; ++k) {
+      const int nk = s->bsize_h[size_t(k)];
+      by_cls[{nk, strom::dev::project_threads(merged ? s->cls_n[0] : nk)}].push_back({i, k});
+    }
+  }
+  auto merge = [&](size_t ng, bool forward, std::vector<BatchItem> &items, std::vector<int32_t> &gptr) {
+    gptr.assign(1, 0);
+    for (size_t g = 0; g < ng; ++g) {
+      for (int32_t i = 0; i < count; ++i) {
+        const auto &sch = v[size_t(i)]->sch;
+        const auto &gp = forward ? sch.fwd_gptr : sch.bwd_gptr;
+        const auto &order = forward ? sch.fwd_order : sch.bwd_order;
+        if (g + 1 >= gp.size()) continue;
+        for (int32_t k = gp[g]; k < gp[g + 1]; ++k) items.push_back({i, order[size_t(k)]});
+      }
+      gptr.push_back(int32_t(items.size()));
+    }
+  };
+  merge(gf, true, fwd, b->fwd_gptr);
+  merge(gb, false, bwd, b->bwd_gptr);
+  for (auto it = by_cls.rbegin(); it != by_cls.rend(); ++it) {  // largest blocks first
+    const int nt = it->first.second;
+    b->cls.push_back({it->first.first, int(blocks.size()), int(it->second.size()), {nt, nt}});
+    blocks.insert(blocks.end(), it->second.begin(), it->second.end());
+  }
+  b->nrows = int(rows.size());
+  b->ncols = int(cols.size());
+
+  Arena ar;
+  const size_t oBi = ar.reserve<BatchInst>(size_t(count)), oSa = ar.reserve<SolveArgs>(size_t(count)),
+               oRows = ar.reserve<BatchItem>(rows.size()), oCols = ar.reserve<BatchItem>(cols.size()),
+               oFwd = ar.reserve<BatchItem>(fwd.size()), oBwd = ar.reserve<BatchItem>(bwd.size()),
+               oBlk = ar.reserve<BatchItem>(blocks.size()), oSt = ar.reserve<DevState>(size_t(count));
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
+  auto undo = [&](strom_status st, const std::string &msg) {
+    if (b->arena) hipFree(b->arena);
+    if (b->bi_host) hipHostFree(b->bi_host);
+    if (b->states_host) hipHostFree(b->states_host);
+    delete b;
+    return fail(st, msg);
+  };
+  if (hipSetDevice(ctx->device) != hipSuccess) return undo(STROM_E_HIP, "hipSetDevice failed");
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return undo(STROM_E_HIP, "stream synchronization failed");
+  if (hipMalloc(&b->arena, ar.bytes) != hipSuccess) return undo(STROM_E_NOMEM, "hipMalloc of the batch tables failed");
+  if (hipHostMalloc(&b->bi_host, sizeof(BatchInst) * size_t(count), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&b->states_host, sizeof(DevState) * size_t(count), hipHostMallocDefault) != hipSuccess)
+    return undo(STROM_E_NOMEM, "hipHostMalloc failed");
+  unsigned char *base = b->arena;
+  b->bi_dev = reinterpret_cast<BatchInst *>(base + oBi);
+  b->sa_dev = reinterpret_cast<SolveArgs *>(base + oSa);
+  b->rows = reinterpret_cast<BatchItem *>(base + oRows);
+  b->cols = reinterpret_cast<BatchItem *>(base + oCols);
+  b->fwd = reinterpret_cast<BatchItem *>(base + oFwd);
+  b->bwd = reinterpret_cast<BatchItem *>(base + oBwd);
+  b->blocks = reinterpret_cast<BatchItem *>(base + oBlk);
+  b->states_dev = reinterpret_cast<DevState *>(base + oSt);
+  std::memcpy(b->bi_host, bi.data(), sizeof(BatchInst) * bi.size());
+  bool ok = true;
+  auto up = [&](void *dst, const void *src, size_t bytes) {
+    if (bytes) ok &= hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  up(b->bi_dev, bi.data(), sizeof(BatchInst) * bi.size());
+  up(b->sa_dev, sa.data(), sizeof(SolveArgs) * sa.size());
+  up(b->rows, rows.data(), sizeof(BatchItem) * rows.size());
+  up(b->cols, cols.data(), sizeof(BatchItem) * cols.size());
+  up(b->fwd, fwd.data(), sizeof(BatchItem) * fwd.size());
+  up(b->bwd, bwd.data(), sizeof(BatchItem) * bwd.size());
+  up(b->blocks, blocks.data(), sizeof(BatchItem) * blocks.size());
+  if (!ok) return undo(STROM_E_HIP, "upload of the batch tables failed");
+  for (strom_sdp *s : v) s->batch = b;
+  *out = b;
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_batch_step(strom_batch *b, int32_t n_iter, strom_info *infos) {
+  if (!b || n_iter < 0) return fail(STROM_E_INVAL, "bad argument");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  const double t0 = now_s();
+  const size_t K = b->inst.size();
+  std::vector<char> ran(K, 0);
+  int done = 0;
+  while (done < n_iter) {
+    int64_t room = INT64_MAX;
+    bool all_warm = true;
+    for (const strom_sdp *s : b->inst)
+      if (s->state == STROM_RUNNING) {
+        room = std::min(room, s->opts.maxiter - s->iters);
+        all_warm &= s->q_valid;
+      }
+    if (room == INT64_MAX) break;  // every instance retired
+    const int chunk = int(std::min<int64_t>(std::min<int64_t>(b->kk - b->iters % b->kk, n_iter - done), room));
+    if (chunk <= 0) break;
+    HIP_TRY(batch_upload_flags(b));
+    bool launched = false;
+    if (b->graphs && all_warm && chunk == b->kk) {
+      const int sl = (b->se > 0 && (b->iters + b->kk) % b->se == 0) ? 1 : 0;
+      if (!b->graph[sl] && batch_capture(b, sl != 0, &b->graph[sl]) != hipSuccess) {
+        b->graphs = false;  // capture not available: launch directly from now on
+        b->graph[sl] = nullptr;
+        (void)hipGetLastError();
+      }
+      if (b->graph[sl]) {
+        HIP_TRY(hipGraphLaunch(b->graph[sl], b->stream));
+        launched = true;
+      }
+    }
+    for (int k = 0; !launched && k < chunk; ++k) {
+      const bool sig = b->se > 0 && (b->iters + k + 1) % b->se == 0;
+      HIP_TRY(batch_iteration(b, b->stream, k == chunk - 1, sig));
+      if (k == 0 && !all_warm) {  // the first projection has filled every running instance's Q
+        for (strom_sdp *s : b->inst)
+          if (s->state == STROM_RUNNING) s->q_valid = true;
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        HIP_TRY(batch_upload_flags(b));
+      }
+    }
+    b->iters += chunk;
+    done += chunk;
+    HIP_TRY(strom::dev::launch_gather_states(b->stream, int(K), b->bi_dev, b->states_dev));
+    HIP_TRY(hipMemcpyAsync(b->states_host, b->states_dev, sizeof(DevState) * K, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < K; ++i) {
+      strom_sdp *s = b->inst[i];
+      if (s->state != STROM_RUNNING) continue;
+      ran[i] = 1;
+      s->iters += chunk;
+      s->q_valid = true;
+      *s->st_host = b->states_host[i];
+      strom::apply_polish_switch(s);
+      s->state = classify(s);
+    }
+  }
+  const double dt = now_s() - t0;
+  for (size_t i = 0; i < K; ++i) {
+    if (ran[i]) b->inst[i]->t_solve += dt;
+    if (infos) fill_info(b->inst[i], &infos[i]);
+  }
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_batch_tune(strom_batch *b, int32_t reps, int32_t cap, int32_t *n, int32_t *nt_f64,
+                                         int32_t *nt_f32, int32_t *nclass) {
+  if (!b || reps < 0 || cap < 0) return fail(STROM_E_INVAL, "bad argument");
+  if (reps > 0) {
+    bool any = false, has[2] = {false, false};
+    for (const strom_sdp *s : b->inst) {
+      if (s->state != STROM_RUNNING) continue;
+      if (!s->q_valid) return fail(STROM_E_STATE, "tuning needs a completed iteration");
+      any = true;
+      has[s->f32_active ? 1 : 0] = true;
+    }
+    if (any) {
+      HIP_TRY(hipSetDevice(b->ctx->device));
+      HIP_TRY(batch_upload_flags(b));
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      hipError_t err = hipSuccess;
+      for (auto &c : b->cls) {
+        for (int prec = 0; prec < 2 && err == hipSuccess; ++prec) {
+          if (!has[prec]) continue;
+          int opt[5];
+          const int no = strom::dev::project_thread_options(c.n, prec == 1, opt);
+          float best = 0.0f;
+          int best_nt = c.nt[prec];
+          for (int j = 0; j < no && err == hipSuccess; ++j) {
+            auto launch = [&]() {
+              return strom::dev::launch_project_batch(b->stream, prec == 1, c.n, opt[j], c.cnt, b->blocks + c.off,
+                                                      b->bi_dev, 1);
+            };
+            if ((err = launch())) break;  // untimed first launch
+            if ((err = hipEventRecord(e0, b->stream))) break;
+            for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+            if (err || (err = hipEventRecord(e1, b->stream)) || (err = hipEventSynchronize(e1))) break;
+            float ms = 0.0f;
+            if ((err = hipEventElapsedTime(&ms, e0, e1))) break;
+            if (j == 0 || ms < best) {
+              best = ms;
+              best_nt = opt[j];
+            }
+          }
+          c.nt[prec] = best_nt;
+        }
+      }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      batch_drop_graphs(b);
+      if (err != hipSuccess) return fail(STROM_E_HIP, std::string("tuning launch failed: ") + hipGetErrorString(err));
+    }
+  }
+  for (int32_t c = 0; c < cap && c < int32_t(b->cls.size()); ++c) {
+    if (n) n[c] = b->cls[size_t(c)].n;
+    if (nt_f64) nt_f64[c] = b->cls[size_t(c)].nt[0];
+    if (nt_f32) nt_f32[c] = b->cls[size_t(c)].nt[1];
+  }
+  if (nclass) *nclass = int32_t(b->cls.size());
+  return STROM_OK;
+}
+
+extern "C" strom_status strom_batch_destroy(strom_batch *b) {
+  if (!b) return fail(STROM_E_INVAL, "batch is NULL");
+  std::lock_guard<std::recursive_mutex> dl(device_lock());
+  hipSetDevice(b->ctx->device);
+  hipStreamSynchronize(b->stream);
+  batch_drop_graphs(b);
+  if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+  hipFree(b->arena);
+  hipHostFree(b->bi_host);
+  hipHostFree(b->states_host);
+  for (strom_sdp *s : b->inst) s->batch = nullptr;
+  delete b;
   return STROM_OK;
 }
 

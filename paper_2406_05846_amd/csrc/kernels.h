@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
@@ -19,36 +20,90 @@ struct DevState {
   double sigma_used;  // sigma of the iteration the residuals belong to
 };
 
+// Pointer policies of the argument structs below: plain pointers (host side and kernel
+// arguments), or pointers typed as global memory -- the device's view of a struct that merged
+// launches read from a table in device memory.  The compiler takes a plain pointer loaded
+// from memory as generic and accesses through it with flat instructions; the global view keeps
+// global ones.  G(p) gives the plain pointer (an explicit cast for a global one).
+template <class T>
+using HostPtr = T *;
+template <class T>
+using GlobPtr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ T *G(T *p) {
+  return p;
+}
+template <class T>
+__device__ __forceinline__ T *G(__attribute__((address_space(1))) T *p) {
+  return (T *)p;
+}
+
 // Device arrays of the triangular solves (see setup.cpp for their meaning).
-struct SolveArgs {
-  const int32_t *task_r0, *task_r1, *task_ph0, *task_ph1;
-  const int32_t *ph_a, *ph_nns;  // first row and rows in components of 2+ of every phase
-  const double *D;
-  const int32_t *perm;
+template <template <class> class Ptr>
+struct SolveArgsT {
+  Ptr<const int32_t> task_r0, task_r1, task_ph0, task_ph1;
+  Ptr<const int32_t> ph_a, ph_nns;  // first row and rows in components of 2+ of every phase
+  Ptr<const double> D;
+  Ptr<const int32_t> perm;
   // pushes: task t sums its push stream (kind 4) into part[tseg[tsptr[t] + r]], row r
-  const int32_t *tsptr, *tseg;
-  double *part;
+  Ptr<const int32_t> tsptr, tseg;
+  Ptr<double> part;
   // streams, kinds 0 forward gather, 1 forward inverse, 2 backward gather, 3 backward inverse
   // (per phase), 4 push (per task): values, indices, per-phase (task) offset, entries per
   // thread, thread stride, first rows of the slices
-  const double *sval[kStreamKinds];
-  const int32_t *sidx[kStreamKinds];
-  const int64_t *s_off[kStreamKinds];
-  const int32_t *s_K[kStreamKinds];
-  const int32_t *s_T[kStreamKinds];
-  const int32_t *s_ra[kStreamKinds];
+  Ptr<const double> sval[kStreamKinds];
+  Ptr<const int32_t> sidx[kStreamKinds];
+  Ptr<const int64_t> s_off[kStreamKinds];
+  Ptr<const int32_t> s_K[kStreamKinds];
+  Ptr<const int32_t> s_T[kStreamKinds];
+  Ptr<const int32_t> s_ra[kStreamKinds];
   // task-local staging (task_inl[t] != 0): the task's rows, then its incoming partial sums
   // part[task_pin[t] ..] (forward) or the later-task rows task_xrow[task_xoff[t] ..]
   // (backward) are staged in LDS and the fg / bg stream indices address that buffer
-  const int32_t *task_pin, *task_inl;
-  const int64_t *task_xoff;
-  const int32_t *task_xrow;
+  Ptr<const int32_t> task_pin, task_inl;
+  Ptr<const int64_t> task_xoff;
+  Ptr<const int32_t> task_xrow;
   int32_t lds_rows;  // LDS doubles for a staged task (at least every staged task's total)
   int32_t c_cap;     // LDS doubles for the right-hand sides of a phase's components
 };
+using SolveArgs = SolveArgsT<HostPtr>;
+using SolveArgsG = SolveArgsT<GlobPtr>;
+
+// One instance of a merged (batched) launch: what the kernels read of it, and its flags, which
+// the host rewrites between rounds (a captured round stays valid for any flags).
+template <template <class> class Ptr>
+struct BatchInstT {
+  int32_t m, nrow_chunks;  // rows of A, and 256-row chunks
+  int64_t n;               // svec length
+  int32_t ncol_chunks;     // 256-column chunks
+  int32_t active;          // 0: retired, every merged launch skips the instance
+  int32_t f32;             // projection precision: 1 FP32, 0 FP64
+  int32_t warm;            // Q holds eigenvectors to start from
+  Ptr<const int64_t> A_rp, At_rp, boff, qoff;
+  Ptr<const int32_t> A_ci, At_ci, pinv, bsz;
+  Ptr<const double> A_v, At_v, b, C;
+  Ptr<double> X, S, Xb, y, w, part_rows, part_cols, part_cone, Q;
+  Ptr<DevState> st;
+  double normb, normC;
+};
+using BatchInst = BatchInstT<HostPtr>;
+using BatchInstG = BatchInstT<GlobPtr>;
+// The host fills these tables and the device reads them through the global view: both
+// compilations must see one layout.
+static_assert(sizeof(SolveArgs) == 368 && sizeof(SolveArgsG) == sizeof(SolveArgs), "SolveArgs layout");
+static_assert(sizeof(BatchInst) == 224 && sizeof(BatchInstG) == sizeof(BatchInst) &&
+                  offsetof(BatchInst, st) == 200 && offsetof(BatchInstG, st) == 200,
+              "BatchInst layout");
+
+// A work item of a merged launch: the instance and its local index (row or column chunk, solve
+// task, or PSD block).
+struct BatchItem {
+  int32_t inst, idx;
+};
 
 struct SolveSchedule {
-  std::vector<int32_t> fwd_gptr, bwd_gptr;  // host: group boundaries
+  std::vector<int32_t> fwd_gptr, bwd_gptr;    // host: group boundaries
+  std::vector<int32_t> fwd_order, bwd_order;  // host: tasks of the groups in launch order
   const int32_t *fwd_order_dev = nullptr, *bwd_order_dev = nullptr;
 };
 
@@ -88,6 +143,27 @@ hipError_t launch_kkt(hipStream_t s, int32_t m, int64_t n, const int64_t *rp, co
                       const double *X, const double *b, const double *y, double *part_rows, const double *part_cols,
                       const double *cone_diff, double *part_cone, double normb, double normC, int do_sigma,
                       DevState *st);
+
+// Merged launches over the instances of a batch (items: one workgroup each; retired
+// instances are skipped).  The solve's groups are merged by dependency depth: group g of every
+// instance in one launch, lds_bytes at least every instance's need.
+hipError_t launch_rhs_batch(hipStream_t s, int count, const BatchItem *rows, const BatchInst *bi);
+hipError_t launch_solve_batch(hipStream_t s, const std::vector<int32_t> &fwd_gptr, const BatchItem *fwd,
+                              const std::vector<int32_t> &bwd_gptr, const BatchItem *bwd, const SolveArgs *args,
+                              const BatchInst *bi, size_t lds_bytes);
+hipError_t launch_xb_batch(hipStream_t s, int count, const BatchItem *cols, const BatchInst *bi);
+hipError_t launch_xupdate_batch(hipStream_t s, int count, const BatchItem *cols, const BatchInst *bi, int want_part);
+hipError_t launch_kkt_batch(hipStream_t s, int nrows, const BatchItem *rows, int ncols, const BatchItem *cols,
+                            int ninst, const BatchInst *bi, int do_sigma);
+// Copies every instance's DevState to out[0 .. ninst).
+hipError_t launch_gather_states(hipStream_t s, int ninst, const BatchInst *bi, DevState *out);
+// PSD projection of blocks of one size n over a batch, nt threads per workgroup; only the
+// instances whose precision flag matches f32 are projected.  cone = 0: S = (Pi(X_b) - X_b) /
+// sigma (step 2); cone = 1: X_b = Pi(X) - X (the sigma rule's cone distance).
+hipError_t launch_project_batch(hipStream_t s, bool f32, int n, int nt, int count, const BatchItem *items,
+                                const BatchInst *bi, int cone);
+// Thread counts the projection kernel accepts for blocks of size n (at most 5, ascending).
+int project_thread_options(int n, bool f32, int *out);
 
 }  // namespace dev
 }  // namespace strom

@@ -38,12 +38,12 @@ __device__ inline double block_sum(double v, double *red) {
 }
 
 // ------------------------------------------------------------------ step 1 / 3: right-hand side
-__global__ void __launch_bounds__(256) k_rhs(int32_t m, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                             const double *__restrict__ av, const double *__restrict__ X,
-                                             const double *__restrict__ S, const double *__restrict__ C,
-                                             const double *__restrict__ b, const int32_t *__restrict__ pinv,
-                                             const DevState *__restrict__ st, double *__restrict__ w) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rhs_row(int32_t i, int32_t m, const int64_t *__restrict__ rp,
+                                        const int32_t *__restrict__ ci, const double *__restrict__ av,
+                                        const double *__restrict__ X, const double *__restrict__ S,
+                                        const double *__restrict__ C, const double *__restrict__ b,
+                                        const int32_t *__restrict__ pinv, const DevState *__restrict__ st,
+                                        double *__restrict__ w) {
   if (i >= m) return;
   const double sig = st->sigma;
   double acc = 0.0;
@@ -52,6 +52,23 @@ __global__ void __launch_bounds__(256) k_rhs(int32_t m, const int64_t *__restric
     acc += av[p] * (X[c] / sig + S[c] - C[c]);
   }
   w[pinv[i]] = b[i] / sig - acc;
+}
+
+__global__ void __launch_bounds__(256) k_rhs(int32_t m, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                             const double *__restrict__ av, const double *__restrict__ X,
+                                             const double *__restrict__ S, const double *__restrict__ C,
+                                             const double *__restrict__ b, const int32_t *__restrict__ pinv,
+                                             const DevState *__restrict__ st, double *__restrict__ w) {
+  rhs_row(blockIdx.x * blockDim.x + threadIdx.x, m, rp, ci, av, X, S, C, b, pinv, st, w);
+}
+
+__global__ void __launch_bounds__(256) k_rhs_batch(const BatchItem *__restrict__ items,
+                                                   const BatchInst *__restrict__ bi) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
+  if (!I.active) return;
+  rhs_row(it.idx * 256 + threadIdx.x, I.m, G(I.A_rp), G(I.A_ci), G(I.A_v), G(I.X), G(I.S), G(I.C), G(I.b),
+          G(I.pinv), G(I.st), G(I.w));
 }
 
 // ------------------------------------------------------------------ triangular solves
@@ -123,28 +140,28 @@ __device__ inline void stream_phase(const double *__restrict__ val, const int32_
 // pushed to it -- and the stream indices are task-local; else its values are read and written
 // in place in w and the indices are global.  A separate instantiation for each case keeps every
 // access in one address space (LDS or global).
-template <bool INL>
-__device__ __forceinline__ void solve_fwd_task(int32_t t, const SolveArgs &a, double *__restrict__ w, double *sh) {
+template <bool INL, class A>
+__device__ __forceinline__ void solve_fwd_task(int32_t t, const A &a, double *__restrict__ w, double *sh) {
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int32_t r0 = a.task_r0[t], r1 = a.task_r1[t], nt = r1 - r0;
+  const int32_t r0 = G(a.task_r0)[t], r1 = G(a.task_r1)[t], nt = r1 - r0;
   double *tail_v = sh;  // open-row pieces of the stream slices
   int32_t *tail_r = reinterpret_cast<int32_t *>(sh + kSolveThreads);
   double *buf = sh + kSolveThreads + kSolveThreads / 2;
-  const int32_t p0 = INL ? a.task_pin[t] : 0, npin = INL ? a.task_pin[t + 1] - p0 : 0;
+  const int32_t p0 = INL ? G(a.task_pin)[t] : 0, npin = INL ? G(a.task_pin)[t + 1] - p0 : 0;
   double *xs = INL ? buf : (w + r0);          // values of the task rows, index i - r0
   double *c = INL ? buf + nt + npin : buf;    // right-hand sides of the phase's components
   if (INL) {
     for (int i = tid; i < nt; i += nth) xs[i] = w[r0 + i];
-    for (int k = tid; k < npin; k += nth) xs[nt + k] = a.part[p0 + k];
+    for (int k = tid; k < npin; k += nth) xs[nt + k] = G(a.part)[p0 + k];
   }
   __syncthreads();
-  for (int32_t ph = a.task_ph0[t]; ph < a.task_ph1[t]; ++ph) {
-    const int32_t pa = a.ph_a[ph], nns = a.ph_nns[ph];
-    stream_phase(a.sval[0], a.sidx[0], a.s_off[0][ph], a.s_K[0][ph], a.s_T[0][ph],
-                a.s_ra[0] + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
+  for (int32_t ph = G(a.task_ph0)[t]; ph < G(a.task_ph1)[t]; ++ph) {
+    const int32_t pa = G(a.ph_a)[ph], nns = G(a.ph_nns)[ph];
+    stream_phase(G(a.sval[0]), G(a.sidx[0]), G(a.s_off[0])[ph], G(a.s_K[0])[ph], G(a.s_T[0])[ph],
+                G(a.s_ra[0]) + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
                 [&](int32_t j) {
                   if constexpr (INL) return xs[j];
-                  else return (j & kPartFlag) ? a.part[j & (kPartFlag - 1)] : w[j];
+                  else return (j & kPartFlag) ? G(a.part)[j & (kPartFlag - 1)] : w[j];
                 },
                 [&](int32_t r, double acc) {
                   const double v = xs[pa + r - r0] - acc;
@@ -153,22 +170,22 @@ __device__ __forceinline__ void solve_fwd_task(int32_t t, const SolveArgs &a, do
                 });
     if (nns > 0) {
       __syncthreads();
-      stream_phase(a.sval[1], a.sidx[1], a.s_off[1][ph], a.s_K[1][ph], a.s_T[1][ph],
-                  a.s_ra[1] + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
+      stream_phase(G(a.sval[1]), G(a.sidx[1]), G(a.s_off[1])[ph], G(a.s_K[1])[ph], G(a.s_T[1])[ph],
+                  G(a.s_ra[1]) + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
                   [&](int32_t j) { return c[j]; }, [&](int32_t r, double acc) { xs[pa + r - r0] = acc; });
     }
     __syncthreads();
   }
   // push: partial sums of the later rows over this task's columns, one stream row per segment
-  if (a.tsptr[t] < a.tsptr[t + 1]) {
-    const int32_t s0 = a.tsptr[t];
-    stream_phase(a.sval[4], a.sidx[4], a.s_off[4][t], a.s_K[4][t], a.s_T[4][t],
-                 a.s_ra[4] + (int64_t)t * (kSolveThreads + 1), tail_v, tail_r,
+  if (G(a.tsptr)[t] < G(a.tsptr)[t + 1]) {
+    const int32_t s0 = G(a.tsptr)[t];
+    stream_phase(G(a.sval[4]), G(a.sidx[4]), G(a.s_off[4])[t], G(a.s_K[4])[t], G(a.s_T[4])[t],
+                 G(a.s_ra[4]) + (int64_t)t * (kSolveThreads + 1), tail_v, tail_r,
                  [&](int32_t j) {
                    if constexpr (INL) return xs[j];
                    else return w[j];
                  },
-                 [&](int32_t r, double acc) { a.part[a.tseg[s0 + r]] = acc; });
+                 [&](int32_t r, double acc) { G(a.part)[G(a.tseg)[s0 + r]] = acc; });
   }
   if (INL)
     for (int i = tid; i < nt; i += nth) w[r0 + i] = xs[i];
@@ -182,44 +199,56 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__re
   else solve_fwd_task<false>(t, a, w, sh);
 }
 
+__global__ void __launch_bounds__(kSolveThreads) k_solve_fwd_batch(const BatchItem *__restrict__ tasks,
+                                                                   const SolveArgs *__restrict__ args,
+                                                                   const BatchInst *__restrict__ bi) {
+  extern __shared__ double sh[];
+  const BatchItem it = tasks[blockIdx.x];
+  const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
+  if (!I.active) return;
+  const SolveArgsG &a = reinterpret_cast<const SolveArgsG *>(args)[it.inst];
+  if (G(a.task_inl)[it.idx]) solve_fwd_task<true>(it.idx, a, G(I.w), sh);
+  else solve_fwd_task<false>(it.idx, a, G(I.w), sh);
+}
+
 // Backward: L^T x = D^{-1} z over the phases in reverse order (a row only depends here on
 // its own component, later phases and later tasks).  INL: the task's rows and the rows of
 // later tasks it reads are staged in LDS, stream indices task-local.
-template <bool INL>
-__device__ __forceinline__ void solve_bwd_task(int32_t t, const SolveArgs &a, double *__restrict__ w,
+template <bool INL, class A>
+__device__ __forceinline__ void solve_bwd_task(int32_t t, const A &a, double *__restrict__ w,
                                                double *__restrict__ y, double *sh) {
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int32_t r0 = a.task_r0[t], r1 = a.task_r1[t], nt = r1 - r0;
+  const int32_t r0 = G(a.task_r0)[t], r1 = G(a.task_r1)[t], nt = r1 - r0;
   double *tail_v = sh;
   int32_t *tail_r = reinterpret_cast<int32_t *>(sh + kSolveThreads);
   double *buf = sh + kSolveThreads + kSolveThreads / 2;
-  const int64_t x0 = INL ? a.task_xoff[t] : 0;
-  const int32_t nx = INL ? (int32_t)(a.task_xoff[t + 1] - x0) : 0;
+  const int64_t x0 = INL ? G(a.task_xoff)[t] : 0;
+  const int32_t nx = INL ? (int32_t)(G(a.task_xoff)[t + 1] - x0) : 0;
   double *xs = INL ? buf : (w + r0);
   double *c = INL ? buf + nt + nx : buf;
   if (INL) {
     for (int i = tid; i < nt; i += nth) xs[i] = w[r0 + i];
-    for (int k = tid; k < nx; k += nth) xs[nt + k] = w[a.task_xrow[x0 + k]];
+    for (int k = tid; k < nx; k += nth) xs[nt + k] = w[G(a.task_xrow)[x0 + k]];
   }
   __syncthreads();
-  for (int32_t ph = a.task_ph1[t] - 1; ph >= a.task_ph0[t]; --ph) {
-    const int32_t pa = a.ph_a[ph], nns = a.ph_nns[ph];
-    stream_phase(a.sval[2], a.sidx[2], a.s_off[2][ph], a.s_K[2][ph], a.s_T[2][ph],
-                a.s_ra[2] + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
+  for (int32_t ph = G(a.task_ph1)[t] - 1; ph >= G(a.task_ph0)[t]; --ph) {
+    const int32_t pa = G(a.ph_a)[ph], nns = G(a.ph_nns)[ph];
+    stream_phase(G(a.sval[2]), G(a.sidx[2]), G(a.s_off[2])[ph], G(a.s_K[2])[ph], G(a.s_T[2])[ph],
+                G(a.s_ra[2]) + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
                 [&](int32_t i) {
                   if constexpr (INL) return xs[i];
                   else return w[i];
                 },
                 [&](int32_t r, double acc) {
                   const int32_t j = pa + r;
-                  const double v = xs[j - r0] / a.D[j] - acc;
+                  const double v = xs[j - r0] / G(a.D)[j] - acc;
                   if (r < nns) c[r] = v;
                   else xs[j - r0] = v;
                 });
     if (nns > 0) {
       __syncthreads();
-      stream_phase(a.sval[3], a.sidx[3], a.s_off[3][ph], a.s_K[3][ph], a.s_T[3][ph],
-                  a.s_ra[3] + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
+      stream_phase(G(a.sval[3]), G(a.sidx[3]), G(a.s_off[3])[ph], G(a.s_K[3])[ph], G(a.s_T[3])[ph],
+                  G(a.s_ra[3]) + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
                   [&](int32_t j) { return c[j]; }, [&](int32_t r, double acc) { xs[pa + r - r0] = acc; });
     }
     __syncthreads();
@@ -227,7 +256,7 @@ __device__ __forceinline__ void solve_bwd_task(int32_t t, const SolveArgs &a, do
   for (int i = tid; i < nt; i += nth) {
     const double v = xs[i];
     if (INL) w[r0 + i] = v;
-    y[a.perm[r0 + i]] = v;
+    y[G(a.perm)[r0 + i]] = v;
   }
 }
 
@@ -239,26 +268,55 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd(const int32_t *__re
   else solve_bwd_task<false>(t, a, w, y, sh);
 }
 
+__global__ void __launch_bounds__(kSolveThreads) k_solve_bwd_batch(const BatchItem *__restrict__ tasks,
+                                                                   const SolveArgs *__restrict__ args,
+                                                                   const BatchInst *__restrict__ bi) {
+  extern __shared__ double sh[];
+  const BatchItem it = tasks[blockIdx.x];
+  const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
+  if (!I.active) return;
+  const SolveArgsG &a = reinterpret_cast<const SolveArgsG *>(args)[it.inst];
+  if (G(a.task_inl)[it.idx]) solve_bwd_task<true>(it.idx, a, G(I.w), G(I.y), sh);
+  else solve_bwd_task<false>(it.idx, a, G(I.w), G(I.y), sh);
+}
+
 // ------------------------------------------------------------------ step 2: X_b
-__global__ void __launch_bounds__(256) k_xb(int64_t n, const int64_t *__restrict__ trp, const int32_t *__restrict__ tci,
-                                            const double *__restrict__ tv, const double *__restrict__ y,
-                                            const double *__restrict__ X, const double *__restrict__ C,
-                                            const DevState *__restrict__ st, double *__restrict__ Xb) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void xb_col(int64_t c, int64_t n, const int64_t *__restrict__ trp,
+                                       const int32_t *__restrict__ tci, const double *__restrict__ tv,
+                                       const double *__restrict__ y, const double *__restrict__ X,
+                                       const double *__restrict__ C, const DevState *__restrict__ st,
+                                       double *__restrict__ Xb) {
   if (c >= n) return;
   double aty = 0.0;
   for (int64_t p = trp[c]; p < trp[c + 1]; ++p) aty += tv[p] * y[tci[p]];
   Xb[c] = X[c] + st->sigma * (aty - C[c]);
 }
 
+__global__ void __launch_bounds__(256) k_xb(int64_t n, const int64_t *__restrict__ trp, const int32_t *__restrict__ tci,
+                                            const double *__restrict__ tv, const double *__restrict__ y,
+                                            const double *__restrict__ X, const double *__restrict__ C,
+                                            const DevState *__restrict__ st, double *__restrict__ Xb) {
+  xb_col((int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, trp, tci, tv, y, X, C, st, Xb);
+}
+
+__global__ void __launch_bounds__(256) k_xb_batch(const BatchItem *__restrict__ items, const BatchInst *__restrict__ bi) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
+  if (!I.active) return;
+  xb_col((int64_t)it.idx * 256 + threadIdx.x, I.n, G(I.At_rp), G(I.At_ci), G(I.At_v), G(I.y), G(I.X), G(I.C), G(I.st),
+         G(I.Xb));
+}
+
 // ------------------------------------------------------------------ step 4: X update + dual residual
-__global__ void __launch_bounds__(256) k_xupdate(int64_t n, const int64_t *__restrict__ trp, const int32_t *__restrict__ tci,
-                                                 const double *__restrict__ tv, const double *__restrict__ y,
-                                                 const double *__restrict__ S, const double *__restrict__ C,
-                                                 const DevState *__restrict__ st, double *__restrict__ X,
-                                                 double *__restrict__ part, int32_t update) {
-  __shared__ double red[256];
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Columns [256 chunk, 256 chunk + 256): X += tau sigma d (update != 0), d = S + A^* y - C, and
+// with part the chunk's sums of d^2 and C X at part[2 chunk ..].  Call from all 256 threads.
+__device__ __forceinline__ void xupdate_chunk(int32_t chunk, int64_t n, const int64_t *__restrict__ trp,
+                                              const int32_t *__restrict__ tci, const double *__restrict__ tv,
+                                              const double *__restrict__ y, const double *__restrict__ S,
+                                              const double *__restrict__ C, const DevState *__restrict__ st,
+                                              double *__restrict__ X, double *__restrict__ part, int32_t update,
+                                              double *red) {
+  const int64_t c = (int64_t)chunk * 256 + threadIdx.x;
   double d2 = 0.0, cx = 0.0;
   if (c < n) {
     double aty = 0.0;
@@ -276,19 +334,38 @@ __global__ void __launch_bounds__(256) k_xupdate(int64_t n, const int64_t *__res
     d2 = block_sum<256>(d2, red);
     cx = block_sum<256>(cx, red);
     if (threadIdx.x == 0) {
-      part[2 * blockIdx.x] = d2;
-      part[2 * blockIdx.x + 1] = cx;
+      part[2 * chunk] = d2;
+      part[2 * chunk + 1] = cx;
     }
   }
 }
 
-// ------------------------------------------------------------------ KKT
-__global__ void __launch_bounds__(256) k_kkt_rows(int32_t m, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                  const double *__restrict__ av, const double *__restrict__ X,
-                                                  const double *__restrict__ b, const double *__restrict__ y,
-                                                  double *__restrict__ part) {
+__global__ void __launch_bounds__(256) k_xupdate(int64_t n, const int64_t *__restrict__ trp, const int32_t *__restrict__ tci,
+                                                 const double *__restrict__ tv, const double *__restrict__ y,
+                                                 const double *__restrict__ S, const double *__restrict__ C,
+                                                 const DevState *__restrict__ st, double *__restrict__ X,
+                                                 double *__restrict__ part, int32_t update) {
   __shared__ double red[256];
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  xupdate_chunk(blockIdx.x, n, trp, tci, tv, y, S, C, st, X, part, update, red);
+}
+
+__global__ void __launch_bounds__(256) k_xupdate_batch(const BatchItem *__restrict__ items,
+                                                       const BatchInst *__restrict__ bi, int32_t want_part) {
+  __shared__ double red[256];
+  const BatchItem it = items[blockIdx.x];
+  const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
+  if (!I.active) return;
+  xupdate_chunk(it.idx, I.n, G(I.At_rp), G(I.At_ci), G(I.At_v), G(I.y), G(I.S), G(I.C), G(I.st), G(I.X),
+                want_part ? G(I.part_cols) : nullptr, 1, red);
+}
+
+// ------------------------------------------------------------------ KKT
+// Rows [256 chunk, 256 chunk + 256): sums of (A X - b)_i^2 and b_i y_i at part[2 chunk ..].
+__device__ __forceinline__ void kkt_rows_chunk(int32_t chunk, int32_t m, const int64_t *__restrict__ rp,
+                                               const int32_t *__restrict__ ci, const double *__restrict__ av,
+                                               const double *__restrict__ X, const double *__restrict__ b,
+                                               const double *__restrict__ y, double *__restrict__ part, double *red) {
+  const int32_t i = chunk * 256 + threadIdx.x;
   double r2 = 0.0, by = 0.0;
   if (i < m) {
     double ax = 0.0;
@@ -300,16 +377,23 @@ __global__ void __launch_bounds__(256) k_kkt_rows(int32_t m, const int64_t *__re
   r2 = block_sum<256>(r2, red);
   by = block_sum<256>(by, red);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = r2;
-    part[2 * blockIdx.x + 1] = by;
+    part[2 * chunk] = r2;
+    part[2 * chunk + 1] = by;
   }
 }
 
-// Per-block partial sums of ||a||^2 and ||b||^2 (a = Pi(X) - X, b = X for the cone distance).
-__global__ void __launch_bounds__(256) k_sqnorms(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
-                                                 double *__restrict__ part) {
+__global__ void __launch_bounds__(256) k_kkt_rows(int32_t m, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                  const double *__restrict__ av, const double *__restrict__ X,
+                                                  const double *__restrict__ b, const double *__restrict__ y,
+                                                  double *__restrict__ part) {
   __shared__ double red[256];
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  kkt_rows_chunk(blockIdx.x, m, rp, ci, av, X, b, y, part, red);
+}
+
+// Per-block partial sums of ||a||^2 and ||b||^2 (a = Pi(X) - X, b = X for the cone distance).
+__device__ __forceinline__ void sqnorms_chunk(int32_t chunk, int64_t n, const double *__restrict__ a,
+                                              const double *__restrict__ b, double *__restrict__ part, double *red) {
+  const int64_t c = (int64_t)chunk * 256 + threadIdx.x;
   double sa = 0.0, sb = 0.0;
   if (c < n) {
     sa = a[c] * a[c];
@@ -318,20 +402,25 @@ __global__ void __launch_bounds__(256) k_sqnorms(int64_t n, const double *__rest
   sa = block_sum<256>(sa, red);
   sb = block_sum<256>(sb, red);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = sa;
-    part[2 * blockIdx.x + 1] = sb;
+    part[2 * chunk] = sa;
+    part[2 * chunk + 1] = sb;
   }
+}
+
+__global__ void __launch_bounds__(256) k_sqnorms(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                                                 double *__restrict__ part) {
+  __shared__ double red[256];
+  sqnorms_chunk(blockIdx.x, n, a, b, part, red);
 }
 
 // Sums the partials in a fixed order (deterministic), forms the residuals of the
 // termination rule and, when asked, balances sigma: with eta_K = ||X - Pi(X)|| / (1 + ||X||)
 // and r_P = max(eta_p, eta_K), sigma is multiplied by 1.5 when eta_d > 3 r_P and divided by
 // 1.5 when r_P > 3 eta_d, kept in [1e-4, 1e4].
-__global__ void k_kkt_final(const double *__restrict__ part_rows, int32_t nrow_parts,
-                            const double *__restrict__ part_cols, int32_t ncol_parts,
-                            const double *__restrict__ part_cone, double normb, double normC,
-                            int32_t do_sigma, DevState *__restrict__ st) {
-  __shared__ double red[256];
+__device__ __forceinline__ void kkt_final_body(const double *__restrict__ part_rows, int32_t nrow_parts,
+                                               const double *__restrict__ part_cols, int32_t ncol_parts,
+                                               const double *__restrict__ part_cone, double normb, double normC,
+                                               int32_t do_sigma, DevState *__restrict__ st, double *red) {
   double r2 = 0.0, by = 0.0, d2 = 0.0, cx = 0.0, k2 = 0.0, x2 = 0.0;
   for (int32_t k = threadIdx.x; k < nrow_parts; k += blockDim.x) { r2 += part_rows[2 * k]; by += part_rows[2 * k + 1]; }
   for (int32_t k = threadIdx.x; k < ncol_parts; k += blockDim.x) { d2 += part_cols[2 * k]; cx += part_cols[2 * k + 1]; }
@@ -360,6 +449,46 @@ __global__ void k_kkt_final(const double *__restrict__ part_rows, int32_t nrow_p
       else if (rp > 3.0 * ed) st->sigma = fmax(st->sigma / 1.5, 1e-4);
     }
   }
+}
+
+__global__ void k_kkt_final(const double *__restrict__ part_rows, int32_t nrow_parts,
+                            const double *__restrict__ part_cols, int32_t ncol_parts,
+                            const double *__restrict__ part_cone, double normb, double normC,
+                            int32_t do_sigma, DevState *__restrict__ st) {
+  __shared__ double red[256];
+  kkt_final_body(part_rows, nrow_parts, part_cols, ncol_parts, part_cone, normb, normC, do_sigma, st, red);
+}
+
+// ------------------------------------------------------------------ merged KKT over a batch
+__global__ void __launch_bounds__(256) k_kkt_rows_batch(const BatchItem *__restrict__ items,
+                                                        const BatchInst *__restrict__ bi) {
+  __shared__ double red[256];
+  const BatchItem it = items[blockIdx.x];
+  const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
+  if (!I.active) return;
+  kkt_rows_chunk(it.idx, I.m, G(I.A_rp), G(I.A_ci), G(I.A_v), G(I.X), G(I.b), G(I.y), G(I.part_rows), red);
+}
+
+__global__ void __launch_bounds__(256) k_sqnorms_batch(const BatchItem *__restrict__ items,
+                                                       const BatchInst *__restrict__ bi) {
+  __shared__ double red[256];
+  const BatchItem it = items[blockIdx.x];
+  const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
+  if (!I.active) return;
+  sqnorms_chunk(it.idx, I.n, G(I.Xb), G(I.X), G(I.part_cone), red);
+}
+
+__global__ void __launch_bounds__(256) k_kkt_final_batch(const BatchInst *__restrict__ bi, int32_t do_sigma) {
+  __shared__ double red[256];
+  const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[blockIdx.x];
+  if (!I.active) return;
+  kkt_final_body(G(I.part_rows), I.nrow_chunks, G(I.part_cols), I.ncol_chunks, G(I.part_cone), I.normb, I.normC,
+                 do_sigma, G(I.st), red);
+}
+
+__global__ void k_gather_states(int32_t ninst, const BatchInst *__restrict__ bi, DevState *__restrict__ out) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst) out[i] = *G(reinterpret_cast<const BatchInstG *>(bi)[i].st);
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -429,6 +558,53 @@ hipError_t launch_kkt(hipStream_t s, int32_t m, int64_t n, const int64_t *rp, co
   if (do_sigma) hipLaunchKernelGGL(k_sqnorms, dim3(ncb), dim3(256), 0, s, n, cone_diff, X, part_cone);
   hipLaunchKernelGGL(k_kkt_final, dim3(1), dim3(256), 0, s, part_rows, nrb, part_cols, ncb, part_cone, normb, normC,
                      do_sigma, st);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ merged launchers
+hipError_t launch_rhs_batch(hipStream_t s, int count, const BatchItem *rows, const BatchInst *bi) {
+  if (count > 0) hipLaunchKernelGGL(k_rhs_batch, dim3(count), dim3(256), 0, s, rows, bi);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_batch(hipStream_t s, const std::vector<int32_t> &fwd_gptr, const BatchItem *fwd,
+                              const std::vector<int32_t> &bwd_gptr, const BatchItem *bwd, const SolveArgs *args,
+                              const BatchInst *bi, size_t lds_bytes) {
+  (void)hipFuncSetAttribute((const void *)k_solve_fwd_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  (void)hipFuncSetAttribute((const void *)k_solve_bwd_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  for (size_t g = 0; g + 1 < fwd_gptr.size(); ++g) {
+    const int cnt = fwd_gptr[g + 1] - fwd_gptr[g];
+    if (cnt > 0)
+      hipLaunchKernelGGL(k_solve_fwd_batch, dim3(cnt), dim3(kSolveThreads), lds_bytes, s, fwd + fwd_gptr[g], args, bi);
+  }
+  for (size_t g = 0; g + 1 < bwd_gptr.size(); ++g) {
+    const int cnt = bwd_gptr[g + 1] - bwd_gptr[g];
+    if (cnt > 0)
+      hipLaunchKernelGGL(k_solve_bwd_batch, dim3(cnt), dim3(kSolveThreads), lds_bytes, s, bwd + bwd_gptr[g], args, bi);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_xb_batch(hipStream_t s, int count, const BatchItem *cols, const BatchInst *bi) {
+  if (count > 0) hipLaunchKernelGGL(k_xb_batch, dim3(count), dim3(256), 0, s, cols, bi);
+  return hipGetLastError();
+}
+
+hipError_t launch_xupdate_batch(hipStream_t s, int count, const BatchItem *cols, const BatchInst *bi, int want_part) {
+  if (count > 0) hipLaunchKernelGGL(k_xupdate_batch, dim3(count), dim3(256), 0, s, cols, bi, want_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_kkt_batch(hipStream_t s, int nrows, const BatchItem *rows, int ncols, const BatchItem *cols,
+                            int ninst, const BatchInst *bi, int do_sigma) {
+  if (nrows > 0) hipLaunchKernelGGL(k_kkt_rows_batch, dim3(nrows), dim3(256), 0, s, rows, bi);
+  if (do_sigma && ncols > 0) hipLaunchKernelGGL(k_sqnorms_batch, dim3(ncols), dim3(256), 0, s, cols, bi);
+  if (ninst > 0) hipLaunchKernelGGL(k_kkt_final_batch, dim3(ninst), dim3(256), 0, s, bi, do_sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_states(hipStream_t s, int ninst, const BatchInst *bi, DevState *out) {
+  if (ninst > 0) hipLaunchKernelGGL(k_gather_states, dim3((ninst + 255) / 256), dim3(256), 0, s, ninst, bi, out);
   return hipGetLastError();
 }
 

@@ -514,13 +514,11 @@ __device__ inline double rebuild(int i, int j, int n, const double *lam, const d
 // live at Q + qoff[k]; warm selects a start from them (else a cold start) and they are written
 // back after the sweeps.  lds_cap: the dynamic LDS of the launch.
 template <typename T, bool BIG>
-__global__ void __launch_bounds__(1024) k_project_admm(const int32_t *__restrict__ blk_ids, const int64_t *__restrict__ boff,
-                                                       const int32_t *__restrict__ bsz, const double *__restrict__ Xb,
-                                                       double *__restrict__ S, const DevState *__restrict__ st,
-                                                       double scale, double *__restrict__ Q,
-                                                       const int64_t *__restrict__ qoff, int32_t warm, uint32_t lds_cap) {
-  extern __shared__ __align__(32) unsigned char smem[];
-  const int32_t bk = blk_ids[blockIdx.x];
+__device__ __forceinline__ void project_block(int32_t bk, const int64_t *__restrict__ boff, const int32_t *__restrict__ bsz,
+                                              const double *__restrict__ Xb, double *__restrict__ S,
+                                              const DevState *__restrict__ st, double scale, double *__restrict__ Q,
+                                              const int64_t *__restrict__ qoff, int32_t warm, uint32_t lds_cap,
+                                              unsigned char *smem) {
   const int n = bsz[bk];
   const int nn = n + (n & 1), np2 = nn / 2, nblk = np2 * (np2 + 1) / 2;
   const int64_t off = boff[bk];
@@ -559,6 +557,33 @@ __global__ void __launch_bounds__(1024) k_project_admm(const int32_t *__restrict
     S[off + k] = pos ? (acc - Xb[off + k]) * mul   // (Pi - X_b) * mul
                      : -acc * mul;                  // -Pi_-(X_b) * mul
   }
+}
+
+template <typename T, bool BIG>
+__global__ void __launch_bounds__(1024) k_project_admm(const int32_t *__restrict__ blk_ids, const int64_t *__restrict__ boff,
+                                                       const int32_t *__restrict__ bsz, const double *__restrict__ Xb,
+                                                       double *__restrict__ S, const DevState *__restrict__ st,
+                                                       double scale, double *__restrict__ Q,
+                                                       const int64_t *__restrict__ qoff, int32_t warm, uint32_t lds_cap) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  project_block<T, BIG>(blk_ids[blockIdx.x], boff, bsz, Xb, S, st, scale, Q, qoff, warm, lds_cap, smem);
+}
+
+// The same over a batch: item = (instance, block); instances that are retired or whose
+// projection precision is not T are skipped.  cone = 0: X_b -> S with 1 / sigma; cone = 1:
+// X -> X_b with scale 1.
+template <typename T, bool BIG>
+__global__ void __launch_bounds__(1024) k_project_batch(const BatchItem *__restrict__ items,
+                                                        const BatchInst *__restrict__ bi, int32_t cone,
+                                                        uint32_t lds_cap) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const BatchItem it = items[blockIdx.x];
+  const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
+  if (!I.active || I.f32 != (sizeof(T) == sizeof(float) ? 1 : 0)) return;
+  const double *in = G(cone ? I.X : I.Xb);
+  double *out = G(cone ? I.Xb : I.S);
+  project_block<T, BIG>(it.idx, G(I.boff), G(I.bsz), in, out, G(I.st), cone ? 1.0 : 0.0, G(I.Q), G(I.qoff), I.warm,
+                        lds_cap, smem);
 }
 
 // strom_project_psd_batched: column-major blocks in T, at element offsets.
@@ -728,6 +753,38 @@ hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const 
     else launch_admm_t<double, false>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
   }
   return hipGetLastError();
+}
+
+template <typename T, bool BIG>
+static void launch_batch_t(hipStream_t s, int count, int nt, size_t lds, const BatchItem *items, const BatchInst *bi,
+                           int cone) {
+  (void)hipFuncSetAttribute((const void *)k_project_batch<T, BIG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_project_batch<T, BIG>), dim3(count), dim3(nt), lds, s, items, bi, cone, (uint32_t)lds);
+}
+
+hipError_t launch_project_batch(hipStream_t s, bool f32, int n, int nt, int count, const BatchItem *items,
+                                const BatchInst *bi, int cone) {
+  if (count <= 0) return hipSuccess;
+  const size_t lds = project_lds_bytes(n, f32, nt);
+  bool big = false;
+  if (!threads_ok(n, nt, f32, big) || lds > kLdsCap) return hipErrorInvalidValue;
+  if (f32) {
+    if (big) launch_batch_t<float, true>(s, count, nt, lds, items, bi, cone);
+    else launch_batch_t<float, false>(s, count, nt, lds, items, bi, cone);
+  } else {
+    if (big) launch_batch_t<double, true>(s, count, nt, lds, items, bi, cone);
+    else launch_batch_t<double, false>(s, count, nt, lds, items, bi, cone);
+  }
+  return hipGetLastError();
+}
+
+int project_thread_options(int n, bool f32, int *out) {
+  int k = 0;
+  for (int nt = 64; nt <= 1024; nt *= 2) {
+    bool big = false;
+    if (threads_ok(n, nt, f32, big)) out[k++] = nt;
+  }
+  return k;
 }
 
 template <typename T, bool BIG>

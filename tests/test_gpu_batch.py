@@ -1,0 +1,126 @@
+"""GPU tests of the merged form (strom_batch_*): instances of different families and sizes
+advanced together, one launch per step over all of them, through the C ABI.  Each instance
+must follow the iterates it follows alone (same kernels, same thread counts per block), and
+those of the oracle; retired instances must stay unchanged."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+CAR_PRM = [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2406_05846_amd as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    c = S.Context(0)
+    yield c
+    c.close()
+
+
+def _cases():
+    import workloads as W
+    return [(W.PENDULUM, 5, [0.5, 0.0]), (W.CARTPOLE, 3, [0.1, 0.2, 0.5, 0.3]), (W.CAR, 3, CAR_PRM),
+            (W.PENDULUM, 12, [-2.0, 0.4])]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(1.0, np.linalg.norm(b))
+
+
+def test_batch_fixed_sigma_iterates_match_alone_and_oracle(S, ctx, orc):
+    """25 iterations with a fixed sigma (a first round launched directly, one graph round, a
+    partial round): every instance of the batch equals its own run alone and the oracle's."""
+    cases = _cases()
+    opts = S.default_opts(sigma_every=0, tol=0.0)
+    alone = []
+    for fam, N, prm in cases:
+        ins = S.Instance(ctx, S.generate(fam, N, prm), opts)
+        ins.step(25)
+        alone.append(ins.get_iterate())
+        ins.close()
+    insts = [S.Instance(ctx, S.generate(fam, N, prm), opts) for fam, N, prm in cases]
+    bat = S.Batch(ctx, insts)
+    infos = bat.step(25)
+    assert [i["iters"] for i in infos] == [25] * len(cases)
+    bat.close()
+    for (fam, N, prm), ins, (Xa, ya, Sa) in zip(cases, insts, alone):
+        Xg, yg, Sg = ins.get_iterate()
+        assert _rel(Xg, Xa) <= 1e-12 and _rel(Sg, Sa) <= 1e-12, (fam, N)
+        osdp = orc.relax(fam, N, prm)
+        r = orc.admm_solve(osdp, maxiter=25, tol=0.0, sigma_every=0)
+        assert _rel(Xg, r["X"]) <= 1e-9 and _rel(Sg, r["S"]) <= 1e-9, (fam, N)
+        assert _rel(osdp.A.T @ yg, osdp.A.T @ r["y"]) <= 1e-9, (fam, N)
+        ins.close()
+
+
+def test_batch_converged_solves_match_alone_and_retire(S, ctx):
+    """Default rules (sigma balancing, tol 1e-6), one instance with the FP32 projection and the
+    FP64 polish: every instance converges at the iteration it converges alone, to the same
+    objective, and stays unchanged once retired."""
+    import workloads as W
+    cases = [(W.PENDULUM, 6, [2.0, 0.0], "f64"), (W.PENDULUM, 8, [0.8, 0.0], "f32"),
+             (W.PENDULUM, 5, [-1.2, 0.5], "f64")]
+    alone = []
+    for fam, N, prm, dt in cases:
+        ins = S.Instance(ctx, S.generate(fam, N, prm), S.default_opts(proj_dtype=dt))
+        alone.append(ins.step(50000))
+        ins.close()
+    insts = [S.Instance(ctx, S.generate(fam, N, prm), S.default_opts(proj_dtype=dt)) for fam, N, prm, dt in cases]
+    bat = S.Batch(ctx, insts)
+    infos = bat.step(50000)
+    frozen = [ins.get_iterate()[0] for ins in insts]
+    again = bat.step(100)
+    for a, b, c in zip(alone, infos, again):
+        assert a["state"] == b["state"] == S.CONVERGED
+        assert b["iters"] == a["iters"], (a["iters"], b["iters"])
+        assert abs(b["pobj"] - a["pobj"]) <= 1e-9 * (1.0 + abs(a["pobj"]))
+        assert c["iters"] == b["iters"] and c["pobj"] == b["pobj"]
+    for ins, X0 in zip(insts, frozen):
+        assert np.array_equal(ins.get_iterate()[0], X0)
+    bat.close()
+    for ins in insts:
+        ins.close()
+
+
+def test_batch_tune_keeps_the_iterates(S, ctx, orc):
+    """The autotuner picks a thread count per block class among those the kernel accepts; the
+    iterates after it stay those of the oracle."""
+    cases = _cases()[:3]
+    opts = S.default_opts(sigma_every=0, tol=0.0, proj_dtype="f64")
+    insts = [S.Instance(ctx, S.generate(fam, N, prm), opts) for fam, N, prm in cases]
+    bat = S.Batch(ctx, insts)
+    bat.step(10)
+    cls = bat.tune(reps=2)
+    assert len(cls) >= 2
+    for n, t64, t32 in cls:
+        assert t64 in (64, 128, 256, 512, 1024) and t64 >= n
+    bat.step(10)
+    bat.close()
+    for (fam, N, prm), ins in zip(cases, insts):
+        Xg, yg, Sg = ins.get_iterate()
+        r = orc.admm_solve(orc.relax(fam, N, prm), maxiter=20, tol=0.0, sigma_every=0)
+        assert _rel(Xg, r["X"]) <= 1e-9 and _rel(Sg, r["S"]) <= 1e-9, (fam, N)
+        ins.close()
+
+
+def test_batch_membership_is_enforced(S, ctx):
+    import workloads as W
+    ins = S.Instance(ctx, S.generate(W.PENDULUM, 4, [0.5, 0.0]))
+    bat = S.Batch(ctx, [ins])
+    with pytest.raises(S.StromError) as e:
+        ins.step(1)
+    assert e.value.code == -7
+    with pytest.raises(S.StromError):
+        S.Batch(ctx, [ins])  # already in a batch
+    bat.step(1)
+    bat.close()
+    assert ins.step(1)["iters"] == 2
+    ins.close()
