@@ -107,34 +107,51 @@ def _serving(S, W, np, ctx, args) -> dict:
 def _batched(S, W, torch, args) -> dict:
     """Batched form: a mixed batch of instances (families uniform over pendulum, cart-pole, car;
     horizons N ~ U{10..60}) advanced together by merged launches (one per step over all
-    instances, rounds replayed from HIP graphs), FP32 projection with the FP64 polish, FP64
-    solves and residuals, after the projection autotuner.  Beside it, a sample of the same
-    problems stepped one instance at a time in the FP64 per-instance form."""
+    instances of a lane, rounds replayed from HIP graphs), FP32 projection with the FP64
+    polish, FP64 solves and residuals, after the projection autotuner.  The instances are dealt
+    round-robin to `lanes` batches, each on a context with its own stream and stepped from its
+    own host thread, so that one lane's launch tails overlap another's work.  Beside it, a
+    sample of the same problems stepped one instance at a time in the FP64 per-instance form."""
+    import threading
     from concurrent.futures import ThreadPoolExecutor
-    K, iters = args.batch, 50
+    K, iters, L = args.batch, 50, max(1, args.batch_lanes)
     cases = W.mixed_batch(args.seed, count=K, nmin=10, nmax=60)
     t0 = time.perf_counter()
     probs = [S.generate(f, N, p) for f, N, p in cases]
     t1 = time.perf_counter()
-    ctx = S.Context(0)
+    ctxs = [S.Context(0, stream=torch.cuda.Stream()) for _ in range(L)]
     opts = S.default_opts(tol=0.0, maxiter=10**9, proj_dtype="f32")
     with ThreadPoolExecutor(max_workers=16) as ex:  # the host analysis runs outside the GIL
-        insts = list(ex.map(lambda pr: S.Instance(ctx, pr, opts), probs))
+        insts = [list(ex.map(lambda pr: S.Instance(ctxs[l], pr, opts), probs[l::L])) for l in range(L)]
     t2 = time.perf_counter()
     _log(f"batched: {K} instances generated in {t1 - t0:.1f} s, set up in {t2 - t1:.1f} s")
-    bat = S.Batch(ctx, insts)
-    bat.step(10)
-    tuned = bat.tune(reps=3)
-    bat.step(args.batch_warmup)
+    bats = [S.Batch(ctxs[l], insts[l]) for l in range(L)]
+
+    def step_all(n):
+        th = [threading.Thread(target=b.step, args=(n,)) for b in bats]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+
+    step_all(10)
+    tuned = [b.tune(reps=3) for b in bats][0]
+    step_all(args.batch_warmup)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    bat.step(iters)
+    step_all(iters)
+    torch.cuda.synchronize()
     t4 = time.perf_counter()
-    bat.close()
+    for b in bats:
+        b.close()
     nsvec = sum(pr.nsvec for pr in probs)
-    for ins in insts:
-        ins.close()
+    for lane in insts:
+        for ins in lane:
+            ins.close()
+    for c in ctxs[1:]:
+        c.close()
     # the same problems one at a time, FP64 per-instance form
+    ctx = ctxs[0]
     sample = probs[:: max(1, K // 16)][:16]
     t_alone, it_alone = 0.0, 30
     for pr in sample:
@@ -148,10 +165,10 @@ def _batched(S, W, torch, args) -> dict:
     rate = K * iters / (t4 - t3)
     rate_alone = len(sample) * it_alone / t_alone
     out = {"workload": f"{K} instances of the mixed batch of seed {args.seed} (pendulum / cart-pole / car uniform, "
-                       f"N ~ U{{10..60}}, total n_svec {nsvec}), FP32 projection + FP64 polish, merged launches, "
-                       f"{iters} timed iterations after {10 + args.batch_warmup} and the autotuner",
+                       f"N ~ U{{10..60}}, total n_svec {nsvec}), FP32 projection + FP64 polish, merged launches in "
+                       f"{L} lanes, {iters} timed iterations after {10 + args.batch_warmup} and the autotuner",
            "instance_iters_per_s": round(rate, 1), "ms_per_batch_iteration": round(1e3 * (t4 - t3) / iters, 3),
-           "setup_s": round(t2 - t1, 2), "tuned_threads": tuned,
+           "setup_s": round(t2 - t1, 2), "lanes": L, "tuned_threads_lane0": tuned,
            "per_instance_fp64": {"sample": f"{len(sample)} of the same problems one at a time, {it_alone} "
                                            f"iterations each", "instance_iters_per_s": round(rate_alone, 1)},
            "speedup_vs_per_instance_fp64": round(rate / rate_alone, 2)}
@@ -208,6 +225,7 @@ def main():
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving sample (0: skip)")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched form (0: skip)")
     ap.add_argument("--batch-warmup", type=int, default=20, help="warmup iterations of the batched form")
+    ap.add_argument("--batch-lanes", type=int, default=4, help="lanes (contexts with their own stream) of the batch")
     ap.add_argument("--warm", type=int, default=3, help="receding-horizon warm-start steps (0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
