@@ -89,7 +89,7 @@ template <typename T>
 struct JacobiTol;
 template <>
 struct JacobiTol<double> {
-  static constexpr double off_rel = 1e-13;   // stop when off(A) <= off_rel * ||A||_F
+  static constexpr double off_rel = 1e-11;   // stop when off(A) <= off_rel * ||A||_F
   static constexpr double skip_rel = 1e-18;  // no rotation for |a_pq| <= skip_rel * ||A||_F
 };
 template <>
