@@ -405,3 +405,22 @@ def test_batched_instances_on_streams_match_alone(S):
         ins.close()
     for c in ctxs:
         c.close()
+
+
+def test_paper_pendulum_full_size_iterates(S, ctx, orc):
+    """The paper's own pendulum shape (variational-integrator dynamics; n_svec 49,500, m 47,351,
+    30 moment blocks 55x55 + 60 localizing 10x10): three iterations with a fixed sigma."""
+    import workloads as W
+    prm = W.instance_params(W.PAPER_PENDULUM, 0)
+    osdp = orc.relax(W.PAPER_PENDULUM, 30, prm)
+    prob = S.generate(W.PAPER_PENDULUM, 30, prm)
+    assert (prob.nsvec, prob.m) == (49500, 47351)
+    inst = S.Instance(ctx, prob, _opts(S, sigma_every=0, kkt_every=1, tol=0.0))
+    inst.step(3)
+    Xg, yg, Sg = inst.get_iterate()
+    r = orc.admm_solve(osdp, maxiter=3, tol=0.0, sigma_every=0)
+    assert np.linalg.norm(Xg - r["X"]) / max(1.0, np.linalg.norm(r["X"])) <= 1e-9
+    assert np.linalg.norm(Sg - r["S"]) / max(1.0, np.linalg.norm(r["S"])) <= 1e-9
+    aty, atyo = osdp.A.T @ yg, osdp.A.T @ r["y"]
+    assert np.linalg.norm(aty - atyo) / max(1.0, np.linalg.norm(atyo)) <= 1e-9
+    inst.close()
