@@ -62,11 +62,12 @@ def _cpu_baseline(fam: int, N: int, prm, iters: int) -> dict:
                       f"{t1 - t0:.2f} s and LDL^T {r['t_setup_s']:.2f} s excluded), one thread, FP64"}
 
 
-def _serving(S, W, np, ctx, args) -> dict:
-    """Seeded Poisson arrivals of pendulum requests (N ~ U{6..12}) through the request loop;
-    latency is arrival to retire."""
-    # Poisson arrivals (seeded), pendulum requests with N ~ U{6..12}, admitted by the
-    # context's request loop; latency = arrival to retire
+def _serving(S, W, np, ctx, args, dtype="f64") -> dict:
+    """Seeded Poisson arrivals of pendulum requests (N ~ U{6..12}) through the request loop
+    (continuous batching: admitted instances join the merged batch between rounds, converged
+    ones retire); latency is arrival to retire.  dtype: projection precision of the requests
+    ("f32": FP32 projection with the FP64 polish)."""
+    opts = S.default_opts(proj_dtype=dtype)
     rng = W.SplitMix64(1000 + args.seed)
     rate = 400.0
     reqs, t_arr = [], 0.0
@@ -80,7 +81,7 @@ def _serving(S, W, np, ctx, args) -> dict:
     while k < len(reqs) or pending:
         now = time.perf_counter() - start
         while k < len(reqs) and reqs[k][0] <= now:
-            pending[ctx.submit(reqs[k][1])] = reqs[k][0]
+            pending[ctx.submit(reqs[k][1], opts)] = reqs[k][0]
             k += 1
         for tk in list(pending):
             r = ctx.poll(tk)
@@ -93,8 +94,9 @@ def _serving(S, W, np, ctx, args) -> dict:
         time.sleep(0.0005)
     wall = time.perf_counter() - start
     lat = np.array(lat)
+    form = "FP64" if dtype == "f64" else "FP32 projection + FP64 polish"
     serving = {"workload": f"{len(reqs)} pendulum requests, N ~ U{{6..12}}, Poisson arrivals at "
-                           f"{rate:.0f}/s, FP64, retire at eta <= 1e-6 (or maxiter)",
+                           f"{rate:.0f}/s, {form}, retire at eta <= 1e-6 (or maxiter)",
                "solves_per_s": round(float(sum(st == S.CONVERGED for st in states) / wall), 3),
                "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4),
                              "p99": round(float(np.percentile(lat, 99)), 4)} if len(lat) else None,
@@ -371,6 +373,9 @@ def main():
     solves32 = solve_set(S.default_opts(proj_dtype=S.F32), "fp32+polish")
 
     serving = _serving(S, W, np, ctx, args) if args.serve > 0 else None
+    serving32 = _serving(S, W, np, ctx, args, "f32") if args.serve > 0 else None
+    if serving is not None:
+        serving["fp32_polish"] = serving32
     batched = _batched(S, W, torch, args) if args.batch > 0 else None
     warm = _warm_start(S, W, np, ctx, args) if args.warm > 0 else None
     paper = _paper_pendulum(S, W, ctx, args) if args.paper else None

@@ -208,8 +208,9 @@ strom_status strom_dual_bound(strom_sdp *sdp, const double *R_beta, double *lb, 
 strom_status strom_extract(strom_sdp *sdp, int32_t nlist, const int32_t *blocks, double *lam, double *vtop);
 
 /* Merged form: Alg. 1 advanced for many independent instances at once.  A batch groups instances
- * of one ctx that were set up with the same kkt_every and sigma_every and stand at the same
- * iteration count; while it exists they are iterated only through it (strom_admm_step,
+ * of one ctx that were set up with the same kkt_every and sigma_every and whose iteration
+ * counts agree modulo kkt_every (a fresh instance, at 0, joins instances that have run whole
+ * rounds); while it exists they are iterated only through it (strom_admm_step,
  * strom_admm_enqueue, strom_set_iterate and strom_sdp_destroy on them return E_STATE).  Each
  * step of the iteration is one launch over all instances (a workgroup per row or column chunk,
  * solve task or PSD block of any instance; the solve's dependency groups are merged by depth),

@@ -588,10 +588,8 @@ hipError_t sdp_read_state(strom_sdp *s) {
   apply_polish_switch(s);
   return hipSuccess;
 }
-strom_solve_state sdp_classify(strom_sdp *s) { return s->state = classify(s); }
 void sdp_info(strom_sdp *s, strom_info *info) { fill_info(s, info); }
 const strom_opts &sdp_opts(strom_sdp *s) { return s->opts; }
-void sdp_set_stream(strom_sdp *s, hipStream_t q) { s->stream = q; }
 }  // namespace strom
 
 extern "C" strom_status strom_admm_step(strom_sdp *s, int32_t n_iter, strom_info *info) {
@@ -911,7 +909,7 @@ struct strom_batch {
   std::vector<strom_sdp *> inst;
   hipStream_t stream = nullptr;  // the context's stream
   int kk = 10, se = 50;          // kkt_every and sigma_every shared by the instances
-  int64_t iters = 0;             // iteration count of the running instances
+  int phase = 0;                 // iteration count of every instance modulo kk
   unsigned char *arena = nullptr;
   strom::dev::BatchInst *bi_dev = nullptr, *bi_host = nullptr;  // bi_host: pinned mirror
   strom::dev::SolveArgs *sa_dev = nullptr;
@@ -926,7 +924,7 @@ struct strom_batch {
   bool any_f32 = false;  // an instance was set up with the FP32 projection
   size_t solve_lds = 0;
   DevState *states_dev = nullptr, *states_host = nullptr;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};  // one round, [sigma rule on its last iteration]
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // one round, [sigma rule for some instance at its end]
   hipStream_t capture_stream = nullptr;
   bool graphs = true;
 };
@@ -990,15 +988,18 @@ void batch_drop_graphs(strom_batch *b) {
     }
 }
 
-// Flags of every instance for the next launches, copied on the batch stream; the pinned host
-// copy is not written again before that stream has been synchronized.
-hipError_t batch_upload_flags(strom_batch *b) {
+// Flags of every instance for the next launches (a round of `chunk` iterations; chunk < 0:
+// every running instance takes the sigma-rule projection, as the autotuner's launches do),
+// copied on the batch stream; the pinned host copy is not written again before that stream
+// has been synchronized.
+hipError_t batch_upload_flags(strom_batch *b, int chunk) {
   for (size_t i = 0; i < b->inst.size(); ++i) {
     const strom_sdp *s = b->inst[i];
     auto &I = b->bi_host[i];
     I.active = s->state == STROM_RUNNING ? 1 : 0;
     I.f32 = s->f32_active ? 1 : 0;
     I.warm = s->q_valid ? 1 : 0;
+    I.sig = I.active && (chunk < 0 || (b->se > 0 && (s->iters + chunk) % b->se == 0)) ? 1 : 0;
   }
   return hipMemcpyAsync(b->bi_dev, b->bi_host, sizeof(strom::dev::BatchInst) * b->inst.size(), hipMemcpyHostToDevice,
                         b->stream);
@@ -1021,7 +1022,8 @@ extern "C" strom_status strom_batch_create(strom_ctx *ctx, int32_t count, strom_
     if (s->batch) return fail(STROM_E_STATE, "instance " + std::to_string(i) + " already belongs to a batch");
     if (s->opts.kkt_every != v[0]->opts.kkt_every || s->opts.sigma_every != v[0]->opts.sigma_every)
       return fail(STROM_E_INVAL, "the instances of a batch need the same kkt_every and sigma_every");
-    if (s->iters != v[0]->iters) return fail(STROM_E_INVAL, "the instances of a batch need the same iteration count");
+    if (s->iters % s->opts.kkt_every != v[0]->iters % v[0]->opts.kkt_every)
+      return fail(STROM_E_INVAL, "the iteration counts of a batch's instances must agree modulo kkt_every");
     for (int32_t j = 0; j < i; ++j)
       if (v[size_t(j)] == s) return fail(STROM_E_INVAL, "instance listed twice");
   }
@@ -1031,7 +1033,7 @@ extern "C" strom_status strom_batch_create(strom_ctx *ctx, int32_t count, strom_
   b->stream = ctx->stream;
   b->kk = v[0]->opts.kkt_every;
   b->se = v[0]->opts.sigma_every;
-  b->iters = v[0]->iters;
+  b->phase = int(v[0]->iters % b->kk);
 
   std::vector<BatchInst> bi(static_cast<size_t>(count));
   std::vector<SolveArgs> sa(static_cast<size_t>(count));
@@ -1154,12 +1156,14 @@ extern "C" strom_status strom_batch_step(strom_batch *b, int32_t n_iter, strom_i
         all_warm &= s->q_valid;
       }
     if (room == INT64_MAX) break;  // every instance retired
-    const int chunk = int(std::min<int64_t>(std::min<int64_t>(b->kk - b->iters % b->kk, n_iter - done), room));
+    const int chunk = int(std::min<int64_t>(std::min<int64_t>(b->kk - b->phase, n_iter - done), room));
     if (chunk <= 0) break;
-    HIP_TRY(batch_upload_flags(b));
+    HIP_TRY(batch_upload_flags(b, chunk));
+    bool any_sig = false;
+    for (size_t i = 0; i < K; ++i) any_sig |= b->bi_host[i].sig != 0;
     bool launched = false;
     if (b->graphs && all_warm && chunk == b->kk) {
-      const int sl = (b->se > 0 && (b->iters + b->kk) % b->se == 0) ? 1 : 0;
+      const int sl = any_sig ? 1 : 0;
       if (!b->graph[sl] && batch_capture(b, sl != 0, &b->graph[sl]) != hipSuccess) {
         b->graphs = false;  // capture not available: launch directly from now on
         b->graph[sl] = nullptr;
@@ -1171,16 +1175,15 @@ extern "C" strom_status strom_batch_step(strom_batch *b, int32_t n_iter, strom_i
       }
     }
     for (int k = 0; !launched && k < chunk; ++k) {
-      const bool sig = b->se > 0 && (b->iters + k + 1) % b->se == 0;
-      HIP_TRY(batch_iteration(b, b->stream, k == chunk - 1, sig));
+      HIP_TRY(batch_iteration(b, b->stream, k == chunk - 1, any_sig && k == chunk - 1));
       if (k == 0 && !all_warm) {  // the first projection has filled every running instance's Q
         for (strom_sdp *s : b->inst)
           if (s->state == STROM_RUNNING) s->q_valid = true;
         HIP_TRY(hipStreamSynchronize(b->stream));
-        HIP_TRY(batch_upload_flags(b));
+        HIP_TRY(batch_upload_flags(b, chunk));
       }
     }
-    b->iters += chunk;
+    b->phase = (b->phase + chunk) % b->kk;
     done += chunk;
     HIP_TRY(strom::dev::launch_gather_states(b->stream, int(K), b->bi_dev, b->states_dev));
     HIP_TRY(hipMemcpyAsync(b->states_host, b->states_dev, sizeof(DevState) * K, hipMemcpyDeviceToHost, b->stream));
@@ -1217,7 +1220,7 @@ extern "C" strom_status strom_batch_tune(strom_batch *b, int32_t reps, int32_t c
     }
     if (any) {
       HIP_TRY(hipSetDevice(b->ctx->device));
-      HIP_TRY(batch_upload_flags(b));
+      HIP_TRY(batch_upload_flags(b, -1));
       hipEvent_t e0 = nullptr, e1 = nullptr;
       HIP_TRY(hipEventCreate(&e0));
       HIP_TRY(hipEventCreate(&e1));

@@ -79,6 +79,7 @@ struct BatchInstT {
   int32_t active;          // 0: retired, every merged launch skips the instance
   int32_t f32;             // projection precision: 1 FP32, 0 FP64
   int32_t warm;            // Q holds eigenvectors to start from
+  int32_t sig;             // the sigma rule applies at the end of this round
   Ptr<const int64_t> A_rp, At_rp, boff, qoff;
   Ptr<const int32_t> A_ci, At_ci, pinv, bsz;
   Ptr<const double> A_v, At_v, b, C;
@@ -91,8 +92,8 @@ using BatchInstG = BatchInstT<GlobPtr>;
 // The host fills these tables and the device reads them through the global view: both
 // compilations must see one layout.
 static_assert(sizeof(SolveArgs) == 368 && sizeof(SolveArgsG) == sizeof(SolveArgs), "SolveArgs layout");
-static_assert(sizeof(BatchInst) == 224 && sizeof(BatchInstG) == sizeof(BatchInst) &&
-                  offsetof(BatchInst, st) == 200 && offsetof(BatchInstG, st) == 200,
+static_assert(sizeof(BatchInst) == 232 && sizeof(BatchInstG) == sizeof(BatchInst) &&
+                  offsetof(BatchInst, st) == 208 && offsetof(BatchInstG, st) == 208,
               "BatchInst layout");
 
 // A work item of a merged launch: the instance and its local index (row or column chunk, solve
@@ -153,13 +154,16 @@ hipError_t launch_solve_batch(hipStream_t s, const std::vector<int32_t> &fwd_gpt
                               const BatchInst *bi, size_t lds_bytes);
 hipError_t launch_xb_batch(hipStream_t s, int count, const BatchItem *cols, const BatchInst *bi);
 hipError_t launch_xupdate_batch(hipStream_t s, int count, const BatchItem *cols, const BatchInst *bi, int want_part);
+// Residuals of every running instance; with do_sigma, the sigma rule too for the instances whose
+// sig flag is set.
 hipError_t launch_kkt_batch(hipStream_t s, int nrows, const BatchItem *rows, int ncols, const BatchItem *cols,
                             int ninst, const BatchInst *bi, int do_sigma);
 // Copies every instance's DevState to out[0 .. ninst).
 hipError_t launch_gather_states(hipStream_t s, int ninst, const BatchInst *bi, DevState *out);
 // PSD projection of blocks of one size n over a batch, nt threads per workgroup; only the
 // instances whose precision flag matches f32 are projected.  cone = 0: S = (Pi(X_b) - X_b) /
-// sigma (step 2); cone = 1: X_b = Pi(X) - X (the sigma rule's cone distance).
+// sigma (step 2); cone = 1: X_b = Pi(X) - X (the sigma rule's cone distance), only for the
+// instances whose sig flag is set.
 hipError_t launch_project_batch(hipStream_t s, bool f32, int n, int nt, int count, const BatchItem *items,
                                 const BatchInst *bi, int cone);
 // Thread counts the projection kernel accepts for blocks of size n (at most 5, ascending).

@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(256) k_sqnorms_batch(const BatchItem *__restri
   __shared__ double red[256];
   const BatchItem it = items[blockIdx.x];
   const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
-  if (!I.active) return;
+  if (!I.active || !I.sig) return;
   sqnorms_chunk(it.idx, I.n, G(I.Xb), G(I.X), G(I.part_cone), red);
 }
 
@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(256) k_kkt_final_batch(const BatchInst *__rest
   const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[blockIdx.x];
   if (!I.active) return;
   kkt_final_body(G(I.part_rows), I.nrow_chunks, G(I.part_cols), I.ncol_chunks, G(I.part_cone), I.normb, I.normC,
-                 do_sigma, G(I.st), red);
+                 do_sigma && I.sig, G(I.st), red);
 }
 
 __global__ void k_gather_states(int32_t ninst, const BatchInst *__restrict__ bi, DevState *__restrict__ out) {

@@ -571,7 +571,7 @@ __global__ void __launch_bounds__(1024) k_project_admm(const int32_t *__restrict
 
 // The same over a batch: item = (instance, block); instances that are retired or whose
 // projection precision is not T are skipped.  cone = 0: X_b -> S with 1 / sigma; cone = 1:
-// X -> X_b with scale 1.
+// X -> X_b with scale 1, for the instances that apply the sigma rule this round.
 template <typename T, bool BIG>
 __global__ void __launch_bounds__(1024) k_project_batch(const BatchItem *__restrict__ items,
                                                         const BatchInst *__restrict__ bi, int32_t cone,
@@ -579,7 +579,7 @@ __global__ void __launch_bounds__(1024) k_project_batch(const BatchItem *__restr
   extern __shared__ __align__(32) unsigned char smem[];
   const BatchItem it = items[blockIdx.x];
   const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
-  if (!I.active || I.f32 != (sizeof(T) == sizeof(float) ? 1 : 0)) return;
+  if (!I.active || I.f32 != (sizeof(T) == sizeof(float) ? 1 : 0) || (cone && !I.sig)) return;
   const double *in = G(cone ? I.X : I.Xb);
   double *out = G(cone ? I.Xb : I.S);
   project_block<T, BIG>(it.idx, G(I.boff), G(I.bsz), in, out, G(I.st), cone ? 1.0 : 0.0, G(I.Q), G(I.qoff), I.warm,

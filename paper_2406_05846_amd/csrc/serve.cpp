@@ -2,11 +2,12 @@
 //
 // A setup thread takes submitted problems in arrival order, builds each instance (host
 // analysis + upload) as soon as its device footprint fits the context's HBM budget, and
-// hands it to the solver thread.  The solver thread keeps up to `max_slots` instances in
-// flight, each on its own non-blocking stream, so that kernels of different instances overlap
-// on the device; it advances every instance by a few iterations per round, reads back the
-// residuals, retires instances that converged (or hit maxiter, or diverged), frees their
-// memory and admits the next ready instance into the free slot.
+// hands it to the solver thread.  The solver thread keeps every admitted instance in a merged
+// batch (strom_batch_*: one launch per step over all of them) of instances with the same
+// round length and sigma period; it advances each batch one round at a time, retires the
+// instances that converged (or hit maxiter, or diverged), frees their memory, and rebuilds the
+// batch with the instances admitted meanwhile.  A batch's instances have run whole rounds, so
+// a fresh one (at iteration 0) can join it.
 #include "serve.h"
 
 #include <chrono>
@@ -38,12 +39,20 @@ struct Job {
   strom_opts o{};
   double t_arrive = 0, t_admit = 0, t_done = 0;
   strom_sdp *sdp = nullptr;
-  int slot = -1;
   bool done = false;
   strom_status err = STROM_OK;
   std::string errmsg;
   strom_info info{};
   std::vector<double> X, y, S;
+};
+
+// Instances iterated together: same kkt_every and sigma_every, iteration counts equal modulo
+// kkt_every (phase).
+struct Group {
+  int kk = 10, se = 50, phase = 0;
+  std::vector<Job *> act;
+  strom_batch *bat = nullptr;
+  bool dirty = true;  // membership changed since the batch was built
 };
 
 struct Server {
@@ -53,13 +62,11 @@ struct Server {
   std::mutex mu;
   std::condition_variable cv_setup, cv_solve;
   std::deque<Job *> queued, ready;
-  std::vector<Job *> active;
+  size_t n_active = 0;
   std::map<uint64_t, Job *> jobs;
   bool stop = false;
   uint64_t next = 1;
-  std::vector<hipStream_t> streams;
-  std::vector<char> slot_busy;
-  int iters_per_round = 10;
+  std::vector<Group> groups;  // solver thread only
   uint64_t retired_since_wait = 0;
   std::FILE *log = nullptr;  // round timing, when STROM_SERVE_LOG names a file
 };
@@ -101,7 +108,7 @@ void setup_loop(Server *S) {
     if (rc == STROM_E_NOMEM) {
       // wait for a retirement to free memory; fail only if nothing else holds any
       std::unique_lock<std::mutex> lk(S->mu);
-      if (S->active.empty() && S->ready.empty()) {
+      if (S->n_active == 0 && S->ready.empty()) {
         S->queued.pop_front();
         lk.unlock();
         finish(S, j, rc, strom_last_error());
@@ -139,7 +146,7 @@ void retire(Server *S, Job *j) {
   strom_sdp_destroy(sdp);
   std::lock_guard<std::mutex> lk(S->mu);
   j->sdp = nullptr;
-  S->slot_busy[size_t(j->slot)] = 0;
+  S->n_active--;
   j->t_done = now_s();
   j->info.t_queue_s = j->t_admit - j->t_arrive;
   j->info.t_solve_s = j->t_done - j->t_admit;
@@ -150,67 +157,96 @@ void retire(Server *S, Job *j) {
   S->cv_setup.notify_one();
 }
 
+void drop_batch(Group &g) {
+  if (g.bat) strom_batch_destroy(g.bat);
+  g.bat = nullptr;
+  g.dirty = true;
+}
+
+// Every job of the group fails (device error): their instances are released.
+void fail_group(Server *S, Group &g, const std::string &msg) {
+  drop_batch(g);
+  for (Job *j : g.act) {
+    strom_sdp_destroy(j->sdp);
+    j->sdp = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->n_active--;
+      S->retired_since_wait++;
+    }
+    finish(S, j, STROM_E_HIP, msg);
+  }
+  g.act.clear();
+  S->cv_setup.notify_one();
+}
+
 void solve_loop(Server *S) {
   hipSetDevice(S->device);
   for (;;) {
+    std::vector<Job *> admit;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_solve.wait(lk, [&] { return S->stop || !S->ready.empty() || !S->active.empty(); });
+      S->cv_solve.wait(lk, [&] { return S->stop || !S->ready.empty() || S->n_active > 0; });
       if (S->stop) return;
       while (!S->ready.empty()) {
-        int slot = -1;
-        for (size_t k = 0; k < S->slot_busy.size(); ++k)
-          if (!S->slot_busy[k]) { slot = int(k); break; }
-        if (slot < 0) break;
         Job *j = S->ready.front();
         S->ready.pop_front();
-        S->slot_busy[size_t(slot)] = 1;
-        j->slot = slot;
         j->t_admit = now_s();
-        sdp_set_stream(j->sdp, S->streams[size_t(slot)]);
-        S->active.push_back(j);
+        admit.push_back(j);
+        S->n_active++;
       }
     }
-    // one round: enqueue on every slot's stream first, then read back, so instances overlap
-    std::vector<Job *> act;
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      act = S->active;
+    for (Job *j : admit) {  // join a group at phase 0 with the same round structure, else open one
+      const strom_opts &o = sdp_opts(j->sdp);
+      Group *g = nullptr;
+      for (auto &c : S->groups)
+        if (c.kk == o.kkt_every && c.se == o.sigma_every && (c.phase == 0 || c.act.empty())) { g = &c; break; }
+      if (!g) {
+        S->groups.emplace_back();
+        g = &S->groups.back();
+        g->kk = o.kkt_every;
+        g->se = o.sigma_every;
+      }
+      if (g->act.empty()) g->phase = 0;
+      g->act.push_back(j);
+      g->dirty = true;
     }
-    std::vector<char> bad(act.size(), 0);
-    const double t_round = now_s();
-    for (size_t k = 0; k < act.size(); ++k) {
-      const strom_opts &o = sdp_opts(act[k]->sdp);
-      int n = S->iters_per_round;
-      (void)o;
-      if (sdp_enqueue(act[k]->sdp, n, true) != hipSuccess) bad[k] = 1;
-    }
-    const double t_enq = now_s();
-    std::vector<Job *> keep;
-    for (size_t k = 0; k < act.size(); ++k) {
-      Job *j = act[k];
-      const double t_s0 = now_s();
-      const bool rd_ok = !bad[k] && sdp_read_state(j->sdp) == hipSuccess;
-      if (S->log) std::fprintf(S->log, "  job %llu wait %.3f ms\n", (unsigned long long)j->id, 1e3 * (now_s() - t_s0));
-      if (!rd_ok) {
-        strom_sdp_destroy(j->sdp);
-        j->sdp = nullptr;
-        {
-          std::lock_guard<std::mutex> lk(S->mu);
-          S->slot_busy[size_t(j->slot)] = 0;
-          S->retired_since_wait++;
+    for (auto &g : S->groups) {
+      if (g.act.empty()) continue;
+      const double t_round = now_s();
+      if (g.dirty) {
+        drop_batch(g);
+        std::vector<strom_sdp *> h;
+        for (Job *j : g.act) h.push_back(j->sdp);
+        if (strom_batch_create(S->ctx, int32_t(h.size()), h.data(), &g.bat) != STROM_OK) {
+          fail_group(S, g, std::string("batch creation failed: ") + strom_last_error());
+          continue;
         }
-        finish(S, j, STROM_E_HIP, "device error while solving");
+        g.dirty = false;
+      }
+      std::vector<strom_info> infos(g.act.size());
+      if (strom_batch_step(g.bat, g.kk - g.phase, infos.data()) != STROM_OK) {
+        fail_group(S, g, std::string("device error while solving: ") + strom_last_error());
         continue;
       }
-      if (sdp_classify(j->sdp) != STROM_RUNNING) retire(S, j);
-      else keep.push_back(j);
+      bool any_done = false;
+      for (const auto &inf : infos) {
+        any_done |= inf.state != STROM_RUNNING;
+        if (inf.state == STROM_RUNNING) g.phase = int(inf.iters % g.kk);
+      }
+      if (any_done) {
+        drop_batch(g);  // the retiring instances leave the batch before they are destroyed
+        std::vector<Job *> keep;
+        for (size_t k = 0; k < g.act.size(); ++k) {
+          if (infos[k].state != STROM_RUNNING) retire(S, g.act[k]);
+          else keep.push_back(g.act[k]);
+        }
+        g.act = keep;
+      }
+      if (S->log)
+        std::fprintf(S->log, "round t=%.3f group kk %d active %zu retired %d total %.3f ms\n", t_round, g.kk,
+                     infos.size(), any_done ? 1 : 0, 1e3 * (now_s() - t_round));
     }
-    if (S->log)
-      std::fprintf(S->log, "round t=%.3f active %zu enqueue %.3f ms total %.3f ms\n", t_round, act.size(),
-                   1e3 * (t_enq - t_round), 1e3 * (now_s() - t_round));
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->active = keep;
   }
 }
 
@@ -221,10 +257,6 @@ Server *server_start(strom_ctx *ctx) {
   S->ctx = ctx;
   hipGetDevice(&S->device);
   if (const char *lp = std::getenv("STROM_SERVE_LOG")) S->log = std::fopen(lp, "w");
-  const int slots = 8;
-  S->streams.resize(slots);
-  S->slot_busy.assign(slots, 0);
-  for (int k = 0; k < slots; ++k) hipStreamCreateWithFlags(&S->streams[size_t(k)], hipStreamNonBlocking);
   S->setup_th = std::thread(setup_loop, S);
   S->solve_th = std::thread(solve_loop, S);
   return S;
@@ -239,11 +271,11 @@ void server_stop(Server *S) {
   S->cv_solve.notify_all();
   S->setup_th.join();
   S->solve_th.join();
+  for (auto &g : S->groups) drop_batch(g);
   for (auto &kv : S->jobs) {
     if (kv.second->sdp) strom_sdp_destroy(kv.second->sdp);
     delete kv.second;
   }
-  for (auto q : S->streams) hipStreamDestroy(q);
   if (S->log) std::fclose(S->log);
   delete S;
 }

@@ -21,9 +21,7 @@ strom_status server_poll(Server *s, uint64_t ticket, strom_info *out, double *X,
 // Instance hooks implemented next to the C ABI (api.cpp).
 hipError_t sdp_enqueue(strom_sdp *s, int n_iter, bool kkt_last);
 hipError_t sdp_read_state(strom_sdp *s);
-strom_solve_state sdp_classify(strom_sdp *s);
 void sdp_info(strom_sdp *s, strom_info *info);
 const strom_opts &sdp_opts(strom_sdp *s);
-void sdp_set_stream(strom_sdp *s, hipStream_t q);
 
 }  // namespace strom
