@@ -124,3 +124,45 @@ def test_batch_membership_is_enforced(S, ctx):
     bat.close()
     assert ins.step(1)["iters"] == 2
     ins.close()
+
+
+def test_batch_members_at_different_iteration_counts(S, ctx):
+    """An instance that has run a round joins a fresh one (their counts agree modulo kkt_every):
+    each keeps its own sigma schedule, so after 50 batched iterations each equals its own run
+    alone (60 and 50 iterations, default sigma rule)."""
+    import workloads as W
+    pa, pb = S.generate(W.PENDULUM, 5, [0.7, 0.0]), S.generate(W.PENDULUM, 6, [-1.9, 0.3])
+    opts = S.default_opts(tol=0.0)
+    ref = []
+    for pr, n in ((pa, 60), (pb, 50)):
+        ins = S.Instance(ctx, pr, opts)
+        info = ins.step(n)
+        ref.append((info, ins.get_iterate()))
+        ins.close()
+    a, b = S.Instance(ctx, pa, opts), S.Instance(ctx, pb, opts)
+    a.step(10)
+    bat = S.Batch(ctx, [a, b])
+    infos = bat.step(50)
+    assert bat.step(0) == infos  # no iteration: the same state again
+    bat.close()
+    for ins, inf, (ri, (Xr, yr, Sr)) in zip((a, b), infos, ref):
+        assert inf["iters"] == ri["iters"] and inf["sigma"] == ri["sigma"]
+        X, y, Sv = ins.get_iterate()
+        assert _rel(X, Xr) <= 1e-12 and _rel(Sv, Sr) <= 1e-12
+        ins.close()
+
+
+def test_batch_rejects_mismatched_rounds(S, ctx):
+    import workloads as W
+    pr = S.generate(W.PENDULUM, 4, [0.5, 0.0])
+    a, b = S.Instance(ctx, pr), S.Instance(ctx, pr, S.default_opts(kkt_every=5, sigma_every=50))
+    with pytest.raises(S.StromError) as e:
+        S.Batch(ctx, [a, b])
+    assert e.value.code == -1
+    c = S.Instance(ctx, pr)
+    c.step(5)  # mid-round: its count differs from a's modulo kkt_every
+    with pytest.raises(S.StromError) as e:
+        S.Batch(ctx, [a, c])
+    assert e.value.code == -1
+    for ins in (a, b, c):
+        ins.close()
