@@ -49,7 +49,7 @@ int32_t lanes_for(int64_t len) {
 
 strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *rowptr,
                               const int32_t *col, const double *val, double eps_reg, HostAnalysis &H,
-                              std::string &err) {
+                              std::string &err, int split_mode) {
   // ---------------------------------------------------------------- validation
   if (nblocks <= 0 || !bsize || m <= 0 || !rowptr || !col || !val) {
     err = "empty problem or NULL array";
@@ -293,9 +293,11 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     const long v = std::strtol(ev, nullptr, 10);
     if (v >= 1 && v <= 256) max_block = int32_t(v);
   }
-  // STROM_TASK_SPLIT: 0 no split, 1 overweight group tasks only, 2 (default) every group task
-  int split_mode = 2;
-  if (const char *ev = std::getenv("STROM_TASK_SPLIT")) split_mode = int(std::strtol(ev, nullptr, 10));
+  // 0 no split, 1 overweight group tasks only, 2 every group task; -1: STROM_TASK_SPLIT, else 2
+  if (split_mode < 0) {
+    split_mode = 2;
+    if (const char *ev = std::getenv("STROM_TASK_SPLIT")) split_mode = int(std::strtol(ev, nullptr, 10));
+  }
   const bool allow_split = split_mode != 0;
   int32_t ntask = int32_t(H.task_r0.size());
   std::vector<int32_t> row_task(static_cast<size_t>(m));
