@@ -1,8 +1,8 @@
 // serve.cpp -- continuous batching of SDP solves on one device.
 //
-// A setup thread takes submitted problems in arrival order, builds each instance (host
-// analysis + upload) as soon as its device footprint fits the context's HBM budget, and
-// hands it to the solver thread.  The solver thread keeps every admitted instance in a merged
+// Setup workers take submitted problems in arrival order, build each instance (host analysis,
+// in parallel across workers, + upload) as soon as its device footprint fits the context's HBM
+// budget, and hand it to the solver thread.  The solver thread keeps every admitted instance in a merged
 // batch (strom_batch_*: one launch per step over all of them) of instances with the same
 // round length and sigma period; it advances each batch one round at a time, retires the
 // instances that converged (or hit maxiter, or diverged), frees their memory, and rebuilds the
@@ -58,7 +58,9 @@ struct Group {
 struct Server {
   strom_ctx *ctx = nullptr;
   int device = 0;
-  std::thread setup_th, solve_th;
+  std::vector<std::thread> setup_th;
+  std::thread solve_th;
+  int in_setup = 0;  // jobs taken by a setup worker and not yet handed on
   std::mutex mu;
   std::condition_variable cv_setup, cv_solve;
   std::deque<Job *> queued, ready;
@@ -72,6 +74,8 @@ struct Server {
 };
 
 namespace {
+
+constexpr int kSetupWorkers = 8;  // host analyses in parallel (the uploads are serialized)
 
 void finish(Server *S, Job *j, strom_status err, const std::string &msg) {
   std::lock_guard<std::mutex> lk(S->mu);
@@ -90,6 +94,8 @@ void setup_loop(Server *S) {
       S->cv_setup.wait(lk, [&] { return S->stop || !S->queued.empty(); });
       if (S->stop) return;
       j = S->queued.front();
+      S->queued.pop_front();
+      S->in_setup++;
     }
     strom_problem P{};
     P.nblocks = int32_t(j->bs.size());
@@ -106,28 +112,31 @@ void setup_loop(Server *S) {
     strom_sdp *sdp = nullptr;
     strom_status rc = strom_sdp_setup(S->ctx, &P, &j->o, &sdp);
     if (rc == STROM_E_NOMEM) {
-      // wait for a retirement to free memory; fail only if nothing else holds any
+      // back to the front of the queue until a retirement frees memory; fail only if nothing
+      // else holds or is about to hold any
       std::unique_lock<std::mutex> lk(S->mu);
-      if (S->n_active == 0 && S->ready.empty()) {
-        S->queued.pop_front();
+      S->in_setup--;
+      if (S->n_active == 0 && S->ready.empty() && S->in_setup == 0) {
         lk.unlock();
         finish(S, j, rc, strom_last_error());
         continue;
       }
+      S->queued.push_front(j);
       const uint64_t seen = S->retired_since_wait;
       S->cv_setup.wait_for(lk, std::chrono::milliseconds(50),
                            [&] { return S->stop || S->retired_since_wait != seen; });
       continue;
     }
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->queued.pop_front();
-    }
     if (rc != STROM_OK) {
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->in_setup--;
+      }
       finish(S, j, rc, strom_last_error());
       continue;
     }
     std::lock_guard<std::mutex> lk(S->mu);
+    S->in_setup--;
     j->sdp = sdp;
     j->nsvec = int64_t(j->C.size());
     S->ready.push_back(j);
@@ -257,7 +266,7 @@ Server *server_start(strom_ctx *ctx) {
   S->ctx = ctx;
   hipGetDevice(&S->device);
   if (const char *lp = std::getenv("STROM_SERVE_LOG")) S->log = std::fopen(lp, "w");
-  S->setup_th = std::thread(setup_loop, S);
+  for (int k = 0; k < kSetupWorkers; ++k) S->setup_th.emplace_back(setup_loop, S);
   S->solve_th = std::thread(solve_loop, S);
   return S;
 }
@@ -269,7 +278,7 @@ void server_stop(Server *S) {
   }
   S->cv_setup.notify_all();
   S->cv_solve.notify_all();
-  S->setup_th.join();
+  for (auto &t : S->setup_th) t.join();
   S->solve_th.join();
   for (auto &g : S->groups) drop_batch(g);
   for (auto &kv : S->jobs) {
