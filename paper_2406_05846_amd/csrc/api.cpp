@@ -328,6 +328,19 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   s->sch.bwd_gptr = H.bwd_gptr;
   s->sch.fwd_order = H.fwd_order;
   s->sch.bwd_order = H.bwd_order;
+  // a task's duration is about the stream entries each of its threads walks, plus a few
+  // per phase for the barriers (merged launches start their longest tasks first)
+  s->sch.fwd_cost.assign(size_t(ntask), 0);
+  s->sch.bwd_cost.assign(size_t(ntask), 0);
+  for (int t = 0; t < ntask; ++t) {
+    int32_t f = H.s_K[4][size_t(t)], b = 0;
+    for (int32_t q = H.task_ph0[size_t(t)]; q < H.task_ph1[size_t(t)]; ++q) {
+      f += H.s_K[0][size_t(q)] + H.s_K[1][size_t(q)] + 4;
+      b += H.s_K[2][size_t(q)] + H.s_K[3][size_t(q)] + 4;
+    }
+    s->sch.fwd_cost[size_t(t)] = f;
+    s->sch.bwd_cost[size_t(t)] = b;
+  }
   s->sch.fwd_order_dev = P32(oFo);
   s->sch.bwd_order_dev = P32(oBo);
 
@@ -1072,9 +1085,12 @@ extern "C" strom_status strom_batch_create(strom_ctx *ctx, int32_t count, strom_
       by_cls[{nk, strom::dev::project_threads(merged ? s->cls_n[0] : nk)}].push_back({i, k});
     }
   }
+  // group g of every instance in one launch, its longest tasks first: workgroups start
+  // roughly in item order, so the launch does not end on a long task started last
   auto merge = [&](size_t ng, bool forward, std::vector<BatchItem> &items, std::vector<int32_t> &gptr) {
     gptr.assign(1, 0);
     for (size_t g = 0; g < ng; ++g) {
+      const size_t first = items.size();
       for (int32_t i = 0; i < count; ++i) {
         const auto &sch = v[size_t(i)]->sch;
         const auto &gp = forward ? sch.fwd_gptr : sch.bwd_gptr;
@@ -1082,6 +1098,12 @@ extern "C" strom_status strom_batch_create(strom_ctx *ctx, int32_t count, strom_
         if (g + 1 >= gp.size()) continue;
         for (int32_t k = gp[g]; k < gp[g + 1]; ++k) items.push_back({i, order[size_t(k)]});
       }
+      auto cost = [&](const BatchItem &it) {
+        const auto &sch = v[size_t(it.inst)]->sch;
+        return (forward ? sch.fwd_cost : sch.bwd_cost)[size_t(it.idx)];
+      };
+      std::stable_sort(items.begin() + long(first), items.end(),
+                       [&](const BatchItem &a, const BatchItem &b) { return cost(a) > cost(b); });
       gptr.push_back(int32_t(items.size()));
     }
   };

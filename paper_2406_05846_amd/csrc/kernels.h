@@ -105,6 +105,7 @@ struct BatchItem {
 struct SolveSchedule {
   std::vector<int32_t> fwd_gptr, bwd_gptr;    // host: group boundaries
   std::vector<int32_t> fwd_order, bwd_order;  // host: tasks of the groups in launch order
+  std::vector<int32_t> fwd_cost, bwd_cost;    // host: stream entries per thread of each task
   const int32_t *fwd_order_dev = nullptr, *bwd_order_dev = nullptr;
 };
 
