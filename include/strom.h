@@ -62,7 +62,7 @@ typedef struct strom_sdp strom_sdp; /* one per SDP instance: device data, factor
  * this library's choices.  strom_default_opts fills:
  *   sigma0 = 1, tau = 1.6, eps_reg = 1e-12 (eps = eps_reg * max_i (A A^*)_ii), tol = 1e-6,
  *   maxiter = 100000, kkt_every = 10, proj_dtype = STROM_F64, polish_eta = 1e-5,
- *   sigma_every = 50, task_split = -1.  Sigma rule: every sigma_every iterations, with the primal
+ *   sigma_every = 50, task_split = -1, block_rows = 0.  Sigma rule: every sigma_every iterations, with the primal
  *   infeasibility r_P = max(eta_p, eta_K), eta_K = ||X - Pi(X)|| / (1 + ||X||) the distance of
  *   X from the cone, sigma is multiplied by 1.5 when eta_d > 3 r_P and divided by 1.5 when
  *   r_P > 3 eta_d, kept in [1e-4, 1e4]; 0 keeps sigma fixed.  sigma_every must be a multiple
@@ -85,6 +85,11 @@ typedef struct {
    * flight), -1 (default) the STROM_TASK_SPLIT environment variable if set, else 2.  In a
    * merged batch the instances supply the parallelism and 1 is faster. */
   int32_t task_split;
+  /* largest connected component (rows) a phase of the y-solve solves through its explicit
+   * inverse, 1..256; 0 (default): the STROM_BLOCK_ROWS environment variable if set, else 192.
+   * Larger components mean fewer dependent phases (one instance's latency) but more inverse
+   * entries to stream (a batch's throughput prefers 64). */
+  int32_t block_rows;
 } strom_opts;
 
 typedef struct {

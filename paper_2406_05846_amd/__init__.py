@@ -39,7 +39,8 @@ class StromError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("sigma0", C.c_double), ("tau", C.c_double), ("eps_reg", C.c_double), ("tol", C.c_double),
                 ("maxiter", C.c_int64), ("kkt_every", C.c_int32), ("proj_dtype", C.c_int32),
-                ("polish_eta", C.c_double), ("sigma_every", C.c_int32), ("task_split", C.c_int32)]
+                ("polish_eta", C.c_double), ("sigma_every", C.c_int32), ("task_split", C.c_int32),
+                ("block_rows", C.c_int32)]
 
 
 class Info(C.Structure):

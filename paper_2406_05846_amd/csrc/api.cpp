@@ -121,6 +121,7 @@ extern "C" void strom_default_opts(strom_opts *o) {
   o->polish_eta = 1e-5;
   o->sigma_every = 50;
   o->task_split = -1;
+  o->block_rows = 0;
 }
 
 extern "C" const char *strom_last_error(void) { return g_err.c_str(); }
@@ -183,7 +184,8 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   strom_opts o;
   if (opts) o = *opts; else strom_default_opts(&o);
   if (!(o.sigma0 > 0) || !(o.tau > 0 && o.tau < 2) || o.kkt_every <= 0 || o.maxiter <= 0 || o.sigma_every < 0 ||
-      (o.sigma_every > 0 && o.sigma_every % o.kkt_every != 0) || o.task_split < -1 || o.task_split > 2)
+      (o.sigma_every > 0 && o.sigma_every % o.kkt_every != 0) || o.task_split < -1 || o.task_split > 2 ||
+      o.block_rows < 0 || o.block_rows > 256)
     return fail(STROM_E_INVAL, "invalid options");
   if (!P->A_rowptr || !P->A_col || !P->A_val || !P->b || !P->C_svec || !P->block_sizes)
     return fail(STROM_E_INVAL, "NULL problem array");
@@ -191,7 +193,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   strom::HostAnalysis H;
   std::string err;
   strom_status rc = strom::analyze_instance(P->nblocks, P->block_sizes, P->m, P->A_rowptr, P->A_col, P->A_val,
-                                            o.eps_reg, H, err, o.task_split);
+                                            o.eps_reg, H, err, o.task_split, o.block_rows);
   if (rc != STROM_OK) return fail(rc, err);
   int32_t max_n = 0;
   for (int32_t n : H.bsize) max_n = std::max(max_n, n);

@@ -49,7 +49,7 @@ int32_t lanes_for(int64_t len) {
 
 strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *rowptr,
                               const int32_t *col, const double *val, double eps_reg, HostAnalysis &H,
-                              std::string &err, int split_mode) {
+                              std::string &err, int split_mode, int block_rows) {
   // ---------------------------------------------------------------- validation
   if (nblocks <= 0 || !bsize || m <= 0 || !rowptr || !col || !val) {
     err = "empty problem or NULL array";
@@ -288,8 +288,11 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   // become a task of their own when the coupling task next to it (which depends on them) is
   // at depth 2 or more, else they move into that coupling task.  Either way the split adds
   // no depth.
-  int32_t max_block = kMaxBlockRows;  // STROM_BLOCK_ROWS overrides (tuning of the solve schedule)
-  if (const char *ev = std::getenv("STROM_BLOCK_ROWS")) {
+  // largest component: block_rows if given, else STROM_BLOCK_ROWS if set, else kMaxBlockRows
+  int32_t max_block = kMaxBlockRows;
+  if (block_rows > 0) {
+    max_block = block_rows;
+  } else if (const char *ev = std::getenv("STROM_BLOCK_ROWS")) {
     const long v = std::strtol(ev, nullptr, 10);
     if (v >= 1 && v <= 256) max_block = int32_t(v);
   }
@@ -801,9 +804,17 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
       for (int32_t t = 0; t < Tp; ++t) {
         const int64_t e0 = int64_t(t) * K;
         if (e0 < E) ra[size_t(t)] = erow[size_t(e0)] | (efirst[size_t(e0)] ? kStartFlag : 0);
-        for (int64_t k = 0; k < K && e0 + k < E; ++k) {
-          V[size_t(off + k * Tp + t)] = ent[size_t(e0 + k)].second;
-          X[size_t(off + k * Tp + t)] = ent[size_t(e0 + k)].first;
+      }
+      // entry k of slice t (entry t K + k of the phase) at off + k Tp + t, written in
+      // destination order so that the stores run contiguously
+      for (int64_t k = 0; k < K; ++k) {
+        double *vd = V.data() + off + k * Tp;
+        int32_t *xd = X.data() + off + k * Tp;
+        for (int32_t t = 0; t < Tp; ++t) {
+          const int64_t e = int64_t(t) * K + k;
+          if (e >= E) break;  // later slices hold no more entries
+          vd[t] = ent[size_t(e)].second;
+          xd[t] = ent[size_t(e)].first;
         }
       }
       H.s_off[size_t(kind)].push_back(off);

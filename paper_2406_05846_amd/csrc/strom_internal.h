@@ -96,9 +96,11 @@ struct HostAnalysis {
 
 // Validates the CSR, orders, factors and analyses.  Returns STROM_OK or an error with `err`.
 // split_mode: task split of the solve schedule (0 none, 1 overweight tasks, 2 every group
-// task, -1 the STROM_TASK_SPLIT environment variable if set, else 2).
+// task, -1 the STROM_TASK_SPLIT environment variable if set, else 2).  block_rows: largest
+// component of a phase (1..256; 0: the STROM_BLOCK_ROWS environment variable if set, else
+// kMaxBlockRows).
 strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *rowptr,
                               const int32_t *col, const double *val, double eps_reg, HostAnalysis &H,
-                              std::string &err, int split_mode = -1);
+                              std::string &err, int split_mode = -1, int block_rows = 0);
 
 }  // namespace strom

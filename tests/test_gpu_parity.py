@@ -426,20 +426,22 @@ def test_paper_pendulum_full_size_iterates(S, ctx, orc):
     inst.close()
 
 
-@pytest.mark.parametrize("split", [0, 1])
-def test_task_split_option_iterates(S, ctx, orc, split):
-    """The solve schedule's task split chosen per instance (strom_opts.task_split): cart-pole
-    N = 10, five fixed-sigma iterations against the oracle; an out-of-range value is rejected."""
+@pytest.mark.parametrize("split,rows", [(0, 0), (1, 64), (2, 32)])
+def test_task_split_option_iterates(S, ctx, orc, split, rows):
+    """The solve schedule chosen per instance (strom_opts.task_split, strom_opts.block_rows):
+    cart-pole N = 10, five fixed-sigma iterations against the oracle; out-of-range values are
+    rejected."""
     prm = [0.1, 0.2, 0.5, 0.3]
     osdp = orc.relax(2, 10, prm)
     prob = S.generate(2, 10, prm)
-    inst = S.Instance(ctx, prob, _opts(S, sigma_every=0, kkt_every=1, tol=0.0, task_split=split))
+    inst = S.Instance(ctx, prob, _opts(S, sigma_every=0, kkt_every=1, tol=0.0, task_split=split, block_rows=rows))
     inst.step(5)
     Xg, yg, Sg = inst.get_iterate()
     r = orc.admm_solve(osdp, maxiter=5, tol=0.0, sigma_every=0)
     assert np.linalg.norm(Xg - r["X"]) / max(1.0, np.linalg.norm(r["X"])) <= 1e-9
     assert np.linalg.norm(Sg - r["S"]) / max(1.0, np.linalg.norm(r["S"])) <= 1e-9
     inst.close()
-    with pytest.raises(S.StromError) as e:
-        S.Instance(ctx, prob, _opts(S, task_split=3))
-    assert e.value.code == -1
+    for bad in (dict(task_split=3), dict(block_rows=300)):
+        with pytest.raises(S.StromError) as e:
+            S.Instance(ctx, prob, _opts(S, **bad))
+        assert e.value.code == -1

@@ -41,7 +41,7 @@ def test_default_opts():
     import paper_2406_05846_amd as S
     o = S.default_opts()
     assert o.sigma0 == 1.0 and o.tau == 1.6 and o.tol == 1e-6 and o.kkt_every == 10 and o.sigma_every == 50
-    assert o.task_split == -1
+    assert o.task_split == -1 and o.block_rows == 0
 
 
 CASES = [
