@@ -116,7 +116,7 @@ def _serving_mixed(S, W, np, ctx, args) -> dict:
     cap = 1000
     reqs = W.poisson_arrivals(args.seed, 2000.0, args.serve_mixed / 2000.0)
     probs = [(t, S.generate(f, N, p)) for t, f, N, p in reqs]
-    opts = S.default_opts(proj_dtype="f32", maxiter=cap, task_split=1)
+    opts = S.default_opts(proj_dtype="f32", maxiter=cap, task_split=1, block_rows=64)  # throughput schedule
     start = time.perf_counter()
     pending, lat, states, iters, k = {}, [], [], 0, 0
     while k < len(probs) or pending:
