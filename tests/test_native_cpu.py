@@ -107,3 +107,13 @@ def test_shift_one_clique_moves_whole_cliques():
     assert np.array_equal(out[:per], x[per:2 * per])
     assert np.array_equal(out[per:2 * per], x[2 * per:])
     assert np.array_equal(out[2 * per:], x[2 * per:])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it says so and exits before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in (r.stdout + r.stderr)
