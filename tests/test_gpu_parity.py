@@ -445,3 +445,45 @@ def test_task_split_option_iterates(S, ctx, orc, split, rows):
         with pytest.raises(S.StromError) as e:
             S.Instance(ctx, prob, _opts(S, **bad))
         assert e.value.code == -1
+
+
+def test_serving_under_a_tight_budget_with_mixed_round_structures(S, ctx):
+    """The request loop under an HBM budget that holds about two instances at a time (setup
+    workers wait for retirements), with requests of two round structures (kkt_every 10 and 5,
+    which go to separate batches): every request ends as it does alone."""
+    import time
+    import workloads as W
+    probs = [S.generate(W.PENDULUM, 5 + k % 3, W.instance_params(W.PENDULUM, 40 + k)) for k in range(6)]
+    optsets = [S.default_opts(), S.default_opts(kkt_every=5, sigma_every=50)]
+    alone = []
+    for k, pr in enumerate(probs):
+        ins = S.Instance(ctx, pr, optsets[k % 2])
+        alone.append(ins.step(50000))
+        ins.close()
+    budget = 1 << 16  # smallest power of two that holds the largest request, found by doubling
+    while True:
+        c = S.Context(0, hbm_budget=budget)
+        try:
+            S.Instance(c, probs[2]).close()
+            c.close()
+            break
+        except S.StromError:
+            c.close()
+            budget *= 2
+    small = S.Context(0, hbm_budget=2 * budget)
+    tickets = [small.submit(pr, optsets[k % 2]) for k, pr in enumerate(probs)]
+    done, t0 = {}, time.time()
+    while len(done) < len(tickets):
+        assert time.time() - t0 < 240, "request loop did not finish"
+        for t in tickets:
+            if t not in done:
+                r = small.poll(t)
+                if r is not None:
+                    done[t] = r[0]
+        time.sleep(0.01)
+    small.close()
+    for a, t in zip(alone, tickets):
+        b = done[t]
+        assert a["state"] == b["state"] == S.CONVERGED
+        assert b["iters"] == a["iters"]
+        assert abs(b["pobj"] - a["pobj"]) <= 1e-9 * (1.0 + abs(a["pobj"]))
