@@ -322,7 +322,9 @@ def main():
     ap.add_argument("--solves", type=int, default=8, help="pendulum solves timed for solves/s and latency")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving sample (0: skip)")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched form (0: skip)")
-    ap.add_argument("--batch-warmup", type=int, default=20, help="warmup iterations of the batched form")
+    ap.add_argument("--batch-warmup", type=int, default=40,
+                    help="warmup iterations of the batched form after the first 10 (with them, past the first "
+                         "sigma-rule round, whose graph is captured on first use)")
     ap.add_argument("--batch-lanes", type=int, default=4, help="lanes (contexts with their own stream) of the batch")
     ap.add_argument("--warm", type=int, default=3, help="receding-horizon warm-start steps (0: skip)")
     ap.add_argument("--paper", type=int, default=1, help="the paper's pendulum shape (0: skip)")
