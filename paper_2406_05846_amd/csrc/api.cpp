@@ -963,7 +963,7 @@ hipError_t batch_iteration(strom_batch *b, hipStream_t q, bool kkt, bool sig) {
   using namespace strom::dev;
   hipError_t e;
   for (int half = 0; half < 2; ++half) {
-    if ((e = launch_rhs_batch(q, b->nrows, b->rows, b->bi_dev))) return e;
+    if ((e = launch_rhs_batch(q, b->nrows, b->rows, b->ncols, b->cols, b->bi_dev))) return e;
     if ((e = launch_solve_batch(q, b->fwd_gptr, b->fwd, b->bwd_gptr, b->bwd, b->sa_dev, b->bi_dev, b->solve_lds)))
       return e;
     if (half == 0) {

@@ -149,7 +149,10 @@ hipError_t launch_kkt(hipStream_t s, int32_t m, int64_t n, const int64_t *rp, co
 // Merged launches over the instances of a batch (items: one workgroup each; retired
 // instances are skipped).  The solve's groups are merged by dependency depth: group g of every
 // instance in one launch, lds_bytes at least every instance's need.
-hipError_t launch_rhs_batch(hipStream_t s, int count, const BatchItem *rows, const BatchInst *bi);
+// r_s of every running instance: a column pass forms X/sigma + S - C in the X_b buffer, a row
+// pass gathers it.
+hipError_t launch_rhs_batch(hipStream_t s, int nrows, const BatchItem *rows, int ncols, const BatchItem *cols,
+                            const BatchInst *bi);
 hipError_t launch_solve_batch(hipStream_t s, const std::vector<int32_t> &fwd_gptr, const BatchItem *fwd,
                               const std::vector<int32_t> &bwd_gptr, const BatchItem *bwd, const SolveArgs *args,
                               const BatchInst *bi, size_t lds_bytes);

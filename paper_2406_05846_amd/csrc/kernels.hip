@@ -62,13 +62,34 @@ __global__ void __launch_bounds__(256) k_rhs(int32_t m, const int64_t *__restric
   rhs_row(blockIdx.x * blockDim.x + threadIdx.x, m, rp, ci, av, X, S, C, b, pinv, st, w);
 }
 
+// The same over a batch, in two passes: every column's term X/sigma + S - C once, into the X_b
+// buffer (free at both right-hand sides of an iteration: step 2 recomputes it), then the rows
+// gather that one array instead of three (the gathers fetch whole lines, so one array instead
+// of three is most of the kernel's traffic).
+__global__ void __launch_bounds__(256) k_rhs_term_batch(const BatchItem *__restrict__ items,
+                                                        const BatchInst *__restrict__ bi) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
+  if (!I.active) return;
+  const int64_t c = (int64_t)it.idx * 256 + threadIdx.x;
+  if (c >= I.n) return;
+  const double sig = G(I.st)->sigma;
+  G(I.Xb)[c] = G(I.X)[c] / sig + G(I.S)[c] - G(I.C)[c];
+}
+
 __global__ void __launch_bounds__(256) k_rhs_batch(const BatchItem *__restrict__ items,
                                                    const BatchInst *__restrict__ bi) {
   const BatchItem it = items[blockIdx.x];
   const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
   if (!I.active) return;
-  rhs_row(it.idx * 256 + threadIdx.x, I.m, G(I.A_rp), G(I.A_ci), G(I.A_v), G(I.X), G(I.S), G(I.C), G(I.b),
-          G(I.pinv), G(I.st), G(I.w));
+  const int32_t i = it.idx * 256 + threadIdx.x;
+  if (i >= I.m) return;
+  const int64_t *rp = G(I.A_rp);
+  const int32_t *ci = G(I.A_ci);
+  const double *av = G(I.A_v), *T = G(I.Xb);
+  double acc = 0.0;
+  for (int64_t p = rp[i]; p < rp[i + 1]; ++p) acc += av[p] * T[ci[p]];
+  G(I.w)[G(I.pinv)[i]] = G(I.b)[i] / G(I.st)->sigma - acc;
 }
 
 // ------------------------------------------------------------------ triangular solves
@@ -562,8 +583,10 @@ hipError_t launch_kkt(hipStream_t s, int32_t m, int64_t n, const int64_t *rp, co
 }
 
 // ------------------------------------------------------------------ merged launchers
-hipError_t launch_rhs_batch(hipStream_t s, int count, const BatchItem *rows, const BatchInst *bi) {
-  if (count > 0) hipLaunchKernelGGL(k_rhs_batch, dim3(count), dim3(256), 0, s, rows, bi);
+hipError_t launch_rhs_batch(hipStream_t s, int nrows, const BatchItem *rows, int ncols, const BatchItem *cols,
+                            const BatchInst *bi) {
+  if (ncols > 0) hipLaunchKernelGGL(k_rhs_term_batch, dim3(ncols), dim3(256), 0, s, cols, bi);
+  if (nrows > 0) hipLaunchKernelGGL(k_rhs_batch, dim3(nrows), dim3(256), 0, s, rows, bi);
   return hipGetLastError();
 }
 
