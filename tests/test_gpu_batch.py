@@ -166,3 +166,35 @@ def test_batch_rejects_mismatched_rounds(S, ctx):
     assert e.value.code == -1
     for ins in (a, b, c):
         ins.close()
+
+
+def test_full_batch_sampled_against_the_oracle(S, ctx, orc):
+    """The whole 256-instance mixed batch (families uniform, N ~ U{10..60}) in the benchmark's
+    launch configuration (task split 1, 64-row components, merged launches), FP64 with a fixed
+    sigma for three iterations; the smallest instance of each family is checked against the
+    oracle, which can afford those one at a time."""
+    from concurrent.futures import ThreadPoolExecutor
+    import workloads as W
+    cases = W.mixed_batch(0, count=256, nmin=10, nmax=60)
+    opts = S.default_opts(sigma_every=0, tol=0.0, task_split=1, block_rows=64)
+    probs = [S.generate(f, N, p) for f, N, p in cases]
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        insts = list(ex.map(lambda pr: S.Instance(ctx, pr, opts), probs))
+    bat = S.Batch(ctx, insts)
+    infos = bat.step(3)
+    bat.close()
+    assert all(i["iters"] == 3 for i in infos)
+    picks = {}
+    for k, (f, N, _) in enumerate(cases):
+        if f not in picks or N < cases[picks[f]][1]:
+            picks[f] = k
+    assert len(picks) == 3
+    for k in picks.values():
+        f, N, prm = cases[k]
+        Xg, yg, Sg = insts[k].get_iterate()
+        osdp = orc.relax(f, N, prm)
+        r = orc.admm_solve(osdp, maxiter=3, tol=0.0, sigma_every=0)
+        assert _rel(Xg, r["X"]) <= 1e-9 and _rel(Sg, r["S"]) <= 1e-9, (f, N)
+        assert _rel(osdp.A.T @ yg, osdp.A.T @ r["y"]) <= 1e-9, (f, N)
+    for ins in insts:
+        ins.close()
