@@ -301,6 +301,19 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd_batch(const BatchIt
   else solve_bwd_task<false>(it.idx, a, G(I.w), G(I.y), sh);
 }
 
+// The root task: the last forward group and the first backward group are both this one task,
+// so one workgroup solves it forward and then backward (the barrier between makes its rows,
+// written back to w by the forward pass, visible to the backward pass of the same group).
+__global__ void __launch_bounds__(kSolveThreads) k_solve_root(int32_t t, SolveArgs a, double *__restrict__ w,
+                                                              double *__restrict__ y) {
+  extern __shared__ double sh[];
+  if (a.task_inl[t]) solve_fwd_task<true>(t, a, w, sh);
+  else solve_fwd_task<false>(t, a, w, sh);
+  __syncthreads();
+  if (a.task_inl[t]) solve_bwd_task<true>(t, a, w, y, sh);
+  else solve_bwd_task<false>(t, a, w, y, sh);
+}
+
 // ------------------------------------------------------------------ step 2: X_b
 __device__ __forceinline__ void xb_col(int64_t c, int64_t n, const int64_t *__restrict__ trp,
                                        const int32_t *__restrict__ tci, const double *__restrict__ tv,
@@ -524,12 +537,21 @@ hipError_t launch_solve(hipStream_t s, const SolveSchedule &sch, const SolveArgs
   const size_t lds = sizeof(double) * (size_t)(kSolveThreads + kSolveThreads / 2 + a.lds_rows + a.c_cap);
   (void)hipFuncSetAttribute((const void *)k_solve_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipFuncSetAttribute((const void *)k_solve_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  for (int g = 0; g + 1 < (int)sch.fwd_gptr.size(); ++g) {
+  (void)hipFuncSetAttribute((const void *)k_solve_root, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const int nf = (int)sch.fwd_gptr.size() - 1, nb = (int)sch.bwd_gptr.size() - 1;
+  // one task closes the forward solve and opens the backward one: a single launch for both
+  const bool root = nf > 0 && nb > 0 && sch.fwd_gptr[nf] - sch.fwd_gptr[nf - 1] == 1 &&
+                    sch.bwd_gptr[1] - sch.bwd_gptr[0] == 1 && !sch.fwd_order.empty() &&
+                    sch.fwd_order[size_t(sch.fwd_gptr[nf - 1])] == sch.bwd_order[size_t(sch.bwd_gptr[0])];
+  for (int g = 0; g < nf - (root ? 1 : 0); ++g) {
     const int cnt = sch.fwd_gptr[g + 1] - sch.fwd_gptr[g];
     if (cnt <= 0) continue;
     hipLaunchKernelGGL(k_solve_fwd, dim3(cnt), dim3(kSolveThreads), lds, s, sch.fwd_order_dev + sch.fwd_gptr[g], a, w);
   }
-  for (int g = 0; g + 1 < (int)sch.bwd_gptr.size(); ++g) {
+  if (root)
+    hipLaunchKernelGGL(k_solve_root, dim3(1), dim3(kSolveThreads), lds, s, sch.fwd_order[size_t(sch.fwd_gptr[nf - 1])],
+                       a, w, y);
+  for (int g = root ? 1 : 0; g < nb; ++g) {
     const int cnt = sch.bwd_gptr[g + 1] - sch.bwd_gptr[g];
     if (cnt <= 0) continue;
     hipLaunchKernelGGL(k_solve_bwd, dim3(cnt), dim3(kSolveThreads), lds, s, sch.bwd_order_dev + sch.bwd_gptr[g], a, w,
