@@ -250,10 +250,11 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
     /* theta from upright (the paper's cart-pole with theta = theta_up + pi), explicit Euler:
      *  (m1 + m2 rs^2)(v' - v) = dt(-l m2 rs w^2 + f + m2 g rc rs)
      *  l (m1 + m2 rs^2)(w' - w) = dt(-l m2 rs rc w^2 + f rc + (m1 + m2) g rs)
-     *  x' = x + dt v; Cayley rotation with rate dt*w/2.  |f| <= 10, |x'| <= 1.
+     *  x' = x + dt v; Cayley rotation with rate dt*w/2.  |f| <= 10, |x'| <= 1, |v'| <= 4, |w'| <= 16.
      *  Cost: identity on scaled variables, target (0, 0, 1, 0, 0), terminal P_f = 1. */
     if (nprm < 4) return -1;
     const double m1 = 1.0, m2 = 0.3, l = 0.5, g = 9.8, dt = 0.05, fmax_ = 10, xmax = 1, Pf = 1;
+    const double vmax = 4, wmax = 16;
     if (k == 0) {
       push(eq, sub_(X0(&L, 0), cst(prm[0])));
       push(eq, sub_(X0(&L, 1), cst(prm[1])));
@@ -285,6 +286,11 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
     if (k >= 1) push(eq, circle(X0(&L, 2), X0(&L, 3)));
     push(ineq, sub_(cst(fmax_ * fmax_), sq_(U(&L, 0))));
     push(ineq, sub_(cst(xmax * xmax), sq_(X1(&L, 0))));
+    /* velocity boxes |v'| <= 4, |w'| <= 16: inactive at the optimum, they bound the moments of
+     * the velocities, which nothing else limits (without them the degree-4 moments of w grow
+     * without bound along the iteration) */
+    push(ineq, sub_(cst(vmax * vmax), sq_(X1(&L, 1))));
+    push(ineq, sub_(cst(wmax * wmax), sq_(X1(&L, 4))));
     /* identity weights on the scaled variables: (z_i - target_i)^2 */
     const double tgt[5] = {0, 0, 1, 0, 0};
     for (int i = 0; i < 5; ++i) *cost = add_(*cost, sq_(sub_(pl_var(i, 1.0), cst(tgt[i]))));
@@ -326,7 +332,8 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
     /* planar car: r' = r + dt v (rc, rs); v' = v + dt a; heading advanced by the Cayley
      * rotation with rate dt*w/2 where w is the turn rate (unicycle) or the lifted yaw rate
      * p = v * dtilde with p - v*dtilde = 0 (bicycle, unit wheelbase).  One circular obstacle
-     * of radius 0.5 at o; |rx|,|ry| <= 3, |v| <= 2, |a| <= 2, |w| <= 1.5 or |dtilde| <= 0.6.
+     * of radius 0.5 at o; |rx|,|ry| <= 3, |v| <= 2, |a| <= 2, |w| <= 1.5 or |dtilde| <= 0.6 and
+     * |p| <= 1.2.
      * Cost: |r - goal|^2 + v^2 + 0.1 a^2 + 0.1 (w^2 or dtilde^2); terminal P_f = 10. */
     if (nprm < 8) return -1;
     const int bicycle = prm[0] != 0.0;
@@ -358,6 +365,9 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
     push(ineq, sub_(cst(4), sq_(U(&L, 0))));
     if (bicycle) push(ineq, sub_(cst(0.36), sq_(U(&L, 1))));
     else push(ineq, sub_(cst(2.25), sq_(U(&L, 1))));
+    /* |p| <= 1.2 follows from |v| <= 2 and |dtilde| <= 0.6; stated so that the moments of p
+     * are bounded too */
+    if (bicycle) push(ineq, sub_(cst(1.44), sq_(U(&L, 2))));
     *cost = add_(add_(sq_(sub_(X0(&L, 0), cst(gx))), sq_(sub_(X0(&L, 1), cst(gy)))), sq_(X0(&L, 4)));
     *cost = add_(*cost, scl_(0.1, sq_(U(&L, 0))));
     *cost = add_(*cost, scl_(0.1, sq_(U(&L, 1))));

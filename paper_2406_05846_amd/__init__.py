@@ -146,6 +146,7 @@ class Problem:
         self.m = len(self.b)
         self.nsvec = len(self.C)
         self.nnz = len(self.col)
+        _validate_problem(self)
 
     def _c(self) -> Problem_:
         p = Problem_()
@@ -161,6 +162,61 @@ class Problem:
         p.X0_svec = _ptr(self.X0)
         p.S0_svec = _ptr(self.S0)
         return p
+
+
+def _bad(msg: str):
+    raise StromError(-1, msg)
+
+
+def _validate_problem(p) -> None:
+    """Lengths the C ABI cannot see behind its raw pointers (E_INVAL on a mismatch)."""
+    if p.block_sizes.ndim != 1 or len(p.block_sizes) == 0 or (p.block_sizes <= 0).any():
+        _bad("block sizes must be a non-empty list of positive integers")
+    n = int(np.sum(p.block_sizes.astype(np.int64) * (p.block_sizes.astype(np.int64) + 1) // 2))
+    if p.nsvec != n:
+        _bad(f"C has {p.nsvec} entries, the blocks' svec length is {n}")
+    for name in ("X0", "S0"):
+        v = getattr(p, name)
+        if v is not None and len(v) != n:
+            _bad(f"{name} has {len(v)} entries, the blocks' svec length is {n}")
+    if len(p.rowptr) != p.m + 1:
+        _bad(f"rowptr has {len(p.rowptr)} entries, expected m + 1 = {p.m + 1}")
+    if len(p.val) != p.nnz or (p.m >= 0 and len(p.rowptr) and p.rowptr[-1] != p.nnz) or \
+            (len(p.rowptr) and p.rowptr[0] != 0):
+        _bad("rowptr, col and val do not describe one CSR matrix")
+
+
+def _check_dense_blocks(n_dev, offset_dev, inp, out, max_n: int, device, out_dtype=None, elems=None) -> None:
+    """Checks of the device arguments of the dense batched calls, done on the host before any
+    launch: index dtypes, device, contiguity, matching float types, and every block inside the
+    buffers (offset + n*n <= numel, n <= max_n).  `elems(n)` is the per-block extent (n*n)."""
+    import torch
+    elems = elems or (lambda n: n * n)
+    if n_dev.dtype != torch.int32 or offset_dev.dtype != torch.int64:
+        _bad("block sizes must be int32 and offsets int64")
+    if n_dev.dim() != 1 or offset_dev.dim() != 1 or n_dev.numel() != offset_dev.numel():
+        _bad("block sizes and offsets must be 1-D tensors of equal length")
+    tensors = [n_dev, offset_dev, inp] + ([out] if out is not None else [])
+    for t in tensors:
+        if t.device != device:
+            _bad(f"tensor on {t.device}, the context is on {device}")
+        if not t.is_contiguous():
+            _bad("tensors must be contiguous")
+    if inp.dtype not in (torch.float32, torch.float64):
+        _bad("matrices must be float32 or float64")
+    if out is not None and out.dtype != (out_dtype or inp.dtype):
+        _bad("output dtype differs from the input's")
+    if n_dev.numel() == 0:
+        return
+    n = n_dev.to("cpu", torch.int64)
+    o = offset_dev.to("cpu")
+    if int(n.min()) <= 0 or int(n.max()) > max_n:
+        _bad(f"block sizes must be in 1..max_n = {max_n}")
+    if int(o.min()) < 0:
+        _bad("negative block offset")
+    end = int((o + elems(n)).max())
+    if end > inp.numel() or (out is not None and end > out.numel()):
+        _bad("a block reaches past the end of its buffer")
 
 
 def generate(family: int, N: int, params) -> Problem:
@@ -201,7 +257,11 @@ class Context:
         self._h = C.c_void_p()
         self._instances = weakref.WeakSet()
         self._batches = weakref.WeakSet()
+        self._sizes = {}  # ticket -> (n_svec, m), so poll never hands a short buffer to the library
+        self.device = None
         _check(_L.strom_ctx_create(int(device), _stream_handle(stream), C.c_size_t(hbm_budget), C.byref(self._h)))
+        import torch
+        self.device = torch.device("cuda", int(device))
 
     def close(self):
         """Destroy the context; instances still alive on it are destroyed first."""
@@ -223,23 +283,34 @@ class Context:
         t = C.c_uint64()
         p = problem._c()
         _check(_L.strom_submit(self._h, C.byref(p), C.byref(opts) if opts is not None else None, C.byref(t)))
+        self._sizes[t.value] = (problem.nsvec, problem.m)
         return t.value
 
     def poll(self, ticket: int, nsvec: int | None = None, m: int | None = None):
-        """None while in flight, else (info dict, X, y, S) (arrays only if sizes are given)."""
+        """None while in flight, else (info dict, X, y, S).  The iterates are returned when sizes
+        are passed (they must be the request's own n_svec and m); the buffers are always allocated
+        from the sizes recorded at submit."""
+        want = nsvec is not None or m is not None
+        rec = self._sizes.get(int(ticket))
+        if want and rec is not None and (nsvec not in (None, rec[0]) or m not in (None, rec[1])):
+            _bad(f"request {ticket} has n_svec {rec[0]} and m {rec[1]}, not {nsvec} and {m}")
         info = Info()
-        X = np.zeros(nsvec) if nsvec else None
-        S = np.zeros(nsvec) if nsvec else None
-        y = np.zeros(m) if m else None
+        X = y = S = None
+        if want and rec is not None:
+            X, S, y = np.zeros(rec[0]), np.zeros(rec[0]), np.zeros(rec[1])
+        elif want:
+            _bad(f"unknown request {ticket}")
         rc = _L.strom_poll(self._h, C.c_uint64(ticket), C.byref(info), _ptr(X), _ptr(y), _ptr(S))
         if rc == -5:
             return None
         _check(rc)
+        self._sizes.pop(int(ticket), None)
         return info.as_dict(), X, y, S
 
     def project_psd_batched(self, n_dev, offset_dev, inp, out, max_n: int, stream=None):
         """Project dense column-major blocks (torch device tensors) onto the PSD cone."""
         import torch
+        _check_dense_blocks(n_dev, offset_dev, inp, out, int(max_n), self.device)
         dt = F32 if inp.dtype == torch.float32 else F64
         _check(_L.strom_project_psd_batched(self._h, int(n_dev.numel()), int(max_n), C.c_void_p(n_dev.data_ptr()),
                                             C.c_void_p(offset_dev.data_ptr()), C.c_void_p(inp.data_ptr()),
@@ -250,6 +321,10 @@ class Context:
         """Eigenvalues (ascending, at woff_dev[k] of w) and optionally eigenvectors (columns at
         offset_dev[k] of v) of dense column-major blocks (torch device tensors)."""
         import torch
+        _check_dense_blocks(n_dev, offset_dev, inp, v, int(max_n), self.device)
+        _check_dense_blocks(n_dev, woff_dev, w, None, int(max_n), self.device, elems=lambda n: n)
+        if w.dtype != inp.dtype:
+            _bad("eigenvalue dtype differs from the input's")
         dt = F32 if inp.dtype == torch.float32 else F64
         _check(_L.strom_eig_batched(self._h, int(n_dev.numel()), int(max_n), C.c_void_p(n_dev.data_ptr()),
                                     C.c_void_p(offset_dev.data_ptr()), C.c_void_p(inp.data_ptr()),
@@ -332,6 +407,9 @@ class Instance:
         X = None if X is None else np.ascontiguousarray(X, dtype=np.float64)
         y = None if y is None else np.ascontiguousarray(y, dtype=np.float64)
         S = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
+        for name, v, n in (("X", X, self.nsvec), ("y", y, self.m), ("S", S, self.nsvec)):
+            if v is not None and len(v) != n:
+                _bad(f"{name} has {len(v)} entries, the instance needs {n}")
         _check(_L.strom_set_iterate(self._h, _ptr(X), _ptr(y), _ptr(S)))
 
     def profile(self, reps: int = 10) -> dict:

@@ -180,6 +180,7 @@ CliquePolys clique_polys(int family, int N, int k, const double *p, const Layout
     if (last) q.cost = q.cost + Pf * (sq(1.0 - L.x1(0)) + 0.1 * sq(L.x1(2)));
   } else if (family == 2) {  // cart-pole, pole angle from upright
     const double m1 = 1.0, m2 = 0.3, l = 0.5, g = 9.8, dt = 0.05, fmax = 10, xmax = 1, Pf = 1;
+    const double vmax = 4, wmax = 16;
     if (first) {
       q.eq.push_back(L.x0(0) - p[0]);
       q.eq.push_back(L.x0(1) - p[1]);
@@ -198,6 +199,9 @@ CliquePolys clique_polys(int family, int N, int k, const double *p, const Layout
     if (!first) q.eq.push_back(unit_circle(rc, rs));
     q.ineq.push_back(fmax * fmax - sq(f));
     q.ineq.push_back(xmax * xmax - sq(L.x1(0)));
+    // speed limits (inactive at the optimum) keep every moment of the velocities bounded
+    q.ineq.push_back(vmax * vmax - sq(L.x1(1)));
+    q.ineq.push_back(wmax * wmax - sq(L.x1(4)));
     const double target[5] = {0, 0, 1, 0, 0};
     for (int i = 0; i < 5; ++i) q.cost = q.cost + sq(L.zx0(i) - target[i]);
     q.cost = q.cost + sq(L.zu(0));
@@ -253,6 +257,7 @@ CliquePolys clique_polys(int family, int N, int k, const double *p, const Layout
     q.ineq.push_back(4.0 - sq(L.x1(4)));
     q.ineq.push_back(4.0 - sq(L.u(0)));
     q.ineq.push_back(bicycle ? 0.36 - sq(L.u(1)) : 2.25 - sq(L.u(1)));
+    if (bicycle) q.ineq.push_back(1.44 - sq(L.u(2)));  // |p| = |v dtilde| <= 1.2, bounds p's moments
     q.cost = sq(L.x0(0) - gx) + sq(L.x0(1) - gy) + sq(v) + 0.1 * sq(L.u(0)) + 0.1 * sq(L.u(1));
     if (last) q.cost = q.cost + Pf * (sq(L.x1(0) - gx) + sq(L.x1(1) - gy) + sq(L.x1(4)));
   }

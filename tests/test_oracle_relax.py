@@ -132,7 +132,7 @@ def _binom(n, k):
 @pytest.mark.parametrize("fam,N,prm,n_ineq,n_eq_deg", [
     # (family, N, params, inequalities per clique, [(eq degree, count) in clique k >= 1], init count)
     ("PENDULUM", 10, [0.5, 0.0], 1, [(1, 1), (3, 2), (2, 2)]),
-    ("CARTPOLE", 6, [0.1, 0.2, 0.5, 0.3], 2, [(1, 1), (3, 1), (4, 1), (3, 2), (2, 2)]),
+    ("CARTPOLE", 6, [0.1, 0.2, 0.5, 0.3], 4, [(1, 1), (3, 1), (4, 1), (3, 2), (2, 2)]),
 ])
 def test_row_counts_closed_form(orc, fam, N, prm, n_ineq, n_eq_deg):
     """m from Prop. 1: tri(s(d,2)) - s(d,4) moment rows, tri(s(d,1)) per localizing matrix,
