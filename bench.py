@@ -1,10 +1,11 @@
 """Benchmark of the sGS-ADMM hot path on one MI355X; prints one JSON line.
 
 Workload of ``value``: cart-pole swing-up, horizon N = 30 (cliques of 11 variables: 30 moment
-blocks 78x78 and 60 localizing blocks 12x12; n_svec = 97,110, m = 78,267), instance seed 0,
+blocks 78x78 and 120 localizing blocks 12x12; n_svec = 101,790, m = 82,947), instance seed 0,
 plain FP64.  A step is one full sGS-ADMM iteration (steps 1-4 of Algorithm 1 with the
 device-side sigma rule and the KKT residuals every ``kkt_every`` iterations) over that
-instance, its data resident in HBM.  ``value`` is iterations per second.
+instance, its data resident in HBM, taken after the first `settle` iterations of the solve
+(the warm-started eigensolver needs more sweeps early on).  ``value`` is iterations per second.
 
 Beside it: full solves to max KKT residual 1e-6 of the pendulum workload (N = 10, seeds
 0..solves-1; generator + setup + solve, one after another) for solves/s and p50/p99
@@ -50,16 +51,49 @@ def _traffic(path: str, source: str):
     return rec["hbm_bytes_per_dispatch"] if rec.get("source_sha256") == sha else None
 
 
-def _cpu_baseline(fam: int, N: int, prm, iters: int) -> dict:
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_baseline(W, fam: int, N: int, seed: int, iters: int, iters_all: int) -> dict:
+    """The FP64 oracle on the host: one thread on the headline instance, then all cores (one
+    instance per worker thread, seeds seed..seed+P-1; the oracle's C calls release the GIL),
+    each for a bounded number of iterations after its relaxation and LDL^T (excluded)."""
+    import threading
     import oracle
     oracle.build(force=False)
     t0 = time.perf_counter()
-    sdp = oracle.relax(fam, N, prm)
+    sdp = oracle.relax(fam, N, W.instance_params(fam, seed))
     t1 = time.perf_counter()
     r = oracle.admm_solve(sdp, maxiter=iters, tol=0.0)
-    return {"value": round(iters / r["t_solve_s"], 4), "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} sGS-ADMM iterations of the same cart-pole N=30 instance (relaxation "
-                      f"{t1 - t0:.2f} s and LDL^T {r['t_setup_s']:.2f} s excluded), one thread, FP64"}
+    single = iters / r["t_solve_s"]
+    P = len(os.sched_getaffinity(0))
+    sdps = [oracle.relax(fam, N, W.instance_params(fam, seed + k)) for k in range(P)]
+    solve_s = [0.0] * P
+
+    def work(k):
+        solve_s[k] = oracle.admm_solve(sdps[k], maxiter=iters_all, tol=0.0)["t_solve_s"]
+    ths = [threading.Thread(target=work, args=(k,)) for k in range(P)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    agg = P * iters_all / max(solve_s)
+    return {"value": round(agg, 3), "unit": "iters/s", "cores": P, "kind": "oracle",
+            "cpu_model": _cpu_model(),
+            "sample": f"all cores: {P} worker threads, each {iters_all} sGS-ADMM iterations of its own cart-pole "
+                      f"N={N} instance (seeds {seed}..{seed + P - 1}; relaxation and LDL^T excluded), "
+                      f"aggregate = {P} x {iters_all} / slowest worker's solve time, FP64",
+            "single_thread": {"value": round(single, 4), "unit": "iters/s", "cores": 1,
+                              "sample": f"{iters} iterations of the headline instance (relaxation "
+                                        f"{t1 - t0:.2f} s and LDL^T {r['t_setup_s']:.2f} s excluded)"}}
 
 
 def _serving(S, W, np, ctx, args, dtype="f64") -> dict:
@@ -106,45 +140,59 @@ def _serving(S, W, np, ctx, args, dtype="f64") -> dict:
     return serving
 
 
-def _serving_mixed(S, W, np, ctx, args) -> dict:
+def _serving_mixed(S, W, np, args) -> dict:
     """Serving under the mixed request stream of the serving config: Poisson arrivals at
-    2000/s, pendulum / cart-pole / car 40/40/20, N ~ U{10..80}, FP32 projection + FP64 polish.
-    Cart-pole and car requests need far more iterations to reach eta <= 1e-6 than a bench can
-    wait, so every request is capped at `cap` iterations: the sample measures the loop's
-    throughput and latency under that load (retired requests/s, instance-iterations/s), not
-    solves at 1e-6."""
-    cap = 1000
+    2000/s, pendulum / cart-pole / car 40/40/20, N ~ U{10..80}, FP32 projection + FP64 polish,
+    retire at eta <= 1e-6 (or the iteration cap): a seeded prefix of the stream (the first
+    `serve_mixed` arrivals) through the request loop on a context of its own, for at most
+    `serve_window` seconds; requests still in flight at the end are counted, not dropped.
+    solves/s = requests retired at eta <= 1e-6 per wall-second (setup included: a request's
+    setup runs inside the loop); latency = arrival to retire, over the converged requests."""
+    cap = args.serve_cap
     reqs = W.poisson_arrivals(args.seed, 2000.0, args.serve_mixed / 2000.0)
     probs = [(t, S.generate(f, N, p)) for t, f, N, p in reqs]
     opts = S.default_opts(proj_dtype="f32", maxiter=cap, task_split=1, block_rows=64)  # throughput schedule
+    ctx = S.Context(0)
     start = time.perf_counter()
     pending, lat, states, iters, k = {}, [], [], 0, 0
+    fam_of = {}
+    conv_by_fam = {}
     while k < len(probs) or pending:
         now = time.perf_counter() - start
         while k < len(probs) and probs[k][0] <= now:
-            pending[ctx.submit(probs[k][1], opts)] = probs[k][0]
+            tk = ctx.submit(probs[k][1], opts)
+            pending[tk] = probs[k][0]
+            fam_of[tk] = W.FAMILY_NAMES[reqs[k][1]]
             k += 1
         for tk in list(pending):
             r = ctx.poll(tk)
             if r is not None:
-                lat.append(time.perf_counter() - start - pending.pop(tk))
+                t_arr = pending.pop(tk)
                 states.append(r[0]["state"])
                 iters += int(r[0]["iters"])
-        if time.perf_counter() - start > 180:
-            _log("mixed serving sample cut at 180 s")
+                if r[0]["state"] == S.CONVERGED:
+                    lat.append(time.perf_counter() - start - t_arr)
+                    conv_by_fam[fam_of[tk]] = conv_by_fam.get(fam_of[tk], 0) + 1
+        if time.perf_counter() - start > args.serve_window:
+            _log(f"mixed serving sample cut at {args.serve_window} s with {len(pending)} requests in flight")
             break
-        time.sleep(0.0005)
+        time.sleep(0.001)
     wall = time.perf_counter() - start
+    in_flight = len(pending)
+    ctx.close()
     lat = np.array(lat)
     fams = [f for _, f, _, _ in reqs]
-    out = {"workload": f"{len(reqs)} requests, Poisson arrivals at 2000/s, pendulum / cart-pole / car "
+    conv = int(sum(st == S.CONVERGED for st in states))
+    out = {"workload": f"first {len(reqs)} requests of the seeded stream: Poisson arrivals at 2000/s, pendulum / cart-pole / car "
                        f"{fams.count(W.PENDULUM)}/{fams.count(W.CARTPOLE)}/{fams.count(W.CAR)}, N ~ U{{10..80}}, "
-                       f"FP32 projection + FP64 polish, retire at eta <= 1e-6 or {cap} iterations",
-           "retired_per_s": round(len(lat) / wall, 3), "instance_iters_per_s": round(iters / wall, 1),
-           "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4),
-                         "p99": round(float(np.percentile(lat, 99)), 4)} if len(lat) else None,
-           "completed": int(len(lat)), "converged": int(sum(st == S.CONVERGED for st in states)),
-           "at_cap": int(sum(st == S.MAXITER for st in states))}
+                       f"FP32 projection + FP64 polish, retire at eta <= 1e-6 or {cap} iterations, "
+                       f"window {args.serve_window:.0f} s",
+           "solves_per_s": round(conv / wall, 3), "wall_s": round(wall, 2),
+           "latency_s": {"p50": round(float(np.percentile(lat, 50)), 3),
+                         "p99": round(float(np.percentile(lat, 99)), 3)} if len(lat) else None,
+           "converged": conv, "converged_by_family": conv_by_fam,
+           "retired_at_cap": int(sum(st == S.MAXITER for st in states)), "in_flight_at_end": in_flight,
+           "retired_instance_iters_per_s": round(iters / wall, 1)}
     _log(f"mixed serving: {out}")
     return out
 
@@ -168,79 +216,180 @@ def _car(S, W, ctx, args) -> dict:
     return out
 
 
-def _batched(S, W, torch, args) -> dict:
-    """Batched form: a mixed batch of instances (families uniform over pendulum, cart-pole, car;
-    horizons N ~ U{10..60}) advanced together by merged launches (one per step over all
-    instances of a lane, rounds replayed from HIP graphs), FP32 projection with the FP64
+def _lanes(S, torch, probs, opts, L):
+    """Set up instances (host analyses in 16 threads, outside the GIL) dealt round-robin to L
+    lanes (contexts with their own stream); returns (contexts, instances per lane)."""
+    from concurrent.futures import ThreadPoolExecutor
+    ctxs = [S.Context(0, stream=torch.cuda.Stream()) for _ in range(L)]
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        insts = [list(ex.map(lambda pr: S.Instance(ctxs[l], pr, opts), probs[l::L])) for l in range(L)]
+    return ctxs, insts
+
+
+def _run_lanes(bats, n):
+    """Step every lane's batch n iterations, one host thread per lane; returns their infos."""
+    import threading
+    res = [None] * len(bats)
+
+    def go(k):
+        res[k] = bats[k].step(n)
+    th = [threading.Thread(target=go, args=(k,)) for k in range(len(bats))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    return res
+
+
+def _solve_window(S, np, bats, t_arrive, window_s, chunk, cap):
+    """Step the lanes in chunks until every instance has retired or the window has passed;
+    latency of a converged instance = its retire time (end of the chunk it retired in) minus
+    t_arrive.  Returns (wall, latencies of the converged, states, iterations)."""
+    import time as _t
+    n_inst = sum(len(b.instances) for b in bats)
+    lat, states, iters = {}, {}, {}
+    t0 = _t.perf_counter()
+    while len(states) < n_inst and _t.perf_counter() - t0 < window_s:
+        infos = _run_lanes(bats, chunk)
+        now = _t.perf_counter()
+        for l, inf in enumerate(infos):
+            for k, i in enumerate(inf):
+                key = (l, k)
+                if key not in states and i["state"] != S.RUNNING:
+                    states[key], iters[key] = int(i["state"]), int(i["iters"])
+                    if i["state"] == S.CONVERGED:
+                        lat[key] = now - t_arrive
+        if all(i["iters"] >= cap for inf in infos for i in inf):
+            break
+    return _t.perf_counter() - t0, np.array(sorted(lat.values())), states, iters
+
+
+def _batched(S, W, np, torch, args) -> dict:
+    """Batched form (the C4 shape): a mixed batch of instances (families uniform over pendulum,
+    cart-pole, car; horizons N ~ U{10..60}) advanced together by merged launches (one per step over
+    all instances of a lane, rounds replayed from HIP graphs), FP32 projection with the FP64
     polish, FP64 solves and residuals, after the projection autotuner.  The instances are dealt
     round-robin to `lanes` batches, each on a context with its own stream and stepped from its
-    own host thread, so that one lane's launch tails overlap another's work.  Beside it, a
-    sample of the same problems stepped one instance at a time in the FP64 per-instance form."""
-    import threading
-    from concurrent.futures import ThreadPoolExecutor
+    own host thread, so that one lane's launch tails overlap another's work.
+
+    Measured: instance-iterations/s over 50 iterations after 50 of warmup (every instance still
+    running), then a solve window: the lanes keep stepping until every instance has retired
+    (eta <= 1e-6, or the iteration cap) or the window ends; solves/s = instances retired at
+    eta <= 1e-6 per wall-second with setup included, latency = from the start of setup to retire.
+    Beside it, on a sample of the same problems with a common iteration cap: the FP64
+    per-instance form (one instance at a time), the FP64 batch and the FP32+polish batch, each
+    timed from setup to the last retirement, so that batching and precision are separate ratios."""
     K, iters, L = args.batch, 50, max(1, args.batch_lanes)
+    cap = args.batch_cap
     cases = W.mixed_batch(args.seed, count=K, nmin=10, nmax=60)
     t0 = time.perf_counter()
     probs = [S.generate(f, N, p) for f, N, p in cases]
     t1 = time.perf_counter()
-    ctxs = [S.Context(0, stream=torch.cuda.Stream()) for _ in range(L)]
     # a throughput schedule: in a batch the instances supply the parallelism, so splitting only
     # the overweight tasks (+4.8%) and 64-row components (fewer inverse entries to stream,
     # +7%) beat the single-instance choices (every group task split, 192-row components)
-    opts = S.default_opts(tol=0.0, maxiter=10**9, proj_dtype="f32", task_split=1, block_rows=64)
-    with ThreadPoolExecutor(max_workers=16) as ex:  # the host analysis runs outside the GIL
-        insts = [list(ex.map(lambda pr: S.Instance(ctxs[l], pr, opts), probs[l::L])) for l in range(L)]
+    opts = S.default_opts(tol=1e-6, maxiter=cap, proj_dtype="f32", task_split=1, block_rows=64)
+    ctxs, insts = _lanes(S, torch, probs, opts, L)
     t2 = time.perf_counter()
     _log(f"batched: {K} instances generated in {t1 - t0:.1f} s, set up in {t2 - t1:.1f} s")
     bats = [S.Batch(ctxs[l], insts[l]) for l in range(L)]
-
-    def step_all(n):
-        th = [threading.Thread(target=b.step, args=(n,)) for b in bats]
-        for t in th:
-            t.start()
-        for t in th:
-            t.join()
-
-    step_all(10)
+    _run_lanes(bats, 10)
     tuned = [b.tune(reps=3) for b in bats][0]
-    step_all(args.batch_warmup)
+    _run_lanes(bats, args.batch_warmup)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    step_all(iters)
+    infos = _run_lanes(bats, iters)
     torch.cuda.synchronize()
     t4 = time.perf_counter()
+    running = sum(i["state"] == S.RUNNING for inf in infos for i in inf)
+    wall, lat, states, its = _solve_window(S, np, bats, t1, args.batch_window, 100, cap)
+    t5 = time.perf_counter()
+    conv = int(sum(st == S.CONVERGED for st in states.values()))
+    fam_of = {}
+    for l in range(L):
+        for k, idx in enumerate(range(l, K, L)):
+            fam_of[(l, k)] = W.FAMILY_NAMES[cases[idx][0]]
+    by_fam = {}
+    for key, fam in fam_of.items():
+        d = by_fam.setdefault(fam, {"instances": 0, "converged": 0})
+        d["instances"] += 1
+        d["converged"] += int(states.get(key) == S.CONVERGED)
     for b in bats:
         b.close()
     nsvec = sum(pr.nsvec for pr in probs)
     for lane in insts:
         for ins in lane:
             ins.close()
-    for c in ctxs[1:]:
+    for c in ctxs:
         c.close()
-    # the same problems one at a time, FP64 per-instance form
-    ctx = ctxs[0]
-    sample = probs[:: max(1, K // 16)][:16]
-    t_alone, it_alone = 0.0, 30
-    for pr in sample:
-        ins = S.Instance(ctx, pr, S.default_opts(tol=0.0, maxiter=10**9))
-        ins.step(10)
-        ta = time.perf_counter()
-        ins.step(it_alone)
-        t_alone += time.perf_counter() - ta
-        ins.close()
-    ctx.close()
     rate = K * iters / (t4 - t3)
-    rate_alone = len(sample) * it_alone / t_alone
     out = {"workload": f"{K} instances of the mixed batch of seed {args.seed} (pendulum / cart-pole / car uniform, "
-                       f"N ~ U{{10..60}}, total n_svec {nsvec}), FP32 projection + FP64 polish, task split 1, 64-row components, merged launches in "
-                       f"{L} lanes, {iters} timed iterations after {10 + args.batch_warmup} and the autotuner",
+                       f"N ~ U{{10..60}}, total n_svec {nsvec}), FP32 projection + FP64 polish, task split 1, "
+                       f"64-row components, merged launches in {L} lanes",
            "instance_iters_per_s": round(rate, 1), "ms_per_batch_iteration": round(1e3 * (t4 - t3) / iters, 3),
+           "iters_timed": f"{iters} iterations after {10 + args.batch_warmup} and the autotuner, "
+                          f"{running} of {K} instances running",
            "setup_s": round(t2 - t1, 2), "lanes": L, "tuned_threads_lane0": tuned,
-           "per_instance_fp64": {"sample": f"{len(sample)} of the same problems one at a time, {it_alone} "
-                                           f"iterations each", "instance_iters_per_s": round(rate_alone, 1)},
-           "speedup_vs_per_instance_fp64": round(rate / rate_alone, 2)}
+           "solve_window": {"rule": f"retire at eta <= 1e-6 or {cap} iterations; window {args.batch_window} s",
+                            "wall_s_with_setup": round(t5 - t1, 2),
+                            "solves_per_s": round(conv / (t5 - t1), 3), "converged": conv,
+                            "retired_at_cap": int(sum(st == S.MAXITER for st in states.values())),
+                            "still_running_at_end": K - len(states),
+                            "latency_s": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                          "p99": round(float(np.percentile(lat, 99)), 3)} if len(lat) else None,
+                            "by_family": by_fam}}
     _log(f"batched: {out}")
+    if args.batch_compare > 0:
+        # the comparison runs on problems the batch solved within its window, so that every
+        # form has solves to count: up to batch_compare of them, spread over their iteration counts
+        done = sorted((its[key], key[0] + key[1] * L) for key, st in states.items() if st == S.CONVERGED)
+        pick = [done[int(j * len(done) / args.batch_compare)][1] for j in range(min(args.batch_compare, len(done)))]
+        if pick:
+            cap_c = int(1.25 * max(its[(k % L, k // L)] for k in pick)) + 200
+            out["same_problems"] = _compare_forms(S, W, np, torch, probs, cases, pick, cap_c)
     return out
+
+
+def _compare_forms(S, W, np, torch, probs, cases, idx, cap) -> dict:
+    """Problems of the batch (indices idx) solved to eta <= 1e-6 with a common iteration cap by
+    three forms, each timed from setup to the last retirement: the plain FP64 per-instance form
+    (one instance at a time), the FP64 merged batch, the FP32+polish merged batch (one lane each)."""
+    sample = [probs[k] for k in idx]
+    res = {"sample": f"{len(sample)} problems the batch solved in its window, spread over their iteration counts "
+                     f"({', '.join(W.FAMILY_NAMES[cases[k][0]] + ' N=' + str(cases[k][1]) for k in idx)}), "
+                     f"retire at eta <= 1e-6 or {cap} iterations"}
+    ctx = S.Context(0)
+    t = time.perf_counter()
+    conv, iters = 0, []
+    for pr in sample:
+        ins = S.Instance(ctx, pr, S.default_opts(maxiter=cap))
+        inf = ins.step(cap)
+        conv += inf["state"] == S.CONVERGED
+        iters.append(int(inf["iters"]))
+        ins.close()
+    wall = time.perf_counter() - t
+    res["per_instance_fp64"] = {"solves_per_s": round(conv / wall, 4), "converged": int(conv),
+                                "wall_s": round(wall, 2), "iters": iters}
+    for label, dt in (("batched_fp64", "f64"), ("batched_fp32_polish", "f32")):
+        t = time.perf_counter()
+        ctxs, insts = _lanes(S, torch, sample, S.default_opts(maxiter=cap, proj_dtype=dt, task_split=1, block_rows=64), 1)
+        bat = S.Batch(ctxs[0], insts[0])
+        infos = bat.step(cap)
+        wall = time.perf_counter() - t
+        bat.close()
+        for ins in insts[0]:
+            ins.close()
+        ctxs[0].close()
+        c = int(sum(i["state"] == S.CONVERGED for i in infos))
+        res[label] = {"solves_per_s": round(c / wall, 4), "converged": c, "wall_s": round(wall, 2),
+                      "iters": [int(i["iters"]) for i in infos]}
+    ctx.close()
+    a, b, c = (res[k]["solves_per_s"] for k in ("per_instance_fp64", "batched_fp64", "batched_fp32_polish"))
+    res["ratio_batched_fp64_vs_per_instance_fp64"] = round(b / a, 3) if a > 0 else None
+    res["ratio_fp32_polish_vs_fp64_batched"] = round(c / b, 3) if b > 0 else None
+    res["ratio_fp32_polish_batched_vs_per_instance_fp64"] = round(c / a, 3) if a > 0 else None
+    _log(f"same problems: {res}")
+    return res
 
 
 def _warm_start(S, W, np, ctx, args) -> dict:
@@ -326,11 +475,22 @@ def main():
                     help="warmup iterations of the batched form after the first 10 (with them, past the first "
                          "sigma-rule round, whose graph is captured on first use)")
     ap.add_argument("--batch-lanes", type=int, default=4, help="lanes (contexts with their own stream) of the batch")
+    ap.add_argument("--batch-cap", type=int, default=30000, help="iteration cap of the batch's solve window")
+    ap.add_argument("--batch-window", type=float, default=60.0, help="seconds of the batch's solve window")
+    ap.add_argument("--batch-compare", type=int, default=8,
+                    help="problems the batch solved in its window, solved again by the per-instance FP64 form "
+                         "and both batches (0: skip)")
     ap.add_argument("--warm", type=int, default=3, help="receding-horizon warm-start steps (0: skip)")
     ap.add_argument("--paper", type=int, default=1, help="the paper's pendulum shape (0: skip)")
     ap.add_argument("--car", type=int, default=1, help="car N=50 iterations/s (0: skip)")
     ap.add_argument("--serve-mixed", type=int, default=64, help="requests of the mixed serving sample (0: skip)")
-    ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the CPU baseline")
+    ap.add_argument("--serve-cap", type=int, default=30000, help="iteration cap of the mixed serving requests")
+    ap.add_argument("--serve-window", type=float, default=90.0, help="seconds of the mixed serving sample")
+    ap.add_argument("--settle", type=int, default=1000,
+                    help="iterations run before the warmup of the headline instance (the warm-started "
+                         "eigensolver needs more sweeps in the first hundreds of iterations)")
+    ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the one-thread CPU baseline")
+    ap.add_argument("--cpu-iters-all", type=int, default=20, help="oracle iterations per worker, all-core baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-only", action="store_true", help="only the serving sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -381,8 +541,9 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    # per-phase times from HIP events on the instance's stream over 200 iterations after the
-    # warmup (the same regime as the timed region that follows)
+    # settle, then per-phase times from HIP events on the instance's stream over 200 iterations
+    # (the same regime as the timed region that follows)
+    inst.enqueue(args.settle)
     inst.enqueue(args.warmup)
     prof = inst.profile(200)
     _log(f"phase profile (ms): {prof}")
@@ -408,6 +569,7 @@ def main():
 
     # the reduced-precision form on the same instance (eta stays above the polish switch here)
     inst32 = S.Instance(ctx, prob, S.default_opts(proj_dtype=S.F32))
+    inst32.enqueue(args.settle + 200)
     elapsed32 = timed_iterations(inst32)
     prof32 = inst32.profile(20)
     inst32.close()
@@ -445,9 +607,9 @@ def main():
     serving32 = _serving(S, W, np, ctx, args, "f32") if args.serve > 0 else None
     if serving is not None:
         serving["fp32_polish"] = serving32
-    mixed = _serving_mixed(S, W, np, ctx, args) if args.serve_mixed > 0 else None
+    mixed = _serving_mixed(S, W, np, args) if args.serve_mixed > 0 else None
     car = _car(S, W, ctx, args) if args.car else None
-    batched = _batched(S, W, torch, args) if args.batch > 0 else None
+    batched = _batched(S, W, np, torch, args) if args.batch > 0 else None
     warm = _warm_start(S, W, np, ctx, args) if args.warm > 0 else None
     paper = _paper_pendulum(S, W, ctx, args) if args.paper else None
 
@@ -468,7 +630,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "cart-pole swing-up N=30, plain FP64 single instance: 30 moment blocks 78x78 + "
-                               f"60 localizing blocks 12x12, n_svec {prob.nsvec}, m {prob.m}, seed {args.seed}",
+                               f"120 localizing blocks 12x12, n_svec {prob.nsvec}, m {prob.m}, seed {args.seed}; "
+                               f"iterations timed after the first {args.settle} + 200 + warmup of the solve",
                    "n_svec": prob.nsvec, "m": prob.m, "nnz_A": int(prob.nnz)},
         "kkt_after_timed": {"iters": int(info_after["iters"]), "eta_p": info_after["eta_p"],
                             "eta_d": info_after["eta_d"], "eta_g": info_after["eta_g"]},
@@ -496,7 +659,7 @@ def main():
     }
     if not args.no_cpu:
         _log("CPU oracle baseline ...")
-        out["cpu_baseline"] = _cpu_baseline(fam, N, prm, args.cpu_iters)
+        out["cpu_baseline"] = _cpu_baseline(W, fam, N, args.seed, args.cpu_iters, args.cpu_iters_all)
     print(json.dumps(out), flush=True)
     ctx.close()
 

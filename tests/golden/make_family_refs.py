@@ -1,0 +1,48 @@
+"""Writes converged_refs_families.json: the oracle's optimal values of cart-pole and car
+instances (instance parameters from workloads.instance_params) solved to max KKT residual 1e-8:
+cart-pole N = 6 (seeds 0-2), car N = 4 (seed 0: unicycle-12, seed 1: bicycle-13) and the
+full-size cart-pole N = 30 seed 7 (one of the seeds that reaches 1e-6 quickly).  Calls only the
+oracle (one process per case); the GPU tests compare converged device solutions with these.
+
+Run from the repository root:  python tests/golden/make_family_refs.py
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+from concurrent.futures import ProcessPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workloads as W  # noqa: E402
+
+CASES = [("cartpole", W.CARTPOLE, 6, 0), ("cartpole", W.CARTPOLE, 6, 1), ("cartpole", W.CARTPOLE, 6, 2),
+         ("car", W.CAR, 4, 0), ("car", W.CAR, 4, 1), ("cartpole", W.CARTPOLE, 30, 7)]
+
+
+def solve(case):
+    name, fam, N, seed = case
+    prm = W.instance_params(fam, seed)
+    r = oracle.admm_solve(oracle.relax(fam, N, prm), tol=1e-8, maxiter=200000)
+    return {"family": name, "N": N, "seed": seed, "params": [float(v) for v in prm], "pobj": r["pobj"],
+            "dobj": r["dobj"], "iters": int(r["iters"]), "converged": bool(r["converged"]),
+            "eta": max(r["eta_p"], r["eta_d"], r["eta_g"])}
+
+
+def main():
+    oracle.build(force=False)
+    with ProcessPoolExecutor(max_workers=len(CASES)) as ex:
+        cases = list(ex.map(solve, CASES))
+    for c in cases:
+        print(c, flush=True)
+    out = {"what": "oracle sGS-ADMM (Algorithm 1, FP64) run to max(eta_p, eta_d, eta_g) <= 1e-8", "cases": cases}
+    with open(os.path.join(HERE, "converged_refs_families.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
