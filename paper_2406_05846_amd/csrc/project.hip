@@ -98,6 +98,39 @@ struct JacobiTol<float> {
   static constexpr double skip_rel = 1e-9;
 };
 
+// One 16 x 16 x 4 matrix-core step, acc += A B, per element type: FP64 operands with FP64
+// accumulation, FP32 operands with FP32 accumulation.  Lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; it receives column l % 16 of the 16 x 16 result, register r holding row
+// row(l, r) (the two instructions order their result rows differently).
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef mfma_d4 acc_t;
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+  typedef mfma_f4 acc_t;
+  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// Position of logical index i in round 0 of the circle ordering (inverse of logical_index(., 0)):
+// indices below np2 sit at the even positions, index mm at position 1, the others at odd ones.
+__device__ inline int position0(int i, int np2, int mm) {
+  if (i < np2) return 2 * i;
+  if (i == mm) return 1;
+  return 2 * (mm - i) + 1;
+}
+
 // LDS: V (n x nn doubles, column-major, column = index) | red (16 doubles) | rotd (two
 //      buffers of (c, s) doubles per slot) | A (nbuf buffers of four arrays of nblk T) | rot
 //      (two buffers of (c, s, new a_pp, new a_qq) T per slot) | lam (nn doubles) | sel (nn + 4 ints), every
@@ -179,15 +212,18 @@ __device__ inline T diag_entry(const T *Ab, int nblk, int x) {
 }
 
 // A <- Q^T X Q in the block arrays Ab (position order of round 0), with Q = V (n x nn, LDS)
-// and X the svec block at xs (global).  X is staged (packed upper triangle, unscaled off-diagonal) in the first buffer;
-// each thread forms 4 entries of a column of W = X Q at a time; W is kept in the block's slot
-// wq of the eigenvector buffer (n x nn doubles, free until the eigenvectors are written back);
-// then A is written from Q and W.
+// and X the svec block at xs (global), as two products on the matrix cores in T: X is staged
+// (packed upper triangle, unscaled off-diagonal) in the first buffer; W = X Q (n x nn) goes to
+// wq, row-major, in the global eigenvector slot of the block (free until the eigenvectors are
+// written back; its rows are read back coalesced); then the upper tiles of A = Q^T W are stored
+// in position order, every unordered entry once.  A wave computes whole 16 x 16 tiles.
 template <typename T>
 __device__ __forceinline__ void rotate_into_basis(int n, const double *xs, const double *V, double *wq, T *Ab,
                                                   int nblk) {
+  typedef Mfma<T> M;
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int nn = n + (n & 1);
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6;
+  const int nn = n + (n & 1), np2 = nn / 2, mm = nn - 1;
   const double rs2 = 0.70710678118654752440;
   const int npk = n * (n + 1) / 2;
   T *Xs = Ab;
@@ -198,34 +234,42 @@ __device__ __forceinline__ void rotate_into_basis(int n, const double *xs, const
     Xs[k] = (T)(i == j ? v : v * rs2);
   }
   __syncthreads();
-  const int nc4 = (nn + 3) / 4;
-  for (int e = tid; e < n * nc4; e += nth) {  // W(i, 4c .. 4c+3) = sum_k X(i,k) Q(k, 4c ..)
-    const int i = e % n, c0 = 4 * (e / n);
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    const int c1 = min(c0 + 1, nn - 1), c2 = min(c0 + 2, nn - 1), c3 = min(c0 + 3, nn - 1);
-    for (int k = 0; k < n; ++k) {
-      const double x = (double)Xs[pidx(i, k)];
-      s0 += x * V[c0 * n + k];
-      s1 += x * V[c1 * n + k];
-      s2 += x * V[c2 * n + k];
-      s3 += x * V[c3 * n + k];
+  const int rt = (n + 15) >> 4, ct = (nn + 15) >> 4, ks = (n + 3) >> 2;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < rt * ct; t += nwaves) {  // W = X Q, tile (I, J)
+    const int I = t / ct, J = t % ct;
+    const int i = 16 * I + li, j = 16 * J + li;
+    typename M::acc_t acc = {0, 0, 0, 0};
+    for (int s = 0; s < ks; ++s) {
+      const int k = 4 * s + lk;
+      const T a = (i < n && k < n) ? Xs[pidx(i, k)] : T(0);
+      const T b = (k < n && j < nn) ? (T)V[j * n + k] : T(0);
+      acc = M::step(a, b, acc);
     }
-    wq[c0 * n + i] = s0;
-    if (c0 + 1 < nn) wq[(c0 + 1) * n + i] = s1;
-    if (c0 + 2 < nn) wq[(c0 + 2) * n + i] = s2;
-    if (c0 + 3 < nn) wq[(c0 + 3) * n + i] = s3;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = 16 * I + M::row(lane, r);
+      if (ii < n && j < nn) wq[ii * nn + j] = (double)acc[r];
+    }
   }
   __threadfence_block();
   __syncthreads();
-  const int mm = nn - 1;
-  for (int e = tid; e < nn * (nn + 1) / 2; e += nth) {  // A(x, y) = sum_k Q(k, i) W(k, j), x <= y
-    int x, y;
-    tri_ij(e, x, y);
-    const double *q = V + logical_index(x, 0, mm) * n;
-    const double *w = wq + logical_index(y, 0, mm) * n;
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) s += q[k] * w[k];
-    store_entry<T>(Ab, nblk, x, y, (T)s);
+  for (int t = wave; t < ct * (ct + 1) / 2; t += nwaves) {  // A = Q^T W, upper tile (I <= J)
+    int I, J;
+    tri_ij(t, I, J);
+    const int i = 16 * I + li, j = 16 * J + li;
+    typename M::acc_t acc = {0, 0, 0, 0};
+    for (int s = 0; s < ks; ++s) {
+      const int k = 4 * s + lk;
+      const T a = (k < n && i < nn) ? (T)V[i * n + k] : T(0);
+      const T b = (k < n && j < nn) ? (T)wq[k * nn + j] : T(0);
+      acc = M::step(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = 16 * I + M::row(lane, r);
+      if (ii <= j && j < nn) store_entry<T>(Ab, nblk, position0(ii, np2, mm), position0(j, np2, mm), (T)acc[r]);
+    }
   }
   __syncthreads();
 }
@@ -550,12 +594,33 @@ __device__ __forceinline__ void project_block(int32_t bk, const int64_t *__restr
     for (int k = tid; k < n * nn; k += nth) q[k] = sm.V[k];
   const int pos = sm.sel[nn], cnt = sm.sel[nn + 1];
   const double mul = scale > 0.0 ? scale : 1.0 / st->sigma;
-  for (int k = tid; k < npk; k += nth) {
-    int i, j;
-    tri_ij(k, i, j);
-    const double acc = rebuild(i, j, n, sm.lam, sm.V, sm.sel, cnt) * (i == j ? 1.0 : s2);
-    S[off + k] = pos ? (acc - Xb[off + k]) * mul   // (Pi - X_b) * mul
-                     : -acc * mul;                  // -Pi_-(X_b) * mul
+  // P = U diag(lam) U^T over the selected eigenpairs (U = the columns sel of V) on the matrix
+  // cores in T, upper tiles; entry (i <= j) goes to svec place j (j + 1) / 2 + i
+  typedef Mfma<T> M;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6, li = lane & 15, lk = lane >> 4;
+  const int rt = (n + 15) >> 4, ks = (cnt + 3) >> 2;
+  for (int t = wave; t < rt * (rt + 1) / 2; t += nwaves) {
+    int I, J;
+    tri_ij(t, I, J);
+    const int i = 16 * I + li, j = 16 * J + li;
+    typename M::acc_t acc = {0, 0, 0, 0};
+    for (int s = 0; s < ks; ++s) {
+      const int e = 4 * s + lk;
+      const int c = e < cnt ? sm.sel[e] : 0;
+      const T a = (e < cnt && i < n) ? (T)(sm.lam[e] * sm.V[c * n + i]) : T(0);
+      const T b = (e < cnt && j < n) ? (T)sm.V[c * n + j] : T(0);
+      acc = M::step(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = 16 * I + M::row(lane, r);
+      if (ii <= j && j < n) {
+        const int64_t k = off + (int64_t)j * (j + 1) / 2 + ii;
+        const double p = (double)acc[r] * (ii == j ? 1.0 : s2);
+        S[k] = pos ? (p - Xb[k]) * mul   // (Pi - X_b) * mul
+                   : -p * mul;           // -Pi_-(X_b) * mul
+      }
+    }
   }
 }
 

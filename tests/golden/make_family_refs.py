@@ -1,7 +1,7 @@
 """Writes converged_refs_families.json: the oracle's optimal values of cart-pole and car
 instances (instance parameters from workloads.instance_params) solved to max KKT residual 1e-8:
-cart-pole N = 6 (seeds 0-2), car N = 4 (seed 0: unicycle-12, seed 1: bicycle-13) and the
-full-size cart-pole N = 30 seed 7 (one of the seeds that reaches 1e-6 quickly).  Calls only the
+cart-pole N = 6 (seeds 0 and 2) and car N = 4 (seed 1, bicycle-13): instances the oracle takes
+to 1e-8 within minutes (others, e.g. cart-pole N = 6 seed 1, stall above 1e-8 on the duality gap).  Calls only the
 oracle (one process per case); the GPU tests compare converged device solutions with these.
 
 Run from the repository root:  python tests/golden/make_family_refs.py
@@ -20,14 +20,13 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
-CASES = [("cartpole", W.CARTPOLE, 6, 0), ("cartpole", W.CARTPOLE, 6, 1), ("cartpole", W.CARTPOLE, 6, 2),
-         ("car", W.CAR, 4, 0), ("car", W.CAR, 4, 1), ("cartpole", W.CARTPOLE, 30, 7)]
+CASES = [("cartpole", W.CARTPOLE, 6, 0), ("cartpole", W.CARTPOLE, 6, 2), ("car", W.CAR, 4, 1)]
 
 
 def solve(case):
     name, fam, N, seed = case
     prm = W.instance_params(fam, seed)
-    r = oracle.admm_solve(oracle.relax(fam, N, prm), tol=1e-8, maxiter=200000)
+    r = oracle.admm_solve(oracle.relax(fam, N, prm), tol=1e-8, maxiter=20000)
     return {"family": name, "N": N, "seed": seed, "params": [float(v) for v in prm], "pobj": r["pobj"],
             "dobj": r["dobj"], "iters": int(r["iters"]), "converged": bool(r["converged"]),
             "eta": max(r["eta_p"], r["eta_d"], r["eta_g"])}
