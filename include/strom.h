@@ -206,6 +206,18 @@ strom_status strom_eig_batched(strom_ctx *ctx, int32_t nblocks, int32_t max_n, c
  * eigenvalue of every block of C - A^* y.  FP64; synchronizes; uses temporary device memory. */
 strom_status strom_dual_bound(strom_sdp *sdp, const double *R_beta, double *lb, double *lam_min);
 
+/* strom_dual_bound without any device allocation, for callers that cannot allocate (code
+ * around graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results and synchronization as strom_dual_bound; its temporary device memory (the dense
+ * copies of every block, their eigenvalues and the index lists) lives in a static per-device
+ * work buffer of strom_scratch_bytes() bytes (32 MiB, held until the process ends), whose
+ * address is taken when the device's first context is created.  E_INVAL (nothing launched)
+ * when the instance's blocks need more than that: about 8 * sum n_beta^2 bytes plus the
+ * eigenvalues.  Every call on a device shares the buffer: the library serializes its own calls,
+ * but calls that overlap on one device from elsewhere race. */
+strom_status strom_dual_bound_noalloc(strom_sdp *sdp, const double *R_beta, double *lb, double *lam_min);
+size_t strom_scratch_bytes(void);
+
 /* Rank test and extraction from the current X (Sec. "Sparse Moment Relaxation": the rank-one
  * condition of the convergence theorem, and the first two steps of the extraction heuristic).
  * For each listed block: lam[2k], lam[2k+1] = the largest and second largest eigenvalue

@@ -24,7 +24,7 @@ EXPORTS = [
     "strom_sdp_setup", "strom_sdp_destroy", "strom_admm_step", "strom_admm_enqueue",
     "strom_kkt_residuals", "strom_get_iterate", "strom_set_iterate", "strom_sdp_sizes",
     "strom_project_psd_batched", "strom_submit", "strom_poll", "strom_profile_iteration",
-    "strom_eig_batched", "strom_dual_bound", "strom_extract",
+    "strom_eig_batched", "strom_dual_bound", "strom_dual_bound_noalloc", "strom_extract",
     "strom_batch_create", "strom_batch_step", "strom_batch_tune", "strom_batch_destroy",
     "strom_gen_build", "strom_gen_sizes", "strom_gen_export", "strom_gen_free",
 ]
@@ -86,6 +86,8 @@ def _load():
     L.strom_project_psd_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp, C.c_int, vp]
     L.strom_eig_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, C.c_int, vp]
     L.strom_dual_bound.argtypes = [vp, vp, vp, vp]
+    L.strom_dual_bound_noalloc.argtypes = [vp, vp, vp, vp]
+    L.strom_scratch_bytes.restype = C.c_size_t
     L.strom_extract.argtypes = [vp, i32, vp, vp, vp]
     L.strom_batch_create.argtypes = [vp, i32, vp, C.POINTER(vp)]
     L.strom_batch_step.argtypes = [vp, i32, vp]
@@ -368,13 +370,15 @@ class Instance:
     def enqueue(self, n_iter: int):
         _check(_L.strom_admm_enqueue(self._h, int(n_iter)))
 
-    def dual_bound(self, R_beta):
-        """(lb, lambda_min per block) of the certificate's lower bound at the current y."""
+    def dual_bound(self, R_beta, noalloc: bool = False):
+        """(lb, lambda_min per block) of the certificate's lower bound at the current y;
+        noalloc: through strom_dual_bound_noalloc (static work buffer, no device allocation)."""
         R = np.ascontiguousarray(R_beta, dtype=np.float64)
         lam = np.zeros(len(R))
         lb = C.c_double()
-        _check(_L.strom_dual_bound(self._h, R.ctypes.data_as(C.c_void_p), C.cast(C.byref(lb), C.c_void_p),
-                                   lam.ctypes.data_as(C.c_void_p)))
+        fn = _L.strom_dual_bound_noalloc if noalloc else _L.strom_dual_bound
+        _check(fn(self._h, R.ctypes.data_as(C.c_void_p), C.cast(C.byref(lb), C.c_void_p),
+                  lam.ctypes.data_as(C.c_void_p)))
         return lb.value, lam
 
     def extract(self, blocks, sizes):

@@ -153,6 +153,13 @@ extern "C" strom_status strom_ctx_create(int device, void *hip_stream, size_t hb
     delete c;
     return fail(STROM_E_NOMEM, "hipMalloc of the context flag failed");
   }
+  const strom_status sst = strom::scratch_init(device);  // the static work buffer's address on this device
+  if (sst != STROM_OK) {
+    hipFree(c->err_flag);
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    return sst;
+  }
   *out = c;
   return STROM_OK;
 }
@@ -803,7 +810,7 @@ namespace {
 // eigenvalues in ascending order, concatenated; v: per listed block its n x n eigenvectors
 // (column j for eigenvalue j), concatenated.
 strom_status block_eigs(strom_sdp *s, const double *sv, const std::vector<int32_t> &list, bool want_v,
-                        std::vector<double> &w, std::vector<double> &v) {
+                        std::vector<double> &w, std::vector<double> &v, const strom::DeviceBuf *work = nullptr) {
   const size_t nl = list.size();
   std::vector<int64_t> od(nl), wo(nl);
   std::vector<int32_t> nd(nl);
@@ -825,7 +832,14 @@ strom_status block_eigs(strom_sdp *s, const double *sv, const std::vector<int32_
   const size_t bytes = sizeof(int32_t) * nl * 2 + sizeof(int64_t) * nl * 2 + sizeof(double) * size_t(tn) +
                        sizeof(double) * size_t(tn2) * (want_v ? 2 : 1) + 7 * 256;  // + alignment of 7 regions
   unsigned char *buf = nullptr;
-  if (hipMalloc(&buf, bytes) != hipSuccess) return fail(STROM_E_NOMEM, "device memory for the block eigenvalues");
+  if (work) {  // the caller's device buffer (no allocation)
+    if (bytes > work->bytes)
+      return fail(STROM_E_INVAL, "the blocks need " + std::to_string(bytes) + " bytes of work memory, the buffer holds " +
+                                     std::to_string(work->bytes));
+    buf = work->base;
+  } else if (hipMalloc(&buf, bytes) != hipSuccess) {
+    return fail(STROM_E_NOMEM, "device memory for the block eigenvalues");
+  }
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   size_t o = 0;
   int32_t *d_ids = reinterpret_cast<int32_t *>(buf + o); o = al(o + sizeof(int32_t) * nl);
@@ -855,13 +869,20 @@ strom_status block_eigs(strom_sdp *s, const double *sv, const std::vector<int32_
     v.resize(size_t(tn2));
     chk(hipMemcpy(v.data(), d_v, sizeof(double) * size_t(tn2), hipMemcpyDeviceToHost), "download");
   }
-  hipFree(buf);
+  if (!work) hipFree(buf);
   if (st != STROM_OK) return fail(st, msg);
   return STROM_OK;
 }
 }  // namespace
 
-extern "C" strom_status strom_dual_bound(strom_sdp *s, const double *R_beta, double *lb, double *lam_min) {
+namespace strom {
+int sdp_device(const strom_sdp *s) { return s->ctx->device; }
+
+strom_status set_error(strom_status st, const std::string &msg) { return fail(st, msg); }
+
+// The dual bound with its temporary device memory in `work` (nullptr: allocated per call).
+strom_status dual_bound_impl(strom_sdp *s, const double *R_beta, double *lb, double *lam_min,
+                             const DeviceBuf *work) {
   if (!s || !R_beta || !lb) return fail(STROM_E_INVAL, "bad argument");
   strom_info inf{};
   const strom_status kst = strom_kkt_residuals(s, &inf);  // <b, y> of the current iterate
@@ -875,7 +896,7 @@ extern "C" strom_status strom_dual_bound(strom_sdp *s, const double *R_beta, dou
   std::vector<int32_t> all(size_t(s->nblocks));
   for (int32_t k = 0; k < s->nblocks; ++k) all[size_t(k)] = k;
   std::vector<double> w, v;
-  const strom_status est = block_eigs(s, s->Xb, all, false, w, v);
+  const strom_status est = block_eigs(s, s->Xb, all, false, w, v, work);
   if (est != STROM_OK) return est;
   double bound = inf.dobj;
   int64_t wo = 0;
@@ -887,6 +908,11 @@ extern "C" strom_status strom_dual_bound(strom_sdp *s, const double *R_beta, dou
   }
   *lb = bound;
   return STROM_OK;
+}
+}  // namespace strom
+
+extern "C" strom_status strom_dual_bound(strom_sdp *s, const double *R_beta, double *lb, double *lam_min) {
+  return strom::dual_bound_impl(s, R_beta, lb, lam_min, nullptr);
 }
 
 extern "C" strom_status strom_extract(strom_sdp *s, int32_t nlist, const int32_t *blocks, double *lam, double *vtop) {

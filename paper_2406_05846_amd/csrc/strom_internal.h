@@ -103,4 +103,18 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
                               const int32_t *col, const double *val, double eps_reg, HostAnalysis &H,
                               std::string &err, int split_mode = -1, int block_rows = 0);
 
+// A device buffer handed to an entry point instead of a per-call allocation.
+struct DeviceBuf {
+  unsigned char *base = nullptr;
+  size_t bytes = 0;
+};
+
+// The certificate's dual bound; its temporary device memory comes from `work` (nullptr:
+// allocated and freed per call).
+strom_status dual_bound_impl(strom_sdp *s, const double *R_beta, double *lb, double *lam_min, const DeviceBuf *work);
+int sdp_device(const strom_sdp *s);
+strom_status set_error(strom_status st, const std::string &msg);
+// Address of the static work buffer on `device` (current), looked up once per device.
+strom_status scratch_init(int device);
+
 }  // namespace strom
