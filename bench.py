@@ -431,6 +431,43 @@ def _warm_start(S, W, np, ctx, args) -> dict:
     return res
 
 
+def _certificate(S, W, np, ctx, args) -> dict:
+    """The certificate on a converged full-size solve: car N = 50, bicycle-13 (seed 1), solved to
+    eta <= 1e-6 in FP64; the valid lower bound <b, y> + sum R_beta min(0, lambda_min((C - A^* y)_beta))
+    with the family's trace bounds R_beta, its gap to the objective, and the rank test with the
+    top eigenvectors of the 50 moment blocks (wall time of each call, temporary device memory
+    included; the no-allocation variant of the bound beside it)."""
+    prm = W.instance_params(W.CAR, 1)
+    prob = S.generate(W.CAR, 50, prm)
+    ins = S.Instance(ctx, prob, S.default_opts(maxiter=30000))
+    t = time.perf_counter()
+    inf = ins.step(30000)
+    t_solve = time.perf_counter() - t
+    bs = [int(n) for n in prob.block_sizes]
+    t = time.perf_counter()
+    lb, _ = ins.dual_bound(prob.trace_bounds)
+    t_db = time.perf_counter() - t
+    t = time.perf_counter()
+    lb2, _ = ins.dual_bound(prob.trace_bounds, noalloc=True)
+    t_db2 = time.perf_counter() - t
+    moment = [k for k, n in enumerate(bs) if n == max(bs)]
+    t = time.perf_counter()
+    lam_top, _ = ins.extract(moment, [bs[k] for k in moment])
+    t_ex = time.perf_counter() - t
+    ins.close()
+    p = inf["pobj"]
+    out = {"workload": f"car N=50 bicycle-13 seed 1 (n_svec {prob.nsvec}, m {prob.m}), FP64 solve to eta <= 1e-6, "
+                       f"then the lower bound over all {len(bs)} blocks and the rank test of the {len(moment)} moment blocks",
+           "state": int(inf["state"]), "iters": int(inf["iters"]), "solve_s": round(t_solve, 3),
+           "pobj": p, "lower_bound": lb, "rel_gap": (p - lb) / (1 + abs(p) + abs(lb)),
+           "noalloc_bound_equal": lb2 == lb,
+           "dual_bound_ms": round(1e3 * t_db, 3), "dual_bound_noalloc_ms": round(1e3 * t_db2, 3),
+           "extract_ms": round(1e3 * t_ex, 3),
+           "max_rank_ratio": float(np.max(lam_top[:, 1] / np.maximum(lam_top[:, 0], 1e-300)))}
+    _log(f"certificate: {out}")
+    return out
+
+
 def _paper_pendulum(S, W, ctx, args) -> dict:
     """The paper's own pendulum problem shape (variational-integrator dynamics, 30 moment blocks
     55x55 + 60 localizing blocks 10x10, n_svec 49,500, m 47,351): FP64 iterations/s of one
@@ -483,9 +520,11 @@ def main():
     ap.add_argument("--warm", type=int, default=3, help="receding-horizon warm-start steps (0: skip)")
     ap.add_argument("--paper", type=int, default=1, help="the paper's pendulum shape (0: skip)")
     ap.add_argument("--car", type=int, default=1, help="car N=50 iterations/s (0: skip)")
+    ap.add_argument("--cert", type=int, default=1, help="certificate on a converged car N=50 solve (0: skip)")
     ap.add_argument("--serve-mixed", type=int, default=64, help="requests of the mixed serving sample (0: skip)")
     ap.add_argument("--serve-cap", type=int, default=30000, help="iteration cap of the mixed serving requests")
     ap.add_argument("--serve-window", type=float, default=90.0, help="seconds of the mixed serving sample")
+    ap.add_argument("--profile-iters", type=int, default=200, help="iterations of the per-phase HIP-event profile")
     ap.add_argument("--settle", type=int, default=1000,
                     help="iterations run before the warmup of the headline instance (the warm-started "
                          "eigensolver needs more sweeps in the first hundreds of iterations)")
@@ -545,31 +584,16 @@ def main():
     # (the same regime as the timed region that follows)
     inst.enqueue(args.settle)
     inst.enqueue(args.warmup)
-    prof = inst.profile(200)
+    prof = inst.profile(args.profile_iters)
     _log(f"phase profile (ms): {prof}")
     elapsed = timed_iterations(inst)
     _log(f"timed {args.steps} FP64 iterations in {elapsed:.3f} s")
     info_after = inst.kkt()
-    # certificate pieces on the final iterate (wall time of each call, temporary device memory
-    # included); R_beta = 1 stands in for the problem's trace bounds (timing only)
-    bs = [int(n) for n in prob.block_sizes]
-    t = time.perf_counter()
-    lb, _ = inst.dual_bound(np.ones(len(bs)))
-    t_db = time.perf_counter() - t
-    moment = [k for k, n in enumerate(bs) if n == max(bs)]
-    t = time.perf_counter()
-    lam_top, _ = inst.extract(moment, [bs[k] for k in moment])
-    t_ex = time.perf_counter() - t
-    cert = {"workload": f"cart-pole N=30 final iterate: dual bound over all {len(bs)} blocks (eigenvalues only), "
-                        f"rank test and top eigenvector of the {len(moment)} moment blocks",
-            "dual_bound_ms": round(1e3 * t_db, 3), "extract_ms": round(1e3 * t_ex, 3),
-            "max_rank_ratio": float(np.max(lam_top[:, 1] / np.maximum(lam_top[:, 0], 1e-300)))}
-    _log(f"certificate: {cert}")
     inst.close()
 
     # the reduced-precision form on the same instance (eta stays above the polish switch here)
     inst32 = S.Instance(ctx, prob, S.default_opts(proj_dtype=S.F32))
-    inst32.enqueue(args.settle + 200)
+    inst32.enqueue(args.settle + args.profile_iters)
     elapsed32 = timed_iterations(inst32)
     prof32 = inst32.profile(20)
     inst32.close()
@@ -612,6 +636,7 @@ def main():
     batched = _batched(S, W, np, torch, args) if args.batch > 0 else None
     warm = _warm_start(S, W, np, ctx, args) if args.warm > 0 else None
     paper = _paper_pendulum(S, W, ctx, args) if args.paper else None
+    cert = _certificate(S, W, np, ctx, args) if args.cert else None
 
     flops = _proj_flops(prob.block_sizes)
     proj_s = prof["project_ms"] * 1e-3
@@ -631,7 +656,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "cart-pole swing-up N=30, plain FP64 single instance: 30 moment blocks 78x78 + "
                                f"120 localizing blocks 12x12, n_svec {prob.nsvec}, m {prob.m}, seed {args.seed}; "
-                               f"iterations timed after the first {args.settle} + 200 + warmup of the solve",
+                               f"iterations timed after the first {args.settle} + {args.profile_iters} + warmup of the solve",
                    "n_svec": prob.nsvec, "m": prob.m, "nnz_A": int(prob.nnz)},
         "kkt_after_timed": {"iters": int(info_after["iters"]), "eta_p": info_after["eta_p"],
                             "eta_d": info_after["eta_d"], "eta_g": info_after["eta_g"]},

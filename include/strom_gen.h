@@ -43,6 +43,16 @@ int strom_gen_sizes(const strom_gen_sdp *g, int32_t *nblocks, int32_t *m, int64_
 int strom_gen_export(const strom_gen_sdp *g, int32_t *block_sizes, int64_t *rowptr, int32_t *col,
                      double *val, double *b, double *C_svec, int32_t *row_kind);
 
+/* Trace bounds R_beta (nblocks values) of the certificate's valid lower bound (Sec.
+ * "Algorithmic Backbone", the valid-lower-bound equation), from App. "Existence of R_beta": with
+ * every scaled variable of clique k bounded by R_k (box constraints, unit circles and the
+ * initial state of the family), R_beta = s(d, 2) max(1, R_k)^4 for M_k and
+ * max_{|z| <= R_k} g_{k,i}(z) * s(d, 1) max(1, R_k)^2 for L_{k,i}.  (The appendix writes s(d, 2) R_k^2,
+ * which is not a bound when R_k < 1 or for the degree-two monomials; max(1, R_k)^(2 deg) bounds
+ * the square of every monomial of the basis.)  E_INVAL when a variable of the family has no
+ * bound (the pendulum's angular rate). */
+int strom_gen_trace_bounds(const strom_gen_sdp *g, double *R_beta);
+
 void strom_gen_free(strom_gen_sdp *g);
 
 #ifdef __cplusplus

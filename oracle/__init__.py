@@ -99,6 +99,8 @@ def lib():
         L.orc_project_svec.argtypes = [C.c_int32, _i32, _dp, _dp]
         L.orc_kkt.argtypes = [C.c_int32, _i32, C.c_int32, _i64, _i32, _dp, _dp, _dp, _dp, _dp, _dp,
                               C.POINTER(_Info)]
+        L.orc_trace_bounds.argtypes = [C.c_int, C.c_int, _dp, C.c_int, _dp]
+        L.orc_trace_bounds.restype = C.c_int
         L.orc_dual_bound.argtypes = [C.c_int32, _i32, C.c_int32, _i64, _i32, _dp, _dp, _dp, _dp, _dp,
                                      C.POINTER(C.c_double), _dp]
         L.orc_dual_bound.restype = C.c_int
@@ -250,6 +252,19 @@ def kkt(sdp: SDP, X, y, S) -> dict:
                   np.ascontiguousarray(X, dtype=np.float64), np.ascontiguousarray(y, dtype=np.float64),
                   np.ascontiguousarray(S, dtype=np.float64), C.byref(info))
     return {f: getattr(info, f) for f, _ in _Info._fields_}
+
+
+def trace_bounds(family: int, N: int, params):
+    """R_beta per block of the certificate (relax.c), or None if a variable is unbounded."""
+    prm = np.ascontiguousarray(params, dtype=np.float64)
+    nb = relax(family, N, prm).nblocks
+    out = np.zeros(nb)
+    rc = lib().orc_trace_bounds(int(family), int(N), prm, len(prm), out)
+    if rc == -2:
+        return None
+    if rc != 0:
+        raise ValueError(f"orc_trace_bounds failed: {rc}")
+    return out
 
 
 def dual_bound(sdp: SDP, y, R_beta):

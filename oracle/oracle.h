@@ -82,6 +82,12 @@ double orc_lift(int family, int N, const double *params, int nparams, const doub
 double orc_rollout(int family, int N, const double *params, int nparams, const double *u,
                    double *z);
 
+/* Trace bounds R_beta (nblocks values, block order of orc_relax) for the certificate's lower
+ * bound: every trace of a block of the rank-one lifting of a feasible point is below them
+ * (App. "Existence of R_beta", see relax.c).  Returns -2 if a variable of the family is
+ * unbounded (the pendulum's angular rate). */
+int orc_trace_bounds(int family, int N, const double *params, int nparams, double *R_beta);
+
 /* ---- sparse LDL^T of eps I + A A^* (ldl.c) ---- */
 typedef struct {
   int32_t m;

@@ -453,3 +453,29 @@ int fam_init_state(int family, const double *prm, int nprm, double *x0) {
   for (int i = 0; i < dx; ++i) x0[i] = X[i] / sx[i];
   return 0;
 }
+
+/* Bound on every scaled clique variable (x_k, u_k, x_{k+1} order) of a family, from its box
+ * constraints, unit circles and initial state; returns -1 when some variable has none (the
+ * pendulum's angular rate).  Used for the trace bounds of the certificate. */
+int fam_var_bounds(int family, const double *prm, int nprm, double *bnd) {
+  int dx, du; double sx[PL_MAXV], su[PL_MAXV];
+  if (fam_layout(family, prm, nprm, &dx, &du, sx, su)) return -1;
+  double bx[PL_MAXV], bu[PL_MAXV];
+  if (family == ORC_TOY1D) {          /* x' = (1 - dt (1 + u)) x with |u| <= 1: |x| <= |x_init| */
+    bx[0] = fabs(prm[0]); bu[0] = 1;
+  } else if (family == ORC_CARTPOLE) { /* |x'| <= 1, |v'| <= 4, circle, |w'| <= 16, |f| <= 10 */
+    bx[0] = fmax(1.0, fabs(prm[0])); bx[1] = fmax(4.0, fabs(prm[1])) / sx[1];
+    bx[2] = bx[3] = 1; bx[4] = fmax(16.0, fabs(prm[3])) / sx[4]; bu[0] = 10.0 / su[0];
+  } else if (family == ORC_PAPER_PENDULUM) {
+    bx[0] = bx[1] = bx[2] = bx[3] = 1; bu[0] = 5.0 / su[0];
+  } else if (family == ORC_CAR) {      /* |rx|, |ry| <= 3, circle, |v| <= 2, |a| <= 2, ... */
+    bx[0] = fmax(3.0, fabs(prm[1])) / sx[0]; bx[1] = fmax(3.0, fabs(prm[2])) / sx[1];
+    bx[2] = bx[3] = 1; bx[4] = 2.0 / sx[4]; bu[0] = 2.0 / su[0];
+    if (prm[0] != 0.0) { bu[1] = 0.6; bu[2] = 1.2; } else bu[1] = 1.5;
+  } else {
+    return -1;
+  }
+  for (int i = 0; i < dx; ++i) { bnd[i] = bx[i]; bnd[dx + du + i] = bx[i]; }
+  for (int i = 0; i < du; ++i) bnd[dx + i] = bu[i];
+  return 0;
+}

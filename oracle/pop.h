@@ -29,5 +29,6 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
                pl_poly *cost);
 int fam_step(int family, const double *prm, int nprm, const double *x0, double *u, double *x1);
 int fam_init_state(int family, const double *prm, int nprm, double *x0);
+int fam_var_bounds(int family, const double *prm, int nprm, double *bnd);
 
 #endif

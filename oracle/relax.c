@@ -445,3 +445,70 @@ double orc_rollout(int family, int N, const double *prm, int nprm, const double 
   for (int i = 0; i < dx; ++i) z[(int64_t)N * (dx + du) + i] = x[i];
   return orc_lift(family, N, prm, nprm, z, NULL);
 }
+
+/* Trace bounds for the certificate (App. "Existence of R_beta", with the square that the proof
+ * drops restored): if every variable of clique k satisfies |z_v| <= R_k, each monomial of
+ * degree t of the basis is at most max(1, R_k)^t in size, so for the rank-one lifting
+ *   tr M_k(z) = ||[z]_2||^2 <= s(d, 2) * max(1, R_k)^4,
+ *   tr L_{k,i}(z) = g(z) ||[z]_1||^2 <= (max of g over the box |z| <= R_k) * s(d, 1) * max(1, R_k)^2.
+ * The maximum of g is taken term by term: every inequality of the families is a sum of
+ * one-variable terms of degree <= 2 (other shapes return -3).  R_beta: nblocks values. */
+static int box_max_sep(const pl_poly *g, double R, double *out) {
+  double a[PL_MAXV] = {0}, b[PL_MAXV] = {0}, c = 0;
+  for (int t = 0; t < g->n; ++t) {
+    int var = -1, e = 0;
+    for (int v = 0; v < PL_MAXV; ++v)
+      if (g->t[t].e[v]) {
+        if (var >= 0) return -3;
+        var = v;
+        e = g->t[t].e[v];
+      }
+    if (var < 0) c += g->t[t].c;
+    else if (e == 2) a[var] += g->t[t].c;
+    else if (e == 1) b[var] += g->t[t].c;
+    else return -3;
+  }
+  for (int v = 0; v < PL_MAXV; ++v) {
+    if (a[v] == 0 && b[v] == 0) continue;
+    double best = fmax(a[v] * R * R + b[v] * R, a[v] * R * R - b[v] * R);
+    if (a[v] != 0) {
+      const double t = -b[v] / (2 * a[v]);
+      if (fabs(t) <= R) best = fmax(best, a[v] * t * t + b[v] * t);
+    }
+    c += best;
+  }
+  *out = c;
+  return 0;
+}
+
+int orc_trace_bounds(int family, int N, const double *prm, int nprm, double *R_beta) {
+  int dx, du;
+  double sx[PL_MAXV], su[PL_MAXV], bnd[PL_MAXV];
+  if (N < 1 || fam_layout(family, prm, nprm, &dx, &du, sx, su)) return -1;
+  if (fam_var_bounds(family, prm, nprm, bnd)) return -2;
+  const int d = 2 * dx + du;
+  double Rk = 0;
+  for (int v = 0; v < d; ++v) Rk = fmax(Rk, bnd[v]);
+  const double r1 = fmax(1.0, Rk);
+  const double sM = (double)binom(d + 2, 2), s1 = (double)(d + 1);
+  int bi = 0, rc = 0;
+  for (int k = 0; k < N && !rc; ++k) {
+    pl_list eq, iq;
+    pl_poly cost;
+    memset(&eq, 0, sizeof eq);
+    memset(&iq, 0, sizeof iq);
+    rc = fam_clique(family, N, k, prm, nprm, &eq, &iq, &cost);
+    if (!rc) {
+      R_beta[bi++] = sM * r1 * r1 * r1 * r1;
+      for (int i = 0; i < iq.n && !rc; ++i) {
+        double gm = 0;
+        rc = box_max_sep(&iq.p[i], Rk, &gm);
+        R_beta[bi++] = fmax(0.0, gm) * s1 * r1 * r1;
+      }
+    }
+    pl_list_free(&eq);
+    pl_list_free(&iq);
+    pl_free(&cost);
+  }
+  return rc;
+}

@@ -26,7 +26,7 @@ EXPORTS = [
     "strom_project_psd_batched", "strom_submit", "strom_poll", "strom_profile_iteration",
     "strom_eig_batched", "strom_dual_bound", "strom_dual_bound_noalloc", "strom_extract",
     "strom_batch_create", "strom_batch_step", "strom_batch_tune", "strom_batch_destroy",
-    "strom_gen_build", "strom_gen_sizes", "strom_gen_export", "strom_gen_free",
+    "strom_gen_build", "strom_gen_sizes", "strom_gen_export", "strom_gen_trace_bounds", "strom_gen_free",
 ]
 
 
@@ -99,6 +99,7 @@ def _load():
     L.strom_gen_build.argtypes = [C.c_int, C.c_int, vp, C.c_int, C.POINTER(vp)]
     L.strom_gen_sizes.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), C.POINTER(i64)]
     L.strom_gen_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.strom_gen_trace_bounds.argtypes = [vp, vp]
     L.strom_gen_free.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("strom_default_opts", "strom_last_error", "strom_gen_free"):
@@ -237,9 +238,13 @@ def generate(family: int, N: int, params) -> Problem:
         Cv = np.zeros(n.value, np.float64)
         kind = np.zeros(m.value, np.int32)
         _check(_L.strom_gen_export(h, _ptr(bs), _ptr(rp), _ptr(ci), _ptr(av), _ptr(b), _ptr(Cv), _ptr(kind)))
+        rb = np.zeros(nb.value, np.float64)
+        has_rb = _L.strom_gen_trace_bounds(h, _ptr(rb)) == 0
     finally:
         _L.strom_gen_free(h)
-    return Problem(bs, rp, ci, av, b, Cv, row_kind=kind)
+    prob = Problem(bs, rp, ci, av, b, Cv, row_kind=kind)
+    prob.trace_bounds = rb if has_rb else None  # R_beta of the certificate, None if a variable is unbounded
+    return prob
 
 
 def _stream_handle(stream):

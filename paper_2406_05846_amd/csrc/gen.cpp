@@ -266,6 +266,59 @@ CliquePolys clique_polys(int family, int N, int k, const double *p, const Layout
   return q;
 }
 
+// Bounds on every scaled clique variable implied by the problem (box constraints, unit
+// circles, the initial state), state components first, then controls; false when a variable
+// has none (the pendulum's angular rate).
+bool var_bounds(int family, const double *p, const Layout &L, std::vector<double> &bx, std::vector<double> &bu) {
+  bx.assign(size_t(L.dx), 0.0);
+  bu.assign(size_t(L.du), 0.0);
+  switch (family) {
+    case 0: bx = {std::fabs(p[0])}; bu = {1.0}; return true;  // |x| never grows for |u| <= 1
+    case 2:  // |x| <= 1, |v| <= 4, unit circle, |w| <= 16, |f| <= 10 (scaled by 1, 2, 1, 1, 8 and 10)
+      bx = {std::max(1.0, std::fabs(p[0])), std::max(2.0, std::fabs(p[1]) / 2), 1.0, 1.0,
+            std::max(2.0, std::fabs(p[3]) / 8)};
+      bu = {1.0};
+      return true;
+    case 3: bx = {1.0, 1.0, 1.0, 1.0}; bu = {1.0}; return true;  // unit circles, |u| <= 5 (scaled by 5)
+    case 4:  // |rx|, |ry| <= 3, unit circle, |v| <= 2, |a| <= 2; |w| <= 1.5 or |dtilde| <= 0.6 and |p| <= 1.2
+      bx = {std::max(1.0, std::fabs(p[1]) / 3), std::max(1.0, std::fabs(p[2]) / 3), 1.0, 1.0, 1.0};
+      if (p[0] != 0.0) bu = {1.0, 0.6, 1.2}; else bu = {1.0, 1.5};
+      return true;
+    default: return false;
+  }
+}
+
+// max of g over the box |z_v| <= R for a polynomial whose terms each involve one variable with
+// degree <= 2 (every inequality of the families); false for any other g.
+bool box_max(const Poly &g, double R, double &out) {
+  std::map<int, std::pair<double, double>> ab;  // variable -> (coefficient of z^2, of z)
+  double c = 0.0;
+  for (auto &t : g.c) {
+    if (t.first == 0) { c += t.second; continue; }
+    int var = -1, e = 0;
+    for (int v = 0; v < kMaxVars; ++v)
+      if (mono_exp(t.first, v)) {
+        if (var >= 0) return false;
+        var = v;
+        e = mono_exp(t.first, v);
+      }
+    if (e == 2) ab[var].first += t.second;
+    else if (e == 1) ab[var].second += t.second;
+    else return false;
+  }
+  for (auto &kv : ab) {
+    const double a = kv.second.first, b = kv.second.second;
+    double m = std::max(a * R * R + b * R, a * R * R - b * R);
+    if (a != 0.0) {
+      const double t = -b / (2 * a);
+      if (std::fabs(t) <= R) m = std::max(m, a * t * t + b * t);
+    }
+    c += m;
+  }
+  out = c;
+  return true;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------ relaxation
@@ -279,6 +332,7 @@ struct strom_gen_sdp {
   std::vector<double> C;
   std::vector<int32_t> kind;
   int64_t nsvec = 0;
+  std::vector<double> trace_bound;  // R_beta per block (empty: some variable is unbounded)
 };
 
 namespace {
@@ -351,6 +405,28 @@ extern "C" int strom_gen_build(int family, int N, const double *params, int npar
   }
   S->nsvec = off;
   S->C.assign(size_t(off), 0.0);
+  // Trace bounds of the rank-one liftings (App. "Existence of R_beta"): with |z_v| <= R_k on the
+  // clique, every monomial of degree <= t is at most max(1, R_k)^t in size, so
+  // tr M_k(z) = ||[z]_2||^2 <= s(d, 2) max(1, R_k)^4 and tr L_{k,i}(z) <= max_box g * s(d, 1) max(1, R_k)^2.
+  {
+    std::vector<double> bx, bu;
+    if (var_bounds(family, params, L, bx, bu)) {
+      double Rk = 0.0;
+      for (double v : bx) Rk = std::max(Rk, v);
+      for (double v : bu) Rk = std::max(Rk, v);
+      const double r1 = std::max(1.0, Rk);
+      bool ok = true;
+      for (int k = 0; k < N && ok; ++k) {
+        S->trace_bound.push_back(double(nM) * r1 * r1 * r1 * r1);
+        for (const Poly &g : cl[size_t(k)].ineq) {
+          double gm = 0.0;
+          ok = ok && box_max(g, Rk, gm);
+          S->trace_bound.push_back(std::max(0.0, gm) * double(n1) * r1 * r1);
+        }
+      }
+      if (!ok) S->trace_bound.clear();
+    }
+  }
 
   RowWriter W{*S, {}};
   auto put_rep = [&](int k, Mono mono, double coef) {
@@ -426,3 +502,10 @@ extern "C" int strom_gen_export(const strom_gen_sdp *g, int32_t *block_sizes, in
 }
 
 extern "C" void strom_gen_free(strom_gen_sdp *g) { delete g; }
+
+extern "C" int strom_gen_trace_bounds(const strom_gen_sdp *g, double *R_beta) {
+  if (!g || !R_beta) return STROM_E_INVAL;
+  if (g->trace_bound.empty()) return STROM_E_INVAL;
+  std::memcpy(R_beta, g->trace_bound.data(), g->trace_bound.size() * sizeof(double));
+  return 0;
+}

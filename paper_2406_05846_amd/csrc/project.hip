@@ -317,20 +317,31 @@ __device__ __forceinline__ void rotate_entries(T a, T bq, T cq, T d, T c1, T s1,
   o[3] = s2 * rc + c2 * rd;
 }
 
-// New entries of block b = (I, J) for the rotations rot of the current round.
+// New entries of block b = (I, J) for the rotations of the current round: rot (c, s, new a_pp,
+// new a_qq in T per slot) and rotd (c, s in double per slot).  In double, (c, s) are read from
+// rotd: 16-byte records at consecutive slots, where the 32-byte records of rot would make every
+// wide LDS read of a wave a two-way bank conflict.  In float, rot's records are 16 bytes.
 template <typename T>
-__device__ __forceinline__ void rotate_block(int b, int I, int J, int nblk, const T *A, const T *rot, T *o) {
+__device__ __forceinline__ void rotate_block(int b, int I, int J, int nblk, const T *A, const T *rot,
+                                             const double *rotd, T *o) {
   typedef typename Vec4<T>::type V4;
-  const V4 ri = reinterpret_cast<const V4 *>(rot)[I];
   if (I == J) {
+    const V4 ri = reinterpret_cast<const V4 *>(rot)[I];
     o[0] = ri.z;
     o[1] = T(0);
     o[2] = T(0);
     o[3] = ri.w;
     return;
   }
-  const V4 rj = reinterpret_cast<const V4 *>(rot)[J];
-  rotate_entries<T>(A[b], A[nblk + b], A[2 * nblk + b], A[3 * nblk + b], ri.x, ri.y, rj.x, rj.y, o);
+  T c1, s1, c2, s2;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    const double2 ri = reinterpret_cast<const double2 *>(rotd)[I], rj = reinterpret_cast<const double2 *>(rotd)[J];
+    c1 = ri.x; s1 = ri.y; c2 = rj.x; s2 = rj.y;
+  } else {
+    const V4 ri = reinterpret_cast<const V4 *>(rot)[I], rj = reinterpret_cast<const V4 *>(rot)[J];
+    c1 = ri.x; s1 = ri.y; c2 = rj.x; s2 = rj.y;
+  }
+  rotate_entries<T>(A[b], A[nblk + b], A[2 * nblk + b], A[3 * nblk + b], c1, s1, c2, s2, o);
 }
 
 template <typename T>
@@ -492,8 +503,8 @@ __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *
         }
       }
       T o0[4], o1[4];
-      if (I0 >= 0) rotate_block<T>(b0, I0, J0, nblk, A, rc, o0);
-      if (BIG && I1 >= 0) rotate_block<T>(b1, I1, J1, nblk, A, rc, o1);
+      if (I0 >= 0) rotate_block<T>(b0, I0, J0, nblk, A, rc, rdc, o0);
+      if (BIG && I1 >= 0) rotate_block<T>(b1, I1, J1, nblk, A, rc, rdc, o1);
       if (nbuf == 1) __syncthreads();
       if (I0 >= 0) store_block<T>(An, nblk, d0, tw0, o0);
       if (BIG && I1 >= 0) store_block<T>(An, nblk, d1, tw1, o1);

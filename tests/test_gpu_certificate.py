@@ -150,3 +150,33 @@ def test_warm_started_resolve_reaches_the_cold_optimum(S, ctx):
     assert r[0]["state"] == S.CONVERGED
     assert r[0]["iters"] == res["warm"]["iters"]
     assert abs(r[0]["pobj"] - pw) <= 1e-9 * (1.0 + abs(pw))
+
+
+def test_car_full_size_certificate(S, ctx, orc):
+    """Car N = 50, bicycle-13 (seed 1: 50 moment blocks 105 x 105, 400 localizing), solved to
+    eta <= 1e-6: the valid lower bound with the family's trace bounds R_beta (App. "Existence of
+    R_beta"; the same values from both generators) through strom_dual_bound, against the
+    oracle's bound at the device's y, block by block; the bound sits below <b, y>; the rank test
+    and extraction of the moment blocks against the oracle's."""
+    import workloads as W
+    prm = W.instance_params(W.CAR, 1)
+    prob = S.generate(W.CAR, 50, prm)
+    R = prob.trace_bounds
+    assert R is not None and np.array_equal(R, orc.trace_bounds(W.CAR, 50, prm))
+    inst = S.Instance(ctx, prob, S.default_opts(maxiter=30000))
+    info = inst.step(30000)
+    assert info["state"] == S.CONVERGED, info
+    lb, lam = inst.dual_bound(R)
+    X, y, _ = inst.get_iterate()
+    osdp = orc.relax(W.CAR, 50, prm)
+    ref_lb, ref_lam = orc.dual_bound(osdp, y, R)
+    assert np.abs(lam - ref_lam).max() <= 1e-9 * max(1.0, np.abs(ref_lam).max())
+    assert abs(lb - ref_lb) <= 1e-9 * (1.0 + abs(ref_lb))
+    assert lb <= info["dobj"]
+    gap = (info["pobj"] - lb) / (1.0 + abs(info["pobj"]) + abs(lb))
+    assert 0.0 <= gap <= 5e-2, (info["pobj"], lb)
+    moments = [k for k in range(osdp.nblocks) if osdp.bkind[k] == 0]
+    lt, vt = inst.extract(moments, [int(osdp.bsize[k]) for k in moments])
+    lt_o, vt_o = orc.extract(osdp, X, moments)
+    assert np.abs(lt - lt_o).max() <= 1e-9 * (1.0 + np.abs(lt_o).max())
+    inst.close()

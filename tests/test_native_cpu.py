@@ -117,3 +117,14 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_trace_bounds_agree_with_the_oracle(orc):
+    import paper_2406_05846_amd as S
+    import workloads as W
+    for fam, N, seed in [(W.CARTPOLE, 5, 0), (W.CAR, 4, 0), (W.CAR, 4, 1), (W.PAPER_PENDULUM, 3, 0)]:
+        prm = W.instance_params(fam, seed)
+        ref = orc.trace_bounds(fam, N, prm)
+        got = S.generate(fam, N, prm).trace_bounds
+        assert got is not None and np.array_equal(got, ref), (fam, N)
+    assert S.generate(W.PENDULUM, 3, W.instance_params(W.PENDULUM, 0)).trace_bounds is None

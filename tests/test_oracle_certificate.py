@@ -104,3 +104,36 @@ def test_warm_start_shifted_horizon_reaches_the_cold_optimum(orc):
                           sigma0=r0["sigma"], tol=1e-7, maxiter=50000)
     assert cold["converged"] and warm["converged"]
     assert abs(warm["pobj"] - cold["pobj"]) <= 1e-5 * (1.0 + abs(cold["pobj"]))
+
+
+@pytest.mark.parametrize("fam,N,prm", [("CARTPOLE", 4, [0.1, 0.2, 0.5, 0.3]), ("CARTPOLE", 3, [-0.4, 0.5, 2.9, -1.0]),
+                                       ("CAR", 3, [0, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
+                                       ("CAR", 3, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
+                                       ("PAPER_PENDULUM", 3, [0.3, 0.5]), ("TOY1D", 4, [2.0, 0.1, 1.0])])
+def test_trace_bounds_hold_for_feasible_points(orc, fam, N, prm):
+    """App. "Existence of R_beta" (with the proof's dropped square restored): every block of the
+    rank-one lifting of a feasible trajectory has trace <= R_beta.  Feasible points: rollouts of
+    random controls inside the control box, kept when every inequality holds (their lifted
+    localizing blocks are then PSD with nonnegative diagonals)."""
+    f = getattr(orc, fam)
+    R = orc.trace_bounds(f, N, prm)
+    sdp = orc.relax(f, N, prm)
+    assert R is not None and len(R) == sdp.nblocks and np.all(R > 0)
+    rng = np.random.default_rng(7)
+    kept = 0
+    for trial in range(200):
+        u = rng.uniform(-1.0, 1.0, N * sdp.du) * rng.uniform(0.0, 1.0)
+        z, _ = orc.rollout(f, N, prm, u, sdp.dx, sdp.du)
+        if not np.all(np.isfinite(z)):
+            continue
+        X, _ = orc.lift(f, N, prm, z)
+        tr = _block_traces(sdp, X)
+        if np.any(tr[sdp.bkind == 1] < 0):  # an inequality fails: not a feasible point
+            continue
+        kept += 1
+        assert np.all(tr <= R * (1 + 1e-12)), (trial, np.max(tr / R))
+    assert kept >= 20
+
+
+def test_trace_bounds_need_bounded_variables(orc):
+    assert orc.trace_bounds(orc.PENDULUM, 3, [0.5, 0.0]) is None  # the angular rate has no bound
