@@ -457,12 +457,12 @@ namespace {
 // S_out = (Pi(X_in) - X_in) * scale for every block (scale <= 0: 1 / sigma).  Every call
 // warm-starts from, and refreshes, the eigenvectors kept per block (the cone distance of X
 // uses them too: X and X_b differ little, and any orthogonal start gives the same result).
-hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, double scale) {
+hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, double scale, bool reorth) {
   const bool f32 = s->f32_active;
   for (size_t c = 0; c < s->cls_n.size(); ++c) {
     hipError_t e = strom::dev::launch_project_admm(s->stream, f32, s->cls_n[c], s->cls_cnt[c],
                                                    s->blk_ids + s->cls_off[c], s->boff, s->bsz, X_in, S_out, s->st,
-                                                   scale, s->Q, s->qoff, s->q_valid);
+                                                   scale, s->Q, s->qoff, s->q_valid, reorth);
     if (e != hipSuccess) return e;
   }
   s->q_valid = true;
@@ -473,15 +473,16 @@ hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, d
 // do_sigma, the cone distance of X (through the scratch X_b buffer) and the sigma rule.
 hipError_t enqueue_kkt(strom_sdp *s, bool do_sigma) {
   if (do_sigma) {
-    hipError_t e = enqueue_projection(s, s->X, s->Xb, 1.0);
+    hipError_t e = enqueue_projection(s, s->X, s->Xb, 1.0, true);
     if (e != hipSuccess) return e;
   }
   return strom::dev::launch_kkt(s->stream, s->m, s->nsvec, s->A_rp, s->A_ci, s->A_v, s->X, s->b, s->y, s->part_rows,
                                 s->part_cols, s->Xb, s->part_cone, s->normb, s->normC, do_sigma ? 1 : 0, s->st);
 }
 
-// Enqueue one iteration (steps 1-4); with kkt, also the residuals of the new iterate.
-hipError_t enqueue_iteration(strom_sdp *s, bool kkt, bool do_sigma) {
+// Enqueue one iteration (steps 1-4); with kkt, also the residuals of the new iterate.  first:
+// the iteration opens a round (its projection re-orthogonalizes the kept eigenvectors).
+hipError_t enqueue_iteration(strom_sdp *s, bool kkt, bool do_sigma, bool first) {
   hipStream_t q = s->stream;
   hipError_t e;
   // step 1
@@ -490,7 +491,7 @@ hipError_t enqueue_iteration(strom_sdp *s, bool kkt, bool do_sigma) {
   if ((e = strom::dev::launch_solve(q, s->sch, s->sa, s->w, s->y))) return e;
   // step 2
   if ((e = strom::dev::launch_xb(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->X, s->C, s->st, s->Xb))) return e;
-  if ((e = enqueue_projection(s, s->Xb, s->S, 0.0))) return e;
+  if ((e = enqueue_projection(s, s->Xb, s->S, 0.0, first))) return e;
   // step 3
   if ((e = strom::dev::launch_rhs(q, s->m, s->A_rp, s->A_ci, s->A_v, s->X, s->S, s->C, s->b, s->pinv, s->st, s->w)))
     return e;
@@ -546,7 +547,7 @@ static hipError_t capture_round(strom_sdp *s, bool sigma_last, hipGraphExec_t *o
   hipError_t e2 = hipSuccess;
   const int kk = s->opts.kkt_every;
   for (int k = 0; k < kk && e == hipSuccess && e2 == hipSuccess; ++k)
-    e2 = enqueue_iteration(s, k == kk - 1, sigma_last && k == kk - 1);
+    e2 = enqueue_iteration(s, k == kk - 1, sigma_last && k == kk - 1, k == 0);
   hipGraph_t g = nullptr;
   if (e == hipSuccess) e = hipStreamEndCapture(s->capture_stream, &g);
   s->stream = saved;
@@ -581,7 +582,7 @@ hipError_t sdp_enqueue(strom_sdp *s, int n_iter, bool kkt_last) {
     }
     const bool sig = se > 0 && (it + 1) % se == 0;
     const bool kkt = sig || (it + 1) % kk == 0 || (kkt_last && k == n_iter - 1);
-    hipError_t e = enqueue_iteration(s, kkt, sig);
+    hipError_t e = enqueue_iteration(s, kkt, sig, it % kk == 0);
     if (e != hipSuccess) return e;
     s->iters++;
     ++k;
@@ -668,7 +669,7 @@ extern "C" strom_status strom_profile_iteration(strom_sdp *s, int32_t reps, stro
     rec(2);
     if (!e) e = strom::dev::launch_xb(q, s->nsvec, s->At_rp, s->At_ci, s->At_v, s->y, s->X, s->C, s->st, s->Xb);
     rec(3);
-    if (!e) e = enqueue_projection(s, s->Xb, s->S, 0.0);
+    if (!e) e = enqueue_projection(s, s->Xb, s->S, 0.0, it % s->opts.kkt_every == 0);
     rec(4);
     if (!e) e = strom::dev::launch_rhs(q, s->m, s->A_rp, s->A_ci, s->A_v, s->X, s->S, s->C, s->b, s->pinv, s->st, s->w);
     rec(5);
@@ -973,19 +974,21 @@ struct strom_batch {
 
 namespace {
 
-hipError_t batch_projection(strom_batch *b, hipStream_t q, int cone) {
+hipError_t batch_projection(strom_batch *b, hipStream_t q, int cone, bool reorth) {
   for (const auto &c : b->cls) {
-    hipError_t e = strom::dev::launch_project_batch(q, false, c.n, c.nt[0], c.cnt, b->blocks + c.off, b->bi_dev, cone);
+    hipError_t e = strom::dev::launch_project_batch(q, false, c.n, c.nt[0], c.cnt, b->blocks + c.off, b->bi_dev, cone,
+                                                    reorth);
     if (e != hipSuccess) return e;
-    if (b->any_f32 &&
-        (e = strom::dev::launch_project_batch(q, true, c.n, c.nt[1], c.cnt, b->blocks + c.off, b->bi_dev, cone)))
+    if (b->any_f32 && (e = strom::dev::launch_project_batch(q, true, c.n, c.nt[1], c.cnt, b->blocks + c.off,
+                                                            b->bi_dev, cone, reorth)))
       return e;
   }
   return hipSuccess;
 }
 
-// One iteration of every running instance (the steps of enqueue_iteration, merged).
-hipError_t batch_iteration(strom_batch *b, hipStream_t q, bool kkt, bool sig) {
+// One iteration of every running instance (the steps of enqueue_iteration, merged); first: the
+// iteration opens a round.
+hipError_t batch_iteration(strom_batch *b, hipStream_t q, bool kkt, bool sig, bool first) {
   using namespace strom::dev;
   hipError_t e;
   for (int half = 0; half < 2; ++half) {
@@ -994,12 +997,12 @@ hipError_t batch_iteration(strom_batch *b, hipStream_t q, bool kkt, bool sig) {
       return e;
     if (half == 0) {
       if ((e = launch_xb_batch(q, b->ncols, b->cols, b->bi_dev))) return e;
-      if ((e = batch_projection(b, q, 0))) return e;
+      if ((e = batch_projection(b, q, 0, first))) return e;
     }
   }
   if ((e = launch_xupdate_batch(q, b->ncols, b->cols, b->bi_dev, kkt ? 1 : 0))) return e;
   if (kkt) {
-    if (sig && (e = batch_projection(b, q, 1))) return e;
+    if (sig && (e = batch_projection(b, q, 1, true))) return e;
     if ((e = launch_kkt_batch(q, b->nrows, b->rows, b->ncols, b->cols, int(b->inst.size()), b->bi_dev, sig ? 1 : 0)))
       return e;
   }
@@ -1013,7 +1016,7 @@ hipError_t batch_capture(strom_batch *b, bool sigma_last, hipGraphExec_t *out) {
   e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
   hipError_t e2 = hipSuccess;
   for (int k = 0; k < b->kk && e == hipSuccess && e2 == hipSuccess; ++k)
-    e2 = batch_iteration(b, b->capture_stream, k == b->kk - 1, sigma_last && k == b->kk - 1);
+    e2 = batch_iteration(b, b->capture_stream, k == b->kk - 1, sigma_last && k == b->kk - 1, k == 0);
   hipGraph_t g = nullptr;
   if (e == hipSuccess) e = hipStreamEndCapture(b->capture_stream, &g);
   if (e == hipSuccess) e = e2;
@@ -1226,7 +1229,7 @@ extern "C" strom_status strom_batch_step(strom_batch *b, int32_t n_iter, strom_i
       }
     }
     for (int k = 0; !launched && k < chunk; ++k) {
-      HIP_TRY(batch_iteration(b, b->stream, k == chunk - 1, any_sig && k == chunk - 1));
+      HIP_TRY(batch_iteration(b, b->stream, k == chunk - 1, any_sig && k == chunk - 1, (b->phase + k) % b->kk == 0));
       if (k == 0 && !all_warm) {  // the first projection has filled every running instance's Q
         for (strom_sdp *s : b->inst)
           if (s->state == STROM_RUNNING) s->q_valid = true;
@@ -1286,7 +1289,7 @@ extern "C" strom_status strom_batch_tune(strom_batch *b, int32_t reps, int32_t c
           for (int j = 0; j < no && err == hipSuccess; ++j) {
             auto launch = [&]() {
               return strom::dev::launch_project_batch(b->stream, prec == 1, c.n, opt[j], c.cnt, b->blocks + c.off,
-                                                      b->bi_dev, 1);
+                                                      b->bi_dev, 1, false);
             };
             if ((err = launch())) break;  // untimed first launch
             if ((err = hipEventRecord(e0, b->stream))) break;

@@ -120,10 +120,10 @@ hipError_t launch_xb(hipStream_t s, int64_t n, const int64_t *trp, const int32_t
                      const double *y, const double *X, const double *C, const DevState *st, double *Xb);
 // S = (Pi(X_b) - X_b) * scale for the listed blocks; scale <= 0 means 1 / sigma.  Q (nullable)
 // holds the eigenvectors of each block at qoff[k]; warm starts from them, and they are
-// overwritten with the new ones.
+// overwritten with the new ones, re-orthogonalized (one Newton-Schulz step) when reorth.
 hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const int32_t *ids, const int64_t *boff,
                                const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale,
-                               double *Q, const int64_t *qoff, bool warm);
+                               double *Q, const int64_t *qoff, bool warm, bool reorth);
 // Eigenvalues (ascending, at w + woff[k]) and, with v != nullptr, eigenvectors (columns of an
 // n x n block at v + od[k]) of dense column-major blocks; err as for launch_project_dense.
 hipError_t launch_eig_dense(hipStream_t s, bool f32, int nblocks, int max_n, const int32_t *nd, const int64_t *od,
@@ -169,7 +169,7 @@ hipError_t launch_gather_states(hipStream_t s, int ninst, const BatchInst *bi, D
 // sigma (step 2); cone = 1: X_b = Pi(X) - X (the sigma rule's cone distance), only for the
 // instances whose sig flag is set.
 hipError_t launch_project_batch(hipStream_t s, bool f32, int n, int nt, int count, const BatchItem *items,
-                                const BatchInst *bi, int cone);
+                                const BatchInst *bi, int cone, bool reorth);
 // Thread counts the projection kernel accepts for blocks of size n (at most 5, ascending).
 int project_thread_options(int n, bool f32, int *out);
 

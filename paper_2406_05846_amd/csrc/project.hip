@@ -14,9 +14,9 @@
 // eigenvectors stay in logical order (column i belongs to index i; position x holds index
 // logical_index(x, r) in round r), rotated in place one round late while the first wave
 // computes the next rotation parameters.  Rotation
-// parameters are computed in double for both storage types; the matrix is held in T (double,
-// or float for the reduced-precision form); eigenvectors, norms and the reconstruction are
-// double.
+// parameters are computed in double for both storage types; the matrix and the eigenvectors
+// are held in T (double, or float for the reduced-precision form), norms in double; the
+// products (warm start, reconstruction) run on the matrix cores in T.
 //
 // Warm start (ADMM step): the eigenvectors of the previous call on the same block are kept
 // in HBM; the sweeps start from A = Q^T X_b Q and V = Q, which is nearly diagonal once the
@@ -131,7 +131,7 @@ __device__ inline int position0(int i, int np2, int mm) {
   return 2 * (mm - i) + 1;
 }
 
-// LDS: V (n x nn doubles, column-major, column = index) | red (16 doubles) | rotd (two
+// LDS: V (n x nn of T, column-major, column = index) | red (16 doubles) | rotd (two
 //      buffers of (c, s) doubles per slot) | A (nbuf buffers of four arrays of nblk T) | rot
 //      (two buffers of (c, s, new a_pp, new a_qq) T per slot) | lam (nn doubles) | sel (nn + 4 ints), every
 //      region 32-byte aligned.  nbuf = 2 (a round writes the other buffer) when that fits,
@@ -145,7 +145,7 @@ __host__ __device__ inline size_t align32(size_t x) { return (x + 31) & ~(size_t
 __host__ __device__ inline Layout lds_layout(int n, size_t tsize, int nbuf) {
   const size_t nn = (size_t)n + (n & 1), np2 = nn / 2, nblk = np2 * (np2 + 1) / 2;
   Layout L;
-  L.red = align32(8 * (size_t)n * nn);
+  L.red = align32(tsize * (size_t)n * nn);
   L.rotd = align32(L.red + 8 * 16);
   L.A = align32(L.rotd + 2 * 16 * np2);
   L.rot = align32(L.A + (size_t)nbuf * 4 * tsize * nblk);
@@ -162,7 +162,8 @@ inline size_t lds_bytes_for(int n, size_t tsize) {
 }
 
 struct Smem {
-  double *V, *red, *rotd, *lam;
+  void *V;  // n x nn of the launch's element type
+  double *red, *rotd, *lam;
   void *A, *rot;
   int *sel;
   int nbuf;
@@ -173,7 +174,7 @@ __device__ inline Smem carve(unsigned char *base, int n, size_t lds_cap) {
   const int nbuf = lds_layout(n, sizeof(T), 2).total <= lds_cap ? 2 : 1;
   const Layout L = lds_layout(n, sizeof(T), nbuf);
   Smem s;
-  s.V = reinterpret_cast<double *>(base);
+  s.V = base;
   s.red = reinterpret_cast<double *>(base + L.red);
   s.rotd = reinterpret_cast<double *>(base + L.rotd);
   s.A = base + L.A;
@@ -218,7 +219,7 @@ __device__ inline T diag_entry(const T *Ab, int nblk, int x) {
 // written back; its rows are read back coalesced); then the upper tiles of A = Q^T W are stored
 // in position order, every unordered entry once.  A wave computes whole 16 x 16 tiles.
 template <typename T>
-__device__ __forceinline__ void rotate_into_basis(int n, const double *xs, const double *V, double *wq, T *Ab,
+__device__ __forceinline__ void rotate_into_basis(int n, const double *xs, const T *V, double *wq, T *Ab,
                                                   int nblk) {
   typedef Mfma<T> M;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -243,7 +244,7 @@ __device__ __forceinline__ void rotate_into_basis(int n, const double *xs, const
     for (int s = 0; s < ks; ++s) {
       const int k = 4 * s + lk;
       const T a = (i < n && k < n) ? Xs[pidx(i, k)] : T(0);
-      const T b = (k < n && j < nn) ? (T)V[j * n + k] : T(0);
+      const T b = (k < n && j < nn) ? V[j * n + k] : T(0);
       acc = M::step(a, b, acc);
     }
 #pragma unroll
@@ -261,7 +262,7 @@ __device__ __forceinline__ void rotate_into_basis(int n, const double *xs, const
     typename M::acc_t acc = {0, 0, 0, 0};
     for (int s = 0; s < ks; ++s) {
       const int k = 4 * s + lk;
-      const T a = (k < n && i < nn) ? (T)V[i * n + k] : T(0);
+      const T a = (k < n && i < nn) ? V[i * n + k] : T(0);
       const T b = (k < n && j < nn) ? (T)wq[k * nn + j] : T(0);
       acc = M::step(a, b, acc);
     }
@@ -431,7 +432,7 @@ __device__ inline double block_mass(const T *A, int nblk, int b, int I, int J, b
 // 2x2 blocks, storing them to their permuted places (in the other buffer; single-buffered, the
 // stores wait for one more barrier).  With few threads (no split) every thread does all three.
 template <typename T, bool BIG, bool WANT_V = true>
-__device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *rot, double *rotd, double *red,
+__device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, T *V, T *rot, double *rotd, double *red,
                                           bool v_ready, int &rfin) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int nn = n + (n & 1), np2 = nn / 2, mm = nn - 1;
@@ -462,7 +463,7 @@ __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *
     vcq[j] = k < np2 ? logical_index(2 * k + 1, 0, mm) * n : 0;
   }
   if (WANT_V && !v_ready)
-    for (int k = tid; k < n * nn; k += nth) V[k] = (k % (n + 1) == 0 && k / n < n) ? 1.0 : 0.0;
+    for (int k = tid; k < n * nn; k += nth) V[k] = (k % (n + 1) == 0 && k / n < n) ? T(1) : T(0);
   double f2 = 0.0;
   if (I0 >= 0) f2 += block_mass<T>(Ab, nblk, b0, I0, J0, true);
   if (BIG && I1 >= 0) f2 += block_mass<T>(Ab, nblk, b1, I1, J1, true);
@@ -491,12 +492,19 @@ __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, double *V, T *
         for (int j = 0; j < kMaxVs; ++j) {  // eigenvector columns of slot k, in place
           const int k = vk0 + j * vks;
           if (k < np2) {
-            const double2 cs = reinterpret_cast<const double2 *>(rdc)[k];
-            double *vp = V + vcp[j] + vrow;
-            double *vq = V + vcq[j] + vrow;
-            const double va = *vp, vb = *vq;
-            *vp = cs.x * va - cs.y * vb;
-            *vq = cs.y * va + cs.x * vb;
+            T c, sn;  // (c, s) of slot k: from the double records, or the T records in float
+            if constexpr (sizeof(T) == sizeof(double)) {
+              const double2 cs = reinterpret_cast<const double2 *>(rdc)[k];
+              c = cs.x; sn = cs.y;
+            } else {
+              const typename Vec4<T>::type cs = reinterpret_cast<const typename Vec4<T>::type *>(rc)[k];
+              c = cs.x; sn = cs.y;
+            }
+            T *vp = V + vcp[j] + vrow;
+            T *vq = V + vcq[j] + vrow;
+            const T va = *vp, vb = *vq;
+            *vp = c * va - sn * vb;
+            *vq = sn * va + c * vb;
             vcp[j] = vcp[j] + n >= vwrap ? vcp[j] + n - vwrap : vcp[j] + n;
             if (k > 0) vcq[j] = vcq[j] + n >= vwrap ? vcq[j] + n - vwrap : vcq[j] + n;
           }
@@ -555,19 +563,73 @@ __device__ __forceinline__ void select_side(int nn, int nblk, const T *A, int rf
   __syncthreads();
 }
 
-__device__ inline double rebuild(int i, int j, int n, const double *lam, const double *V, const int *sel, int cnt) {
+template <typename T>
+__device__ inline double rebuild(int i, int j, int n, const double *lam, const T *V, const int *sel, int cnt) {
   double acc = 0.0;
   for (int t = 0; t < cnt; ++t) {
     const int c = sel[t];
-    acc += lam[t] * V[i + c * n] * V[j + c * n];
+    acc += lam[t] * (double)V[i + c * n] * (double)V[j + c * n];
   }
   return acc;
 }
 
+// Eigenvectors V (n x nn, T) written back to q in double after one Newton-Schulz step towards
+// orthogonality, q = V - V (V^T V - I) / 2.  Eigenvectors carried from one projection to the
+// next drift away from orthogonal by a rounding error per iteration (float: ~1e-7 each; a
+// float-era Q also reaches the double projection when the polish switches precision), and the
+// warm start's Q^T X_b Q assumes Q orthogonal; one step maps a defect d to about d^2.  G - I =
+// V^T V - I (upper tiles, packed) goes to Gp, the block arrays, free once the eigenvalues are
+// selected; both products on the matrix cores in T, the update in double.  The dummy column of
+// an odd block is zero and stays zero.
+template <typename T>
+__device__ __forceinline__ void store_reorthogonalized(int n, const T *V, T *Gp, double *q) {
+  typedef Mfma<T> M;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6, li = lane & 15, lk = lane >> 4;
+  const int nn = n + (n & 1), ct = (nn + 15) >> 4, rt = (n + 15) >> 4;
+  for (int t = wave; t < ct * (ct + 1) / 2; t += nwaves) {
+    int I, J;
+    tri_ij(t, I, J);
+    const int i = 16 * I + li, j = 16 * J + li;
+    typename M::acc_t acc = {0, 0, 0, 0};
+    for (int s = 0; s < (n + 3) >> 2; ++s) {
+      const int k = 4 * s + lk;
+      const T a = (k < n && i < nn) ? V[i * n + k] : T(0);
+      const T b = (k < n && j < nn) ? V[j * n + k] : T(0);
+      acc = M::step(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = 16 * I + M::row(lane, r);
+      if (ii <= j && j < nn) Gp[pidx(ii, j)] = acc[r] - (ii == j ? T(1) : T(0));
+    }
+  }
+  __syncthreads();
+  for (int t = wave; t < rt * ct; t += nwaves) {
+    const int I = t / ct, J = t % ct;
+    const int i = 16 * I + li, j = 16 * J + li;
+    typename M::acc_t acc = {0, 0, 0, 0};
+    for (int s = 0; s < (nn + 3) >> 2; ++s) {
+      const int k = 4 * s + lk;
+      const T a = (i < n && k < nn) ? V[k * n + i] : T(0);
+      const T b = (k < nn && j < nn) ? Gp[pidx(k, j)] : T(0);
+      acc = M::step(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = 16 * I + M::row(lane, r);
+      if (ii < n && j < nn) q[j * n + ii] = (double)V[j * n + ii] - 0.5 * (double)acc[r];
+    }
+  }
+}
+
 // ADMM step 2: S = (Pi(X_b) - X_b) * scale for the listed blocks (svec in and out), scale <= 0
 // meaning 1 / sigma.  With Q != nullptr the eigenvectors of block k (n x nn, position order)
-// live at Q + qoff[k]; warm selects a start from them (else a cold start) and they are written
-// back after the sweeps.  lds_cap: the dynamic LDS of the launch.
+// live at Q + qoff[k]; bit 0 of warm selects a start from them (else a cold start), and they
+// are written back after the sweeps, re-orthogonalized when bit 1 is set (the host sets it on
+// the first projection of every round and on the cone projections of the sigma rule, so the
+// drift of the kept eigenvectors stays at that of a round).  lds_cap: the dynamic LDS of the
+// launch.
 template <typename T, bool BIG>
 __device__ __forceinline__ void project_block(int32_t bk, const int64_t *__restrict__ boff, const int32_t *__restrict__ bsz,
                                               const double *__restrict__ Xb, double *__restrict__ S,
@@ -583,11 +645,12 @@ __device__ __forceinline__ void project_block(int32_t bk, const int64_t *__restr
   T *Ab = reinterpret_cast<T *>(sm.A);
   const double rs2 = 0.70710678118654752440, s2 = 1.41421356237309504880;
   double *q = Q ? Q + qoff[bk] : nullptr;
-  const bool use_q = q && warm;
+  const bool use_q = q && (warm & 1);
+  T *Vt = reinterpret_cast<T *>(sm.V);
   if (use_q) {
-    for (int k = tid; k < n * nn; k += nth) sm.V[k] = q[k];
+    for (int k = tid; k < n * nn; k += nth) Vt[k] = (T)q[k];
     __syncthreads();
-    rotate_into_basis<T>(n, Xb + off, sm.V, q, Ab, nblk);
+    rotate_into_basis<T>(n, Xb + off, Vt, q, Ab, nblk);
   } else {
     for (int e = tid; e < nn * (nn + 1) / 2; e += nth) {  // svec: packed upper triangle, sqrt(2) off-diagonal
       int x, y;
@@ -599,10 +662,13 @@ __device__ __forceinline__ void project_block(int32_t bk, const int64_t *__restr
     __syncthreads();
   }
   int rfin = 0;
-  const int cur = jacobi_eig<T, BIG>(n, Ab, sm.nbuf, sm.V, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red, use_q, rfin);
+  const int cur = jacobi_eig<T, BIG>(n, Ab, sm.nbuf, Vt, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red, use_q, rfin);
   select_side<T>(nn, nblk, Ab + (size_t)cur * 4 * nblk, rfin, sm.sel, sm.lam);
-  if (q)
-    for (int k = tid; k < n * nn; k += nth) q[k] = sm.V[k];
+  if (q) {
+    if (warm & 2) store_reorthogonalized<T>(n, Vt, Ab, q);
+    else
+      for (int k = tid; k < n * nn; k += nth) q[k] = (double)Vt[k];
+  }
   const int pos = sm.sel[nn], cnt = sm.sel[nn + 1];
   const double mul = scale > 0.0 ? scale : 1.0 / st->sigma;
   // P = U diag(lam) U^T over the selected eigenpairs (U = the columns sel of V) on the matrix
@@ -618,8 +684,8 @@ __device__ __forceinline__ void project_block(int32_t bk, const int64_t *__restr
     for (int s = 0; s < ks; ++s) {
       const int e = 4 * s + lk;
       const int c = e < cnt ? sm.sel[e] : 0;
-      const T a = (e < cnt && i < n) ? (T)(sm.lam[e] * sm.V[c * n + i]) : T(0);
-      const T b = (e < cnt && j < n) ? (T)sm.V[c * n + j] : T(0);
+      const T a = (e < cnt && i < n) ? (T)(sm.lam[e] * (double)Vt[c * n + i]) : T(0);
+      const T b = (e < cnt && j < n) ? Vt[c * n + j] : T(0);
       acc = M::step(a, b, acc);
     }
 #pragma unroll
@@ -651,15 +717,15 @@ __global__ void __launch_bounds__(1024) k_project_admm(const int32_t *__restrict
 template <typename T, bool BIG>
 __global__ void __launch_bounds__(1024) k_project_batch(const BatchItem *__restrict__ items,
                                                         const BatchInst *__restrict__ bi, int32_t cone,
-                                                        uint32_t lds_cap) {
+                                                        int32_t reorth, uint32_t lds_cap) {
   extern __shared__ __align__(32) unsigned char smem[];
   const BatchItem it = items[blockIdx.x];
   const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
   if (!I.active || I.f32 != (sizeof(T) == sizeof(float) ? 1 : 0) || (cone && !I.sig)) return;
   const double *in = G(cone ? I.X : I.Xb);
   double *out = G(cone ? I.Xb : I.S);
-  project_block<T, BIG>(it.idx, G(I.boff), G(I.bsz), in, out, G(I.st), cone ? 1.0 : 0.0, G(I.Q), G(I.qoff), I.warm,
-                        lds_cap, smem);
+  project_block<T, BIG>(it.idx, G(I.boff), G(I.bsz), in, out, G(I.st), cone ? 1.0 : 0.0, G(I.Q), G(I.qoff),
+                        (I.warm ? 1 : 0) | (cone || reorth ? 2 : 0), lds_cap, smem);
 }
 
 // strom_project_psd_batched: column-major blocks in T, at element offsets.
@@ -689,14 +755,15 @@ __global__ void __launch_bounds__(1024) k_project_dense(int32_t nblocks, const i
   }
   __syncthreads();
   int rfin = 0;
-  const int cur = jacobi_eig<T, BIG>(n, Ab, sm.nbuf, sm.V, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red, false, rfin);
+  T *Vt = reinterpret_cast<T *>(sm.V);
+  const int cur = jacobi_eig<T, BIG>(n, Ab, sm.nbuf, Vt, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red, false, rfin);
   select_side<T>(nn, nblk, Ab + (size_t)cur * 4 * nblk, rfin, sm.sel, sm.lam);
   const int pos = sm.sel[nn], cnt = sm.sel[nn + 1];
   // every thread reads only the upper entries it writes, so out may alias in
   for (int k = tid; k < npk; k += nth) {
     int i, j;
     tri_ij(k, i, j);
-    const double acc = rebuild(i, j, n, sm.lam, sm.V, sm.sel, cnt);
+    const double acc = rebuild<T>(i, j, n, sm.lam, Vt, sm.sel, cnt);
     const double x = (double)in[off + i + (int64_t)j * n];
     const T pv = (T)(pos ? acc : x - acc);
     out[off + i + (int64_t)j * n] = pv;
@@ -733,7 +800,8 @@ __global__ void __launch_bounds__(1024) k_eig_dense(int32_t nblocks, const int32
   }
   __syncthreads();
   int rfin = 0;
-  const int cur = jacobi_eig<T, BIG, WANT_V>(n, Ab, sm.nbuf, sm.V, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red,
+  T *Vt = reinterpret_cast<T *>(sm.V);
+  const int cur = jacobi_eig<T, BIG, WANT_V>(n, Ab, sm.nbuf, Vt, reinterpret_cast<T *>(sm.rot), sm.rotd, sm.red,
                                              false, rfin);
   const T *A = Ab + (size_t)cur * 4 * nblk;
   for (int x = tid; x < nn; x += nth) sm.lam[logical_index(x, rfin, mm)] = (double)diag_entry(A, nblk, x);
@@ -752,7 +820,7 @@ __global__ void __launch_bounds__(1024) k_eig_dense(int32_t nblocks, const int32
     __syncthreads();
     for (int e = tid; e < n * n; e += nth) {
       const int r = e % n, i = e / n;
-      v[off + r + (int64_t)sm.sel[i] * n] = (T)sm.V[i * n + r];
+      v[off + r + (int64_t)sm.sel[i] * n] = Vt[i * n + r];
     }
   }
 }
@@ -807,49 +875,49 @@ static bool threads_ok(int n, int nt, bool f32, bool &big) {
 template <typename T, bool BIG>
 static void launch_admm_t(hipStream_t s, int count, int nt, size_t lds, const int32_t *ids, const int64_t *boff,
                           const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale, double *Q,
-                          const int64_t *qoff, bool warm) {
+                          const int64_t *qoff, bool warm, bool reorth) {
   (void)hipFuncSetAttribute((const void *)k_project_admm<T, BIG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((k_project_admm<T, BIG>), dim3(count), dim3(nt), lds, s, ids, boff, bsz, Xb, S, st, scale, Q, qoff,
-                     warm ? 1 : 0, (uint32_t)lds);
+                     (warm ? 1 : 0) | (reorth ? 2 : 0), (uint32_t)lds);
 }
 
 hipError_t launch_project_admm(hipStream_t s, bool f32, int n, int count, const int32_t *ids, const int64_t *boff,
                                const int32_t *bsz, const double *Xb, double *S, const DevState *st, double scale,
-                               double *Q, const int64_t *qoff, bool warm) {
+                               double *Q, const int64_t *qoff, bool warm, bool reorth) {
   if (count <= 0) return hipSuccess;
   const int nt = project_threads(n);
   const size_t lds = project_lds_bytes(n, f32, nt);
   bool big = false;
   if (!threads_ok(n, nt, f32, big) || lds > kLdsCap) return hipErrorInvalidValue;
   if (f32) {
-    if (big) launch_admm_t<float, true>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
-    else launch_admm_t<float, false>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
+    if (big) launch_admm_t<float, true>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm, reorth);
+    else launch_admm_t<float, false>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm, reorth);
   } else {
-    if (big) launch_admm_t<double, true>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
-    else launch_admm_t<double, false>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm);
+    if (big) launch_admm_t<double, true>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm, reorth);
+    else launch_admm_t<double, false>(s, count, nt, lds, ids, boff, bsz, Xb, S, st, scale, Q, qoff, warm, reorth);
   }
   return hipGetLastError();
 }
 
 template <typename T, bool BIG>
 static void launch_batch_t(hipStream_t s, int count, int nt, size_t lds, const BatchItem *items, const BatchInst *bi,
-                           int cone) {
+                           int cone, int reorth) {
   (void)hipFuncSetAttribute((const void *)k_project_batch<T, BIG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_project_batch<T, BIG>), dim3(count), dim3(nt), lds, s, items, bi, cone, (uint32_t)lds);
+  hipLaunchKernelGGL((k_project_batch<T, BIG>), dim3(count), dim3(nt), lds, s, items, bi, cone, reorth, (uint32_t)lds);
 }
 
 hipError_t launch_project_batch(hipStream_t s, bool f32, int n, int nt, int count, const BatchItem *items,
-                                const BatchInst *bi, int cone) {
+                                const BatchInst *bi, int cone, bool reorth) {
   if (count <= 0) return hipSuccess;
   const size_t lds = project_lds_bytes(n, f32, nt);
   bool big = false;
   if (!threads_ok(n, nt, f32, big) || lds > kLdsCap) return hipErrorInvalidValue;
   if (f32) {
-    if (big) launch_batch_t<float, true>(s, count, nt, lds, items, bi, cone);
-    else launch_batch_t<float, false>(s, count, nt, lds, items, bi, cone);
+    if (big) launch_batch_t<float, true>(s, count, nt, lds, items, bi, cone, reorth ? 1 : 0);
+    else launch_batch_t<float, false>(s, count, nt, lds, items, bi, cone, reorth ? 1 : 0);
   } else {
-    if (big) launch_batch_t<double, true>(s, count, nt, lds, items, bi, cone);
-    else launch_batch_t<double, false>(s, count, nt, lds, items, bi, cone);
+    if (big) launch_batch_t<double, true>(s, count, nt, lds, items, bi, cone, reorth ? 1 : 0);
+    else launch_batch_t<double, false>(s, count, nt, lds, items, bi, cone, reorth ? 1 : 0);
   }
   return hipGetLastError();
 }
