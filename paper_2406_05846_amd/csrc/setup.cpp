@@ -18,10 +18,17 @@
 //    nothing is refactored).  Contributions to rows of later tasks are pushed as partial
 //    sums by the task owning the columns.  Tasks are launched by dependency depth.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <list>
+#include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "strom_internal.h"
@@ -45,11 +52,234 @@ int32_t lanes_for(int64_t len) {
   return g;
 }
 
+// Where every value of an analysis comes from, so that an instance with the same sparsity
+// pattern (the same family, variant and horizon: only the initial state and the obstacle
+// change the coefficients) reuses the symbolic part and recomputes only the numbers.
+struct NumericMaps {
+  std::vector<int64_t> at_src;                 // Atv[q] = val[at_src[q]]
+  std::vector<int32_t> perm0, pinv0;           // the row order the factor is computed in
+  std::vector<int64_t> Cp0;                    // pattern of L in that order, by columns
+  std::vector<int32_t> Ci0;
+  std::vector<int32_t> tr0, tr1;               // the tasks of that order (parallel factorization)
+  std::vector<int64_t> lv_src, uv_src;         // Lv[p] = Cx0[lv_src[p]], Uv[p] = Cx0[uv_src[p]]
+  std::vector<int32_t> d_src;                  // D[i] = D0[d_src[i]]
+  std::vector<int64_t> push_src;               // push_v[e] = Lv[push_src[e]]
+  std::vector<int64_t> s_src[kStreamKinds];    // stream values: code of Lv / Uv / invR / invC, -1: 0, -2: 1
+};
+
+// K = P (A A^*) P^T, lower triangle by columns (diagonal first), in the row order perm;
+// returns max diag.
+double assemble_K(int32_t m, const int64_t *rowptr, const int32_t *col, const double *val,
+                  const std::vector<int32_t> &perm, const std::vector<int32_t> &pinv, const HostAnalysis &H,
+                  std::vector<int64_t> &Kp, std::vector<int32_t> &Ki, std::vector<double> &Kx) {
+  Kp.assign(size_t(m) + 1, 0);
+  Ki.clear();
+  Kx.clear();
+  double maxdiag = 0.0;
+  std::vector<double> acc(size_t(m), 0.0);
+  std::vector<int32_t> seen(size_t(m), -1), list;
+  Ki.reserve(size_t(rowptr[m]) * 6);
+  Kx.reserve(size_t(rowptr[m]) * 6);
+  for (int32_t j = 0; j < m; ++j) {  // column j of the lower triangle (new order)
+    const int32_t oj = perm[size_t(j)];
+    list.clear();
+    for (int64_t p = rowptr[oj]; p < rowptr[oj + 1]; ++p) {
+      const int32_t c = col[p];
+      for (int64_t q = H.Atrp[size_t(c)]; q < H.Atrp[size_t(c) + 1]; ++q) {
+        const int32_t ni = pinv[size_t(H.Atci[size_t(q)])];
+        if (ni < j) continue;
+        if (seen[size_t(ni)] != j) { seen[size_t(ni)] = j; acc[size_t(ni)] = 0.0; list.push_back(ni); }
+        acc[size_t(ni)] += val[p] * H.Atv[size_t(q)];
+      }
+    }
+    if (seen[size_t(j)] != j) { seen[size_t(j)] = j; acc[size_t(j)] = 0.0; list.push_back(j); }
+    std::sort(list.begin(), list.end());
+    Kp[size_t(j)] = int64_t(Ki.size());
+    for (int32_t ni : list) { Ki.push_back(ni); Kx.push_back(acc[size_t(ni)]); }
+    maxdiag = std::max(maxdiag, acc[size_t(j)]);
+  }
+  Kp[size_t(m)] = int64_t(Ki.size());
+  return maxdiag;
+}
+
+// Left-looking LDL^T of K on the known pattern (Cp, Ci) of L by columns.  Column j gathers
+// the updates of the earlier columns k with L(j, k) != 0 from a list of columns "waiting on
+// row j" (a column waits on the row of its next unused entry): the list is last-in first-out,
+// so the order of the updates, and with it the rounding, is the order in which the columns
+// arrived at row j.
+//
+// The columns come in tasks (contiguous row ranges: clique groups, then the coupling sets in
+// nested-dissection order).  A task depends on the tasks whose columns have entries in its rows;
+// tasks of one dependency level run in parallel threads, each with its own work vector.  A
+// column arriving at a row of another task is recorded instead of linked; before a task runs,
+// the arrivals at its rows are linked in the sequential order (by the task that performed them,
+// then in its order) -- every such task is one of its dependencies (if L(j, k) and L(r, k) are
+// nonzero for k < j < r, so is L(r, j)) -- so the result is bit for bit the sequential one.
+// STROM_SETUP_THREADS sets the thread count (1: the sequential loop).
+strom_status numeric_factor(int32_t m, const std::vector<int64_t> &Kp, const std::vector<int32_t> &Ki,
+                            const std::vector<double> &Kx, const std::vector<int64_t> &Cp,
+                            const std::vector<int32_t> &Ci, const std::vector<int32_t> &tr0,
+                            const std::vector<int32_t> &tr1, std::vector<double> &Cx, std::vector<double> &Dn,
+                            std::string &err) {
+  Cx.assign(size_t(Cp[size_t(m)]), 0.0);
+  Dn.assign(size_t(m), 0.0);
+  std::vector<int64_t> nxt(size_t(m), 0);                          // next unused entry of column k
+  std::vector<int32_t> head(size_t(m), -1), link(size_t(m), -1);  // columns waiting on row j
+  struct Arrival { int32_t r, k; };
+  // Columns [a, b) with work vector w; arrivals at rows >= b go to out (when given), else linked.
+  auto run = [&](int32_t a, int32_t b, std::vector<double> &w, std::vector<Arrival> *out, int32_t &bad) {
+    auto arrive = [&](int32_t r, int32_t k) {
+      if (out && r >= b) { out->push_back({r, k}); return; }
+      link[size_t(k)] = head[size_t(r)];
+      head[size_t(r)] = k;
+    };
+    for (int32_t j = a; j < b; ++j) {
+      for (int64_t p = Kp[size_t(j)]; p < Kp[size_t(j) + 1]; ++p) w[size_t(Ki[size_t(p)])] = Kx[size_t(p)];
+      int32_t k = head[size_t(j)];
+      while (k >= 0) {
+        const int32_t knext = link[size_t(k)];
+        const int64_t p0 = nxt[size_t(k)], pend = Cp[size_t(k) + 1];
+        const double f = Cx[size_t(p0)] * Dn[size_t(k)];  // L(j,k) D(k)
+        for (int64_t p = p0; p < pend; ++p) w[size_t(Ci[size_t(p)])] -= Cx[size_t(p)] * f;
+        nxt[size_t(k)] = p0 + 1;
+        if (p0 + 1 < pend) arrive(Ci[size_t(p0 + 1)], k);
+        k = knext;
+      }
+      const double dj = w[size_t(j)];
+      w[size_t(j)] = 0.0;
+      if (!(dj > 0.0) || !std::isfinite(dj)) {
+        bad = j;
+        return;
+      }
+      Dn[size_t(j)] = dj;
+      for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
+        const int32_t i = Ci[size_t(p)];
+        Cx[size_t(p)] = w[size_t(i)] / dj;
+        w[size_t(i)] = 0.0;
+      }
+      if (Cp[size_t(j)] < Cp[size_t(j) + 1]) {
+        nxt[size_t(j)] = Cp[size_t(j)];
+        arrive(Ci[size_t(Cp[size_t(j)])], j);
+      }
+    }
+  };
+  auto pivot_error = [&](int32_t j) {
+    err = "non-positive pivot in LDL^T of eps*I + A A^* at row " + std::to_string(j);
+    return STROM_E_FACTOR;
+  };
+  int threads = int(std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency())));
+  if (const char *ev = std::getenv("STROM_SETUP_THREADS")) threads = std::max(1, std::atoi(ev));
+  const int32_t nt = int32_t(tr0.size());
+  bool tasks_ok = nt > 1 && threads > 1 && tr0.size() == tr1.size() && tr0[0] == 0 && tr1[size_t(nt) - 1] == m;
+  for (int32_t t = 1; tasks_ok && t < nt; ++t) tasks_ok = tr0[size_t(t)] == tr1[size_t(t) - 1];
+  std::vector<int32_t> rtask, level;
+  if (tasks_ok) {
+    rtask.resize(size_t(m));
+    for (int32_t t = 0; t < nt; ++t)
+      for (int32_t r = tr0[size_t(t)]; r < tr1[size_t(t)]; ++r) rtask[size_t(r)] = t;
+    level.assign(size_t(nt), 0);
+    for (int32_t t = 0; t < nt && tasks_ok; ++t)  // tasks ascend, so their dependencies come first
+      for (int32_t k = tr0[size_t(t)]; k < tr1[size_t(t)]; ++k)
+        for (int64_t p = Cp[size_t(k)]; p < Cp[size_t(k) + 1]; ++p) {
+          const int32_t u = rtask[size_t(Ci[size_t(p)])];
+          if (u < t) { tasks_ok = false; break; }
+          if (u > t) level[size_t(u)] = std::max(level[size_t(u)], level[size_t(t)] + 1);
+        }
+  }
+  if (!tasks_ok) {
+    std::vector<double> w(size_t(m), 0.0);
+    int32_t bad = -1;
+    run(0, m, w, nullptr, bad);
+    return bad >= 0 ? pivot_error(bad) : STROM_OK;
+  }
+  const int32_t nlev = *std::max_element(level.begin(), level.end()) + 1;
+  std::vector<std::vector<int32_t>> by_level(static_cast<size_t>(nlev));
+  for (int32_t t = 0; t < nt; ++t) by_level[size_t(level[size_t(t)])].push_back(t);
+  struct Rec { int32_t src; int64_t seq; Arrival a; };
+  std::vector<std::vector<Rec>> inbox(static_cast<size_t>(nt));
+  std::vector<std::vector<Arrival>> outs(static_cast<size_t>(nt));
+  std::vector<int32_t> bad(size_t(nt), -1);
+  std::vector<std::vector<double>> works(static_cast<size_t>(threads));
+  bool dag_ok = true;
+  for (int32_t L = 0; L < nlev && dag_ok; ++L) {
+    const std::vector<int32_t> &ts = by_level[size_t(L)];
+    std::atomic<size_t> next(0);
+    auto worker = [&](int id) {
+      std::vector<double> &w = works[size_t(id)];
+      if (w.empty()) w.assign(size_t(m), 0.0);
+      for (size_t q; (q = next.fetch_add(1)) < ts.size();) {
+        const int32_t t = ts[q];
+        std::vector<Rec> &in = inbox[size_t(t)];
+        std::sort(in.begin(), in.end(), [](const Rec &x, const Rec &y) {
+          return x.src != y.src ? x.src < y.src : x.seq < y.seq;
+        });
+        for (const Rec &x : in) {
+          link[size_t(x.a.k)] = head[size_t(x.a.r)];
+          head[size_t(x.a.r)] = x.a.k;
+        }
+        run(tr0[size_t(t)], tr1[size_t(t)], w, &outs[size_t(t)], bad[size_t(t)]);
+      }
+    };
+    const int nth = int(std::min<size_t>(size_t(threads), ts.size()));
+    std::vector<std::thread> pool;
+    for (int i = 1; i < nth; ++i) pool.emplace_back(worker, i);
+    worker(0);
+    for (auto &th : pool) th.join();
+    for (int32_t t : ts) {
+      if (bad[size_t(t)] >= 0) continue;
+      const std::vector<Arrival> &o = outs[size_t(t)];
+      for (size_t i = 0; i < o.size(); ++i) {
+        const int32_t u = rtask[size_t(o[i].r)];
+        if (level[size_t(u)] <= L) { dag_ok = false; break; }
+        inbox[size_t(u)].push_back({t, int64_t(i), o[i]});
+      }
+      std::vector<Arrival>().swap(outs[size_t(t)]);
+    }
+  }
+  int32_t first_bad = -1;
+  for (int32_t b : bad)
+    if (b >= 0 && (first_bad < 0 || b < first_bad)) first_bad = b;
+  if (first_bad >= 0) return pivot_error(first_bad);
+  if (!dag_ok) {  // an arrival outside the dependency structure: not expected, redo sequentially
+    std::fill(nxt.begin(), nxt.end(), 0);
+    std::fill(head.begin(), head.end(), -1);
+    std::fill(link.begin(), link.end(), -1);
+    std::vector<double> w(size_t(m), 0.0);
+    int32_t b = -1;
+    run(0, m, w, nullptr, b);
+    return b >= 0 ? pivot_error(b) : STROM_OK;
+  }
+  return STROM_OK;
+}
+
+// Inverse of the unit lower-triangular diagonal block of L over the component rows [c0, c1)
+// (final order, CSR of L), row-major in inv (cn x cn).
+void component_inverse(const HostAnalysis &H, int32_t c0, int32_t c1, std::vector<double> &blk,
+                       std::vector<double> &inv) {
+  const int32_t cn = c1 - c0;
+  blk.assign(size_t(cn) * cn, 0.0);
+  inv.assign(size_t(cn) * cn, 0.0);
+  for (int32_t i = c0; i < c1; ++i)
+    for (int64_t p = H.Lrp[size_t(i)]; p < H.Lrp[size_t(i) + 1]; ++p) {
+      const int32_t j = H.Lci[size_t(p)];
+      if (j >= c0) blk[size_t(i - c0) * cn + size_t(j - c0)] = H.Lv[size_t(p)];
+    }
+  for (int32_t c = 0; c < cn; ++c) {
+    inv[size_t(c) * cn + size_t(c)] = 1.0;
+    for (int32_t i = c + 1; i < cn; ++i) {
+      double sacc = 0.0;
+      for (int32_t k = c; k < i; ++k) sacc -= blk[size_t(i) * cn + size_t(k)] * inv[size_t(k) * cn + size_t(c)];
+      inv[size_t(i) * cn + size_t(c)] = sacc;
+    }
+  }
+}
+
 }  // namespace
 
-strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *rowptr,
-                              const int32_t *col, const double *val, double eps_reg, HostAnalysis &H,
-                              std::string &err, int split_mode, int block_rows) {
+namespace {
+strom_status analyze_full(int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *rowptr,
+                          const int32_t *col, const double *val, double eps_reg, HostAnalysis &H,
+                          std::string &err, int split_mode, int block_rows, NumericMaps *mp) {
   // ---------------------------------------------------------------- validation
   if (nblocks <= 0 || !bsize || m <= 0 || !rowptr || !col || !val) {
     err = "empty problem or NULL array";
@@ -91,6 +321,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   for (int64_t c = 0; c < H.nsvec; ++c) H.Atrp[size_t(c) + 1] += H.Atrp[size_t(c)];
   H.Atci.resize(size_t(nnz));
   H.Atv.resize(size_t(nnz));
+  if (mp) mp->at_src.resize(size_t(nnz));
   {
     std::vector<int64_t> fill(H.Atrp.begin(), H.Atrp.end() - 1);
     for (int32_t i = 0; i < m; ++i)
@@ -98,6 +329,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
         const int64_t q = fill[size_t(col[p])]++;
         H.Atci[size_t(q)] = i;
         H.Atv[size_t(q)] = val[p];
+        if (mp) mp->at_src[size_t(q)] = p;
       }
   }
 
@@ -163,35 +395,11 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   }
 
   // ---------------------------------------------------------------- K = P A A^* P^T (lower)
-  std::vector<int64_t> Kp(size_t(m) + 1, 0);
+  std::vector<int64_t> Kp;
   std::vector<int32_t> Ki;
   std::vector<double> Kx;
-  double maxdiag = 0.0;
-  {
-    std::vector<double> acc(size_t(m), 0.0);
-    std::vector<int32_t> seen(size_t(m), -1), list;
-    Ki.reserve(size_t(nnz) * 6);
-    Kx.reserve(size_t(nnz) * 6);
-    for (int32_t j = 0; j < m; ++j) {  // column j of the lower triangle (new order)
-      const int32_t oj = H.perm[size_t(j)];
-      list.clear();
-      for (int64_t p = rowptr[oj]; p < rowptr[oj + 1]; ++p) {
-        const int32_t c = col[p];
-        for (int64_t q = H.Atrp[size_t(c)]; q < H.Atrp[size_t(c) + 1]; ++q) {
-          const int32_t ni = H.pinv[size_t(H.Atci[size_t(q)])];
-          if (ni < j) continue;
-          if (seen[size_t(ni)] != j) { seen[size_t(ni)] = j; acc[size_t(ni)] = 0.0; list.push_back(ni); }
-          acc[size_t(ni)] += val[p] * H.Atv[size_t(q)];
-        }
-      }
-      if (seen[size_t(j)] != j) { seen[size_t(j)] = j; acc[size_t(j)] = 0.0; list.push_back(j); }
-      std::sort(list.begin(), list.end());
-      Kp[size_t(j)] = int64_t(Ki.size());
-      for (int32_t ni : list) { Ki.push_back(ni); Kx.push_back(acc[size_t(ni)]); }
-      maxdiag = std::max(maxdiag, acc[size_t(j)]);
-    }
-    Kp[size_t(m)] = int64_t(Ki.size());
-  }
+  const double maxdiag = assemble_K(m, rowptr, col, val, H.perm, H.pinv, H, Kp, Ki, Kx);
+  if (mp) { mp->perm0 = H.perm; mp->pinv0 = H.pinv; }
   H.eps = (eps_reg > 0 ? eps_reg : 1e-12) * (maxdiag > 0 ? maxdiag : 1.0);
   for (int32_t j = 0; j < m; ++j) Kx[size_t(Kp[size_t(j)])] += H.eps;  // first entry is the diagonal
 
@@ -225,47 +433,20 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
 
   // ---------------------------------------------------------------- numeric, left-looking
   const int64_t nnzL = Cp[size_t(m)];
-  std::vector<double> Cx(size_t(nnzL), 0.0);
-  std::vector<double> Dn(size_t(m), 0.0);
+  std::vector<double> Cx, Dn;
   {
-    std::vector<double> w(size_t(m), 0.0);
-    std::vector<int64_t> nxt(size_t(m), 0);        // next unused entry of column k
-    std::vector<int32_t> head(size_t(m), -1), link(size_t(m), -1);  // columns waiting on row j
-    for (int32_t j = 0; j < m; ++j) {
-      for (int64_t p = Kp[size_t(j)]; p < Kp[size_t(j) + 1]; ++p) w[size_t(Ki[size_t(p)])] = Kx[size_t(p)];
-      int32_t k = head[size_t(j)];
-      while (k >= 0) {
-        const int32_t knext = link[size_t(k)];
-        const int64_t p0 = nxt[size_t(k)], pend = Cp[size_t(k) + 1];
-        const double f = Cx[size_t(p0)] * Dn[size_t(k)];  // L(j,k) D(k)
-        for (int64_t p = p0; p < pend; ++p) w[size_t(Ci[size_t(p)])] -= Cx[size_t(p)] * f;
-        nxt[size_t(k)] = p0 + 1;
-        if (p0 + 1 < pend) {
-          const int32_t r = Ci[size_t(p0 + 1)];
-          link[size_t(k)] = head[size_t(r)];
-          head[size_t(r)] = k;
-        }
-        k = knext;
-      }
-      const double dj = w[size_t(j)];
-      w[size_t(j)] = 0.0;
-      if (!(dj > 0.0) || !std::isfinite(dj)) {
-        err = "non-positive pivot in LDL^T of eps*I + A A^* at row " + std::to_string(j);
-        return STROM_E_FACTOR;
-      }
-      Dn[size_t(j)] = dj;
-      for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
-        const int32_t i = Ci[size_t(p)];
-        Cx[size_t(p)] = w[size_t(i)] / dj;
-        w[size_t(i)] = 0.0;
-      }
-      if (Cp[size_t(j)] < Cp[size_t(j) + 1]) {
-        nxt[size_t(j)] = Cp[size_t(j)];
-        const int32_t r = Ci[size_t(Cp[size_t(j)])];
-        link[size_t(j)] = head[size_t(r)];
-        head[size_t(r)] = j;
-      }
-    }
+    const strom_status fst = numeric_factor(m, Kp, Ki, Kx, Cp, Ci, H.task_r0, H.task_r1, Cx, Dn, err);
+    if (fst != STROM_OK) return fst;
+  }
+  if (mp) { mp->Cp0 = Cp; mp->Ci0 = Ci; mp->tr0 = H.task_r0; mp->tr1 = H.task_r1; }
+  // where each factor value and pivot of the final order comes from (tracked through relabeling)
+  std::vector<int64_t> xsrc;
+  std::vector<int32_t> dsrc;
+  if (mp) {
+    xsrc.resize(size_t(nnzL));
+    std::iota(xsrc.begin(), xsrc.end(), int64_t(0));
+    dsrc.resize(size_t(m));
+    std::iota(dsrc.begin(), dsrc.end(), 0);
   }
   H.nnzL = nnzL;
   Kp.clear(); Ki.clear(); Kx.clear();
@@ -409,6 +590,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     std::vector<int64_t> Cp2(size_t(m) + 1, 0);
     std::vector<int32_t> Ci2(static_cast<size_t>(nnzL));
     std::vector<double> Cx2(static_cast<size_t>(nnzL));
+    std::vector<int64_t> xs2(xsrc.size());
     for (int32_t j = 0; j < m; ++j) Cp2[size_t(np[size_t(j)]) + 1] = Cp[size_t(j) + 1] - Cp[size_t(j)];
     for (int32_t j = 0; j < m; ++j) Cp2[size_t(j) + 1] += Cp2[size_t(j)];
     for (int32_t j = 0; j < m; ++j) {
@@ -416,11 +598,13 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
       for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p, ++q) {
         Ci2[size_t(q)] = np[size_t(Ci[size_t(p)])];
         Cx2[size_t(q)] = Cx[size_t(p)];
+        if (mp) xs2[size_t(q)] = xsrc[size_t(p)];
       }
     }
     Cp.swap(Cp2);
     Ci.swap(Ci2);
     Cx.swap(Cx2);
+    xsrc.swap(xs2);
     auto permute = [&](auto &v) {
       auto w = v;
       for (int32_t i = 0; i < m; ++i) w[size_t(np[size_t(i)])] = v[size_t(i)];
@@ -428,6 +612,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     };
     permute(H.perm);
     permute(Dn);
+    if (mp) permute(dsrc);
     permute(rphase);
     permute(rcomp);
     permute(rcsize);
@@ -578,6 +763,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   H.Lci.resize(size_t(nnzL)); H.Lv.resize(size_t(nnzL));
   H.Uci.resize(size_t(nnzL)); H.Uv.resize(size_t(nnzL));
   {
+    std::vector<int64_t> lsrc(mp ? size_t(nnzL) : 0), usrc(mp ? size_t(nnzL) : 0);
     std::vector<int64_t> fl(H.Lrp.begin(), H.Lrp.end() - 1), fu(H.Urp.begin(), H.Urp.end() - 1);
     for (int32_t j = 0; j < m; ++j)
       for (int64_t p = Cp[size_t(j)]; p < Cp[size_t(j) + 1]; ++p) {
@@ -585,19 +771,32 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
         const int64_t ql = fl[size_t(ni)]++, qu = fu[size_t(nj)]++;
         H.Lci[size_t(ql)] = nj; H.Lv[size_t(ql)] = Cx[size_t(p)];
         H.Uci[size_t(qu)] = ni; H.Uv[size_t(qu)] = Cx[size_t(p)];
+        if (mp) { lsrc[size_t(ql)] = xsrc[size_t(p)]; usrc[size_t(qu)] = xsrc[size_t(p)]; }
       }
-    auto sort_rows = [](std::vector<int64_t> &rp, std::vector<int32_t> &ci, std::vector<double> &v, int32_t mm) {
-      std::vector<std::pair<int32_t, double>> tmp;
+    // rows by ascending column (the column indices of a row are distinct); sources follow
+    auto sort_rows = [&](std::vector<int64_t> &rp, std::vector<int32_t> &ci, std::vector<double> &v,
+                         std::vector<int64_t> &src, int32_t mm) {
+      std::vector<std::pair<int32_t, int64_t>> tmp;
+      std::vector<double> vv;
       for (int32_t i = 0; i < mm; ++i) {
         tmp.clear();
-        for (int64_t p = rp[size_t(i)]; p < rp[size_t(i) + 1]; ++p) tmp.emplace_back(ci[size_t(p)], v[size_t(p)]);
+        vv.clear();
+        for (int64_t p = rp[size_t(i)]; p < rp[size_t(i) + 1]; ++p) tmp.emplace_back(ci[size_t(p)], p);
         std::sort(tmp.begin(), tmp.end());
+        for (auto &e : tmp) vv.push_back(v[size_t(e.second)]);
+        std::vector<int64_t> ss;
+        if (mp) for (auto &e : tmp) ss.push_back(src[size_t(e.second)]);
         int64_t q = rp[size_t(i)];
-        for (auto &e : tmp) { ci[size_t(q)] = e.first; v[size_t(q)] = e.second; ++q; }
+        for (size_t k = 0; k < tmp.size(); ++k, ++q) {
+          ci[size_t(q)] = tmp[k].first;
+          v[size_t(q)] = vv[k];
+          if (mp) src[size_t(q)] = ss[k];
+        }
       }
     };
-    sort_rows(H.Lrp, H.Lci, H.Lv, m);
-    sort_rows(H.Urp, H.Uci, H.Uv, m);
+    sort_rows(H.Lrp, H.Lci, H.Lv, lsrc, m);
+    sort_rows(H.Urp, H.Uci, H.Uv, usrc, m);
+    if (mp) { mp->lv_src.swap(lsrc); mp->uv_src.swap(usrc); mp->d_src = dsrc; }
   }
   for (int32_t i = 0; i < m; ++i)  // relabeling kept L lower triangular
     for (int64_t p = H.Lrp[size_t(i)]; p < H.Lrp[size_t(i) + 1]; ++p)
@@ -640,21 +839,13 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
         int64_t io = -1;
         if (cn > 1) {
           nns += cn;
-          std::vector<double> blk(size_t(cn) * cn, 0.0), inv(size_t(cn) * cn, 0.0);
           for (int32_t i = c0; i < c1; ++i)
             for (int64_t p = H.Lrp[size_t(i)]; p < H.Lrp[size_t(i) + 1]; ++p) {
               const int32_t j = H.Lci[size_t(p)];
-              if (j >= c0) blk[size_t(i - c0) * cn + size_t(j - c0)] = H.Lv[size_t(p)];
-              else if (j >= a) { err = "internal: dependency between components of a phase"; return STROM_E_FACTOR; }
+              if (j < c0 && j >= a) { err = "internal: dependency between components of a phase"; return STROM_E_FACTOR; }
             }
-          for (int32_t c = 0; c < cn; ++c) {  // inverse of the unit lower-triangular block
-            inv[size_t(c) * cn + size_t(c)] = 1.0;
-            for (int32_t i = c + 1; i < cn; ++i) {
-              double sacc = 0.0;
-              for (int32_t k = c; k < i; ++k) sacc -= blk[size_t(i) * cn + size_t(k)] * inv[size_t(k) * cn + size_t(c)];
-              inv[size_t(i) * cn + size_t(c)] = sacc;
-            }
-          }
+          std::vector<double> blk, inv;
+          component_inverse(H, c0, c1, blk, inv);
           io = int64_t(H.invR.size());
           for (int32_t i = 0; i < cn; ++i)
             for (int32_t j = 0; j <= i; ++j) H.invR.push_back(inv[size_t(i) * cn + size_t(j)]);
@@ -726,6 +917,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     for (int64_t p = H.seg_pb[sg]; p < H.seg_pe[sg]; ++p) {
       H.push_ci.push_back(H.Lci[size_t(p)]);
       H.push_v.push_back(H.Lv[size_t(p)]);
+      if (mp) mp->push_src.push_back(p);
     }
     H.push_off.push_back(int64_t(H.push_ci.size()));
   }
@@ -788,6 +980,10 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
     const int32_t T = kSolveThreads;
     // Lays out the entries of nrows rows (row r's entries contiguous, the last one flagged) as
     // the stream of one phase (or task) of the given kind.
+    // value codes of the stream entries (see NumericMaps): factor entry p of L (p) or of L^T
+    // (nnzL + p), packed inverse entry r by rows (2 nnzL + r) or by columns (2 nnzL + ninv + r)
+    const int64_t c_uv = nnzL, c_ir = 2 * nnzL, c_ic = 2 * nnzL + int64_t(H.invR.size());
+    std::vector<int64_t> esrc;  // code of each entry of the current phase (with mp)
     auto emit = [&](const std::vector<std::pair<int32_t, double>> &ent, const std::vector<int32_t> &erow,
                     const std::vector<char> &efirst, int32_t nrows, int kind, int32_t pad_idx) {
       const int64_t E = int64_t(ent.size());
@@ -801,6 +997,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
       const int64_t off = int64_t(V.size());
       V.resize(size_t(off + K * Tp), 0.0);
       X.resize(size_t(off + K * Tp), pad_idx);
+      if (mp) mp->s_src[size_t(kind)].resize(size_t(off + K * Tp), -1);
       for (int32_t t = 0; t < Tp; ++t) {
         const int64_t e0 = int64_t(t) * K;
         if (e0 < E) ra[size_t(t)] = erow[size_t(e0)] | (efirst[size_t(e0)] ? kStartFlag : 0);
@@ -815,6 +1012,7 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
           if (e >= E) break;  // later slices hold no more entries
           vd[t] = ent[size_t(e)].second;
           xd[t] = ent[size_t(e)].first;
+          if (mp) mp->s_src[size_t(kind)][size_t(off + k * Tp + t)] = esrc[size_t(e)];
         }
       }
       H.s_off[size_t(kind)].push_back(off);
@@ -837,24 +1035,35 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
       std::vector<std::pair<int32_t, double>> ent;  // the whole phase, rows in order
       std::vector<int32_t> erow;                    // phase-relative row of each entry
       std::vector<char> efirst;                     // entry starts its row
+      esrc.clear();
+      auto put = [&](int32_t idx, double v, int64_t code) {
+        ent.emplace_back(idx, v);
+        if (mp) esrc.push_back(code);
+      };
       for (int32_t i = rbeg; i < rend; ++i) {
         const size_t e0 = ent.size();
         if (kind == 0) {
           for (int64_t q = H.sptr[size_t(i)]; q < H.sptr[size_t(i) + 1]; ++q)
-            ent.emplace_back(inl ? (r1 - r0) + int32_t(q - H.task_pin[size_t(t)]) : (int32_t(q) | kPartFlag), 1.0);
-          for (int64_t p = H.Lin[size_t(i)]; p < H.Lend[size_t(i)]; ++p) ent.emplace_back(fidx(H.Lci[size_t(p)]), H.Lv[size_t(p)]);
+            put(inl ? (r1 - r0) + int32_t(q - H.task_pin[size_t(t)]) : (int32_t(q) | kPartFlag), 1.0, -2);
+          for (int64_t p = H.Lin[size_t(i)]; p < H.Lend[size_t(i)]; ++p) put(fidx(H.Lci[size_t(p)]), H.Lv[size_t(p)], p);
         } else if (kind == 2) {
-          for (int64_t p = H.Ubeg[size_t(i)]; p < H.Urp[size_t(i) + 1]; ++p) ent.emplace_back(bidx(H.Uci[size_t(p)]), H.Uv[size_t(p)]);
+          for (int64_t p = H.Ubeg[size_t(i)]; p < H.Urp[size_t(i) + 1]; ++p)
+            put(bidx(H.Uci[size_t(p)]), H.Uv[size_t(p)], c_uv + p);
         } else {
           const int32_t cs = H.rcs[size_t(i)], cn = H.rce[size_t(i)] - cs, kk = i - cs;
           const int32_t base = cs - H.ph_a[size_t(ph)];
           if (kind == 1)
-            for (int32_t j = 0; j <= kk; ++j) ent.emplace_back(base + j, H.invR[size_t(H.rio[size_t(i)] + int64_t(kk) * (kk + 1) / 2 + j)]);
+            for (int32_t j = 0; j <= kk; ++j) {
+              const int64_t r = H.rio[size_t(i)] + int64_t(kk) * (kk + 1) / 2 + j;
+              put(base + j, H.invR[size_t(r)], c_ir + r);
+            }
           else
-            for (int32_t e = 0; e < cn - kk; ++e)
-              ent.emplace_back(base + kk + e, H.invC[size_t(H.rio[size_t(i)] + int64_t(kk) * cn - int64_t(kk) * (kk - 1) / 2 + e)]);
+            for (int32_t e = 0; e < cn - kk; ++e) {
+              const int64_t r = H.rio[size_t(i)] + int64_t(kk) * cn - int64_t(kk) * (kk - 1) / 2 + e;
+              put(base + kk + e, H.invC[size_t(r)], c_ic + r);
+            }
         }
-        if (ent.size() == e0) ent.emplace_back(pad_idx, 0.0);
+        if (ent.size() == e0) put(pad_idx, 0.0, -1);
         ent.back().first |= kLastFlag;
         for (size_t e = e0; e < ent.size(); ++e) {
           erow.push_back(i - rbeg);
@@ -879,12 +1088,18 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
       std::vector<int32_t> erow;
       std::vector<char> efirst;
       const int32_t nseg = H.tsptr[size_t(t) + 1] - H.tsptr[size_t(t)];
+      esrc.clear();
       for (int32_t r = 0; r < nseg; ++r) {
         const int32_t sg = H.tseg[size_t(H.tsptr[size_t(t)] + r)];
         const size_t e0 = ent.size();
-        for (int64_t e = H.push_off[size_t(sg)]; e < H.push_off[size_t(sg) + 1]; ++e)
+        for (int64_t e = H.push_off[size_t(sg)]; e < H.push_off[size_t(sg) + 1]; ++e) {
           ent.emplace_back(inl ? H.push_ci[size_t(e)] - r0 : H.push_ci[size_t(e)], H.push_v[size_t(e)]);
-        if (ent.size() == e0) ent.emplace_back(inl ? 0 : r0, 0.0);
+          if (mp) esrc.push_back(mp->push_src[size_t(e)]);
+        }
+        if (ent.size() == e0) {
+          ent.emplace_back(inl ? 0 : r0, 0.0);
+          if (mp) esrc.push_back(-1);
+        }
         ent.back().first |= kLastFlag;
         for (size_t e = e0; e < ent.size(); ++e) {
           erow.push_back(r);
@@ -917,6 +1132,247 @@ strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, 
   group_by(fdepth, H.fwd_order, H.fwd_gptr);
   group_by(bdepth, H.bwd_order, H.bwd_gptr);
   (void)task_nph;
+  return STROM_OK;
+}
+
+// The numbers of an analysis for new values of A on the pattern the maps were made for: A^T,
+// K and its factor in the same order with the same arithmetic, then every value derived from
+// the factor through the maps.  H holds the cached analysis on entry.
+strom_status refresh_numeric(const NumericMaps &mp, int32_t m, const int64_t *rowptr, const int32_t *col,
+                             const double *val, double eps_reg, HostAnalysis &H, std::string &err) {
+  const int64_t nnz = rowptr[m];
+  for (int64_t p = 0; p < nnz; ++p)
+    if (!std::isfinite(val[p])) { err = "non-finite value in A"; return STROM_E_INVAL; }
+  for (size_t q = 0; q < mp.at_src.size(); ++q) H.Atv[q] = val[mp.at_src[q]];
+  std::vector<int64_t> Kp;
+  std::vector<int32_t> Ki;
+  std::vector<double> Kx;
+  const double maxdiag = assemble_K(m, rowptr, col, val, mp.perm0, mp.pinv0, H, Kp, Ki, Kx);
+  H.eps = (eps_reg > 0 ? eps_reg : 1e-12) * (maxdiag > 0 ? maxdiag : 1.0);
+  for (int32_t j = 0; j < m; ++j) Kx[size_t(Kp[size_t(j)])] += H.eps;
+  std::vector<double> Cx, Dn;
+  const strom_status fst = numeric_factor(m, Kp, Ki, Kx, mp.Cp0, mp.Ci0, mp.tr0, mp.tr1, Cx, Dn, err);
+  if (fst != STROM_OK) return fst;
+  for (size_t p = 0; p < mp.lv_src.size(); ++p) H.Lv[p] = Cx[size_t(mp.lv_src[p])];
+  for (size_t p = 0; p < mp.uv_src.size(); ++p) H.Uv[p] = Cx[size_t(mp.uv_src[p])];
+  for (int32_t i = 0; i < m; ++i) H.D[size_t(i)] = Dn[size_t(mp.d_src[size_t(i)])];
+  std::vector<double> blk, inv;
+  for (int32_t i = 0; i < m; ++i) {  // components of two or more rows, at their first row
+    if (H.rcs[size_t(i)] != i || H.rio[size_t(i)] < 0) continue;
+    const int32_t c0 = i, c1 = H.rce[size_t(i)], cn = c1 - c0;
+    component_inverse(H, c0, c1, blk, inv);
+    int64_t o = H.rio[size_t(i)];
+    for (int32_t r = 0; r < cn; ++r)
+      for (int32_t c = 0; c <= r; ++c) H.invR[size_t(o++)] = inv[size_t(r) * cn + size_t(c)];
+    o = H.rio[size_t(i)];
+    for (int32_t c = 0; c < cn; ++c)
+      for (int32_t r = c; r < cn; ++r) H.invC[size_t(o++)] = inv[size_t(r) * cn + size_t(c)];
+  }
+  for (size_t e = 0; e < mp.push_src.size(); ++e) H.push_v[e] = H.Lv[size_t(mp.push_src[e])];
+  const int64_t nnzL = int64_t(H.Lv.size()), ninv = int64_t(H.invR.size());
+  for (int k = 0; k < kStreamKinds; ++k) {
+    const std::vector<int64_t> &src = mp.s_src[size_t(k)];
+    std::vector<double> &V = H.sval[size_t(k)];
+    for (size_t e = 0; e < src.size(); ++e) {
+      const int64_t c = src[e];
+      V[e] = c == -1 ? 0.0 : c == -2 ? 1.0 : c < nnzL ? H.Lv[size_t(c)] : c < 2 * nnzL ? H.Uv[size_t(c - nnzL)]
+             : c < 2 * nnzL + ninv ? H.invR[size_t(c - 2 * nnzL)] : H.invC[size_t(c - 2 * nnzL - ninv)];
+    }
+  }
+  return STROM_OK;
+}
+
+// Cache of analyses by sparsity pattern and schedule options (LRU, bounded by memory): a hit
+// copies the cached analysis and refreshes its numbers.  A pattern is cached on its second
+// analysis (recording the maps costs about half an analysis), so one-off instances pay
+// nothing.  STROM_SETUP_CACHE=0 turns it off.
+struct CacheEntry {
+  std::vector<int32_t> bsize;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  double eps_reg = 0;
+  int split_mode = 0, block_rows = 0;
+  std::string env;  // schedule knobs read from the environment by the analysis
+  HostAnalysis H;
+  NumericMaps maps;
+  size_t bytes = 0;
+};
+
+struct SetupCache {
+  std::mutex mu;
+  std::list<std::shared_ptr<const CacheEntry>> lru;  // most recent first
+  size_t bytes = 0;
+  std::vector<uint64_t> seen;  // keys of patterns analysed once (cached on their second analysis)
+};
+
+SetupCache &setup_cache() {
+  static SetupCache c;
+  return c;
+}
+
+constexpr size_t kCacheBytes = size_t(6) << 30;
+
+template <class T>
+size_t vbytes(const std::vector<T> &v) { return v.size() * sizeof(T); }
+
+size_t entry_bytes(const CacheEntry &e) {
+  const HostAnalysis &H = e.H;
+  size_t b = vbytes(e.rowptr) + vbytes(e.col) + vbytes(H.Atci) + vbytes(H.Atv) + vbytes(H.Lci) + vbytes(H.Lv) +
+             vbytes(H.Uci) + vbytes(H.Uv) + vbytes(H.invR) + vbytes(H.invC) + vbytes(H.push_ci) + vbytes(H.push_v) +
+             vbytes(e.maps.at_src) + vbytes(e.maps.Ci0) + vbytes(e.maps.lv_src) + vbytes(e.maps.uv_src) +
+             vbytes(e.maps.push_src);
+  for (int k = 0; k < kStreamKinds; ++k)
+    b += vbytes(H.sval[size_t(k)]) + vbytes(H.sidx[size_t(k)]) + vbytes(e.maps.s_src[size_t(k)]);
+  return b;
+}
+
+std::string env_knobs() {
+  std::string s;
+  for (const char *name : {"STROM_STAGE_ROWS", "STROM_TASK_SPLIT", "STROM_BLOCK_ROWS"}) {
+    const char *v = std::getenv(name);
+    s += std::string(name) + "=" + (v ? v : "") + ";";
+  }
+  return s;
+}
+
+// H = src with the large arrays copied by parallel threads (first touches of fresh pages
+// dominate a single-threaded copy of a few hundred MB).  Every field of HostAnalysis is listed
+// here (the cache test compares them all).
+void copy_analysis(const HostAnalysis &src, HostAnalysis &H) {
+  std::vector<std::function<void()>> jobs;
+  HostAnalysis &d = H;
+  auto add = [&](auto member) { jobs.emplace_back([&src, &d, member] { d.*member = src.*member; }); };
+  add(&HostAnalysis::Atci); add(&HostAnalysis::Atv); add(&HostAnalysis::Lci); add(&HostAnalysis::Lv);
+  add(&HostAnalysis::Uci); add(&HostAnalysis::Uv); add(&HostAnalysis::invR); add(&HostAnalysis::invC);
+  add(&HostAnalysis::push_ci); add(&HostAnalysis::push_v);
+  for (int k = 0; k < kStreamKinds; ++k) {
+    jobs.emplace_back([&src, &d, k] { d.sval[k] = src.sval[k]; });
+    jobs.emplace_back([&src, &d, k] { d.sidx[k] = src.sidx[k]; });
+  }
+  // the small arrays and scalars: everything else
+  HostAnalysis rest;
+  {
+    HostAnalysis &r = rest;
+    r.m = src.m; r.nsvec = src.nsvec; r.nblocks = src.nblocks; r.bsize = src.bsize; r.boff = src.boff;
+    r.Atrp = src.Atrp; r.perm = src.perm; r.pinv = src.pinv; r.eps = src.eps; r.Lrp = src.Lrp; r.Urp = src.Urp;
+    r.D = src.D; r.task_r0 = src.task_r0; r.task_r1 = src.task_r1; r.task_ph0 = src.task_ph0;
+    r.task_ph1 = src.task_ph1; r.ph_a = src.ph_a; r.ph_b = src.ph_b; r.ph_nns = src.ph_nns; r.ph_gf = src.ph_gf;
+    r.ph_gb = src.ph_gb; r.rcs = src.rcs; r.rce = src.rce; r.rio = src.rio; r.Lin = src.Lin; r.Lend = src.Lend;
+    r.Ubeg = src.Ubeg; r.sptr = src.sptr; r.seg_pb = src.seg_pb; r.seg_pe = src.seg_pe; r.tsptr = src.tsptr;
+    r.tseg = src.tseg; r.task_sg = src.task_sg; r.push_off = src.push_off;
+    for (int k = 0; k < kStreamKinds; ++k) {
+      r.s_off[k] = src.s_off[k]; r.s_K[k] = src.s_K[k]; r.s_T[k] = src.s_T[k]; r.s_ra[k] = src.s_ra[k];
+    }
+    r.task_pin = src.task_pin; r.task_xoff = src.task_xoff; r.task_xrow = src.task_xrow; r.task_inl = src.task_inl;
+    r.max_task_stage = src.max_task_stage; r.fwd_order = src.fwd_order; r.fwd_gptr = src.fwd_gptr;
+    r.bwd_order = src.bwd_order; r.bwd_gptr = src.bwd_gptr; r.max_task_rows = src.max_task_rows;
+    r.max_phase_nns = src.max_phase_nns; r.nnzL = src.nnzL;
+  }
+  H = std::move(rest);
+  std::atomic<size_t> next(0);
+  auto worker = [&] {
+    for (size_t q; (q = next.fetch_add(1)) < jobs.size();) jobs[q]();
+  };
+  const size_t nth = std::min<size_t>(jobs.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  std::vector<std::thread> pool;
+  for (size_t i = 1; i < nth; ++i) pool.emplace_back(worker);
+  worker();
+  for (auto &th : pool) th.join();
+}
+
+bool cache_on() {
+  const char *v = std::getenv("STROM_SETUP_CACHE");
+  return !(v && v[0] == '0');
+}
+
+// FNV-1a over the pattern, the options and the schedule knobs.
+uint64_t pattern_hash(int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *rowptr, const int32_t *col,
+                      double eps_reg, int split_mode, int block_rows, const std::string &env) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  };
+  mix(&nblocks, sizeof nblocks);
+  mix(bsize, sizeof(int32_t) * size_t(nblocks));
+  mix(&m, sizeof m);
+  mix(rowptr, sizeof(int64_t) * size_t(m + 1));
+  mix(col, sizeof(int32_t) * size_t(rowptr[m]));
+  mix(&eps_reg, sizeof eps_reg);
+  mix(&split_mode, sizeof split_mode);
+  mix(&block_rows, sizeof block_rows);
+  mix(env.data(), env.size());
+  return h;
+}
+
+bool same_key(const CacheEntry &e, int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *rowptr,
+              const int32_t *col, double eps_reg, int split_mode, int block_rows, const std::string &env) {
+  if (int32_t(e.bsize.size()) != nblocks || int32_t(e.rowptr.size()) != m + 1 || e.eps_reg != eps_reg ||
+      e.split_mode != split_mode || e.block_rows != block_rows || e.env != env)
+    return false;
+  if (std::memcmp(e.bsize.data(), bsize, sizeof(int32_t) * size_t(nblocks)) != 0) return false;
+  if (std::memcmp(e.rowptr.data(), rowptr, sizeof(int64_t) * size_t(m + 1)) != 0) return false;
+  return int64_t(e.col.size()) == rowptr[m] && std::memcmp(e.col.data(), col, sizeof(int32_t) * e.col.size()) == 0;
+}
+}  // namespace
+
+strom_status analyze_instance(int32_t nblocks, const int32_t *bsize, int32_t m, const int64_t *rowptr,
+                              const int32_t *col, const double *val, double eps_reg, HostAnalysis &H,
+                              std::string &err, int split_mode, int block_rows) {
+  if (!cache_on() || nblocks <= 0 || !bsize || m <= 0 || !rowptr || !col || !val || m >= kPartFlag || rowptr[0] != 0)
+    return analyze_full(nblocks, bsize, m, rowptr, col, val, eps_reg, H, err, split_mode, block_rows, nullptr);
+  const std::string env = env_knobs();
+  SetupCache &C = setup_cache();
+  std::shared_ptr<const CacheEntry> hit;
+  {
+    std::lock_guard<std::mutex> lk(C.mu);
+    for (auto it = C.lru.begin(); it != C.lru.end(); ++it)
+      if (same_key(**it, nblocks, bsize, m, rowptr, col, eps_reg, split_mode, block_rows, env)) {
+        hit = *it;
+        C.lru.splice(C.lru.begin(), C.lru, it);
+        break;
+      }
+  }
+  if (hit) {
+    copy_analysis(hit->H, H);
+    return refresh_numeric(hit->maps, m, rowptr, col, val, eps_reg, H, err);
+  }
+  // a pattern's first analysis runs plain; its second records the maps and fills the cache
+  const uint64_t key = pattern_hash(nblocks, bsize, m, rowptr, col, eps_reg, split_mode, block_rows, env);
+  {
+    std::lock_guard<std::mutex> lk(C.mu);
+    if (std::find(C.seen.begin(), C.seen.end(), key) == C.seen.end()) {
+      C.seen.push_back(key);
+      if (C.seen.size() > 4096) C.seen.erase(C.seen.begin());
+      hit = nullptr;
+    } else {
+      hit = std::make_shared<const CacheEntry>();  // marker: seen before
+    }
+  }
+  if (!hit) return analyze_full(nblocks, bsize, m, rowptr, col, val, eps_reg, H, err, split_mode, block_rows, nullptr);
+  auto e = std::make_shared<CacheEntry>();
+  const strom_status rc =
+      analyze_full(nblocks, bsize, m, rowptr, col, val, eps_reg, H, err, split_mode, block_rows, &e->maps);
+  if (rc != STROM_OK) return rc;
+  e->bsize.assign(bsize, bsize + nblocks);
+  e->rowptr.assign(rowptr, rowptr + m + 1);
+  e->col.assign(col, col + rowptr[m]);
+  e->eps_reg = eps_reg;
+  e->split_mode = split_mode;
+  e->block_rows = block_rows;
+  e->env = env;
+  copy_analysis(H, e->H);
+  e->bytes = entry_bytes(*e);
+  if (e->bytes > kCacheBytes / 2) return STROM_OK;  // too large to keep
+  std::lock_guard<std::mutex> lk(C.mu);
+  for (auto &x : C.lru)
+    if (same_key(*x, nblocks, bsize, m, rowptr, col, eps_reg, split_mode, block_rows, env)) return STROM_OK;
+  C.lru.push_front(e);
+  C.bytes += e->bytes;
+  while (C.bytes > kCacheBytes && C.lru.size() > 1) {
+    C.bytes -= C.lru.back()->bytes;
+    C.lru.pop_back();
+  }
   return STROM_OK;
 }
 
