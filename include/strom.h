@@ -135,7 +135,10 @@ strom_status strom_ctx_destroy(strom_ctx *ctx);
  * then the rows coupling two cliques by nested dissection over the chain, a consequence of the
  * chain-like sparsity of Def. 1), factors eps*I + A A^* = P L D L^T P^T in FP64 on the host
  * (the paper's Cholesky-with-pre-permutation equation; E_FACTOR on a non-positive pivot),
- * uploads everything and sets the iterate to (X0, 0, S0).  opts may be NULL (defaults). */
+ * uploads everything and sets the iterate to (X0, 0, S0).  opts may be NULL (defaults).
+ * Blocks up to n = 114 are projected by one workgroup each (in FP64, or FP32 before the polish
+ * switch); larger ones, up to n = 512 (E_INVAL beyond), by the multi-workgroup block Jacobi,
+ * always in FP64, with about 16 n^2 bytes of device memory each. */
 strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *problem, const strom_opts *opts,
                              strom_sdp **out);
 strom_status strom_sdp_destroy(strom_sdp *sdp);
@@ -174,18 +177,21 @@ strom_status strom_sdp_sizes(strom_sdp *sdp, int64_t *n_svec, int32_t *m, int64_
  * projection of Sec. "GPU Speedup": eigendecomposition, negative eigenvalues set to zero,
  * reconstruction).  Block k is n_dev[k] x n_dev[k], column-major, starting at element
  * offset_dev[k] of in_dev / out_dev; in and out may alias.  n_dev, offset_dev, in_dev and
- * out_dev are device pointers; max_n (host) bounds every n_dev[k]; one block and its
- * eigenvectors must fit the LDS of one workgroup (160 KiB on gfx950: max_n <= 114 for F64,
- * <= 125 for F32 -- the eigenvectors are accumulated in double in both), else E_INVAL.  A block with n_dev[k] <= 0 or > max_n makes the call
- * return E_INVAL (other blocks are still written).  dtype selects double or float data.
- * Only the upper triangle of each input block is read; the output is exactly symmetric. */
+ * out_dev are device pointers; max_n (host) bounds every n_dev[k], 1 <= max_n <= 512.  When
+ * one block and its eigenvectors fit the LDS of one workgroup (160 KiB on gfx950: max_n <= 114
+ * in F64, about 160 in F32) every block is projected by one workgroup; beyond that (F64 only,
+ * else E_INVAL) by the multi-workgroup block Jacobi, every block padded to max_n's size, with
+ * temporary device memory of about 16 max_n^2 bytes per block.  A block with n_dev[k] <= 0 or
+ * > max_n makes the call return E_INVAL (other blocks are still written).  dtype selects double
+ * or float data.  The one-workgroup path reads only the upper triangle of each input block, the
+ * other both; the output is exactly symmetric. */
 strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblocks, int32_t max_n,
                                        const int32_t *n_dev, const int64_t *offset_dev,
                                        const void *in_dev, void *out_dev, strom_dtype dtype,
                                        void *hip_stream);
 
-/* Eigendecomposition of nblocks dense symmetric blocks (layout and limits as
- * strom_project_psd_batched; the same Jacobi eigensolver).  Eigenvalues of block k, in
+/* Eigendecomposition of nblocks dense symmetric blocks (layout, limits and eigensolvers as
+ * strom_project_psd_batched).  Eigenvalues of block k, in
  * ascending order (ties in index order), are written at element offset woff_dev[k] of w_dev;
  * with v_dev != NULL the eigenvectors are written as the columns of an n x n column-major block
  * at offset_dev[k] of v_dev (column j for eigenvalue j; v_dev may alias in_dev).  With
@@ -241,7 +247,8 @@ strom_status strom_extract(strom_sdp *sdp, int32_t nlist, const int32_t *blocks,
  * instances by up to n_iter iterations and retires each one, unchanged from then on, at the
  * round where it converges, reaches maxiter or diverges, exactly as strom_admm_step would.
  * instances: host array of count handles (copied).  infos (host, nullable): count entries,
- * filled as strom_admm_step fills its info.  Synchronizes once per round. */
+ * filled as strom_admm_step fills its info.  Synchronizes once per round.  Instances with
+ * blocks beyond one workgroup's LDS (see strom_sdp_setup) are not batched: E_INVAL. */
 typedef struct strom_batch strom_batch;
 strom_status strom_batch_create(strom_ctx *ctx, int32_t count, strom_sdp *const *instances, strom_batch **out);
 strom_status strom_batch_step(strom_batch *batch, int32_t n_iter, strom_info *infos);

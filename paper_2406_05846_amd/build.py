@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libstrom.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["kernels.hip", "project.hip", "noalloc.hip", "api.cpp", "setup.cpp", "serve.cpp", "gen.cpp"]
+SOURCES = ["kernels.hip", "project.hip", "big.hip", "noalloc.hip", "api.cpp", "setup.cpp", "serve.cpp", "gen.cpp"]
 ARCH = "gfx950"
 # Packed FP32 VALU forms are disabled for all device code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function", "-Wno-unused-value",

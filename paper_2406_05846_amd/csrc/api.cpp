@@ -99,6 +99,7 @@ struct strom_sdp {
   strom::dev::SolveArgs sa{};
   strom::dev::SolveSchedule sch;
   std::vector<int> cls_n, cls_off, cls_cnt;  // projection launches, one per block size
+  strom::dev::BigArgs big;                   // blocks beyond one workgroup's LDS (big.count may be 0)
   double normb = 0, normC = 0;
   int64_t iters = 0;
   strom_solve_state state = STROM_RUNNING;
@@ -183,6 +184,10 @@ static size_t proj_need(int n, bool f32) {
   return strom::dev::project_lds_bytes(n, f32, strom::dev::project_threads(n));
 }
 
+// Blocks whose FP64 projection fits one workgroup's LDS take the one-workgroup kernel (in FP64 or
+// FP32); larger ones the multi-workgroup block Jacobi of big.hip, always in FP64.
+static bool fits_lds(const strom_ctx *ctx, int n) { return proj_need(n, false) <= ctx->max_lds; }
+
 extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, const strom_opts *opts,
                                         strom_sdp **out) {
   if (!ctx || !P || !out) return fail(STROM_E_INVAL, "NULL argument");
@@ -202,11 +207,14 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   strom_status rc = strom::analyze_instance(P->nblocks, P->block_sizes, P->m, P->A_rowptr, P->A_col, P->A_val,
                                             o.eps_reg, H, err, o.task_split, o.block_rows);
   if (rc != STROM_OK) return fail(rc, err);
-  int32_t max_n = 0;
-  for (int32_t n : H.bsize) max_n = std::max(max_n, n);
-  const bool f32 = o.proj_dtype == STROM_F32;
-  if (proj_need(max_n, false) > ctx->max_lds || (f32 && proj_need(max_n, true) > ctx->max_lds))
-    return fail(STROM_E_INVAL, "block of size " + std::to_string(max_n) + " does not fit the LDS of one workgroup");
+  int32_t max_n = 0, big_max = 0;
+  for (int32_t n : H.bsize) {
+    max_n = std::max(max_n, n);
+    if (!fits_lds(ctx, n)) big_max = std::max(big_max, n);
+  }
+  if (big_max > strom::dev::kBigMaxN)
+    return fail(STROM_E_INVAL, "block of size " + std::to_string(big_max) + " is over the largest supported size " +
+                                   std::to_string(strom::dev::kBigMaxN));
 
   auto *s = new strom_sdp();
   s->ctx = ctx;
@@ -228,10 +236,15 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   // projection launches: one launch over every block (largest first) when they fit the chip
   // in one wave of workgroups, else one launch per block size
   std::map<int, std::vector<int32_t>> by_n;
-  for (int32_t k = 0; k < P->nblocks; ++k) by_n[H.bsize[size_t(k)]].push_back(k);
+  std::vector<int32_t> big_ids;
+  for (int32_t k = 0; k < P->nblocks; ++k) {
+    if (fits_lds(ctx, H.bsize[size_t(k)])) by_n[H.bsize[size_t(k)]].push_back(k);
+    else big_ids.push_back(k);
+  }
+  const int32_t nsmall = P->nblocks - int32_t(big_ids.size());
   std::vector<int32_t> ids;
   for (auto it = by_n.rbegin(); it != by_n.rend(); ++it) {
-    if (P->nblocks > 256 || s->cls_n.empty()) {
+    if (nsmall > 256 || s->cls_n.empty()) {
       s->cls_n.push_back(it->first);
       s->cls_off.push_back(int(ids.size()));
       s->cls_cnt.push_back(0);
@@ -283,6 +296,10 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
     qtot += nb * (nb + (nb & 1));  // eigenvectors n x (n rounded up to even) of the projection
   }
   const size_t oQ = ar.reserve<double>(size_t(qtot)), oQoff = ar.reserve<int64_t>(size_t(P->nblocks));
+  s->big.np = big_max > 0 ? strom::dev::big_padded(big_max) : 0;
+  s->big.count = int32_t(big_ids.size());
+  const size_t oBig = ar.reserve<int32_t>(std::max<size_t>(1, big_ids.size())),
+               oBigW = ar.reserve<double>(big_ids.empty() ? 1 : strom::dev::big_work_doubles(s->big.np, s->big.count));
   s->arena_bytes = ar.bytes;
 
   {
@@ -318,6 +335,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   s->st = reinterpret_cast<DevState *>(base + oSt);
   s->part_rows = PD(oPr); s->part_cols = PD(oPc); s->part_cone = PD(oPk);
   s->Q = PD(oQ); s->qoff = P64(oQoff);
+  s->big.ids = P32(oBig); s->big.boff = s->boff; s->big.bsz = s->bsz; s->big.work = PD(oBigW);
   int32_t *tk = P32(oTk), *ph = P32(oPh);
   auto &sa = s->sa;
   sa.task_r0 = tk; sa.task_r1 = tk + ntask; sa.task_ph0 = tk + 2 * ntask; sa.task_ph1 = tk + 3 * ntask;
@@ -413,6 +431,7 @@ extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, 
   ok &= up(const_cast<int32_t *>(s->sch.bwd_order_dev), H.bwd_order.data(), sizeof(int32_t) * H.bwd_order.size());
   ok &= up(s->boff, H.boff.data(), sizeof(int64_t) * size_t(P->nblocks));
   ok &= up(s->qoff, qoff.data(), sizeof(int64_t) * qoff.size());
+  if (!big_ids.empty()) ok &= up(s->big.ids, big_ids.data(), sizeof(int32_t) * big_ids.size());
   ok &= up(s->bsz, H.bsize.data(), sizeof(int32_t) * size_t(P->nblocks));
   ok &= up(s->blk_ids, ids.data(), sizeof(int32_t) * ids.size());
   DevState st0{};
@@ -463,6 +482,11 @@ hipError_t enqueue_projection(strom_sdp *s, const double *X_in, double *S_out, d
     hipError_t e = strom::dev::launch_project_admm(s->stream, f32, s->cls_n[c], s->cls_cnt[c],
                                                    s->blk_ids + s->cls_off[c], s->boff, s->bsz, X_in, S_out, s->st,
                                                    scale, s->Q, s->qoff, s->q_valid, reorth);
+    if (e != hipSuccess) return e;
+  }
+  if (s->big.count > 0) {
+    hipError_t e = strom::dev::launch_project_big_admm(s->stream, s->big, X_in, S_out, s->st, scale, s->Q, s->qoff,
+                                                       s->q_valid, reorth);
     if (e != hipSuccess) return e;
   }
   s->q_valid = true;
@@ -758,6 +782,41 @@ extern "C" strom_status strom_sdp_sizes(strom_sdp *s, int64_t *n_svec, int32_t *
   return STROM_OK;
 }
 
+namespace {
+// max_n of the dense batched calls: within one workgroup's LDS in either precision, or up to
+// kBigMaxN in FP64 (the multi-workgroup path).
+strom_status check_dense_max_n(const strom_ctx *ctx, int32_t max_n, bool f32) {
+  if (max_n <= 0 || max_n > strom::dev::kBigMaxN)
+    return fail(STROM_E_INVAL, "max_n out of range (1.." + std::to_string(strom::dev::kBigMaxN) + ")");
+  if (f32 && proj_need(max_n, true) > ctx->max_lds)
+    return fail(STROM_E_INVAL, "max_n beyond one workgroup's LDS needs FP64 blocks");
+  return STROM_OK;
+}
+
+// Work memory of a dense multi-workgroup call (every block padded to max_n's size), held until
+// the call returns (the call synchronizes its stream before).
+struct BigDense {
+  strom::dev::BigArgs a;
+  void *mem = nullptr;
+  strom_status init(strom_ctx *ctx, int32_t nblocks, int32_t max_n, const int32_t *nd, const int64_t *od) {
+    a.np = strom::dev::big_padded(max_n);
+    a.count = nblocks;
+    a.nd = nd;
+    a.od = od;
+    a.err = ctx->err_flag;
+    if (hipMalloc(&mem, sizeof(double) * strom::dev::big_work_doubles(a.np, nblocks)) != hipSuccess) {
+      mem = nullptr;
+      return fail(STROM_E_NOMEM, "device memory for the multi-workgroup eigensolver");
+    }
+    a.work = static_cast<double *>(mem);
+    return STROM_OK;
+  }
+  ~BigDense() {
+    if (mem) hipFree(mem);  // hipFree waits for the device
+  }
+};
+}  // namespace
+
 extern "C" strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblocks, int32_t max_n,
                                                   const int32_t *n_dev, const int64_t *offset_dev,
                                                   const void *in_dev, void *out_dev, strom_dtype dtype,
@@ -767,13 +826,20 @@ extern "C" strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblock
   if (nblocks == 0) return STROM_OK;
   const bool f32 = dtype == STROM_F32;
   if (dtype != STROM_F32 && dtype != STROM_F64) return fail(STROM_E_INVAL, "bad dtype");
-  if (max_n <= 0 || proj_need(max_n, f32) > ctx->max_lds)
-    return fail(STROM_E_INVAL, "max_n out of range for the LDS of one workgroup");
+  const strom_status vst = check_dense_max_n(ctx, max_n, f32);
+  if (vst != STROM_OK) return vst;
   std::lock_guard<std::recursive_mutex> dl(device_lock());
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t q = (hipStream_t)hip_stream;
   HIP_TRY(hipMemsetAsync(ctx->err_flag, 0, sizeof(int32_t), q));
-  HIP_TRY(strom::dev::launch_project_dense(q, f32, nblocks, max_n, n_dev, offset_dev, in_dev, out_dev, ctx->err_flag));
+  if (proj_need(max_n, f32) <= ctx->max_lds) {
+    HIP_TRY(strom::dev::launch_project_dense(q, f32, nblocks, max_n, n_dev, offset_dev, in_dev, out_dev, ctx->err_flag));
+  } else {
+    BigDense bd;
+    const strom_status bst = bd.init(ctx, nblocks, max_n, n_dev, offset_dev);
+    if (bst != STROM_OK) return bst;
+    HIP_TRY(strom::dev::launch_project_big_dense(q, bd.a, static_cast<const double *>(in_dev), static_cast<double *>(out_dev)));
+  }
   int32_t flag = 0;
   HIP_TRY(hipMemcpyAsync(&flag, ctx->err_flag, sizeof(int32_t), hipMemcpyDeviceToHost, q));
   HIP_TRY(hipStreamSynchronize(q));
@@ -790,14 +856,22 @@ extern "C" strom_status strom_eig_batched(strom_ctx *ctx, int32_t nblocks, int32
   if (nblocks == 0) return STROM_OK;
   const bool f32 = dtype == STROM_F32;
   if (dtype != STROM_F32 && dtype != STROM_F64) return fail(STROM_E_INVAL, "bad dtype");
-  if (max_n <= 0 || proj_need(max_n, f32) > ctx->max_lds)
-    return fail(STROM_E_INVAL, "max_n out of range for the LDS of one workgroup");
+  const strom_status vst = check_dense_max_n(ctx, max_n, f32);
+  if (vst != STROM_OK) return vst;
   std::lock_guard<std::recursive_mutex> dl(device_lock());
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t q = (hipStream_t)hip_stream;
   HIP_TRY(hipMemsetAsync(ctx->err_flag, 0, sizeof(int32_t), q));
-  HIP_TRY(strom::dev::launch_eig_dense(q, f32, nblocks, max_n, n_dev, offset_dev, in_dev, woff_dev, w_dev, v_dev,
-                                       ctx->err_flag));
+  if (proj_need(max_n, f32) <= ctx->max_lds) {
+    HIP_TRY(strom::dev::launch_eig_dense(q, f32, nblocks, max_n, n_dev, offset_dev, in_dev, woff_dev, w_dev, v_dev,
+                                         ctx->err_flag));
+  } else {
+    BigDense bd;
+    const strom_status bst = bd.init(ctx, nblocks, max_n, n_dev, offset_dev);
+    if (bst != STROM_OK) return bst;
+    HIP_TRY(strom::dev::launch_eig_big_dense(q, bd.a, static_cast<const double *>(in_dev), woff_dev,
+                                             static_cast<double *>(w_dev), static_cast<double *>(v_dev)));
+  }
   int32_t flag = 0;
   HIP_TRY(hipMemcpyAsync(&flag, ctx->err_flag, sizeof(int32_t), hipMemcpyDeviceToHost, q));
   HIP_TRY(hipStreamSynchronize(q));
@@ -830,8 +904,11 @@ strom_status block_eigs(strom_sdp *s, const double *sv, const std::vector<int32_
   HIP_TRY(hipSetDevice(s->ctx->device));
   hipStream_t q = s->stream;
   HIP_TRY(hipStreamSynchronize(q));
+  const bool big = !fits_lds(s->ctx, mx);  // the multi-workgroup eigensolver, every block padded to mx's size
+  const size_t big_doubles = big ? strom::dev::big_work_doubles(strom::dev::big_padded(mx), int(nl)) : 0;
   const size_t bytes = sizeof(int32_t) * nl * 2 + sizeof(int64_t) * nl * 2 + sizeof(double) * size_t(tn) +
-                       sizeof(double) * size_t(tn2) * (want_v ? 2 : 1) + 7 * 256;  // + alignment of 7 regions
+                       sizeof(double) * size_t(tn2) * (want_v ? 2 : 1) + sizeof(double) * big_doubles +
+                       8 * 256;  // + alignment of 8 regions
   unsigned char *buf = nullptr;
   if (work) {  // the caller's device buffer (no allocation)
     if (bytes > work->bytes)
@@ -850,6 +927,8 @@ strom_status block_eigs(strom_sdp *s, const double *sv, const std::vector<int32_
   double *d_w = reinterpret_cast<double *>(buf + o); o = al(o + sizeof(double) * size_t(tn));
   double *d_dense = reinterpret_cast<double *>(buf + o); o = al(o + sizeof(double) * size_t(tn2));
   double *d_v = want_v ? reinterpret_cast<double *>(buf + o) : nullptr;
+  if (want_v) o = al(o + sizeof(double) * size_t(tn2));
+  double *d_big = reinterpret_cast<double *>(buf + o);
   strom_status st = STROM_OK;
   std::string msg;
   auto chk = [&](hipError_t e, const char *what) {
@@ -861,8 +940,19 @@ strom_status block_eigs(strom_sdp *s, const double *sv, const std::vector<int32_
   chk(hipMemcpy(d_wo, wo.data(), sizeof(int64_t) * nl, hipMemcpyHostToDevice), "upload");
   chk(hipMemsetAsync(s->ctx->err_flag, 0, sizeof(int32_t), q), "hipMemsetAsync");
   chk(strom::dev::launch_unpack_svec(q, int(nl), d_ids, s->boff, s->bsz, sv, d_od, d_dense), "unpack");
-  chk(strom::dev::launch_eig_dense(q, false, int(nl), mx, d_nd, d_od, d_dense, d_wo, d_w, d_v, s->ctx->err_flag),
-      "eigenvalues");
+  if (big) {
+    strom::dev::BigArgs a;
+    a.np = strom::dev::big_padded(mx);
+    a.count = int32_t(nl);
+    a.nd = d_nd;
+    a.od = d_od;
+    a.work = d_big;
+    a.err = s->ctx->err_flag;
+    chk(strom::dev::launch_eig_big_dense(q, a, d_dense, d_wo, d_w, d_v), "eigenvalues");
+  } else {
+    chk(strom::dev::launch_eig_dense(q, false, int(nl), mx, d_nd, d_od, d_dense, d_wo, d_w, d_v, s->ctx->err_flag),
+        "eigenvalues");
+  }
   chk(hipStreamSynchronize(q), "hipStreamSynchronize");
   w.resize(size_t(tn));
   chk(hipMemcpy(w.data(), d_w, sizeof(double) * size_t(tn), hipMemcpyDeviceToHost), "download");
@@ -1065,6 +1155,9 @@ extern "C" strom_status strom_batch_create(strom_ctx *ctx, int32_t count, strom_
     if (!s) return fail(STROM_E_INVAL, "instance " + std::to_string(i) + " is NULL");
     if (s->ctx != ctx) return fail(STROM_E_INVAL, "instance " + std::to_string(i) + " belongs to another context");
     if (s->batch) return fail(STROM_E_STATE, "instance " + std::to_string(i) + " already belongs to a batch");
+    if (s->big.count > 0)
+      return fail(STROM_E_INVAL, "instance " + std::to_string(i) +
+                                     " has blocks beyond one workgroup's LDS; those instances iterate on their own");
     if (s->opts.kkt_every != v[0]->opts.kkt_every || s->opts.sigma_every != v[0]->opts.sigma_every)
       return fail(STROM_E_INVAL, "the instances of a batch need the same kkt_every and sigma_every");
     if (s->iters % s->opts.kkt_every != v[0]->iters % v[0]->opts.kkt_every)

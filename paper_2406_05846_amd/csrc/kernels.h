@@ -173,5 +173,31 @@ hipError_t launch_project_batch(hipStream_t s, bool f32, int n, int nt, int coun
 // Thread counts the projection kernel accepts for blocks of size n (at most 5, ascending).
 int project_thread_options(int n, bool f32, int *out);
 
+// Blocks too large for one workgroup's LDS (big.hip): count blocks padded to np (a multiple of
+// 64, at most kBigMaxN).  Block k is block ids[k] of an svec vector (boff, bsz) or, with ids ==
+// nullptr, the dense column-major block k (nd[k], od[k]).  work: big_work_doubles(np, count)
+// doubles of device memory; err (nullable) is or-ed with 1 when a block size is <= 0 or > np.
+constexpr int kBigMaxN = 512;
+struct BigArgs {
+  int32_t np = 0, count = 0;
+  const int32_t *ids = nullptr;
+  const int64_t *boff = nullptr;
+  const int32_t *bsz = nullptr;
+  const int32_t *nd = nullptr;
+  const int64_t *od = nullptr;
+  double *work = nullptr;
+  int32_t *err = nullptr;
+};
+size_t big_work_doubles(int np, int count);
+int big_padded(int n);
+// ADMM step 2 for the listed svec blocks, as launch_project_admm (always FP64).
+hipError_t launch_project_big_admm(hipStream_t s, const BigArgs &a, const double *X, double *S, const DevState *st,
+                                   double scale, double *Q, const int64_t *qoff, bool warm, bool reorth);
+// out = Pi(in) for dense column-major FP64 blocks (out may alias in).
+hipError_t launch_project_big_dense(hipStream_t s, const BigArgs &a, const double *in, double *out);
+// Eigenvalues ascending at w + woff[k]; with v, eigenvectors as the columns of the block at v + od[k].
+hipError_t launch_eig_big_dense(hipStream_t s, const BigArgs &a, const double *in, const int64_t *woff, double *w,
+                                double *v);
+
 }  // namespace dev
 }  // namespace strom

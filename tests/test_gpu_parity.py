@@ -108,8 +108,8 @@ def test_projection_in_place_and_errors(S, ctx, orc):
     assert np.linalg.norm(p - orc.project_psd(a)) <= 1e-10 * np.linalg.norm(a)
     with pytest.raises(S.StromError):  # block larger than max_n
         ctx.project_psd_batched(nd, od, x, x, 10)
-    with pytest.raises(S.StromError):  # does not fit the LDS of a workgroup in FP64
-        ctx.project_psd_batched(nd, od, x, x, 400)
+    with pytest.raises(S.StromError):  # over the largest block size (512)
+        ctx.project_psd_batched(nd, od, x, x, 600)
     empty_n = torch.zeros(0, dtype=torch.int32, device="cuda")
     empty_o = torch.zeros(0, dtype=torch.int64, device="cuda")
     ctx.project_psd_batched(empty_n, empty_o, x, x, 20)  # nothing to do
