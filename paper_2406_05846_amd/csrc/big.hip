@@ -169,8 +169,14 @@ int big_padded(int n) { return (n + kTile - 1) / kTile * kTile; }
 
 namespace {
 
-constexpr int kColdSweeps = 24;  // sweeps enqueued from a cold start (a random block needs 6-8)
-constexpr int kWarmSweeps = 10;  // from the kept eigenvectors (1-2 once the iteration settles)
+// Outer sweeps enqueued from a cold start (a random block of 190-300 needs 8-9) and from the kept
+// eigenvectors (about 3 for a perturbation of 1e-4 of the block); every pair subproblem is solved
+// to its tolerance.  (One Jacobi sweep per subproblem and round needs as many outer sweeps on
+// random spectra in a model of the method on the CPU, but fell short of the outer tolerance
+// within 16 sweeps on clustered ones.)
+constexpr int kColdSweeps = 24;
+constexpr int kWarmSweeps = 10;
+constexpr int kPairSweeps = 40;
 
 // ------------------------------------------------------------------------------ start
 
@@ -312,7 +318,7 @@ __global__ void __launch_bounds__(1024) k_big_pair(BigArgs a, int32_t r, uint32_
   int rfin = 0, rounds = 0;
   double *V = reinterpret_cast<double *>(sm.V);
   jacobi_eig<double, false, true, SubTol>(kTile, Ab, sm.nbuf, V, reinterpret_cast<double *>(sm.rot), sm.rotd, sm.red,
-                                          false, rfin, &rounds);
+                                          false, rfin, &rounds, kPairSweeps);
   double *G = b.G + (size_t)p * kTile * kTile;
   for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) G[e] = V[e];  // column c = local index c
   if (threadIdx.x == 0) b.flag[2 + p] = rounds > 0 ? 1 : 0;

@@ -359,14 +359,15 @@ __device__ inline double block_mass(const T *A, int nblk, int b, int I, int J, b
 
 // Cyclic Jacobi on the block arrays (buffer 0 on entry, position order of round 0).  Returns
 // the buffer holding the final matrix; rfin = the round (mod mm) whose position order it is in,
-// *rounds (when given) = the rounds run, 0 when the block was already diagonal to Tol.
+// *rounds (when given) = the rounds run, 0 when the block was already diagonal to Tol.  At most
+// max_sweeps sweeps.
 // A round is one phase and one barrier: the first wave computes the next round's rotation
 // parameters (look-ahead) while the other threads rotate the eigenvector pairs in place and the
 // 2x2 blocks, storing them to their permuted places (in the other buffer; single-buffered, the
 // stores wait for one more barrier).  With few threads (no split) every thread does all three.
 template <typename T, bool BIG, bool WANT_V = true, class Tol = JacobiTol<T>>
 __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, T *V, T *rot, double *rotd, double *red,
-                                          bool v_ready, int &rfin, int *rounds = nullptr) {
+                                          bool v_ready, int &rfin, int *rounds = nullptr, int max_sweeps = 40) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int nn = n + (n & 1), np2 = nn / 2, mm = nn - 1;
   const int nblk = np2 * (np2 + 1) / 2;
@@ -406,7 +407,7 @@ __device__ __forceinline__ int jacobi_eig(int n, T *Ab, int nbuf, T *V, T *rot, 
   // parameters of the first round; then round g uses buffer g & 1 and writes (g + 1) & 1
   round_rotations<T>(np2, nblk, skip, Ab, rot, rotd, tid, nth);
   int cur = 0, g = 0;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     const T *Ac = Ab + (size_t)cur * 4 * nblk;
     double off = 0.0;  // off-diagonal mass at the start of the sweep
     if (I0 >= 0) off += block_mass<T>(Ac, nblk, b0, I0, J0, false);
