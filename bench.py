@@ -37,15 +37,27 @@ def _proj_flops(block_sizes) -> float:
     return float(sum(11.0 * int(n) ** 3 for n in block_sizes))
 
 
-def _traffic(path: str, source: str):
-    """HBM bytes per launch of the dominant kernel from the committed counter record, or None
-    when the kernel source has changed since the counters were taken."""
+# the sources of the projection kernel (its traffic record is valid for exactly these)
+PROJECT_SOURCES = ("paper_2406_05846_amd/csrc/project.hip", "paper_2406_05846_amd/csrc/jacobi_lds.h")
+
+
+def _sources_sha(sources) -> str:
+    """sha256 of the kernel's source files, concatenated in the given order."""
     import hashlib
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _traffic(path: str, sources):
+    """HBM bytes per launch of the dominant kernel from the committed counter record, or None
+    when the kernel's sources have changed since the counters were taken."""
     try:
         with open(os.path.join(ROOT, path)) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, source), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = _sources_sha(sources)
     except OSError:
         return None
     return rec["hbm_bytes_per_dispatch"] if rec.get("source_sha256") == sha else None
@@ -703,7 +715,7 @@ def main():
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 6),
                      "traffic": _traffic("profiles/k_project_admm_cartpole_n30_traffic.json",
-                                         "paper_2406_05846_amd/csrc/project.hip")},
+                                         PROJECT_SOURCES)},
     }
     if not args.no_cpu:
         _log("CPU oracle baseline ...")
