@@ -125,41 +125,12 @@ def test_big_eig_vs_oracle(S, ctx, orc):
 
 
 def _synthetic_sdp(orc, S, sizes, m, seed):
-    """A feasible, bounded SDP with the given blocks: m sparse rows (1-6 svec entries of one
-    block, the last rows coupling two blocks), b = A(X_f) for a random positive definite X_f,
-    C = G G^T / n + I per block."""
-    rng = np.random.default_rng(seed)
-    sizes = np.array(sizes, np.int32)
-    tri = sizes.astype(np.int64) * (sizes + 1) // 2
-    boff = np.concatenate([[0], np.cumsum(tri)[:-1]]).astype(np.int64)
-    nsvec = int(tri.sum())
-    rows = []
-    for r in range(m):
-        ks = rng.choice(len(sizes), 2, replace=False) if r >= m - 8 else [rng.integers(len(sizes))]
-        ent = {}
-        for k in ks:
-            for _ in range(rng.integers(1, 7)):
-                ent[int(boff[k] + rng.integers(tri[k]))] = rng.standard_normal()
-        rows.append(sorted(ent.items()))
-    rowptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
-    col = np.array([c for r in rows for c, _ in r], np.int32)
-    val = np.array([v for r in rows for _, v in r], np.float64)
-
-    def svec(M):
-        iu = np.triu_indices(M.shape[0])
-        j, i = iu[1], iu[0]
-        order = np.lexsort((i, j))  # column-major upper triangle
-        v = M[i[order], j[order]] * np.where(i[order] == j[order], 1.0, np.sqrt(2.0))
-        return v
-
-    Xf = np.concatenate([svec((lambda G: G @ G.T / n + 0.1 * np.eye(n))(rng.standard_normal((n, n)))) for n in sizes])
-    Cv = np.concatenate([svec((lambda G: G @ G.T / n + np.eye(n))(rng.standard_normal((n, n)))) for n in sizes])
-    import scipy.sparse as sp
-    A = sp.csr_matrix((val, col, rowptr), shape=(m, nsvec))
-    b = A @ Xf
-    osdp = orc.SDP(nblocks=len(sizes), bsize=sizes, boff=boff, nsvec=nsvec, m=m, nnz=len(val), rowptr=rowptr,
-                   col=col, val=val, b=b, C=Cv)
-    prob = S.Problem(sizes, rowptr, col, val, b, Cv)
+    """A feasible, bounded instance with the given blocks (workloads.synthetic), for both sides."""
+    from workloads.synthetic import large_block_sdp
+    d = large_block_sdp(sizes, m, seed)
+    osdp = orc.SDP(nblocks=len(d["block_sizes"]), bsize=d["block_sizes"], boff=d["boff"], nsvec=d["nsvec"], m=m,
+                   nnz=len(d["val"]), rowptr=d["rowptr"], col=d["col"], val=d["val"], b=d["b"], C=d["C"])
+    prob = S.Problem(d["block_sizes"], d["rowptr"], d["col"], d["val"], d["b"], d["C"])
     return osdp, prob
 
 
