@@ -136,7 +136,7 @@ strom_status strom_ctx_destroy(strom_ctx *ctx);
  * chain-like sparsity of Def. 1), factors eps*I + A A^* = P L D L^T P^T in FP64 on the host
  * (the paper's Cholesky-with-pre-permutation equation; E_FACTOR on a non-positive pivot),
  * uploads everything and sets the iterate to (X0, 0, S0).  opts may be NULL (defaults).
- * Blocks up to n = 114 are projected by one workgroup each (in FP64, or FP32 before the polish
+ * Blocks up to n = 113 are projected by one workgroup each (in FP64, or FP32 before the polish
  * switch); larger ones, up to n = 512 (E_INVAL beyond), by the multi-workgroup block Jacobi,
  * always in FP64, with about 16 n^2 bytes of device memory each. */
 strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *problem, const strom_opts *opts,
@@ -178,8 +178,9 @@ strom_status strom_sdp_sizes(strom_sdp *sdp, int64_t *n_svec, int32_t *m, int64_
  * reconstruction).  Block k is n_dev[k] x n_dev[k], column-major, starting at element
  * offset_dev[k] of in_dev / out_dev; in and out may alias.  n_dev, offset_dev, in_dev and
  * out_dev are device pointers; max_n (host) bounds every n_dev[k], 1 <= max_n <= 512.  When
- * one block and its eigenvectors fit the LDS of one workgroup (160 KiB on gfx950: max_n <= 114
- * in F64, about 160 in F32) every block is projected by one workgroup; beyond that (F64 only,
+ * one block and its eigenvectors fit one workgroup (160 KiB of LDS on gfx950, and a worker thread
+ * per 2 x 2 block: max_n <= 113 in F64, <= 122 in F32) every block is projected by one
+ * workgroup; beyond that (F64 only,
  * else E_INVAL) by the multi-workgroup block Jacobi, every block padded to max_n's size, with
  * temporary device memory of about 16 max_n^2 bytes per block.  A block with n_dev[k] <= 0 or
  * > max_n makes the call return E_INVAL (other blocks are still written).  dtype selects double

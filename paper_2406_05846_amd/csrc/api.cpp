@@ -180,13 +180,9 @@ extern "C" strom_status strom_ctx_destroy(strom_ctx *c) {
   return STROM_OK;
 }
 
-static size_t proj_need(int n, bool f32) {
-  return strom::dev::project_lds_bytes(n, f32, strom::dev::project_threads(n));
-}
-
 // Blocks whose FP64 projection fits one workgroup's LDS take the one-workgroup kernel (in FP64 or
 // FP32); larger ones the multi-workgroup block Jacobi of big.hip, always in FP64.
-static bool fits_lds(const strom_ctx *ctx, int n) { return proj_need(n, false) <= ctx->max_lds; }
+static bool fits_lds(const strom_ctx *ctx, int n) { return strom::dev::project_fits(n, false, ctx->max_lds); }
 
 extern "C" strom_status strom_sdp_setup(strom_ctx *ctx, const strom_problem *P, const strom_opts *opts,
                                         strom_sdp **out) {
@@ -788,8 +784,8 @@ namespace {
 strom_status check_dense_max_n(const strom_ctx *ctx, int32_t max_n, bool f32) {
   if (max_n <= 0 || max_n > strom::dev::kBigMaxN)
     return fail(STROM_E_INVAL, "max_n out of range (1.." + std::to_string(strom::dev::kBigMaxN) + ")");
-  if (f32 && proj_need(max_n, true) > ctx->max_lds)
-    return fail(STROM_E_INVAL, "max_n beyond one workgroup's LDS needs FP64 blocks");
+  if (f32 && !strom::dev::project_fits(max_n, true, ctx->max_lds))
+    return fail(STROM_E_INVAL, "max_n beyond the one-workgroup kernel (122 in FP32) needs FP64 blocks");
   return STROM_OK;
 }
 
@@ -832,7 +828,7 @@ extern "C" strom_status strom_project_psd_batched(strom_ctx *ctx, int32_t nblock
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t q = (hipStream_t)hip_stream;
   HIP_TRY(hipMemsetAsync(ctx->err_flag, 0, sizeof(int32_t), q));
-  if (proj_need(max_n, f32) <= ctx->max_lds) {
+  if (strom::dev::project_fits(max_n, f32, ctx->max_lds)) {
     HIP_TRY(strom::dev::launch_project_dense(q, f32, nblocks, max_n, n_dev, offset_dev, in_dev, out_dev, ctx->err_flag));
   } else {
     BigDense bd;
@@ -862,7 +858,7 @@ extern "C" strom_status strom_eig_batched(strom_ctx *ctx, int32_t nblocks, int32
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t q = (hipStream_t)hip_stream;
   HIP_TRY(hipMemsetAsync(ctx->err_flag, 0, sizeof(int32_t), q));
-  if (proj_need(max_n, f32) <= ctx->max_lds) {
+  if (strom::dev::project_fits(max_n, f32, ctx->max_lds)) {
     HIP_TRY(strom::dev::launch_eig_dense(q, f32, nblocks, max_n, n_dev, offset_dev, in_dev, woff_dev, w_dev, v_dev,
                                          ctx->err_flag));
   } else {

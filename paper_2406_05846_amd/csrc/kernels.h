@@ -170,6 +170,9 @@ hipError_t launch_gather_states(hipStream_t s, int ninst, const BatchInst *bi, D
 // instances whose sig flag is set.
 hipError_t launch_project_batch(hipStream_t s, bool f32, int n, int nt, int count, const BatchItem *items,
                                 const BatchInst *bi, int cone, bool reorth);
+// Whether the one-workgroup projection takes blocks of size n (its LDS within lds_cap and a
+// worker thread for every 2 x 2 block and eigenvector row): n <= 113 in FP64, <= 122 in FP32.
+bool project_fits(int n, bool f32, size_t lds_cap);
 // Thread counts the projection kernel accepts for blocks of size n (at most 5, ascending).
 int project_thread_options(int n, bool f32, int *out);
 

@@ -479,6 +479,14 @@ hipError_t launch_project_batch(hipStream_t s, bool f32, int n, int nt, int coun
   return hipGetLastError();
 }
 
+bool project_fits(int n, bool f32, size_t lds_cap) {
+  if (n <= 0) return false;
+  const int nt = project_threads(n);
+  bool big = false;
+  const size_t lds = project_lds_bytes(n, f32, nt);
+  return threads_ok(n, nt, f32, big) && lds <= kLdsCap && lds <= lds_cap;
+}
+
 int project_thread_options(int n, bool f32, int *out) {
   int k = 0;
   for (int nt = 64; nt <= 1024; nt *= 2) {

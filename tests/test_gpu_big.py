@@ -1,4 +1,4 @@
-"""Blocks beyond one workgroup's LDS (n > 114 in FP64): the multi-workgroup block Jacobi, through
+"""Blocks beyond one workgroup's LDS (n > 113 in FP64): the multi-workgroup block Jacobi, through
 the C ABI, against the FP64 oracle.  Needs an MI355X.
 
 The sizes are those of the paper's larger moment blocks (Table 1: 190 for the car back-in and
@@ -187,3 +187,23 @@ def test_big_certificate_vs_oracle(S, ctx, orc):
     assert abs(lb - ref_lb) <= 1e-9 * max(1.0, abs(ref_lb))
     assert np.abs(lam - ref_lam).max() <= 1e-9 * max(1.0, np.abs(ref_lam).max())
     inst.close()
+
+
+def test_big_boundary_sizes(S, ctx, orc):
+    """n = 113 is the last FP64 size of the one-workgroup kernel and 114 the first of the block
+    Jacobi (both against the oracle); FP32 data beyond 122 is refused (the block Jacobi is FP64)."""
+    import torch
+    rng = np.random.default_rng(203)
+    for n in (113, 114):
+        a = _rand_sym(rng, n)
+        x = torch.tensor(a.reshape(-1, order="F"), dtype=torch.float64, device="cuda")
+        nd = torch.tensor([n], dtype=torch.int32, device="cuda")
+        od = torch.tensor([0], dtype=torch.int64, device="cuda")
+        ctx.project_psd_batched(nd, od, x, x, n)
+        p = x.cpu().numpy().reshape((n, n), order="F")
+        assert np.linalg.norm(p - orc.project_psd(a)) / np.linalg.norm(a) <= 1e-10, n
+    x32 = torch.zeros(123 * 123, dtype=torch.float32, device="cuda")
+    nd = torch.tensor([123], dtype=torch.int32, device="cuda")
+    od = torch.tensor([0], dtype=torch.int64, device="cuda")
+    with pytest.raises(S.StromError):
+        ctx.project_psd_batched(nd, od, x32, x32, 123)
