@@ -16,6 +16,8 @@
  *   3 the paper's variational-integrator pendulum     [theta0, omega0]
  *   4 planar car, unicycle-12 (91x91 / 13x13) or bicycle-13 (105x105 / 14x14)
  *                                                     [variant, sx, sy, heading0, gx, gy, ox, oy]
+ *   5 the paper's flying robot (App. "Flying Robot"; 20-variable cliques, 231x231 / 21x21)
+ *                                                     [x0, y0, theta0, vx0, vy0, omega0]
  *
  * Every function returns 0 on success and a negative strom_status on error.
  */

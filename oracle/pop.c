@@ -155,6 +155,11 @@ int fam_layout(int family, const double *prm, int nprm, int *dx, int *du, double
       else { *du = 2; su[0] = 2; su[1] = 1; }
       return 0;
     }
+    case ORC_FLYING: /* state (rx, ry, vx, vy, rc, rs, fc, fs), thrusts u1..u4; r/10, v/10, u/8 */
+      *dx = 8; *du = 4;
+      sx[0] = sx[1] = sx[2] = sx[3] = 10; sx[4] = sx[5] = sx[6] = sx[7] = 1;
+      su[0] = su[1] = su[2] = su[3] = 8;
+      return 0;
     default: return -1;
   }
 }
@@ -374,6 +379,51 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
     if (last)
       *cost = add_(*cost, scl_(Pf, add_(add_(sq_(sub_(X1(&L, 0), cst(gx))), sq_(sub_(X1(&L, 1), cst(gy)))),
                                         sq_(X1(&L, 4)))));
+  } else if (family == ORC_FLYING) {
+    /* the paper's flying robot (App. "Flying Robot"), Lie-group integrator for the heading:
+     *  r' = r + dt v;  v' = v + dt T (rc, rs) with T = u1 - u2 + u3 - u4;
+     *  fs' - fs = dt^2 (alpha (u2 - u1) + beta (u3 - u4));  (rc', rs') = (rc, rs) rotated by (fc, fs);
+     *  unit circles for r and f;  fc' >= fc_min;  u_i (u_max - u_i) >= 0;  |rx|, |ry|, |vx|, |vy|
+     *  within their maxima.  Cost: distance to the rest state at the origin plus |u|^2 (scaled
+     *  variables), terminal weight P_f = 10.  Parameters: x0, y0, theta0, vx0, vy0, omega0. */
+    if (nprm < 6) return -1;
+    const double dt = 0.2, alpha = 0.2, beta = 0.2, fcmin = 0.7, umax = 8, Pf = 10;
+    const double rmax = 10, vmax = 10;
+    if (k == 0) {
+      const double init[8] = {prm[0], prm[1], prm[3], prm[4], cos(prm[2]), sin(prm[2]), cos(dt * prm[5]),
+                              sin(dt * prm[5])};
+      for (int i = 0; i < 8; ++i) push(eq, sub_(X0(&L, i), cst(init[i])));
+    }
+    pl_poly T = sub_(add_(sub_(U(&L, 0), U(&L, 1)), U(&L, 2)), U(&L, 3));
+    push(eq, sub_(sub_(X1(&L, 0), X0(&L, 0)), scl_(dt, X0(&L, 2))));
+    push(eq, sub_(sub_(X1(&L, 1), X0(&L, 1)), scl_(dt, X0(&L, 3))));
+    {
+      pl_poly T2 = pl_copy(&T);
+      push(eq, sub_(sub_(X1(&L, 2), X0(&L, 2)), scl_(dt, mul_(T, X0(&L, 4)))));
+      push(eq, sub_(sub_(X1(&L, 3), X0(&L, 3)), scl_(dt, mul_(T2, X0(&L, 5)))));
+    }
+    push(eq, sub_(sub_(X1(&L, 7), X0(&L, 7)),
+                  add_(scl_(dt * dt * alpha, sub_(U(&L, 1), U(&L, 0))), scl_(dt * dt * beta, sub_(U(&L, 2), U(&L, 3))))));
+    push(eq, sub_(X1(&L, 4), sub_(mul_(X0(&L, 4), X0(&L, 6)), mul_(X0(&L, 5), X0(&L, 7)))));
+    push(eq, sub_(X1(&L, 5), add_(mul_(X0(&L, 5), X0(&L, 6)), mul_(X0(&L, 4), X0(&L, 7)))));
+    push(eq, circle(X1(&L, 4), X1(&L, 5)));
+    push(eq, circle(X1(&L, 6), X1(&L, 7)));
+    if (k >= 1) {
+      push(eq, circle(X0(&L, 4), X0(&L, 5)));
+      push(eq, circle(X0(&L, 6), X0(&L, 7)));
+    }
+    for (int i = 0; i < 4; ++i) push(ineq, mul_(U(&L, i), sub_(cst(umax), U(&L, i))));
+    push(ineq, sub_(X1(&L, 6), cst(fcmin)));
+    push(ineq, sub_(cst(rmax * rmax), sq_(X1(&L, 0))));
+    push(ineq, sub_(cst(rmax * rmax), sq_(X1(&L, 1))));
+    push(ineq, sub_(cst(vmax * vmax), sq_(X1(&L, 2))));
+    push(ineq, sub_(cst(vmax * vmax), sq_(X1(&L, 3))));
+    const double tgt[8] = {0, 0, 0, 0, 1, 0, 1, 0};
+    for (int i = 0; i < 8; ++i) *cost = add_(*cost, sq_(sub_(pl_var(i, 1.0), cst(tgt[i]))));
+    for (int i = 0; i < 4; ++i) *cost = add_(*cost, sq_(pl_var(L.dx + i, 1.0)));
+    if (last)
+      for (int i = 0; i < 8; ++i)
+        *cost = add_(*cost, scl_(Pf, sq_(sub_(pl_var(L.dx + L.du + i, 1.0), cst(tgt[i])))));
   } else {
     return -1;
   }
@@ -428,6 +478,18 @@ int fam_step(int family, const double *prm, int nprm, const double *x0, double *
     const double a = dt * w / 2, a2 = a * a;
     Y[2] = ((1 - a2) * X[2] - 2 * a * X[3]) / (1 + a2);
     Y[3] = ((1 - a2) * X[3] + 2 * a * X[2]) / (1 + a2);
+  } else if (family == ORC_FLYING) {
+    const double dt = 0.2, alpha = 0.2, beta = 0.2;
+    const double T = Uo[0] - Uo[1] + Uo[2] - Uo[3];
+    Y[0] = X[0] + dt * X[2];
+    Y[1] = X[1] + dt * X[3];
+    Y[2] = X[2] + dt * T * X[4];
+    Y[3] = X[3] + dt * T * X[5];
+    Y[7] = X[7] + dt * dt * (alpha * (Uo[1] - Uo[0]) + beta * (Uo[2] - Uo[3]));
+    if (fabs(Y[7]) > 1) return -2;
+    Y[6] = sqrt(1 - Y[7] * Y[7]);
+    Y[4] = X[4] * X[6] - X[5] * X[7];
+    Y[5] = X[5] * X[6] + X[4] * X[7];
   } else {
     return -1;
   }
@@ -449,6 +511,9 @@ int fam_init_state(int family, const double *prm, int nprm, double *x0) {
     X[0] = cos(prm[0]); X[1] = sin(prm[0]); X[2] = cos(0.1 * prm[1]); X[3] = sin(0.1 * prm[1]);
   } else if (family == ORC_CAR) {
     X[0] = prm[1]; X[1] = prm[2]; X[2] = cos(prm[3]); X[3] = sin(prm[3]); X[4] = 0;
+  } else if (family == ORC_FLYING) {
+    X[0] = prm[0]; X[1] = prm[1]; X[2] = prm[3]; X[3] = prm[4];
+    X[4] = cos(prm[2]); X[5] = sin(prm[2]); X[6] = cos(0.2 * prm[5]); X[7] = sin(0.2 * prm[5]);
   } else return -1;
   for (int i = 0; i < dx; ++i) x0[i] = X[i] / sx[i];
   return 0;
@@ -472,6 +537,11 @@ int fam_var_bounds(int family, const double *prm, int nprm, double *bnd) {
     bx[0] = fmax(3.0, fabs(prm[1])) / sx[0]; bx[1] = fmax(3.0, fabs(prm[2])) / sx[1];
     bx[2] = bx[3] = 1; bx[4] = 2.0 / sx[4]; bu[0] = 2.0 / su[0];
     if (prm[0] != 0.0) { bu[1] = 0.6; bu[2] = 1.2; } else bu[1] = 1.5;
+  } else if (family == ORC_FLYING) {   /* |rx|, |ry|, |vx|, |vy| <= 10, circles, 0 <= u_i <= 8 */
+    bx[0] = fmax(10.0, fabs(prm[0])) / sx[0]; bx[1] = fmax(10.0, fabs(prm[1])) / sx[1];
+    bx[2] = fmax(10.0, fabs(prm[3])) / sx[2]; bx[3] = fmax(10.0, fabs(prm[4])) / sx[3];
+    bx[4] = bx[5] = bx[6] = bx[7] = 1;
+    bu[0] = bu[1] = bu[2] = bu[3] = 1;
   } else {
     return -1;
   }

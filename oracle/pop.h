@@ -5,7 +5,7 @@
 
 #include "oracle.h"
 
-#define PL_MAXV 16 /* max variables per clique */
+#define PL_MAXV 21 /* max variables per clique (3-bit exponents of 21 variables fit a 64-bit key) */
 
 typedef struct { uint8_t e[PL_MAXV]; double c; } pl_term;
 typedef struct { int n, cap; pl_term *t; } pl_poly;

@@ -64,9 +64,11 @@ static int basis(int d, int n, mono_t **out) {
   return cnt;
 }
 
+/* Key of a monomial: exponent of variable v in bits [3v, 3v + 3).  Every monomial here has total
+ * degree <= 4, so each exponent fits three bits and the key is unique. */
 static uint64_t mkey(const uint8_t *e) {
   uint64_t k = 0;
-  for (int v = 0; v < PL_MAXV; ++v) k = (k << 4) | (uint64_t)(e[v] & 15);
+  for (int v = 0; v < PL_MAXV; ++v) k |= (uint64_t)(e[v] & 7) << (3 * v);
   return k;
 }
 

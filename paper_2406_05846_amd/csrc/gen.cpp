@@ -27,18 +27,21 @@
 
 namespace {
 
-// A monomial packs the exponent of variable v into bits [4v, 4v + 4).  Exponents stay below
-// 16 (total degree <= 4 everywhere), so the product of two monomials is their integer sum.
+// A monomial packs the exponent of variable v into bits [3v, 3v + 3).  Exponents stay below 8
+// (total degree <= 4 everywhere), so the product of two monomials is their integer sum; 21
+// variables fit 64 bits.
 using Mono = uint64_t;
-constexpr int kMaxVars = 16;
+constexpr int kMaxVars = 21;
+constexpr int kExpBits = 3;
+constexpr Mono kExpMask = 7;
 
 int mono_deg(Mono m) {
   int s = 0;
-  for (; m; m >>= 4) s += int(m & 15u);
+  for (; m; m >>= kExpBits) s += int(m & kExpMask);
   return s;
 }
-int mono_exp(Mono m, int v) { return int((m >> (4 * v)) & 15u); }
-Mono mono_var(int v) { return Mono(1) << (4 * v); }
+int mono_exp(Mono m, int v) { return int((m >> (kExpBits * v)) & kExpMask); }
+Mono mono_var(int v) { return Mono(1) << (kExpBits * v); }
 
 struct Poly {
   std::map<Mono, double> c;
@@ -89,7 +92,7 @@ double eval_mono(Mono m, const double *z, int d) {
 // (e_0, e_1, ...) in descending lexicographic order.
 void collect_monos(int d, int v, int budget, Mono acc, std::vector<Mono> &all) {
   if (v == d) { all.push_back(acc); return; }
-  for (int e = 0; e <= budget; ++e) collect_monos(d, v + 1, budget - e, acc | (Mono(e) << (4 * v)), all);
+  for (int e = 0; e <= budget; ++e) collect_monos(d, v + 1, budget - e, acc | (Mono(e) << (kExpBits * v)), all);
 }
 
 std::vector<Mono> monomial_basis(int d, int n) {
@@ -138,6 +141,7 @@ bool make_layout(int family, const double *p, int np, Layout &L) {
       setx({3, 3, 1, 1, 2});
       if (p[0] != 0.0) setu({2, 1, 1}); else setu({2, 1});
       return true;
+    case 5: if (np < 6) return false; setx({10, 10, 10, 10, 1, 1, 1, 1}); setu({8, 8, 8, 8}); return true;
     default: return false;
   }
 }
@@ -232,6 +236,36 @@ CliquePolys clique_polys(int family, int N, int k, const double *p, const Layout
     q.cost = q.cost + sq(L.zu(0));
     if (last)
       for (int i = 0; i < 4; ++i) q.cost = q.cost + Pf * sq(L.zx1(i) - target[i]);
+  } else if (family == 5) {  // the paper's flying robot: thrusts u1..u4, Lie-group heading update
+    const double dt = 0.2, alpha = 0.2, beta = 0.2, fcmin = 0.7, umax = 8, Pf = 10, rmax = 10, vmax = 10;
+    if (first) {
+      const double init[8] = {p[0], p[1], p[3], p[4], std::cos(p[2]), std::sin(p[2]), std::cos(dt * p[5]),
+                              std::sin(dt * p[5])};
+      for (int i = 0; i < 8; ++i) q.eq.push_back(L.x0(i) - init[i]);
+    }
+    const Poly thrust = L.u(0) - L.u(1) + L.u(2) - L.u(3);
+    q.eq.push_back(L.x1(0) - L.x0(0) - dt * L.x0(2));
+    q.eq.push_back(L.x1(1) - L.x0(1) - dt * L.x0(3));
+    q.eq.push_back(L.x1(2) - L.x0(2) - dt * (thrust * L.x0(4)));
+    q.eq.push_back(L.x1(3) - L.x0(3) - dt * (thrust * L.x0(5)));
+    q.eq.push_back(L.x1(7) - L.x0(7) - ((dt * dt * alpha) * (L.u(1) - L.u(0)) + (dt * dt * beta) * (L.u(2) - L.u(3))));
+    q.eq.push_back(L.x1(4) - (L.x0(4) * L.x0(6) - L.x0(5) * L.x0(7)));
+    q.eq.push_back(L.x1(5) - (L.x0(5) * L.x0(6) + L.x0(4) * L.x0(7)));
+    q.eq.push_back(unit_circle(L.x1(4), L.x1(5)));
+    q.eq.push_back(unit_circle(L.x1(6), L.x1(7)));
+    if (!first) {
+      q.eq.push_back(unit_circle(L.x0(4), L.x0(5)));
+      q.eq.push_back(unit_circle(L.x0(6), L.x0(7)));
+    }
+    for (int i = 0; i < 4; ++i) q.ineq.push_back(L.u(i) * (umax - L.u(i)));
+    q.ineq.push_back(L.x1(6) - fcmin);
+    for (int i = 0; i < 2; ++i) q.ineq.push_back(rmax * rmax - sq(L.x1(i)));
+    for (int i = 2; i < 4; ++i) q.ineq.push_back(vmax * vmax - sq(L.x1(i)));
+    const double target[8] = {0, 0, 0, 0, 1, 0, 1, 0};
+    for (int i = 0; i < 8; ++i) q.cost = q.cost + sq(L.zx0(i) - target[i]);
+    for (int i = 0; i < 4; ++i) q.cost = q.cost + sq(L.zu(i));
+    if (last)
+      for (int i = 0; i < 8; ++i) q.cost = q.cost + Pf * sq(L.zx1(i) - target[i]);
   } else {  // planar car with one circular obstacle
     const bool bicycle = p[0] != 0.0;
     const double dt = 0.1, Pf = 10;
@@ -283,6 +317,11 @@ bool var_bounds(int family, const double *p, const Layout &L, std::vector<double
     case 4:  // |rx|, |ry| <= 3, unit circle, |v| <= 2, |a| <= 2; |w| <= 1.5 or |dtilde| <= 0.6 and |p| <= 1.2
       bx = {std::max(1.0, std::fabs(p[1]) / 3), std::max(1.0, std::fabs(p[2]) / 3), 1.0, 1.0, 1.0};
       if (p[0] != 0.0) bu = {1.0, 0.6, 1.2}; else bu = {1.0, 1.5};
+      return true;
+    case 5:  // |rx|, |ry|, |vx|, |vy| <= 10 (scaled by 10), circles, 0 <= u_i <= 8 (scaled by 8)
+      bx = {std::max(1.0, std::fabs(p[0]) / 10), std::max(1.0, std::fabs(p[1]) / 10),
+            std::max(1.0, std::fabs(p[3]) / 10), std::max(1.0, std::fabs(p[4]) / 10), 1.0, 1.0, 1.0, 1.0};
+      bu = {1.0, 1.0, 1.0, 1.0};
       return true;
     default: return false;
   }
@@ -461,7 +500,7 @@ extern "C" int strom_gen_build(int family, int N, const double *params, int npar
       }
     }
     if (k + 1 < N) {  // consensus rows on the monomials of x_{k+1}
-      const int shift = 4 * (L.dx + L.du);
+      const int shift = kExpBits * (L.dx + L.du);
       for (Mono a : Bshared) {
         put_rep(k, a << shift, 1.0);
         put_rep(k + 1, a, -1.0);

@@ -207,3 +207,22 @@ def test_big_boundary_sizes(S, ctx, orc):
     od = torch.tensor([0], dtype=torch.int64, device="cuda")
     with pytest.raises(S.StromError):
         ctx.project_psd_batched(nd, od, x32, x32, 123)
+
+
+def test_flying_robot_iterates(S, ctx, orc):
+    """The paper's flying robot relaxation (231 x 231 moment blocks through the block Jacobi, 21 x 21
+    localizing blocks), N = 2: iterates after 1 and 6 iterations with a fixed sigma against the
+    oracle (its own generator, LDL^T and Jacobi)."""
+    import workloads as W
+    prm = W.instance_params(W.FLYING, 0)
+    osdp = orc.relax(W.FLYING, 2, prm)
+    prob = S.generate(W.FLYING, 2, prm)
+    inst = S.Instance(ctx, prob, S.default_opts(sigma_every=0, kkt_every=1, tol=0.0))
+    for k in [1, 6]:
+        inst.set_iterate(np.zeros(prob.nsvec), np.zeros(prob.m), np.zeros(prob.nsvec))
+        inst.step(k)
+        Xg, yg, Sg = inst.get_iterate()
+        r = orc.admm_solve(osdp, maxiter=k, tol=0.0, sigma_every=0)
+        assert blockwise_rel(Xg, r["X"], osdp.bsize) <= 1e-9, k
+        assert blockwise_rel(Sg, r["S"], osdp.bsize) <= 1e-9, k
+    inst.close()

@@ -125,6 +125,40 @@ def test_paper_pendulum_sizes(orc):
     assert (kinds == 1).sum() == gold["num_L"] and set(sdp.bsize[kinds == 1]) == {gold["size_L"]}
 
 
+def test_flying_robot_sizes(orc):
+    """The paper's flying robot at its horizon: 60 moment blocks of 231 = s(20, 2) (cliques of
+    x_k, u_k, x_{k+1} with d_x = 8, d_u = 4) and localizing blocks of 21 = s(20, 1), as in Table 1;
+    nine inequalities per clique (four thrust ranges, f_c >= f_c,min, four boxes)."""
+    gold = json.load(open(os.path.join(GOLD, "paper_sizes.json")))["flying_robot"]
+    sdp = orc.relax(orc.FLYING, gold["N"], [3.0, -2.0, 0.5, 0.5, -0.5, 0.2])
+    kinds = sdp.bkind
+    assert (kinds == 0).sum() == gold["num_M"] and set(sdp.bsize[kinds == 0]) == {gold["size_M"]}
+    assert set(sdp.bsize[kinds == 1]) == {gold["size_L"]}
+    assert (kinds == 1).sum() == 9 * gold["N"]
+    assert sdp.dx == 8 and sdp.du == 4 and sdp.nclique_vars == 20
+    # the paper's m is this relaxation's m plus the rows of the localizing matrices its count has
+    # beyond the listed inequalities (tri(21) rows each): the moment, equality, consensus and
+    # normalization rows agree with Table 1 exactly
+    extra = gold["num_L_paper"] - int((kinds == 1).sum())
+    assert sdp.m + extra * (21 * 22 // 2) == gold["m_paper"]
+
+
+def test_flying_robot_row_counts(orc):
+    """m of the flying robot from the same closed form as the other families: per clique k >= 1
+    three equalities of degree 1 (position updates, f_s update) and eight of degree 2 (velocity
+    updates, heading rotation, unit circles of r and f on x_{k+1} and x_k); clique 0 has the eight
+    initial-state equalities instead of the two circles on x_0."""
+    N = 4
+    sdp = orc.relax(orc.FLYING, N, [3.0, -2.0, 0.5, 0.5, -0.5, 0.2])
+    d, dx = 20, 8
+    s = lambda n: math.comb(d + n, n)
+    tri = lambda n: n * (n + 1) // 2
+    m = 1 + N * (tri(s(2)) - s(4)) + N * 9 * tri(s(1))
+    m += N * (3 * s(3) + 6 * s(2)) + (N - 1) * 2 * s(2) + dx * s(3)
+    m += (N - 1) * math.comb(dx + 4, 4)
+    assert sdp.m == m
+
+
 def _binom(n, k):
     return math.comb(n, k)
 
@@ -158,6 +192,7 @@ FAMS = [
     ("PAPER_PENDULUM", 4, [0.3, 0.5], 0.5),
     ("CAR", 4, [0, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1], 0.5),
     ("CAR", 4, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1], 0.5),
+    ("FLYING", 3, [3.0, -2.0, 0.5, 0.5, -0.5, 0.2], 1.0),
 ]
 
 

@@ -10,14 +10,15 @@ Parameter vectors, per family (angles in radians, original units):
   pendulum [theta0, omega0]                theta measured from upright, omega0 = 0
   cartpole [x0, v0, theta0, omega0]
   car      [variant, sx, sy, heading0, gx, gy, ox, oy]   variant 0 unicycle-12, 1 bicycle-13
+  flying   [x0, y0, theta0, vx0, vy0, omega0]      the paper's flying robot (rest at the origin is the goal)
 """
 from __future__ import annotations
 
 import math
 
-TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR = 0, 1, 2, 3, 4
+TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING = 0, 1, 2, 3, 4, 5
 FAMILY_NAMES = {TOY1D: "toy1d", PENDULUM: "pendulum", CARTPOLE: "cartpole",
-                PAPER_PENDULUM: "paper_pendulum", CAR: "car"}
+                PAPER_PENDULUM: "paper_pendulum", CAR: "car", FLYING: "flying"}
 _MASK = (1 << 64) - 1
 
 
@@ -67,6 +68,9 @@ def instance_params(family: int, seed: int) -> list:
             if math.hypot(sx - ox, sy - oy) >= 0.6 and math.hypot(gx - ox, gy - oy) >= 0.6:
                 break
         return [float(variant), sx, sy, r.uniform(-math.pi, math.pi), gx, gy, ox, oy]
+    if family == FLYING:
+        return [r.uniform(-5, 5), r.uniform(-5, 5), r.uniform(-math.pi, math.pi), r.uniform(-1, 1), r.uniform(-1, 1),
+                r.uniform(-0.5, 0.5)]
     raise ValueError(family)
 
 
