@@ -533,7 +533,7 @@ def _paper_pendulum(S, W, ctx, args) -> dict:
 
 def _large_blocks(S, ctx, args) -> dict:
     """Iterations/s on the block shapes of the paper's two largest problems (Table 1), and on the
-    flying robot's relaxation itself (N = 60, setup included).  The shapes: car back-in,
+    flying robot's and vehicle landing's relaxations themselves (N = 60 and 50, setup included).  The shapes: car back-in,
     30 moment blocks 190x190 + 659 localizing 19x19; flying robot, 60 moment blocks 231x231 + 659
     localizing 21x21.  The blocks beyond one workgroup's LDS run the multi-workgroup block Jacobi.
     The constraints are synthetic (workloads.synthetic: 20,000 sparse rows, feasible and bounded),
@@ -554,25 +554,29 @@ def _large_blocks(S, ctx, args) -> dict:
                                  f"m 20000 synthetic rows, seed {args.seed + 11}",
                      "iters_per_s": round(100 / (tb - ta), 1), "ms_per_iter": round((tb - ta) * 10, 3),
                      "eta_after": max(inf["eta_p"], inf["eta_d"], inf["eta_g"])}
-    # the paper's flying robot itself (this generator's relaxation, N = 60): setup and iterations/s
+    # the paper's flying robot and vehicle landing themselves (this generator's relaxations at the
+    # paper's horizons): setup and iterations/s
     import workloads as W
-    prm = W.instance_params(W.FLYING, args.seed)
-    t0 = time.perf_counter()
-    prob = S.generate(W.FLYING, 60, prm)
-    ins = S.Instance(ctx, prob, S.default_opts(tol=0.0, maxiter=10**9))
-    t1 = time.perf_counter()
-    ins.step(20)
-    ta = time.perf_counter()
-    inf = ins.step(100)
-    tb = time.perf_counter()
-    ins.close()
-    out["flying_robot_relaxation"] = {
-        "workload": f"the paper's flying robot, N = 60, seed {args.seed}: 60 moment blocks 231x231 + 540 localizing 21x21, "
-                    f"n_svec {prob.nsvec}, m {prob.m}, FP64",
-        "setup_s": round(t1 - t0, 3), "iters_per_s": round(100 / (tb - ta), 1), "ms_per_iter": round((tb - ta) * 10, 3),
-        "eta_after": max(inf["eta_p"], inf["eta_d"], inf["eta_g"])}
-    out["paper_context"] = ("the paper's totals on these problems: car back-in 431.5 s, flying robot 1648 s, at most "
-                            "12,000 iterations each, on an RTX 6000 Ada; context only")
+    for name, fam, N, nL, big, small in (("flying_robot_relaxation", W.FLYING, 60, 9, 231, 21),
+                                         ("vehicle_landing_relaxation", W.LANDING, 50, 7, 190, 19)):
+        prm = W.instance_params(fam, args.seed)
+        t0 = time.perf_counter()
+        prob = S.generate(fam, N, prm)
+        ins = S.Instance(ctx, prob, S.default_opts(tol=0.0, maxiter=10**9))
+        t1 = time.perf_counter()
+        ins.step(20)
+        ta = time.perf_counter()
+        inf = ins.step(100)
+        tb = time.perf_counter()
+        ins.close()
+        out[name] = {
+            "workload": f"the paper's {name.rsplit('_', 1)[0].replace('_', ' ')}, N = {N}, seed {args.seed}: {N} moment "
+                        f"blocks {big}x{big} + {nL * N} localizing {small}x{small}, n_svec {prob.nsvec}, m {prob.m}, FP64",
+            "setup_s": round(t1 - t0, 3), "iters_per_s": round(100 / (tb - ta), 1), "ms_per_iter": round((tb - ta) * 10, 3),
+            "eta_after": max(inf["eta_p"], inf["eta_d"], inf["eta_g"])}
+    out["paper_context"] = ("the paper's totals on these problems: car back-in 431.5 s, flying robot 1648 s (at most "
+                            "12,000 iterations each), vehicle landing 919.2 s (at most 10,000), on an RTX 6000 Ada; "
+                            "context only")
     _log(f"large blocks: {out}")
     return out
 

@@ -18,6 +18,8 @@
  *                                                     [variant, sx, sy, heading0, gx, gy, ox, oy]
  *   5 the paper's flying robot (App. "Flying Robot"; 20-variable cliques, 231x231 / 21x21)
  *                                                     [x0, y0, theta0, vx0, vy0, omega0]
+ *   6 the paper's vehicle landing (App. "Vehicle Landing"; 18-variable cliques, 190x190 / 19x19)
+ *                                                     [x0, y0, theta0, vx0, vy0, omega0]
  *
  * Every function returns 0 on success and a negative strom_status on error.
  */

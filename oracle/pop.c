@@ -160,6 +160,11 @@ int fam_layout(int family, const double *prm, int nprm, int *dx, int *du, double
       sx[0] = sx[1] = sx[2] = sx[3] = 10; sx[4] = sx[5] = sx[6] = sx[7] = 1;
       su[0] = su[1] = su[2] = su[3] = 8;
       return 0;
+    case ORC_LANDING: /* state (rx, ry, vx, vy, rc, rs, fc, fs), thrusts u1, u2; rx/100, ry/120, v/20, u/8 */
+      *dx = 8; *du = 2;
+      sx[0] = 100; sx[1] = 120; sx[2] = sx[3] = 20; sx[4] = sx[5] = sx[6] = sx[7] = 1;
+      su[0] = su[1] = 8;
+      return 0;
     default: return -1;
   }
 }
@@ -424,6 +429,52 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
     if (last)
       for (int i = 0; i < 8; ++i)
         *cost = add_(*cost, scl_(Pf, sq_(sub_(pl_var(L.dx + L.du + i, 1.0), cst(tgt[i])))));
+  } else if (family == ORC_LANDING) {
+    /* the paper's vehicle landing (App. "Vehicle Landing"), Lie-group integrator for the heading:
+     *  r' = r + dt v;  m (vx' - vx) = -dt (u1 + u2) rs;  m (vy' - vy) = dt (u1 + u2) rc - dt m g;
+     *  I (fs' - fs) = L dt^2 (u2 - u1);  (rc', rs') = (rc, rs) rotated by (fc, fs);  unit circles;
+     *  fc' >= fc_min;  u_i (u_max - u_i) >= 0;  |rx| <= rx_max, ry_min <= ry <= ry_max (one
+     *  product), |vx|, |vy| <= v_max.  (The appendix writes the gravity term of the vy update
+     *  without dt; it is read as the impulse dt m g of one step.)  Cost: distance to rest at
+     *  (0, 10) upright plus |u|^2 (scaled variables), terminal weight P_f = 10.  Parameters:
+     *  x0, y0, theta0, vx0, vy0, omega0. */
+    if (nprm < 6) return -1;
+    const double mass = 1, inertia = 50, arm = 5, g = 9.8, dt = 0.2, fcmin = 0.7, umax = 8, Pf = 10;
+    const double rxmax = 100, rymin = 10, rymax = 120, vmax = 20;
+    if (k == 0) {
+      const double init[8] = {prm[0], prm[1], prm[3], prm[4], cos(prm[2]), sin(prm[2]), cos(dt * prm[5]),
+                              sin(dt * prm[5])};
+      for (int i = 0; i < 8; ++i) push(eq, sub_(X0(&L, i), cst(init[i])));
+    }
+    pl_poly T = add_(U(&L, 0), U(&L, 1));
+    push(eq, sub_(sub_(X1(&L, 0), X0(&L, 0)), scl_(dt, X0(&L, 2))));
+    push(eq, sub_(sub_(X1(&L, 1), X0(&L, 1)), scl_(dt, X0(&L, 3))));
+    {
+      pl_poly T2 = pl_copy(&T);
+      push(eq, add_(scl_(mass, sub_(X1(&L, 2), X0(&L, 2))), scl_(dt, mul_(T, X0(&L, 5)))));
+      push(eq, add_(sub_(scl_(mass, sub_(X1(&L, 3), X0(&L, 3))), scl_(dt, mul_(T2, X0(&L, 4)))), cst(dt * mass * g)));
+    }
+    push(eq, sub_(scl_(inertia, sub_(X1(&L, 7), X0(&L, 7))), scl_(arm * dt * dt, sub_(U(&L, 1), U(&L, 0)))));
+    push(eq, sub_(X1(&L, 4), sub_(mul_(X0(&L, 4), X0(&L, 6)), mul_(X0(&L, 5), X0(&L, 7)))));
+    push(eq, sub_(X1(&L, 5), add_(mul_(X0(&L, 5), X0(&L, 6)), mul_(X0(&L, 4), X0(&L, 7)))));
+    push(eq, circle(X1(&L, 4), X1(&L, 5)));
+    push(eq, circle(X1(&L, 6), X1(&L, 7)));
+    if (k >= 1) {
+      push(eq, circle(X0(&L, 4), X0(&L, 5)));
+      push(eq, circle(X0(&L, 6), X0(&L, 7)));
+    }
+    for (int i = 0; i < 2; ++i) push(ineq, mul_(U(&L, i), sub_(cst(umax), U(&L, i))));
+    push(ineq, sub_(X1(&L, 6), cst(fcmin)));
+    push(ineq, sub_(cst(rxmax * rxmax), sq_(X1(&L, 0))));
+    push(ineq, mul_(sub_(X1(&L, 1), cst(rymin)), sub_(cst(rymax), X1(&L, 1))));
+    push(ineq, sub_(cst(vmax * vmax), sq_(X1(&L, 2))));
+    push(ineq, sub_(cst(vmax * vmax), sq_(X1(&L, 3))));
+    const double tgt[8] = {0, 10.0 / 120.0, 0, 0, 1, 0, 1, 0};
+    for (int i = 0; i < 8; ++i) *cost = add_(*cost, sq_(sub_(pl_var(i, 1.0), cst(tgt[i]))));
+    for (int i = 0; i < 2; ++i) *cost = add_(*cost, sq_(pl_var(L.dx + i, 1.0)));
+    if (last)
+      for (int i = 0; i < 8; ++i)
+        *cost = add_(*cost, scl_(Pf, sq_(sub_(pl_var(L.dx + L.du + i, 1.0), cst(tgt[i])))));
   } else {
     return -1;
   }
@@ -490,6 +541,18 @@ int fam_step(int family, const double *prm, int nprm, const double *x0, double *
     Y[6] = sqrt(1 - Y[7] * Y[7]);
     Y[4] = X[4] * X[6] - X[5] * X[7];
     Y[5] = X[5] * X[6] + X[4] * X[7];
+  } else if (family == ORC_LANDING) {
+    const double mass = 1, inertia = 50, arm = 5, g = 9.8, dt = 0.2;
+    const double T = Uo[0] + Uo[1];
+    Y[0] = X[0] + dt * X[2];
+    Y[1] = X[1] + dt * X[3];
+    Y[2] = X[2] - dt * T * X[5] / mass;
+    Y[3] = X[3] + dt * T * X[4] / mass - dt * g;
+    Y[7] = X[7] + arm * dt * dt * (Uo[1] - Uo[0]) / inertia;
+    if (fabs(Y[7]) > 1) return -2;
+    Y[6] = sqrt(1 - Y[7] * Y[7]);
+    Y[4] = X[4] * X[6] - X[5] * X[7];
+    Y[5] = X[5] * X[6] + X[4] * X[7];
   } else {
     return -1;
   }
@@ -511,7 +574,7 @@ int fam_init_state(int family, const double *prm, int nprm, double *x0) {
     X[0] = cos(prm[0]); X[1] = sin(prm[0]); X[2] = cos(0.1 * prm[1]); X[3] = sin(0.1 * prm[1]);
   } else if (family == ORC_CAR) {
     X[0] = prm[1]; X[1] = prm[2]; X[2] = cos(prm[3]); X[3] = sin(prm[3]); X[4] = 0;
-  } else if (family == ORC_FLYING) {
+  } else if (family == ORC_FLYING || family == ORC_LANDING) {
     X[0] = prm[0]; X[1] = prm[1]; X[2] = prm[3]; X[3] = prm[4];
     X[4] = cos(prm[2]); X[5] = sin(prm[2]); X[6] = cos(0.2 * prm[5]); X[7] = sin(0.2 * prm[5]);
   } else return -1;
@@ -542,6 +605,11 @@ int fam_var_bounds(int family, const double *prm, int nprm, double *bnd) {
     bx[2] = fmax(10.0, fabs(prm[3])) / sx[2]; bx[3] = fmax(10.0, fabs(prm[4])) / sx[3];
     bx[4] = bx[5] = bx[6] = bx[7] = 1;
     bu[0] = bu[1] = bu[2] = bu[3] = 1;
+  } else if (family == ORC_LANDING) {  /* |rx| <= 100, 10 <= ry <= 120, |vx|, |vy| <= 20, circles, 0 <= u <= 8 */
+    bx[0] = fmax(100.0, fabs(prm[0])) / sx[0]; bx[1] = fmax(120.0, fabs(prm[1])) / sx[1];
+    bx[2] = fmax(20.0, fabs(prm[3])) / sx[2]; bx[3] = fmax(20.0, fabs(prm[4])) / sx[3];
+    bx[4] = bx[5] = bx[6] = bx[7] = 1;
+    bu[0] = bu[1] = 1;
   } else {
     return -1;
   }

@@ -142,6 +142,7 @@ bool make_layout(int family, const double *p, int np, Layout &L) {
       if (p[0] != 0.0) setu({2, 1, 1}); else setu({2, 1});
       return true;
     case 5: if (np < 6) return false; setx({10, 10, 10, 10, 1, 1, 1, 1}); setu({8, 8, 8, 8}); return true;
+    case 6: if (np < 6) return false; setx({100, 120, 20, 20, 1, 1, 1, 1}); setu({8, 8}); return true;
     default: return false;
   }
 }
@@ -266,6 +267,40 @@ CliquePolys clique_polys(int family, int N, int k, const double *p, const Layout
     for (int i = 0; i < 4; ++i) q.cost = q.cost + sq(L.zu(i));
     if (last)
       for (int i = 0; i < 8; ++i) q.cost = q.cost + Pf * sq(L.zx1(i) - target[i]);
+  } else if (family == 6) {  // the paper's vehicle landing: two thrusters, Lie-group heading update
+    // (the vy update's gravity term is read as the impulse dt m g of one step)
+    const double mass = 1, inertia = 50, arm = 5, g = 9.8, dt = 0.2, fcmin = 0.7, umax = 8, Pf = 10;
+    const double rxmax = 100, rymin = 10, rymax = 120, vmax = 20;
+    if (first) {
+      const double init[8] = {p[0], p[1], p[3], p[4], std::cos(p[2]), std::sin(p[2]), std::cos(dt * p[5]),
+                              std::sin(dt * p[5])};
+      for (int i = 0; i < 8; ++i) q.eq.push_back(L.x0(i) - init[i]);
+    }
+    const Poly thrust = L.u(0) + L.u(1);
+    q.eq.push_back(L.x1(0) - L.x0(0) - dt * L.x0(2));
+    q.eq.push_back(L.x1(1) - L.x0(1) - dt * L.x0(3));
+    q.eq.push_back(mass * (L.x1(2) - L.x0(2)) + dt * (thrust * L.x0(5)));
+    q.eq.push_back(mass * (L.x1(3) - L.x0(3)) - dt * (thrust * L.x0(4)) + dt * mass * g);
+    q.eq.push_back(inertia * (L.x1(7) - L.x0(7)) - (arm * dt * dt) * (L.u(1) - L.u(0)));
+    q.eq.push_back(L.x1(4) - (L.x0(4) * L.x0(6) - L.x0(5) * L.x0(7)));
+    q.eq.push_back(L.x1(5) - (L.x0(5) * L.x0(6) + L.x0(4) * L.x0(7)));
+    q.eq.push_back(unit_circle(L.x1(4), L.x1(5)));
+    q.eq.push_back(unit_circle(L.x1(6), L.x1(7)));
+    if (!first) {
+      q.eq.push_back(unit_circle(L.x0(4), L.x0(5)));
+      q.eq.push_back(unit_circle(L.x0(6), L.x0(7)));
+    }
+    for (int i = 0; i < 2; ++i) q.ineq.push_back(L.u(i) * (umax - L.u(i)));
+    q.ineq.push_back(L.x1(6) - fcmin);
+    q.ineq.push_back(rxmax * rxmax - sq(L.x1(0)));
+    q.ineq.push_back((L.x1(1) - rymin) * (rymax - L.x1(1)));
+    q.ineq.push_back(vmax * vmax - sq(L.x1(2)));
+    q.ineq.push_back(vmax * vmax - sq(L.x1(3)));
+    const double target[8] = {0, 10.0 / 120.0, 0, 0, 1, 0, 1, 0};
+    for (int i = 0; i < 8; ++i) q.cost = q.cost + sq(L.zx0(i) - target[i]);
+    for (int i = 0; i < 2; ++i) q.cost = q.cost + sq(L.zu(i));
+    if (last)
+      for (int i = 0; i < 8; ++i) q.cost = q.cost + Pf * sq(L.zx1(i) - target[i]);
   } else {  // planar car with one circular obstacle
     const bool bicycle = p[0] != 0.0;
     const double dt = 0.1, Pf = 10;
@@ -322,6 +357,11 @@ bool var_bounds(int family, const double *p, const Layout &L, std::vector<double
       bx = {std::max(1.0, std::fabs(p[0]) / 10), std::max(1.0, std::fabs(p[1]) / 10),
             std::max(1.0, std::fabs(p[3]) / 10), std::max(1.0, std::fabs(p[4]) / 10), 1.0, 1.0, 1.0, 1.0};
       bu = {1.0, 1.0, 1.0, 1.0};
+      return true;
+    case 6:  // |rx| <= 100, 10 <= ry <= 120, |vx|, |vy| <= 20 (scaled by 100, 120, 20, 20), circles, 0 <= u <= 8
+      bx = {std::max(1.0, std::fabs(p[0]) / 100), std::max(1.0, std::fabs(p[1]) / 120),
+            std::max(1.0, std::fabs(p[3]) / 20), std::max(1.0, std::fabs(p[4]) / 20), 1.0, 1.0, 1.0, 1.0};
+      bu = {1.0, 1.0};
       return true;
     default: return false;
   }

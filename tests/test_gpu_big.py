@@ -209,14 +209,16 @@ def test_big_boundary_sizes(S, ctx, orc):
         ctx.project_psd_batched(nd, od, x32, x32, 123)
 
 
-def test_flying_robot_iterates(S, ctx, orc):
-    """The paper's flying robot relaxation (231 x 231 moment blocks through the block Jacobi, 21 x 21
-    localizing blocks), N = 2: iterates after 1 and 6 iterations with a fixed sigma against the
-    oracle (its own generator, LDL^T and Jacobi)."""
+@pytest.mark.parametrize("fam_name", ["FLYING", "LANDING"])
+def test_paper_family_iterates(S, ctx, orc, fam_name):
+    """The paper's flying robot (231 x 231 moment blocks) and vehicle landing (190 x 190) relaxations,
+    whose moment blocks take the block Jacobi, N = 2: iterates after 1 and 6 iterations with a fixed
+    sigma against the oracle (its own generator, LDL^T and Jacobi)."""
     import workloads as W
-    prm = W.instance_params(W.FLYING, 0)
-    osdp = orc.relax(W.FLYING, 2, prm)
-    prob = S.generate(W.FLYING, 2, prm)
+    fam = getattr(W, fam_name)
+    prm = W.instance_params(fam, 0)
+    osdp = orc.relax(fam, 2, prm)
+    prob = S.generate(fam, 2, prm)
     inst = S.Instance(ctx, prob, S.default_opts(sigma_every=0, kkt_every=1, tol=0.0))
     for k in [1, 6]:
         inst.set_iterate(np.zeros(prob.nsvec), np.zeros(prob.m), np.zeros(prob.nsvec))

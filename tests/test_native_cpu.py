@@ -52,6 +52,7 @@ CASES = [
     (4, 3, [0, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
     (4, 3, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
     (5, 2, [3.0, -2.0, 0.5, 0.5, -0.5, 0.2]),
+    (6, 2, [5.0, 80.0, 0.1, 0.5, -1.0, 0.05]),
 ]
 
 
@@ -123,7 +124,8 @@ def test_bench_refuses_more_than_one_gpu():
 def test_trace_bounds_agree_with_the_oracle(orc):
     import paper_2406_05846_amd as S
     import workloads as W
-    for fam, N, seed in [(W.CARTPOLE, 5, 0), (W.CAR, 4, 0), (W.CAR, 4, 1), (W.PAPER_PENDULUM, 3, 0), (W.FLYING, 2, 0)]:
+    for fam, N, seed in [(W.CARTPOLE, 5, 0), (W.CAR, 4, 0), (W.CAR, 4, 1), (W.PAPER_PENDULUM, 3, 0), (W.FLYING, 2, 0),
+                         (W.LANDING, 2, 0)]:
         prm = W.instance_params(fam, seed)
         ref = orc.trace_bounds(fam, N, prm)
         got = S.generate(fam, N, prm).trace_bounds

@@ -143,6 +143,20 @@ def test_flying_robot_sizes(orc):
     assert sdp.m + extra * (21 * 22 // 2) == gold["m_paper"]
 
 
+def test_vehicle_landing_sizes(orc):
+    """The paper's vehicle landing at its horizon: 50 moment blocks of 190 = s(18, 2) (d_x = 8,
+    d_u = 2) and localizing blocks of 19 = s(18, 1), as in Table 1; seven inequalities per clique;
+    Table 1's m once the rows of the localizing matrices its count has beyond them are added."""
+    gold = json.load(open(os.path.join(GOLD, "paper_sizes.json")))["vehicle_landing"]
+    sdp = orc.relax(orc.LANDING, gold["N"], [5.0, 80.0, 0.1, 0.5, -1.0, 0.05])
+    kinds = sdp.bkind
+    assert (kinds == 0).sum() == gold["num_M"] and set(sdp.bsize[kinds == 0]) == {gold["size_M"]}
+    assert set(sdp.bsize[kinds == 1]) == {gold["size_L"]}
+    assert (kinds == 1).sum() == 7 * gold["N"]
+    extra = gold["num_L_paper"] - int((kinds == 1).sum())
+    assert sdp.m + extra * (19 * 20 // 2) == gold["m_paper"]
+
+
 def test_flying_robot_row_counts(orc):
     """m of the flying robot from the same closed form as the other families: per clique k >= 1
     three equalities of degree 1 (position updates, f_s update) and eight of degree 2 (velocity
@@ -193,6 +207,7 @@ FAMS = [
     ("CAR", 4, [0, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1], 0.5),
     ("CAR", 4, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1], 0.5),
     ("FLYING", 3, [3.0, -2.0, 0.5, 0.5, -0.5, 0.2], 1.0),
+    ("LANDING", 3, [5.0, 80.0, 0.1, 0.5, -1.0, 0.05], 1.0),
 ]
 
 

@@ -11,14 +11,16 @@ Parameter vectors, per family (angles in radians, original units):
   cartpole [x0, v0, theta0, omega0]
   car      [variant, sx, sy, heading0, gx, gy, ox, oy]   variant 0 unicycle-12, 1 bicycle-13
   flying   [x0, y0, theta0, vx0, vy0, omega0]      the paper's flying robot (rest at the origin is the goal)
+  landing  [x0, y0, theta0, vx0, vy0, omega0]      the paper's vehicle landing (rest at (0, 10) is the goal)
 """
 from __future__ import annotations
 
 import math
 
-TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING = 0, 1, 2, 3, 4, 5
+TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING, LANDING = 0, 1, 2, 3, 4, 5, 6
 FAMILY_NAMES = {TOY1D: "toy1d", PENDULUM: "pendulum", CARTPOLE: "cartpole",
-                PAPER_PENDULUM: "paper_pendulum", CAR: "car", FLYING: "flying"}
+                PAPER_PENDULUM: "paper_pendulum", CAR: "car", FLYING: "flying",
+                LANDING: "landing"}
 _MASK = (1 << 64) - 1
 
 
@@ -71,6 +73,9 @@ def instance_params(family: int, seed: int) -> list:
     if family == FLYING:
         return [r.uniform(-5, 5), r.uniform(-5, 5), r.uniform(-math.pi, math.pi), r.uniform(-1, 1), r.uniform(-1, 1),
                 r.uniform(-0.5, 0.5)]
+    if family == LANDING:
+        return [r.uniform(-20, 20), r.uniform(60, 100), r.uniform(-0.3, 0.3), r.uniform(-2, 2), r.uniform(-2, 2),
+                r.uniform(-0.2, 0.2)]
     raise ValueError(family)
 
 
