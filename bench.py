@@ -533,7 +533,8 @@ def _paper_pendulum(S, W, ctx, args) -> dict:
 
 def _large_blocks(S, ctx, args) -> dict:
     """Iterations/s on the block shapes of the paper's two largest problems (Table 1), and on the
-    flying robot's and vehicle landing's relaxations themselves (N = 60 and 50, setup included).  The shapes: car back-in,
+    relaxations of the paper's flying robot, vehicle landing and car back-in themselves (N = 60, 50
+    and 30, setup included).  The shapes: car back-in,
     30 moment blocks 190x190 + 659 localizing 19x19; flying robot, 60 moment blocks 231x231 + 659
     localizing 21x21.  The blocks beyond one workgroup's LDS run the multi-workgroup block Jacobi.
     The constraints are synthetic (workloads.synthetic: 20,000 sparse rows, feasible and bounded),
@@ -554,11 +555,12 @@ def _large_blocks(S, ctx, args) -> dict:
                                  f"m 20000 synthetic rows, seed {args.seed + 11}",
                      "iters_per_s": round(100 / (tb - ta), 1), "ms_per_iter": round((tb - ta) * 10, 3),
                      "eta_after": max(inf["eta_p"], inf["eta_d"], inf["eta_g"])}
-    # the paper's flying robot and vehicle landing themselves (this generator's relaxations at the
-    # paper's horizons): setup and iterations/s
+    # the paper's flying robot, vehicle landing and car back-in themselves (this generator's
+    # relaxations at the paper's horizons): setup and iterations/s
     import workloads as W
     for name, fam, N, nL, big, small in (("flying_robot_relaxation", W.FLYING, 60, 9, 231, 21),
-                                         ("vehicle_landing_relaxation", W.LANDING, 50, 7, 190, 19)):
+                                         ("vehicle_landing_relaxation", W.LANDING, 50, 7, 190, 19),
+                                         ("car_back_in_relaxation", W.BACKIN, 30, 20, 190, 19)):
         prm = W.instance_params(fam, args.seed)
         t0 = time.perf_counter()
         prob = S.generate(fam, N, prm)

@@ -20,6 +20,7 @@
  *                                                     [x0, y0, theta0, vx0, vy0, omega0]
  *   6 the paper's vehicle landing (App. "Vehicle Landing"; 18-variable cliques, 190x190 / 19x19)
  *                                                     [x0, y0, theta0, vx0, vy0, omega0]
+ *   7 the paper's car back-in (App. "Car Back-in"; 18-variable cliques, 190x190 / 19x19) [x0, y0, theta0]
  *
  * Every function returns 0 on success and a negative strom_status on error.
  */

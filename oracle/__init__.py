@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRCS = ["pop.c", "relax.c", "ldl.c", "jacobi.c", "admm.c", "cert.c"]
 
-TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING, LANDING = 0, 1, 2, 3, 4, 5, 6
+TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING, LANDING, BACKIN = 0, 1, 2, 3, 4, 5, 6, 7
 ROW_NORM, ROW_MOMENT, ROW_LOCALIZING, ROW_EQUALITY, ROW_CONSENSUS = 0, 1, 2, 3, 4
 
 

@@ -33,7 +33,8 @@ enum {
   ORC_PAPER_PENDULUM = 3, /* the paper's variational-integrator pendulum (sizes only)   */
   ORC_CAR = 4,            /* planar car, unicycle-12 / bicycle-13, one obstacle          */
   ORC_FLYING = 5,         /* the paper's flying robot (App. "Flying Robot"), 20-var cliques */
-  ORC_LANDING = 6         /* the paper's vehicle landing (App. "Vehicle Landing"), 18-var cliques */
+  ORC_LANDING = 6,        /* the paper's vehicle landing (App. "Vehicle Landing"), 18-var cliques */
+  ORC_BACKIN = 7          /* the paper's car back-in (App. "Car Back-in"), 18-var cliques */
 };
 
 /* Row types, in the order they are generated inside a clique. */

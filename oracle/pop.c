@@ -165,6 +165,13 @@ int fam_layout(int family, const double *prm, int nprm, int *dx, int *du, double
       sx[0] = 100; sx[1] = 120; sx[2] = sx[3] = 20; sx[4] = sx[5] = sx[6] = sx[7] = 1;
       su[0] = su[1] = 8;
       return 0;
+    case ORC_BACKIN: /* state (rx, ry, rc, rs); per step (v, w, fc, fs) and the separating lines
+                      * (A1, B1, C1), (A2, B2, C2); r/10, v/4, w/0.5 */
+      *dx = 4; *du = 10;
+      sx[0] = sx[1] = 10; sx[2] = sx[3] = 1;
+      su[0] = 4; su[1] = 0.5;
+      for (int i = 2; i < 10; ++i) su[i] = 1;
+      return 0;
     default: return -1;
   }
 }
@@ -475,6 +482,60 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
     if (last)
       for (int i = 0; i < 8; ++i)
         *cost = add_(*cost, scl_(Pf, sq_(sub_(pl_var(L.dx + L.du + i, 1.0), cst(tgt[i])))));
+  } else if (family == ORC_BACKIN) {
+    /* the paper's car back-in (App. "Car Back-in"): simple car r' = r + dt v (rc, rs), heading
+     * rotated by (fc, fs) with fs = dt w - (dt w)^3 / 6; unit circles; no collision of the car (a
+     * 6 x 2.5 rectangle at x_{k+1}) with two 8 x 8 squares centred at (6, -4) and (-6, -4), as
+     * separating lines A x + B y + C (>= 0 at the car's corners, <= 0 at the square's) with
+     * A^2 + B^2 + C^2 = 1; boxes |rx| <= |x0| + 2, |ry| <= 8, |v| <= 4, |w| <= 0.5.  Cost: distance
+     * to (0, -3) heading pi/2 plus |(v, w, fc, fs)|^2 (scaled), terminal weight P_f = 10.
+     * Parameters: x0, y0, theta0. */
+    if (nprm < 3) return -1;
+    const double dt = 0.25, Lc = 6, Wc = 2.5, Pf = 10, rymax = 8, vmax = 4, wmax = 0.5;
+    const double rxmax = fabs(prm[0]) + 2;
+    if (k == 0) {
+      const double init[4] = {prm[0], prm[1], cos(prm[2]), sin(prm[2])};
+      for (int i = 0; i < 4; ++i) push(eq, sub_(X0(&L, i), cst(init[i])));
+    }
+    push(eq, sub_(sub_(X1(&L, 0), X0(&L, 0)), scl_(dt, mul_(U(&L, 0), X0(&L, 2)))));
+    push(eq, sub_(sub_(X1(&L, 1), X0(&L, 1)), scl_(dt, mul_(U(&L, 0), X0(&L, 3)))));
+    {
+      pl_poly a = scl_(dt, U(&L, 1));
+      pl_poly a3 = mul_(mul_(pl_copy(&a), pl_copy(&a)), pl_copy(&a));
+      push(eq, add_(sub_(U(&L, 3), a), scl_(1.0 / 6.0, a3)));
+    }
+    push(eq, sub_(X1(&L, 2), sub_(mul_(X0(&L, 2), U(&L, 2)), mul_(X0(&L, 3), U(&L, 3)))));
+    push(eq, sub_(X1(&L, 3), add_(mul_(X0(&L, 3), U(&L, 2)), mul_(X0(&L, 2), U(&L, 3)))));
+    push(eq, circle(X1(&L, 2), X1(&L, 3)));
+    push(eq, circle(U(&L, 2), U(&L, 3)));
+    if (k >= 1) push(eq, circle(X0(&L, 2), X0(&L, 3)));
+    for (int o = 0; o < 2; ++o)
+      push(eq, sub_(add_(add_(sq_(U(&L, 4 + 3 * o)), sq_(U(&L, 5 + 3 * o))), sq_(U(&L, 6 + 3 * o))), cst(1)));
+    const double cx[2] = {6, -6}, cy[2] = {-4, -4};
+    const double sgn[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};  /* corner i: (+-L/2, +-W/2) */
+    for (int o = 0; o < 2; ++o) {
+      for (int i = 0; i < 4; ++i) {  /* corner i of the car, in the car's frame (sgn L/2, sgn W/2) */
+        const double a = sgn[i][0] * Lc / 2, b = sgn[i][1] * Wc / 2;
+        /* xc = x + a c - b s,  yc = y + a s + b c */
+        pl_poly xc = add_(X1(&L, 0), sub_(scl_(a, X1(&L, 2)), scl_(b, X1(&L, 3))));
+        pl_poly yc = add_(X1(&L, 1), add_(scl_(a, X1(&L, 3)), scl_(b, X1(&L, 2))));
+        push(ineq, add_(add_(mul_(U(&L, 4 + 3 * o), xc), mul_(U(&L, 5 + 3 * o), yc)), U(&L, 6 + 3 * o)));
+      }
+      for (int j = 0; j < 4; ++j) {  /* corner j of square o */
+        const double xo = cx[o] + sgn[j][0] * 4, yo = cy[o] + sgn[j][1] * 4;
+        push(ineq, scl_(-1.0, add_(add_(scl_(xo, U(&L, 4 + 3 * o)), scl_(yo, U(&L, 5 + 3 * o))), U(&L, 6 + 3 * o))));
+      }
+    }
+    push(ineq, sub_(cst(rxmax * rxmax), sq_(X1(&L, 0))));
+    push(ineq, sub_(cst(rymax * rymax), sq_(X1(&L, 1))));
+    push(ineq, sub_(cst(vmax * vmax), sq_(U(&L, 0))));
+    push(ineq, sub_(cst(wmax * wmax), sq_(U(&L, 1))));
+    const double tgt[4] = {0, -0.3, 0, 1};
+    for (int i = 0; i < 4; ++i) *cost = add_(*cost, sq_(sub_(pl_var(i, 1.0), cst(tgt[i]))));
+    for (int i = 0; i < 4; ++i) *cost = add_(*cost, sq_(pl_var(L.dx + i, 1.0)));
+    if (last)
+      for (int i = 0; i < 4; ++i)
+        *cost = add_(*cost, scl_(Pf, sq_(sub_(pl_var(L.dx + L.du + i, 1.0), cst(tgt[i])))));
   } else {
     return -1;
   }
@@ -553,6 +614,22 @@ int fam_step(int family, const double *prm, int nprm, const double *x0, double *
     Y[6] = sqrt(1 - Y[7] * Y[7]);
     Y[4] = X[4] * X[6] - X[5] * X[7];
     Y[5] = X[5] * X[6] + X[4] * X[7];
+  } else if (family == ORC_BACKIN) {
+    /* (fc, fs) from w; each separating line scaled to the unit sphere (or (0, 0, 1)) */
+    const double dt = 0.25, a = dt * Uo[1];
+    Uo[3] = a - a * a * a / 6;
+    if (fabs(Uo[3]) > 1) return -2;
+    Uo[2] = sqrt(1 - Uo[3] * Uo[3]);
+    for (int o = 0; o < 2; ++o) {
+      double *l = Uo + 4 + 3 * o;
+      const double nrm = sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+      if (nrm > 0) { l[0] /= nrm; l[1] /= nrm; l[2] /= nrm; } else { l[0] = l[1] = 0; l[2] = 1; }
+    }
+    for (int i = 2; i < 10; ++i) u[i] = Uo[i] / su[i];
+    Y[0] = X[0] + dt * Uo[0] * X[2];
+    Y[1] = X[1] + dt * Uo[0] * X[3];
+    Y[2] = X[2] * Uo[2] - X[3] * Uo[3];
+    Y[3] = X[3] * Uo[2] + X[2] * Uo[3];
   } else {
     return -1;
   }
@@ -574,6 +651,8 @@ int fam_init_state(int family, const double *prm, int nprm, double *x0) {
     X[0] = cos(prm[0]); X[1] = sin(prm[0]); X[2] = cos(0.1 * prm[1]); X[3] = sin(0.1 * prm[1]);
   } else if (family == ORC_CAR) {
     X[0] = prm[1]; X[1] = prm[2]; X[2] = cos(prm[3]); X[3] = sin(prm[3]); X[4] = 0;
+  } else if (family == ORC_BACKIN) {
+    X[0] = prm[0]; X[1] = prm[1]; X[2] = cos(prm[2]); X[3] = sin(prm[2]);
   } else if (family == ORC_FLYING || family == ORC_LANDING) {
     X[0] = prm[0]; X[1] = prm[1]; X[2] = prm[3]; X[3] = prm[4];
     X[4] = cos(prm[2]); X[5] = sin(prm[2]); X[6] = cos(0.2 * prm[5]); X[7] = sin(0.2 * prm[5]);

@@ -143,6 +143,7 @@ bool make_layout(int family, const double *p, int np, Layout &L) {
       return true;
     case 5: if (np < 6) return false; setx({10, 10, 10, 10, 1, 1, 1, 1}); setu({8, 8, 8, 8}); return true;
     case 6: if (np < 6) return false; setx({100, 120, 20, 20, 1, 1, 1, 1}); setu({8, 8}); return true;
+    case 7: if (np < 3) return false; setx({10, 10, 1, 1}); setu({4, 0.5, 1, 1, 1, 1, 1, 1, 1, 1}); return true;
     default: return false;
   }
 }
@@ -301,6 +302,47 @@ CliquePolys clique_polys(int family, int N, int k, const double *p, const Layout
     for (int i = 0; i < 2; ++i) q.cost = q.cost + sq(L.zu(i));
     if (last)
       for (int i = 0; i < 8; ++i) q.cost = q.cost + Pf * sq(L.zx1(i) - target[i]);
+  } else if (family == 7) {  // the paper's car back-in: two square obstacles, separating lines per step
+    // u = (v, w, fc, fs, A1, B1, C1, A2, B2, C2); the car's corners are taken at x_{k+1}
+    const double dt = 0.25, Lc = 6, Wc = 2.5, Pf = 10, rymax = 8, vmax = 4, wmax = 0.5;
+    const double rxmax = std::fabs(p[0]) + 2;
+    if (first) {
+      const double init[4] = {p[0], p[1], std::cos(p[2]), std::sin(p[2])};
+      for (int i = 0; i < 4; ++i) q.eq.push_back(L.x0(i) - init[i]);
+    }
+    q.eq.push_back(L.x1(0) - L.x0(0) - dt * (L.u(0) * L.x0(2)));
+    q.eq.push_back(L.x1(1) - L.x0(1) - dt * (L.u(0) * L.x0(3)));
+    const Poly a = dt * L.u(1);
+    q.eq.push_back(L.u(3) - a + (1.0 / 6.0) * (a * a * a));
+    q.eq.push_back(L.x1(2) - (L.x0(2) * L.u(2) - L.x0(3) * L.u(3)));
+    q.eq.push_back(L.x1(3) - (L.x0(3) * L.u(2) + L.x0(2) * L.u(3)));
+    q.eq.push_back(unit_circle(L.x1(2), L.x1(3)));
+    q.eq.push_back(unit_circle(L.u(2), L.u(3)));
+    if (!first) q.eq.push_back(unit_circle(L.x0(2), L.x0(3)));
+    for (int o = 0; o < 2; ++o)
+      q.eq.push_back(sq(L.u(4 + 3 * o)) + sq(L.u(5 + 3 * o)) + sq(L.u(6 + 3 * o)) - 1.0);
+    const double cx[2] = {6, -6}, cy[2] = {-4, -4};
+    const double sgn[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+    for (int o = 0; o < 2; ++o) {
+      const Poly A = L.u(4 + 3 * o), B = L.u(5 + 3 * o), Cl = L.u(6 + 3 * o);
+      for (int i = 0; i < 4; ++i) {  // the car's corner (sgn L/2, sgn W/2) in its own frame
+        const double ca = sgn[i][0] * Lc / 2, cb = sgn[i][1] * Wc / 2;
+        const Poly xc = L.x1(0) + (ca * L.x1(2) - cb * L.x1(3));
+        const Poly yc = L.x1(1) + (ca * L.x1(3) + cb * L.x1(2));
+        q.ineq.push_back(A * xc + B * yc + Cl);
+      }
+      for (int j = 0; j < 4; ++j)  // the square's corner
+        q.ineq.push_back(-1.0 * ((cx[o] + sgn[j][0] * 4) * A + (cy[o] + sgn[j][1] * 4) * B + Cl));
+    }
+    q.ineq.push_back(rxmax * rxmax - sq(L.x1(0)));
+    q.ineq.push_back(rymax * rymax - sq(L.x1(1)));
+    q.ineq.push_back(vmax * vmax - sq(L.u(0)));
+    q.ineq.push_back(wmax * wmax - sq(L.u(1)));
+    const double target[4] = {0, -0.3, 0, 1};
+    for (int i = 0; i < 4; ++i) q.cost = q.cost + sq(L.zx0(i) - target[i]);
+    for (int i = 0; i < 4; ++i) q.cost = q.cost + sq(L.zu(i));
+    if (last)
+      for (int i = 0; i < 4; ++i) q.cost = q.cost + Pf * sq(L.zx1(i) - target[i]);
   } else {  // planar car with one circular obstacle
     const bool bicycle = p[0] != 0.0;
     const double dt = 0.1, Pf = 10;

@@ -209,9 +209,10 @@ def test_big_boundary_sizes(S, ctx, orc):
         ctx.project_psd_batched(nd, od, x32, x32, 123)
 
 
-@pytest.mark.parametrize("fam_name", ["FLYING", "LANDING"])
+@pytest.mark.parametrize("fam_name", ["FLYING", "LANDING", "BACKIN"])
 def test_paper_family_iterates(S, ctx, orc, fam_name):
-    """The paper's flying robot (231 x 231 moment blocks) and vehicle landing (190 x 190) relaxations,
+    """The paper's flying robot (231 x 231 moment blocks), vehicle landing and car back-in (190 x 190)
+    relaxations,
     whose moment blocks take the block Jacobi, N = 2: iterates after 1 and 6 iterations with a fixed
     sigma against the oracle (its own generator, LDL^T and Jacobi)."""
     import workloads as W

@@ -53,6 +53,7 @@ CASES = [
     (4, 3, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
     (5, 2, [3.0, -2.0, 0.5, 0.5, -0.5, 0.2]),
     (6, 2, [5.0, 80.0, 0.1, 0.5, -1.0, 0.05]),
+    (7, 2, [3.0, 4.0, 0.1]),
 ]
 
 

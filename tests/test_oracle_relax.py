@@ -157,6 +157,21 @@ def test_vehicle_landing_sizes(orc):
     assert sdp.m + extra * (19 * 20 // 2) == gold["m_paper"]
 
 
+def test_car_back_in_sizes(orc):
+    """The paper's car back-in at its horizon: 30 moment blocks of 190 = s(18, 2) (x_k and x_{k+1}
+    of 4, the step's v, w, f_c, f_s and the two separating lines' six coefficients) and localizing
+    blocks of 19, as in Table 1; 20 inequalities per clique (16 separations, 4 boxes); Table 1's m
+    once the rows of the localizing matrices its count has beyond them are added."""
+    gold = json.load(open(os.path.join(GOLD, "paper_sizes.json")))["car_back_in"]
+    sdp = orc.relax(orc.BACKIN, gold["N"], [3.0, 4.0, 0.1])
+    kinds = sdp.bkind
+    assert (kinds == 0).sum() == gold["num_M"] and set(sdp.bsize[kinds == 0]) == {gold["size_M"]}
+    assert set(sdp.bsize[kinds == 1]) == {gold["size_L"]}
+    assert (kinds == 1).sum() == 20 * gold["N"]
+    extra = gold["num_L_paper"] - int((kinds == 1).sum())
+    assert sdp.m + extra * (19 * 20 // 2) == gold["m_paper"]
+
+
 def test_flying_robot_row_counts(orc):
     """m of the flying robot from the same closed form as the other families: per clique k >= 1
     three equalities of degree 1 (position updates, f_s update) and eight of degree 2 (velocity
@@ -208,6 +223,7 @@ FAMS = [
     ("CAR", 4, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1], 0.5),
     ("FLYING", 3, [3.0, -2.0, 0.5, 0.5, -0.5, 0.2], 1.0),
     ("LANDING", 3, [5.0, 80.0, 0.1, 0.5, -1.0, 0.05], 1.0),
+    ("BACKIN", 3, [3.0, 4.0, 0.1], 1.0),
 ]
 
 

@@ -12,15 +12,16 @@ Parameter vectors, per family (angles in radians, original units):
   car      [variant, sx, sy, heading0, gx, gy, ox, oy]   variant 0 unicycle-12, 1 bicycle-13
   flying   [x0, y0, theta0, vx0, vy0, omega0]      the paper's flying robot (rest at the origin is the goal)
   landing  [x0, y0, theta0, vx0, vy0, omega0]      the paper's vehicle landing (rest at (0, 10) is the goal)
+  backin   [x0, y0, theta0]                        the paper's car back-in (goal (0, -3), heading pi/2)
 """
 from __future__ import annotations
 
 import math
 
-TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING, LANDING = 0, 1, 2, 3, 4, 5, 6
+TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING, LANDING, BACKIN = 0, 1, 2, 3, 4, 5, 6, 7
 FAMILY_NAMES = {TOY1D: "toy1d", PENDULUM: "pendulum", CARTPOLE: "cartpole",
                 PAPER_PENDULUM: "paper_pendulum", CAR: "car", FLYING: "flying",
-                LANDING: "landing"}
+                LANDING: "landing", BACKIN: "backin"}
 _MASK = (1 << 64) - 1
 
 
@@ -76,6 +77,8 @@ def instance_params(family: int, seed: int) -> list:
     if family == LANDING:
         return [r.uniform(-20, 20), r.uniform(60, 100), r.uniform(-0.3, 0.3), r.uniform(-2, 2), r.uniform(-2, 2),
                 r.uniform(-0.2, 0.2)]
+    if family == BACKIN:  # above the slot between the two squares, roughly level
+        return [r.uniform(2, 5), r.uniform(2, 5), r.uniform(-0.3, 0.3)]
     raise ValueError(family)
 
 
