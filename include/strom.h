@@ -271,7 +271,8 @@ strom_status strom_batch_destroy(strom_batch *batch);
  * iterates on the device, advances every admitted instance, retires an instance when it
  * converges (or reaches maxiter, or diverges) and admits the next.  strom_poll returns
  * E_AGAIN while the ticket is in flight; once done it fills info (and the optional host
- * arrays) and forgets the ticket. */
+ * arrays) and forgets the ticket.  The loop iterates merged batches: a problem with blocks
+ * beyond one workgroup's LDS (see strom_sdp_setup) is refused with E_INVAL. */
 strom_status strom_submit(strom_ctx *ctx, const strom_problem *problem, const strom_opts *opts,
                           uint64_t *ticket);
 strom_status strom_poll(strom_ctx *ctx, uint64_t ticket, strom_info *out, double *X_svec,

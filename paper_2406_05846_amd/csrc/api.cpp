@@ -1427,6 +1427,13 @@ extern "C" strom_status strom_batch_destroy(strom_batch *b) {
 extern "C" strom_status strom_submit(strom_ctx *ctx, const strom_problem *P, const strom_opts *opts,
                                      uint64_t *ticket) {
   if (!ctx || !P || !ticket) return fail(STROM_E_INVAL, "NULL argument");
+  // the request loop iterates merged batches, which take blocks of the one-workgroup projection
+  // only; a problem with larger blocks is set up and iterated on its own (strom_sdp_setup)
+  if (P->block_sizes)
+    for (int32_t k = 0; k < P->nblocks; ++k)
+      if (P->block_sizes[k] > 0 && !fits_lds(ctx, P->block_sizes[k]))
+        return fail(STROM_E_INVAL, "block of size " + std::to_string(P->block_sizes[k]) +
+                                       " is beyond the one-workgroup projection, which the request loop needs");
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (!ctx->server) ctx->server = strom::server_start(ctx);

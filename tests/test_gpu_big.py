@@ -174,6 +174,21 @@ def test_big_batch_rejected(S, ctx, orc):
     inst.close()
 
 
+def test_big_only_instance_and_serving_refusal(S, ctx, orc):
+    """An instance whose every block takes the block Jacobi (no one-workgroup launch at all):
+    fixed-sigma iterates against the oracle; the request loop refuses such a problem at submit."""
+    osdp, prob = _synthetic_sdp(orc, S, [150, 120], 80, 12)
+    inst = S.Instance(ctx, prob, S.default_opts(sigma_every=0, kkt_every=1, tol=0.0))
+    inst.step(4)
+    Xg, yg, Sg = inst.get_iterate()
+    r = orc.admm_solve(osdp, maxiter=4, tol=0.0, sigma_every=0)
+    assert blockwise_rel(Xg, r["X"], osdp.bsize) <= 1e-9
+    assert blockwise_rel(Sg, r["S"], osdp.bsize) <= 1e-9
+    inst.close()
+    with pytest.raises(S.StromError):
+        ctx.submit(prob)
+
+
 def test_big_certificate_vs_oracle(S, ctx, orc):
     """The dual bound's smallest eigenvalues of C - A^* y on the large blocks (eigenvalues-only
     path of the multi-workgroup solver) against the oracle's."""
