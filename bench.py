@@ -51,6 +51,23 @@ def _sources_sha(sources) -> str:
     return h.hexdigest()
 
 
+def _mfma(path: str, sources, launch_ms: float):
+    """Matrix-core work of the dominant kernel from the committed counter record
+    (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 flops per launch) over its measured launch time, against
+    the FP64 MFMA peak; None when the kernel's sources have changed since the counters were taken."""
+    try:
+        with open(os.path.join(ROOT, path)) as f:
+            rec = json.load(f)
+        sha = _sources_sha(sources)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != sha or launch_ms <= 0:
+        return None
+    achieved = rec["mfma_flops_per_dispatch"] / (launch_ms * 1e-3) / 1e12
+    return {"flops_per_launch": rec["mfma_flops_per_dispatch"], "achieved": round(achieved, 4),
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 6)}
+
+
 def _traffic(path: str, sources):
     """HBM bytes per launch of the dominant kernel from the committed counter record, or None
     when the kernel's sources have changed since the counters were taken."""
@@ -770,7 +787,9 @@ def main():
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 6),
                      "traffic": _traffic("profiles/k_project_admm_cartpole_n30_traffic.json",
-                                         PROJECT_SOURCES)},
+                                         PROJECT_SOURCES),
+                     "mfma": _mfma("profiles/k_project_admm_cartpole_n30_mfma.json", PROJECT_SOURCES,
+                                   prof["project_ms"])},
     }
     if not args.no_cpu:
         _log("CPU oracle baseline ...")
