@@ -36,13 +36,30 @@
 namespace strom {
 namespace {
 
-// Nested-dissection post-order of the chain positions [lo, hi].
-void chain_nd(int lo, int hi, std::vector<int> &out) {
+// Nested-dissection post-order of the chain positions [lo, hi]; depth[p] = the level of
+// position p in the dissection tree (0 at the root).
+void chain_nd(int lo, int hi, std::vector<int> &out, std::vector<int> &depth, int d = 0) {
   if (lo > hi) return;
   const int mid = lo + (hi - lo) / 2;
-  chain_nd(lo, mid - 1, out);
-  chain_nd(mid + 1, hi, out);
+  chain_nd(lo, mid - 1, out, depth, d + 1);
+  chain_nd(mid + 1, hi, out, depth, d + 1);
   out.push_back(mid);
+  depth[size_t(mid)] = d;
+}
+
+// Levels of the dissection tree (from the root) whose coupling sets form one task, the root
+// task.  Their rows come last, in post-order: the schedule loses that many launches per
+// direction minus one, and the root task does their work in sequence.  STROM_TOP_LEVELS if set;
+// else as many levels as keep the merged rows within kTopRows (measured on MI355X: the pendulum
+// N = 10 solve 26% faster with its top three levels merged, 245 rows, and 17% with four, 315;
+// cart-pole N = 30 within 2% either way with two, 378 rows, and 4% slower with three, 882).
+constexpr int64_t kTopRows = 256;
+int top_levels(const std::vector<int64_t> &rows_at_depth) {
+  if (const char *ev = std::getenv("STROM_TOP_LEVELS")) return std::max(1, std::atoi(ev));
+  int k = 1;
+  int64_t rows = rows_at_depth.empty() ? 0 : rows_at_depth[0];
+  while (k < int(rows_at_depth.size()) && rows + rows_at_depth[size_t(k)] <= kTopRows) rows += rows_at_depth[size_t(k++)];
+  return k;
 }
 
 // Lanes per row for a gather of up to `len` entries.
@@ -369,27 +386,42 @@ strom_status analyze_full(int32_t nblocks, const int32_t *bsize, int32_t m, cons
     else if (rg.size() == 2 && rg[1] == rg[0] + 1) { rclass[size_t(i)] = 1; rkey[size_t(i)] = rg[0]; }
     else { rclass[size_t(i)] = 2; rkey[size_t(i)] = 0; }
   }
-  std::vector<int> sep_pos;
-  chain_nd(0, std::max(0, ngroups - 2), sep_pos);
+  std::vector<int> sep_pos, sep_depth(static_cast<size_t>(std::max(1, ngroups)), 0);
+  chain_nd(0, std::max(0, ngroups - 2), sep_pos, sep_depth);
   std::vector<int32_t> sep_rank(static_cast<size_t>(std::max(1, ngroups)), 0);
   for (size_t r = 0; r < sep_pos.size(); ++r) sep_rank[size_t(sep_pos[r])] = int32_t(r);
+  // the coupling sets of the top levels of the dissection tree go last and form one task
+  std::vector<int64_t> rows_at_depth;
+  for (int32_t i = 0; i < m; ++i)
+    if (rclass[size_t(i)] == 1) {
+      const size_t dd = size_t(sep_depth[size_t(rkey[size_t(i)])]);
+      if (rows_at_depth.size() <= dd) rows_at_depth.resize(dd + 1, 0);
+      rows_at_depth[dd]++;
+    }
+  const int ntop = top_levels(rows_at_depth);
+  auto top = [&](int32_t i) { return rclass[size_t(i)] == 1 && sep_depth[size_t(rkey[size_t(i)])] < ntop; };
   H.perm.resize(size_t(m));
   std::iota(H.perm.begin(), H.perm.end(), 0);
   std::stable_sort(H.perm.begin(), H.perm.end(), [&](int32_t a, int32_t b) {
     if (rclass[size_t(a)] != rclass[size_t(b)]) return rclass[size_t(a)] < rclass[size_t(b)];
     if (rclass[size_t(a)] == 0) return rkey[size_t(a)] < rkey[size_t(b)];
-    if (rclass[size_t(a)] == 1) return sep_rank[size_t(rkey[size_t(a)])] < sep_rank[size_t(rkey[size_t(b)])];
+    if (rclass[size_t(a)] == 1) {
+      const bool ta = top(a), tb = top(b);
+      if (ta != tb) return tb;  // the top sets after every lower one
+      return sep_rank[size_t(rkey[size_t(a)])] < sep_rank[size_t(rkey[size_t(b)])];
+    }
     return false;
   });
   H.pinv.resize(size_t(m));
   for (int32_t k = 0; k < m; ++k) H.pinv[size_t(H.perm[size_t(k)])] = k;
 
-  // task ranges: maximal runs of rows with the same (class, key)
+  // task ranges: maximal runs of rows with the same (class, key), the top coupling sets as one
   {
+    auto tkey = [&](int32_t i) { return top(i) ? -1 : rkey[size_t(i)]; };
     int32_t r0 = 0;
     for (int32_t k = 1; k <= m; ++k) {
       const bool brk = (k == m) || rclass[size_t(H.perm[size_t(k)])] != rclass[size_t(H.perm[size_t(r0)])] ||
-                       rkey[size_t(H.perm[size_t(k)])] != rkey[size_t(H.perm[size_t(r0)])];
+                       tkey(H.perm[size_t(k)]) != tkey(H.perm[size_t(r0)]);
       if (brk) { H.task_r0.push_back(r0); H.task_r1.push_back(k); r0 = k; }
     }
   }
@@ -1228,7 +1260,7 @@ size_t entry_bytes(const CacheEntry &e) {
 
 std::string env_knobs() {
   std::string s;
-  for (const char *name : {"STROM_STAGE_ROWS", "STROM_TASK_SPLIT", "STROM_BLOCK_ROWS"}) {
+  for (const char *name : {"STROM_STAGE_ROWS", "STROM_TASK_SPLIT", "STROM_BLOCK_ROWS", "STROM_TOP_LEVELS"}) {
     const char *v = std::getenv(name);
     s += std::string(name) + "=" + (v ? v : "") + ";";
   }

@@ -2,7 +2,8 @@
 
 tests/native/solve_schedule_sim.cpp runs the library's host analysis (row order, FP64 LDL^T,
 task split, phases, component inverses, push segments, task-local staging, phase streams,
-launch groups) and then walks the schedule exactly as the solve kernels read it.  Its
+launch groups, the top levels of the coupling sets' dissection tree merged into the root task)
+and then walks the schedule exactly as the solve kernels read it.  Its
 y = (eps I + A A^*)^{-1} r must match the oracle's own sparse factorization: a schedule that
 drops, doubles or misindexes a stream entry, or runs a task before one it depends on, fails
 here.  Every case runs with the task split of every group task, of the overweight ones only
@@ -28,6 +29,8 @@ VARIANTS = [  # environment of the analysis
     {"STROM_TASK_SPLIT": "1"},
     {"STROM_STAGE_ROWS": "0"},
     {"STROM_STAGE_ROWS": "600", "STROM_BLOCK_ROWS": "32"},
+    {"STROM_TOP_LEVELS": "1"},  # only the root coupling set in the root task
+    {"STROM_TOP_LEVELS": "4"},  # the top four levels of the dissection tree in one task
 ]
 
 
