@@ -21,6 +21,8 @@
  *   6 the paper's vehicle landing (App. "Vehicle Landing"; 18-variable cliques, 190x190 / 19x19)
  *                                                     [x0, y0, theta0, vx0, vy0, omega0]
  *   7 the paper's car back-in (App. "Car Back-in"; 18-variable cliques, 190x190 / 19x19) [x0, y0, theta0]
+ *   8 the paper's cart-pole (App. "Cart-Pole"; 13-variable cliques (x_k, u_k, x_{k+1}, a_{k+2},
+ *     rs_{k+2}) that share 7 variables, 105x105 / 14x14)  [a0, adot0, theta0 from hanging, thetadot0]
  *
  * Every function returns 0 on success and a negative strom_status on error.
  */

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRCS = ["pop.c", "relax.c", "ldl.c", "jacobi.c", "admm.c", "cert.c"]
 
-TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING, LANDING, BACKIN = 0, 1, 2, 3, 4, 5, 6, 7
+TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING, LANDING, BACKIN, PAPER_CARTPOLE = 0, 1, 2, 3, 4, 5, 6, 7, 8
 ROW_NORM, ROW_MOMENT, ROW_LOCALIZING, ROW_EQUALITY, ROW_CONSENSUS = 0, 1, 2, 3, 4
 
 
@@ -83,6 +83,8 @@ def lib():
         L.orc_lift.restype = C.c_double
         L.orc_rollout.argtypes = [C.c_int, C.c_int, _dp, C.c_int, _dp, _dp]
         L.orc_rollout.restype = C.c_double
+        L.orc_lookahead.argtypes = [C.c_int]
+        L.orc_lookahead.restype = C.c_int
         L.orc_ldl_factor.argtypes = [C.c_int32, C.c_int64, _i64, _i32, _dp, C.c_double,
                                      C.POINTER(C.POINTER(_Ldl))]
         L.orc_ldl_factor.restype = C.c_int
@@ -163,7 +165,7 @@ def lift(family: int, N: int, params, z, want_X: bool = True):
 def rollout(family: int, N: int, params, u, dx: int, du: int):
     prm = np.ascontiguousarray(params, dtype=np.float64)
     u = np.ascontiguousarray(u, dtype=np.float64).copy()
-    z = np.zeros((N + 1) * dx + N * du)
+    z = np.zeros((N + 1) * dx + N * du + lib().orc_lookahead(int(family)))
     obj = lib().orc_rollout(int(family), int(N), prm, len(prm), u, z)
     return z, obj
 

@@ -34,7 +34,8 @@ enum {
   ORC_CAR = 4,            /* planar car, unicycle-12 / bicycle-13, one obstacle          */
   ORC_FLYING = 5,         /* the paper's flying robot (App. "Flying Robot"), 20-var cliques */
   ORC_LANDING = 6,        /* the paper's vehicle landing (App. "Vehicle Landing"), 18-var cliques */
-  ORC_BACKIN = 7          /* the paper's car back-in (App. "Car Back-in"), 18-var cliques */
+  ORC_BACKIN = 7,         /* the paper's car back-in (App. "Car Back-in"), 18-var cliques */
+  ORC_PAPER_CARTPOLE = 8  /* the paper's cart-pole (App. "Cart-Pole"), 13-var cliques with lookahead */
 };
 
 /* Row types, in the order they are generated inside a clique. */
@@ -70,18 +71,27 @@ typedef struct {
  *   CARTPOLE:       [x0, v0, theta0, omega0]
  *   PAPER_PENDULUM: [theta0, omega0]
  *   CAR:            [variant(0 unicycle-12, 1 bicycle-13), sx, sy, heading0, gx, gy, ox, oy]
+ *   FLYING, LANDING: [x0, y0, theta0, vx0, vy0, omega0]
+ *   BACKIN:         [x0, y0, theta0]
+ *   PAPER_CARTPOLE: [a0, adot0, theta0, thetadot0]  (theta from the hanging position)
  * Returns 0 on success, <0 on a bad argument. */
 int orc_relax(int family, int N, const double *params, int nparams, orc_sdp **out);
 void orc_sdp_free(orc_sdp *p);
 
+/* Number of lookahead variables of a family (0 for most): clique k of such a family holds
+ * (x_k, u_k, x_{k+1}) followed by some components of x_{k+2}, which it shares with clique k+1. */
+int orc_lookahead(int family);
+
 /* Evaluate the POP at a trajectory z (all clique variables in chain order:
- * x_0, u_0, x_1, u_1, ..., x_N, in scaled variables).  Writes the rank-one lifting
+ * x_0, u_0, x_1, u_1, ..., x_N, in scaled variables, then for a family with lookahead the
+ * lookahead components of x_{N+1}).  Writes the rank-one lifting
  * X(z) in svec form (length nsvec) and returns the POP objective sum_k f_k(z).
  * Used to pin A and C against the POP (A(X(z)) = b, <C,X(z)> = f(z)). */
 double orc_lift(int family, int N, const double *params, int nparams, const double *z,
                 double *X_svec);
 /* Roll out the dynamics from the initial state with the given (scaled) controls
- * u[0..N*du-1]; writes z (length (N+1)*dx + N*du) and returns the POP objective. */
+ * u[0..N*du-1]; writes z (length (N+1)*dx + N*du + orc_lookahead(family)) and returns the
+ * POP objective. */
 double orc_rollout(int family, int N, const double *params, int nparams, const double *u,
                    double *z);
 

@@ -172,15 +172,32 @@ int fam_layout(int family, const double *prm, int nprm, int *dx, int *du, double
       su[0] = 4; su[1] = 0.5;
       for (int i = 2; i < 10; ++i) su[i] = 1;
       return 0;
+    case ORC_PAPER_CARTPOLE: /* state (a, rc, rs, fc, fs), force u; a/a_max = a, u/10 */
+      *dx = 5; *du = 1; sx[0] = sx[1] = sx[2] = sx[3] = sx[4] = 1; su[0] = 10; return 0;
     default: return -1;
   }
 }
 
+/* Lookahead variables: a family whose dynamics span three steps (second differences) has clique
+ * k hold, after (x_k, u_k, x_{k+1}), the components lmap[0..dl) of x_{k+2}; clique k+1 holds them
+ * in its x_{k+1} part, so consecutive cliques share x_{k+1} and these.  Returns dl. */
+int fam_lookahead(int family, int *lmap) {
+  if (family == ORC_PAPER_CARTPOLE) { /* a_{k+2} and rs_{k+2} */
+    if (lmap) { lmap[0] = 0; lmap[1] = 2; }
+    return 2;
+  }
+  return 0;
+}
+
+int orc_lookahead(int family) { return fam_lookahead(family, NULL); }
+
 /* Variable in original units: scale * z_i. */
-typedef struct { int dx, du; double sx[PL_MAXV], su[PL_MAXV]; } lay_t;
+typedef struct { int dx, du; double sx[PL_MAXV], su[PL_MAXV]; int lmap[PL_MAXV]; } lay_t;
 static pl_poly X0(const lay_t *L, int i) { return pl_var(i, L->sx[i]); }                 /* x_k     */
 static pl_poly U(const lay_t *L, int i) { return pl_var(L->dx + i, L->su[i]); }          /* u_k     */
 static pl_poly X1(const lay_t *L, int i) { return pl_var(L->dx + L->du + i, L->sx[i]); } /* x_{k+1} */
+/* lookahead j: component lmap[j] of x_{k+2} */
+static pl_poly XL(const lay_t *L, int j) { return pl_var(2 * L->dx + L->du + j, L->sx[L->lmap[j]]); }
 
 static void push(pl_list *l, pl_poly p) {
   if (l->n == l->cap) {
@@ -221,6 +238,7 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
   lay_t L;
   memset(&L, 0, sizeof L);
   if (fam_layout(family, prm, nprm, &L.dx, &L.du, L.sx, L.su)) return -1;
+  fam_lookahead(family, L.lmap);
   const int last = (k == N - 1);
   pl_init(cost);
 
@@ -536,6 +554,51 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
     if (last)
       for (int i = 0; i < 4; ++i)
         *cost = add_(*cost, scl_(Pf, sq_(sub_(pl_var(L.dx + L.du + i, 1.0), cst(tgt[i])))));
+  } else if (family == ORC_PAPER_CARTPOLE) {
+    /* the paper's cart-pole (App. "Cart-Pole"), Lie-group variational integrator.  State
+     * (a, rc, rs, fc, fs): cart position, the pole's angle from the hanging position as a point
+     * on the unit circle, and its rotation over one step.  Clique k holds the discrete dynamics
+     * centred at step k+1, driven by u_k, with A = a_{k+2} - 2 a_{k+1} + a_k:
+     *   (m1 + m2)/dt A + m2 l/dt (rs_{k+2} - 2 rs_{k+1} + rs_k) - dt u_k = 0,
+     *   l/dt (fs_{k+1} - fs_k) + A/dt rc_{k+1} + g dt rs_{k+1} = 0,
+     * the rotation r_{k+1} = r_k f_k and the sine of r_{k+2} = r_{k+1} f_{k+1}, unit circles,
+     * fc >= fc_min, a^2 <= a_max^2, u^2 <= u_max^2.  Initial state: a_0, theta_0 and the step
+     * rotation of thetadot_0 fix x_0, adot_0 fixes a_1.  Cost: identity weights on the distance
+     * to (a, theta) = (0, pi) at rest and on u (scaled variables), terminal weight P_f. */
+    if (nprm < 4) return -1;
+    const double m1 = 1.0, m2 = 0.3, l = 0.5, g = 9.8, dt = 0.1, fcmin = 0.5, amax = 1, umax = 10, Pf = 1;
+    if (k == 0) {
+      push(eq, sub_(X0(&L, 0), cst(prm[0])));
+      push(eq, sub_(X0(&L, 1), cst(cos(prm[2]))));
+      push(eq, sub_(X0(&L, 2), cst(sin(prm[2]))));
+      push(eq, sub_(X0(&L, 3), cst(cos(dt * prm[3]))));
+      push(eq, sub_(X0(&L, 4), cst(sin(dt * prm[3]))));
+      push(eq, sub_(X1(&L, 0), cst(prm[0] + dt * prm[1])));
+    }
+    /* second differences of a and rs over (k, k+1, k+2) */
+    pl_poly d2a = add_(sub_(XL(&L, 0), scl_(2.0, X1(&L, 0))), X0(&L, 0));
+    pl_poly d2s = add_(sub_(XL(&L, 1), scl_(2.0, X1(&L, 2))), X0(&L, 2));
+    push(eq, sub_(add_(scl_((m1 + m2) / dt, pl_copy(&d2a)), scl_(m2 * l / dt, d2s)), scl_(dt, U(&L, 0))));
+    push(eq, add_(add_(scl_(l / dt, sub_(X1(&L, 4), X0(&L, 4))), scl_(1.0 / dt, mul_(d2a, X1(&L, 1)))),
+                  scl_(g * dt, X1(&L, 2))));
+    push(eq, sub_(X1(&L, 1), sub_(mul_(X0(&L, 1), X0(&L, 3)), mul_(X0(&L, 2), X0(&L, 4)))));
+    push(eq, sub_(X1(&L, 2), add_(mul_(X0(&L, 2), X0(&L, 3)), mul_(X0(&L, 1), X0(&L, 4)))));
+    push(eq, sub_(XL(&L, 1), add_(mul_(X1(&L, 2), X1(&L, 3)), mul_(X1(&L, 1), X1(&L, 4)))));
+    push(eq, circle(X1(&L, 1), X1(&L, 2)));
+    push(eq, circle(X1(&L, 3), X1(&L, 4)));
+    if (k >= 1) {
+      push(eq, circle(X0(&L, 1), X0(&L, 2)));
+      push(eq, circle(X0(&L, 3), X0(&L, 4)));
+    }
+    push(ineq, sub_(X1(&L, 3), cst(fcmin)));
+    push(ineq, sub_(cst(amax * amax), sq_(X1(&L, 0))));
+    push(ineq, sub_(cst(umax * umax), sq_(U(&L, 0))));
+    const double tgt[5] = {0, -1, 0, 1, 0};
+    for (int i = 0; i < 5; ++i) *cost = add_(*cost, sq_(sub_(pl_var(i, 1.0), cst(tgt[i]))));
+    *cost = add_(*cost, sq_(pl_var(L.dx, 1.0)));
+    if (last)
+      for (int i = 0; i < 5; ++i)
+        *cost = add_(*cost, scl_(Pf, sq_(sub_(pl_var(L.dx + L.du + i, 1.0), cst(tgt[i])))));
   } else {
     return -1;
   }
@@ -545,8 +608,9 @@ int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *e
 }
 
 /* One explicit step of the dynamics in scaled variables: x1 = F(x0, u).  For the bicycle,
- * the lifted control p is overwritten with v * dtilde so the step is feasible. */
-int fam_step(int family, const double *prm, int nprm, const double *x0, double *u, double *x1) {
+ * the lifted control p is overwritten with v * dtilde so the step is feasible.  aux carries
+ * what a family with lookahead needs beyond x (the paper's cart-pole: a_{k+1} in, a_{k+2} out). */
+int fam_step(int family, const double *prm, int nprm, const double *x0, double *u, double *x1, double *aux) {
   int dx, du; double sx[PL_MAXV], su[PL_MAXV];
   if (fam_layout(family, prm, nprm, &dx, &du, sx, su)) return -1;
   double X[PL_MAXV], Uo[PL_MAXV], Y[PL_MAXV];
@@ -590,6 +654,30 @@ int fam_step(int family, const double *prm, int nprm, const double *x0, double *
     const double a = dt * w / 2, a2 = a * a;
     Y[2] = ((1 - a2) * X[2] - 2 * a * X[3]) / (1 + a2);
     Y[3] = ((1 - a2) * X[3] + 2 * a * X[2]) / (1 + a2);
+  } else if (family == ORC_PAPER_CARTPOLE) {
+    /* x_{k+1} = (a_{k+1}, r_k f_k, f_{k+1}); the two dynamics equations centred at k+1 fix the
+     * second difference A of a and f_{k+1}: fixed-point iteration on A, a contraction (the
+     * factor is at most m2 rc^2 / (m1 + m2) <= 0.24) */
+    const double m1 = 1.0, m2 = 0.3, l = 0.5, g = 9.8, dt = 0.1;
+    if (!aux) return -1;
+    const double a1 = aux[0] * sx[0];
+    const double rc1 = X[1] * X[3] - X[2] * X[4], rs1 = X[2] * X[3] + X[1] * X[4];
+    double A = 0, fs1 = 0, fc1 = 1;
+    for (int it = 0; it < 200; ++it) {
+      fs1 = X[4] - (A * rc1 + g * dt * dt * rs1) / l;
+      if (fabs(fs1) > 1) return -2;
+      fc1 = sqrt(1 - fs1 * fs1);
+      const double rs2 = rs1 * fc1 + rc1 * fs1;
+      const double An = (dt * dt * Uo[0] - m2 * l * (rs2 - 2 * rs1 + X[2])) / (m1 + m2);
+      const int done = fabs(An - A) <= 1e-17;
+      A = An;
+      if (done) break;
+    }
+    fs1 = X[4] - (A * rc1 + g * dt * dt * rs1) / l;
+    if (fabs(fs1) > 1) return -2;
+    fc1 = sqrt(1 - fs1 * fs1);
+    Y[0] = a1; Y[1] = rc1; Y[2] = rs1; Y[3] = fc1; Y[4] = fs1;
+    aux[0] = (A + 2 * a1 - X[0]) / sx[0];
   } else if (family == ORC_FLYING) {
     const double dt = 0.2, alpha = 0.2, beta = 0.2;
     const double T = Uo[0] - Uo[1] + Uo[2] - Uo[3];
@@ -653,11 +741,23 @@ int fam_init_state(int family, const double *prm, int nprm, double *x0) {
     X[0] = prm[1]; X[1] = prm[2]; X[2] = cos(prm[3]); X[3] = sin(prm[3]); X[4] = 0;
   } else if (family == ORC_BACKIN) {
     X[0] = prm[0]; X[1] = prm[1]; X[2] = cos(prm[2]); X[3] = sin(prm[2]);
+  } else if (family == ORC_PAPER_CARTPOLE) {
+    X[0] = prm[0]; X[1] = cos(prm[2]); X[2] = sin(prm[2]); X[3] = cos(0.1 * prm[3]); X[4] = sin(0.1 * prm[3]);
   } else if (family == ORC_FLYING || family == ORC_LANDING) {
     X[0] = prm[0]; X[1] = prm[1]; X[2] = prm[3]; X[3] = prm[4];
     X[4] = cos(prm[2]); X[5] = sin(prm[2]); X[6] = cos(0.2 * prm[5]); X[7] = sin(0.2 * prm[5]);
   } else return -1;
   for (int i = 0; i < dx; ++i) x0[i] = X[i] / sx[i];
+  return 0;
+}
+
+/* The step memory of a family with lookahead at the start (the paper's cart-pole: a_1 from the
+ * initial cart velocity, scaled). */
+int fam_init_aux(int family, const double *prm, int nprm, double *aux) {
+  if (family == ORC_PAPER_CARTPOLE) {
+    if (nprm < 4) return -1;
+    aux[0] = prm[0] + 0.1 * prm[1];
+  }
   return 0;
 }
 

@@ -27,8 +27,10 @@ void pl_list_free(pl_list *l);
 int fam_layout(int family, const double *prm, int nprm, int *dx, int *du, double *sx, double *su);
 int fam_clique(int family, int N, int k, const double *prm, int nprm, pl_list *eq, pl_list *ineq,
                pl_poly *cost);
-int fam_step(int family, const double *prm, int nprm, const double *x0, double *u, double *x1);
+int fam_lookahead(int family, int *lmap);
+int fam_step(int family, const double *prm, int nprm, const double *x0, double *u, double *x1, double *aux);
 int fam_init_state(int family, const double *prm, int nprm, double *x0);
+int fam_init_aux(int family, const double *prm, int nprm, double *aux);
 int fam_var_bounds(int family, const double *prm, int nprm, double *bnd);
 
 #endif

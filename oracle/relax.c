@@ -17,7 +17,8 @@
  *
  * Conventions (each reproduces the indices printed in the worked example):
  *   - monomial basis [z]_n: graded by degree, inside a degree the exponent tuples in
- *     descending lexicographic order, variables in the order (x_k, u_k, x_{k+1});
+ *     descending lexicographic order, variables in the order (x_k, u_k, x_{k+1}), then, for a
+ *     family whose dynamics span three steps, its lookahead components of x_{k+2};
  *   - svec: column-major upper triangle, off-diagonal entries times sqrt(2);
  *   - the representative entry of a monomial in M_k is its first occurrence in svec order;
  *     localizing, equality, consensus rows and the objective refer to representatives;
@@ -209,7 +210,9 @@ int orc_relax(int family, int N, const double *prm, int nprm, orc_sdp **out) {
   double sx[PL_MAXV], su[PL_MAXV];
   *out = NULL;
   if (N < 1 || fam_layout(family, prm, nprm, &dx, &du, sx, su)) return -1;
-  const int d = 2 * dx + du;
+  int lmap[PL_MAXV];
+  const int dl = fam_lookahead(family, lmap);
+  const int d = 2 * dx + du + dl;
   if (d > PL_MAXV) return -1;
 
   mono_t *B2 = NULL, *B1 = NULL;
@@ -315,17 +318,22 @@ int orc_relax(int family, int N, const double *prm, int nprm, orc_sdp **out) {
         }
         free(Bm);
       }
-      /* (4) consensus rows with clique k+1: every monomial of degree <= 4 in x_{k+1} */
+      /* (4) consensus rows with clique k+1: every monomial of degree <= 4 in the variables the
+       * two cliques share, x_{k+1} and the lookahead components of x_{k+2} (in that order) */
       if (k + 1 < N) {
         mono_t *Bx = NULL;
-        const int nx = basis(dx, 4, &Bx);
+        const int nx = basis(dx + dl, 4, &Bx);
         for (int q = 0; q < nx; ++q) {
           uint8_t ek[PL_MAXV], ek1[PL_MAXV];
           memset(ek, 0, sizeof ek);
           memset(ek1, 0, sizeof ek1);
           for (int v = 0; v < dx; ++v) {
-            ek[dx + du + v] = Bx[q][v]; /* x_{k+1} is last in clique k   */
-            ek1[v] = Bx[q][v];          /* and first in clique k+1       */
+            ek[dx + du + v] = Bx[q][v]; /* x_{k+1} follows u_k in clique k */
+            ek1[v] = Bx[q][v];          /* and is first in clique k+1      */
+          }
+          for (int j = 0; j < dl; ++j) {
+            ek[2 * dx + du + j] = Bx[q][dx + j];         /* lookahead of clique k          */
+            ek1[dx + du + lmap[j]] = Bx[q][dx + j];      /* part of x_{k+2} in clique k+1  */
           }
           const occ_t *r0 = find_rep(&T, ek), *r1 = find_rep(&T, ek1);
           rb_entry(&R, offM[k], r0->i, r0->j, 1.0);
@@ -394,7 +402,9 @@ double orc_lift(int family, int N, const double *prm, int nprm, const double *z,
   int dx, du;
   double sx[PL_MAXV], su[PL_MAXV];
   if (N < 1 || fam_layout(family, prm, nprm, &dx, &du, sx, su)) return NAN;
-  const int d = 2 * dx + du;
+  int lmap[PL_MAXV];
+  const int dl = fam_lookahead(family, lmap);
+  const int d = 2 * dx + du + dl;
   mono_t *B2 = NULL, *B1 = NULL;
   const int nM = basis(d, 2, &B2);
   const int n1 = basis(d, 1, &B1);
@@ -404,7 +414,10 @@ double orc_lift(int family, int N, const double *prm, int nprm, const double *z,
   for (int k = 0; k < N; ++k) {
     double zc[PL_MAXV];
     memset(zc, 0, sizeof zc);
-    for (int i = 0; i < d; ++i) zc[i] = z[(int64_t)k * (dx + du) + i];
+    for (int i = 0; i < 2 * dx + du; ++i) zc[i] = z[(int64_t)k * (dx + du) + i];
+    for (int j = 0; j < dl; ++j) /* x_{k+2}, or past x_N the trailing lookahead values */
+      zc[2 * dx + du + j] = k + 2 <= N ? z[(int64_t)(k + 2) * (dx + du) + lmap[j]]
+                                       : z[(int64_t)N * (dx + du) + dx + j];
     pl_list eq = {0, 0, NULL}, iq = {0, 0, NULL};
     pl_poly cost;
     fam_clique(family, N, k, prm, nprm, &eq, &iq, &cost);
@@ -435,16 +448,25 @@ double orc_rollout(int family, int N, const double *prm, int nprm, const double 
   int dx, du;
   double sx[PL_MAXV], su[PL_MAXV];
   if (N < 1 || fam_layout(family, prm, nprm, &dx, &du, sx, su)) return NAN;
-  double x[PL_MAXV], x1[PL_MAXV], uk[PL_MAXV];
-  if (fam_init_state(family, prm, nprm, x)) return NAN;
+  double x[PL_MAXV], x1[PL_MAXV], uk[PL_MAXV], aux[PL_MAXV];
+  int lmap[PL_MAXV];
+  const int dl = fam_lookahead(family, lmap);
+  if (fam_init_state(family, prm, nprm, x) || fam_init_aux(family, prm, nprm, aux)) return NAN;
   for (int k = 0; k < N; ++k) {
     for (int i = 0; i < du; ++i) uk[i] = u[(int64_t)k * du + i];
-    if (fam_step(family, prm, nprm, x, uk, x1)) return NAN;
+    if (fam_step(family, prm, nprm, x, uk, x1, aux)) return NAN;
     for (int i = 0; i < dx; ++i) z[(int64_t)k * (dx + du) + i] = x[i];
     for (int i = 0; i < du; ++i) z[(int64_t)k * (dx + du) + dx + i] = uk[i];
     memcpy(x, x1, sizeof x);
   }
   for (int i = 0; i < dx; ++i) z[(int64_t)N * (dx + du) + i] = x[i];
+  if (dl > 0) {
+    /* the lookahead components of x_{N+1} (those of the families here do not depend on the
+     * control of that step) */
+    for (int i = 0; i < du; ++i) uk[i] = 0;
+    if (fam_step(family, prm, nprm, x, uk, x1, aux)) return NAN;
+    for (int j = 0; j < dl; ++j) z[(int64_t)N * (dx + du) + dx + j] = x1[lmap[j]];
+  }
   return orc_lift(family, N, prm, nprm, z, NULL);
 }
 
@@ -488,7 +510,10 @@ int orc_trace_bounds(int family, int N, const double *prm, int nprm, double *R_b
   double sx[PL_MAXV], su[PL_MAXV], bnd[PL_MAXV];
   if (N < 1 || fam_layout(family, prm, nprm, &dx, &du, sx, su)) return -1;
   if (fam_var_bounds(family, prm, nprm, bnd)) return -2;
-  const int d = 2 * dx + du;
+  int lmap[PL_MAXV];
+  const int dl = fam_lookahead(family, lmap);
+  for (int j = 0; j < dl; ++j) bnd[2 * dx + du + j] = bnd[lmap[j]];
+  const int d = 2 * dx + du + dl;
   double Rk = 0;
   for (int v = 0; v < d; ++v) Rk = fmax(Rk, bnd[v]);
   const double r1 = fmax(1.0, Rk);

@@ -2,7 +2,8 @@
 //
 // Sparse second-order moment relaxation (Prop. 1, relaxation order 2) of a chain-like POP
 // (Def. 1) and its PSD-only standard-SDP form ("Faster Conversion to Standard SDP"):
-//   * clique k holds (x_k, u_k, x_{k+1}); M_k = l([z]_2 [z]_2^T), one localizing matrix
+//   * clique k holds (x_k, u_k, x_{k+1}) and, where the dynamics span three steps, some
+//     components of x_{k+2} (lookahead); M_k = l([z]_2 [z]_2^T), one localizing matrix
 //     l(g [z]_1 [z]_1^T) per inequality g of degree <= 2, l(h [z]_{4 - deg h}) = 0 per
 //     equality h, phi_0 = 1;
 //   * monomial bases are graded, and descending-lexicographic inside a degree, variables in
@@ -10,7 +11,8 @@
 //   * a monomial is represented by its first upper-triangle position in svec order; the
 //     other positions get a moment row "position - representative";
 //   * rows: normalization, then per clique moment / localizing / equality (the initial
-//     state first in clique 0) / consensus with the next clique; blocks M_0, L_0*, M_1, ...
+//     state first in clique 0) / consensus with the next clique on every monomial of the
+//     shared variables (x_{k+1}, then the lookahead); blocks M_0, L_0*, M_1, ...
 //   * every equality and inequality polynomial is divided by its largest |coefficient|;
 //     variables are used in scaled form (original = scale * scaled).
 #include <algorithm>
@@ -114,10 +116,14 @@ std::vector<Mono> monomial_basis(int d, int n) {
 
 struct Layout {
   int dx = 0, du = 0;
+  int dl = 0;                // lookahead variables: components look[0..dl) of x_{k+2}
+  int look[kMaxVars] = {0};
   double sx[kMaxVars] = {0}, su[kMaxVars] = {0};
+  int nvars() const { return 2 * dx + du + dl; }
   Poly x0(int i) const { return Poly::var(i, sx[i]); }
   Poly u(int i) const { return Poly::var(dx + i, su[i]); }
   Poly x1(int i) const { return Poly::var(dx + du + i, sx[i]); }
+  Poly x2(int j) const { return Poly::var(2 * dx + du + j, sx[look[j]]); }  // lookahead j
   Poly zx0(int i) const { return Poly::var(i, 1.0); }       // scaled x_k
   Poly zu(int i) const { return Poly::var(dx + i, 1.0); }   // scaled u_k
   Poly zx1(int i) const { return Poly::var(dx + du + i, 1.0); }
@@ -144,6 +150,14 @@ bool make_layout(int family, const double *p, int np, Layout &L) {
     case 5: if (np < 6) return false; setx({10, 10, 10, 10, 1, 1, 1, 1}); setu({8, 8, 8, 8}); return true;
     case 6: if (np < 6) return false; setx({100, 120, 20, 20, 1, 1, 1, 1}); setu({8, 8}); return true;
     case 7: if (np < 3) return false; setx({10, 10, 1, 1}); setu({4, 0.5, 1, 1, 1, 1, 1, 1, 1, 1}); return true;
+    case 8:  // (a, rc, rs, fc, fs), force u / 10; a_{k+2} and rs_{k+2} ahead
+      if (np < 4) return false;
+      setx({1, 1, 1, 1, 1});
+      setu({10});
+      L.dl = 2;
+      L.look[0] = 0;
+      L.look[1] = 2;
+      return true;
     default: return false;
   }
 }
@@ -343,6 +357,35 @@ CliquePolys clique_polys(int family, int N, int k, const double *p, const Layout
     for (int i = 0; i < 4; ++i) q.cost = q.cost + sq(L.zu(i));
     if (last)
       for (int i = 0; i < 4; ++i) q.cost = q.cost + Pf * sq(L.zx1(i) - target[i]);
+  } else if (family == 8) {  // the paper's cart-pole: variational integrator, dynamics centred at x_{k+1}
+    // x = (a, rc, rs, fc, fs): r = pole angle from hanging, f = its rotation over a step
+    const double m1 = 1.0, m2 = 0.3, l = 0.5, g = 9.8, dt = 0.1, fcmin = 0.5, amax = 1, umax = 10, Pf = 1;
+    if (first) {
+      const double init[5] = {p[0], std::cos(p[2]), std::sin(p[2]), std::cos(dt * p[3]), std::sin(dt * p[3])};
+      for (int i = 0; i < 5; ++i) q.eq.push_back(L.x0(i) - init[i]);
+      q.eq.push_back(L.x1(0) - (p[0] + dt * p[1]));  // the cart's initial velocity sets a_1
+    }
+    const Poly acc = L.x2(0) - 2.0 * L.x1(0) + L.x0(0);   // a_{k+2} - 2 a_{k+1} + a_k
+    const Poly sacc = L.x2(1) - 2.0 * L.x1(2) + L.x0(2);  // the same of rs
+    q.eq.push_back(((m1 + m2) / dt) * acc + (m2 * l / dt) * sacc - dt * L.u(0));
+    q.eq.push_back((l / dt) * (L.x1(4) - L.x0(4)) + (1.0 / dt) * (acc * L.x1(1)) + (g * dt) * L.x1(2));
+    q.eq.push_back(L.x1(1) - (L.x0(1) * L.x0(3) - L.x0(2) * L.x0(4)));  // r_{k+1} = r_k f_k
+    q.eq.push_back(L.x1(2) - (L.x0(2) * L.x0(3) + L.x0(1) * L.x0(4)));
+    q.eq.push_back(L.x2(1) - (L.x1(2) * L.x1(3) + L.x1(1) * L.x1(4)));  // sine of r_{k+1} f_{k+1}
+    q.eq.push_back(unit_circle(L.x1(1), L.x1(2)));
+    q.eq.push_back(unit_circle(L.x1(3), L.x1(4)));
+    if (!first) {
+      q.eq.push_back(unit_circle(L.x0(1), L.x0(2)));
+      q.eq.push_back(unit_circle(L.x0(3), L.x0(4)));
+    }
+    q.ineq.push_back(L.x1(3) - fcmin);
+    q.ineq.push_back(amax * amax - sq(L.x1(0)));
+    q.ineq.push_back(umax * umax - sq(L.u(0)));
+    const double target[5] = {0, -1, 0, 1, 0};  // theta = pi, at rest
+    for (int i = 0; i < 5; ++i) q.cost = q.cost + sq(L.zx0(i) - target[i]);
+    q.cost = q.cost + sq(L.zu(0));
+    if (last)
+      for (int i = 0; i < 5; ++i) q.cost = q.cost + Pf * sq(L.zx1(i) - target[i]);
   } else {  // planar car with one circular obstacle
     const bool bicycle = p[0] != 0.0;
     const double dt = 0.1, Pf = 10;
@@ -490,7 +533,7 @@ extern "C" int strom_gen_build(int family, int N, const double *params, int npar
   *out = nullptr;
   Layout L;
   if (N < 1 || !params || !make_layout(family, params, nparams, L)) return STROM_E_INVAL;
-  const int d = 2 * L.dx + L.du;
+  const int d = L.nvars();
   if (d > kMaxVars) return STROM_E_INVAL;
 
   const std::vector<Mono> B2 = monomial_basis(d, 2), B1 = monomial_basis(d, 1);
@@ -557,7 +600,18 @@ extern "C" int strom_gen_build(int family, int N, const double *params, int npar
 
   W.put(offM[0], 0, 0, 1.0);  // phi_0 = M_0(1,1) = 1
   W.close(0, 1.0);
-  const std::vector<Mono> Bshared = monomial_basis(L.dx, 4);
+  // the variables clique k shares with clique k+1: x_{k+1} and the lookahead, the last dx + dl of
+  // clique k; in clique k+1, x_{k+1} comes first and the lookahead sits in its x_{k+2} part
+  const int nshared = L.dx + L.dl;
+  const std::vector<Mono> Bshared = monomial_basis(nshared, 4);
+  auto in_next = [&](Mono a) {
+    Mono r = 0;
+    for (int v = 0; v < nshared; ++v) {
+      const int pos = v < L.dx ? v : L.dx + L.du + L.look[v - L.dx];
+      r += Mono(mono_exp(a, v)) << (kExpBits * pos);
+    }
+    return r;
+  };
   for (int k = 0; k < N; ++k) {
     const CliquePolys &q = cl[size_t(k)];
     for (int j = 0; j < nM; ++j)  // moment rows
@@ -581,11 +635,11 @@ extern "C" int strom_gen_build(int family, int N, const double *params, int npar
         W.close(3, 0.0);
       }
     }
-    if (k + 1 < N) {  // consensus rows on the monomials of x_{k+1}
+    if (k + 1 < N) {  // consensus rows on the monomials of the shared variables
       const int shift = kExpBits * (L.dx + L.du);
       for (Mono a : Bshared) {
         put_rep(k, a << shift, 1.0);
-        put_rep(k + 1, a, -1.0);
+        put_rep(k + 1, in_next(a), -1.0);
         W.close(4, 0.0);
       }
     }

@@ -54,6 +54,8 @@ CASES = [
     (5, 2, [3.0, -2.0, 0.5, 0.5, -0.5, 0.2]),
     (6, 2, [5.0, 80.0, 0.1, 0.5, -1.0, 0.05]),
     (7, 2, [3.0, 4.0, 0.1]),
+    (8, 3, [0.1, 0.2, 0.3, 0.5]),
+    (8, 1, [-0.2, 0.4, -0.3, -0.8]),
 ]
 
 

@@ -172,6 +172,79 @@ def test_car_back_in_sizes(orc):
     assert sdp.m + extra * (19 * 20 // 2) == gold["m_paper"]
 
 
+def test_paper_cart_pole_sizes(orc):
+    """The paper's cart-pole at its horizon: 30 moment blocks of 105 = s(13, 2) and localizing
+    blocks of 14 = s(13, 1), as in Table 1: the second-difference dynamics centred at x_{k+1} put
+    (x_k, u_k, x_{k+1}) and a_{k+2}, rs_{k+2} in clique k (d_x = 5, d_u = 1), so consecutive cliques
+    share 7 variables.  Modulo tri(14) = 105 every localizing matrix and every equality of degree 2
+    adds nothing and an equality of degree 1 adds s(13, 3) = 560 = 35 (mod 105), so with equalities
+    of degree <= 2 the normalization, the moment rows and the consensus rows fix m mod 105 up to a
+    multiple of 35.  With s(7, 4) = 330 consensus rows per adjacent pair Table 1's m fits (16, as
+    here, with a multiple of three linear equalities); with five shared variables (s(5, 4) = 126)
+    no count of linear equalities fits (85, 15 or 50).  The paper's localizing count and m
+    themselves are not reproduced (three inequalities per clique here)."""
+    gold = json.load(open(os.path.join(GOLD, "paper_sizes.json")))["cart_pole"]
+    sdp = orc.relax(orc.PAPER_CARTPOLE, gold["N"], [0.1, 0.2, 0.3, 0.5])
+    kinds = sdp.bkind
+    assert (kinds == 0).sum() == gold["num_M"] and set(sdp.bsize[kinds == 0]) == {gold["size_M"]}
+    assert set(sdp.bsize[kinds == 1]) == {gold["size_L"]}
+    assert (kinds == 1).sum() == 3 * gold["N"]
+    assert sdp.dx == 5 and sdp.du == 1 and sdp.nclique_vars == 13
+    assert (sdp.rowkind == orc.ROW_CONSENSUS).sum() == (gold["N"] - 1) * math.comb(7 + 4, 4)
+    assert sdp.m % 105 == gold["m_paper"] % 105 == 16
+    five = 1 + gold["N"] * (math.comb(15, 2) * (math.comb(15, 2) + 1) // 2 - math.comb(17, 4)) + \
+        (gold["N"] - 1) * math.comb(5 + 4, 4)
+    assert {(five + 35 * t) % 105 for t in range(3)} == {85, 15, 50}
+
+
+def test_paper_cart_pole_row_counts(orc):
+    """m of the paper's cart-pole reading in closed form: per clique one linear dynamics
+    equation and, of degree 2, the pole equation, the rotation r_{k+1} = r_k f_k (2), the sine of
+    r_{k+2} (1) and the unit circles of r and f on x_{k+1} (2) and, for k >= 1, on x_k (2); clique
+    0 has five initial-state equalities and a_1 from the initial cart velocity."""
+    N = 4
+    sdp = orc.relax(orc.PAPER_CARTPOLE, N, [0.1, 0.2, 0.3, 0.5])
+    d = 13
+    s = lambda n: math.comb(d + n, n)
+    tri = lambda n: n * (n + 1) // 2
+    m = 1 + N * (tri(s(2)) - s(4)) + N * 3 * tri(s(1))
+    m += N * (s(3) + 6 * s(2)) + (N - 1) * 2 * s(2) + 6 * s(3)
+    m += (N - 1) * math.comb(7 + 4, 4)
+    assert sdp.m == m
+    assert sdp.nsvec == N * tri(s(2)) + N * 3 * tri(s(1))
+
+
+def test_paper_cart_pole_step_follows_the_continuous_dynamics(orc):
+    """The cart-pole's discrete dynamics (the oracle's step, which the rank-one lifting test ties to
+    the relaxation's equality rows) against the continuous model of App. "Cart-Pole" integrated
+    to 1e-12: started from the exact a and theta at t = 0 and dt, one step with a constant force
+    lands within the integrator's local error of the exact state at 2 dt (here <= 4e-4 in a, 4e-3
+    in theta).  A flipped sign of gravity, of the force, of the pole term of the cart equation or
+    of the cart term of the pole equation would change the step by far more (each term's size over
+    one step is 0.02 to 0.1)."""
+    from scipy.integrate import solve_ivp
+    m1, m2, l, g, dt = 1.0, 0.3, 0.5, 9.8, 0.1
+
+    def rhs(t, y, u):
+        a, th, ad, thd = y
+        s, c = np.sin(th), np.cos(th)
+        den = m1 + m2 * s * s
+        add = (l * m2 * s * thd ** 2 + u + m2 * g * c * s) / den
+        thdd = -((l * m2 * s * thd ** 2 + u) * c + (m1 + m2) * g * s) / (l * den)
+        return [ad, thd, add, thdd]
+
+    for u, th0, w0, v0 in [(3.0, 0.3, 0.0, 0.0), (-5.0, 1.0, 1.0, 0.5), (0.0, 2.5, -1.0, -0.3), (8.0, -0.7, 2.0, 0.2)]:
+        sol = solve_ivp(rhs, [0, 2 * dt], [0, th0, v0, w0], args=(u,), t_eval=[0, dt, 2 * dt], rtol=1e-12,
+                        atol=1e-13)
+        a, th = sol.y[0], sol.y[1]
+        prm = [a[0], (a[1] - a[0]) / dt, th[0], (th[1] - th[0]) / dt]
+        z, _ = orc.rollout(orc.PAPER_CARTPOLE, 2, prm, np.full(2, u / 10), 5, 1)
+        x2 = z[12:17]  # (a, rc, rs, fc, fs) at step 2
+        th2 = th[1] + np.angle((x2[1] + 1j * x2[2]) * np.exp(-1j * th[1]))
+        assert abs(x2[0] - a[2]) <= 1e-3
+        assert abs(th2 - th[2]) <= 1e-2
+
+
 def test_flying_robot_row_counts(orc):
     """m of the flying robot from the same closed form as the other families: per clique k >= 1
     three equalities of degree 1 (position updates, f_s update) and eight of degree 2 (velocity
@@ -224,6 +297,7 @@ FAMS = [
     ("FLYING", 3, [3.0, -2.0, 0.5, 0.5, -0.5, 0.2], 1.0),
     ("LANDING", 3, [5.0, 80.0, 0.1, 0.5, -1.0, 0.05], 1.0),
     ("BACKIN", 3, [3.0, 4.0, 0.1], 1.0),
+    ("PAPER_CARTPOLE", 3, [0.1, 0.2, 0.3, 0.5], 1.0),
 ]
 
 

@@ -13,15 +13,16 @@ Parameter vectors, per family (angles in radians, original units):
   flying   [x0, y0, theta0, vx0, vy0, omega0]      the paper's flying robot (rest at the origin is the goal)
   landing  [x0, y0, theta0, vx0, vy0, omega0]      the paper's vehicle landing (rest at (0, 10) is the goal)
   backin   [x0, y0, theta0]                        the paper's car back-in (goal (0, -3), heading pi/2)
+  paper_cartpole [a0, adot0, theta0, thetadot0]    the paper's cart-pole, theta from hanging (goal upright at a = 0)
 """
 from __future__ import annotations
 
 import math
 
-TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING, LANDING, BACKIN = 0, 1, 2, 3, 4, 5, 6, 7
+TOY1D, PENDULUM, CARTPOLE, PAPER_PENDULUM, CAR, FLYING, LANDING, BACKIN, PAPER_CARTPOLE = 0, 1, 2, 3, 4, 5, 6, 7, 8
 FAMILY_NAMES = {TOY1D: "toy1d", PENDULUM: "pendulum", CARTPOLE: "cartpole",
                 PAPER_PENDULUM: "paper_pendulum", CAR: "car", FLYING: "flying",
-                LANDING: "landing", BACKIN: "backin"}
+                LANDING: "landing", BACKIN: "backin", PAPER_CARTPOLE: "paper_cartpole"}
 _MASK = (1 << 64) - 1
 
 
@@ -79,6 +80,8 @@ def instance_params(family: int, seed: int) -> list:
                 r.uniform(-0.2, 0.2)]
     if family == BACKIN:  # above the slot between the two squares, roughly level
         return [r.uniform(2, 5), r.uniform(2, 5), r.uniform(-0.3, 0.3)]
+    if family == PAPER_CARTPOLE:  # near the hanging rest state
+        return [r.uniform(-0.5, 0.5), r.uniform(-0.5, 0.5), r.uniform(-0.5, 0.5), r.uniform(-1, 1)]
     raise ValueError(family)
 
 
