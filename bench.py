@@ -517,14 +517,15 @@ def _setup_cache(S, W, ctx) -> dict:
     return out
 
 
-def _paper_pendulum(S, W, ctx, args) -> dict:
-    """The paper's own pendulum problem shape (variational-integrator dynamics, 30 moment blocks
-    55x55 + 60 localizing blocks 10x10, n_svec 49,500, m 47,351): FP64 iterations/s of one
-    instance, and a cold solve under the paper's own termination rule (tol 1e-4, at most 10^4
-    iterations), setup included."""
-    prm = W.instance_params(W.PAPER_PENDULUM, args.seed)
+def _paper_problem(S, W, ctx, args, fam, label, shape, context) -> dict:
+    """One of the paper's problems at N = 30 (the pendulum: variational-integrator dynamics, 30
+    moment blocks 55x55 + 60 localizing blocks 10x10, n_svec 49,500, m 47,351; the cart-pole: 30
+    moment blocks 105x105 over cliques with second-difference dynamics + 90 localizing 14x14):
+    FP64 iterations/s of one instance, and a cold solve under the paper's own termination rule
+    (tol 1e-4, at most 10^4 iterations), setup included."""
+    prm = W.instance_params(fam, args.seed)
     t0 = time.perf_counter()
-    prob = S.generate(W.PAPER_PENDULUM, 30, prm)
+    prob = S.generate(fam, 30, prm)
     ins = S.Instance(ctx, prob, S.default_opts(tol=1e-4, maxiter=10**4))
     t1 = time.perf_counter()
     inf = ins.step(10**4)
@@ -536,15 +537,13 @@ def _paper_pendulum(S, W, ctx, args) -> dict:
     ins.step(500)
     tb = time.perf_counter()
     ins.close()
-    out = {"workload": f"paper pendulum N=30, seed {args.seed}: 30 moment blocks 55x55 + 60 localizing 10x10, "
-                       f"n_svec {prob.nsvec}, m {prob.m}, FP64",
+    out = {"workload": f"{label} N=30, seed {args.seed}: {shape}, n_svec {prob.nsvec}, m {prob.m}, FP64",
            "iters_per_s": round(500 / (tb - ta), 1),
            "cold_solve_tol_1e-4": {"seconds": round(t2 - t0, 3), "setup_s": round(t1 - t0, 3),
                                    "iters": int(inf["iters"]), "state": int(inf["state"]),
                                    "eta": max(inf["eta_p"], inf["eta_d"], inf["eta_g"])},
-           "paper_context": "the paper's cold solve of this shape: 31.2 s mean (14.6 s median) on an RTX 6000 "
-                            "Ada with CPU LDL^T solves, tol 1e-4, at most 10^4 iterations; context only"}
-    _log(f"paper pendulum: {out}")
+           "paper_context": context}
+    _log(f"{label}: {out}")
     return out
 
 
@@ -619,7 +618,7 @@ def main():
                     help="problems the batch solved in its window, solved again by the per-instance FP64 form "
                          "and both batches (0: skip)")
     ap.add_argument("--warm", type=int, default=3, help="receding-horizon warm-start steps (0: skip)")
-    ap.add_argument("--paper", type=int, default=1, help="the paper's pendulum shape (0: skip)")
+    ap.add_argument("--paper", type=int, default=1, help="the paper's pendulum and cart-pole (0: skip)")
     ap.add_argument("--car", type=int, default=1, help="car N=50 iterations/s (0: skip)")
     ap.add_argument("--cert", type=int, default=1, help="certificate on a converged car N=50 solve (0: skip)")
     ap.add_argument("--large", type=int, default=1, help="the paper's 190/231 block shapes (0: skip)")
@@ -738,7 +737,17 @@ def main():
     car = _car(S, W, ctx, args) if args.car else None
     batched = _batched(S, W, np, torch, args) if args.batch > 0 else None
     warm = _warm_start(S, W, np, ctx, args) if args.warm > 0 else None
-    paper = _paper_pendulum(S, W, ctx, args) if args.paper else None
+    paper = paper_cp = None
+    if args.paper:
+        paper = _paper_problem(S, W, ctx, args, W.PAPER_PENDULUM, "paper pendulum",
+                               "30 moment blocks 55x55 + 60 localizing 10x10",
+                               "the paper's cold solve of this shape: 31.2 s mean (14.6 s median) on an RTX 6000 Ada "
+                               "with CPU LDL^T solves, tol 1e-4, at most 10^4 iterations; context only")
+        paper_cp = _paper_problem(S, W, ctx, args, W.PAPER_CARTPOLE, "paper cart-pole",
+                                  "30 moment blocks 105x105 + 90 localizing 14x14",
+                                  "the paper's cart-pole (its m is 168,961, this reading's 159,721): 183.0 s mean "
+                                  "(173.1 s median) on an RTX 6000 Ada with CPU LDL^T solves, tol 1e-4, at most 10^4 "
+                                  "iterations; context only")
     large = _large_blocks(S, ctx, args) if args.large else None
     cert = _certificate(S, W, np, ctx, args) if args.cert else None
     setup_cache = _setup_cache(S, W, ctx) if args.setup_cache else None
@@ -780,6 +789,7 @@ def main():
         "setup_cache": setup_cache,
         "warm_start": warm,
         "paper_pendulum": paper,
+        "paper_cart_pole": paper_cp,
         "large_blocks": large,
         "car_n50": car,
         "phase_ms": {k: round(v, 4) for k, v in prof.items()},

@@ -1,6 +1,7 @@
 """Writes converged_refs_families.json: the oracle's optimal values of cart-pole and car
 instances (instance parameters from workloads.instance_params) solved to max KKT residual 1e-8:
-cart-pole N = 6 (seeds 0 and 2) and car N = 4 (seed 1, bicycle-13): instances the oracle takes
+cart-pole N = 6 (seeds 0 and 2), car N = 4 (seed 1, bicycle-13) and the paper's cart-pole N = 3
+(seed 0): instances the oracle takes
 to 1e-8 within minutes (others, e.g. cart-pole N = 6 seed 1, stall above 1e-8 on the duality gap).  Calls only the
 oracle (one process per case); the GPU tests compare converged device solutions with these.
 
@@ -20,7 +21,8 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
-CASES = [("cartpole", W.CARTPOLE, 6, 0), ("cartpole", W.CARTPOLE, 6, 2), ("car", W.CAR, 4, 1)]
+CASES = [("cartpole", W.CARTPOLE, 6, 0), ("cartpole", W.CARTPOLE, 6, 2), ("car", W.CAR, 4, 1),
+         ("paper_cartpole", W.PAPER_CARTPOLE, 3, 0)]
 
 
 def solve(case):

@@ -430,6 +430,26 @@ def test_paper_pendulum_full_size_iterates(S, ctx, orc):
     inst.close()
 
 
+def test_paper_cart_pole_full_size_iterates(S, ctx, orc):
+    """The paper's cart-pole (variational integrator with second differences; 30 moment blocks of
+    105 over 13-variable cliques that share 7 variables with the next, 90 localizing blocks of 14;
+    n_svec 176,400, m 159,721): three iterations with a fixed sigma against the oracle."""
+    import workloads as W
+    prm = W.instance_params(W.PAPER_CARTPOLE, 0)
+    osdp = orc.relax(W.PAPER_CARTPOLE, 30, prm)
+    prob = S.generate(W.PAPER_CARTPOLE, 30, prm)
+    assert (prob.nsvec, prob.m) == (176400, 159721)
+    inst = S.Instance(ctx, prob, _opts(S, sigma_every=0, kkt_every=1, tol=0.0))
+    inst.step(3)
+    Xg, yg, Sg = inst.get_iterate()
+    r = orc.admm_solve(osdp, maxiter=3, tol=0.0, sigma_every=0)
+    assert blockwise_rel(Xg, r["X"], osdp.bsize) <= 1e-9
+    assert blockwise_rel(Sg, r["S"], osdp.bsize) <= 1e-9
+    aty, atyo = osdp.A.T @ yg, osdp.A.T @ r["y"]
+    assert np.linalg.norm(aty - atyo) / max(1.0, np.linalg.norm(atyo)) <= 1e-9
+    inst.close()
+
+
 @pytest.mark.parametrize("split,rows", [(0, 0), (1, 64), (2, 32)])
 def test_task_split_option_iterates(S, ctx, orc, split, rows):
     """The solve schedule chosen per instance (strom_opts.task_split, strom_opts.block_rows):
@@ -526,10 +546,10 @@ def _family_refs():
         return json.load(f)["cases"]
 
 
-@pytest.mark.parametrize("case", range(3))
+@pytest.mark.parametrize("case", range(4))
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_family_converged_vs_oracle(S, ctx, orc, case, dtype):
-    """Cart-pole N = 6 and the bicycle car N = 4, solved on the device (FP64, or the FP32 projection
+    """Cart-pole N = 6, the bicycle car N = 4 and the paper's cart-pole N = 3, solved on the device (FP64, or the FP32 projection
     with the FP64 polish) to tol 1e-8, the oracle's own accuracy: the oracle's KKT evaluation of
     the device iterate is <= 1e-6 and the objective is within 1e-6 of the oracle's optimum.  (At
     tol 1e-6 the objective of cart-pole N = 6 seed 0 is 3.4e-6 away in this normalization, and
@@ -537,7 +557,7 @@ def test_family_converged_vs_oracle(S, ctx, orc, case, dtype):
     part of primal feasibility, X's negative eigenvalues, which moves <C, X> too.)"""
     import workloads as W
     ref = _family_refs()[case]
-    fam = {"cartpole": W.CARTPOLE, "car": W.CAR}[ref["family"]]
+    fam = {"cartpole": W.CARTPOLE, "car": W.CAR, "paper_cartpole": W.PAPER_CARTPOLE}[ref["family"]]
     prm = W.instance_params(fam, ref["seed"])
     assert np.allclose(ref["params"], prm, rtol=0, atol=0)
     prob = S.generate(fam, ref["N"], prm)
