@@ -18,10 +18,11 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-CASES = [  # (family, N, parameters): pendulum, cart-pole, car (the split applies to the first two)
+CASES = [  # (family, N, parameters): pendulum, cart-pole, car, the paper's cart-pole (the split applies to the first two)
     (1, 10, [0.5, 0.0]),
     (2, 10, [0.1, 0.2, 0.5, 0.3]),
     (4, 4, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
+    (8, 4, [0.1, 0.2, 0.3, 0.5]),  # the paper's cart-pole: 330-row coupling sets (7 shared variables)
 ]
 VARIANTS = [  # environment of the analysis
     {},
