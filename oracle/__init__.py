@@ -85,6 +85,8 @@ def lib():
         L.orc_rollout.restype = C.c_double
         L.orc_lookahead.argtypes = [C.c_int]
         L.orc_lookahead.restype = C.c_int
+        L.orc_lookahead_map.argtypes = [C.c_int, C.POINTER(C.c_int)]
+        L.orc_lookahead_map.restype = C.c_int
         L.orc_ldl_factor.argtypes = [C.c_int32, C.c_int64, _i64, _i32, _dp, C.c_double,
                                      C.POINTER(C.POINTER(_Ldl))]
         L.orc_ldl_factor.restype = C.c_int
@@ -160,6 +162,23 @@ def lift(family: int, N: int, params, z, want_X: bool = True):
         ptr = X.ctypes.data_as(C.c_void_p)
     obj = lib().orc_lift(int(family), int(N), prm, len(prm), z, ptr)
     return X, obj
+
+
+def lookahead_map(family: int):
+    """Components of x_{k+2} that clique k of the family holds after (x_k, u_k, x_{k+1})."""
+    lmap = (C.c_int * 21)()
+    dl = lib().orc_lookahead_map(int(family), lmap)
+    return [int(lmap[j]) for j in range(dl)]
+
+
+def clique_vars(sdp: SDP, z, k: int):
+    """The variables of clique k in a trajectory z of rollout(): z's window (x_k, u_k, x_{k+1}),
+    then the lookahead components of x_{k+2} (past x_N: z's trailing values)."""
+    step, base = sdp.dx + sdp.du, 2 * sdp.dx + sdp.du
+    out = list(z[k * step: k * step + base])
+    for j, c in enumerate(lookahead_map(sdp.family)):
+        out.append(z[(k + 2) * step + c] if k + 2 <= sdp.N else z[sdp.N * step + sdp.dx + j])
+    return np.array(out)
 
 
 def rollout(family: int, N: int, params, u, dx: int, du: int):

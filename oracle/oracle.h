@@ -81,6 +81,8 @@ void orc_sdp_free(orc_sdp *p);
 /* Number of lookahead variables of a family (0 for most): clique k of such a family holds
  * (x_k, u_k, x_{k+1}) followed by some components of x_{k+2}, which it shares with clique k+1. */
 int orc_lookahead(int family);
+/* The same, with the lookahead components (indices into x) written to lmap (up to 21). */
+int orc_lookahead_map(int family, int *lmap);
 
 /* Evaluate the POP at a trajectory z (all clique variables in chain order:
  * x_0, u_0, x_1, u_1, ..., x_N, in scaled variables, then for a family with lookahead the

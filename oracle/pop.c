@@ -190,6 +190,7 @@ int fam_lookahead(int family, int *lmap) {
 }
 
 int orc_lookahead(int family) { return fam_lookahead(family, NULL); }
+int orc_lookahead_map(int family, int *lmap) { return fam_lookahead(family, lmap); }
 
 /* Variable in original units: scale * z_i. */
 typedef struct { int dx, du; double sx[PL_MAXV], su[PL_MAXV]; int lmap[PL_MAXV]; } lay_t;

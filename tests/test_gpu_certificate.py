@@ -100,6 +100,8 @@ def test_dual_bound_vs_oracle(S, ctx, orc, fam, N, prm):
     # space's eigenvalues are resolved to about that)
     (7, 2, [3.0, 4.0, 0.1], 1e-10),
     (5, 2, [3.0, -2.0, 0.5, 0.5, -0.5, 0.2], 1e-10),
+    # the paper's cart-pole: cliques with lookahead variables (a_{k+2}, rs_{k+2})
+    (8, 3, [0.1, 0.2, 0.3, 0.5], 1e-11),
 ])
 def test_extract_vs_oracle_on_a_lifting(S, ctx, orc, fam, N, prm, rank_tol):
     osdp = orc.relax(fam, N, prm)
@@ -112,14 +114,13 @@ def test_extract_vs_oracle_on_a_lifting(S, ctx, orc, fam, N, prm, rank_tol):
     lam, vt = inst.extract(blocks, [int(osdp.bsize[k]) for k in blocks])
     lam_o, vt_o = orc.extract(osdp, X, blocks)
     assert np.abs(lam - lam_o).max() <= 1e-11 * (1.0 + np.abs(lam_o).max())
-    d, step = osdp.nclique_vars, osdp.dx + osdp.du
+    d = osdp.nclique_vars
     for t, k in enumerate(blocks):
         if osdp.bkind[k] != 0:
             continue
         assert lam[t, 1] <= rank_tol * lam[t, 0]
         assert np.allclose(vt[t], vt_o[t], atol=1e-9)
-        c = int(osdp.bclique[k])
-        assert np.allclose(vt[t][1:1 + d], z[c * step: c * step + d], atol=1e-9)
+        assert np.allclose(vt[t][1:1 + d], orc.clique_vars(osdp, z, int(osdp.bclique[k])), atol=1e-9)
     inst.close()
 
 

@@ -513,7 +513,8 @@ def test_serving_under_a_tight_budget_with_mixed_round_structures(S, ctx):
         assert abs(b["pobj"] - a["pobj"]) <= 1e-9 * (1.0 + abs(a["pobj"]))
 
 
-@pytest.mark.parametrize("fam,N,prm", [(2, 4, [0.1, 0.2, 0.5, 0.3]), (4, 2, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1])])
+@pytest.mark.parametrize("fam,N,prm", [(2, 4, [0.1, 0.2, 0.5, 0.3]), (4, 2, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
+                                       (8, 2, [0.1, 0.2, 0.3, 0.5])])
 def test_fp32_admm_projection_per_block(S, ctx, orc, fam, N, prm):
     """The FP32 projection inside an iteration (warm-started from the eigenvectors the previous
     iterations kept): the device's Pi(X_b) = X_b + sigma S, block by block, against the oracle's

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 CASES = [("PENDULUM", 4, [0.5, 0.0]), ("CARTPOLE", 3, [0.1, 0.2, 0.5, 0.3]),
-         ("CAR", 3, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1])]
+         ("CAR", 3, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]), ("PAPER_CARTPOLE", 3, [0.1, 0.2, 0.3, 0.5])]
 
 
 def _block_traces(sdp, X):
@@ -77,11 +77,11 @@ def test_extract_recovers_the_lifted_point(orc, fam, N, prm):
     moment = [k for k in range(sdp.nblocks) if sdp.bkind[k] == 0]
     assert len(moment) == N
     lam, vt = orc.extract(sdp, X, moment)
-    d, step = sdp.nclique_vars, sdp.dx + sdp.du
+    d = sdp.nclique_vars
     for t, k in enumerate(moment):
         assert lam[t, 1] <= 1e-12 * lam[t, 0]  # rank one
-        clique = int(sdp.bclique[k])
-        zk = z[clique * step: clique * step + d]
+        zk = orc.clique_vars(sdp, z, int(sdp.bclique[k]))
+        assert len(zk) == d
         assert abs(vt[t][0] - 1.0) <= 1e-14
         assert np.allclose(vt[t][1:1 + d], zk, atol=1e-10 * max(1.0, np.abs(zk).max()))
 
