@@ -29,7 +29,7 @@ def ctx(S):
 def _cases():
     import workloads as W
     return [(W.PENDULUM, 5, [0.5, 0.0]), (W.CARTPOLE, 3, [0.1, 0.2, 0.5, 0.3]), (W.CAR, 3, CAR_PRM),
-            (W.PENDULUM, 12, [-2.0, 0.4])]
+            (W.PENDULUM, 12, [-2.0, 0.4]), (W.PAPER_CARTPOLE, 2, [0.1, 0.2, 0.3, 0.5])]
 
 
 def _rel(a, b):
