@@ -54,7 +54,10 @@ int strom_gen_export(const strom_gen_sdp *g, int32_t *block_sizes, int64_t *rowp
  * "Algorithmic Backbone", the valid-lower-bound equation), from App. "Existence of R_beta": with
  * every scaled variable of clique k bounded by R_k (box constraints, unit circles and the
  * initial state of the family), R_beta = s(d, 2) max(1, R_k)^4 for M_k and
- * max_{|z| <= R_k} g_{k,i}(z) * s(d, 1) max(1, R_k)^2 for L_{k,i}.  (The appendix writes s(d, 2) R_k^2,
+ * max_{|z| <= R_k} g_{k,i}(z) * s(d, 1) max(1, R_k)^2 for L_{k,i}, the maximum taken exactly for
+ * the one-variable terms of degree <= 2 and as |c| R_k^deg for every other term.  (The cart-pole
+ * of the paper bounds its last clique's lookahead a_{N+1} through the dynamics.)  (The appendix
+ * writes s(d, 2) R_k^2,
  * which is not a bound when R_k < 1 or for the degree-two monomials; max(1, R_k)^(2 deg) bounds
  * the square of every monomial of the basis.)  E_INVAL when a variable of the family has no
  * bound (the pendulum's angular rate). */

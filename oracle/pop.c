@@ -790,6 +790,21 @@ int fam_var_bounds(int family, const double *prm, int nprm, double *bnd) {
     bx[2] = fmax(20.0, fabs(prm[3])) / sx[2]; bx[3] = fmax(20.0, fabs(prm[4])) / sx[3];
     bx[4] = bx[5] = bx[6] = bx[7] = 1;
     bu[0] = bu[1] = 1;
+  } else if (family == ORC_BACKIN) {  /* |rx| <= |x0| + 2, |ry| <= 8 (by 10), circles, |v| <= 4, |w| <= 0.5,
+                                        * circle of f, unit spheres of the separating lines */
+    bx[0] = (fabs(prm[0]) + 2) / sx[0]; bx[1] = fmax(8.0, fabs(prm[1])) / sx[1];
+    bx[2] = bx[3] = 1;
+    for (int i = 0; i < 10; ++i) bu[i] = 1;
+  } else if (family == ORC_PAPER_CARTPOLE) {
+    /* |a_k| <= A = max(a_max, |a_0|, |a_1|) for k <= N, circles, |u| <= 10 (scaled: 1).  The
+     * lookahead a_{N+1} of the last clique has no box; the dynamics centred at x_N give
+     * |a_{N+1}| <= 2|a_N| + |a_{N-1}| + (4 m2 l + dt^2 u_max) / (m1 + m2) (|rs| <= 1), which
+     * bounds the a entries of every clique (R_beta takes the largest bound anyway) */
+    const double m1 = 1.0, m2 = 0.3, l = 0.5, dt = 0.1, umax = 10;
+    const double A = fmax(1.0, fmax(fabs(prm[0]), fabs(prm[0] + dt * prm[1])));
+    bx[0] = (3 * A + (4 * m2 * l + dt * dt * umax) / (m1 + m2)) / sx[0];
+    bx[1] = bx[2] = bx[3] = bx[4] = 1;
+    bu[0] = umax / su[0];
   } else {
     return -1;
   }

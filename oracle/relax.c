@@ -475,22 +475,35 @@ double orc_rollout(int family, int N, const double *prm, int nprm, const double 
  * degree t of the basis is at most max(1, R_k)^t in size, so for the rank-one lifting
  *   tr M_k(z) = ||[z]_2||^2 <= s(d, 2) * max(1, R_k)^4,
  *   tr L_{k,i}(z) = g(z) ||[z]_1||^2 <= (max of g over the box |z| <= R_k) * s(d, 1) * max(1, R_k)^2.
- * The maximum of g is taken term by term: every inequality of the families is a sum of
- * one-variable terms of degree <= 2 (other shapes return -3).  R_beta: nblocks values. */
+ * The maximum of g is bounded term by term: exactly for the one-variable terms of degree <= 2
+ * of each variable together, by |c| R^deg for every other term (the car back-in's separation
+ * inequalities are products of two variables).  R_beta: nblocks values. */
+static int dbl_cmp(const void *x, const void *y) {
+  const double u = *(const double *)x, v = *(const double *)y;
+  return u < v ? -1 : (u > v ? 1 : 0);
+}
+
 static int box_max_sep(const pl_poly *g, double R, double *out) {
   double a[PL_MAXV] = {0}, b[PL_MAXV] = {0}, c = 0;
+  double *mixed = (double *)malloc(sizeof(double) * (size_t)(g->n + 1));
+  int nmixed = 0;
   for (int t = 0; t < g->n; ++t) {
-    int var = -1, e = 0;
+    int var = -1, e = 0, deg = 0, nv = 0;
     for (int v = 0; v < PL_MAXV; ++v)
       if (g->t[t].e[v]) {
-        if (var >= 0) return -3;
         var = v;
         e = g->t[t].e[v];
+        deg += e;
+        nv++;
       }
-    if (var < 0) c += g->t[t].c;
-    else if (e == 2) a[var] += g->t[t].c;
-    else if (e == 1) b[var] += g->t[t].c;
-    else return -3;
+    if (nv == 0) c += g->t[t].c;
+    else if (nv == 1 && e == 2) a[var] += g->t[t].c;
+    else if (nv == 1 && e == 1) b[var] += g->t[t].c;
+    else {  /* any other term: at most |c| R^deg on the box */
+      double m = fabs(g->t[t].c);
+      for (int q = 0; q < deg; ++q) m *= R;
+      mixed[nmixed++] = m;
+    }
   }
   for (int v = 0; v < PL_MAXV; ++v) {
     if (a[v] == 0 && b[v] == 0) continue;
@@ -501,7 +514,12 @@ static int box_max_sep(const pl_poly *g, double R, double *out) {
     }
     c += best;
   }
-  *out = c;
+  /* the bounds of the other terms, summed in ascending order */
+  qsort(mixed, (size_t)nmixed, sizeof(double), dbl_cmp);
+  double sm = 0;
+  for (int q = 0; q < nmixed; ++q) sm += mixed[q];
+  free(mixed);
+  *out = c + sm;
   return 0;
 }
 

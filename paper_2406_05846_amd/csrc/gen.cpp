@@ -448,27 +448,44 @@ bool var_bounds(int family, const double *p, const Layout &L, std::vector<double
             std::max(1.0, std::fabs(p[3]) / 20), std::max(1.0, std::fabs(p[4]) / 20), 1.0, 1.0, 1.0, 1.0};
       bu = {1.0, 1.0};
       return true;
+    case 7:  // |rx| <= |x0| + 2, |ry| <= 8 (scaled by 10), circles; |v| <= 4, |w| <= 0.5, circle, unit spheres
+      bx = {(std::fabs(p[0]) + 2) / 10, std::max(8.0, std::fabs(p[1])) / 10, 1.0, 1.0};
+      bu.assign(10, 1.0);
+      return true;
+    case 8: {  // |a| <= A for a_0..a_N; the last clique's a_{N+1} only through the dynamics centred
+               // at x_N: |a_{N+1}| <= 2|a_N| + |a_{N-1}| + (4 m2 l + dt^2 u_max)/(m1 + m2); circles; |u| <= 10
+      const double A = std::max(1.0, std::max(std::fabs(p[0]), std::fabs(p[0] + 0.1 * p[1])));
+      bx = {3 * A + (4 * 0.3 * 0.5 + 0.1 * 0.1 * 10) / (1.0 + 0.3), 1.0, 1.0, 1.0, 1.0};
+      bu = {1.0};
+      return true;
+    }
     default: return false;
   }
 }
 
-// max of g over the box |z_v| <= R for a polynomial whose terms each involve one variable with
-// degree <= 2 (every inequality of the families); false for any other g.
+// An upper bound of g over the box |z_v| <= R: exact for the terms of one variable of degree
+// <= 2 (each variable's together), |c| R^deg for every other term (products of two variables in
+// the car back-in's separation inequalities), the latter summed in ascending order.
 bool box_max(const Poly &g, double R, double &out) {
   std::map<int, std::pair<double, double>> ab;  // variable -> (coefficient of z^2, of z)
+  std::vector<double> other;
   double c = 0.0;
   for (auto &t : g.c) {
     if (t.first == 0) { c += t.second; continue; }
-    int var = -1, e = 0;
+    int var = -1, e = 0, nv = 0;
     for (int v = 0; v < kMaxVars; ++v)
       if (mono_exp(t.first, v)) {
-        if (var >= 0) return false;
         var = v;
         e = mono_exp(t.first, v);
+        ++nv;
       }
-    if (e == 2) ab[var].first += t.second;
-    else if (e == 1) ab[var].second += t.second;
-    else return false;
+    if (nv == 1 && e == 2) ab[var].first += t.second;
+    else if (nv == 1 && e == 1) ab[var].second += t.second;
+    else {
+      double m = std::fabs(t.second);
+      for (int q = mono_deg(t.first); q > 0; --q) m *= R;
+      other.push_back(m);
+    }
   }
   for (auto &kv : ab) {
     const double a = kv.second.first, b = kv.second.second;
@@ -479,7 +496,10 @@ bool box_max(const Poly &g, double R, double &out) {
     }
     c += m;
   }
-  out = c;
+  std::sort(other.begin(), other.end());
+  double so = 0.0;
+  for (double v : other) so += v;
+  out = c + so;
   return true;
 }
 

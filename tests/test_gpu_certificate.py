@@ -189,3 +189,31 @@ def test_car_full_size_certificate(S, ctx, orc):
     lt_o, vt_o = orc.extract(osdp, X, moments)
     assert np.abs(lt - lt_o).max() <= 1e-9 * (1.0 + np.abs(lt_o).max())
     inst.close()
+
+
+@pytest.mark.parametrize("fam,N,seed", [(8, 3, 0), (7, 2, 0)])
+def test_paper_problem_certificates(S, ctx, orc, fam, N, seed):
+    """The paper's cart-pole (its last clique's lookahead a_{N+1} bounded through the dynamics) and
+    car back-in (separation inequalities with products of two variables): the trace bounds R_beta
+    agree between the generators, and after a solve (to 1e-8; the back-in 1,000 iterations) the
+    device's valid lower bound equals the oracle's at the device's y, block by block, and lies
+    below <b, y> and the objective."""
+    import workloads as W
+    prm = W.instance_params(fam, seed)
+    prob = S.generate(fam, N, prm)
+    R = prob.trace_bounds
+    assert R is not None and np.array_equal(R, orc.trace_bounds(fam, N, prm))
+    cap = 20000 if fam == 8 else 1000  # the bound is valid at any y: the back-in stops at a short cap
+    inst = S.Instance(ctx, prob, S.default_opts(maxiter=cap, tol=1e-8))
+    info = inst.step(cap)
+    if fam == 8:
+        assert info["state"] == S.CONVERGED, info
+    lb, lam = inst.dual_bound(R)
+    _, y, _ = inst.get_iterate()
+    osdp = orc.relax(fam, N, prm)
+    ref_lb, ref_lam = orc.dual_bound(osdp, y, R)
+    assert np.abs(lam - ref_lam).max() <= 1e-9 * max(1.0, np.abs(ref_lam).max())
+    assert abs(lb - ref_lb) <= 1e-9 * (1.0 + abs(ref_lb))
+    assert lb <= info["dobj"] + 1e-12 * (1.0 + abs(info["dobj"]))
+    assert lb <= info["pobj"] + 1e-9 * (1.0 + abs(info["pobj"]))
+    inst.close()

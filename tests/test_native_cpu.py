@@ -128,7 +128,8 @@ def test_trace_bounds_agree_with_the_oracle(orc):
     import paper_2406_05846_amd as S
     import workloads as W
     for fam, N, seed in [(W.CARTPOLE, 5, 0), (W.CAR, 4, 0), (W.CAR, 4, 1), (W.PAPER_PENDULUM, 3, 0), (W.FLYING, 2, 0),
-                         (W.LANDING, 2, 0)]:
+                         (W.LANDING, 2, 0), (W.BACKIN, 2, 0), (W.BACKIN, 30, 1), (W.PAPER_CARTPOLE, 3, 0),
+                         (W.PAPER_CARTPOLE, 3, 1)]:
         prm = W.instance_params(fam, seed)
         ref = orc.trace_bounds(fam, N, prm)
         got = S.generate(fam, N, prm).trace_bounds

@@ -109,7 +109,9 @@ def test_warm_start_shifted_horizon_reaches_the_cold_optimum(orc):
 @pytest.mark.parametrize("fam,N,prm", [("CARTPOLE", 4, [0.1, 0.2, 0.5, 0.3]), ("CARTPOLE", 3, [-0.4, 0.5, 2.9, -1.0]),
                                        ("CAR", 3, [0, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
                                        ("CAR", 3, [1, -1.5, -1.0, 0.3, 1.5, 1.2, 0.0, 0.1]),
-                                       ("PAPER_PENDULUM", 3, [0.3, 0.5]), ("TOY1D", 4, [2.0, 0.1, 1.0])])
+                                       ("PAPER_PENDULUM", 3, [0.3, 0.5]), ("TOY1D", 4, [2.0, 0.1, 1.0]),
+                                       ("PAPER_CARTPOLE", 3, [0.1, 0.2, 0.3, 0.5]),
+                                       ("PAPER_CARTPOLE", 2, [-0.4, 0.5, -0.3, 0.9])])
 def test_trace_bounds_hold_for_feasible_points(orc, fam, N, prm):
     """App. "Existence of R_beta" (with the proof's dropped square restored): every block of the
     rank-one lifting of a feasible trajectory has trace <= R_beta.  Feasible points: rollouts of
@@ -133,6 +135,34 @@ def test_trace_bounds_hold_for_feasible_points(orc, fam, N, prm):
         kept += 1
         assert np.all(tr <= R * (1 + 1e-12)), (trial, np.max(tr / R))
     assert kept >= 20
+
+
+def test_trace_bounds_hold_on_the_variable_box(orc):
+    """The car back-in, whose separation inequalities are products of two variables (their
+    localizing bounds take |c| R^2 for each product term): the traces of the lifting stay below
+    R_beta at points anywhere in the box of the variable bounds, feasible or not (the bound needs
+    only |z_v| <= R_k), including its corners, where the products reach their largest values."""
+    prm = [3.0, 4.0, 0.1]
+    N = 2
+    R = orc.trace_bounds(orc.BACKIN, N, prm)
+    sdp = orc.relax(orc.BACKIN, N, prm)
+    assert R is not None and len(R) == sdp.nblocks
+    dx, du = sdp.dx, sdp.du
+    bx = np.array([(abs(prm[0]) + 2) / 10, max(8.0, abs(prm[1])) / 10, 1.0, 1.0])
+    bu = np.ones(du)
+    box = np.concatenate([np.concatenate([bx, bu]) for _ in range(N)] + [bx])
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for trial in range(300):
+        if trial < 100:  # corners
+            z = box * rng.choice([-1.0, 1.0], size=box.size)
+        else:
+            z = box * rng.uniform(-1.0, 1.0, size=box.size)
+        X, _ = orc.lift(orc.BACKIN, N, prm, z)
+        tr = _block_traces(sdp, X)
+        worst = max(worst, float(np.max(tr / R)))
+        assert np.all(tr <= R * (1 + 1e-12)), (trial, np.max(tr / R))
+    assert worst > 0.1  # the corners come within an order of magnitude of the bound
 
 
 def test_trace_bounds_need_bounded_variables(orc):
