@@ -752,6 +752,18 @@ int fam_init_state(int family, const double *prm, int nprm, double *x0) {
   return 0;
 }
 
+/* Bound of the last clique's lookahead variables, which lie past the horizon (0: none beyond the
+ * other bounds).  The paper's cart-pole: a_{N+1} has no box, but the dynamics centred at x_N
+ * give |a_{N+1}| <= 2|a_N| + |a_{N-1}| + (4 m2 l + dt^2 u_max) / (m1 + m2) (|rs| <= 1). */
+double fam_tail_bound(int family, const double *prm, int nprm) {
+  if (family == ORC_PAPER_CARTPOLE && nprm >= 4) {
+    const double m1 = 1.0, m2 = 0.3, l = 0.5, dt = 0.1, umax = 10;
+    const double A = fmax(1.0, fmax(fabs(prm[0]), fabs(prm[0] + dt * prm[1])));
+    return 3 * A + (4 * m2 * l + dt * dt * umax) / (m1 + m2);
+  }
+  return 0.0;
+}
+
 /* The step memory of a family with lookahead at the start (the paper's cart-pole: a_1 from the
  * initial cart velocity, scaled). */
 int fam_init_aux(int family, const double *prm, int nprm, double *aux) {
@@ -796,15 +808,11 @@ int fam_var_bounds(int family, const double *prm, int nprm, double *bnd) {
     bx[2] = bx[3] = 1;
     for (int i = 0; i < 10; ++i) bu[i] = 1;
   } else if (family == ORC_PAPER_CARTPOLE) {
-    /* |a_k| <= A = max(a_max, |a_0|, |a_1|) for k <= N, circles, |u| <= 10 (scaled: 1).  The
-     * lookahead a_{N+1} of the last clique has no box; the dynamics centred at x_N give
-     * |a_{N+1}| <= 2|a_N| + |a_{N-1}| + (4 m2 l + dt^2 u_max) / (m1 + m2) (|rs| <= 1), which
-     * bounds the a entries of every clique (R_beta takes the largest bound anyway) */
-    const double m1 = 1.0, m2 = 0.3, l = 0.5, dt = 0.1, umax = 10;
-    const double A = fmax(1.0, fmax(fabs(prm[0]), fabs(prm[0] + dt * prm[1])));
-    bx[0] = (3 * A + (4 * m2 * l + dt * dt * umax) / (m1 + m2)) / sx[0];
+    /* |a_k| <= A = max(a_max, |a_0|, |a_1|) for k <= N (the lookahead a_{k+2} of every clique but
+     * the last, see fam_tail_bound), circles, |u| <= 10 (scaled: 1) */
+    bx[0] = fmax(1.0, fmax(fabs(prm[0]), fabs(prm[0] + 0.1 * prm[1]))) / sx[0];
     bx[1] = bx[2] = bx[3] = bx[4] = 1;
-    bu[0] = umax / su[0];
+    bu[0] = 10.0 / su[0];
   } else {
     return -1;
   }

@@ -32,5 +32,6 @@ int fam_step(int family, const double *prm, int nprm, const double *x0, double *
 int fam_init_state(int family, const double *prm, int nprm, double *x0);
 int fam_init_aux(int family, const double *prm, int nprm, double *aux);
 int fam_var_bounds(int family, const double *prm, int nprm, double *bnd);
+double fam_tail_bound(int family, const double *prm, int nprm);
 
 #endif

@@ -532,12 +532,14 @@ int orc_trace_bounds(int family, int N, const double *prm, int nprm, double *R_b
   const int dl = fam_lookahead(family, lmap);
   for (int j = 0; j < dl; ++j) bnd[2 * dx + du + j] = bnd[lmap[j]];
   const int d = 2 * dx + du + dl;
-  double Rk = 0;
-  for (int v = 0; v < d; ++v) Rk = fmax(Rk, bnd[v]);
-  const double r1 = fmax(1.0, Rk);
+  double R0 = 0;
+  for (int v = 0; v < d; ++v) R0 = fmax(R0, bnd[v]);
   const double sM = (double)binom(d + 2, 2), s1 = (double)(d + 1);
   int bi = 0, rc = 0;
   for (int k = 0; k < N && !rc; ++k) {
+    /* R_k: the last clique also holds the lookahead past the horizon */
+    const double Rk = k == N - 1 ? fmax(R0, fam_tail_bound(family, prm, nprm)) : R0;
+    const double r1 = fmax(1.0, Rk);
     pl_list eq, iq;
     pl_poly cost;
     memset(&eq, 0, sizeof eq);

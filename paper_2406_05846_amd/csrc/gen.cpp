@@ -452,15 +452,21 @@ bool var_bounds(int family, const double *p, const Layout &L, std::vector<double
       bx = {(std::fabs(p[0]) + 2) / 10, std::max(8.0, std::fabs(p[1])) / 10, 1.0, 1.0};
       bu.assign(10, 1.0);
       return true;
-    case 8: {  // |a| <= A for a_0..a_N; the last clique's a_{N+1} only through the dynamics centred
-               // at x_N: |a_{N+1}| <= 2|a_N| + |a_{N-1}| + (4 m2 l + dt^2 u_max)/(m1 + m2); circles; |u| <= 10
-      const double A = std::max(1.0, std::max(std::fabs(p[0]), std::fabs(p[0] + 0.1 * p[1])));
-      bx = {3 * A + (4 * 0.3 * 0.5 + 0.1 * 0.1 * 10) / (1.0 + 0.3), 1.0, 1.0, 1.0, 1.0};
+    case 8:  // |a| <= A for a_0..a_N (see tail_bound for the last clique's a_{N+1}); circles; |u| <= 10
+      bx = {std::max(1.0, std::max(std::fabs(p[0]), std::fabs(p[0] + 0.1 * p[1]))), 1.0, 1.0, 1.0, 1.0};
       bu = {1.0};
       return true;
-    }
     default: return false;
   }
+}
+
+// Bound of the last clique's variables past the horizon (0: none beyond var_bounds): the
+// paper's cart-pole holds a_{N+1}, which only its dynamics centred at x_N bound:
+// |a_{N+1}| <= 2|a_N| + |a_{N-1}| + (4 m2 l + dt^2 u_max)/(m1 + m2).
+double tail_bound(int family, const double *p) {
+  if (family != 8) return 0.0;
+  const double A = std::max(1.0, std::max(std::fabs(p[0]), std::fabs(p[0] + 0.1 * p[1])));
+  return 3 * A + (4 * 0.3 * 0.5 + 0.1 * 0.1 * 10) / (1.0 + 0.3);
 }
 
 // An upper bound of g over the box |z_v| <= R: exact for the terms of one variable of degree
@@ -595,12 +601,13 @@ extern "C" int strom_gen_build(int family, int N, const double *params, int npar
   {
     std::vector<double> bx, bu;
     if (var_bounds(family, params, L, bx, bu)) {
-      double Rk = 0.0;
-      for (double v : bx) Rk = std::max(Rk, v);
-      for (double v : bu) Rk = std::max(Rk, v);
-      const double r1 = std::max(1.0, Rk);
+      double R0 = 0.0;
+      for (double v : bx) R0 = std::max(R0, v);
+      for (double v : bu) R0 = std::max(R0, v);
       bool ok = true;
       for (int k = 0; k < N && ok; ++k) {
+        const double Rk = k == N - 1 ? std::max(R0, tail_bound(family, params)) : R0;  // past the horizon
+        const double r1 = std::max(1.0, Rk);
         S->trace_bound.push_back(double(nM) * r1 * r1 * r1 * r1);
         for (const Poly &g : cl[size_t(k)].ineq) {
           double gm = 0.0;
