@@ -7,8 +7,10 @@ and then walks the schedule exactly as the solve kernels read it.  Its
 y = (eps I + A A^*)^{-1} r must match the oracle's own sparse factorization: a schedule that
 drops, doubles or misindexes a stream entry, or runs a task before one it depends on, fails
 here.  Every case runs with the task split of every group task, of the overweight ones only
-and none, and with every task staged in LDS, some staged, and none (the in-place kernel
-path).
+and none, with every task staged in LDS, some staged, and none (the in-place kernel
+path), and with the groups' interior rows in their own order and in minimum-degree order (by
+default the analysis keeps the one whose schedule has fewer stream entries on the longest
+path, the largest task of every launch group).
 """
 import os
 import subprocess
@@ -32,6 +34,8 @@ VARIANTS = [  # environment of the analysis
     {"STROM_STAGE_ROWS": "600", "STROM_BLOCK_ROWS": "32"},
     {"STROM_TOP_LEVELS": "1"},  # only the root coupling set in the root task
     {"STROM_TOP_LEVELS": "4"},  # the top four levels of the dissection tree in one task
+    {"STROM_ROW_ORDER": "0"},  # the interior rows of every group in their own order
+    {"STROM_ROW_ORDER": "1"},  # ... in minimum-degree order
 ]
 
 
@@ -73,3 +77,7 @@ def test_schedule_solves_the_system(sim, orc, tmp_path, fam, N, prm):
     if fam in (1, 2):  # the first clique carries the initial-state rows: its task is split
         assert base["tasks"] > tasks[(("STROM_TASK_SPLIT", "0"),)]["tasks"]
         assert base["fwd_groups"] == tasks[(("STROM_TASK_SPLIT", "0"),)]["fwd_groups"]
+    nat, md = tasks[(("STROM_ROW_ORDER", "0"),)], tasks[(("STROM_ROW_ORDER", "1"),)]
+    assert md["nnzL"] < nat["nnzL"]  # minimum degree: less fill
+    pick = md if md["solve_entries"] < nat["solve_entries"] else nat
+    assert (base["nnzL"], base["solve_entries"]) == (pick["nnzL"], pick["solve_entries"])
