@@ -133,7 +133,10 @@ strom_status strom_ctx_destroy(strom_ctx *ctx);
 
 /* Set up one instance: validates the CSR (E_INVAL), orders the rows (clique interiors first,
  * then the rows coupling two cliques by nested dissection over the chain, a consequence of the
- * chain-like sparsity of Def. 1), factors eps*I + A A^* = P L D L^T P^T in FP64 on the host
+ * chain-like sparsity of Def. 1; inside each clique's interior either the given order or a
+ * minimum-degree one, whichever gives the shorter modelled y-solve, decided once per sparsity
+ * pattern up to 500,000 rows; the STROM_ROW_ORDER environment variable, 0 or 1, forces the
+ * given or the minimum-degree order), factors eps*I + A A^* = P L D L^T P^T in FP64 on the host
  * (the paper's Cholesky-with-pre-permutation equation; E_FACTOR on a non-positive pivot),
  * uploads everything and sets the iterate to (X0, 0, S0).  opts may be NULL (defaults).
  * Blocks up to n = 113 are projected by one workgroup each (in FP64, or FP32 before the polish
