@@ -14,6 +14,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.h"
 #include "strom_internal.h"
@@ -121,18 +122,19 @@ __device__ inline void stream_phase(const double *__restrict__ val, const int32_
     const double *vp = val + off + t;
     const int32_t *ip = idx + off + t;
     double acc = 0.0;
-    for (int32_t k0 = 0; k0 < K; k0 += kStreamBatch) {
-      double v[kStreamBatch];
-      int32_t x[kStreamBatch];
+    auto batch = [&](auto nb, int32_t k0) {  // nb entries from k0: loads, factors, then sums in order
+      constexpr int NB = decltype(nb)::value;
+      double v[NB];
+      int32_t x[NB];
 #pragma unroll
-      for (int u = 0; u < kStreamBatch; ++u) {
+      for (int u = 0; u < NB; ++u) {
         v[u] = vp[(int64_t)(k0 + u) * Tp];
         x[u] = ip[(int64_t)(k0 + u) * Tp];
       }
 #pragma unroll
-      for (int u = 0; u < kStreamBatch; ++u) v[u] *= get(x[u] & (kLastFlag - 1));
+      for (int u = 0; u < NB; ++u) v[u] *= get(x[u] & (kLastFlag - 1));
 #pragma unroll
-      for (int u = 0; u < kStreamBatch; ++u) {
+      for (int u = 0; u < NB; ++u) {
         acc += v[u];
         if (x[u] & kLastFlag) {
           if (own) fin(row, acc);
@@ -142,7 +144,12 @@ __device__ inline void stream_phase(const double *__restrict__ val, const int32_
           own = true;
         }
       }
-    }
+    };
+    // two batches' loads in flight where the slice holds them (K is a multiple of kStreamBatch)
+    int32_t k0 = 0;
+    for (; k0 + 2 * kStreamBatch <= K; k0 += 2 * kStreamBatch)
+      batch(std::integral_constant<int, 2 * kStreamBatch>(), k0);
+    if (k0 < K) batch(std::integral_constant<int, kStreamBatch>(), k0);
     tail_v[t] = acc;
     tail_r[t] = own ? row : -1 - row;  // the open row; negative: it started in an earlier slice
   }
