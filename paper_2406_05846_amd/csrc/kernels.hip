@@ -103,8 +103,9 @@ __global__ void __launch_bounds__(256) k_rhs_batch(const BatchItem *__restrict__
 // ("push segments", its push stream) right after its own rows are solved, so the work of a
 // separator row is spread over the tasks below it.
 // One phase stream (see setup.cpp): thread t walks its slice of K entries (entry k at
-// off + k * Tp + t), kStreamBatch loads in flight, then their factors get(index) (get never
-// reads what fin writes), then adds them in order; fin(row, sum) completes a row.  A row
+// off + k * Tp + t), 2 kStreamBatch loads in flight (kStreamBatch for an odd last granule),
+// then their factors get(index) (get never reads what fin writes), then adds them in order;
+// fin(row, sum) completes a row.  A row
 // that started in an earlier slice is completed after a barrier by the thread holding its
 // last entry, adding the pieces of the earlier slices in order (tail_v / tail_r: the open
 // row of every slice).  Contains one __syncthreads(): call from all threads.

@@ -12,7 +12,7 @@ constexpr int32_t kSolveThreads = 1024;       // workgroup size of the solve ker
 constexpr int32_t kMaxBlockRows = 192;        // rows of one component (dense diagonal block) of a phase
 constexpr int32_t kMaxPhaseBlockRows = 4096;  // rows in components of two or more, per phase
 constexpr int32_t kMaxLdsTaskRows = 14336;    // task values kept in LDS up to this many rows
-constexpr int32_t kStreamBatch = 8;              // stream entries loaded per thread at a time
+constexpr int32_t kStreamBatch = 8;              // granule of a stream slice (entries per thread); read two at a time
 constexpr int kStreamKinds = 5;                  // fg, fi, bg, bi (per phase), push (per task)
 constexpr int32_t kLastFlag = int32_t(1) << 30;  // stream index flag: last entry of a row
 constexpr int32_t kPartFlag = int32_t(1) << 29;  // forward gather index flag: a pushed partial sum
