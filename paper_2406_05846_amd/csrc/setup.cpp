@@ -1441,30 +1441,41 @@ bool same_key(const CacheEntry &e, int32_t nblocks, const int32_t *bsize, int32_
 
 // Modelled y-solve time of a schedule, in stream entries: over the launch groups of both
 // directions, the entries of the group's largest task (a launch lasts as long as its slowest
-// workgroup; a task streams its phases' gathers and inverse blocks, and forward its pushes).
-int64_t modelled_solve_entries(const HostAnalysis &H) {
+// workgroup; a task streams its phases' gathers and inverse blocks, and forward its pushes);
+// with total set, the entries of every task (a merged batch fills its launches, so it pays
+// for all of them).
+int64_t modelled_solve_entries(const HostAnalysis &H, bool total) {
   auto task = [&](int32_t t, int k0, bool push) {
     int64_t e = push ? int64_t(H.s_K[4][size_t(t)]) * H.s_T[4][size_t(t)] : 0;
     for (int32_t p = H.task_ph0[size_t(t)]; p < H.task_ph1[size_t(t)]; ++p)
       for (int k = k0; k <= k0 + 1; ++k) e += int64_t(H.s_K[k][size_t(p)]) * H.s_T[k][size_t(p)];
     return e;
   };
-  int64_t total = 0;
+  int64_t entries = 0;
   for (int dir = 0; dir < 2; ++dir) {
     const std::vector<int32_t> &gp = dir ? H.bwd_gptr : H.fwd_gptr, &ord = dir ? H.bwd_order : H.fwd_order;
     for (size_t g = 0; g + 1 < gp.size(); ++g) {
       int64_t mx = 0;
-      for (int32_t i = gp[g]; i < gp[g + 1]; ++i) mx = std::max(mx, task(ord[size_t(i)], dir ? 2 : 0, dir == 0));
-      total += mx;
+      int64_t sum = 0;
+      for (int32_t i = gp[g]; i < gp[g + 1]; ++i) {
+        const int64_t e = task(ord[size_t(i)], dir ? 2 : 0, dir == 0);
+        mx = std::max(mx, e);
+        sum += e;
+      }
+      entries += total ? sum : mx;
     }
   }
-  return total;
+  return entries;
 }
 
 // Row order inside the groups' interior runs.  STROM_ROW_ORDER if set (0: the rows' own order,
 // 1: minimum degree).  Else, up to kAutoOrderRows rows, both orders are analysed and the one
-// whose schedule has the shorter modelled solve is kept; the choice is remembered per sparsity
-// pattern, so a pattern pays the second analysis once.  Larger problems keep their own order.
+// whose schedule has the shorter modelled solve is kept: the longest path for the default
+// schedule, the total stream entries for the throughput schedule of merged batches (task split
+// of overweight tasks only, split mode 1: cart-pole N = 30 5.03 -> 4.41 M entries under
+// minimum degree, its longest path 3% longer).  The choice is remembered per sparsity pattern
+// and schedule options, so a pattern pays the second analysis once.  Larger problems keep
+// their own order.
 // Minimum degree cuts the fill of L by a third or more on every family, but the solve follows
 // the largest task of each launch group, most often the one with the first clique (it carries
 // the initial-state rows), and that one gains or loses with the family.  Measured on MI355X,
@@ -1517,7 +1528,13 @@ strom_status analyze_full(int32_t nblocks, const int32_t *bsize, int32_t m, cons
       analyze_order(nblocks, bsize, m, rowptr, col, val, eps_reg, H, err, split_mode, block_rows, mp, false);
   other.join();
   if (rc != STROM_OK) return rc;
-  const bool md = rc1 == STROM_OK && modelled_solve_entries(H1) < modelled_solve_entries(H);
+  int mode = split_mode;  // the split mode the analysis resolves (see analyze_instance)
+  if (mode < 0) {
+    mode = 2;
+    if (const char *ev = std::getenv("STROM_TASK_SPLIT")) mode = int(std::strtol(ev, nullptr, 10));
+  }
+  const bool total = mode == 1;
+  const bool md = rc1 == STROM_OK && modelled_solve_entries(H1, total) < modelled_solve_entries(H, total);
   if (md) {
     H = std::move(H1);
     if (mp) *mp = std::move(m1);

@@ -254,8 +254,8 @@ int main(int argc, char **argv) {
       for (int i = r0; i < r1; ++i) y[size_t(H.perm[size_t(i)])] = w[size_t(i)];
       bdone[size_t(t)] = 1;
     }
-  // stream entries of the largest task of every launch group, both directions
-  long entries = 0;
+  // stream entries of the largest task of every launch group, both directions, and of all tasks
+  long entries = 0, total_entries = 0;
   for (int dir = 0; dir < 2; ++dir) {
     const std::vector<int32_t> &gp = dir ? H.bwd_gptr : H.fwd_gptr, &ord = dir ? H.bwd_order : H.fwd_order;
     for (size_t g = 0; g + 1 < gp.size(); ++g) {
@@ -266,12 +266,15 @@ int main(int argc, char **argv) {
         for (int32_t p = H.task_ph0[size_t(t)]; p < H.task_ph1[size_t(t)]; ++p)
           for (int k = dir ? 2 : 0; k <= (dir ? 3 : 1); ++k) e += long(H.s_K[k][size_t(p)]) * H.s_T[k][size_t(p)];
         mx = e > mx ? e : mx;
+        total_entries += e;
       }
       entries += mx;
     }
   }
-  std::printf("m %d tasks %d staged %d fwd_groups %zu bwd_groups %zu phases %ld nnzL %ld solve_entries %ld\n", m,
-              ntask, staged, H.fwd_gptr.size() - 1, H.bwd_gptr.size() - 1, nph, long(H.nnzL), entries);
+  std::printf("m %d tasks %d staged %d fwd_groups %zu bwd_groups %zu phases %ld nnzL %ld solve_entries %ld "
+              "total_entries %ld\n",
+              m, ntask, staged, H.fwd_gptr.size() - 1, H.bwd_gptr.size() - 1, nph, long(H.nnzL), entries,
+              total_entries);
   FILE *fo = std::fopen((d + "/y").c_str(), "wb");
   REQ(fo);
   std::fwrite(y.data(), sizeof(double), size_t(m), fo);

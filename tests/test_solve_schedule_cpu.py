@@ -10,7 +10,8 @@ here.  Every case runs with the task split of every group task, of the overweigh
 and none, with every task staged in LDS, some staged, and none (the in-place kernel
 path), and with the groups' interior rows in their own order and in minimum-degree order (by
 default the analysis keeps the one whose schedule has fewer stream entries on the longest
-path, the largest task of every launch group).
+path, the largest task of every launch group; with the throughput schedule of merged batches,
+task split 1, the one with fewer entries in all).
 """
 import os
 import subprocess
@@ -36,6 +37,8 @@ VARIANTS = [  # environment of the analysis
     {"STROM_TOP_LEVELS": "4"},  # the top four levels of the dissection tree in one task
     {"STROM_ROW_ORDER": "0"},  # the interior rows of every group in their own order
     {"STROM_ROW_ORDER": "1"},  # ... in minimum-degree order
+    {"STROM_TASK_SPLIT": "1", "STROM_ROW_ORDER": "0"},  # the throughput schedule in both orders
+    {"STROM_TASK_SPLIT": "1", "STROM_ROW_ORDER": "1"},
 ]
 
 
@@ -81,3 +84,9 @@ def test_schedule_solves_the_system(sim, orc, tmp_path, fam, N, prm):
     assert md["nnzL"] < nat["nnzL"]  # minimum degree: less fill
     pick = md if md["solve_entries"] < nat["solve_entries"] else nat
     assert (base["nnzL"], base["solve_entries"]) == (pick["nnzL"], pick["solve_entries"])
+    # the throughput schedule (task split 1, merged batches) keeps the order with fewer entries in all
+    s1 = tasks[(("STROM_TASK_SPLIT", "1"),)]
+    nat1 = tasks[(("STROM_ROW_ORDER", "0"), ("STROM_TASK_SPLIT", "1"))]
+    md1 = tasks[(("STROM_ROW_ORDER", "1"), ("STROM_TASK_SPLIT", "1"))]
+    pick1 = md1 if md1["total_entries"] < nat1["total_entries"] else nat1
+    assert (s1["nnzL"], s1["total_entries"]) == (pick1["nnzL"], pick1["total_entries"])
