@@ -103,21 +103,45 @@ __global__ void __launch_bounds__(256) k_rhs_batch(const BatchItem *__restrict__
 // ("push segments", its push stream) right after its own rows are solved, so the work of a
 // separator row is spread over the tasks below it.
 // One phase stream (see setup.cpp): thread t walks its slice of K entries (entry k at
-// off + k * Tp + t), 2 kStreamBatch loads in flight (kStreamBatch for an odd last granule),
+// off + k * Tp + t), W kStreamBatch loads in flight (kStreamBatch for the last granules),
 // then their factors get(index) (get never reads what fin writes), then adds them in order;
 // fin(row, sum) completes a row.  A row
 // that started in an earlier slice is completed after a barrier by the thread holding its
 // last entry, adding the pieces of the earlier slices in order (tail_v / tail_r: the open
 // row of every slice).  Contains one __syncthreads(): call from all threads.
-template <class Get, class Fin>
-__device__ inline void stream_phase(const double *__restrict__ val, const int32_t *__restrict__ idx, int64_t off,
-                                    int32_t K, int32_t Tp, const int32_t *__restrict__ first, double *tail_v,
-                                    int32_t *tail_r, Get get, Fin fin) {
+// Shape of one stream of a phase (or of a task's push stream): its offset, entries per thread
+// and thread count, the same for the whole workgroup (kept in scalar registers), and its
+// slice starts (kSolveThreads + 1 of them).  Every phase has all four streams and every task a
+// push stream, so the heads of a phase's streams are loaded together, ahead of the passes that
+// use them; a pass then issues its slice start and its first entries at once.
+struct StreamHead {
+  int64_t off;
+  int32_t K, Tp;
+  const int32_t *first;
+};
+
+template <class A>
+__device__ __forceinline__ StreamHead stream_head(const A &a, int kind, int32_t ph) {
+  StreamHead h;
+  const int64_t off = G(a.s_off[kind])[ph];
+  h.off = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(off >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)off));
+  h.K = __builtin_amdgcn_readfirstlane(G(a.s_K[kind])[ph]);
+  h.Tp = __builtin_amdgcn_readfirstlane(G(a.s_T[kind])[ph]);
+  h.first = G(a.s_ra[kind]) + (int64_t)ph * (kSolveThreads + 1);
+  return h;
+}
+
+template <int W, class Get, class Fin>
+__device__ inline void stream_phase(const double *__restrict__ val, const int32_t *__restrict__ idx,
+                                    const StreamHead &h, double *tail_v, int32_t *tail_r, Get get, Fin fin) {
   const int t = threadIdx.x;
+  const int64_t off = h.off;
+  const int32_t K = h.K, Tp = h.Tp;
   int32_t head_row = -1;
   double head_v = 0.0;
   if (t < Tp) {
-    const int32_t f = first[t];
+    const int32_t f = h.first[t];
     int32_t row = f & (kStartFlag - 1);
     bool own = (f & kStartFlag) != 0;
     const double *vp = val + off + t;
@@ -146,11 +170,11 @@ __device__ inline void stream_phase(const double *__restrict__ val, const int32_
         }
       }
     };
-    // two batches' loads in flight where the slice holds them (K is a multiple of kStreamBatch)
+    // W granules' loads in flight where the slice holds them (K is a multiple of kStreamBatch)
     int32_t k0 = 0;
-    for (; k0 + 2 * kStreamBatch <= K; k0 += 2 * kStreamBatch)
-      batch(std::integral_constant<int, 2 * kStreamBatch>(), k0);
-    if (k0 < K) batch(std::integral_constant<int, kStreamBatch>(), k0);
+    for (; k0 + W * kStreamBatch <= K; k0 += W * kStreamBatch)
+      batch(std::integral_constant<int, W * kStreamBatch>(), k0);
+    for (; k0 < K; k0 += kStreamBatch) batch(std::integral_constant<int, kStreamBatch>(), k0);
     tail_v[t] = acc;
     tail_r[t] = own ? row : -1 - row;  // the open row; negative: it started in an earlier slice
   }
@@ -169,7 +193,7 @@ __device__ inline void stream_phase(const double *__restrict__ val, const int32_
 // pushed to it -- and the stream indices are task-local; else its values are read and written
 // in place in w and the indices are global.  A separate instantiation for each case keeps every
 // access in one address space (LDS or global).
-template <bool INL, class A>
+template <int W, bool INL, class A>
 __device__ __forceinline__ void solve_fwd_task(int32_t t, const A &a, double *__restrict__ w, double *sh) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int32_t r0 = G(a.task_r0)[t], r1 = G(a.task_r1)[t], nt = r1 - r0;
@@ -183,11 +207,12 @@ __device__ __forceinline__ void solve_fwd_task(int32_t t, const A &a, double *__
     for (int i = tid; i < nt; i += nth) xs[i] = w[r0 + i];
     for (int k = tid; k < npin; k += nth) xs[nt + k] = G(a.part)[p0 + k];
   }
+  const StreamHead hp = stream_head(a, 4, t);
   __syncthreads();
   for (int32_t ph = G(a.task_ph0)[t]; ph < G(a.task_ph1)[t]; ++ph) {
     const int32_t pa = G(a.ph_a)[ph], nns = G(a.ph_nns)[ph];
-    stream_phase(G(a.sval[0]), G(a.sidx[0]), G(a.s_off[0])[ph], G(a.s_K[0])[ph], G(a.s_T[0])[ph],
-                G(a.s_ra[0]) + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
+    const StreamHead h0 = stream_head(a, 0, ph), h1 = stream_head(a, 1, ph);
+    stream_phase<W>(G(a.sval[0]), G(a.sidx[0]), h0, tail_v, tail_r,
                 [&](int32_t j) {
                   if constexpr (INL) return xs[j];
                   else return (j & kPartFlag) ? G(a.part)[j & (kPartFlag - 1)] : w[j];
@@ -199,17 +224,15 @@ __device__ __forceinline__ void solve_fwd_task(int32_t t, const A &a, double *__
                 });
     if (nns > 0) {
       __syncthreads();
-      stream_phase(G(a.sval[1]), G(a.sidx[1]), G(a.s_off[1])[ph], G(a.s_K[1])[ph], G(a.s_T[1])[ph],
-                  G(a.s_ra[1]) + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
-                  [&](int32_t j) { return c[j]; }, [&](int32_t r, double acc) { xs[pa + r - r0] = acc; });
+      stream_phase<W>(G(a.sval[1]), G(a.sidx[1]), h1, tail_v, tail_r, [&](int32_t j) { return c[j]; },
+                   [&](int32_t r, double acc) { xs[pa + r - r0] = acc; });
     }
     __syncthreads();
   }
   // push: partial sums of the later rows over this task's columns, one stream row per segment
   if (G(a.tsptr)[t] < G(a.tsptr)[t + 1]) {
     const int32_t s0 = G(a.tsptr)[t];
-    stream_phase(G(a.sval[4]), G(a.sidx[4]), G(a.s_off[4])[t], G(a.s_K[4])[t], G(a.s_T[4])[t],
-                 G(a.s_ra[4]) + (int64_t)t * (kSolveThreads + 1), tail_v, tail_r,
+    stream_phase<W>(G(a.sval[4]), G(a.sidx[4]), hp, tail_v, tail_r,
                  [&](int32_t j) {
                    if constexpr (INL) return xs[j];
                    else return w[j];
@@ -224,8 +247,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd(const int32_t *__re
                                                              double *__restrict__ w) {
   extern __shared__ double sh[];
   const int32_t t = tasks[blockIdx.x];
-  if (a.task_inl[t]) solve_fwd_task<true>(t, a, w, sh);
-  else solve_fwd_task<false>(t, a, w, sh);
+  if (a.task_inl[t]) solve_fwd_task<2, true>(t, a, w, sh);
+  else solve_fwd_task<2, false>(t, a, w, sh);
 }
 
 __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd_batch(const BatchItem *__restrict__ tasks,
@@ -236,14 +259,14 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_fwd_batch(const BatchIt
   const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
   if (!I.active) return;
   const SolveArgsG &a = reinterpret_cast<const SolveArgsG *>(args)[it.inst];
-  if (G(a.task_inl)[it.idx]) solve_fwd_task<true>(it.idx, a, G(I.w), sh);
-  else solve_fwd_task<false>(it.idx, a, G(I.w), sh);
+  if (G(a.task_inl)[it.idx]) solve_fwd_task<2, true>(it.idx, a, G(I.w), sh);
+  else solve_fwd_task<2, false>(it.idx, a, G(I.w), sh);
 }
 
 // Backward: L^T x = D^{-1} z over the phases in reverse order (a row only depends here on
 // its own component, later phases and later tasks).  INL: the task's rows and the rows of
 // later tasks it reads are staged in LDS, stream indices task-local.
-template <bool INL, class A>
+template <int W, bool INL, class A>
 __device__ __forceinline__ void solve_bwd_task(int32_t t, const A &a, double *__restrict__ w,
                                                double *__restrict__ y, double *sh) {
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -262,8 +285,8 @@ __device__ __forceinline__ void solve_bwd_task(int32_t t, const A &a, double *__
   __syncthreads();
   for (int32_t ph = G(a.task_ph1)[t] - 1; ph >= G(a.task_ph0)[t]; --ph) {
     const int32_t pa = G(a.ph_a)[ph], nns = G(a.ph_nns)[ph];
-    stream_phase(G(a.sval[2]), G(a.sidx[2]), G(a.s_off[2])[ph], G(a.s_K[2])[ph], G(a.s_T[2])[ph],
-                G(a.s_ra[2]) + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
+    const StreamHead h2 = stream_head(a, 2, ph), h3 = stream_head(a, 3, ph);
+    stream_phase<W>(G(a.sval[2]), G(a.sidx[2]), h2, tail_v, tail_r,
                 [&](int32_t i) {
                   if constexpr (INL) return xs[i];
                   else return w[i];
@@ -276,9 +299,8 @@ __device__ __forceinline__ void solve_bwd_task(int32_t t, const A &a, double *__
                 });
     if (nns > 0) {
       __syncthreads();
-      stream_phase(G(a.sval[3]), G(a.sidx[3]), G(a.s_off[3])[ph], G(a.s_K[3])[ph], G(a.s_T[3])[ph],
-                  G(a.s_ra[3]) + (int64_t)ph * (kSolveThreads + 1), tail_v, tail_r,
-                  [&](int32_t j) { return c[j]; }, [&](int32_t r, double acc) { xs[pa + r - r0] = acc; });
+      stream_phase<W>(G(a.sval[3]), G(a.sidx[3]), h3, tail_v, tail_r, [&](int32_t j) { return c[j]; },
+                   [&](int32_t r, double acc) { xs[pa + r - r0] = acc; });
     }
     __syncthreads();
   }
@@ -293,8 +315,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd(const int32_t *__re
                                                              double *__restrict__ w, double *__restrict__ y) {
   extern __shared__ double sh[];
   const int32_t t = tasks[blockIdx.x];
-  if (a.task_inl[t]) solve_bwd_task<true>(t, a, w, y, sh);
-  else solve_bwd_task<false>(t, a, w, y, sh);
+  if (a.task_inl[t]) solve_bwd_task<2, true>(t, a, w, y, sh);
+  else solve_bwd_task<2, false>(t, a, w, y, sh);
 }
 
 __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd_batch(const BatchItem *__restrict__ tasks,
@@ -305,8 +327,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd_batch(const BatchIt
   const BatchInstG &I = reinterpret_cast<const BatchInstG *>(bi)[it.inst];
   if (!I.active) return;
   const SolveArgsG &a = reinterpret_cast<const SolveArgsG *>(args)[it.inst];
-  if (G(a.task_inl)[it.idx]) solve_bwd_task<true>(it.idx, a, G(I.w), G(I.y), sh);
-  else solve_bwd_task<false>(it.idx, a, G(I.w), G(I.y), sh);
+  if (G(a.task_inl)[it.idx]) solve_bwd_task<2, true>(it.idx, a, G(I.w), G(I.y), sh);
+  else solve_bwd_task<2, false>(it.idx, a, G(I.w), G(I.y), sh);
 }
 
 // The root task: the last forward group and the first backward group are both this one task,
@@ -315,11 +337,11 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_bwd_batch(const BatchIt
 __global__ void __launch_bounds__(kSolveThreads) k_solve_root(int32_t t, SolveArgs a, double *__restrict__ w,
                                                               double *__restrict__ y) {
   extern __shared__ double sh[];
-  if (a.task_inl[t]) solve_fwd_task<true>(t, a, w, sh);
-  else solve_fwd_task<false>(t, a, w, sh);
+  if (a.task_inl[t]) solve_fwd_task<1, true>(t, a, w, sh);
+  else solve_fwd_task<1, false>(t, a, w, sh);
   __syncthreads();
-  if (a.task_inl[t]) solve_bwd_task<true>(t, a, w, y, sh);
-  else solve_bwd_task<false>(t, a, w, y, sh);
+  if (a.task_inl[t]) solve_bwd_task<1, true>(t, a, w, y, sh);
+  else solve_bwd_task<1, false>(t, a, w, y, sh);
 }
 
 // ------------------------------------------------------------------ step 2: X_b
